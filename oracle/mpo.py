@@ -1,0 +1,90 @@
+"""Matrix product operators (Sec. 2.1, Eq. [FSMPO]; Sec. 2.2, Eq. [Sfac]).
+Test infrastructure only.
+
+An MPO is a list of L arrays W[k] of shape (w_left, w_right, 4, 4) with
+W[k][a, b, s, t] = <s| O_ab |t>, the operator-valued matrix of the recursion
+"vector of operators on sites [k, L] = W[k] times vector on [k+1, L]" used in
+Sec. 2.1.  The first row of W[1] and the last column of W[L] are kept (the
+boundary reading of Sec. 2.1), so W[1] has w_left = 1 and W[L] w_right = 1.
+Row/column 0 carries the complete operator and the last row/column the
+identity, as in Eq. [Sfac].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import local_ops as lo
+
+
+def _trim(Ws):
+    """Keep the first row of site 1 and the last column of site L."""
+    Ws = [w.copy() for w in Ws]
+    Ws[0] = Ws[0][:1]
+    Ws[-1] = Ws[-1][:, -1:]
+    return Ws
+
+
+def hubbard_mpo(L: int, t: float, U: float):
+    """Open-boundary 1D Hubbard chain
+        H = -t sum_{k, sigma} (c+_{k sigma} c_{k+1 sigma} + h.c.)
+            + U sum_k n_{k alpha} n_{k beta}
+    as an MPO of bond dimension 6 built with the recursion of Sec. 2.1.
+
+    Right-vector order (H, c_a, c_b, c+_a, c+_b, I) on sites [k+1, L].  A hop
+    c+_{k s} c_{k+1 s} equals (c+_s F)_k (x) (c_s)_{k+1} and
+    c+_{k+1 s} c_{k s} equals (F c_s)_k (x) (c+_s)_{k+1}, where F is the site
+    parity (the Jordan-Wigner string of Eq. [JWtrans] over both spin
+    orbitals of the site).
+    """
+    F = lo.PARITY
+    w = np.zeros((6, 6, 4, 4))
+    w[0, 0] = lo.I4
+    w[0, 1] = -t * lo.CDAG_A @ F
+    w[0, 2] = -t * lo.CDAG_B @ F
+    w[0, 3] = -t * F @ lo.C_A
+    w[0, 4] = -t * F @ lo.C_B
+    w[0, 5] = U * lo.N_A @ lo.N_B
+    w[1, 5] = lo.C_A
+    w[2, 5] = lo.C_B
+    w[3, 5] = lo.CDAG_A
+    w[4, 5] = lo.CDAG_B
+    w[5, 5] = lo.I4
+    return _trim([w] * L)
+
+
+def s2_mpo(L: int):
+    """Total-spin S^2 as an MPO of bond dimension 5, Eq. [Sfac]:
+    right-vector order (S^2, S_+, S_-, S_z, I)."""
+    w = np.zeros((5, 5, 4, 4))
+    w[0, 0] = lo.I4
+    w[0, 1] = lo.S_MINUS
+    w[0, 2] = lo.S_PLUS
+    w[0, 3] = 2.0 * lo.S_Z
+    w[0, 4] = lo.S2_LOCAL
+    w[1, 1] = lo.I4
+    w[1, 4] = lo.S_PLUS
+    w[2, 2] = lo.I4
+    w[2, 4] = lo.S_MINUS
+    w[3, 3] = lo.I4
+    w[3, 4] = lo.S_Z
+    w[4, 4] = lo.I4
+    return _trim([w] * L)
+
+
+def identity_mpo(L: int):
+    """The identity operator as a bond-dimension-1 MPO."""
+    return [lo.I4.reshape(1, 1, 4, 4).copy() for _ in range(L)]
+
+
+def mpo_to_dense(Ws) -> np.ndarray:
+    """Contract an MPO to the dense 4^L x 4^L matrix (site 1 is the most
+    significant digit of the index).  Tiny chains only."""
+    L = len(Ws)
+    # cur[a, S, T] accumulates operator strings over sites 1..k
+    cur = Ws[0][0]                      # (w1, 4, 4)
+    for k in range(1, L):
+        W = Ws[k]
+        cur = np.einsum("aST,abst->bSsTt", cur, W)
+        b, S, s, T, tt = cur.shape
+        cur = cur.reshape(b, S * s, T * tt)
+    return cur[0]

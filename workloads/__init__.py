@@ -1,0 +1,245 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the HIP library.
+
+This module holds no arithmetic of the spin-projected method itself.  It only
+produces the *inputs* both sides consume:
+
+* the bond block table of a matrix product state with Abelian (N, 2M)
+  quantum numbers (which sectors each bond carries and how many states each
+  sector keeps), and
+* seeded N(0, 1) initial site tensors in the canonical packed block order,
+* named workload descriptions (Hubbard chain parameters, bond dimension,
+  number of quadrature points, number of sweeps, seeds).
+
+Conventions (shared interface, stated once here):
+
+* Sites are spatial orbitals k = 1..L with local basis index
+  sigma = 2*n_alpha + n_beta, i.e. (|0>, |b>, |a>, |ab>).  The local quantum
+  numbers (N, 2M) of sigma = 0, 1, 2, 3 are (0,0), (1,-1), (1,+1), (2,0).
+* Bond k (k = 0..L) sits to the right of site k; its sector label q = (N, 2M)
+  counts the particles and twice the spin projection of sites 1..k.  Bond 0
+  is the single sector (0, 0) of dimension 1; bond L is the single sector
+  (N, 2M) of dimension 1.
+* Within a bond, sectors are sorted by (N, 2M) ascending; the states of one
+  sector are contiguous, so the states of one particle number N form one
+  contiguous range of the bond index.
+* Site tensor A[k] is stored as blocks, one per pair (left sector a of bond
+  k-1, sigma) whose right sector b = a + q_sigma exists in bond k.  Blocks are
+  ordered by left-sector index, then sigma; each block is a dense
+  dim(a) x dim(b) row-major matrix.  Sites are concatenated k = 1..L.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# local quantum numbers (N, 2M) of sigma = 2*n_alpha + n_beta
+SIGMA_QN = ((0, 0), (1, -1), (1, 1), (2, 0))
+D_LOCAL = 4
+
+
+@dataclass
+class BlockTable:
+    """Bond sectors of an (N, 2M)-symmetric MPS.
+
+    ``bonds[k]`` is a list of (N, twoM, dim) tuples sorted by (N, twoM).
+    """
+
+    L: int
+    N: int
+    twoM: int
+    bonds: list = field(default_factory=list)
+
+    def bond_dim(self, k: int) -> int:
+        return sum(s[2] for s in self.bonds[k])
+
+    def max_bond_dim(self) -> int:
+        return max(self.bond_dim(k) for k in range(self.L + 1))
+
+    def site_blocks(self, k: int):
+        """Blocks of site k (1-based) in canonical order.
+
+        Returns a list of (ia, sigma, ib, rows, cols) with sector indices into
+        bonds[k-1] and bonds[k].
+        """
+        left = self.bonds[k - 1]
+        right = self.bonds[k]
+        index_r = {(n, m): i for i, (n, m, _) in enumerate(right)}
+        out = []
+        for ia, (n, m, da) in enumerate(left):
+            for s, (dn, dm) in enumerate(SIGMA_QN):
+                ib = index_r.get((n + dn, m + dm))
+                if ib is not None:
+                    out.append((ia, s, ib, da, right[ib][2]))
+        return out
+
+    def site_size(self, k: int) -> int:
+        return sum(r * c for (_, _, _, r, c) in self.site_blocks(k))
+
+    def total_size(self) -> int:
+        return sum(self.site_size(k) for k in range(1, self.L + 1))
+
+    # flat arrays in the layout the C library takes
+    def flat(self):
+        nsec = np.array([len(b) for b in self.bonds], dtype=np.int32)
+        sec = np.array([s for b in self.bonds for s in b], dtype=np.int32).reshape(-1, 3)
+        return nsec, np.ascontiguousarray(sec[:, 0]), np.ascontiguousarray(sec[:, 1]), \
+            np.ascontiguousarray(sec[:, 2])
+
+
+def _sector_count(nsites: int, na: int, nb: int) -> int:
+    """Number of occupation states of nsites spatial orbitals with na alpha and
+    nb beta electrons."""
+    if na < 0 or nb < 0 or na > nsites or nb > nsites:
+        return 0
+    return math.comb(nsites, na) * math.comb(nsites, nb)
+
+
+def _allocate(weights, caps, total):
+    """Water-filling allocation of ``total`` states over sectors in proportion
+    to ``weights``, each capped at ``caps``; largest-remainder rounding."""
+    weights = np.asarray(weights, dtype=float)
+    caps = np.asarray(caps, dtype=float)
+    n = len(weights)
+    alloc = np.zeros(n)
+    free = np.ones(n, dtype=bool)
+    remaining = float(min(total, caps.sum()))
+    for _ in range(n + 1):
+        w = np.where(free, weights, 0.0)
+        if remaining <= 0 or w.sum() == 0:
+            break
+        share = remaining * w / w.sum()
+        over = free & (alloc + share > caps)
+        if not over.any():
+            alloc += share
+            remaining = 0.0
+            break
+        remaining -= (caps[over] - alloc[over]).sum()
+        alloc[over] = caps[over]
+        free &= ~over
+    target = int(round(min(total, caps.sum())))
+    base = np.floor(alloc + 1e-9).astype(int)
+    base = np.minimum(base, caps.astype(int))
+    rem = alloc - base
+    order = np.argsort(-rem, kind="stable")
+    short = target - base.sum()
+    for i in order:
+        if short <= 0:
+            break
+        if base[i] < caps[i]:
+            base[i] += 1
+            short -= 1
+    return base
+
+
+def make_block_table(L: int, N: int, twoM: int, D: int) -> BlockTable:
+    """Bond sectors for an L-site chain with N electrons and spin projection
+    twoM/2, keeping at most D states per bond.
+
+    Each bond distributes its D states over the sectors (N_l, 2M_l) in
+    proportion to dim_left * dim_right (the number of occupation states that
+    realise the sector on each side), each sector capped at
+    min(dim_left, dim_right).  The table is then made consistent: every
+    sector keeps no more states than the neighbouring bonds can reach through
+    one site.
+    """
+    if (N + twoM) % 2 != 0 or abs(twoM) > N:
+        raise ValueError("N and twoM must have equal parity and |twoM| <= N")
+    na_tot = (N + twoM) // 2
+    nb_tot = (N - twoM) // 2
+    if na_tot > L or nb_tot > L:
+        raise ValueError("too many electrons of one spin for L orbitals")
+    bonds = [[(0, 0, 1)]]
+    for k in range(1, L):
+        secs, w, caps = [], [], []
+        for na in range(0, min(k, na_tot) + 1):
+            for nb in range(0, min(k, nb_tot) + 1):
+                dl = _sector_count(k, na, nb)
+                dr = _sector_count(L - k, na_tot - na, nb_tot - nb)
+                if dl == 0 or dr == 0:
+                    continue
+                secs.append((na + nb, na - nb))
+                w.append(float(dl) * float(dr))
+                caps.append(min(dl, dr))
+        dims = _allocate(w, caps, D)
+        bond = sorted((n, m, int(d)) for (n, m), d in zip(secs, dims) if d > 0)
+        bonds.append(bond)
+    bonds.append([(N, twoM, 1)])
+
+    # consistency: a sector cannot hold more states than reachable from
+    # either neighbour bond through one site
+    def reach(bond_from, q, sign):
+        tab = {(n, m): d for (n, m, d) in bond_from}
+        return sum(tab.get((q[0] - sign * dn, q[1] - sign * dm), 0) for dn, dm in SIGMA_QN)
+
+    for _ in range(4 * L):
+        changed = False
+        for k in range(1, L):
+            nb = []
+            for (n, m, d) in bonds[k]:
+                lim = min(reach(bonds[k - 1], (n, m), +1), reach(bonds[k + 1], (n, m), -1))
+                if lim < d:
+                    changed = True
+                    d = lim
+                if d > 0:
+                    nb.append((n, m, d))
+                else:
+                    changed = True
+            bonds[k] = nb
+        if not changed:
+            break
+    return BlockTable(L=L, N=N, twoM=twoM, bonds=bonds)
+
+
+def random_blocks(table: BlockTable, seed: int) -> np.ndarray:
+    """Seeded N(0,1) entries for every site block, in canonical packed order."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(table.total_size())
+
+
+def site_offsets(table: BlockTable):
+    """Start of each site (1..L) in the concatenated packed array."""
+    offs = [0]
+    for k in range(1, table.L + 1):
+        offs.append(offs[-1] + table.site_size(k))
+    return offs
+
+
+# ---------------------------------------------------------------------------
+# Named workloads.  Hubbard chains: open boundary, hopping t, on-site U.
+
+
+@dataclass
+class HubbardWorkload:
+    name: str
+    L: int
+    t: float
+    U: float
+    N: int
+    twoS: int
+    twoM: int
+    D: int
+    G: int
+    sweeps: int
+    seed: int
+
+    def table(self) -> BlockTable:
+        return make_block_table(self.L, self.N, self.twoM, self.D)
+
+    def blocks(self) -> np.ndarray:
+        return random_blocks(self.table(), self.seed)
+
+
+def hubbard_small() -> HubbardWorkload:
+    """1D Hubbard, L=8, t=1, U=4, N=8, M=0, S=0, D=16, G=5, 4 sweeps."""
+    return HubbardWorkload("hubbard_L8_D16_G5", L=8, t=1.0, U=4.0, N=8, twoS=0, twoM=0,
+                           D=16, G=5, sweeps=4, seed=1)
+
+
+def hubbard_bench(twoS: int = 0) -> HubbardWorkload:
+    """1D Hubbard, L=32, t=1, U=8, N=32, M=0, S=0 (seed 2) or S=1 (seed 3),
+    D=256, G=9, 4 sweeps."""
+    return HubbardWorkload(f"hubbard_L32_D256_G9_S{twoS // 2}", L=32, t=1.0, U=8.0, N=32,
+                           twoS=twoS, twoM=0, D=256, G=9, sweeps=4,
+                           seed=2 if twoS == 0 else 3)
