@@ -1,0 +1,220 @@
+/*
+ * spmps.h -- C ABI of the spin-projected MPS (SP-MPS) hot path on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Li & Chan, "Spin-projected matrix product states" (SP-MPS).  The
+ * underlying MPS has definite particle number N and spin projection M
+ * (Sec. 2.2, Eq. [SPMPS2]).  The energy functional is
+ *     E = <Psi| H P |Psi> / <Psi| P |Psi>                  (Eq. [efunctional])
+ * with the projector written as a Gauss-Legendre sum over rotation angles
+ *     P = sum_g coef_g exp(-i beta_g S_y),
+ *     coef_g = (2S+1)/2 w_g d^S_MM(beta_g),  x_g = cos(beta_g)
+ * (Eqs. [PSMM], [pmpo]); exp(-i beta S_y) is a product of 4x4 local
+ * rotations (Eq. [expSy]).  A one-site sweep solves at each site the local
+ * generalised eigenproblem H_eff x = E N_eff x (Eqs. [spmpsopt],
+ * [geproblem]) and restores the canonical form (Sec. 2.3).
+ *
+ * Conventions
+ *   - Sites k = 1..L are spatial orbitals, local basis sigma = 2 n_a + n_b,
+ *     i.e. (|0>, |b>, |a>, |ab>) with |ab> = a+_alpha a+_beta |0>.
+ *   - Bond k (0..L) lies right of site k; its sectors q = (N, 2M) count the
+ *     particles and twice the spin projection of sites 1..k, sorted by
+ *     (N, 2M).  Bond 0 is (0,0) of dimension 1, bond L is (N, 2M) of
+ *     dimension 1.
+ *   - A site tensor is packed as blocks, one per (left sector a, sigma)
+ *     whose right sector a + q_sigma exists, ordered by a then sigma, each
+ *     a dense dim(a) x dim(b) row-major matrix.  The packed vector of a site
+ *     is what H_eff acts on.
+ *   - All device pointers are HIP device memory on the device that was
+ *     current at sp_init_mps; all work is ordered on the stream given there.
+ *
+ * Errors: every call returns an int status; 0 = SP_OK, > 0 = warning, < 0 =
+ * error.  sp_last_error() gives a message for the calling thread.
+ */
+#ifndef SPMPS_H
+#define SPMPS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SP_OK 0
+#define SP_ENOCONV 1      /* warning: a local solve stopped at max_iter        */
+#define SP_WINEXACT 2     /* warning: G below the exact point count             */
+#define SP_EINVAL (-1)    /* invalid argument (shape, parity, range, layout)    */
+#define SP_ENORM (-2)     /* projected norm <Psi|P|Psi> vanishes (< 1e-12)      */
+#define SP_EHIP (-3)      /* HIP runtime error                                  */
+#define SP_ENOMEM (-4)    /* device allocation failed                           */
+#define SP_ESTATE (-5)    /* environments needed by the call are not built      */
+#define SP_ENAN (-6)      /* NaN or Inf met in a local solve                    */
+
+#define SP_FP64 0         /* every contraction in FP64 */
+
+typedef struct sp_handle sp_handle;
+
+/* Problem: L sites, d must be 4, N electrons, spin S = twoS/2 with projection
+ * M = twoM/2, G quadrature points.  Requires N + twoS even, N + twoM even,
+ * |twoM| <= twoS <= Omega_max (largest seniority, Eq. [exactQuadrature]),
+ * G >= 1.  G below ceil((Omega_max/2 + S + 1)/2) is allowed and makes the
+ * projector approximate (warning SP_WINEXACT). */
+typedef struct sp_problem {
+    int L;
+    int d;
+    int N;
+    int twoS;
+    int twoM;
+    int G;
+    int precision; /* SP_FP64 */
+} sp_problem;
+
+/* MPO in the operator-valued-matrix form of Sec. 2.1, Eq. [FSMPO]:
+ * w[k] (k = 0..L) are the bond dimensions with w[0] = w[L] = 1; site k
+ * (1..L) holds w[k-1]*w[k]*16 doubles, element ((a*w[k] + b)*4 + s)*4 + t
+ * = <s| O_ab |t>.  Channel 0 of every inner bond must be the left identity
+ * string (W[k]_{a,0} = delta_{a,0} I for k < L) and the last channel the
+ * right identity string (W[k]_{w[k-1]-1, b} = delta_{b, w[k]-1} I for
+ * k > 1), the triangular form of Eq. [Sfac]; every operator entry must
+ * change the particle number consistently.  Host memory, copied. */
+typedef struct sp_mpo {
+    const int* w;
+    const double* data;
+} sp_mpo;
+
+/* Bond sectors: nsec[k] sectors for bond k = 0..L; sec_n, sec_2m, sec_dim
+ * concatenated over bonds, each bond sorted by (N, 2M).  Host memory,
+ * copied.  Every sector must be reachable through one site from both
+ * neighbouring bonds with at least as many states as it holds. */
+typedef struct sp_block_table {
+    const int* nsec;
+    const int* sec_n;
+    const int* sec_2m;
+    const int* sec_dim;
+} sp_block_table;
+
+/* Local solver settings (the paper leaves the solver open; Davidson with a
+ * Euclidean-orthonormal search space, canonical orthogonalisation of the
+ * projected metric, a diagonal preconditioner and restarts). */
+typedef struct sp_sweep_opts {
+    int n_sweeps;     /* full sweeps: right-moving 1..L-1, then left L..2   */
+    double tol;       /* residual 2-norm for a unit-norm site tensor        */
+    int max_iter;     /* Ritz evaluations per local solve                   */
+    int max_sub;      /* search-space size that triggers a restart          */
+    int keep;         /* Ritz vectors kept at a restart                     */
+} sp_sweep_opts;
+
+typedef struct sp_step_report {
+    int sweep, site, dir, iters, converged, matvecs;
+    double theta;     /* local eigenvalue = projected energy after the step */
+    double pnorm;     /* x^T N_eff x for the unit-norm site tensor          */
+    double rnorm;     /* final residual norm                                */
+    double usec;      /* wall time of the step                              */
+} sp_step_report;
+
+/* Caller-owned host array of `capacity` steps; n_steps is set. */
+typedef struct sp_sweep_report {
+    int capacity;
+    int n_steps;
+    sp_step_report* steps;
+} sp_sweep_report;
+
+/* Build the state: quadrature table (Eq. [pmpo]), rotated MPO W[k] r(beta_g)
+ * for every g (Eq. [expSy]), device copies of the MPS blocks
+ * (`init_blocks`: host, packed, all sites concatenated), right-canonical
+ * form of sites L..2 by positive-diagonal LQ per left sector, and the right
+ * environments of every quadrature point.  `hip_stream` is a hipStream_t
+ * (NULL = default stream).  On success *out owns all device memory. */
+int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bonds,
+                const double* init_blocks, void* hip_stream, sp_handle** out);
+
+/* Environments (Fig. [spmpsOpt]): dir = +1 builds the left environments
+ * L_g[site] (sites 1..site) from L_g[site-1] and the current site tensor,
+ * for every g; dir = -1 builds R_g[site] (sites site..L) from R_g[site+1].
+ * site in 1..L.  SP_ESTATE if the input environment was never built. */
+int sp_env_update(sp_handle* h, int site, int dir);
+
+/* y = H_eff x and ny = N_eff x at `site` (Eq. [geproblem]) with the current
+ * environments L_g[site-1], R_g[site+1]:
+ *   y  = P_NM sum_g coef_g L_g (W[site] r_g) x R_g
+ *   ny = P_NM sum_g coef_g L_g^I r_g x R_g^I
+ * where the identity-channel environments give N_eff and P_NM keeps the
+ * (N, M) blocks of the packed layout.  x, y, ny: caller-owned device arrays
+ * of sp_site_size(site) doubles; y and ny must not alias x or each other.
+ * Asynchronous on the handle's stream. */
+int sp_heff_apply(sp_handle* h, int site, const double* x, double* y, double* ny);
+
+/* Diagonals of H_eff and N_eff at `site` (device arrays, site size). */
+int sp_heff_diag(sp_handle* h, int site, double* dh, double* dn);
+
+/* One-site sweeps (Sec. 2.3) from the current state, which must have its
+ * canonical centre at site 1 (as after sp_init_mps or a completed sweep).
+ * Each step solves the local problem, moves the centre with a
+ * positive-diagonal QR (right-moving) or LQ (left-moving) per sector and
+ * updates the environments of all g.  Returns SP_ENOCONV if any local
+ * solve stopped at max_iter.  `r` may be NULL. */
+int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r);
+
+/* Projected energy and norm at the canonical centre:
+ * E = <x|H_eff x>/<x|N_eff x>, normP = <x|N_eff x> (the spin-S weight of
+ * the underlying MPS when it is normalised).  Host scalars; synchronises. */
+int sp_energy(sp_handle* h, double* E, double* normP);
+
+/* Release all device memory of the handle. */
+int sp_destroy(sp_handle* h);
+
+/* Packed size (doubles) of a site. */
+int sp_site_size(const sp_handle* h, int site, long long* n);
+
+/* Copy a site tensor to / from host memory (packed layout).  sp_set_site
+ * leaves the environments untouched. */
+int sp_get_site(sp_handle* h, int site, double* host);
+int sp_set_site(sp_handle* h, int site, const double* host);
+
+/* Current canonical centre (1..L). */
+int sp_center(const sp_handle* h, int* site);
+
+/* Algorithmic flops of one sp_heff_apply at `site`: 2 m n k per block
+ * product of the minimal-work contraction order over non-zero blocks only
+ * (L_g x, the W r mixing, then R_g, for both H_eff and N_eff). */
+int sp_heff_flops(const sp_handle* h, int site, double* flops);
+
+/* Timing of the three launches of sp_heff_apply at `site` (left product,
+ * W r mixing, right product with the g reduction), each averaged over
+ * `reps` launches with HIP events on the handle's stream.  out[0..2]: mean
+ * milliseconds per launch; out[3..5]: algorithmic flops per launch;
+ * out[6..8]: algorithmic bytes per launch (every array read or written once:
+ * environments, site vector, intermediates, outputs).  x, y, ny as in
+ * sp_heff_apply.  Synchronises. */
+int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y, double* ny, double* out);
+
+/* Message of the last error on this thread. */
+const char* sp_last_error(void);
+
+/* ---- host-only helpers (no GPU needed) ----------------------------------- */
+
+/* Quadrature of Eq. [pmpo] with the (2S+1)/2 factor of Eq. [PSMM]: nodes x
+ * ascending (Newton on the Legendre polynomial), weights w, and
+ * coef_g = (2S+1)/2 w_g d^S_MM(arccos x_g).  Arrays of G doubles. */
+int sp_quadrature(int G, int twoS, int twoM, double* x, double* w, double* coef);
+
+/* Exact point count ceil((Omega_max/2 + S + 1)/2), Eq. [exactQuadrature]. */
+int sp_exact_points(int N, int K, int twoS, int twoM);
+
+/* MPO builders in the layout of sp_mpo.  Call with data == NULL to get the
+ * bond dimensions in w (L+1 ints) and the element count in *n; then again
+ * with data of that size.  Hubbard: open chain, hopping t, on-site U,
+ * bond dimension 6.  S2: total spin squared, bond dimension 5 (Eq. [Sfac]).
+ * Identity: bond dimension 1. */
+int sp_mpo_hubbard(int L, double t, double U, int* w, double* data, long long* n);
+int sp_mpo_s2(int L, int* w, double* data, long long* n);
+int sp_mpo_identity(int L, int* w, double* data, long long* n);
+
+/* Symmetric eigensolver used for the Davidson subspace problem
+ * (Householder tridiagonalisation + implicit QL): a is n x n row-major
+ * (destroyed), eigenvalues ascending in ev, eigenvectors as columns of vec
+ * (n x n row-major). */
+int sp_small_eigh(int n, double* a, double* ev, double* vec);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPMPS_H */

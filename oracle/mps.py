@@ -90,6 +90,17 @@ class OracleMPS:
         if pos != len(packed):
             raise ValueError("packed size does not match the block table")
 
+    def dense_site(self, k, packed):
+        """Dense-padded array of site k from a packed vector."""
+        A = np.zeros(self.mask[k - 1].shape)
+        pos = 0
+        for (s, sa, sb) in self.site_blocks(k):
+            r = sa.stop - sa.start
+            c = sb.stop - sb.start
+            A[s, sa, sb] = packed[pos:pos + r * c].reshape(r, c)
+            pos += r * c
+        return A
+
     def site_packed(self, k, A=None):
         A = self.A[k - 1] if A is None else A
         return np.concatenate([A[s, sa, sb].ravel() for (s, sa, sb) in self.site_blocks(k)])

@@ -1,0 +1,273 @@
+"""Python binding of libspmps.so, the spin-projected MPS (SP-MPS) hot path on
+an AMD MI355X (gfx950).
+
+Argument marshalling only: every step of the method runs in the HIP library
+(``csrc/``); see ``include/spmps.h`` for the contract of each call.  Device
+buffers are torch tensors on the current HIP device; host inputs are NumPy
+arrays.  The library must be built first (``paper_1703_04789_amd/build.py``);
+importing works without it, but every call raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspmps.so")
+
+SP_OK, SP_ENOCONV, SP_WINEXACT = 0, 1, 2
+SP_EINVAL, SP_ENORM, SP_EHIP, SP_ENOMEM, SP_ESTATE, SP_ENAN = -1, -2, -3, -4, -5, -6
+SP_FP64 = 0
+
+EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_sweep", "sp_energy",
+           "sp_destroy", "sp_site_size", "sp_get_site", "sp_set_site", "sp_center", "sp_heff_flops",
+           "sp_heff_profile",
+           "sp_last_error", "sp_quadrature", "sp_exact_points", "sp_mpo_hubbard", "sp_mpo_s2",
+           "sp_mpo_identity", "sp_small_eigh"]
+
+
+class SpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("d", ctypes.c_int), ("N", ctypes.c_int), ("twoS", ctypes.c_int),
+                ("twoM", ctypes.c_int), ("G", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class _Mpo(ctypes.Structure):
+    _fields_ = [("w", ctypes.POINTER(ctypes.c_int)), ("data", ctypes.POINTER(ctypes.c_double))]
+
+
+class _BlockTable(ctypes.Structure):
+    _fields_ = [("nsec", ctypes.POINTER(ctypes.c_int)), ("sec_n", ctypes.POINTER(ctypes.c_int)),
+                ("sec_2m", ctypes.POINTER(ctypes.c_int)), ("sec_dim", ctypes.POINTER(ctypes.c_int))]
+
+
+class _SweepOpts(ctypes.Structure):
+    _fields_ = [("n_sweeps", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("max_sub", ctypes.c_int), ("keep", ctypes.c_int)]
+
+
+class _StepReport(ctypes.Structure):
+    _fields_ = [("sweep", ctypes.c_int), ("site", ctypes.c_int), ("dir", ctypes.c_int), ("iters", ctypes.c_int),
+                ("converged", ctypes.c_int), ("matvecs", ctypes.c_int), ("theta", ctypes.c_double),
+                ("pnorm", ctypes.c_double), ("rnorm", ctypes.c_double), ("usec", ctypes.c_double)]
+
+
+class _SweepReport(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int), ("n_steps", ctypes.c_int), ("steps", ctypes.POINTER(_StepReport))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libspmps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1703_04789_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, ip, dp = ctypes.c_void_p, P(ctypes.c_int), P(ctypes.c_double)
+    sig = {
+        "sp_init_mps": [P(_Problem), P(_Mpo), P(_BlockTable), dp, vp, P(vp)],
+        "sp_env_update": [vp, ctypes.c_int, ctypes.c_int],
+        "sp_heff_apply": [vp, ctypes.c_int, vp, vp, vp],
+        "sp_heff_diag": [vp, ctypes.c_int, vp, vp],
+        "sp_sweep": [vp, P(_SweepOpts), P(_SweepReport)],
+        "sp_energy": [vp, dp, dp],
+        "sp_destroy": [vp],
+        "sp_site_size": [vp, ctypes.c_int, P(ctypes.c_longlong)],
+        "sp_get_site": [vp, ctypes.c_int, dp],
+        "sp_set_site": [vp, ctypes.c_int, dp],
+        "sp_center": [vp, ip],
+        "sp_heff_flops": [vp, ctypes.c_int, dp],
+        "sp_heff_profile": [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, dp],
+        "sp_quadrature": [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp],
+        "sp_exact_points": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+        "sp_mpo_hubbard": [ctypes.c_int, ctypes.c_double, ctypes.c_double, ip, dp, P(ctypes.c_longlong)],
+        "sp_mpo_s2": [ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
+        "sp_mpo_identity": [ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
+        "sp_small_eigh": [ctypes.c_int, dp, dp, dp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.sp_last_error.argtypes = []
+    L.sp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc < 0:
+        raise SpError(rc, lib().sp_last_error().decode())
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _dev(t):
+    """Device pointer of a contiguous float64 torch tensor."""
+    if t.dtype.__str__() != "torch.float64" or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous float64 tensors on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---- host-only helpers ---------------------------------------------------
+
+def quadrature(G, twoS, twoM):
+    x, w, c = np.zeros(G), np.zeros(G), np.zeros(G)
+    _check(lib().sp_quadrature(G, twoS, twoM, _dptr(x), _dptr(w), _dptr(c)))
+    return x, w, c
+
+
+def exact_points(N, K, twoS, twoM=0):
+    return lib().sp_exact_points(N, K, twoS, twoM)
+
+
+def _mpo(fn, L, *args):
+    w = np.zeros(L + 1, dtype=np.int32)
+    n = ctypes.c_longlong(0)
+    _check(fn(L, *args, _iptr(w), None, ctypes.byref(n)))
+    data = np.zeros(n.value)
+    _check(fn(L, *args, _iptr(w), _dptr(data), ctypes.byref(n)))
+    return w, data
+
+
+def mpo_hubbard(L, t, U):
+    return _mpo(lib().sp_mpo_hubbard, L, ctypes.c_double(t), ctypes.c_double(U))
+
+
+def mpo_s2(L):
+    return _mpo(lib().sp_mpo_s2, L)
+
+
+def mpo_identity(L):
+    return _mpo(lib().sp_mpo_identity, L)
+
+
+def small_eigh(a):
+    a = np.ascontiguousarray(a, dtype=np.float64).copy()
+    n = a.shape[0]
+    ev, vec = np.zeros(n), np.zeros((n, n))
+    _check(lib().sp_small_eigh(n, _dptr(a), _dptr(ev), _dptr(vec)))
+    return ev, vec
+
+
+# ---- the SP-MPS state ------------------------------------------------------
+
+class SPMPS:
+    """Handle of one SP-MPS state on the current HIP device.
+
+    ``table``: an object with ``flat()`` returning (nsec, sec_n, sec_2m,
+    sec_dim) and attributes L, N, twoM; ``blocks``: packed initial site
+    tensors; ``mpo``: (w, data) as returned by :func:`mpo_hubbard`.
+    """
+
+    def __init__(self, table, blocks, mpo, twoS, G, stream=None):
+        import torch
+        self._torch = torch
+        nsec, sn, s2m, sdim = (np.ascontiguousarray(a, dtype=np.int32) for a in table.flat())
+        self._keep = (nsec, sn, s2m, sdim)
+        self.L, self.N, self.twoM, self.twoS, self.G = table.L, table.N, table.twoM, twoS, G
+        prob = _Problem(self.L, 4, self.N, twoS, self.twoM, G, SP_FP64)
+        w, data = mpo
+        w = np.ascontiguousarray(w, dtype=np.int32)
+        data = np.ascontiguousarray(data, dtype=np.float64)
+        m = _Mpo(_iptr(w), _dptr(data))
+        bt = _BlockTable(_iptr(nsec), _iptr(sn), _iptr(s2m), _iptr(sdim))
+        blocks = np.ascontiguousarray(blocks, dtype=np.float64)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        self.status = _check(lib().sp_init_mps(ctypes.byref(prob), ctypes.byref(m), ctypes.byref(bt), _dptr(blocks),
+                                               ctypes.c_void_p(stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().sp_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def site_size(self, k):
+        n = ctypes.c_longlong(0)
+        _check(lib().sp_site_size(self._h, k, ctypes.byref(n)))
+        return n.value
+
+    def get_site(self, k):
+        out = np.zeros(self.site_size(k))
+        _check(lib().sp_get_site(self._h, k, _dptr(out)))
+        return out
+
+    def set_site(self, k, host):
+        host = np.ascontiguousarray(host, dtype=np.float64)
+        _check(lib().sp_set_site(self._h, k, _dptr(host)))
+
+    def env_update(self, k, direction):
+        _check(lib().sp_env_update(self._h, k, direction))
+
+    def heff_apply(self, k, x, y, ny):
+        _check(lib().sp_heff_apply(self._h, k, _dev(x), _dev(y), _dev(ny)))
+
+    def heff_diag(self, k, dh, dn):
+        _check(lib().sp_heff_diag(self._h, k, _dev(dh), _dev(dn)))
+
+    def heff_flops(self, k):
+        f = ctypes.c_double(0)
+        _check(lib().sp_heff_flops(self._h, k, ctypes.byref(f)))
+        return f.value
+
+    def heff_profile(self, k, x, y, ny, reps=20):
+        """Per-launch timing of H_eff x at site k: dict of (ms, flops, bytes)
+        for the left product, the mixing and the right product."""
+        out = np.zeros(9)
+        _check(lib().sp_heff_profile(self._h, k, reps, _dev(x), _dev(y), _dev(ny), _dptr(out)))
+        names = ("left_product", "mixing", "right_product")
+        return {n: dict(ms=out[i], flops=out[3 + i], bytes=out[6 + i]) for i, n in enumerate(names)}
+
+    def center(self):
+        c = ctypes.c_int(0)
+        _check(lib().sp_center(self._h, ctypes.byref(c)))
+        return c.value
+
+    def energy(self):
+        E, p = ctypes.c_double(0), ctypes.c_double(0)
+        _check(lib().sp_energy(self._h, ctypes.byref(E), ctypes.byref(p)))
+        return E.value, p.value
+
+    def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8):
+        """Run sweeps; returns (status, list of per-step dicts)."""
+        L = self.L
+        cap = max(1, n_sweeps * max(1, 2 * (L - 1)))
+        steps = (_StepReport * cap)()
+        rep = _SweepReport(cap, 0, steps)
+        opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep)
+        rc = _check(lib().sp_sweep(self._h, ctypes.byref(opts), ctypes.byref(rep)))
+        out = []
+        for i in range(rep.n_steps):
+            s = steps[i]
+            out.append(dict(sweep=s.sweep, site=s.site, dir=s.dir, iters=s.iters, converged=bool(s.converged),
+                            matvecs=s.matvecs, theta=s.theta, pnorm=s.pnorm, rnorm=s.rnorm, usec=s.usec))
+        return rc, out

@@ -1,0 +1,19 @@
+// Host-side numerics of the SP-MPS library.
+#pragma once
+#include <array>
+
+namespace sph {
+
+void gauss_legendre(int G, double* x, double* w);
+double wigner_d_diag(int twoJ, int twoM, double x);
+int max_seniority(int N, int twoM, int K);
+int exact_points(int N, int K, int twoS, int twoM);
+// x, w: nodes/weights; c = cos(beta/2), s = sin(beta/2); coef_g
+void projector_quadrature(int G, int twoS, int twoM, double* x, double* w, double* c, double* s,
+                          double* coef);
+int mpo_hubbard(int L, double t, double U, int* w, double* data, long long* n);
+int mpo_s2(int L, int* w, double* data, long long* n);
+int mpo_identity(int L, int* w, double* data, long long* n);
+int sym_eigh(int n, double* a, double* ev, double* vec);
+
+}  // namespace sph

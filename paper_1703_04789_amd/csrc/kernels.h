@@ -1,0 +1,89 @@
+// Device kernels of the SP-MPS hot path (gfx950) and their launch wrappers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace spk {
+
+constexpr int kMaxBufs = 8;
+
+// One output block C (M x N, row stride ldc) = sum over terms of
+// coef[cidx] * A(M x K) B(K x N); accumulate != 0 adds to C.  A term with
+// strides (a_rs, a_cs) reads A(r, k) = bufs[a_buf][a_off + r*a_rs + k*a_cs].
+struct BTask {
+    long long c_off;
+    int c_buf, M, N, ldc;
+    int t0, t1, accumulate, pad;
+};
+struct BTerm {
+    long long a_off, b_off;
+    int a_buf, b_buf;
+    int a_rs, a_cs, b_rs, b_cs;
+    int K, cidx;
+};
+// C[e] = sum_terms coef[cidx] * A[a_off + e], e < n.
+struct CTask {
+    long long c_off;
+    int c_buf, n, t0, t1;
+};
+struct CTerm {
+    long long a_off;
+    int a_buf, cidx;
+};
+struct BufSet {
+    double* p[kMaxBufs];
+};
+
+// diagonal of H_eff / N_eff for one packed block
+struct DiagBlk {
+    long long x_off;
+    long long l_off0;  // offset of (row ro) diagonal start inside a left env block, per term
+    int rows, cols, sigma, t0, t1;
+    int pad;
+};
+struct DiagTerm {
+    long long l_off;  // env block offset (per g) in the left env + ro*(ld+1)
+    long long r_off;  // env block offset (per g) in the right env + co*(ld+1)
+    int l_ld, r_ld;   // row length of the env blocks (diagonal stride ld+1)
+    int cidx, pad;
+};
+
+// QR of one gathered sector matrix: pieces are row-major blocks of a packed
+// site tensor; transposed pieces contribute their columns as rows.
+struct QrTask {
+    long long scratch_off;  // rows*cols doubles of scratch (column-major)
+    long long r_off;        // cols*cols output (row-major)
+    int rows, cols, p0, p1;
+};
+struct QrPiece {
+    long long off;  // block offset in the site tensor
+    int prow, pcol;  // stored block dims (row-major, ld = pcol)
+    int transposed, row0;  // row offset in the gathered matrix
+};
+
+void bgemm(hipStream_t s, const BTask* tasks, int ntasks, const BTerm* terms, BufSet bufs,
+           const double* coef);
+void combine(hipStream_t s, const CTask* tasks, int ntasks, const CTerm* terms, BufSet bufs,
+             const double* coef);
+void heff_diag(hipStream_t s, const DiagBlk* blks, int nblk, const DiagTerm* terms,
+               const double* lenv, long long lsize, const double* renv, long long rsize,
+               const double* coef, int ncoef, int G, double* out);
+void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* pieces,
+                double* site, double* scratch, double* rout);
+
+// Davidson vector kernels (n = vector length, ld = stride between vectors)
+void normalize(hipStream_t s, const double* in, double* out, int n, double* norm_out);
+void ritz(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
+          const double* a, const double* theta, const double* dh, const double* dn, int n,
+          double floor_, double* x, double* t, double* partials, int* nblocks_out);
+void multidot(hipStream_t s, const double* A, long long ld, int m, const double* u, int n,
+              double* out);
+void sub_combo(hipStream_t s, const double* A, long long ld, int m, const double* c, double* t,
+               int n);
+void basis_rotate(hipStream_t s, const double* A, long long ld, int m, const double* Q, int keep,
+                  double* out, int n);
+void gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
+          int n, const double* partials, int npart, double* out);
+void scale(hipStream_t s, double* x, int n, const double* factor_inv_sqrt_of);
+
+}  // namespace spk

@@ -1,0 +1,1699 @@
+// Host runtime and C ABI of the SP-MPS hot path (one MI355X, FP64).
+//
+// Holds the block structure of an (N, 2M)-symmetric MPS, the quadrature of
+// the spin projector (Eqs. [PSMM], [pmpo]), the rotated MPO W[k] r(beta_g)
+// (Eq. [expSy]), the environments of every quadrature point, and for every
+// site the precomputed task lists that the device kernels execute:
+//
+//   left  pass:  T_g = L_g[k-1] x            (env blocks (N_bra, N_ket) times
+//                                             (N, M) blocks of the site)
+//                V_g = sum W~_g T_g           (W~_g = W[k] r_g, the rotation
+//                                             acting on the ket index)
+//   y   = P_NM sum_g coef_g V_g R_g[k+1]^T    (H_eff x)
+//   ny  = P_NM sum_g coef_g r_g T_g R^I_g^T   (N_eff x, identity channels)
+//   L_g[k] = A^T V_g                          (left environment update)
+//   right pass mirrors it for R_g[k].
+//
+// The environments are blocked by particle number only: the rotation
+// exp(-i beta S_y) mixes M, so every (N_bra, N_ket) block is dense in M
+// (the subduction described in Sec. 2.3).  Site tensors and H_eff vectors
+// keep the (N, M) blocks.
+#include "spmps.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "host_linalg.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct SpError : std::runtime_error {
+    int code;
+    SpError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SP_REQUIRE(cond, msg)                                  \
+    do {                                                       \
+        if (!(cond)) throw SpError(SP_EINVAL, std::string(msg)); \
+    } while (0)
+
+inline void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) throw SpError(SP_ENOMEM, std::string(what) + ": out of device memory");
+        throw SpError(SP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+#define HIPCK(x) hip_check((x), #x)
+
+constexpr int kSigmaN[4] = {0, 1, 1, 2};
+constexpr int kSigma2M[4] = {0, -1, 1, 0};
+
+template <class T>
+struct DArr {  // owned device array
+    T* p = nullptr;
+    size_t n = 0;
+    DArr() = default;
+    DArr(const DArr&) = delete;
+    DArr& operator=(const DArr&) = delete;
+    DArr(DArr&& o) noexcept : p(o.p), n(o.n) {
+        o.p = nullptr;
+        o.n = 0;
+    }
+    DArr& operator=(DArr&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DArr() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        if (count) HIPCK(hipMalloc(&p, count * sizeof(T)));
+    }
+    void upload(const std::vector<T>& v, hipStream_t s) {
+        alloc(v.size());
+        if (!v.empty()) HIPCK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+};
+
+struct Sector {
+    int n, m2, dim, off, nb, ro;
+};
+struct NBlock {
+    int n, dim, off, s0, s1;
+};
+struct Bond {
+    std::vector<Sector> sec;
+    std::vector<NBlock> nb;
+    int D = 0;
+    std::map<std::pair<int, int>, int> sidx;
+    std::map<int, int> nidx;
+    int sector(int n, int m2) const {
+        auto it = sidx.find({n, m2});
+        return it == sidx.end() ? -1 : it->second;
+    }
+    int nblock(int n) const {
+        auto it = nidx.find(n);
+        return it == nidx.end() ? -1 : it->second;
+    }
+};
+struct XBlk {
+    int sa, s, sb, rows, cols;
+    long long off;
+};
+struct SiteInfo {
+    std::vector<XBlk> blk;
+    long long size = 0, goff = 0;
+    std::map<std::pair<int, int>, int> by_sa_s;  // (left sector, sigma) -> block
+    int find(int sa, int s) const {
+        auto it = by_sa_s.find({sa, s});
+        return it == by_sa_s.end() ? -1 : it->second;
+    }
+};
+struct EnvBlk {
+    int c, i, j, rows, cols;
+    long long off;
+};
+struct EnvLayout {
+    int nc = 0, nnb = 0;
+    std::vector<EnvBlk> blk;
+    std::vector<int> idx;  // c * nnb + i -> block
+    long long size = 0;    // per quadrature point
+    int find(int c, int i) const { return idx[size_t(c) * nnb + i]; }
+};
+
+// task list of one launch (host copy + device copy)
+struct BList {
+    std::vector<spk::BTask> tasks;
+    std::vector<spk::BTerm> terms;
+    DArr<spk::BTask> dtasks;
+    DArr<spk::BTerm> dterms;
+    double flops = 0.0;
+    void add_task(int c_buf, long long c_off, int M, int N, int ldc, int accumulate = 0) {
+        spk::BTask t{};
+        t.c_off = c_off;
+        t.c_buf = c_buf;
+        t.M = M;
+        t.N = N;
+        t.ldc = ldc;
+        t.t0 = t.t1 = int(terms.size());
+        t.accumulate = accumulate;
+        tasks.push_back(t);
+    }
+    void add_term(int a_buf, long long a_off, int a_rs, int a_cs, int b_buf, long long b_off, int b_rs,
+                  int b_cs, int K, int cidx) {
+        spk::BTerm m{};
+        m.a_off = a_off;
+        m.b_off = b_off;
+        m.a_buf = a_buf;
+        m.b_buf = b_buf;
+        m.a_rs = a_rs;
+        m.a_cs = a_cs;
+        m.b_rs = b_rs;
+        m.b_cs = b_cs;
+        m.K = K;
+        m.cidx = cidx;
+        terms.push_back(m);
+        tasks.back().t1 = int(terms.size());
+        flops += 2.0 * tasks.back().M * tasks.back().N * K;
+    }
+    void upload(hipStream_t s) {
+        dtasks.upload(tasks, s);
+        dterms.upload(terms, s);
+    }
+    void launch(hipStream_t s, const spk::BufSet& b, const double* coef) const {
+        spk::bgemm(s, dtasks.p, int(tasks.size()), dterms.p, b, coef);
+    }
+};
+struct CList {
+    std::vector<spk::CTask> tasks;
+    std::vector<spk::CTerm> terms;
+    DArr<spk::CTask> dtasks;
+    DArr<spk::CTerm> dterms;
+    double flops = 0.0;
+    void add_task(int c_buf, long long c_off, int n) {
+        spk::CTask t{};
+        t.c_off = c_off;
+        t.c_buf = c_buf;
+        t.n = n;
+        t.t0 = t.t1 = int(terms.size());
+        tasks.push_back(t);
+    }
+    void add_term(int a_buf, long long a_off, int cidx) {
+        spk::CTerm m{};
+        m.a_off = a_off;
+        m.a_buf = a_buf;
+        m.cidx = cidx;
+        terms.push_back(m);
+        tasks.back().t1 = int(terms.size());
+        flops += 2.0 * tasks.back().n;
+    }
+    void upload(hipStream_t s) {
+        dtasks.upload(tasks, s);
+        dterms.upload(terms, s);
+    }
+    void launch(hipStream_t s, const spk::BufSet& b, const double* coef) const {
+        spk::combine(s, dtasks.p, int(tasks.size()), dterms.p, b, coef);
+    }
+};
+
+// buffer slots of a launch
+enum Buf { B_ENVL = 0, B_ENVR = 1, B_X = 2, B_T = 3, B_V = 4, B_Y = 5, B_NY = 6, B_OUT = 7 };
+
+struct SitePlan {
+    // coefficient table [G][nc]
+    int nW = 0, nc = 0;
+    std::vector<std::array<int, 4>> went;  // (a, b, s, u) of the rotated MPO pattern
+    std::vector<double> coef_h;
+    DArr<double> coef;
+    int c_wt(int e) const { return e; }
+    int c_cwt(int e) const { return nW + e; }
+    int c_g() const { return 2 * nW; }
+    int c_gr(int s, int u) const { return 2 * nW + 1 + 4 * s + u; }
+    int c_one() const { return 2 * nW + 17; }
+    // scratch sizes per quadrature point
+    long long Tsize = 0, Vsize = 0, Zsize = 0, Ztsize = 0;
+    BList p1, yout, envl_out, p1r, envr_out;
+    CList mixl, mixr;
+    double heff_flops = 0.0;
+    // diagonal
+    std::vector<spk::DiagBlk> dblk_h, dblk_n;
+    std::vector<spk::DiagTerm> dterm_h, dterm_n;
+    DArr<spk::DiagBlk> ddblk_h, ddblk_n;
+    DArr<spk::DiagTerm> ddterm_h, ddterm_n;
+    // gauge moves
+    std::vector<spk::QrTask> qr_tasks, lq_tasks;
+    std::vector<spk::QrPiece> qr_pieces, lq_pieces;
+    DArr<spk::QrTask> dqr_tasks, dlq_tasks;
+    DArr<spk::QrPiece> dqr_pieces, dlq_pieces;
+    long long qr_scratch = 0, lq_scratch = 0, qr_rsize = 0, lq_rsize = 0;
+    std::vector<long long> qr_roff;  // per right sector of bond k
+    std::vector<long long> lq_roff;  // per left sector of bond k-1
+    BList absorb_right;  // R of site k into site k+1
+    BList absorb_left;   // L of site k into site k-1
+};
+
+}  // namespace
+
+struct sp_handle {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int L = 0, N = 0, twoS = 0, twoM = 0, G = 0;
+    bool inexact = false;
+    std::vector<double> qx, qw, qc, qs, qcoef;
+    std::vector<int> w;                    // MPO bond dimensions
+    std::vector<std::vector<int>> dn;      // per bond, per channel: particle change
+    std::vector<std::vector<double>> W;    // per site (index k-1)
+    std::vector<Bond> bonds;
+    std::vector<SiteInfo> sites;           // index k-1
+    std::vector<EnvLayout> env;            // per bond
+    std::vector<DArr<double>> envL, envR;  // per bond, G * size
+    std::vector<char> Lvalid, Rvalid;
+    DArr<double> mps;
+    long long mps_size = 0, max_site = 0;
+    std::vector<SitePlan> plan;            // index k-1
+    DArr<double> T, V, qr_scratch, qr_r, tmp_site;
+    long long T_cap = 0, V_cap = 0, qr_scratch_cap = 0, qr_r_cap = 0;
+    int center = 1;
+    // Davidson workspace
+    int dav_sub = 0;
+    long long ld = 0;
+    DArr<double> dV, dHV, dNV, dRot, dx, dt, ddh, ddn, dpart, dsmall, dy, dny;
+    double* pin = nullptr;  // pinned host staging
+    size_t pin_n = 0;
+    ~sp_handle() {
+        if (pin) (void)hipHostFree(pin);
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// setup
+
+void build_bonds(sp_handle* h, const sp_block_table* bt) {
+    const int L = h->L;
+    h->bonds.assign(L + 1, Bond{});
+    long long pos = 0;
+    for (int k = 0; k <= L; ++k) {
+        Bond& b = h->bonds[k];
+        const int ns = bt->nsec[k];
+        SP_REQUIRE(ns >= 1, "every bond needs at least one sector");
+        int off = 0;
+        for (int i = 0; i < ns; ++i, ++pos) {
+            Sector s{bt->sec_n[pos], bt->sec_2m[pos], bt->sec_dim[pos], off, -1, 0};
+            SP_REQUIRE(s.dim >= 1, "sector dimensions must be positive");
+            if (i > 0) {
+                const Sector& p = b.sec.back();
+                SP_REQUIRE(p.n < s.n || (p.n == s.n && p.m2 < s.m2), "sectors must be sorted by (N, 2M)");
+            }
+            off += s.dim;
+            b.sec.push_back(s);
+        }
+        b.D = off;
+        for (int i = 0; i < ns; ++i) {
+            Sector& s = b.sec[i];
+            if (b.nb.empty() || b.nb.back().n != s.n) b.nb.push_back(NBlock{s.n, 0, s.off, i, i});
+            NBlock& nb = b.nb.back();
+            s.nb = int(b.nb.size()) - 1;
+            s.ro = nb.dim;
+            nb.dim += s.dim;
+            nb.s1 = i + 1;
+            b.sidx[{s.n, s.m2}] = i;
+        }
+        for (int i = 0; i < int(b.nb.size()); ++i) b.nidx[b.nb[i].n] = i;
+    }
+    SP_REQUIRE(h->bonds[0].sec.size() == 1 && h->bonds[0].sec[0].n == 0 && h->bonds[0].sec[0].m2 == 0 &&
+                   h->bonds[0].sec[0].dim == 1,
+               "bond 0 must be the single sector (0, 0) of dimension 1");
+    SP_REQUIRE(h->bonds[L].sec.size() == 1 && h->bonds[L].sec[0].n == h->N &&
+                   h->bonds[L].sec[0].m2 == h->twoM && h->bonds[L].sec[0].dim == 1,
+               "bond L must be the single sector (N, 2M) of dimension 1");
+    // reachability: a sector cannot hold more states than its neighbours reach
+    for (int k = 1; k < L; ++k) {
+        for (const Sector& s : h->bonds[k].sec) {
+            int left = 0, right = 0;
+            for (int q = 0; q < 4; ++q) {
+                int a = h->bonds[k - 1].sector(s.n - kSigmaN[q], s.m2 - kSigma2M[q]);
+                if (a >= 0) left += h->bonds[k - 1].sec[a].dim;
+                int c = h->bonds[k + 1].sector(s.n + kSigmaN[q], s.m2 + kSigma2M[q]);
+                if (c >= 0) right += h->bonds[k + 1].sec[c].dim;
+            }
+            SP_REQUIRE(s.dim <= left && s.dim <= right,
+                       "block table: a sector is wider than its support in a neighbouring bond");
+        }
+    }
+    // site blocks in canonical order
+    h->sites.assign(L, SiteInfo{});
+    long long goff = 0;
+    for (int k = 1; k <= L; ++k) {
+        SiteInfo& si = h->sites[k - 1];
+        si.goff = goff;
+        const Bond& bl = h->bonds[k - 1];
+        const Bond& br = h->bonds[k];
+        long long off = 0;
+        for (int a = 0; a < int(bl.sec.size()); ++a) {
+            for (int q = 0; q < 4; ++q) {
+                const int b = br.sector(bl.sec[a].n + kSigmaN[q], bl.sec[a].m2 + kSigma2M[q]);
+                if (b < 0) continue;
+                XBlk x{a, q, b, bl.sec[a].dim, br.sec[b].dim, off};
+                si.by_sa_s[{a, q}] = int(si.blk.size());
+                si.blk.push_back(x);
+                off += (long long)x.rows * x.cols;
+            }
+        }
+        si.size = off;
+        SP_REQUIRE(off > 0, "a site has no allowed block");
+        goff += off;
+        h->max_site = std::max(h->max_site, off);
+    }
+    h->mps_size = goff;
+}
+
+void build_mpo(sp_handle* h, const sp_mpo* Wm) {
+    const int L = h->L;
+    h->w.assign(Wm->w, Wm->w + L + 1);
+    SP_REQUIRE(h->w[0] == 1 && h->w[L] == 1, "MPO: w[0] and w[L] must be 1");
+    for (int k = 0; k <= L; ++k) SP_REQUIRE(h->w[k] >= 1 && h->w[k] <= 4096, "MPO: bad bond dimension");
+    h->W.assign(L, {});
+    long long pos = 0;
+    for (int k = 1; k <= L; ++k) {
+        const long long n = (long long)h->w[k - 1] * h->w[k] * 16;
+        h->W[k - 1].assign(Wm->data + pos, Wm->data + pos + n);
+        pos += n;
+    }
+    // particle change of every channel, propagated from bond 0
+    h->dn.assign(L + 1, {});
+    h->dn[0] = {0};
+    for (int k = 1; k <= L; ++k) {
+        const int wl = h->w[k - 1], wr = h->w[k];
+        std::vector<int> d(wr, INT32_MIN);
+        const auto& Wk = h->W[k - 1];
+        for (int a = 0; a < wl; ++a)
+            for (int b = 0; b < wr; ++b)
+                for (int s = 0; s < 4; ++s)
+                    for (int t = 0; t < 4; ++t) {
+                        const double v = Wk[((size_t(a) * wr + b) * 4 + s) * 4 + t];
+                        if (v == 0.0) continue;
+                        const int val = h->dn[k - 1][a] + kSigmaN[s] - kSigmaN[t];
+                        if (d[b] == INT32_MIN) d[b] = val;
+                        SP_REQUIRE(d[b] == val, "MPO: an operator entry changes the particle number inconsistently");
+                    }
+        for (int b = 0; b < wr; ++b)
+            if (d[b] == INT32_MIN) d[b] = 0;  // channel never reached: unused
+        h->dn[k] = d;
+    }
+    SP_REQUIRE(h->dn[L][0] == 0, "MPO: the full operator must conserve the particle number");
+    // identity channels: column 0 (k < L) and the last row (k > 1)
+    auto op = [&](int k, int a, int b, int s, int t) {
+        return h->W[k - 1][((size_t(a) * h->w[k] + b) * 4 + s) * 4 + t];
+    };
+    for (int k = 1; k <= L; ++k) {
+        const int wl = h->w[k - 1], wr = h->w[k];
+        if (k < L)
+            for (int a = 0; a < wl; ++a)
+                for (int s = 0; s < 4; ++s)
+                    for (int t = 0; t < 4; ++t)
+                        SP_REQUIRE(op(k, a, 0, s, t) == ((a == 0 && s == t) ? 1.0 : 0.0),
+                                   "MPO: channel 0 must be the left identity string");
+        if (k > 1)
+            for (int b = 0; b < wr; ++b)
+                for (int s = 0; s < 4; ++s)
+                    for (int t = 0; t < 4; ++t)
+                        SP_REQUIRE(op(k, wl - 1, b, s, t) == ((b == wr - 1 && s == t) ? 1.0 : 0.0),
+                                   "MPO: the last channel must be the right identity string");
+    }
+}
+
+void build_env_layouts(sp_handle* h) {
+    const int L = h->L;
+    h->env.assign(L + 1, EnvLayout{});
+    for (int k = 0; k <= L; ++k) {
+        EnvLayout& e = h->env[k];
+        const Bond& b = h->bonds[k];
+        e.nc = h->w[k];
+        e.nnb = int(b.nb.size());
+        e.idx.assign(size_t(e.nc) * e.nnb, -1);
+        long long off = 0;
+        for (int c = 0; c < e.nc; ++c)
+            for (int i = 0; i < e.nnb; ++i) {
+                const int j = b.nblock(b.nb[i].n - h->dn[k][c]);
+                if (j < 0) continue;
+                e.idx[size_t(c) * e.nnb + i] = int(e.blk.size());
+                e.blk.push_back(EnvBlk{c, i, j, b.nb[i].dim, b.nb[j].dim, off});
+                off += (long long)b.nb[i].dim * b.nb[j].dim;
+            }
+        e.size = off;
+    }
+    SP_REQUIRE(h->env[0].size == 1 && h->env[L].size == 1, "boundary environments must be 1x1");
+    h->Lvalid.assign(L + 1, 0);
+    h->Rvalid.assign(L + 1, 0);
+}
+
+void alloc_envs(sp_handle* h) {
+    const int L = h->L;
+    h->envL.resize(L + 1);
+    h->envR.resize(L + 1);
+    for (int k = 0; k <= L; ++k) {
+        h->envL[k].alloc(size_t(h->G) * h->env[k].size);
+        h->envR[k].alloc(size_t(h->G) * h->env[k].size);
+    }
+    // boundary environments: one 1x1 block equal to 1 for every g
+    std::vector<double> ones(h->G, 1.0);
+    HIPCK(hipMemcpyAsync(h->envL[0].p, ones.data(), h->G * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCK(hipMemcpyAsync(h->envR[L].p, ones.data(), h->G * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCK(hipStreamSynchronize(h->stream));
+    h->Lvalid[0] = 1;
+    h->Rvalid[L] = 1;
+}
+
+// rotated MPO W[k] r(beta_g): pattern and values
+bool rot_nonzero(int t, int u) { return (t == u) || ((t == 1 || t == 2) && (u == 1 || u == 2)); }
+double rot_value(int t, int u, double c, double s) {
+    if (t == 0 || t == 3) return t == u ? 1.0 : 0.0;
+    if (u == 0 || u == 3) return 0.0;
+    if (t == u) return c;
+    return (t == 1) ? s : -s;  // r[1][2] = s, r[2][1] = -s  (Eq. [expSy])
+}
+
+void build_plan(sp_handle* h, int k) {
+    SitePlan& P = h->plan[k - 1];
+    const int G = h->G;
+    const Bond& bl = h->bonds[k - 1];
+    const Bond& br = h->bonds[k];
+    const SiteInfo& si = h->sites[k - 1];
+    const EnvLayout& el = h->env[k - 1];  // L env at bond k-1 (also output of the right pass)
+    const EnvLayout& er = h->env[k];      // R env at bond k (also output of the left pass)
+    const int wl = h->w[k - 1], wr = h->w[k];
+    const auto& Wk = h->W[k - 1];
+    // ---- rotated MPO pattern and coefficient table
+    std::map<std::array<int, 4>, int> wpos;
+    for (int a = 0; a < wl; ++a)
+        for (int b = 0; b < wr; ++b)
+            for (int s = 0; s < 4; ++s)
+                for (int u = 0; u < 4; ++u) {
+                    bool nz = false;
+                    for (int t = 0; t < 4; ++t)
+                        if (Wk[((size_t(a) * wr + b) * 4 + s) * 4 + t] != 0.0 && rot_nonzero(t, u)) nz = true;
+                    if (nz) {
+                        wpos[{a, b, s, u}] = int(P.went.size());
+                        P.went.push_back({a, b, s, u});
+                    }
+                }
+    P.nW = int(P.went.size());
+    P.nc = 2 * P.nW + 18;
+    P.coef_h.assign(size_t(G) * P.nc, 0.0);
+    for (int g = 0; g < G; ++g) {
+        double* cf = &P.coef_h[size_t(g) * P.nc];
+        for (int e = 0; e < P.nW; ++e) {
+            const auto& q = P.went[e];
+            double v = 0.0;
+            for (int t = 0; t < 4; ++t)
+                v += Wk[((size_t(q[0]) * wr + q[1]) * 4 + q[2]) * 4 + t] * rot_value(t, q[3], h->qc[g], h->qs[g]);
+            cf[P.c_wt(e)] = v;
+            cf[P.c_cwt(e)] = h->qcoef[g] * v;
+        }
+        cf[P.c_g()] = h->qcoef[g];
+        for (int s = 0; s < 4; ++s)
+            for (int u = 0; u < 4; ++u) cf[P.c_gr(s, u)] = h->qcoef[g] * rot_value(s, u, h->qc[g], h->qs[g]);
+        cf[P.c_one()] = 1.0;
+    }
+    const long long Lsz = el.size, Rsz = er.size;
+
+    // ---- left pass, phase 1: T(eb, sigma') = L(eb) X(j, sigma', jb)
+    std::vector<long long> Toff(el.blk.size() * 4, -1);
+    std::vector<int> Tcols(el.blk.size() * 4, 0);
+    long long toff = 0;
+    for (size_t e = 0; e < el.blk.size(); ++e)
+        for (int q = 0; q < 4; ++q) {
+            const EnvBlk& eb = el.blk[e];
+            const int jb = br.nblock(bl.nb[eb.j].n + kSigmaN[q]);
+            if (jb < 0) continue;
+            Toff[e * 4 + q] = toff;
+            Tcols[e * 4 + q] = br.nb[jb].dim;
+            toff += (long long)eb.rows * br.nb[jb].dim;
+        }
+    P.Tsize = toff;
+    for (int g = 0; g < G; ++g) {
+        for (size_t e = 0; e < el.blk.size(); ++e)
+            for (int q = 0; q < 4; ++q) {
+                if (Toff[e * 4 + q] < 0) continue;
+                const EnvBlk& eb = el.blk[e];
+                const int jb = br.nblock(bl.nb[eb.j].n + kSigmaN[q]);
+                const NBlock& NB = br.nb[jb];
+                for (int sb = NB.s0; sb < NB.s1; ++sb) {
+                    const Sector& SB = br.sec[sb];
+                    const long long coff = g * P.Tsize + Toff[e * 4 + q] + SB.ro;
+                    P.p1.add_task(B_T, coff, eb.rows, SB.dim, NB.dim);
+                    const int sa = bl.sector(SB.n - kSigmaN[q], SB.m2 - kSigma2M[q]);
+                    if (sa < 0) continue;
+                    const int xb = si.find(sa, q);
+                    if (xb < 0) continue;
+                    const XBlk& X = si.blk[xb];
+                    P.p1.add_term(B_ENVL, g * Lsz + eb.off + bl.sec[sa].ro, eb.cols, 1, B_X, X.off, X.cols, 1,
+                                  X.rows, g * P.nc + P.c_one());
+                }
+            }
+    }
+    // ---- left pass, mixing: V(sigma, c', i) = sum W~[c, c', sigma, sigma'] T(eb(c, i), sigma')
+    std::map<std::array<int, 3>, long long> Voff;  // (sigma, c', i) -> offset
+    std::map<std::array<int, 3>, int> Vcols;
+    long long voff = 0;
+    struct VTerm { int sig, cp, i; long long toffv; int widx; };
+    std::vector<VTerm> vterms;
+    for (int sig = 0; sig < 4; ++sig)
+        for (int cp = 0; cp < wr; ++cp)
+            for (int i = 0; i < int(bl.nb.size()); ++i) {
+                const int nbk = br.nblock(bl.nb[i].n + kSigmaN[sig]);
+                if (nbk < 0) continue;
+                const int nbp = br.nblock(br.nb[nbk].n - h->dn[k][cp]);
+                if (nbp < 0) continue;
+                bool any = false;
+                for (int c = 0; c < wl; ++c) {
+                    const int e = el.find(c, i);
+                    if (e < 0) continue;
+                    for (int q = 0; q < 4; ++q) {
+                        auto it = wpos.find({c, cp, sig, q});
+                        if (it == wpos.end() || Toff[size_t(e) * 4 + q] < 0) continue;
+                        const int jb = br.nblock(bl.nb[el.blk[e].j].n + kSigmaN[q]);
+                        SP_REQUIRE(jb == nbp, "internal: inconsistent particle numbers in the MPO mixing");
+                        vterms.push_back({sig, cp, i, Toff[size_t(e) * 4 + q], it->second});
+                        any = true;
+                    }
+                }
+                if (!any) continue;
+                Voff[{sig, cp, i}] = voff;
+                Vcols[{sig, cp, i}] = br.nb[nbp].dim;
+                voff += (long long)bl.nb[i].dim * br.nb[nbp].dim;
+            }
+    P.Vsize = voff;
+    for (int g = 0; g < G; ++g) {
+        size_t t = 0;
+        while (t < vterms.size()) {
+            const VTerm& v0 = vterms[t];
+            const long long vo = Voff[{v0.sig, v0.cp, v0.i}];
+            const int n = bl.nb[v0.i].dim * Vcols[{v0.sig, v0.cp, v0.i}];
+            P.mixl.add_task(B_V, g * P.Vsize + vo, n);
+            while (t < vterms.size() && vterms[t].sig == v0.sig && vterms[t].cp == v0.cp && vterms[t].i == v0.i) {
+                P.mixl.add_term(B_T, g * P.Tsize + vterms[t].toffv, g * P.nc + P.c_wt(vterms[t].widx));
+                ++t;
+            }
+        }
+    }
+    // ---- y = sum_g coef_g V R^T  and  ny = sum_g coef_g r T0 R_last^T, per (N, M) block
+    const int lastR = wr - 1;
+    for (const XBlk& X : si.blk) {
+        const Sector& SA = bl.sec[X.sa];
+        const Sector& SB = br.sec[X.sb];
+        P.yout.add_task(B_Y, X.off, X.rows, X.cols, X.cols);
+        for (int g = 0; g < G; ++g)
+            for (int cp = 0; cp < wr; ++cp) {
+                auto it = Voff.find({X.s, cp, SA.nb});
+                if (it == Voff.end()) continue;
+                const int re = er.find(cp, SB.nb);
+                if (re < 0) continue;
+                const EnvBlk& RB = er.blk[re];
+                const int K = Vcols[{X.s, cp, SA.nb}];
+                SP_REQUIRE(K == RB.cols, "internal: V and R blocks disagree");
+                P.yout.add_term(B_V, g * P.Vsize + it->second + (long long)SA.ro * K, K, 1, B_ENVR,
+                                g * Rsz + RB.off + (long long)SB.ro * RB.cols, 1, RB.cols, K, g * P.nc + P.c_g());
+            }
+    }
+    for (const XBlk& X : si.blk) {
+        const Sector& SA = bl.sec[X.sa];
+        const Sector& SB = br.sec[X.sb];
+        P.yout.add_task(B_NY, X.off, X.rows, X.cols, X.cols);
+        const int e0 = el.find(0, SA.nb);
+        const int re = er.find(lastR, SB.nb);
+        if (e0 < 0 || re < 0) continue;
+        SP_REQUIRE(el.blk[e0].j == SA.nb && er.blk[re].j == SB.nb, "internal: identity channels must conserve N");
+        for (int g = 0; g < G; ++g)
+            for (int q = 0; q < 4; ++q) {
+                if (!rot_nonzero(X.s, q)) continue;
+                const long long to = Toff[size_t(e0) * 4 + q];
+                if (to < 0) continue;
+                const int K = Tcols[size_t(e0) * 4 + q];
+                const EnvBlk& RB = er.blk[re];
+                SP_REQUIRE(K == RB.cols, "internal: T and R identity blocks disagree");
+                P.yout.add_term(B_T, g * P.Tsize + to + (long long)SA.ro * K, K, 1, B_ENVR,
+                                g * Rsz + RB.off + (long long)SB.ro * RB.cols, 1, RB.cols, K,
+                                g * P.nc + P.c_gr(X.s, q));
+            }
+    }
+    // ---- left environment update: L[k](c', b, b') rows of sector s_b = sum_sigma A^T V
+    for (int g = 0; g < G; ++g)
+        for (const EnvBlk& OB : er.blk) {
+            const NBlock& NB = br.nb[OB.i];
+            for (int sb = NB.s0; sb < NB.s1; ++sb) {
+                const Sector& SB = br.sec[sb];
+                P.envl_out.add_task(B_OUT, g * Rsz + OB.off + (long long)SB.ro * OB.cols, SB.dim, OB.cols, OB.cols);
+                for (int q = 0; q < 4; ++q) {
+                    const int sa = bl.sector(SB.n - kSigmaN[q], SB.m2 - kSigma2M[q]);
+                    if (sa < 0) continue;
+                    const int xb = si.find(sa, q);
+                    if (xb < 0) continue;
+                    const XBlk& X = si.blk[xb];
+                    auto it = Voff.find({q, OB.c, bl.sec[sa].nb});
+                    if (it == Voff.end()) continue;
+                    SP_REQUIRE((Vcols[{q, OB.c, bl.sec[sa].nb}] == OB.cols), "internal: V and L blocks disagree");
+                    P.envl_out.add_term(B_X, X.off, 1, X.cols, B_V,
+                                        g * P.Vsize + it->second + (long long)bl.sec[sa].ro * OB.cols, OB.cols, 1,
+                                        X.rows, g * P.nc + P.c_one());
+                }
+            }
+        }
+    // ---- right pass, phase 1: Z(rb, sigma') rows of sector s_a' = X R(rb)^T
+    std::vector<long long> Zoff(er.blk.size() * 4, -1);
+    long long zoff = 0;
+    for (size_t e = 0; e < er.blk.size(); ++e)
+        for (int q = 0; q < 4; ++q) {
+            const EnvBlk& rb = er.blk[e];
+            const int i = bl.nblock(br.nb[rb.j].n - kSigmaN[q]);
+            if (i < 0) continue;
+            Zoff[e * 4 + q] = zoff;
+            zoff += (long long)bl.nb[i].dim * rb.rows;
+        }
+    P.Zsize = zoff;
+    for (int g = 0; g < G; ++g)
+        for (size_t e = 0; e < er.blk.size(); ++e)
+            for (int q = 0; q < 4; ++q) {
+                if (Zoff[e * 4 + q] < 0) continue;
+                const EnvBlk& rb = er.blk[e];
+                const int i = bl.nblock(br.nb[rb.j].n - kSigmaN[q]);
+                const NBlock& NA = bl.nb[i];
+                for (int sa = NA.s0; sa < NA.s1; ++sa) {
+                    const Sector& SA = bl.sec[sa];
+                    P.p1r.add_task(B_T, g * P.Zsize + Zoff[e * 4 + q] + (long long)SA.ro * rb.rows, SA.dim, rb.rows,
+                                   rb.rows);
+                    const int xb = si.find(sa, q);
+                    if (xb < 0) continue;
+                    const XBlk& X = si.blk[xb];
+                    const Sector& SB = br.sec[X.sb];
+                    P.p1r.add_term(B_X, X.off, X.cols, 1, B_ENVR, g * Rsz + rb.off + SB.ro, 1, rb.cols, X.cols,
+                                   g * P.nc + P.c_one());
+                }
+            }
+    // ---- right pass, mixing: Zt(sigma, c, i') = sum W~[c, c', sigma, sigma'] Z(rb(c', b), sigma')
+    std::map<std::array<int, 3>, long long> Ztoff;
+    std::map<std::array<int, 3>, int> Ztcols;
+    long long ztoff = 0;
+    std::vector<VTerm> zterms;
+    for (int sig = 0; sig < 4; ++sig)
+        for (int c = 0; c < wl; ++c)
+            for (int ip = 0; ip < int(bl.nb.size()); ++ip) {
+                const int ia = bl.nblock(bl.nb[ip].n + h->dn[k - 1][c]);
+                if (ia < 0) continue;
+                const int nbb = br.nblock(bl.nb[ia].n + kSigmaN[sig]);
+                if (nbb < 0) continue;
+                bool any = false;
+                for (int cp = 0; cp < wr; ++cp) {
+                    const int e = er.find(cp, nbb);
+                    if (e < 0) continue;
+                    for (int q = 0; q < 4; ++q) {
+                        auto it = wpos.find({c, cp, sig, q});
+                        if (it == wpos.end() || Zoff[size_t(e) * 4 + q] < 0) continue;
+                        const int irow = bl.nblock(br.nb[er.blk[e].j].n - kSigmaN[q]);
+                        SP_REQUIRE(irow == ip, "internal: inconsistent particle numbers in the right mixing");
+                        zterms.push_back({sig, c, ip, Zoff[size_t(e) * 4 + q], it->second});
+                        any = true;
+                    }
+                }
+                if (!any) continue;
+                Ztoff[{sig, c, ip}] = ztoff;
+                Ztcols[{sig, c, ip}] = br.nb[nbb].dim;
+                ztoff += (long long)bl.nb[ip].dim * br.nb[nbb].dim;
+            }
+    P.Ztsize = ztoff;
+    for (int g = 0; g < G; ++g) {
+        size_t t = 0;
+        while (t < zterms.size()) {
+            const VTerm& v0 = zterms[t];
+            const long long zo = Ztoff[{v0.sig, v0.cp, v0.i}];
+            const int n = bl.nb[v0.i].dim * Ztcols[{v0.sig, v0.cp, v0.i}];
+            P.mixr.add_task(B_V, g * P.Ztsize + zo, n);
+            while (t < zterms.size() && zterms[t].sig == v0.sig && zterms[t].cp == v0.cp && zterms[t].i == v0.i) {
+                P.mixr.add_term(B_T, g * P.Zsize + zterms[t].toffv, g * P.nc + P.c_wt(zterms[t].widx));
+                ++t;
+            }
+        }
+    }
+    // ---- right environment update: R(c, a, a') rows of sector s_a = sum_sigma A Zt^T
+    for (int g = 0; g < G; ++g)
+        for (const EnvBlk& OB : el.blk) {
+            const NBlock& NA = bl.nb[OB.i];
+            for (int sa = NA.s0; sa < NA.s1; ++sa) {
+                const Sector& SA = bl.sec[sa];
+                P.envr_out.add_task(B_OUT, g * Lsz + OB.off + (long long)SA.ro * OB.cols, SA.dim, OB.cols, OB.cols);
+                for (int q = 0; q < 4; ++q) {
+                    const int xb = si.find(sa, q);
+                    if (xb < 0) continue;
+                    const XBlk& X = si.blk[xb];
+                    const Sector& SB = br.sec[X.sb];
+                    auto it = Ztoff.find({q, OB.c, OB.j});
+                    if (it == Ztoff.end()) continue;
+                    const int nbcols = Ztcols[{q, OB.c, OB.j}];
+                    P.envr_out.add_term(B_X, X.off, X.cols, 1, B_V, g * P.Ztsize + it->second + SB.ro, 1, nbcols,
+                                        X.cols, g * P.nc + P.c_one());
+                }
+            }
+        }
+    // ---- diagonal of H_eff and N_eff
+    for (const XBlk& X : si.blk) {
+        const Sector& SA = bl.sec[X.sa];
+        const Sector& SB = br.sec[X.sb];
+        spk::DiagBlk db{};
+        db.x_off = X.off;
+        db.rows = X.rows;
+        db.cols = X.cols;
+        db.sigma = X.s;
+        db.t0 = int(P.dterm_h.size());
+        for (int c = 0; c < wl; ++c) {
+            const int e = el.find(c, SA.nb);
+            if (e < 0 || el.blk[e].j != SA.nb) continue;
+            for (int cp = 0; cp < wr; ++cp) {
+                const int re = er.find(cp, SB.nb);
+                if (re < 0 || er.blk[re].j != SB.nb) continue;
+                auto it = wpos.find({c, cp, X.s, X.s});
+                if (it == wpos.end()) continue;
+                spk::DiagTerm dt{};
+                dt.l_off = el.blk[e].off + (long long)SA.ro * (el.blk[e].cols + 1);
+                dt.r_off = er.blk[re].off + (long long)SB.ro * (er.blk[re].cols + 1);
+                dt.l_ld = el.blk[e].cols;
+                dt.r_ld = er.blk[re].cols;
+                dt.cidx = P.c_cwt(it->second);
+                P.dterm_h.push_back(dt);
+            }
+        }
+        db.t1 = int(P.dterm_h.size());
+        P.dblk_h.push_back(db);
+        db.t0 = int(P.dterm_n.size());
+        const int e0 = el.find(0, SA.nb);
+        const int re = er.find(lastR, SB.nb);
+        if (e0 >= 0 && re >= 0) {
+            spk::DiagTerm dt{};
+            dt.l_off = el.blk[e0].off + (long long)SA.ro * (el.blk[e0].cols + 1);
+            dt.r_off = er.blk[re].off + (long long)SB.ro * (er.blk[re].cols + 1);
+            dt.l_ld = el.blk[e0].cols;
+            dt.r_ld = er.blk[re].cols;
+            dt.cidx = P.c_gr(X.s, X.s);
+            P.dterm_n.push_back(dt);
+        }
+        db.t1 = int(P.dterm_n.size());
+        P.dblk_n.push_back(db);
+    }
+    // ---- QR per right sector (left-orthonormalise) and LQ per left sector
+    P.qr_roff.assign(br.sec.size(), -1);
+    long long sc = 0, ro = 0;
+    for (int sb = 0; sb < int(br.sec.size()); ++sb) {
+        spk::QrTask t{};
+        t.p0 = int(P.qr_pieces.size());
+        int rows = 0;
+        for (const XBlk& X : si.blk)
+            if (X.sb == sb) {
+                P.qr_pieces.push_back(spk::QrPiece{X.off, X.rows, X.cols, 0, rows});
+                rows += X.rows;
+            }
+        t.p1 = int(P.qr_pieces.size());
+        t.rows = rows;
+        t.cols = br.sec[sb].dim;
+        SP_REQUIRE(t.cols <= 256, "a sector wider than 256 states is not supported");
+        if (rows == 0) continue;
+        SP_REQUIRE(rows >= t.cols, "block table: a sector is wider than its left support");
+        t.scratch_off = sc;
+        t.r_off = ro;
+        P.qr_roff[sb] = ro;
+        sc += 2LL * rows * t.cols;
+        ro += (long long)t.cols * t.cols;
+        P.qr_tasks.push_back(t);
+    }
+    P.qr_scratch = sc;
+    P.qr_rsize = ro;
+    P.lq_roff.assign(bl.sec.size(), -1);
+    sc = 0;
+    ro = 0;
+    for (int sa = 0; sa < int(bl.sec.size()); ++sa) {
+        spk::QrTask t{};
+        t.p0 = int(P.lq_pieces.size());
+        int rows = 0;
+        for (const XBlk& X : si.blk)
+            if (X.sa == sa) {
+                P.lq_pieces.push_back(spk::QrPiece{X.off, X.rows, X.cols, 1, rows});
+                rows += X.cols;
+            }
+        t.p1 = int(P.lq_pieces.size());
+        t.rows = rows;
+        t.cols = bl.sec[sa].dim;
+        SP_REQUIRE(t.cols <= 256, "a sector wider than 256 states is not supported");
+        if (rows == 0) continue;
+        SP_REQUIRE(rows >= t.cols, "block table: a sector is wider than its right support");
+        t.scratch_off = sc;
+        t.r_off = ro;
+        P.lq_roff[sa] = ro;
+        sc += 2LL * rows * t.cols;
+        ro += (long long)t.cols * t.cols;
+        P.lq_tasks.push_back(t);
+    }
+    P.lq_scratch = sc;
+    P.lq_rsize = ro;
+    // absorb R of this site into site k+1: A[k+1](sb, ., .) <- R_sb A[k+1](sb, ., .)
+    if (k < h->L) {
+        const SiteInfo& sn = h->sites[k];
+        for (const XBlk& X : sn.blk) {
+            P.absorb_right.add_task(B_OUT, X.off, X.rows, X.cols, X.cols);
+            const long long r = P.qr_roff[X.sa];
+            SP_REQUIRE(r >= 0, "internal: missing R factor");
+            P.absorb_right.add_term(B_V, r, X.rows, 1, B_X, X.off, X.cols, 1, X.rows, P.c_one());
+        }
+    }
+    // absorb L of this site into site k-1: A[k-1](., ., sa) <- A[k-1](., ., sa) L_sa, L = R'^T
+    if (k > 1) {
+        const SiteInfo& sp = h->sites[k - 2];
+        for (const XBlk& X : sp.blk) {
+            P.absorb_left.add_task(B_OUT, X.off, X.rows, X.cols, X.cols);
+            const long long r = P.lq_roff[X.sb];
+            SP_REQUIRE(r >= 0, "internal: missing L factor");
+            P.absorb_left.add_term(B_X, X.off, X.cols, 1, B_V, r, 1, X.cols, X.cols, P.c_one());
+        }
+    }
+    // algorithmic flops of one H_eff x: per g the left product, the mixing and
+    // the right product for y, and the right product of ny
+    P.heff_flops = P.p1.flops + P.mixl.flops + P.yout.flops;
+}
+
+void upload_plan(sp_handle* h, int k) {
+    SitePlan& P = h->plan[k - 1];
+    hipStream_t s = h->stream;
+    P.coef.upload(P.coef_h, s);
+    P.p1.upload(s);
+    P.mixl.upload(s);
+    P.yout.upload(s);
+    P.envl_out.upload(s);
+    P.p1r.upload(s);
+    P.mixr.upload(s);
+    P.envr_out.upload(s);
+    P.ddblk_h.upload(P.dblk_h, s);
+    P.ddblk_n.upload(P.dblk_n, s);
+    P.ddterm_h.upload(P.dterm_h, s);
+    P.ddterm_n.upload(P.dterm_n, s);
+    P.dqr_tasks.upload(P.qr_tasks, s);
+    P.dlq_tasks.upload(P.lq_tasks, s);
+    P.dqr_pieces.upload(P.qr_pieces, s);
+    P.dlq_pieces.upload(P.lq_pieces, s);
+    P.absorb_right.upload(s);
+    P.absorb_left.upload(s);
+}
+
+// ---------------------------------------------------------------------------
+// bounds validation of every task list against the buffers it will touch
+// (host side, at init): a descriptor error becomes SP_EINVAL, never a device
+// memory fault
+
+using Sizes = std::array<long long, spk::kMaxBufs>;
+
+void check_span(long long off, long long last, long long size, const char* what) {
+    if (off < 0 || last < off || last >= size) throw SpError(SP_EINVAL, std::string("internal bounds check: ") + what);
+}
+
+void validate(const BList& b, const Sizes& sz, long long ncoef, const char* what) {
+    for (const spk::BTask& t : b.tasks) {
+        if (t.M <= 0 || t.N <= 0) continue;
+        check_span(t.c_off, t.c_off + (long long)(t.M - 1) * t.ldc + (t.N - 1), sz[t.c_buf], what);
+        for (int i = t.t0; i < t.t1; ++i) {
+            const spk::BTerm& m = b.terms[i];
+            if (m.K <= 0) throw SpError(SP_EINVAL, std::string("internal: empty term in ") + what);
+            check_span(m.a_off, m.a_off + (long long)(t.M - 1) * m.a_rs + (long long)(m.K - 1) * m.a_cs,
+                       sz[m.a_buf], what);
+            check_span(m.b_off, m.b_off + (long long)(m.K - 1) * m.b_rs + (long long)(t.N - 1) * m.b_cs,
+                       sz[m.b_buf], what);
+            check_span(m.cidx, m.cidx, ncoef, what);
+        }
+    }
+}
+
+void validate(const CList& b, const Sizes& sz, long long ncoef, const char* what) {
+    for (const spk::CTask& t : b.tasks) {
+        check_span(t.c_off, t.c_off + t.n - 1, sz[t.c_buf], what);
+        for (int i = t.t0; i < t.t1; ++i) {
+            check_span(b.terms[i].a_off, b.terms[i].a_off + t.n - 1, sz[b.terms[i].a_buf], what);
+            check_span(b.terms[i].cidx, b.terms[i].cidx, ncoef, what);
+        }
+    }
+}
+
+void validate_plans(sp_handle* h) {
+    const long long G = h->G;
+    for (int k = 1; k <= h->L; ++k) {
+        const SitePlan& P = h->plan[k - 1];
+        const long long nco = G * P.nc;
+        const long long xs = h->sites[k - 1].size;
+        const long long Lb = G * h->env[k - 1].size, Rb = G * h->env[k].size;
+        const long long Tb = h->T_cap, Vb = h->V_cap;
+        Sizes z{};
+        z.fill(0);
+        z[B_ENVL] = Lb;
+        z[B_ENVR] = Rb;
+        z[B_X] = xs;
+        z[B_T] = Tb;
+        z[B_V] = Vb;
+        z[B_Y] = xs;
+        z[B_NY] = xs;
+        if (G * P.Tsize > Tb || G * P.Vsize > Vb || G * P.Zsize > Tb || G * P.Ztsize > Vb)
+            throw SpError(SP_EINVAL, "internal: scratch too small");
+        validate(P.p1, z, nco, "left product");
+        validate(P.mixl, z, nco, "left mixing");
+        validate(P.yout, z, nco, "H_eff output");
+        validate(P.p1r, z, nco, "right product");
+        validate(P.mixr, z, nco, "right mixing");
+        z[B_OUT] = Rb;
+        validate(P.envl_out, z, nco, "left environment");
+        z[B_OUT] = Lb;
+        validate(P.envr_out, z, nco, "right environment");
+        if (k < h->L) {
+            Sizes a{};
+            a.fill(0);
+            a[B_V] = h->qr_r_cap;
+            a[B_X] = h->sites[k].size;
+            a[B_OUT] = std::min<long long>(h->sites[k].size, h->max_site);
+            validate(P.absorb_right, a, P.nc, "absorb right");
+        }
+        if (k > 1) {
+            Sizes a{};
+            a.fill(0);
+            a[B_V] = h->qr_r_cap;
+            a[B_X] = h->sites[k - 2].size;
+            a[B_OUT] = std::min<long long>(h->sites[k - 2].size, h->max_site);
+            validate(P.absorb_left, a, P.nc, "absorb left");
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            const auto& tasks = pass ? P.lq_tasks : P.qr_tasks;
+            const auto& pieces = pass ? P.lq_pieces : P.qr_pieces;
+            for (const spk::QrTask& t : tasks) {
+                if (t.cols > 256 || t.rows < t.cols) throw SpError(SP_EINVAL, "internal: bad QR task");
+                check_span(t.scratch_off, t.scratch_off + 2LL * t.rows * t.cols - 1, h->qr_scratch_cap, "QR scratch");
+                check_span(t.r_off, t.r_off + (long long)t.cols * t.cols - 1, h->qr_r_cap, "QR factor");
+                int rows = 0;
+                for (int i = t.p0; i < t.p1; ++i) {
+                    const spk::QrPiece& pc = pieces[i];
+                    check_span(pc.off, pc.off + (long long)pc.prow * pc.pcol - 1, xs, "QR piece");
+                    if ((pc.transposed ? pc.prow : pc.pcol) != t.cols || pc.row0 != rows)
+                        throw SpError(SP_EINVAL, "internal: QR piece shape");
+                    rows += pc.transposed ? pc.pcol : pc.prow;
+                }
+                if (rows != t.rows) throw SpError(SP_EINVAL, "internal: QR rows");
+            }
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            const auto& blks = pass ? P.dblk_n : P.dblk_h;
+            const auto& terms = pass ? P.dterm_n : P.dterm_h;
+            for (const spk::DiagBlk& d : blks) {
+                check_span(d.x_off, d.x_off + (long long)d.rows * d.cols - 1, xs, "diagonal block");
+                for (int i = d.t0; i < d.t1; ++i) {
+                    const spk::DiagTerm& t = terms[i];
+                    check_span(t.l_off, t.l_off + (long long)(d.rows - 1) * (t.l_ld + 1), h->env[k - 1].size, "diag L");
+                    check_span(t.r_off, t.r_off + (long long)(d.cols - 1) * (t.r_ld + 1), h->env[k].size, "diag R");
+                    check_span(t.cidx, t.cidx, P.nc, "diag coefficient");
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// operations
+
+double* site_ptr(sp_handle* h, int k) { return h->mps.p + h->sites[k - 1].goff; }
+
+spk::BufSet bufset(sp_handle* h, int k, const double* x, double* y, double* ny, double* out) {
+    spk::BufSet b{};
+    b.p[B_ENVL] = h->envL[k - 1].p;
+    b.p[B_ENVR] = h->envR[k].p;
+    b.p[B_X] = const_cast<double*>(x);
+    b.p[B_T] = h->T.p;
+    b.p[B_V] = h->V.p;
+    b.p[B_Y] = y;
+    b.p[B_NY] = ny;
+    b.p[B_OUT] = out;
+    return b;
+}
+
+void check_site(const sp_handle* h, int k) { SP_REQUIRE(k >= 1 && k <= h->L, "site out of range"); }
+
+void heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny) {
+    if (!h->Lvalid[k - 1] || !h->Rvalid[k])
+        throw SpError(SP_ESTATE, "H_eff needs L[site-1] and R[site+1]; build them with sp_env_update");
+    SitePlan& P = h->plan[k - 1];
+    const spk::BufSet b = bufset(h, k, x, y, ny, nullptr);
+    P.p1.launch(h->stream, b, P.coef.p);
+    P.mixl.launch(h->stream, b, P.coef.p);
+    P.yout.launch(h->stream, b, P.coef.p);
+}
+
+void env_left(sp_handle* h, int k) {
+    if (!h->Lvalid[k - 1]) throw SpError(SP_ESTATE, "left environment of the previous bond is not built");
+    SitePlan& P = h->plan[k - 1];
+    const spk::BufSet b = bufset(h, k, site_ptr(h, k), nullptr, nullptr, h->envL[k].p);
+    P.p1.launch(h->stream, b, P.coef.p);
+    P.mixl.launch(h->stream, b, P.coef.p);
+    P.envl_out.launch(h->stream, b, P.coef.p);
+    h->Lvalid[k] = 1;
+    for (int q = k + 1; q <= h->L; ++q) h->Lvalid[q] = 0;
+}
+
+void env_right(sp_handle* h, int k) {
+    if (!h->Rvalid[k]) throw SpError(SP_ESTATE, "right environment of the next bond is not built");
+    SitePlan& P = h->plan[k - 1];
+    spk::BufSet b = bufset(h, k, site_ptr(h, k), nullptr, nullptr, h->envR[k - 1].p);
+    P.p1r.launch(h->stream, b, P.coef.p);
+    P.mixr.launch(h->stream, b, P.coef.p);
+    P.envr_out.launch(h->stream, b, P.coef.p);
+    h->Rvalid[k - 1] = 1;
+    for (int q = 0; q < k - 1; ++q) h->Rvalid[q] = 0;
+}
+
+void diag(sp_handle* h, int k, double* dh, double* dn) {
+    if (!h->Lvalid[k - 1] || !h->Rvalid[k]) throw SpError(SP_ESTATE, "environments for the diagonal are not built");
+    SitePlan& P = h->plan[k - 1];
+    const EnvLayout& el = h->env[k - 1];
+    const EnvLayout& er = h->env[k];
+    spk::heff_diag(h->stream, P.ddblk_h.p, int(P.dblk_h.size()), P.ddterm_h.p, h->envL[k - 1].p, el.size,
+                   h->envR[k].p, er.size, P.coef.p, P.nc, h->G, dh);
+    spk::heff_diag(h->stream, P.ddblk_n.p, int(P.dblk_n.size()), P.ddterm_n.p, h->envL[k - 1].p, el.size,
+                   h->envR[k].p, er.size, P.coef.p, P.nc, h->G, dn);
+}
+
+// positive-diagonal QR per right sector of site k, R pushed into site k+1
+void move_right(sp_handle* h, int k) {
+    SitePlan& P = h->plan[k - 1];
+    spk::qr_sectors(h->stream, P.dqr_tasks.p, int(P.qr_tasks.size()), P.dqr_pieces.p, site_ptr(h, k),
+                    h->qr_scratch.p, h->qr_r.p);
+    if (k < h->L) {
+        spk::BufSet b{};
+        b.p[B_V] = h->qr_r.p;
+        b.p[B_X] = site_ptr(h, k + 1);
+        b.p[B_OUT] = h->tmp_site.p;
+        P.absorb_right.launch(h->stream, b, P.coef.p);
+        HIPCK(hipMemcpyAsync(site_ptr(h, k + 1), h->tmp_site.p, h->sites[k].size * sizeof(double),
+                             hipMemcpyDeviceToDevice, h->stream));
+    }
+}
+
+// positive-diagonal LQ per left sector of site k, L pushed into site k-1
+void move_left(sp_handle* h, int k) {
+    SitePlan& P = h->plan[k - 1];
+    spk::qr_sectors(h->stream, P.dlq_tasks.p, int(P.lq_tasks.size()), P.dlq_pieces.p, site_ptr(h, k),
+                    h->qr_scratch.p, h->qr_r.p);
+    if (k > 1) {
+        spk::BufSet b{};
+        b.p[B_V] = h->qr_r.p;
+        b.p[B_X] = site_ptr(h, k - 1);
+        b.p[B_OUT] = h->tmp_site.p;
+        P.absorb_left.launch(h->stream, b, P.coef.p);
+        HIPCK(hipMemcpyAsync(site_ptr(h, k - 1), h->tmp_site.p, h->sites[k - 2].size * sizeof(double),
+                             hipMemcpyDeviceToDevice, h->stream));
+    }
+}
+
+void invalidate_for_site(sp_handle* h, int k) {
+    for (int q = k; q <= h->L; ++q) h->Lvalid[q] = 0;
+    for (int q = 0; q <= k - 1; ++q) h->Rvalid[q] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Davidson for the singular pencil H_eff x = theta N_eff x (Eq. [geproblem])
+
+void ensure_pinned(sp_handle* h, size_t n) {
+    if (h->pin_n >= n) return;
+    if (h->pin) HIPCK(hipHostFree(h->pin));
+    h->pin = nullptr;
+    HIPCK(hipHostMalloc(&h->pin, n * sizeof(double), hipHostMallocDefault));
+    h->pin_n = n;
+}
+
+void ensure_davidson(sp_handle* h, int max_sub) {
+    if (h->dav_sub >= max_sub && h->ld > 0) return;
+    h->ld = (h->max_site + 63) / 64 * 64;
+    const size_t vec = size_t(max_sub + 1) * h->ld;
+    h->dV.alloc(vec);
+    h->dHV.alloc(vec);
+    h->dNV.alloc(vec);
+    h->dRot.alloc(size_t(max_sub + 1) * h->ld);
+    h->dx.alloc(h->ld);
+    h->dt.alloc(h->ld);
+    h->ddh.alloc(h->ld);
+    h->ddn.alloc(h->ld);
+    h->dpart.alloc(3 * (h->ld / 256 + 2));
+    h->dsmall.alloc(size_t(max_sub + 2) * (max_sub + 2) + 8 * (max_sub + 8));
+    h->dav_sub = max_sub;
+    ensure_pinned(h, size_t(max_sub + 2) * (max_sub + 2) + 8 * (max_sub + 8));
+}
+
+struct DavOut {
+    double theta = 0, rnorm = 0, pnorm = 0;
+    int iters = 0, matvecs = 0;
+    bool converged = false;
+};
+
+// lowest eigenpair of the pencil restricted to range(Nt) (canonical
+// orthogonalisation); returns false if the projected metric vanishes
+bool small_solve(int m, const std::vector<double>& Ht, const std::vector<double>& Nt, int stride, double drop,
+                 double& theta, std::vector<double>& a, std::vector<double>& Xc, int& rk) {
+    std::vector<double> A(size_t(m) * m), ev(m), U(size_t(m) * m);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) A[i * m + j] = 0.5 * (Nt[i * stride + j] + Nt[j * stride + i]);
+    if (sph::sym_eigh(m, A.data(), ev.data(), U.data()) != 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
+    const double lmax = ev[m - 1];
+    if (!(lmax > 1e-12)) return false;
+    std::vector<int> keep;
+    for (int i = 0; i < m; ++i)
+        if (ev[i] > drop * lmax) keep.push_back(i);
+    rk = int(keep.size());
+    std::vector<double> X(size_t(m) * rk);
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < rk; ++c) X[i * rk + c] = U[i * m + keep[c]] / std::sqrt(ev[keep[c]]);
+    // B = X^T Hs X
+    std::vector<double> HX(size_t(m) * rk, 0.0), B(size_t(rk) * rk, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < rk; ++c) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += 0.5 * (Ht[i * stride + j] + Ht[j * stride + i]) * X[j * rk + c];
+            HX[i * rk + c] = s;
+        }
+    for (int r = 0; r < rk; ++r)
+        for (int c = 0; c < rk; ++c) {
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s += X[i * rk + r] * HX[i * rk + c];
+            B[r * rk + c] = s;
+        }
+    for (int r = 0; r < rk; ++r)
+        for (int c = 0; c < r; ++c) B[r * rk + c] = B[c * rk + r] = 0.5 * (B[r * rk + c] + B[c * rk + r]);
+    std::vector<double> mu(rk), C(size_t(rk) * rk);
+    if (sph::sym_eigh(rk, B.data(), mu.data(), C.data()) != 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
+    theta = mu[0];
+    if (!std::isfinite(theta)) throw SpError(SP_ENAN, "non-finite Ritz value");
+    a.assign(m, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < rk; ++c) a[i] += X[i * rk + c] * C[c * rk + 0];
+    // X C (all Ritz coefficient vectors, m x rk) for restarts
+    Xc.assign(size_t(m) * rk, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < rk; ++c) {
+            double s = 0.0;
+            for (int j = 0; j < rk; ++j) s += X[i * rk + j] * C[j * rk + c];
+            Xc[i * rk + c] = s;
+        }
+    return true;
+}
+
+DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
+    const int n = int(h->sites[k - 1].size);
+    const int max_sub = std::max(2, o.max_sub);
+    const int keep = std::max(1, std::min(o.keep, max_sub - 1));
+    ensure_davidson(h, max_sub);
+    hipStream_t s = h->stream;
+    const long long ld = h->ld;
+    double* V = h->dV.p;
+    double* HV = h->dHV.p;
+    double* NV = h->dNV.p;
+    double* sm = h->dsmall.p;  // device small area: [a | theta | c | gram]
+    const int SM_A = 0, SM_TH = max_sub + 2, SM_C = max_sub + 4, SM_G = 2 * max_sub + 8;
+    double* pin = h->pin;
+    const double drop = 1e-10, floor_ = 1e-8;
+    DavOut out;
+
+    diag(h, k, h->ddh.p, h->ddn.p);
+    spk::normalize(s, site_ptr(h, k), V, n, nullptr);
+    heff_apply(h, k, V, HV, NV);
+    out.matvecs = 1;
+    spk::gram(s, V, HV, NV, ld, 0, n, h->dpart.p, 0, sm + SM_G);
+    HIPCK(hipMemcpyAsync(pin, sm + SM_G, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    const int S = max_sub + 1;
+    std::vector<double> Ht(size_t(S) * S, 0.0), Nt(size_t(S) * S, 0.0);
+    Ht[0] = pin[0];
+    Nt[0] = pin[1];
+    int m = 1;
+    std::vector<double> a, Xc;
+    for (int it = 1; it <= std::max(1, o.max_iter); ++it) {
+        out.iters = it;
+        double theta;
+        int rk = 0;
+        if (!small_solve(m, Ht, Nt, S, drop, theta, a, Xc, rk))
+            throw SpError(SP_ENORM, "projected norm vanishes in the search space");
+        out.theta = theta;
+        // upload a, theta
+        for (int i = 0; i < m; ++i) pin[i] = a[i];
+        pin[max_sub + 2] = theta;
+        HIPCK(hipMemcpyAsync(sm + SM_A, pin, (max_sub + 3) * sizeof(double), hipMemcpyHostToDevice, s));
+        int nparts = 0;
+        spk::ritz(s, V, HV, NV, ld, m, sm + SM_A, sm + SM_TH, h->ddh.p, h->ddn.p, n, floor_, h->dx.p, h->dt.p,
+                  h->dpart.p, &nparts);
+        const bool last = (it == std::max(1, o.max_iter));
+        bool restarted = false;
+        if (!last) {
+            if (m >= max_sub) {
+                // restart with the lowest Ritz vectors, Euclidean-orthonormalised
+                const int nk = std::min(keep, rk);
+                std::vector<double> Qk(size_t(m) * nk);
+                // modified Gram-Schmidt on the coefficient vectors (columns of Xc)
+                for (int c = 0; c < nk; ++c) {
+                    std::vector<double> v(m);
+                    for (int i = 0; i < m; ++i) v[i] = Xc[i * rk + c];
+                    for (int p = 0; p < c; ++p) {
+                        double d = 0.0;
+                        for (int i = 0; i < m; ++i) d += Qk[i * nk + p] * v[i];
+                        for (int i = 0; i < m; ++i) v[i] -= d * Qk[i * nk + p];
+                    }
+                    double nr = 0.0;
+                    for (int i = 0; i < m; ++i) nr += v[i] * v[i];
+                    nr = std::sqrt(nr);
+                    for (int i = 0; i < m; ++i) Qk[i * nk + c] = v[i] / nr;
+                }
+                std::vector<double> Q2(size_t(m) * nk);
+                std::copy(Qk.begin(), Qk.end(), Q2.begin());
+                double* pq = pin + (max_sub + 4);
+                std::copy(Qk.begin(), Qk.end(), pq);
+                double* dq = sm + SM_G + 4 * (max_sub + 2);
+                HIPCK(hipMemcpyAsync(dq, pq, Qk.size() * sizeof(double), hipMemcpyHostToDevice, s));
+                for (double* B : {V, HV, NV}) {
+                    spk::basis_rotate(s, B, ld, m, dq, nk, h->dRot.p, n);
+                    HIPCK(hipMemcpyAsync(B, h->dRot.p, size_t(nk) * ld * sizeof(double), hipMemcpyDeviceToDevice, s));
+                }
+                // Ht <- Qk^T Ht Qk, Nt likewise
+                auto rot = [&](std::vector<double>& M) {
+                    std::vector<double> tmp(size_t(m) * nk, 0.0), res(size_t(S) * S, 0.0);
+                    for (int i = 0; i < m; ++i)
+                        for (int c = 0; c < nk; ++c) {
+                            double v = 0.0;
+                            for (int j = 0; j < m; ++j) v += M[i * S + j] * Qk[j * nk + c];
+                            tmp[i * nk + c] = v;
+                        }
+                    for (int r = 0; r < nk; ++r)
+                        for (int c = 0; c < nk; ++c) {
+                            double v = 0.0;
+                            for (int i = 0; i < m; ++i) v += Qk[i * nk + r] * tmp[i * nk + c];
+                            res[r * S + c] = v;
+                        }
+                    M.swap(res);
+                };
+                rot(Ht);
+                rot(Nt);
+                m = nk;
+                restarted = true;
+            }
+            (void)restarted;
+            // CGS2 of the correction against the search space, then normalise
+            double* vnew = V + size_t(m) * ld;
+            for (int pass = 0; pass < 2; ++pass) {
+                spk::multidot(s, V, ld, m, h->dt.p, n, sm + SM_C);
+                spk::sub_combo(s, V, ld, m, sm + SM_C, h->dt.p, n);
+            }
+            spk::normalize(s, h->dt.p, vnew, n, sm + SM_G + 4 * m + 6);
+            heff_apply(h, k, vnew, HV + size_t(m) * ld, NV + size_t(m) * ld);
+            out.matvecs++;
+            spk::gram(s, V, HV, NV, ld, m, n, h->dpart.p, nparts, sm + SM_G);
+            HIPCK(hipMemcpyAsync(pin, sm + SM_G, (4 * m + 7) * sizeof(double), hipMemcpyDeviceToHost, s));
+        } else {
+            spk::gram(s, V, HV, NV, ld, 0, n, h->dpart.p, nparts, sm + SM_G);
+            HIPCK(hipMemcpyAsync(pin + 4 * m + 2 - 2, sm + SM_G + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        HIPCK(hipStreamSynchronize(s));
+        const double xx = last ? pin[4 * m] : pin[4 * m + 2];
+        const double uu = last ? pin[4 * m + 1] : pin[4 * m + 3];
+        const double xn = last ? pin[4 * m + 2] : pin[4 * m + 4];
+        if (!std::isfinite(xx) || !std::isfinite(uu) || !(xx > 0.0)) throw SpError(SP_ENAN, "non-finite Ritz vector");
+        out.rnorm = std::sqrt(uu / xx);
+        out.pnorm = xn / xx;
+        if (out.rnorm <= o.tol) {
+            out.converged = true;
+            break;
+        }
+        if (last) break;
+        const double tn = pin[4 * m + 6];
+        if (!(tn >= 1e-14)) break;
+        // extend the projected matrices with the new vector m (symmetrised)
+        for (int j = 0; j <= m; ++j) {
+            const double hv_new = pin[j];             // V_j . HV_m
+            const double nv_new = pin[m + 1 + j];     // V_j . NV_m
+            const double hv_old = (j < m) ? pin[2 * m + 2 + j] : hv_new;  // V_m . HV_j
+            const double nv_old = (j < m) ? pin[3 * m + 2 + j] : nv_new;
+            Ht[j * S + m] = hv_new;
+            Ht[m * S + j] = hv_old;
+            Nt[j * S + m] = nv_new;
+            Nt[m * S + j] = nv_old;
+        }
+        ++m;
+    }
+    // normalise x and write it into the site
+    spk::normalize(s, h->dx.p, site_ptr(h, k), n, nullptr);
+    return out;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+namespace {
+int guarded(const std::function<int()>& f) {
+    try {
+        return f();
+    } catch (const SpError& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return SP_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SP_EINVAL;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+const char* sp_last_error(void) { return g_last_error.c_str(); }
+
+int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bonds, const double* init_blocks,
+                void* hip_stream, sp_handle** out) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(p && W && bonds && init_blocks && out, "null argument");
+        *out = nullptr;
+        SP_REQUIRE(p->L >= 1 && p->d == 4, "need L >= 1 and d == 4");
+        SP_REQUIRE(p->precision == SP_FP64, "only SP_FP64 is available");
+        SP_REQUIRE(p->N >= 0 && p->N <= 2 * p->L, "N out of range");
+        SP_REQUIRE((p->N + p->twoS) % 2 == 0, "N and 2S must have the same parity");
+        SP_REQUIRE((p->N + p->twoM) % 2 == 0, "N and 2M must have the same parity");
+        SP_REQUIRE(p->twoS >= 0 && std::abs(p->twoM) <= p->twoS, "need |M| <= S");
+        SP_REQUIRE(p->twoS <= sph::max_seniority(p->N, p->twoM, p->L), "S exceeds the largest seniority");
+        SP_REQUIRE(p->G >= 1 && p->G <= 1024, "G out of range");
+        std::unique_ptr<sp_handle> h(new sp_handle());
+        h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        h->L = p->L;
+        h->N = p->N;
+        h->twoS = p->twoS;
+        h->twoM = p->twoM;
+        h->G = p->G;
+        h->inexact = p->G < sph::exact_points(p->N, p->L, p->twoS, p->twoM);
+        h->qx.resize(h->G);
+        h->qw.resize(h->G);
+        h->qc.resize(h->G);
+        h->qs.resize(h->G);
+        h->qcoef.resize(h->G);
+        sph::projector_quadrature(h->G, h->twoS, h->twoM, h->qx.data(), h->qw.data(), h->qc.data(), h->qs.data(),
+                                  h->qcoef.data());
+        build_mpo(h.get(), W);
+        build_bonds(h.get(), bonds);
+        build_env_layouts(h.get());
+        h->plan.resize(h->L);
+        long long Tmax = 0, Vmax = 0, qrs = 0, qrr = 0;
+        for (int k = 1; k <= h->L; ++k) {
+            build_plan(h.get(), k);
+            const SitePlan& P = h->plan[k - 1];
+            Tmax = std::max({Tmax, P.Tsize, P.Zsize});
+            Vmax = std::max({Vmax, P.Vsize, P.Ztsize});
+            qrs = std::max({qrs, P.qr_scratch, P.lq_scratch});
+            qrr = std::max({qrr, P.qr_rsize, P.lq_rsize});
+        }
+        h->T_cap = h->G * std::max(1LL, Tmax);
+        h->V_cap = h->G * std::max(1LL, Vmax);
+        h->qr_scratch_cap = std::max(1LL, qrs);
+        h->qr_r_cap = std::max(1LL, qrr);
+        validate_plans(h.get());
+        // every host-side check is done; device work starts here
+        HIPCK(hipGetDevice(&h->device));
+        alloc_envs(h.get());
+        for (int k = 1; k <= h->L; ++k) upload_plan(h.get(), k);
+        h->T.alloc(h->T_cap);
+        h->V.alloc(h->V_cap);
+        h->qr_scratch.alloc(h->qr_scratch_cap);
+        h->qr_r.alloc(h->qr_r_cap);
+        h->tmp_site.alloc(h->max_site);
+        h->mps.alloc(h->mps_size);
+        HIPCK(hipMemcpyAsync(h->mps.p, init_blocks, h->mps_size * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        // right-canonical form of sites L..2 and the right environments
+        for (int k = h->L; k >= 2; --k) {
+            move_left(h.get(), k);
+            env_right(h.get(), k);
+        }
+        h->center = 1;
+        HIPCK(hipStreamSynchronize(h->stream));
+        HIPCK(hipGetLastError());
+        *out = h.release();
+        return (*out)->inexact ? SP_WINEXACT : SP_OK;
+    });
+}
+
+int sp_destroy(sp_handle* h) {
+    return guarded([&]() -> int {
+        if (!h) return SP_OK;
+        (void)hipStreamSynchronize(h->stream);
+        delete h;
+        return SP_OK;
+    });
+}
+
+int sp_env_update(sp_handle* h, int site, int dir) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h, "null handle");
+        check_site(h, site);
+        SP_REQUIRE(dir == 1 || dir == -1, "dir must be +1 or -1");
+        if (dir > 0) env_left(h, site);
+        else env_right(h, site);
+        HIPCK(hipGetLastError());
+        return SP_OK;
+    });
+}
+
+int sp_heff_apply(sp_handle* h, int site, const double* x, double* y, double* ny) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && x && y && ny, "null argument");
+        check_site(h, site);
+        SP_REQUIRE(x != y && x != ny && y != ny, "x, y and ny must not alias");
+        heff_apply(h, site, x, y, ny);
+        HIPCK(hipGetLastError());
+        return SP_OK;
+    });
+}
+
+int sp_heff_diag(sp_handle* h, int site, double* dh, double* dn) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && dh && dn, "null argument");
+        check_site(h, site);
+        diag(h, site, dh, dn);
+        HIPCK(hipGetLastError());
+        return SP_OK;
+    });
+}
+
+int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && o, "null argument");
+        SP_REQUIRE(o->n_sweeps >= 0 && o->max_iter >= 1 && o->max_sub >= 2 && o->keep >= 1 && o->tol >= 0,
+                   "bad sweep options");
+        SP_REQUIRE(h->center == 1, "sweeps start with the canonical centre at site 1");
+        if (r) r->n_steps = 0;
+        int status = SP_OK;
+        const int L = h->L;
+        for (int sw = 0; sw < o->n_sweeps; ++sw) {
+            std::vector<std::pair<int, int>> order;
+            for (int k = 1; k < L; ++k) order.push_back({k, +1});
+            for (int k = L; k >= 2; --k) order.push_back({k, -1});
+            if (L == 1) order.push_back({1, +1});
+            for (auto [k, d] : order) {
+                const auto t0 = std::chrono::steady_clock::now();
+                DavOut dv = davidson(h, k, *o);
+                if (L > 1) {
+                    if (d > 0) {
+                        move_right(h, k);
+                        env_left(h, k);
+                        h->center = k + 1;
+                    } else {
+                        move_left(h, k);
+                        env_right(h, k);
+                        h->center = k - 1;
+                    }
+                }
+                HIPCK(hipStreamSynchronize(h->stream));
+                HIPCK(hipGetLastError());
+                const auto t1 = std::chrono::steady_clock::now();
+                if (!dv.converged) status = SP_ENOCONV;
+                if (r && r->steps && r->n_steps < r->capacity) {
+                    sp_step_report& st = r->steps[r->n_steps++];
+                    st.sweep = sw;
+                    st.site = k;
+                    st.dir = d;
+                    st.iters = dv.iters;
+                    st.converged = dv.converged ? 1 : 0;
+                    st.matvecs = dv.matvecs;
+                    st.theta = dv.theta;
+                    st.pnorm = dv.pnorm;
+                    st.rnorm = dv.rnorm;
+                    st.usec = std::chrono::duration<double, std::micro>(t1 - t0).count();
+                }
+            }
+        }
+        return status;
+    });
+}
+
+int sp_energy(sp_handle* h, double* E, double* normP) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && E && normP, "null argument");
+        const int k = h->center;
+        const int n = int(h->sites[k - 1].size);
+        ensure_davidson(h, std::max(h->dav_sub, 2));
+        heff_apply(h, k, site_ptr(h, k), h->dHV.p, h->dNV.p);
+        double* sm = h->dsmall.p;
+        spk::multidot(h->stream, h->dHV.p, 0, 1, site_ptr(h, k), n, sm);
+        spk::multidot(h->stream, h->dNV.p, 0, 1, site_ptr(h, k), n, sm + 1);
+        spk::multidot(h->stream, site_ptr(h, k), 0, 1, site_ptr(h, k), n, sm + 2);
+        HIPCK(hipMemcpyAsync(h->pin, sm, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCK(hipStreamSynchronize(h->stream));
+        const double xy = h->pin[0], xny = h->pin[1], xx = h->pin[2];
+        if (!(xx > 0.0) || !(std::fabs(xny) / xx >= 1e-12)) {
+            *E = NAN;
+            *normP = xx > 0.0 ? xny / xx : 0.0;
+            throw SpError(SP_ENORM, "projected norm vanishes");
+        }
+        *E = xy / xny;
+        *normP = xny / xx;
+        return SP_OK;
+    });
+}
+
+int sp_site_size(const sp_handle* h, int site, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && n, "null argument");
+        check_site(h, site);
+        *n = h->sites[site - 1].size;
+        return SP_OK;
+    });
+}
+
+int sp_get_site(sp_handle* h, int site, double* host) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && host, "null argument");
+        check_site(h, site);
+        HIPCK(hipMemcpyAsync(host, site_ptr(h, site), h->sites[site - 1].size * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+        HIPCK(hipStreamSynchronize(h->stream));
+        return SP_OK;
+    });
+}
+
+int sp_set_site(sp_handle* h, int site, const double* host) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && host, "null argument");
+        check_site(h, site);
+        HIPCK(hipMemcpyAsync(site_ptr(h, site), host, h->sites[site - 1].size * sizeof(double),
+                             hipMemcpyHostToDevice, h->stream));
+        HIPCK(hipStreamSynchronize(h->stream));
+        invalidate_for_site(h, site);
+        return SP_OK;
+    });
+}
+
+int sp_center(const sp_handle* h, int* site) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && site, "null argument");
+        *site = h->center;
+        return SP_OK;
+    });
+}
+
+int sp_heff_flops(const sp_handle* h, int site, double* flops) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && flops, "null argument");
+        check_site(h, site);
+        *flops = h->plan[site - 1].heff_flops;
+        return SP_OK;
+    });
+}
+
+int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y, double* ny, double* out) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && x && y && ny && out && reps >= 1, "bad arguments");
+        check_site(h, site);
+        if (!h->Lvalid[site - 1] || !h->Rvalid[site]) throw SpError(SP_ESTATE, "environments are not built");
+        SitePlan& P = h->plan[site - 1];
+        const spk::BufSet b = bufset(h, site, x, y, ny, nullptr);
+        hipEvent_t ev[4];
+        for (auto& e : ev) HIPCK(hipEventCreate(&e));
+        double ms[3] = {0, 0, 0};
+        for (int r = 0; r < reps; ++r) {
+            HIPCK(hipEventRecord(ev[0], h->stream));
+            P.p1.launch(h->stream, b, P.coef.p);
+            HIPCK(hipEventRecord(ev[1], h->stream));
+            P.mixl.launch(h->stream, b, P.coef.p);
+            HIPCK(hipEventRecord(ev[2], h->stream));
+            P.yout.launch(h->stream, b, P.coef.p);
+            HIPCK(hipEventRecord(ev[3], h->stream));
+            HIPCK(hipEventSynchronize(ev[3]));
+            for (int i = 0; i < 3; ++i) {
+                float t = 0.f;
+                HIPCK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+                ms[i] += t;
+            }
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        const double G = h->G, xs = double(h->sites[site - 1].size);
+        const double Lb = G * h->env[site - 1].size, Rb = G * h->env[site].size;
+        for (int i = 0; i < 3; ++i) out[i] = ms[i] / reps;
+        out[3] = P.p1.flops;
+        out[4] = P.mixl.flops;
+        out[5] = P.yout.flops;
+        out[6] = 8.0 * (Lb + xs + G * P.Tsize);
+        out[7] = 8.0 * (G * P.Tsize + G * P.Vsize);
+        out[8] = 8.0 * (G * P.Vsize + G * P.Tsize + Rb + 2.0 * xs);
+        HIPCK(hipGetLastError());
+        return SP_OK;
+    });
+}
+
+int sp_quadrature(int G, int twoS, int twoM, double* x, double* w, double* coef) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(G >= 1 && G <= 1024 && x && w && coef, "bad arguments");
+        SP_REQUIRE(twoS >= 0 && std::abs(twoM) <= twoS && (twoS - twoM) % 2 == 0, "need |M| <= S, S - M integer");
+        std::vector<double> c(G), s(G);
+        sph::projector_quadrature(G, twoS, twoM, x, w, c.data(), s.data(), coef);
+        return SP_OK;
+    });
+}
+
+int sp_exact_points(int N, int K, int twoS, int twoM) { return sph::exact_points(N, K, twoS, twoM); }
+
+int sp_mpo_hubbard(int L, double t, double U, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(L >= 1 && w && n, "bad arguments");
+        return sph::mpo_hubbard(L, t, U, w, data, n);
+    });
+}
+int sp_mpo_s2(int L, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(L >= 1 && w && n, "bad arguments");
+        return sph::mpo_s2(L, w, data, n);
+    });
+}
+int sp_mpo_identity(int L, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(L >= 1 && w && n, "bad arguments");
+        return sph::mpo_identity(L, w, data, n);
+    });
+}
+
+int sp_small_eigh(int n, double* a, double* ev, double* vec) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(n >= 0 && a && ev && vec, "bad arguments");
+        if (sph::sym_eigh(n, a, ev, vec) != 0) throw SpError(SP_ENAN, "eigensolver did not converge");
+        return SP_OK;
+    });
+}
+
+}  // extern "C"

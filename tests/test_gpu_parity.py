@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Element-wise comparisons at sizes the oracle finishes in seconds (several
+blocks per bond, ragged sector sizes, odd electron counts, half-integer
+spin), plus the bench shape (L=32, D=256, G=9) on whole site vectors.
+Tolerances: 1e-11 relative for single contractions (FP64 with reductions of
+a few thousand terms), 1e-8 absolute for sweep energies (the FP64 target).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_util import make_pair, rel_err  # noqa: E402
+
+import paper_1703_04789_amd as sp  # noqa: E402
+import workloads as W  # noqa: E402
+from oracle import mps as omps, quadrature as oq  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (L, N, 2M, D, 2S, G)
+    (8, 8, 0, 16, 0, 5),
+    (6, 5, 1, 12, 1, 3),
+    (7, 6, 2, 20, 4, 4),
+    (10, 10, 0, 48, 2, 6),
+]
+
+
+def _dev(a):
+    return torch.tensor(a, dtype=torch.float64, device="cuda")
+
+
+def _left_envs_to(gpu, orc, k):
+    for j in range(1, k):
+        gpu.env_update(j, +1)
+        orc.update_left(j)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_init_right_canonical_form(case):
+    tab, gpu, orc = make_pair(*case)
+    for k in range(1, tab.L + 1):
+        assert rel_err(gpu.get_site(k), orc.mps.site_packed(k)) < 1e-12, k
+    assert gpu.center() == 1
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_heff_apply_all_sites(case):
+    tab, gpu, orc = make_pair(*case)
+    rng = np.random.default_rng(5)
+    for k in range(1, tab.L + 1):
+        if k > 1:
+            gpu.env_update(k - 1, +1)
+            orc.update_left(k - 1)
+        n = gpu.site_size(k)
+        x = rng.standard_normal(n)
+        y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
+        y_ref = orc.mps.site_packed(k, y_ref)
+        ny_ref = orc.mps.site_packed(k, ny_ref)
+        xd, y, ny = _dev(x), torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(
+            n, dtype=torch.float64, device="cuda")
+        gpu.heff_apply(k, xd, y, ny)
+        torch.cuda.synchronize()
+        assert rel_err(y.cpu().numpy(), y_ref) < 1e-11, k
+        assert rel_err(ny.cpu().numpy(), ny_ref) < 1e-11, k
+        dh, dn = torch.empty_like(y), torch.empty_like(y)
+        gpu.heff_diag(k, dh, dn)
+        dh_ref, dn_ref = orc.heff_diag(k)
+        torch.cuda.synchronize()
+        assert rel_err(dh.cpu().numpy(), orc.mps.site_packed(k, dh_ref)) < 1e-11
+        assert rel_err(dn.cpu().numpy(), orc.mps.site_packed(k, dn_ref)) < 1e-11
+
+
+def test_heff_apply_is_deterministic():
+    tab, gpu, orc = make_pair(*CASES[3], oracle=False)
+    n = gpu.site_size(1)
+    x = _dev(np.random.default_rng(0).standard_normal(n))
+    outs = []
+    for _ in range(3):
+        y, ny = torch.empty_like(x), torch.empty_like(x)
+        gpu.heff_apply(1, x, y, ny)
+        torch.cuda.synchronize()
+        outs.append((y.cpu().numpy(), ny.cpu().numpy()))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_energy_at_centre(case):
+    tab, gpu, orc = make_pair(*case)
+    E, p = gpu.energy()
+    Eo, po = orc.energy(1)
+    x = orc.mps.A[0]
+    assert abs(E - Eo) < 1e-10
+    assert abs(p - po / np.sum(x * x)) < 1e-12
+    Ef, _ = orc.full_contraction()
+    assert abs(E - Ef) < 1e-10
+
+
+@pytest.mark.parametrize("twoS", [0, 2, 4])
+def test_s2_operator_through_kernels(twoS):
+    tab, gpu, orc = make_pair(6, 6, 0, 20, twoS, 4, op="s2", oracle=False)
+    E, p = gpu.energy()
+    s = twoS / 2
+    assert p > 1e-8
+    assert abs(E - s * (s + 1)) < 1e-11
+
+
+@pytest.mark.parametrize("case", CASES[:3])
+def test_gauge_moves_one_sweep(case):
+    # max_iter = 1: each local solve returns its start vector, so one sweep
+    # exercises every QR/LQ move and environment update of both directions
+    tab, gpu, orc = make_pair(*case)
+    rc, steps = gpu.sweep(1, max_iter=1)
+    ref = omps.sweep(orc, 1, max_iter=1)
+    for a, b in zip(steps, ref):
+        assert abs(a["theta"] - b["theta"]) < 1e-10, (a, b)
+    for k in range(1, tab.L + 1):
+        assert rel_err(gpu.get_site(k), orc.mps.site_packed(k)) < 1e-10, k
+
+
+@pytest.mark.parametrize("L,twoS,ref", [(4, 0, -1.953145308684551), (4, 2, -1.4128986959190932),
+                                        (6, 0, -3.092565319505379), (6, 2, -2.6914960192367765)])
+def test_sweep_full_bond_dimension_reaches_ed(L, twoS, ref):
+    G = oq.exact_point_count(L, L, twoS)
+    tab, gpu, orc = make_pair(L, L, 0, 4 ** (L // 2), twoS, G, oracle=False)
+    rc, steps = gpu.sweep(3, max_sub=128, max_iter=200)
+    assert abs(steps[-1]["theta"] - ref) < 1e-10
+    E, p = gpu.energy()
+    assert abs(E - ref) < 1e-10
+
+
+def test_sweep_small_workload_matches_oracle():
+    # exact local solves (search space covers the local problem), so the
+    # trajectory is a smooth function of the input and both sides agree
+    wl = W.hubbard_small()
+    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed)
+    rc, steps = gpu.sweep(wl.sweeps, max_sub=128, max_iter=200)
+    ref = omps.sweep(orc, wl.sweeps, max_sub=128, max_iter=200)
+    dE = max(abs(a["theta"] - b["theta"]) for a, b in zip(steps, ref))
+    assert dE < 1e-8, dE
+    assert steps[-1]["theta"] > -4.235806999129714 - 1e-10
+
+
+def test_bench_shape_heff_parity():
+    # L=32, U=8, D=256, G=9 (the benchmark workload): whole site vectors at the
+    # first site and at the centre, plus the energy
+    wl = W.hubbard_bench(0)
+    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed)
+    E, p = gpu.energy()
+    Eo, po = orc.energy(1)
+    assert abs(E - Eo) < 1e-9 * max(1, abs(Eo))
+    rng = np.random.default_rng(7)
+    kc = wl.L // 2
+    _left_envs_to(gpu, orc, kc)
+    for k in (1, kc):
+        n = gpu.site_size(k)
+        x = rng.standard_normal(n)
+        y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
+        xd = _dev(x)
+        y, ny = torch.empty_like(xd), torch.empty_like(xd)
+        gpu.heff_apply(k, xd, y, ny)
+        torch.cuda.synchronize()
+        assert rel_err(y.cpu().numpy(), orc.mps.site_packed(k, y_ref)) < 1e-11
+        assert rel_err(ny.cpu().numpy(), orc.mps.site_packed(k, ny_ref)) < 1e-11
+
+
+def test_zero_projected_norm_is_reported():
+    # two sites, two electrons, M = 0: the MPS (|a,b> + s|b,a>) for the sign s
+    # that makes it a pure triplet has no singlet component
+    tab = W.make_block_table(2, 2, 0, 4)
+    from oracle import ed, mpo as ompo
+    st = ed.sector_states(2, 2, 0)
+    P0 = ed.spin_projector_dense(ed.s2_operator(2, st), 0)
+    chosen = None
+    for sgn in (1.0, -1.0):
+        blocks = np.zeros(tab.total_size())
+        o = omps.OracleMPS(tab, blocks)
+        # site 1: |b> -> (1,-1), |a> -> (1,1); site 2 completes to (2,0)
+        A1 = np.zeros_like(o.A[0]); A2 = np.zeros_like(o.A[1])
+        for s in (1, 2):
+            for b in range(A1.shape[2]):
+                if o.mask[0][s, 0, b]:
+                    A1[s, 0, b] = 1.0
+        for s in (1, 2):
+            for a in range(A2.shape[1]):
+                if o.mask[1][s, a, 0]:
+                    A2[s, a, 0] = 1.0 if s == 2 else sgn
+        o.A = [A1, A2]
+        psi = ed.mps_to_dense(o.A)[st]
+        if abs(psi @ P0 @ psi) < 1e-14 and np.linalg.norm(psi) > 0.5:
+            chosen = o.packed()
+    assert chosen is not None
+    gpu = sp.SPMPS(tab, chosen, sp.mpo_hubbard(2, 1.0, 4.0), 0, 2)
+    with pytest.raises(sp.SpError) as e:
+        gpu.energy()
+    assert e.value.code == sp.SP_ENORM

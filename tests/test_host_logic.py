@@ -1,0 +1,157 @@
+"""Host-side logic of the library (no GPU): exported symbols, quadrature,
+MPO builders, the subspace eigensolver and argument validation, each
+checked against the oracle or numpy."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1703_04789_amd as sp
+import workloads as W
+from oracle import mpo, quadrature as q
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "spmps.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(sp_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = sp.lib()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(sp.EXPORTS) == names
+
+
+@pytest.mark.parametrize("G,twoS,twoM", [(1, 0, 0), (5, 0, 0), (9, 2, 0), (9, 0, 0), (11, 3, 1), (7, 4, -2),
+                                         (13, 4, 0), (3, 1, -1)])
+def test_quadrature_matches_oracle(G, twoS, twoM):
+    x, w, c = sp.quadrature(G, twoS, twoM)
+    t = q.projector_quadrature(G, twoS, twoM)
+    np.testing.assert_allclose(x, t["x"], atol=1e-15)
+    np.testing.assert_allclose(w, t["w"], atol=2e-15)
+    np.testing.assert_allclose(c, t["coef"], atol=2e-15)
+
+
+@pytest.mark.parametrize("N,K,twoS,twoM", [(16, 16, 0, 0), (8, 8, 0, 0), (32, 32, 2, 0), (14, 10, 0, 0),
+                                           (5, 5, 1, 1), (48, 48, 4, 0)])
+def test_exact_points_matches_oracle(N, K, twoS, twoM):
+    assert sp.exact_points(N, K, twoS, twoM) == q.exact_point_count(N, K, twoS, twoM)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 7])
+def test_mpo_builders_match_oracle(L):
+    for (mine, ref) in ((sp.mpo_hubbard(L, 1.3, 3.7), mpo.hubbard_mpo(L, 1.3, 3.7)),
+                        (sp.mpo_s2(L), mpo.s2_mpo(L)), (sp.mpo_identity(L), mpo.identity_mpo(L))):
+        w, data = mine
+        assert list(w) == [1] + [r.shape[1] for r in ref[:-1]] + [1]
+        np.testing.assert_array_equal(data, np.concatenate([r.ravel() for r in ref]))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 32, 64])
+def test_small_eigh_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    ev, V = sp.small_eigh(A)
+    np.testing.assert_allclose(ev, np.linalg.eigvalsh(A), atol=1e-12 * max(1, np.abs(ev).max()))
+    np.testing.assert_allclose(V @ np.diag(ev) @ V.T, A, atol=1e-12 * n)
+    np.testing.assert_allclose(V.T @ V, np.eye(n), atol=1e-13 * n)
+
+
+def test_small_eigh_degenerate_and_singular():
+    rng = np.random.default_rng(1)
+    B = rng.standard_normal((20, 4))
+    A = B @ B.T
+    ev, V = sp.small_eigh(A)
+    assert np.abs(ev[:16]).max() < 1e-12
+    np.testing.assert_allclose(V @ np.diag(ev) @ V.T, A, atol=1e-12)
+    ev, V = sp.small_eigh(np.diag([2.0, 1.0, 1.0, 3.0]))
+    np.testing.assert_allclose(ev, [1, 1, 2, 3])
+
+
+class _Tab:
+    def __init__(self, L, N, twoM, bonds):
+        self.L, self.N, self.twoM, self.bonds = L, N, twoM, bonds
+
+    def flat(self):
+        return W.BlockTable(self.L, self.N, self.twoM, self.bonds).flat()
+
+
+def _init_rc(table, twoS, G, mpo_=None, N=None):
+    """sp_init_mps return code for host-rejected inputs (never reaches HIP)."""
+    nsec, sn, s2m, sdim = (np.ascontiguousarray(a, dtype=np.int32) for a in table.flat())
+    w, data = mpo_ or sp.mpo_hubbard(table.L, 1.0, 4.0)
+    w = np.ascontiguousarray(w, dtype=np.int32)
+    prob = sp._Problem(table.L, 4, table.N if N is None else N, twoS, table.twoM, G, 0)
+    m = sp._Mpo(sp._iptr(w), sp._dptr(data))
+    bt = sp._BlockTable(sp._iptr(nsec), sp._iptr(sn), sp._iptr(s2m), sp._iptr(sdim))
+    blocks = np.zeros(max(1, W.BlockTable(table.L, table.N, table.twoM, table.bonds).total_size()))
+    h = ctypes.c_void_p()
+    rc = sp.lib().sp_init_mps(ctypes.byref(prob), ctypes.byref(m), ctypes.byref(bt), sp._dptr(blocks), None,
+                              ctypes.byref(h))
+    return rc, sp.lib().sp_last_error().decode()
+
+
+def test_init_rejects_bad_spin_parity_and_range():
+    tab = W.make_block_table(4, 4, 0, 8)
+    assert _init_rc(tab, 1, 3)[0] == sp.SP_EINVAL            # N + 2S odd
+    assert _init_rc(tab, 10, 3)[0] == sp.SP_EINVAL           # S above the largest seniority
+    assert _init_rc(tab, 0, 0)[0] == sp.SP_EINVAL            # G < 1
+    tab2 = W.make_block_table(4, 4, 2, 8)
+    assert _init_rc(tab2, 0, 3)[0] == sp.SP_EINVAL           # |M| > S
+
+
+def test_init_rejects_inconsistent_block_table():
+    tab = W.make_block_table(4, 4, 0, 8)
+    bonds = [list(b) for b in tab.bonds]
+    n, m, d = bonds[2][0]
+    bonds[2][0] = (n, m, d + 50)                            # wider than its support
+    rc, msg = _init_rc(_Tab(4, 4, 0, bonds), 0, 3)
+    assert rc == sp.SP_EINVAL and "wider" in msg
+    bonds = [list(b) for b in tab.bonds]
+    bonds[2] = bonds[2][::-1]                               # unsorted
+    rc, msg = _init_rc(_Tab(4, 4, 0, bonds), 0, 3)
+    assert rc == sp.SP_EINVAL and "sorted" in msg
+
+
+def test_init_rejects_non_triangular_mpo():
+    tab = W.make_block_table(3, 3, 1, 8)
+    w, data = sp.mpo_hubbard(3, 1.0, 4.0)
+    off = 1 * 6 * 16              # site 2 starts after site 1 (1 x 6 x 16 doubles)
+    bad = data.copy()
+    bad[off + ((5 * 6 + 5) * 4 + 0) * 4 + 0] = 2.0   # W[2]_{5,5} no longer the identity
+    rc, msg = _init_rc(tab, 1, 3, mpo_=(w, bad))
+    assert rc == sp.SP_EINVAL and "identity" in msg
+
+
+@pytest.mark.parametrize("wl", [W.hubbard_small(), W.hubbard_bench(0), W.hubbard_bench(2)],
+                         ids=lambda w: w.name)
+def test_init_plans_pass_host_validation(wl):
+    """All per-site task lists of the workload are built and bounds-checked
+    on the host; without a GPU the call then stops at the first HIP call."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present: covered by the GPU tests")
+    rc, msg = _init_rc(wl.table(), wl.twoS, wl.G, mpo_=sp.mpo_hubbard(wl.L, wl.t, wl.U))
+    assert rc == sp.SP_EHIP, msg
+
+
+def test_init_plans_pass_host_validation_odd_cases():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present: covered by the GPU tests")
+    for (L, N, twoM, D, twoS, G) in [(6, 5, 1, 12, 1, 3), (7, 6, 2, 20, 4, 4), (1, 2, 0, 4, 0, 1),
+                                     (2, 2, 0, 4, 0, 2), (12, 10, 0, 128, 2, 5)]:
+        tab = W.make_block_table(L, N, twoM, D)
+        rc, msg = _init_rc(tab, twoS, G)
+        assert rc == sp.SP_EHIP, (L, N, msg)
+    tab = W.make_block_table(6, 6, 0, 20)
+    rc, msg = _init_rc(tab, 2, 4, mpo_=sp.mpo_s2(6))
+    assert rc == sp.SP_EHIP, msg
