@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--keep", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--path", default="tiled", choices=["tiled", "plain"])
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the SP-MPS path here is single-GPU "
@@ -85,37 +87,53 @@ def main():
     torch.cuda.set_device(0)
     wl = W.hubbard_bench(args.twoS)
     tab = wl.table()
-    log(f"[bench] {wl.name}: init")
-    gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G)
     kw = dict(tol=args.tol, max_iter=args.max_iter, max_sub=args.max_sub, keep=args.keep)
-    for i in range(args.warmup):
-        rc, st = gpu.sweep(1, **kw)
-        log(f"[bench] warmup sweep {i}: E={st[-1]['theta']:.10f}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    steps = []
-    for i in range(args.steps):
-        rc, st = gpu.sweep(1, **kw)
-        steps += st
-        log(f"[bench] timed sweep {i}: E={st[-1]['theta']:.10f}")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    kc = wl.L // 2
+
+    def run(path):
+        log(f"[bench] {wl.name} path={path}: init")
+        gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=path)
+        for i in range(args.warmup):
+            rc, st = gpu.sweep(1, **kw)
+            log(f"[bench] {path} warmup sweep {i}: E={st[-1]['theta']:.10f}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = []
+        for i in range(args.steps):
+            rc, st = gpu.sweep(1, **kw)
+            steps += st
+            log(f"[bench] {path} timed sweep {i}: E={st[-1]['theta']:.10f}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        # H_eff x throughput and per-phase timing at the centre site
+        for j in range(1, kc):
+            gpu.env_update(j, +1)
+        x = torch.tensor(gpu.get_site(kc), dtype=torch.float64, device="cuda")
+        y, ny = torch.empty_like(x), torch.empty_like(x)
+        prof = gpu.heff_profile(kc, x, y, ny, reps=50)
+        heff_ms = sum(p["ms"] for p in prof.values())
+        heff_flops = gpu.heff_flops(kc)
+        gpu.close()
+        log(f"[bench] {path}: {len(steps) / (t1 - t0):.2f} site steps/s; H_eff x at site {kc}: {heff_ms:.3f} ms; "
+            + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in prof.items()))
+        return dict(steps=steps, elapsed=t1 - t0, prof=prof, heff_ms=heff_ms, heff_flops=heff_flops,
+                    heff_tflops=heff_flops / (heff_ms * 1e-3) / 1e12)
+
+    main_run = run(args.path)
+    steps, elapsed, prof = main_run["steps"], main_run["elapsed"], main_run["prof"]
     n_site_steps = len(steps)
-    elapsed = t1 - t0
     value = n_site_steps / elapsed
     mv = float(np.mean([s["matvecs"] for s in steps]))
     energy = steps[-1]["theta"]
-
-    # H_eff x throughput and per-launch roofline at the centre site
-    kc = wl.L // 2
-    for j in range(1, kc):
-        gpu.env_update(j, +1)
-    x = torch.tensor(gpu.get_site(kc), dtype=torch.float64, device="cuda")
-    y, ny = torch.empty_like(x), torch.empty_like(x)
-    prof = gpu.heff_profile(kc, x, y, ny, reps=50)
-    heff_ms = sum(p["ms"] for p in prof.values())
-    heff_flops = gpu.heff_flops(kc)
-    heff_tflops = heff_flops / (heff_ms * 1e-3) / 1e12
+    heff_ms, heff_flops, heff_tflops = main_run["heff_ms"], main_run["heff_flops"], main_run["heff_tflops"]
+    plain = None
+    if args.path != "plain" and not args.no_plain:
+        pr = run("plain")
+        pv = len(pr["steps"]) / pr["elapsed"]
+        plain = {"value": pv, "unit": "site steps/s", "heff_tflops": pr["heff_tflops"], "heff_ms": pr["heff_ms"],
+                 "energy_after_timed_sweeps": pr["steps"][-1]["theta"],
+                 "speedup_site_steps": value / pv, "speedup_heff": pr["heff_ms"] / heff_ms,
+                 "max_step_dE_vs_this_path": max(abs(a["theta"] - b["theta"]) for a, b in zip(steps, pr["steps"]))}
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
     intensity = dom["flops"] / dom["bytes"]
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
@@ -127,11 +145,8 @@ def main():
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = f"k_bgemm ({dom_name}) at site {kc}"
+    roof["kernel"] = f"{'k_bgemm' if args.path == 'plain' else 'k_tgemm'} ({dom_name}) at site {kc}"
     roof["per_launch"] = {k: {"ms": v["ms"], "flops": v["flops"], "bytes": v["bytes"]} for k, v in prof.items()}
-    log(f"[bench] H_eff x at site {kc}: {heff_ms:.3f} ms, {heff_tflops:.3f} TFLOP/s; phases "
-        + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in prof.items()))
-    gpu.close()
 
     out = {
         "metric": "projected sweep sites/sec + H_eff·x TFLOP/s vs plain FP64 GPU at |dE|<=1e-6 Eh",
@@ -147,7 +162,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "L": wl.L, "t": wl.t, "U": wl.U, "N": wl.N, "twoS": wl.twoS,
-                   "twoM": wl.twoM, "D": wl.D, "G": wl.G, "seed": wl.seed, "path": "plain FP64",
+                   "twoM": wl.twoM, "D": wl.D, "G": wl.G, "seed": wl.seed, "path": f"{args.path} FP64",
                    "davidson": {"tol": args.tol, "max_iter": args.max_iter, "max_sub": args.max_sub,
                                 "keep": args.keep}},
         "site_steps": n_site_steps,
@@ -157,6 +172,7 @@ def main():
         "heff_ms": heff_ms,
         "heff_flops": heff_flops,
         "roofline": roof,
+        "plain_fp64": plain,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, mv)

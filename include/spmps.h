@@ -50,6 +50,12 @@ extern "C" {
 
 #define SP_FP64 0         /* every contraction in FP64 */
 
+#define SP_PATH_TILED 0   /* LDS-tiled dense products over particle-number
+                             blocks (zero-padded in M, empty K ranges
+                             skipped), per-g partial outputs              */
+#define SP_PATH_PLAIN 1   /* one work-group per (N, M) block product, the
+                             plain FP64 reference path                      */
+
 typedef struct sp_handle sp_handle;
 
 /* Problem: L sites, d must be 4, N electrons, spin S = twoS/2 with projection
@@ -65,6 +71,7 @@ typedef struct sp_problem {
     int twoM;
     int G;
     int precision; /* SP_FP64 */
+    int path;      /* SP_PATH_TILED or SP_PATH_PLAIN: same results to rounding */
 } sp_problem;
 
 /* MPO in the operator-valued-matrix form of Sec. 2.1, Eq. [FSMPO]:
@@ -177,8 +184,9 @@ int sp_center(const sp_handle* h, int* site);
  * (L_g x, the W r mixing, then R_g, for both H_eff and N_eff). */
 int sp_heff_flops(const sp_handle* h, int site, double* flops);
 
-/* Timing of the three launches of sp_heff_apply at `site` (left product,
- * W r mixing, right product with the g reduction), each averaged over
+/* Timing of the three phases of sp_heff_apply at `site` (left product,
+ * W r mixing, right product with the g reduction; on the tiled path the
+ * first includes the dense gather and the last the g sum), each averaged over
  * `reps` launches with HIP events on the handle's stream.  out[0..2]: mean
  * milliseconds per launch; out[3..5]: algorithmic flops per launch;
  * out[6..8]: algorithmic bytes per launch (every array read or written once:

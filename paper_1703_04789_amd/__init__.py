@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libspmps.so")
 SP_OK, SP_ENOCONV, SP_WINEXACT = 0, 1, 2
 SP_EINVAL, SP_ENORM, SP_EHIP, SP_ENOMEM, SP_ESTATE, SP_ENAN = -1, -2, -3, -4, -5, -6
 SP_FP64 = 0
+SP_PATH_TILED, SP_PATH_PLAIN = 0, 1
 
 EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_sweep", "sp_energy",
            "sp_destroy", "sp_site_size", "sp_get_site", "sp_set_site", "sp_center", "sp_heff_flops",
@@ -36,7 +37,8 @@ class SpError(RuntimeError):
 
 class _Problem(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("d", ctypes.c_int), ("N", ctypes.c_int), ("twoS", ctypes.c_int),
-                ("twoM", ctypes.c_int), ("G", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("twoM", ctypes.c_int), ("G", ctypes.c_int), ("precision", ctypes.c_int),
+                ("path", ctypes.c_int)]
 
 
 class _Mpo(ctypes.Structure):
@@ -179,13 +181,14 @@ class SPMPS:
     tensors; ``mpo``: (w, data) as returned by :func:`mpo_hubbard`.
     """
 
-    def __init__(self, table, blocks, mpo, twoS, G, stream=None):
+    def __init__(self, table, blocks, mpo, twoS, G, stream=None, path="tiled"):
         import torch
         self._torch = torch
         nsec, sn, s2m, sdim = (np.ascontiguousarray(a, dtype=np.int32) for a in table.flat())
         self._keep = (nsec, sn, s2m, sdim)
         self.L, self.N, self.twoM, self.twoS, self.G = table.L, table.N, table.twoM, twoS, G
-        prob = _Problem(self.L, 4, self.N, twoS, self.twoM, G, SP_FP64)
+        prob = _Problem(self.L, 4, self.N, twoS, self.twoM, G, SP_FP64,
+                        {"tiled": SP_PATH_TILED, "plain": SP_PATH_PLAIN}[path])
         w, data = mpo
         w = np.ascontiguousarray(w, dtype=np.int32)
         data = np.ascontiguousarray(data, dtype=np.float64)

@@ -61,6 +61,30 @@ struct QrPiece {
     int transposed, row0;  // row offset in the gathered matrix
 };
 
+// Dense tile product: one 64x64 output tile C[r0:r0+64, c0:c0+64] of an
+// M x N block = sum over segments of coef[cidx] * A[:, k0:k1] B[k0:k1, :].
+// ta/tb = 1 read A (resp. B) transposed: A(r, k) = A[k*lda + r],
+// B(k, c) = B[c*ldb + k].  mode 0 stores C[c_off + r*ldc + c]; mode 1 stores
+// element (r, c) at C[c_off + map[pack_off + r*N + c]] when that index is
+// >= 0 (scatter of a particle-number block into the packed (N, M) layout).
+struct TTask {
+    long long c_off, pack_off;
+    int c_buf, ldc, M, N, r0, c0, s0, s1, mode, pad;
+};
+struct TSeg {
+    long long a_off, b_off;
+    int a_buf, b_buf, lda, ldb, ta, tb, k0, k1, cidx, pad;
+};
+constexpr int kTile = 64;
+
+void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
+           const int* map);
+// dst[e] = map[e] >= 0 ? src[map[e]] : 0, e < n
+void gather(hipStream_t s, const int* map, const double* src, double* dst, long long n);
+// out[e] = sum_{g < G} part[g*stride + e] in ascending g, for two arrays at once
+void gsum2(hipStream_t s, const double* pa, const double* pb, long long stride, int G, int n, double* outa,
+           double* outb);
+
 void bgemm(hipStream_t s, const BTask* tasks, int ntasks, const BTerm* terms, BufSet bufs,
            const double* coef);
 void combine(hipStream_t s, const CTask* tasks, int ntasks, const CTerm* terms, BufSet bufs,

@@ -359,10 +359,132 @@ __global__ __launch_bounds__(kThreads) void k_scale(double* __restrict__ x, int 
     x[e] = s > 0.0 ? x[e] / sqrt(s) : x[e];
 }
 
+// 64x64 output tile per work-group of 256 threads (16 x 16 threads, 4 x 4
+// outputs each, rows ty + 16 i and columns tx + 16 j); K staged through LDS
+// in chunks of 16 with coalesced global loads for either operand layout.
+constexpr int kKC = 16;
+
+__global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ tasks,
+                                                      const TSeg* __restrict__ segs, BufSet bufs,
+                                                      const double* __restrict__ coef,
+                                                      const int* __restrict__ map) {
+    __shared__ double As[kKC][kTile + 1];
+    __shared__ double Bs[kKC][kTile + 1];
+    const TTask tk = tasks[blockIdx.x];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int s = tk.s0; s < tk.s1; ++s) {
+        const TSeg sg = segs[s];
+        const double cf = coef[sg.cidx];
+        const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
+        const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
+        for (int kb = sg.k0; kb < sg.k1; kb += kKC) {
+            for (int idx = threadIdx.x; idx < kTile * kKC; idx += kThreads) {
+                int r, k;
+                if (sg.ta == 0) {
+                    r = idx / kKC;
+                    k = idx % kKC;
+                } else {
+                    k = idx / kTile;
+                    r = idx % kTile;
+                }
+                const int gr = tk.r0 + r, gk = kb + k;
+                double v = 0.0;
+                if (gr < tk.M && gk < sg.k1)
+                    v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
+                As[k][r] = cf * v;
+            }
+            for (int idx = threadIdx.x; idx < kTile * kKC; idx += kThreads) {
+                int c, k;
+                if (sg.tb == 0) {
+                    k = idx / kTile;
+                    c = idx % kTile;
+                } else {
+                    c = idx / kKC;
+                    k = idx % kKC;
+                }
+                const int gc = tk.c0 + c, gk = kb + k;
+                double v = 0.0;
+                if (gc < tk.N && gk < sg.k1)
+                    v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
+                Bs[k][c] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kKC; ++k) {
+                double a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+            }
+            __syncthreads();
+        }
+    }
+    double* C = bufs.p[tk.c_buf] + tk.c_off;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = tk.r0 + ty + 16 * i;
+        if (r >= tk.M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = tk.c0 + tx + 16 * j;
+            if (c >= tk.N) continue;
+            if (tk.mode == 0) {
+                C[(long long)r * tk.ldc + c] = acc[i][j];
+            } else {
+                const int p = map[tk.pack_off + (long long)r * tk.N + c];
+                if (p >= 0) C[p] = acc[i][j];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather(const int* __restrict__ map, const double* __restrict__ src,
+                                                       double* __restrict__ dst, long long n) {
+    const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n) return;
+    const int p = map[e];
+    dst[e] = p >= 0 ? src[p] : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gsum2(const double* __restrict__ pa, const double* __restrict__ pb,
+                                                      long long stride, int G, int n, double* __restrict__ outa,
+                                                      double* __restrict__ outb) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n) return;
+    double sa = 0.0, sb = 0.0;
+    for (int g = 0; g < G; ++g) {
+        sa += pa[g * stride + e];
+        sb += pb[g * stride + e];
+    }
+    outa[e] = sa;
+    outb[e] = sb;
+}
+
 inline int nblk(int n) { return (n + kThreads - 1) / kThreads; }
 
 }  // namespace
 
+void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
+           const int* map) {
+    if (ntasks > 0) hipLaunchKernelGGL(k_tgemm, dim3(ntasks), dim3(kThreads), 0, s, tasks, segs, bufs, coef, map);
+}
+void gather(hipStream_t s, const int* map, const double* src, double* dst, long long n) {
+    if (n > 0) hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, map, src, dst, n);
+}
+void gsum2(hipStream_t s, const double* pa, const double* pb, long long stride, int G, int n, double* outa,
+           double* outb) {
+    hipLaunchKernelGGL(k_gsum2, dim3(nblk(n)), dim3(kThreads), 0, s, pa, pb, stride, G, n, outa, outb);
+}
 void bgemm(hipStream_t s, const BTask* tasks, int ntasks, const BTerm* terms, BufSet bufs,
            const double* coef) {
     if (ntasks > 0) hipLaunchKernelGGL(k_bgemm, dim3(ntasks), dim3(kThreads), 0, s, tasks, terms, bufs, coef);

@@ -223,6 +223,51 @@ struct CList {
     }
 };
 
+struct TList {
+    std::vector<spk::TTask> tasks;
+    std::vector<spk::TSeg> segs;
+    DArr<spk::TTask> dtasks;
+    DArr<spk::TSeg> dsegs;
+    void add_task(int c_buf, long long c_off, int ldc, int M, int N, int r0, int c0, int mode, long long pack_off) {
+        spk::TTask t{};
+        t.c_off = c_off;
+        t.pack_off = pack_off;
+        t.c_buf = c_buf;
+        t.ldc = ldc;
+        t.M = M;
+        t.N = N;
+        t.r0 = r0;
+        t.c0 = c0;
+        t.s0 = t.s1 = int(segs.size());
+        t.mode = mode;
+        tasks.push_back(t);
+    }
+    void add_seg(int a_buf, long long a_off, int lda, int ta, int b_buf, long long b_off, int ldb, int tb, int k0,
+                 int k1, int cidx) {
+        spk::TSeg g{};
+        g.a_off = a_off;
+        g.b_off = b_off;
+        g.a_buf = a_buf;
+        g.b_buf = b_buf;
+        g.lda = lda;
+        g.ldb = ldb;
+        g.ta = ta;
+        g.tb = tb;
+        g.k0 = k0;
+        g.k1 = k1;
+        g.cidx = cidx;
+        segs.push_back(g);
+        tasks.back().s1 = int(segs.size());
+    }
+    void upload(hipStream_t s) {
+        dtasks.upload(tasks, s);
+        dsegs.upload(segs, s);
+    }
+    void launch(hipStream_t s, const spk::BufSet& b, const double* coef, const int* map) const {
+        spk::tgemm(s, dtasks.p, int(tasks.size()), dsegs.p, b, coef, map);
+    }
+};
+
 // buffer slots of a launch
 enum Buf { B_ENVL = 0, B_ENVR = 1, B_X = 2, B_T = 3, B_V = 4, B_Y = 5, B_NY = 6, B_OUT = 7 };
 
@@ -257,6 +302,11 @@ struct SitePlan {
     std::vector<long long> lq_roff;  // per left sector of bond k-1
     BList absorb_right;  // R of site k into site k+1
     BList absorb_left;   // L of site k into site k-1
+    // tiled path: dense particle-number layout of the site and its tile lists
+    long long Xd_size = 0;
+    std::vector<int> xmap_h;  // dense element -> packed index or -1
+    DArr<int> xmap;
+    TList t_left, t_right, t_envl, t_zr, t_envr;
 };
 
 }  // namespace
@@ -278,7 +328,9 @@ struct sp_handle {
     DArr<double> mps;
     long long mps_size = 0, max_site = 0;
     std::vector<SitePlan> plan;            // index k-1
-    DArr<double> T, V, qr_scratch, qr_r, tmp_site;
+    int path = SP_PATH_TILED;
+    DArr<double> T, V, qr_scratch, qr_r, tmp_site, Xd, ypart, nypart;
+    long long Xd_cap = 0;
     long long T_cap = 0, V_cap = 0, qr_scratch_cap = 0, qr_r_cap = 0;
     int center = 1;
     // Davidson workspace
@@ -884,6 +936,167 @@ void build_plan(sp_handle* h, int k) {
     // algorithmic flops of one H_eff x: per g the left product, the mixing and
     // the right product for y, and the right product of ny
     P.heff_flops = P.p1.flops + P.mixl.flops + P.yout.flops;
+
+    // ================= tiled path =================
+    // dense particle-number blocks Xd(j, sigma, jb) of the site (zero outside
+    // the (N, M) blocks) and the map from dense elements to packed indices
+    std::vector<long long> Xdoff(bl.nb.size() * 4, -1);
+    long long xd = 0;
+    for (int j = 0; j < int(bl.nb.size()); ++j)
+        for (int q = 0; q < 4; ++q) {
+            const int jb = br.nblock(bl.nb[j].n + kSigmaN[q]);
+            if (jb < 0) continue;
+            Xdoff[size_t(j) * 4 + q] = xd;
+            xd += (long long)bl.nb[j].dim * br.nb[jb].dim;
+        }
+    P.Xd_size = xd;
+    P.xmap_h.assign(size_t(std::max(1LL, xd)), -1);
+    for (const XBlk& X : si.blk) {
+        const Sector& SA = bl.sec[X.sa];
+        const Sector& SB = br.sec[X.sb];
+        const int ldb = br.nb[SB.nb].dim;
+        const long long base = Xdoff[size_t(SA.nb) * 4 + X.s];
+        for (int r = 0; r < X.rows; ++r)
+            for (int c = 0; c < X.cols; ++c)
+                P.xmap_h[base + (long long)(SA.ro + r) * ldb + SB.ro + c] = int(X.off + (long long)r * X.cols + c);
+    }
+    auto xdoff = [&](int j, int q) { return Xdoff[size_t(j) * 4 + q]; };
+    // rows of N-block j (bond k-1) that columns [c0, c1) of N-block jb (bond k)
+    // reach through sigma, as one contiguous range
+    auto k_from_cols = [&](int jb, int q, int c0, int c1, int& k0, int& k1) {
+        k0 = INT32_MAX;
+        k1 = -1;
+        const NBlock& NB = br.nb[jb];
+        for (int sb = NB.s0; sb < NB.s1; ++sb) {
+            const Sector& SB = br.sec[sb];
+            if (SB.ro + SB.dim <= c0 || SB.ro >= c1) continue;
+            const int sa = bl.sector(SB.n - kSigmaN[q], SB.m2 - kSigma2M[q]);
+            if (sa < 0) continue;
+            k0 = std::min(k0, bl.sec[sa].ro);
+            k1 = std::max(k1, bl.sec[sa].ro + bl.sec[sa].dim);
+        }
+        return k1 > k0;
+    };
+    // columns of N-block jb (bond k) that rows [r0, r1) of N-block j reach
+    auto k_from_rows = [&](int j, int q, int r0, int r1, int& k0, int& k1) {
+        k0 = INT32_MAX;
+        k1 = -1;
+        const NBlock& NA = bl.nb[j];
+        for (int sa = NA.s0; sa < NA.s1; ++sa) {
+            const Sector& SA = bl.sec[sa];
+            if (SA.ro + SA.dim <= r0 || SA.ro >= r1) continue;
+            const int sb = br.sector(SA.n + kSigmaN[q], SA.m2 + kSigma2M[q]);
+            if (sb < 0) continue;
+            k0 = std::min(k0, br.sec[sb].ro);
+            k1 = std::max(k1, br.sec[sb].ro + br.sec[sb].dim);
+        }
+        return k1 > k0;
+    };
+    const int TT = spk::kTile;
+    // left product: T(eb, sigma') = L_g(eb) Xd(j, sigma', jb)
+    for (int g = 0; g < G; ++g)
+        for (size_t e = 0; e < el.blk.size(); ++e)
+            for (int q = 0; q < 4; ++q) {
+                if (Toff[e * 4 + q] < 0) continue;
+                const EnvBlk& eb = el.blk[e];
+                const int jb = br.nblock(bl.nb[eb.j].n + kSigmaN[q]);
+                const int ncol = br.nb[jb].dim;
+                for (int r0 = 0; r0 < eb.rows; r0 += TT)
+                    for (int c0 = 0; c0 < ncol; c0 += TT) {
+                        P.t_left.add_task(B_T, g * P.Tsize + Toff[e * 4 + q], ncol, eb.rows, ncol, r0, c0, 0, 0);
+                        int k0, k1;
+                        if (k_from_cols(jb, q, c0, std::min(ncol, c0 + TT), k0, k1))
+                            P.t_left.add_seg(B_ENVL, g * Lsz + eb.off, eb.cols, 0, B_X, xdoff(eb.j, q), ncol, 0, k0, k1,
+                                             g * P.nc + P.c_one());
+                    }
+            }
+    // right product: per g partial y and ny, scattered into the packed layout
+    const long long xs = si.size;
+    for (int g = 0; g < G; ++g)
+        for (int i = 0; i < int(bl.nb.size()); ++i)
+            for (int sig = 0; sig < 4; ++sig) {
+                const int nbb = br.nblock(bl.nb[i].n + kSigmaN[sig]);
+                if (nbb < 0) continue;
+                const int M = bl.nb[i].dim, Nn = br.nb[nbb].dim;
+                for (int r0 = 0; r0 < M; r0 += TT)
+                    for (int c0 = 0; c0 < Nn; c0 += TT) {
+                        int k0, k1;
+                        if (!k_from_rows(i, sig, r0, std::min(M, r0 + TT), k0, k1)) continue;
+                        if (k1 <= c0 || k0 >= std::min(Nn, c0 + TT)) continue;  // no (N, M) block in the tile
+                        P.t_right.add_task(B_Y, g * xs, Nn, M, Nn, r0, c0, 1, xdoff(i, sig));
+                        for (int cp = 0; cp < wr; ++cp) {
+                            auto it = Voff.find({sig, cp, i});
+                            if (it == Voff.end()) continue;
+                            const int re = er.find(cp, nbb);
+                            if (re < 0) continue;
+                            const EnvBlk& RB = er.blk[re];
+                            P.t_right.add_seg(B_V, g * P.Vsize + it->second, RB.cols, 0, B_ENVR, g * Rsz + RB.off,
+                                              RB.cols, 1, 0, RB.cols, g * P.nc + P.c_g());
+                        }
+                        P.t_right.add_task(B_NY, g * xs, Nn, M, Nn, r0, c0, 1, xdoff(i, sig));
+                        const int e0 = el.find(0, i);
+                        const int re = er.find(lastR, nbb);
+                        if (e0 < 0 || re < 0) continue;
+                        for (int q = 0; q < 4; ++q) {
+                            if (!rot_nonzero(sig, q)) continue;
+                            const long long to = Toff[size_t(e0) * 4 + q];
+                            if (to < 0) continue;
+                            const EnvBlk& RB = er.blk[re];
+                            P.t_right.add_seg(B_T, g * P.Tsize + to, Tcols[size_t(e0) * 4 + q], 0, B_ENVR,
+                                              g * Rsz + RB.off, RB.cols, 1, 0, RB.cols, g * P.nc + P.c_gr(sig, q));
+                        }
+                    }
+            }
+    // left environment: L[k](c', b, b') = sum_sigma Xd(a, sigma, b)^T V(sigma, c', a)
+    for (int g = 0; g < G; ++g)
+        for (const EnvBlk& OB : er.blk)
+            for (int r0 = 0; r0 < OB.rows; r0 += TT)
+                for (int c0 = 0; c0 < OB.cols; c0 += TT) {
+                    P.t_envl.add_task(B_OUT, g * Rsz + OB.off, OB.cols, OB.rows, OB.cols, r0, c0, 0, 0);
+                    for (int q = 0; q < 4; ++q) {
+                        const int a = bl.nblock(br.nb[OB.i].n - kSigmaN[q]);
+                        if (a < 0) continue;
+                        auto it = Voff.find({q, OB.c, a});
+                        if (it == Voff.end()) continue;
+                        int k0, k1;
+                        if (!k_from_cols(OB.i, q, r0, std::min(OB.rows, r0 + TT), k0, k1)) continue;
+                        P.t_envl.add_seg(B_X, xdoff(a, q), OB.rows, 1, B_V, g * P.Vsize + it->second, OB.cols, 0, k0,
+                                         k1, g * P.nc + P.c_one());
+                    }
+                }
+    // right pass: Z(rb, sigma') = Xd(i, sigma', b') R_g(rb)^T
+    for (int g = 0; g < G; ++g)
+        for (size_t e = 0; e < er.blk.size(); ++e)
+            for (int q = 0; q < 4; ++q) {
+                if (Zoff[e * 4 + q] < 0) continue;
+                const EnvBlk& rb = er.blk[e];
+                const int i = bl.nblock(br.nb[rb.j].n - kSigmaN[q]);
+                const int M = bl.nb[i].dim;
+                for (int r0 = 0; r0 < M; r0 += TT)
+                    for (int c0 = 0; c0 < rb.rows; c0 += TT) {
+                        P.t_zr.add_task(B_T, g * P.Zsize + Zoff[e * 4 + q], rb.rows, M, rb.rows, r0, c0, 0, 0);
+                        int k0, k1;
+                        if (k_from_rows(i, q, r0, std::min(M, r0 + TT), k0, k1))
+                            P.t_zr.add_seg(B_X, xdoff(i, q), rb.cols, 0, B_ENVR, g * Rsz + rb.off, rb.cols, 1, k0, k1,
+                                           g * P.nc + P.c_one());
+                    }
+            }
+    // right environment: R(c, a, a') = sum_sigma Xd(a, sigma, b) Zt(sigma, c, a')^T
+    for (int g = 0; g < G; ++g)
+        for (const EnvBlk& OB : el.blk)
+            for (int r0 = 0; r0 < OB.rows; r0 += TT)
+                for (int c0 = 0; c0 < OB.cols; c0 += TT) {
+                    P.t_envr.add_task(B_OUT, g * Lsz + OB.off, OB.cols, OB.rows, OB.cols, r0, c0, 0, 0);
+                    for (int q = 0; q < 4; ++q) {
+                        auto it = Ztoff.find({q, OB.c, OB.j});
+                        if (it == Ztoff.end()) continue;
+                        const int nbb = br.nblock(bl.nb[OB.i].n + kSigmaN[q]);
+                        int k0, k1;
+                        if (!k_from_rows(OB.i, q, r0, std::min(OB.rows, r0 + TT), k0, k1)) continue;
+                        P.t_envr.add_seg(B_X, xdoff(OB.i, q), br.nb[nbb].dim, 0, B_V, g * P.Ztsize + it->second,
+                                         br.nb[nbb].dim, 1, k0, k1, g * P.nc + P.c_one());
+                    }
+                }
 }
 
 void upload_plan(sp_handle* h, int k) {
@@ -907,6 +1120,12 @@ void upload_plan(sp_handle* h, int k) {
     P.dlq_pieces.upload(P.lq_pieces, s);
     P.absorb_right.upload(s);
     P.absorb_left.upload(s);
+    P.xmap.upload(P.xmap_h, s);
+    P.t_left.upload(s);
+    P.t_right.upload(s);
+    P.t_envl.upload(s);
+    P.t_zr.upload(s);
+    P.t_envr.upload(s);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,6 +1165,32 @@ void validate(const CList& b, const Sizes& sz, long long ncoef, const char* what
     }
 }
 
+void validate(const TList& b, const Sizes& sz, long long ncoef, long long map_size, long long packed_max,
+              const char* what) {
+    const int TT = spk::kTile;
+    for (const spk::TTask& t : b.tasks) {
+        if (t.r0 < 0 || t.c0 < 0 || t.r0 >= t.M || t.c0 >= t.N) throw SpError(SP_EINVAL, std::string("internal tile: ") + what);
+        const int rl = std::min(t.M, t.r0 + TT) - 1, cl = std::min(t.N, t.c0 + TT) - 1;
+        if (t.mode == 0) {
+            check_span(t.c_off + (long long)t.r0 * t.ldc + t.c0, t.c_off + (long long)rl * t.ldc + cl, sz[t.c_buf], what);
+        } else {
+            check_span(t.pack_off, t.pack_off + (long long)(t.M - 1) * t.N + (t.N - 1), map_size, what);
+            check_span(t.c_off, t.c_off + packed_max - 1, sz[t.c_buf], what);
+        }
+        for (int i = t.s0; i < t.s1; ++i) {
+            const spk::TSeg& g = b.segs[i];
+            if (g.k0 < 0 || g.k1 <= g.k0) throw SpError(SP_EINVAL, std::string("internal segment: ") + what);
+            const long long a_first = g.ta ? g.a_off + (long long)g.k0 * g.lda + t.r0 : g.a_off + (long long)t.r0 * g.lda + g.k0;
+            const long long a_last = g.ta ? g.a_off + (long long)(g.k1 - 1) * g.lda + rl : g.a_off + (long long)rl * g.lda + (g.k1 - 1);
+            const long long b_first = g.tb ? g.b_off + (long long)t.c0 * g.ldb + g.k0 : g.b_off + (long long)g.k0 * g.ldb + t.c0;
+            const long long b_last = g.tb ? g.b_off + (long long)cl * g.ldb + (g.k1 - 1) : g.b_off + (long long)(g.k1 - 1) * g.ldb + cl;
+            check_span(a_first, a_last, sz[g.a_buf], what);
+            check_span(b_first, b_last, sz[g.b_buf], what);
+            check_span(g.cidx, g.cidx, ncoef, what);
+        }
+    }
+}
+
 void validate_plans(sp_handle* h) {
     const long long G = h->G;
     for (int k = 1; k <= h->L; ++k) {
@@ -974,6 +1219,24 @@ void validate_plans(sp_handle* h) {
         validate(P.envl_out, z, nco, "left environment");
         z[B_OUT] = Lb;
         validate(P.envr_out, z, nco, "right environment");
+        // tiled lists: B_X is the dense site layout, B_Y/B_NY the per-g partials
+        {
+            Sizes t = z;
+            t[B_X] = h->Xd_cap;
+            t[B_Y] = G * h->max_site;
+            t[B_NY] = G * h->max_site;
+            for (int e : P.xmap_h)
+                if (e >= xs) throw SpError(SP_EINVAL, "internal: packed map out of range");
+            const long long ms = (long long)P.xmap_h.size();
+            validate(P.t_left, t, nco, ms, xs, "tiled left product");
+            validate(P.t_right, t, nco, ms, xs, "tiled right product");
+            validate(P.t_zr, t, nco, ms, xs, "tiled right-pass product");
+            t[B_OUT] = Rb;
+            validate(P.t_envl, t, nco, ms, xs, "tiled left environment");
+            t[B_OUT] = Lb;
+            validate(P.t_envr, t, nco, ms, xs, "tiled right environment");
+            if (P.Xd_size > h->Xd_cap) throw SpError(SP_EINVAL, "internal: dense site scratch too small");
+        }
         if (k < h->L) {
             Sizes a{};
             a.fill(0);
@@ -1048,19 +1311,39 @@ void heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny) {
     if (!h->Lvalid[k - 1] || !h->Rvalid[k])
         throw SpError(SP_ESTATE, "H_eff needs L[site-1] and R[site+1]; build them with sp_env_update");
     SitePlan& P = h->plan[k - 1];
-    const spk::BufSet b = bufset(h, k, x, y, ny, nullptr);
-    P.p1.launch(h->stream, b, P.coef.p);
-    P.mixl.launch(h->stream, b, P.coef.p);
-    P.yout.launch(h->stream, b, P.coef.p);
+    hipStream_t s = h->stream;
+    if (h->path == SP_PATH_PLAIN) {
+        const spk::BufSet b = bufset(h, k, x, y, ny, nullptr);
+        P.p1.launch(s, b, P.coef.p);
+        P.mixl.launch(s, b, P.coef.p);
+        P.yout.launch(s, b, P.coef.p);
+        return;
+    }
+    const spk::BufSet b = bufset(h, k, h->Xd.p, h->ypart.p, h->nypart.p, nullptr);
+    spk::gather(s, P.xmap.p, x, h->Xd.p, P.Xd_size);
+    P.t_left.launch(s, b, P.coef.p, P.xmap.p);
+    P.mixl.launch(s, b, P.coef.p);
+    P.t_right.launch(s, b, P.coef.p, P.xmap.p);
+    const int n = int(h->sites[k - 1].size);
+    spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
 }
 
 void env_left(sp_handle* h, int k) {
     if (!h->Lvalid[k - 1]) throw SpError(SP_ESTATE, "left environment of the previous bond is not built");
     SitePlan& P = h->plan[k - 1];
-    const spk::BufSet b = bufset(h, k, site_ptr(h, k), nullptr, nullptr, h->envL[k].p);
-    P.p1.launch(h->stream, b, P.coef.p);
-    P.mixl.launch(h->stream, b, P.coef.p);
-    P.envl_out.launch(h->stream, b, P.coef.p);
+    hipStream_t s = h->stream;
+    if (h->path == SP_PATH_PLAIN) {
+        const spk::BufSet b = bufset(h, k, site_ptr(h, k), nullptr, nullptr, h->envL[k].p);
+        P.p1.launch(s, b, P.coef.p);
+        P.mixl.launch(s, b, P.coef.p);
+        P.envl_out.launch(s, b, P.coef.p);
+    } else {
+        const spk::BufSet b = bufset(h, k, h->Xd.p, nullptr, nullptr, h->envL[k].p);
+        spk::gather(s, P.xmap.p, site_ptr(h, k), h->Xd.p, P.Xd_size);
+        P.t_left.launch(s, b, P.coef.p, P.xmap.p);
+        P.mixl.launch(s, b, P.coef.p);
+        P.t_envl.launch(s, b, P.coef.p, P.xmap.p);
+    }
     h->Lvalid[k] = 1;
     for (int q = k + 1; q <= h->L; ++q) h->Lvalid[q] = 0;
 }
@@ -1068,10 +1351,19 @@ void env_left(sp_handle* h, int k) {
 void env_right(sp_handle* h, int k) {
     if (!h->Rvalid[k]) throw SpError(SP_ESTATE, "right environment of the next bond is not built");
     SitePlan& P = h->plan[k - 1];
-    spk::BufSet b = bufset(h, k, site_ptr(h, k), nullptr, nullptr, h->envR[k - 1].p);
-    P.p1r.launch(h->stream, b, P.coef.p);
-    P.mixr.launch(h->stream, b, P.coef.p);
-    P.envr_out.launch(h->stream, b, P.coef.p);
+    hipStream_t s = h->stream;
+    if (h->path == SP_PATH_PLAIN) {
+        const spk::BufSet b = bufset(h, k, site_ptr(h, k), nullptr, nullptr, h->envR[k - 1].p);
+        P.p1r.launch(s, b, P.coef.p);
+        P.mixr.launch(s, b, P.coef.p);
+        P.envr_out.launch(s, b, P.coef.p);
+    } else {
+        const spk::BufSet b = bufset(h, k, h->Xd.p, nullptr, nullptr, h->envR[k - 1].p);
+        spk::gather(s, P.xmap.p, site_ptr(h, k), h->Xd.p, P.Xd_size);
+        P.t_zr.launch(s, b, P.coef.p, P.xmap.p);
+        P.mixr.launch(s, b, P.coef.p);
+        P.t_envr.launch(s, b, P.coef.p, P.xmap.p);
+    }
     h->Rvalid[k - 1] = 1;
     for (int q = 0; q < k - 1; ++q) h->Rvalid[q] = 0;
 }
@@ -1387,6 +1679,7 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         *out = nullptr;
         SP_REQUIRE(p->L >= 1 && p->d == 4, "need L >= 1 and d == 4");
         SP_REQUIRE(p->precision == SP_FP64, "only SP_FP64 is available");
+        SP_REQUIRE(p->path == SP_PATH_TILED || p->path == SP_PATH_PLAIN, "unknown kernel path");
         SP_REQUIRE(p->N >= 0 && p->N <= 2 * p->L, "N out of range");
         SP_REQUIRE((p->N + p->twoS) % 2 == 0, "N and 2S must have the same parity");
         SP_REQUIRE((p->N + p->twoM) % 2 == 0, "N and 2M must have the same parity");
@@ -1395,6 +1688,7 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         SP_REQUIRE(p->G >= 1 && p->G <= 1024, "G out of range");
         std::unique_ptr<sp_handle> h(new sp_handle());
         h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        h->path = p->path;
         h->L = p->L;
         h->N = p->N;
         h->twoS = p->twoS;
@@ -1425,6 +1719,8 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         h->V_cap = h->G * std::max(1LL, Vmax);
         h->qr_scratch_cap = std::max(1LL, qrs);
         h->qr_r_cap = std::max(1LL, qrr);
+        for (int k = 1; k <= h->L; ++k) h->Xd_cap = std::max(h->Xd_cap, h->plan[k - 1].Xd_size);
+        h->Xd_cap = std::max(1LL, h->Xd_cap);
         validate_plans(h.get());
         // every host-side check is done; device work starts here
         HIPCK(hipGetDevice(&h->device));
@@ -1436,6 +1732,11 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         h->qr_r.alloc(h->qr_r_cap);
         h->tmp_site.alloc(h->max_site);
         h->mps.alloc(h->mps_size);
+        if (h->path == SP_PATH_TILED) {
+            h->Xd.alloc(h->Xd_cap);
+            h->ypart.alloc(size_t(h->G) * h->max_site);
+            h->nypart.alloc(size_t(h->G) * h->max_site);
+        }
         HIPCK(hipMemcpyAsync(h->mps.p, init_blocks, h->mps_size * sizeof(double), hipMemcpyHostToDevice, h->stream));
         // right-canonical form of sites L..2 and the right environments
         for (int k = h->L; k >= 2; --k) {
@@ -1623,18 +1924,32 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
         check_site(h, site);
         if (!h->Lvalid[site - 1] || !h->Rvalid[site]) throw SpError(SP_ESTATE, "environments are not built");
         SitePlan& P = h->plan[site - 1];
-        const spk::BufSet b = bufset(h, site, x, y, ny, nullptr);
+        hipStream_t s = h->stream;
+        const bool plain = h->path == SP_PATH_PLAIN;
+        const spk::BufSet b = plain ? bufset(h, site, x, y, ny, nullptr)
+                                    : bufset(h, site, h->Xd.p, h->ypart.p, h->nypart.p, nullptr);
+        const int n = int(h->sites[site - 1].size);
         hipEvent_t ev[4];
         for (auto& e : ev) HIPCK(hipEventCreate(&e));
         double ms[3] = {0, 0, 0};
         for (int r = 0; r < reps; ++r) {
-            HIPCK(hipEventRecord(ev[0], h->stream));
-            P.p1.launch(h->stream, b, P.coef.p);
-            HIPCK(hipEventRecord(ev[1], h->stream));
-            P.mixl.launch(h->stream, b, P.coef.p);
-            HIPCK(hipEventRecord(ev[2], h->stream));
-            P.yout.launch(h->stream, b, P.coef.p);
-            HIPCK(hipEventRecord(ev[3], h->stream));
+            HIPCK(hipEventRecord(ev[0], s));
+            if (plain) {
+                P.p1.launch(s, b, P.coef.p);
+            } else {
+                spk::gather(s, P.xmap.p, x, h->Xd.p, P.Xd_size);
+                P.t_left.launch(s, b, P.coef.p, P.xmap.p);
+            }
+            HIPCK(hipEventRecord(ev[1], s));
+            P.mixl.launch(s, b, P.coef.p);
+            HIPCK(hipEventRecord(ev[2], s));
+            if (plain) {
+                P.yout.launch(s, b, P.coef.p);
+            } else {
+                P.t_right.launch(s, b, P.coef.p, P.xmap.p);
+                spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
+            }
+            HIPCK(hipEventRecord(ev[3], s));
             HIPCK(hipEventSynchronize(ev[3]));
             for (int i = 0; i < 3; ++i) {
                 float t = 0.f;

@@ -45,9 +45,10 @@ def test_init_right_canonical_form(case):
     assert gpu.center() == 1
 
 
+@pytest.mark.parametrize("path", ["tiled", "plain"])
 @pytest.mark.parametrize("case", CASES)
-def test_heff_apply_all_sites(case):
-    tab, gpu, orc = make_pair(*case)
+def test_heff_apply_all_sites(case, path):
+    tab, gpu, orc = make_pair(*case, path=path)
     rng = np.random.default_rng(5)
     for k in range(1, tab.L + 1):
         if k > 1:
@@ -72,8 +73,9 @@ def test_heff_apply_all_sites(case):
         assert rel_err(dn.cpu().numpy(), orc.mps.site_packed(k, dn_ref)) < 1e-11
 
 
-def test_heff_apply_is_deterministic():
-    tab, gpu, orc = make_pair(*CASES[3], oracle=False)
+@pytest.mark.parametrize("path", ["tiled", "plain"])
+def test_heff_apply_is_deterministic(path):
+    tab, gpu, orc = make_pair(*CASES[3], oracle=False, path=path)
     n = gpu.site_size(1)
     x = _dev(np.random.default_rng(0).standard_normal(n))
     outs = []
@@ -107,11 +109,12 @@ def test_s2_operator_through_kernels(twoS):
     assert abs(E - s * (s + 1)) < 1e-11
 
 
-@pytest.mark.parametrize("case", CASES[:3])
-def test_gauge_moves_one_sweep(case):
+@pytest.mark.parametrize("path", ["tiled", "plain"])
+@pytest.mark.parametrize("case", CASES)
+def test_gauge_moves_one_sweep(case, path):
     # max_iter = 1: each local solve returns its start vector, so one sweep
     # exercises every QR/LQ move and environment update of both directions
-    tab, gpu, orc = make_pair(*case)
+    tab, gpu, orc = make_pair(*case, path=path)
     rc, steps = gpu.sweep(1, max_iter=1)
     ref = omps.sweep(orc, 1, max_iter=1)
     for a, b in zip(steps, ref):
@@ -131,11 +134,12 @@ def test_sweep_full_bond_dimension_reaches_ed(L, twoS, ref):
     assert abs(E - ref) < 1e-10
 
 
-def test_sweep_small_workload_matches_oracle():
+@pytest.mark.parametrize("path", ["tiled", "plain"])
+def test_sweep_small_workload_matches_oracle(path):
     # exact local solves (search space covers the local problem), so the
     # trajectory is a smooth function of the input and both sides agree
     wl = W.hubbard_small()
-    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed)
+    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed, path=path)
     rc, steps = gpu.sweep(wl.sweeps, max_sub=128, max_iter=200)
     ref = omps.sweep(orc, wl.sweeps, max_sub=128, max_iter=200)
     dE = max(abs(a["theta"] - b["theta"]) for a, b in zip(steps, ref))
@@ -143,11 +147,12 @@ def test_sweep_small_workload_matches_oracle():
     assert steps[-1]["theta"] > -4.235806999129714 - 1e-10
 
 
-def test_bench_shape_heff_parity():
+@pytest.mark.parametrize("path", ["tiled", "plain"])
+def test_bench_shape_heff_parity(path):
     # L=32, U=8, D=256, G=9 (the benchmark workload): whole site vectors at the
     # first site and at the centre, plus the energy
     wl = W.hubbard_bench(0)
-    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed)
+    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed, path=path)
     E, p = gpu.energy()
     Eo, po = orc.energy(1)
     assert abs(E - Eo) < 1e-9 * max(1, abs(Eo))

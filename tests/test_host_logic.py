@@ -89,7 +89,7 @@ def _init_rc(table, twoS, G, mpo_=None, N=None):
     nsec, sn, s2m, sdim = (np.ascontiguousarray(a, dtype=np.int32) for a in table.flat())
     w, data = mpo_ or sp.mpo_hubbard(table.L, 1.0, 4.0)
     w = np.ascontiguousarray(w, dtype=np.int32)
-    prob = sp._Problem(table.L, 4, table.N if N is None else N, twoS, table.twoM, G, 0)
+    prob = sp._Problem(table.L, 4, table.N if N is None else N, twoS, table.twoM, G, 0, 0)
     m = sp._Mpo(sp._iptr(w), sp._dptr(data))
     bt = sp._BlockTable(sp._iptr(nsec), sp._iptr(sn), sp._iptr(s2m), sp._iptr(sdim))
     blocks = np.zeros(max(1, W.BlockTable(table.L, table.N, table.twoM, table.bonds).total_size()))
