@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", default="tiled", choices=["tiled", "plain"])
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--heff-only", type=int, default=0,
+                    help="only run this many H_eff x applications at the centre site, after a 64 MiB "
+                         "device copy of known size (for hardware-counter runs), and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the SP-MPS path here is single-GPU "
@@ -89,6 +92,25 @@ def main():
     tab = wl.table()
     kw = dict(tol=args.tol, max_iter=args.max_iter, max_sub=args.max_sub, keep=args.keep)
     kc = wl.L // 2
+
+    if args.heff_only:
+        # calibration: a plain copy of exactly 64 MiB (read 64 MiB, write 64 MiB)
+        src = torch.ones(8 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=args.path)
+        for j in range(1, kc):
+            gpu.env_update(j, +1)
+        x = torch.tensor(gpu.get_site(kc), dtype=torch.float64, device="cuda")
+        y, ny = torch.empty_like(x), torch.empty_like(x)
+        for _ in range(args.heff_only):
+            gpu.heff_apply(kc, x, y, ny)
+        torch.cuda.synchronize()
+        log(f"[bench] {args.heff_only} H_eff x applications at site {kc} ({args.path}); "
+            f"site size {x.numel()}, algorithmic flops {gpu.heff_flops(kc):.4e}")
+        gpu.close()
+        return
 
     def run(path):
         log(f"[bench] {wl.name} path={path}: init")
