@@ -167,7 +167,7 @@ def main():
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = f"{'k_bgemm' if args.path == 'plain' else 'k_tgemm'} ({dom_name}) at site {kc}"
+    roof["kernel"] = f"{'k_bgemm' if args.path == 'plain' else 'k_heff_fused'} ({dom_name}) at site {kc}"
     roof["per_launch"] = {k: {"ms": v["ms"], "flops": v["flops"], "bytes": v["bytes"]} for k, v in prof.items()}
 
     out = {

@@ -184,9 +184,10 @@ int sp_center(const sp_handle* h, int* site);
  * (L_g x, the W r mixing, then R_g, for both H_eff and N_eff). */
 int sp_heff_flops(const sp_handle* h, int site, double* flops);
 
-/* Timing of the three phases of sp_heff_apply at `site` (left product,
- * W r mixing, right product with the g reduction; on the tiled path the
- * first includes the dense gather and the last the g sum), each averaged over
+/* Timing of the phases of sp_heff_apply at `site`, each averaged over
+ * `reps` launches.  Plain path: left product, W r mixing, right product.
+ * Tiled path: the fused launch (left product, mixing and right product in
+ * one kernel), nothing, the g sum.  Each phase is averaged over
  * `reps` launches with HIP events on the handle's stream.  out[0..2]: mean
  * milliseconds per launch; out[3..5]: algorithmic flops per launch;
  * out[6..8]: algorithmic bytes per launch (every array read or written once:

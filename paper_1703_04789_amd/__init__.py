@@ -187,6 +187,7 @@ class SPMPS:
         nsec, sn, s2m, sdim = (np.ascontiguousarray(a, dtype=np.int32) for a in table.flat())
         self._keep = (nsec, sn, s2m, sdim)
         self.L, self.N, self.twoM, self.twoS, self.G = table.L, table.N, table.twoM, twoS, G
+        self.path = path
         prob = _Problem(self.L, 4, self.N, twoS, self.twoM, G, SP_FP64,
                         {"tiled": SP_PATH_TILED, "plain": SP_PATH_PLAIN}[path])
         w, data = mpo
@@ -247,8 +248,9 @@ class SPMPS:
         for the left product, the mixing and the right product."""
         out = np.zeros(9)
         _check(lib().sp_heff_profile(self._h, k, reps, _dev(x), _dev(y), _dev(ny), _dptr(out)))
-        names = ("left_product", "mixing", "right_product")
-        return {n: dict(ms=out[i], flops=out[3 + i], bytes=out[6 + i]) for i, n in enumerate(names)}
+        names = (("left_product", "mixing", "right_product") if self.path == "plain"
+                 else ("fused_heff", None, "g_sum"))
+        return {n: dict(ms=out[i], flops=out[3 + i], bytes=out[6 + i]) for i, n in enumerate(names) if n}
 
     def center(self):
         c = ctypes.c_int(0)

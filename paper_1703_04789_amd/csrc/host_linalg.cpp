@@ -215,14 +215,26 @@ int mpo_identity(int L, int* w, double* data, long long* n) {
 // Wilkinson shifts (Givens bulge chase), deflating at negligible
 // off-diagonals.  Eigenvalues ascending; eigenvectors are columns of vec.
 
-int sym_eigh(int n, double* a, double* ev, double* vec) {
-    if (n <= 0) return 0;
-    std::vector<double> Q(size_t(n) * n, 0.0);
-    for (int i = 0; i < n; ++i) Q[size_t(i) * n + i] = 1.0;
-    std::vector<double> v(n), p(n), wv(n);
+// Householder reduction of a symmetric matrix to tridiagonal form.  On
+// return d, e hold the diagonal and the off-diagonal (e[i] couples i, i+1) and
+// the Householder vectors are kept in hv (row k: the vector of step k, length
+// n-k-1, scaled so that H_k = I - beta_k v v^T) with their betas.
+struct Tridiag {
+    int n;
+    std::vector<double> d, e, hv, beta;
+};
+
+static void tridiagonalize(int n, double* a, Tridiag& T) {
+    T.n = n;
+    T.d.assign(n, 0.0);
+    T.e.assign(n, 0.0);
+    T.hv.assign(size_t(n) * n, 0.0);
+    T.beta.assign(n, 0.0);
+    std::vector<double> p(n), wv(n);
     auto A = [&](int i, int j) -> double& { return a[size_t(i) * n + j]; };
     for (int k = 0; k + 2 < n; ++k) {
         const int len = n - k - 1;
+        double* v = &T.hv[size_t(k) * n];
         double ss = 0.0;
         for (int i = 0; i < len; ++i) {
             v[i] = A(k + 1 + i, k);
@@ -236,32 +248,56 @@ int sym_eigh(int n, double* a, double* ev, double* vec) {
         const double vv = ss - x0 * x0 + v[0] * v[0];
         if (vv == 0.0) continue;
         const double beta = 2.0 / vv;
+        T.beta[k] = beta;
         // trailing block S = A[k+1:, k+1:]:  S -= v w^T + w v^T
         double vp = 0.0;
         for (int i = 0; i < len; ++i) {
-            double s = 0.0;
-            for (int j = 0; j < len; ++j) s += A(k + 1 + i, k + 1 + j) * v[j];
-            p[i] = beta * s;
+            const double* row = &A(k + 1 + i, k + 1);
+            double sacc = 0.0;
+            for (int j = 0; j < len; ++j) sacc += row[j] * v[j];
+            p[i] = beta * sacc;
             vp += v[i] * p[i];
         }
         const double K = 0.5 * beta * vp;
         for (int i = 0; i < len; ++i) wv[i] = p[i] - K * v[i];
-        for (int i = 0; i < len; ++i)
-            for (int j = 0; j < len; ++j) A(k + 1 + i, k + 1 + j) -= v[i] * wv[j] + wv[i] * v[j];
+        for (int i = 0; i < len; ++i) {
+            double* row = &A(k + 1 + i, k + 1);
+            const double vi = v[i], wi = wv[i];
+            for (int j = 0; j < len; ++j) row[j] -= vi * wv[j] + wi * v[j];
+        }
         A(k + 1, k) = A(k, k + 1) = alpha;
         for (int i = 1; i < len; ++i) A(k + 1 + i, k) = A(k, k + 1 + i) = 0.0;
-        // Q <- Q H
-        for (int r = 0; r < n; ++r) {
-            double s = 0.0;
-            for (int j = 0; j < len; ++j) s += Q[size_t(r) * n + k + 1 + j] * v[j];
-            s *= beta;
-            for (int j = 0; j < len; ++j) Q[size_t(r) * n + k + 1 + j] -= s * v[j];
+    }
+    for (int i = 0; i < n; ++i) T.d[i] = A(i, i);
+    for (int i = 0; i + 1 < n; ++i) T.e[i] = A(i + 1, i);
+}
+
+// apply Q = H_0 H_1 ... H_{n-3} to the columns of Z (n x nz, row-major):
+// Z <- Q Z
+static void apply_q(const Tridiag& T, double* Z, int nz) {
+    const int n = T.n;
+    std::vector<double> tmp(nz);
+    for (int k = n - 3; k >= 0; --k) {
+        if (T.beta[k] == 0.0) continue;
+        const int len = n - k - 1;
+        const double* v = &T.hv[size_t(k) * n];
+        std::fill(tmp.begin(), tmp.end(), 0.0);
+        for (int i = 0; i < len; ++i) {
+            const double* row = Z + size_t(k + 1 + i) * nz;
+            for (int c = 0; c < nz; ++c) tmp[c] += v[i] * row[c];
+        }
+        for (int i = 0; i < len; ++i) {
+            double* row = Z + size_t(k + 1 + i) * nz;
+            const double f = T.beta[k] * v[i];
+            for (int c = 0; c < nz; ++c) row[c] -= f * tmp[c];
         }
     }
-    std::vector<double> d(n), e(n, 0.0);
-    for (int i = 0; i < n; ++i) d[i] = A(i, i);
-    for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);
+}
 
+// implicit symmetric QR steps with Wilkinson shifts on the tridiagonal
+// (d, e); rotations are applied to the rows of Zt (eigenvectors stored as
+// rows, n x n) when Zt != nullptr.  Returns false if it does not converge.
+static bool tridiag_qr(int n, double* d, double* e, double* Zt) {
     const double eps = 2.220446049250313e-16;
     int m = n - 1;
     int guard = 0;
@@ -274,8 +310,7 @@ int sym_eigh(int n, double* a, double* ev, double* vec) {
         int l = m - 1;
         while (l > 0 && std::fabs(e[l - 1]) > eps * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
         if (l > 0) e[l - 1] = 0.0;
-        if (++guard > 60 * n) return -1;
-        // Wilkinson shift from the trailing 2x2 of the block [l, m]
+        if (++guard > 60 * n) return false;
         const double delta = 0.5 * (d[m - 1] - d[m]);
         const double b2 = e[m - 1] * e[m - 1];
         const double sg = (delta >= 0.0) ? 1.0 : -1.0;
@@ -283,7 +318,7 @@ int sym_eigh(int n, double* a, double* ev, double* vec) {
         double x = d[l] - mu;
         double z = e[l];
         for (int k = l; k < m; ++k) {
-            double r = std::hypot(x, z);
+            const double r = std::sqrt(x * x + z * z);
             double c = 1.0, s = 0.0;
             if (r != 0.0) {
                 c = x / r;
@@ -295,25 +330,113 @@ int sym_eigh(int n, double* a, double* ev, double* vec) {
             d[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ck;
             e[k] = c * s * (ck - ak) + (c * c - s * s) * bk;
             if (k + 1 < m) {
-                z = s * e[k + 1];      // bulge at (k, k+2)
+                z = s * e[k + 1];  // bulge at (k, k+2)
                 e[k + 1] = c * e[k + 1];
                 x = e[k];
             }
-            for (int r0 = 0; r0 < n; ++r0) {
-                double* row = &Q[size_t(r0) * n];
-                const double qk = row[k], qk1 = row[k + 1];
-                row[k] = c * qk + s * qk1;
-                row[k + 1] = -s * qk + c * qk1;
+            if (Zt) {
+                double* rk = Zt + size_t(k) * n;
+                double* rk1 = Zt + size_t(k + 1) * n;
+                for (int j = 0; j < n; ++j) {
+                    const double a0 = rk[j], a1 = rk1[j];
+                    rk[j] = c * a0 + s * a1;
+                    rk1[j] = -s * a0 + c * a1;
+                }
             }
         }
     }
+    return true;
+}
+
+int sym_eigh(int n, double* a, double* ev, double* vec) {
+    if (n <= 0) return 0;
+    Tridiag T;
+    tridiagonalize(n, a, T);
+    // eigenvectors of the tridiagonal as rows of Zt (rotations act on rows:
+    // contiguous memory), then back-transformed by the Householder vectors
+    std::vector<double> Zt(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Zt[size_t(i) * n + i] = 1.0;
+    std::vector<double> d = T.d, e = T.e;
+    if (!tridiag_qr(n, d.data(), e.data(), Zt.data())) return -1;
     std::vector<int> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
     std::sort(idx.begin(), idx.end(), [&](int i, int j) { return d[i] < d[j]; });
+    // Z (n x n, column i = eigenvector i of the tridiagonal) = Zt^T, sorted
+    std::vector<double> Z(size_t(n) * n);
     for (int i = 0; i < n; ++i) {
         ev[i] = d[idx[i]];
-        for (int r = 0; r < n; ++r) vec[size_t(r) * n + i] = Q[size_t(r) * n + idx[i]];
+        const double* row = &Zt[size_t(idx[i]) * n];
+        for (int r = 0; r < n; ++r) Z[size_t(r) * n + i] = row[r];
     }
+    apply_q(T, Z.data(), n);
+    std::copy(Z.begin(), Z.end(), vec);
+    return 0;
+}
+
+int sym_eig_lowest(int n, double* a, double* ev0, double* v0) {
+    if (n <= 0) return 0;
+    Tridiag T;
+    tridiagonalize(n, a, T);
+    std::vector<double> d = T.d, e = T.e;
+    if (!tridiag_qr(n, d.data(), e.data(), nullptr)) return -1;
+    double lam = d[0];
+    for (int i = 1; i < n; ++i) lam = std::min(lam, d[i]);
+    *ev0 = lam;
+    // inverse iteration on the tridiagonal (T - lam) z = z_prev with a tiny
+    // shift below lam; LU without pivoting is stable for this shift choice
+    // only up to a scale, so partial pivoting is used (Gaussian elimination on
+    // the tridiagonal band, 2 upper diagonals after pivoting)
+    const double scale = std::max(1.0, std::fabs(lam));
+    const double shift = lam - 1e-13 * scale;
+    std::vector<double> z(n, 1.0), dd(n), du(n), du2(n), dl(n);
+    std::vector<int> piv(n);
+    for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i < n; ++i) dd[i] = T.d[i] - shift;
+        for (int i = 0; i + 1 < n; ++i) du[i] = dl[i] = T.e[i];
+        // factor (dgttrf-like elimination with row interchanges)
+        for (int i = 0; i < n; ++i) du2[i] = 0.0;
+        for (int i = 0; i + 1 < n; ++i) {
+            if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
+                piv[i] = i;
+                const double f = (dd[i] != 0.0) ? dl[i] / dd[i] : 0.0;
+                dl[i] = f;
+                dd[i + 1] -= f * du[i];
+            } else {
+                piv[i] = i + 1;
+                const double f = dd[i] / dl[i];
+                dd[i] = dl[i];
+                dl[i] = f;
+                const double t = du[i];
+                du[i] = dd[i + 1];
+                dd[i + 1] = t - f * dd[i + 1];
+                if (i + 2 < n) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
+            }
+        }
+        for (int i = 0; i < n; ++i)
+            if (dd[i] == 0.0) dd[i] = 1e-300;
+        // solve L U x = z
+        for (int i = 0; i + 1 < n; ++i) {
+            if (piv[i] == i) {
+                z[i + 1] -= dl[i] * z[i];
+            } else {
+                const double t = z[i];
+                z[i] = z[i + 1];
+                z[i + 1] = t - dl[i] * z[i];
+            }
+        }
+        z[n - 1] /= dd[n - 1];
+        if (n > 1) z[n - 2] = (z[n - 2] - du[n - 2] * z[n - 1]) / dd[n - 2];
+        for (int i = n - 3; i >= 0; --i) z[i] = (z[i] - du[i] * z[i + 1] - du2[i] * z[i + 2]) / dd[i];
+        double nr = 0.0;
+        for (double q : z) nr += q * q;
+        nr = std::sqrt(nr);
+        for (double& q : z) q /= nr;
+    }
+    apply_q(T, z.data(), 1);
+    std::copy(z.begin(), z.end(), v0);
     return 0;
 }
 

@@ -15,5 +15,8 @@ int mpo_hubbard(int L, double t, double U, int* w, double* data, long long* n);
 int mpo_s2(int L, int* w, double* data, long long* n);
 int mpo_identity(int L, int* w, double* data, long long* n);
 int sym_eigh(int n, double* a, double* ev, double* vec);
+// lowest eigenvalue and its unit eigenvector (tridiagonal QR for the value,
+// inverse iteration for the vector); a is destroyed
+int sym_eig_lowest(int n, double* a, double* ev0, double* v0);
 
 }  // namespace sph

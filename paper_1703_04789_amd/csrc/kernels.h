@@ -85,6 +85,50 @@ void gather(hipStream_t s, const int* map, const double* src, double* dst, long 
 void gsum2(hipStream_t s, const double* pa, const double* pb, long long stride, int G, int n, double* outa,
            double* outb);
 
+// Fused H_eff x / N_eff x.  One work-group per (g, bra particle-number block
+// i of the left bond, rows [r0, r0 + rows)).
+//  phase A: every product T(c, s') = L_g(c, i, j_c)[rows] x(j_c, s', .) of a
+//           left channel c and ket index s' goes to LDS once, computed from
+//           the packed site vector through per-column sector descriptors
+//           (one thread per column, all rows at once);
+//  phase B: for each output sigma and each right channel c' (and the
+//           identity channel that gives N_eff): stage the right-environment
+//           rows the outputs need in LDS, form V = sum_terms coef * T (the
+//           W r mixing, coef includes coef_g), and accumulate the allowed
+//           (N, M) outputs y[r][colY] += sum_kk V[r][kk] R_g(c', N_b)[colY][kk].
+// Per-g partials go to ypart/nypart[g*n + packed index].
+struct H2Blk {
+    int t0, t1;        // T-block descriptors of this bra block
+    int ch0[4], ch1[4];  // channels per output sigma
+    int maxch, pad;
+};
+struct H2T {
+    long long l_off;  // left environment block offset (within one g)
+    int l_ld, ci_off, ncol, colpos;  // colpos: LDS column offset (times rows)
+};
+struct H2Chan {
+    long long r_off;  // right environment block offset (within one g)
+    int K, t0, t1, is_ny;
+};
+struct H2Term {
+    int tidx, cidx;  // T block (relative to the bra block's list), coefficient
+};
+struct H2Task {
+    int g, blk, r0, r1;
+    int o0[4], o1[4];
+    int cy0[4], cy1[4];  // right-environment rows needed by the outputs of each sigma
+};
+constexpr int kH2TMax = 6144;  // doubles of LDS for the T rows
+constexpr int kH2VMax = 512;   // doubles of LDS for the V rows of one (sigma, channel)
+constexpr int kH2RMax = 2048;  // doubles of LDS for the staged right-environment rows
+constexpr int kH2TBlk = 64;    // T blocks per bra block (descriptors cached in LDS)
+constexpr int kH2Out = 2;      // outputs per thread and sigma (<= 512 per sigma and task)
+
+void heff2(hipStream_t s, const H2Task* tasks, int ntasks, const H2Blk* blks, const H2T* tdesc,
+           const H2Chan* chans, const H2Term* terms, const int4* colinfo, const int4* yout, int rows_max,
+           const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
+           const double* coef, int nc, double* ypart, double* nypart, long long n);
+
 void bgemm(hipStream_t s, const BTask* tasks, int ntasks, const BTerm* terms, BufSet bufs,
            const double* coef);
 void combine(hipStream_t s, const CTask* tasks, int ntasks, const CTerm* terms, BufSet bufs,
@@ -109,5 +153,28 @@ void basis_rotate(hipStream_t s, const double* A, long long ld, int m, const dou
 void gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
           int n, const double* partials, int npart, double* out);
 void scale(hipStream_t s, double* x, int n, const double* factor_inv_sqrt_of);
+
+// Grid-parallel Davidson passes.  Each work-group owns kDavChunk consecutive
+// elements and writes per-chunk partial sums; consumers add the partials of
+// all chunks in ascending chunk order (deterministic).  m <= kDavMaxVec.
+constexpr int kDavChunk = 256;
+constexpr int kGramGroup = 32;  // dots per work-group of the Gram pass
+constexpr int kDavMaxVec = 256;
+inline int dav_chunks(int n) { return (n + kDavChunk - 1) / kDavChunk; }
+// x = V a, u = HV a - theta NV a, t = -u / floor(dh - theta dn); part_x[3 per
+// chunk] = (x.x, u.u, x.(NV a)); part_c[m per chunk] = V_j . t
+void dav_ritz(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
+              const double* a, const double* theta, const double* dh, const double* dn, int n, double floor_,
+              double* x, double* t, double* part_x, double* part_c);
+// c = sum of part_in over chunks; t -= V c; then part_out = V_j . t (mode 0)
+// or part_out = t.t per chunk (mode 1)
+void dav_cgs(hipStream_t s, const double* V, long long ld, int m_sub, int m_dot, const double* part_in,
+             int nchunk, double* t, int n, double* part_out, int mode);
+// vout = t / sqrt(sum part), tnorm = sqrt(sum part)
+void dav_normalize(hipStream_t s, const double* part, int nchunk, const double* t, double* vout, int n,
+                   double* tnorm);
+// per chunk: V_j.HV_m (j<=m), V_j.NV_m (j<=m), V_m.HV_j (j<m), V_m.NV_j (j<m)
+void dav_gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m, int n,
+              double* part);
 
 }  // namespace spk

@@ -448,6 +448,184 @@ __global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ ta
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_heff2(
+    const H2Task* __restrict__ tasks, const H2Blk* __restrict__ blks, const H2T* __restrict__ tdesc,
+    const H2Chan* __restrict__ chans, const H2Term* __restrict__ terms, const int4* __restrict__ colinfo,
+    const int4* __restrict__ yout, int RC, const double* __restrict__ Lenv, long long Lsz,
+    const double* __restrict__ Renv, long long Rsz, const double* __restrict__ x, const double* __restrict__ coef,
+    int nc, double* __restrict__ ypart, double* __restrict__ nypart, long long n) {
+    constexpr int kMaxRC = 8;
+    __shared__ double Ts[kH2TMax];
+    __shared__ double Vs[kH2VMax];
+    __shared__ double Rs[kH2RMax];
+    __shared__ H2T td[kH2TBlk];
+    __shared__ int tcols[kH2TBlk + 1];
+    __shared__ int s_pos[16];
+    __shared__ double s_cf[16];
+    // task and block descriptors live in LDS: their small arrays are indexed
+    // with a run-time sigma, which would otherwise put them in scratch
+    __shared__ H2Task tk;
+    __shared__ H2Blk B;
+    if (threadIdx.x == 0) {
+        tk = tasks[blockIdx.x];
+        B = blks[tk.blk];
+    }
+    __syncthreads();
+    const double* __restrict__ L = Lenv + tk.g * Lsz;
+    const double* __restrict__ R = Renv + tk.g * Rsz;
+    const double* __restrict__ cf = coef + (long long)tk.g * nc;
+    const int rows = tk.r1 - tk.r0;
+    const int nt = B.t1 - B.t0;
+    for (int t = threadIdx.x; t < nt; t += kThreads) td[t] = tdesc[B.t0 + t];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int t = 0; t < nt; ++t) {
+            tcols[t] = acc;
+            acc += td[t].ncol;
+        }
+        tcols[nt] = acc;
+    }
+    __syncthreads();
+    // phase A: one thread per T column, all rows of the chunk; the column
+    // descriptors of all the thread's columns are loaded first
+    const int tsum = tcols[nt];
+    constexpr int kColReg = 8;
+    for (int base = 0; base < tsum; base += kThreads * kColReg) {
+        int4 cis[kColReg];
+#pragma unroll
+        for (int j = 0; j < kColReg; ++j) {
+            const int idx = base + threadIdx.x + kThreads * j;
+            cis[j] = make_int4(0, 0, 0, 0);
+            if (idx < tsum) {
+                int t = 0;
+                while (tcols[t + 1] <= idx) ++t;
+                cis[j] = colinfo[td[t].ci_off + (idx - tcols[t])];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kColReg; ++j) {
+            const int idx = base + threadIdx.x + kThreads * j;
+            if (idx >= tsum) continue;
+            int t = 0;
+            while (tcols[t + 1] <= idx) ++t;
+            const H2T T = td[t];
+            const int col = idx - tcols[t];
+            const int4 ci = cis[j];
+            double acc[kMaxRC];
+#pragma unroll
+            for (int rr = 0; rr < kMaxRC; ++rr) acc[rr] = 0.0;
+            const double* __restrict__ lbase = L + T.l_off + (long long)tk.r0 * T.l_ld + ci.w;
+            for (int kk = 0; kk < ci.z; ++kk) {
+                const double xv = x[ci.x + kk * ci.y];
+#pragma unroll
+                for (int rr = 0; rr < kMaxRC; ++rr)
+                    if (rr < rows) acc[rr] = fma(lbase[(long long)rr * T.l_ld + kk], xv, acc[rr]);
+            }
+#pragma unroll
+            for (int rr = 0; rr < kMaxRC; ++rr)
+                if (rr < rows) Ts[T.colpos * RC + rr * T.ncol + col] = acc[rr];
+        }
+    }
+    __syncthreads();
+    // phase B: (sigma, channel) steps with the whole work-group; the right-
+    // environment rows of the next step are fetched into registers while the
+    // current step computes (software pipelining of the global loads)
+    constexpr int kRReg = kH2RMax / kThreads;
+    double ay[kH2Out], an[kH2Out];
+#pragma unroll
+    for (int u = 0; u < kH2Out; ++u) ay[u] = an[u] = 0.0;
+    // flattened step list: step = (sigma, channel)
+    int nsteps = 0;
+    int s_first[5];
+#pragma unroll
+    for (int sg = 0; sg < 4; ++sg) {
+        s_first[sg] = nsteps;
+        if (tk.o1[sg] > tk.o0[sg]) nsteps += B.ch1[sg] - B.ch0[sg];
+    }
+    s_first[4] = nsteps;
+    auto step_sigma = [&](int st) {
+        int sg = 0;
+        while (sg < 3 && st >= s_first[sg + 1]) ++sg;
+        return sg;
+    };
+    double pre[kRReg];
+    auto fetch = [&](int st) {
+        const int sg = step_sigma(st);
+        const H2Chan C = chans[B.ch0[sg] + (st - s_first[sg])];
+        const int tot = (tk.cy1[sg] - tk.cy0[sg]) * C.K;
+        const double* __restrict__ Rb = R + C.r_off + (long long)tk.cy0[sg] * C.K;
+#pragma unroll
+        for (int j = 0; j < kRReg; ++j) {
+            const int e = threadIdx.x + kThreads * j;
+            pre[j] = (tot <= kH2RMax && e < tot) ? Rb[e] : 0.0;
+        }
+    };
+    if (nsteps > 0) fetch(0);
+    for (int st = 0; st < nsteps; ++st) {
+        const int sg = step_sigma(st);
+        const H2Chan C = chans[B.ch0[sg] + (st - s_first[sg])];
+        const int K = C.K;
+        const int nterm = C.t1 - C.t0;
+        const int cy0 = tk.cy0[sg], ncy = tk.cy1[sg] - tk.cy0[sg];
+        const bool staged = ncy * K <= kH2RMax;  // else read the rows from global memory
+        const double* __restrict__ Rb = R + C.r_off + (long long)cy0 * K;
+        if (threadIdx.x < nterm) {
+            const H2Term term = terms[C.t0 + threadIdx.x];
+            s_pos[threadIdx.x] = td[term.tidx].colpos * RC;
+            s_cf[threadIdx.x] = cf[term.cidx];
+        }
+#pragma unroll
+        for (int j = 0; j < kRReg; ++j) Rs[threadIdx.x + kThreads * j] = pre[j];
+        __syncthreads();
+        if (st + 1 < nsteps) fetch(st + 1);
+        for (int e = threadIdx.x; e < rows * K; e += kThreads) {
+            double v = 0.0;
+            for (int tm = 0; tm < nterm; ++tm) v = fma(s_cf[tm], Ts[s_pos[tm] + e], v);
+            Vs[e] = v;
+        }
+        __syncthreads();
+        const int o0 = tk.o0[sg], o1 = tk.o1[sg];
+#pragma unroll
+        for (int u = 0; u < kH2Out; ++u) {
+            const int o = o0 + threadIdx.x + kThreads * u;
+            if (o < o1) {
+                const int4 yo = yout[o];
+                const double* vr = Vs + (yo.x - tk.r0) * K;
+                const double* rr = staged ? Rs + (yo.y - cy0) * K : Rb + (long long)(yo.y - cy0) * K;
+                double sacc = 0.0;
+                for (int kk = 0; kk < K; ++kk) sacc = fma(vr[kk], rr[kk], sacc);
+                if (C.is_ny) an[u] += sacc;
+                else ay[u] += sacc;
+            }
+        }
+        __syncthreads();
+        // last channel of this sigma: write its outputs and reset
+        if (st + 1 == s_first[sg + 1]) {
+#pragma unroll
+            for (int u = 0; u < kH2Out; ++u) {
+                const int o = o0 + threadIdx.x + kThreads * u;
+                if (o < o1) {
+                    const long long p = (long long)tk.g * n + yout[o].z;
+                    ypart[p] = ay[u];
+                    nypart[p] = an[u];
+                }
+                ay[u] = an[u] = 0.0;
+            }
+        }
+    }
+    // outputs of a sigma without channels are zero
+#pragma unroll
+    for (int sg = 0; sg < 4; ++sg) {
+        if (s_first[sg + 1] > s_first[sg]) continue;
+        for (int o = tk.o0[sg] + threadIdx.x; o < tk.o1[sg]; o += kThreads) {
+            const long long p = (long long)tk.g * n + yout[o].z;
+            ypart[p] = 0.0;
+            nypart[p] = 0.0;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_gather(const int* __restrict__ map, const double* __restrict__ src,
                                                        double* __restrict__ dst, long long n) {
     const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
@@ -470,6 +648,193 @@ __global__ __launch_bounds__(kThreads) void k_gsum2(const double* __restrict__ p
     outb[e] = sb;
 }
 
+// ---- grid-parallel Davidson passes ----------------------------------------
+
+constexpr int kDavPer = kDavChunk / kThreads;  // elements per thread
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// per-chunk dots V_j . w (w held in registers) for j < m -> out[j]
+__device__ inline void chunk_dots(const double* __restrict__ V, long long ld, int m, const int* es, const double* wv,
+                                  int n, double (*wred)[kDavMaxVec], double* __restrict__ out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = 0; j < m; ++j) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kDavPer; ++i)
+            if (es[i] < n) sacc = fma(V[j * ld + es[i]], wv[i], sacc);
+        sacc = wave_sum(sacc);
+        if (lane == 0) wred[wave][j] = sacc;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += kThreads) out[j] = (wred[0][j] + wred[1][j]) + (wred[2][j] + wred[3][j]);
+    __syncthreads();
+}
+
+__device__ inline double chunk_sum(double v, double* wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) wsum[wave] = v;
+    __syncthreads();
+    const double r = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dav_ritz(const double* __restrict__ V, const double* __restrict__ HV,
+                                                         const double* __restrict__ NV, long long ld, int m,
+                                                         const double* __restrict__ a,
+                                                         const double* __restrict__ theta_p,
+                                                         const double* __restrict__ dh,
+                                                         const double* __restrict__ dn, int n, double floor_,
+                                                         double* __restrict__ x, double* __restrict__ t,
+                                                         double* __restrict__ part_x, double* __restrict__ part_c) {
+    __shared__ double wred[4][kDavMaxVec];
+    __shared__ double wsum[4];
+    const double theta = *theta_p;
+    int es[kDavPer];
+    double tv[kDavPer];
+    double xx = 0.0, uu = 0.0, xn = 0.0;
+#pragma unroll
+    for (int i = 0; i < kDavPer; ++i) {
+        const int e = blockIdx.x * kDavChunk + threadIdx.x + kThreads * i;
+        es[i] = e;
+        tv[i] = 0.0;
+        if (e < n) {
+            double xv = 0.0, hv = 0.0, nv = 0.0;
+            for (int j = 0; j < m; ++j) {
+                const double aj = a[j];
+                xv = fma(aj, V[j * ld + e], xv);
+                hv = fma(aj, HV[j * ld + e], hv);
+                nv = fma(aj, NV[j * ld + e], nv);
+            }
+            const double u = hv - theta * nv;
+            double den = dh[e] - theta * dn[e];
+            if (fabs(den) < floor_) den = (den < 0.0) ? -floor_ : floor_;
+            tv[i] = -u / den;
+            x[e] = xv;
+            t[e] = tv[i];
+            xx = fma(xv, xv, xx);
+            uu = fma(u, u, uu);
+            xn = fma(xv, nv, xn);
+        }
+    }
+    xx = chunk_sum(xx, wsum);
+    uu = chunk_sum(uu, wsum);
+    xn = chunk_sum(xn, wsum);
+    if (threadIdx.x == 0) {
+        part_x[3 * blockIdx.x + 0] = xx;
+        part_x[3 * blockIdx.x + 1] = uu;
+        part_x[3 * blockIdx.x + 2] = xn;
+    }
+    chunk_dots(V, ld, m, es, tv, n, wred, part_c + (long long)blockIdx.x * m);
+}
+
+__global__ __launch_bounds__(kThreads) void k_dav_cgs(const double* __restrict__ V, long long ld, int m,
+                                                        int m_dot, const double* __restrict__ part_in, int nchunk,
+                                                        double* __restrict__ t, int n,
+                                                        double* __restrict__ part_out, int mode) {
+    __shared__ double c[kDavMaxVec];
+    __shared__ double wred[4][kDavMaxVec];
+    __shared__ double wsum[4];
+    for (int j = threadIdx.x; j < m; j += kThreads) {
+        double sacc = 0.0;
+        for (int q = 0; q < nchunk; ++q) sacc += part_in[(long long)q * m + j];
+        c[j] = sacc;
+    }
+    __syncthreads();
+    int es[kDavPer];
+    double tv[kDavPer];
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < kDavPer; ++i) {
+        const int e = blockIdx.x * kDavChunk + threadIdx.x + kThreads * i;
+        es[i] = e;
+        tv[i] = 0.0;
+        if (e < n) {
+            double v = t[e];
+            for (int j = 0; j < m; ++j) v = fma(-c[j], V[j * ld + e], v);
+            t[e] = v;
+            tv[i] = v;
+            ss = fma(v, v, ss);
+        }
+    }
+    if (mode == 0) {
+        chunk_dots(V, ld, m_dot, es, tv, n, wred, part_out + (long long)blockIdx.x * m_dot);
+    } else {
+        ss = chunk_sum(ss, wsum);
+        if (threadIdx.x == 0) part_out[blockIdx.x] = ss;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dav_normalize(const double* __restrict__ part, int nchunk,
+                                                              const double* __restrict__ t,
+                                                              double* __restrict__ vout, int n,
+                                                              double* __restrict__ tnorm) {
+    double ss = 0.0;
+    for (int q = 0; q < nchunk; ++q) ss += part[q];
+    const double nrm = sqrt(ss);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+#pragma unroll
+    for (int i = 0; i < kDavPer; ++i) {
+        const int e = blockIdx.x * kDavChunk + threadIdx.x + kThreads * i;
+        if (e < n) vout[e] = t[e] * inv;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *tnorm = nrm;
+}
+
+__global__ __launch_bounds__(kThreads) void k_dav_gram(const double* __restrict__ V, const double* __restrict__ HV,
+                                                         const double* __restrict__ NV, long long ld, int m, int n,
+                                                         double* __restrict__ part) {
+    __shared__ double wred[4][kGramGroup];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nd = 4 * m + 2;
+    int es[kDavPer];
+    double vm[kDavPer], hm[kDavPer], nm[kDavPer];
+#pragma unroll
+    for (int i = 0; i < kDavPer; ++i) {
+        const int e = blockIdx.x * kDavChunk + threadIdx.x + kThreads * i;
+        es[i] = e;
+        const bool ok = e < n;
+        vm[i] = ok ? V[m * ld + e] : 0.0;
+        hm[i] = ok ? HV[m * ld + e] : 0.0;
+        nm[i] = ok ? NV[m * ld + e] : 0.0;
+    }
+    double* out = part + (long long)blockIdx.x * nd;
+    const int d0 = blockIdx.y * kGramGroup;
+    const int d1 = min(nd, d0 + kGramGroup);
+    for (int d = d0; d < d1; ++d) {
+        const double* __restrict__ src;
+        int which;
+        if (d <= m) {
+            src = V + d * ld;
+            which = 0;
+        } else if (d <= 2 * m + 1) {
+            src = V + (d - m - 1) * ld;
+            which = 1;
+        } else if (d <= 3 * m + 1) {
+            src = HV + (d - 2 * m - 2) * ld;
+            which = 2;
+        } else {
+            src = NV + (d - 3 * m - 2) * ld;
+            which = 2;
+        }
+        double sacc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kDavPer; ++i)
+            if (es[i] < n) sacc = fma(src[es[i]], which == 0 ? hm[i] : (which == 1 ? nm[i] : vm[i]), sacc);
+        sacc = wave_sum(sacc);
+        if (lane == 0) wred[wave][d - d0] = sacc;
+    }
+    __syncthreads();
+    for (int d = d0 + threadIdx.x; d < d1; d += kThreads)
+        out[d] = (wred[0][d - d0] + wred[1][d - d0]) + (wred[2][d - d0] + wred[3][d - d0]);
+}
+
 inline int nblk(int n) { return (n + kThreads - 1) / kThreads; }
 
 }  // namespace
@@ -477,6 +842,14 @@ inline int nblk(int n) { return (n + kThreads - 1) / kThreads; }
 void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
            const int* map) {
     if (ntasks > 0) hipLaunchKernelGGL(k_tgemm, dim3(ntasks), dim3(kThreads), 0, s, tasks, segs, bufs, coef, map);
+}
+void heff2(hipStream_t s, const H2Task* tasks, int ntasks, const H2Blk* blks, const H2T* tdesc,
+           const H2Chan* chans, const H2Term* terms, const int4* colinfo, const int4* yout, int rows_max,
+           const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
+           const double* coef, int nc, double* ypart, double* nypart, long long n) {
+    if (ntasks > 0)
+        hipLaunchKernelGGL(k_heff2, dim3(ntasks), dim3(kThreads), 0, s, tasks, blks, tdesc, chans, terms, colinfo, yout,
+                           rows_max, Lenv, Lsz, Renv, Rsz, x, coef, nc, ypart, nypart, n);
 }
 void gather(hipStream_t s, const int* map, const double* src, double* dst, long long n) {
     if (n > 0) hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, map, src, dst, n);
@@ -528,6 +901,27 @@ void basis_rotate(hipStream_t s, const double* A, long long ld, int m, const dou
 void gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m, int n,
           const double* partials, int npart, double* out) {
     hipLaunchKernelGGL(k_gram, dim3(4 * m + 3), dim3(kThreads), 0, s, V, HV, NV, ld, m, n, partials, npart, out);
+}
+void dav_ritz(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
+              const double* a, const double* theta, const double* dh, const double* dn, int n, double floor_,
+              double* x, double* t, double* part_x, double* part_c) {
+    hipLaunchKernelGGL(k_dav_ritz, dim3(dav_chunks(n)), dim3(kThreads), 0, s, V, HV, NV, ld, m, a, theta, dh, dn, n,
+                       floor_, x, t, part_x, part_c);
+}
+void dav_cgs(hipStream_t s, const double* V, long long ld, int m_sub, int m_dot, const double* part_in,
+             int nchunk, double* t, int n, double* part_out, int mode) {
+    hipLaunchKernelGGL(k_dav_cgs, dim3(dav_chunks(n)), dim3(kThreads), 0, s, V, ld, m_sub, m_dot, part_in, nchunk, t,
+                       n, part_out, mode);
+}
+void dav_normalize(hipStream_t s, const double* part, int nchunk, const double* t, double* vout, int n,
+                   double* tnorm) {
+    hipLaunchKernelGGL(k_dav_normalize, dim3(dav_chunks(n)), dim3(kThreads), 0, s, part, nchunk, t, vout, n, tnorm);
+}
+void dav_gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m, int n,
+              double* part) {
+    const int nd = 4 * m + 2;
+    hipLaunchKernelGGL(k_dav_gram, dim3(dav_chunks(n), (nd + kGramGroup - 1) / kGramGroup), dim3(kThreads), 0, s, V, HV,
+                       NV, ld, m, n, part);
 }
 void scale(hipStream_t s, double* x, int n, const double* ss) {
     hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(kThreads), 0, s, x, n, ss);

@@ -307,6 +307,20 @@ struct SitePlan {
     std::vector<int> xmap_h;  // dense element -> packed index or -1
     DArr<int> xmap;
     TList t_left, t_right, t_envl, t_zr, t_envr;
+    // fused H_eff x
+    int h_rows = 1;
+    std::vector<spk::H2Task> h_tasks;
+    std::vector<spk::H2Blk> h_blks;
+    std::vector<spk::H2T> h_tdesc;
+    std::vector<spk::H2Chan> h_chans;
+    std::vector<spk::H2Term> h_terms;
+    std::vector<int4> h_colinfo, h_yout;
+    DArr<spk::H2Task> dh_tasks;
+    DArr<spk::H2Blk> dh_blks;
+    DArr<spk::H2T> dh_tdesc;
+    DArr<spk::H2Chan> dh_chans;
+    DArr<spk::H2Term> dh_terms;
+    DArr<int4> dh_colinfo, dh_yout;
 };
 
 }  // namespace
@@ -337,10 +351,13 @@ struct sp_handle {
     int dav_sub = 0;
     long long ld = 0;
     DArr<double> dV, dHV, dNV, dRot, dx, dt, ddh, ddn, dpart, dsmall, dy, dny;
-    double* pin = nullptr;  // pinned host staging
+    double* pin = nullptr;  // pinned host staging (device -> host)
     size_t pin_n = 0;
+    double* pin_up = nullptr;  // pinned host staging (host -> device)
+    size_t pin_up_n = 0;
     ~sp_handle() {
         if (pin) (void)hipHostFree(pin);
+        if (pin_up) (void)hipHostFree(pin_up);
     }
 };
 
@@ -1099,6 +1116,184 @@ void build_plan(sp_handle* h, int k) {
                 }
 }
 
+// fused H_eff x plan: column descriptors, products per bra block, channels
+// per output sigma, output lists and row-chunk tasks
+void build_fused(sp_handle* h, int k) {
+    SitePlan& P = h->plan[k - 1];
+    const int G = h->G;
+    const Bond& bl = h->bonds[k - 1];
+    const Bond& br = h->bonds[k];
+    const SiteInfo& si = h->sites[k - 1];
+    const EnvLayout& el = h->env[k - 1];
+    const EnvLayout& er = h->env[k];
+    const int wl = h->w[k - 1], wr = h->w[k];
+    const int lastR = wr - 1;
+    std::map<std::array<int, 4>, int> wpos;
+    for (int e = 0; e < P.nW; ++e) wpos[P.went[e]] = e;
+    std::vector<int> cioff(bl.nb.size() * 4, -1);
+    for (int j = 0; j < int(bl.nb.size()); ++j)
+        for (int q = 0; q < 4; ++q) {
+            const int jb = br.nblock(bl.nb[j].n + kSigmaN[q]);
+            if (jb < 0) continue;
+            cioff[size_t(j) * 4 + q] = int(P.h_colinfo.size());
+            const NBlock& NB = br.nb[jb];
+            for (int sb = NB.s0; sb < NB.s1; ++sb) {
+                const Sector& SB = br.sec[sb];
+                const int sa = bl.sector(SB.n - kSigmaN[q], SB.m2 - kSigma2M[q]);
+                const int xb = sa >= 0 ? si.find(sa, q) : -1;
+                for (int c = 0; c < SB.dim; ++c) {
+                    if (xb < 0) {
+                        P.h_colinfo.push_back(make_int4(0, 0, 0, 0));
+                    } else {
+                        const XBlk& X = si.blk[xb];
+                        P.h_colinfo.push_back(make_int4(int(X.off + c), X.cols, X.rows, bl.sec[sa].ro));
+                    }
+                }
+            }
+        }
+    const int nb = int(bl.nb.size());
+    // per bra block: products, channels, outputs
+    std::vector<std::array<std::vector<int>, 4>> row_first(nb);
+    int tsum_max = 1, kmax = 1;
+    for (int i = 0; i < nb; ++i) {
+        const NBlock& NA = bl.nb[i];
+        spk::H2Blk B{};
+        B.t0 = int(P.h_tdesc.size());
+        std::map<std::pair<int, int>, int> tloc;  // (c, s') -> local index
+        int colpos = 0;
+        for (int c = 0; c < wl; ++c) {
+            const int e = el.find(c, i);
+            if (e < 0) continue;
+            const int j = el.blk[e].j;
+            for (int q = 0; q < 4; ++q) {
+                const int co = cioff[size_t(j) * 4 + q];
+                if (co < 0) continue;
+                const int jb = br.nblock(bl.nb[j].n + kSigmaN[q]);
+                spk::H2T T{};
+                T.l_off = el.blk[e].off;
+                T.l_ld = el.blk[e].cols;
+                T.ci_off = co;
+                T.ncol = br.nb[jb].dim;
+                T.colpos = colpos;
+                colpos += T.ncol;
+                tloc[{c, q}] = int(P.h_tdesc.size()) - B.t0;
+                P.h_tdesc.push_back(T);
+            }
+        }
+        B.t1 = int(P.h_tdesc.size());
+        tsum_max = std::max(tsum_max, colpos);
+        B.maxch = 0;
+        for (int sig = 0; sig < 4; ++sig) {
+            B.ch0[sig] = B.ch1[sig] = int(P.h_chans.size());
+            row_first[i][sig].assign(NA.dim + 1, int(P.h_yout.size()));
+            const int nbb = br.nblock(NA.n + kSigmaN[sig]);
+            if (nbb < 0) continue;
+            for (int r = 0; r < NA.dim; ++r) {
+                row_first[i][sig][r] = int(P.h_yout.size());
+                int sa = NA.s0;
+                while (bl.sec[sa].ro + bl.sec[sa].dim <= r) ++sa;
+                const Sector& SA = bl.sec[sa];
+                const int sb = br.sector(SA.n + kSigmaN[sig], SA.m2 + kSigma2M[sig]);
+                if (sb < 0) continue;
+                const int xb = si.find(sa, sig);
+                SP_REQUIRE(xb >= 0, "internal: missing site block");
+                const XBlk& X = si.blk[xb];
+                const Sector& SB = br.sec[sb];
+                for (int c = 0; c < SB.dim; ++c)
+                    P.h_yout.push_back(make_int4(r, SB.ro + c, int(X.off + (long long)(r - SA.ro) * X.cols + c), 0));
+            }
+            row_first[i][sig][NA.dim] = int(P.h_yout.size());
+            auto add_channel = [&](int re, int is_ny, const std::vector<std::pair<int, int>>& tl) {
+                if (tl.empty()) return;
+                const EnvBlk& RB = er.blk[re];
+                spk::H2Chan C{};
+                C.r_off = RB.off;
+                C.K = RB.cols;
+                C.t0 = int(P.h_terms.size());
+                for (auto& pr : tl) {
+                    SP_REQUIRE(P.h_tdesc[B.t0 + pr.first].ncol == RB.cols, "internal: fused H_eff particle numbers");
+                    P.h_terms.push_back(spk::H2Term{pr.first, pr.second});
+                }
+                C.t1 = int(P.h_terms.size());
+                C.is_ny = is_ny;
+                P.h_chans.push_back(C);
+                kmax = std::max(kmax, RB.cols);
+            };
+            for (int cp = 0; cp < wr; ++cp) {
+                const int re = er.find(cp, nbb);
+                if (re < 0) continue;
+                std::vector<std::pair<int, int>> tl;
+                for (auto& kv : tloc) {
+                    auto it = wpos.find({kv.first.first, cp, sig, kv.first.second});
+                    if (it != wpos.end()) tl.push_back({kv.second, P.c_cwt(it->second)});
+                }
+                add_channel(re, 0, tl);
+            }
+            const int re = er.find(lastR, nbb);
+            if (re >= 0) {
+                std::vector<std::pair<int, int>> tl;
+                for (int q = 0; q < 4; ++q) {
+                    if (!rot_nonzero(sig, q)) continue;
+                    auto it = tloc.find({0, q});
+                    if (it == tloc.end()) continue;
+                    SP_REQUIRE(el.blk[el.find(0, i)].j == i, "internal: identity channel must conserve N");
+                    tl.push_back({it->second, P.c_gr(sig, q)});
+                }
+                add_channel(re, 1, tl);
+            }
+            B.ch1[sig] = int(P.h_chans.size());
+            B.maxch = std::max(B.maxch, B.ch1[sig] - B.ch0[sig]);
+        }
+        P.h_blks.push_back(B);
+    }
+    // rows per chunk from the LDS budgets
+    int RC = std::min({8, spk::kH2TMax / tsum_max, spk::kH2VMax / kmax});
+    SP_REQUIRE(RC >= 1, "a particle-number block is too wide for the fused H_eff kernel");
+    for (int i = 0; i < nb; ++i)
+        SP_REQUIRE(P.h_blks[i].t1 - P.h_blks[i].t0 <= spk::kH2TBlk, "too many products per block for the fused kernel");
+    auto cy_range = [&](int i, int sig, int r0, int r1, int& cy0, int& cy1) {
+        cy0 = INT32_MAX;
+        cy1 = 0;
+        for (int o = row_first[i][sig][r0]; o < row_first[i][sig][r1]; ++o) {
+            cy0 = std::min(cy0, P.h_yout[o].y);
+            cy1 = std::max(cy1, P.h_yout[o].y + 1);
+        }
+        if (cy1 <= cy0) cy0 = cy1 = 0;
+    };
+    for (;;) {  // outputs per sigma and chunk must fit the threads and the staged rows
+        bool ok = true;
+        for (int i = 0; i < nb && ok; ++i)
+            for (int sig = 0; sig < 4 && ok; ++sig)
+                for (int r0 = 0; r0 < bl.nb[i].dim; r0 += RC) {
+                    const int r1 = std::min(bl.nb[i].dim, r0 + RC);
+                    int cy0, cy1;
+                    cy_range(i, sig, r0, r1, cy0, cy1);
+                    if (row_first[i][sig][r1] - row_first[i][sig][r0] > 256 * spk::kH2Out) ok = false;
+                }
+        if (ok) break;
+        SP_REQUIRE(RC > 1, "too many outputs per row for the fused H_eff kernel");
+        --RC;
+    }
+    P.h_rows = RC;
+    for (int g = 0; g < G; ++g)
+        for (int i = 0; i < nb; ++i)
+            for (int r0 = 0; r0 < bl.nb[i].dim; r0 += RC) {
+                spk::H2Task t{};
+                t.g = g;
+                t.blk = i;
+                t.r0 = r0;
+                t.r1 = std::min(bl.nb[i].dim, r0 + RC);
+                bool any = false;
+                for (int sig = 0; sig < 4; ++sig) {
+                    t.o0[sig] = row_first[i][sig][r0];
+                    t.o1[sig] = row_first[i][sig][t.r1];
+                    cy_range(i, sig, r0, t.r1, t.cy0[sig], t.cy1[sig]);
+                    any = any || t.o1[sig] > t.o0[sig];
+                }
+                if (any) P.h_tasks.push_back(t);
+            }
+}
+
 void upload_plan(sp_handle* h, int k) {
     SitePlan& P = h->plan[k - 1];
     hipStream_t s = h->stream;
@@ -1126,6 +1321,13 @@ void upload_plan(sp_handle* h, int k) {
     P.t_envl.upload(s);
     P.t_zr.upload(s);
     P.t_envr.upload(s);
+    P.dh_tasks.upload(P.h_tasks, s);
+    P.dh_blks.upload(P.h_blks, s);
+    P.dh_tdesc.upload(P.h_tdesc, s);
+    P.dh_chans.upload(P.h_chans, s);
+    P.dh_terms.upload(P.h_terms, s);
+    P.dh_colinfo.upload(P.h_colinfo, s);
+    P.dh_yout.upload(P.h_yout, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1237,6 +1439,63 @@ void validate_plans(sp_handle* h) {
             validate(P.t_envr, t, nco, ms, xs, "tiled right environment");
             if (P.Xd_size > h->Xd_cap) throw SpError(SP_EINVAL, "internal: dense site scratch too small");
         }
+        // fused H_eff lists
+        {
+            const long long Lg = h->env[k - 1].size, Rg = h->env[k].size;
+            const long long nci = (long long)P.h_colinfo.size(), nyo = (long long)P.h_yout.size();
+            const int RC = P.h_rows;
+            if (nyo != xs) throw SpError(SP_EINVAL, "internal: fused outputs do not cover the site");
+            std::vector<char> seen(xs, 0);
+            for (const int4& y : P.h_yout) {
+                check_span(y.z, y.z, xs, "fused output index");
+                if (seen[y.z]++) throw SpError(SP_EINVAL, "internal: fused output written twice");
+            }
+            for (const spk::H2Task& t : P.h_tasks) {
+                if (t.g < 0 || t.g >= h->G || t.blk < 0 || t.blk >= int(P.h_blks.size()) || t.r1 <= t.r0 ||
+                    t.r1 - t.r0 > RC)
+                    throw SpError(SP_EINVAL, "internal: fused task");
+                const spk::H2Blk& B = P.h_blks[t.blk];
+                for (int tt = B.t0; tt < B.t1; ++tt) {
+                    const spk::H2T& T = P.h_tdesc[tt];
+                    if ((long long)(T.colpos + T.ncol) * RC > spk::kH2TMax) throw SpError(SP_EINVAL, "internal: fused T exceeds LDS");
+                    check_span(T.ci_off, T.ci_off + T.ncol - 1, nci, "fused column descriptors");
+                    for (int col = 0; col < T.ncol; ++col) {
+                        const int4 ci = P.h_colinfo[T.ci_off + col];
+                        if (ci.z <= 0) continue;
+                        check_span(ci.x, ci.x + (long long)(ci.z - 1) * ci.y, xs, "fused x column");
+                        if (ci.w + ci.z > T.l_ld) throw SpError(SP_EINVAL, "internal: fused L columns");
+                        check_span(T.l_off + (long long)t.r0 * T.l_ld + ci.w,
+                                   T.l_off + (long long)(t.r1 - 1) * T.l_ld + ci.w + ci.z - 1, Lg, "fused L rows");
+                    }
+                }
+                if (t.r1 - t.r0 > 8 || B.t1 - B.t0 > spk::kH2TBlk) throw SpError(SP_EINVAL, "internal: fused task shape");
+                for (int sig = 0; sig < 4; ++sig) {
+                    if (t.o1[sig] - t.o0[sig] > 256 * spk::kH2Out) throw SpError(SP_EINVAL, "internal: fused outputs per thread");
+                    if (t.o1[sig] > t.o0[sig]) check_span(t.o0[sig], t.o1[sig] - 1, nyo, "fused task outputs");
+                    for (int c = B.ch0[sig]; c < B.ch1[sig]; ++c) {
+                        const spk::H2Chan& C = P.h_chans[c];
+                        if ((long long)(t.r1 - t.r0) * C.K > spk::kH2VMax) throw SpError(SP_EINVAL, "internal: fused V exceeds LDS");
+                        if (C.t1 - C.t0 > 16) throw SpError(SP_EINVAL, "internal: fused channel has too many terms");
+                        if (t.o1[sig] > t.o0[sig])
+                            check_span(C.r_off + (long long)t.cy0[sig] * C.K, C.r_off + (long long)t.cy1[sig] * C.K - 1,
+                                       Rg, "fused staged R rows");
+                        for (int tm = C.t0; tm < C.t1; ++tm) {
+                            const spk::H2Term& term = P.h_terms[tm];
+                            if (term.tidx < 0 || B.t0 + term.tidx >= B.t1) throw SpError(SP_EINVAL, "internal: fused term");
+                            if (P.h_tdesc[B.t0 + term.tidx].ncol != C.K) throw SpError(SP_EINVAL, "internal: fused term width");
+                            check_span(term.cidx, term.cidx, P.nc, "fused coefficient");
+                        }
+                        for (int o = t.o0[sig]; o < t.o1[sig]; ++o) {
+                            const int4 y = P.h_yout[o];
+                            if (y.x < t.r0 || y.x >= t.r1 || y.y < t.cy0[sig] || y.y >= t.cy1[sig])
+                                throw SpError(SP_EINVAL, "internal: fused output row");
+                            check_span(C.r_off + (long long)y.y * C.K, C.r_off + (long long)y.y * C.K + C.K - 1, Rg,
+                                       "fused R row");
+                        }
+                    }
+                }
+            }
+        }
         if (k < h->L) {
             Sizes a{};
             a.fill(0);
@@ -1319,12 +1578,10 @@ void heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny) {
         P.yout.launch(s, b, P.coef.p);
         return;
     }
-    const spk::BufSet b = bufset(h, k, h->Xd.p, h->ypart.p, h->nypart.p, nullptr);
-    spk::gather(s, P.xmap.p, x, h->Xd.p, P.Xd_size);
-    P.t_left.launch(s, b, P.coef.p, P.xmap.p);
-    P.mixl.launch(s, b, P.coef.p);
-    P.t_right.launch(s, b, P.coef.p, P.xmap.p);
     const int n = int(h->sites[k - 1].size);
+    spk::heff2(s, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_tdesc.p, P.dh_chans.p, P.dh_terms.p,
+               P.dh_colinfo.p, P.dh_yout.p, P.h_rows, h->envL[k - 1].p, h->env[k - 1].size, h->envR[k].p,
+               h->env[k].size, x, P.coef.p, P.nc, h->ypart.p, h->nypart.p, n);
     spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
 }
 
@@ -1419,16 +1676,42 @@ void invalidate_for_site(sp_handle* h, int k) {
 // ---------------------------------------------------------------------------
 // Davidson for the singular pencil H_eff x = theta N_eff x (Eq. [geproblem])
 
-void ensure_pinned(sp_handle* h, size_t n) {
-    if (h->pin_n >= n) return;
-    if (h->pin) HIPCK(hipHostFree(h->pin));
-    h->pin = nullptr;
-    HIPCK(hipHostMalloc(&h->pin, n * sizeof(double), hipHostMallocDefault));
-    h->pin_n = n;
+void ensure_pinned(sp_handle* h, size_t n, size_t n_up) {
+    if (h->pin_n < n) {
+        if (h->pin) HIPCK(hipHostFree(h->pin));
+        h->pin = nullptr;
+        HIPCK(hipHostMalloc(&h->pin, n * sizeof(double), hipHostMallocDefault));
+        h->pin_n = n;
+    }
+    if (h->pin_up_n < n_up) {
+        if (h->pin_up) HIPCK(hipHostFree(h->pin_up));
+        h->pin_up = nullptr;
+        HIPCK(hipHostMalloc(&h->pin_up, n_up * sizeof(double), hipHostMallocDefault));
+        h->pin_up_n = n_up;
+    }
 }
+
+// device small area of the Davidson solve (offsets in doubles)
+struct DavLayout {
+    long long a, theta, q, pc1, pc2, pn, out, tn, px, pg, total;
+    DavLayout(int max_sub, int nch) {
+        a = 0;
+        theta = max_sub + 2;
+        q = max_sub + 4;
+        pc1 = q + (long long)max_sub * max_sub;
+        pc2 = pc1 + (long long)nch * max_sub;
+        pn = pc2 + (long long)nch * max_sub;
+        out = pn + nch;
+        tn = out;
+        px = out + 1;
+        pg = px + 3LL * nch;
+        total = pg + (long long)nch * (4 * max_sub + 2) + 8;
+    }
+};
 
 void ensure_davidson(sp_handle* h, int max_sub) {
     if (h->dav_sub >= max_sub && h->ld > 0) return;
+    SP_REQUIRE(max_sub + 1 <= spk::kDavMaxVec, "max_sub too large");
     h->ld = (h->max_site + 63) / 64 * 64;
     const size_t vec = size_t(max_sub + 1) * h->ld;
     h->dV.alloc(vec);
@@ -1439,10 +1722,11 @@ void ensure_davidson(sp_handle* h, int max_sub) {
     h->dt.alloc(h->ld);
     h->ddh.alloc(h->ld);
     h->ddn.alloc(h->ld);
-    h->dpart.alloc(3 * (h->ld / 256 + 2));
-    h->dsmall.alloc(size_t(max_sub + 2) * (max_sub + 2) + 8 * (max_sub + 8));
+    const int nch = spk::dav_chunks(int(h->ld));
+    const DavLayout lay(max_sub, nch);
+    h->dsmall.alloc(lay.total);
     h->dav_sub = max_sub;
-    ensure_pinned(h, size_t(max_sub + 2) * (max_sub + 2) + 8 * (max_sub + 8));
+    ensure_pinned(h, lay.total - lay.out + 8, lay.pc1 + 8);
 }
 
 struct DavOut {
@@ -1453,8 +1737,9 @@ struct DavOut {
 
 // lowest eigenpair of the pencil restricted to range(Nt) (canonical
 // orthogonalisation); returns false if the projected metric vanishes
+// (all Ritz coefficient vectors X C only when need_all, for restarts)
 bool small_solve(int m, const std::vector<double>& Ht, const std::vector<double>& Nt, int stride, double drop,
-                 double& theta, std::vector<double>& a, std::vector<double>& Xc, int& rk) {
+                 bool need_all, double& theta, std::vector<double>& a, std::vector<double>& Xc, int& rk) {
     std::vector<double> A(size_t(m) * m), ev(m), U(size_t(m) * m);
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < m; ++j) A[i * m + j] = 0.5 * (Nt[i * stride + j] + Nt[j * stride + i]);
@@ -1484,6 +1769,16 @@ bool small_solve(int m, const std::vector<double>& Ht, const std::vector<double>
         }
     for (int r = 0; r < rk; ++r)
         for (int c = 0; c < r; ++c) B[r * rk + c] = B[c * rk + r] = 0.5 * (B[r * rk + c] + B[c * rk + r]);
+    if (!need_all) {
+        std::vector<double> c0(rk);
+        if (sph::sym_eig_lowest(rk, B.data(), &theta, c0.data()) != 0)
+            throw SpError(SP_ENAN, "subspace eigensolver failed");
+        if (!std::isfinite(theta)) throw SpError(SP_ENAN, "non-finite Ritz value");
+        a.assign(m, 0.0);
+        for (int i = 0; i < m; ++i)
+            for (int c = 0; c < rk; ++c) a[i] += X[i * rk + c] * c0[c];
+        return true;
+    }
     std::vector<double> mu(rk), C(size_t(rk) * rk);
     if (sph::sym_eigh(rk, B.data(), mu.data(), C.data()) != 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
     theta = mu[0];
@@ -1506,77 +1801,88 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     const int n = int(h->sites[k - 1].size);
     const int max_sub = std::max(2, o.max_sub);
     const int keep = std::max(1, std::min(o.keep, max_sub - 1));
+    const int max_iter = std::max(1, o.max_iter);
     ensure_davidson(h, max_sub);
     hipStream_t s = h->stream;
     const long long ld = h->ld;
     double* V = h->dV.p;
     double* HV = h->dHV.p;
     double* NV = h->dNV.p;
-    double* sm = h->dsmall.p;  // device small area: [a | theta | c | gram]
-    const int SM_A = 0, SM_TH = max_sub + 2, SM_C = max_sub + 4, SM_G = 2 * max_sub + 8;
-    double* pin = h->pin;
+    const int nch = spk::dav_chunks(n);
+    const DavLayout lay(h->dav_sub, spk::dav_chunks(int(ld)));
+    double* sm = h->dsmall.p;
+    double* up = h->pin_up;
+    double* dn = h->pin;
     const double drop = 1e-10, floor_ = 1e-8;
     DavOut out;
+    // fixed-order sums of per-chunk partials (host side)
+    auto chunk_total = [&](const double* part, int stride, int idx) {
+        double acc = 0.0;
+        for (int q = 0; q < nch; ++q) acc += part[(size_t)q * stride + idx];
+        return acc;
+    };
 
     diag(h, k, h->ddh.p, h->ddn.p);
     spk::normalize(s, site_ptr(h, k), V, n, nullptr);
     heff_apply(h, k, V, HV, NV);
     out.matvecs = 1;
-    spk::gram(s, V, HV, NV, ld, 0, n, h->dpart.p, 0, sm + SM_G);
-    HIPCK(hipMemcpyAsync(pin, sm + SM_G, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    spk::dav_gram(s, V, HV, NV, ld, 0, n, sm + lay.pg);
+    HIPCK(hipMemcpyAsync(dn, sm + lay.pg, size_t(nch) * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     const int S = max_sub + 1;
     std::vector<double> Ht(size_t(S) * S, 0.0), Nt(size_t(S) * S, 0.0);
-    Ht[0] = pin[0];
-    Nt[0] = pin[1];
+    Ht[0] = chunk_total(dn, 2, 0);
+    Nt[0] = chunk_total(dn, 2, 1);
     int m = 1;
     std::vector<double> a, Xc;
-    for (int it = 1; it <= std::max(1, o.max_iter); ++it) {
+    for (int it = 1; it <= max_iter; ++it) {
         out.iters = it;
         double theta;
         int rk = 0;
-        if (!small_solve(m, Ht, Nt, S, drop, theta, a, Xc, rk))
+        const bool last = (it == max_iter);
+        const bool restart = !last && m >= max_sub;
+        if (!small_solve(m, Ht, Nt, S, drop, restart, theta, a, Xc, rk))
             throw SpError(SP_ENORM, "projected norm vanishes in the search space");
         out.theta = theta;
-        // upload a, theta
-        for (int i = 0; i < m; ++i) pin[i] = a[i];
-        pin[max_sub + 2] = theta;
-        HIPCK(hipMemcpyAsync(sm + SM_A, pin, (max_sub + 3) * sizeof(double), hipMemcpyHostToDevice, s));
-        int nparts = 0;
-        spk::ritz(s, V, HV, NV, ld, m, sm + SM_A, sm + SM_TH, h->ddh.p, h->ddn.p, n, floor_, h->dx.p, h->dt.p,
-                  h->dpart.p, &nparts);
-        const bool last = (it == std::max(1, o.max_iter));
-        bool restarted = false;
-        if (!last) {
-            if (m >= max_sub) {
-                // restart with the lowest Ritz vectors, Euclidean-orthonormalised
-                const int nk = std::min(keep, rk);
-                std::vector<double> Qk(size_t(m) * nk);
-                // modified Gram-Schmidt on the coefficient vectors (columns of Xc)
-                for (int c = 0; c < nk; ++c) {
-                    std::vector<double> v(m);
-                    for (int i = 0; i < m; ++i) v[i] = Xc[i * rk + c];
-                    for (int p = 0; p < c; ++p) {
-                        double d = 0.0;
-                        for (int i = 0; i < m; ++i) d += Qk[i * nk + p] * v[i];
-                        for (int i = 0; i < m; ++i) v[i] -= d * Qk[i * nk + p];
-                    }
-                    double nr = 0.0;
-                    for (int i = 0; i < m; ++i) nr += v[i] * v[i];
-                    nr = std::sqrt(nr);
-                    for (int i = 0; i < m; ++i) Qk[i * nk + c] = v[i] / nr;
+        int nk = 0;
+        std::vector<double> Qk;
+        if (restart) {
+            // the lowest Ritz vectors, Euclidean-orthonormalised (modified
+            // Gram-Schmidt on their coefficient vectors)
+            nk = std::min(keep, rk);
+            Qk.assign(size_t(m) * nk, 0.0);
+            for (int c = 0; c < nk; ++c) {
+                std::vector<double> v(m);
+                for (int i = 0; i < m; ++i) v[i] = Xc[i * rk + c];
+                for (int p = 0; p < c; ++p) {
+                    double d = 0.0;
+                    for (int i = 0; i < m; ++i) d += Qk[i * nk + p] * v[i];
+                    for (int i = 0; i < m; ++i) v[i] -= d * Qk[i * nk + p];
                 }
-                std::vector<double> Q2(size_t(m) * nk);
-                std::copy(Qk.begin(), Qk.end(), Q2.begin());
-                double* pq = pin + (max_sub + 4);
-                std::copy(Qk.begin(), Qk.end(), pq);
-                double* dq = sm + SM_G + 4 * (max_sub + 2);
-                HIPCK(hipMemcpyAsync(dq, pq, Qk.size() * sizeof(double), hipMemcpyHostToDevice, s));
+                double nr = 0.0;
+                for (int i = 0; i < m; ++i) nr += v[i] * v[i];
+                nr = std::sqrt(nr);
+                for (int i = 0; i < m; ++i) Qk[i * nk + c] = v[i] / nr;
+            }
+        }
+        // upload a, theta (and the restart rotation) in one copy
+        for (int i = 0; i < m; ++i) up[lay.a + i] = a[i];
+        up[lay.theta] = theta;
+        size_t nup = size_t(lay.q);
+        if (restart) {
+            std::copy(Qk.begin(), Qk.end(), up + lay.q);
+            nup += Qk.size();
+        }
+        HIPCK(hipMemcpyAsync(sm, up, nup * sizeof(double), hipMemcpyHostToDevice, s));
+        spk::dav_ritz(s, V, HV, NV, ld, m, sm + lay.a, sm + lay.theta, h->ddh.p, h->ddn.p, n, floor_, h->dx.p,
+                      h->dt.p, sm + lay.px, sm + lay.pc1);
+        size_t ncopy;
+        if (!last) {
+            if (restart) {
                 for (double* B : {V, HV, NV}) {
-                    spk::basis_rotate(s, B, ld, m, dq, nk, h->dRot.p, n);
+                    spk::basis_rotate(s, B, ld, m, sm + lay.q, nk, h->dRot.p, n);
                     HIPCK(hipMemcpyAsync(B, h->dRot.p, size_t(nk) * ld * sizeof(double), hipMemcpyDeviceToDevice, s));
                 }
-                // Ht <- Qk^T Ht Qk, Nt likewise
                 auto rot = [&](std::vector<double>& M) {
                     std::vector<double> tmp(size_t(m) * nk, 0.0), res(size_t(S) * S, 0.0);
                     for (int i = 0; i < m; ++i)
@@ -1596,28 +1902,25 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
                 rot(Ht);
                 rot(Nt);
                 m = nk;
-                restarted = true;
+                // the first projections must be taken against the new basis
+                spk::dav_cgs(s, V, ld, 0, m, sm + lay.pc2, nch, h->dt.p, n, sm + lay.pc1, 0);
             }
-            (void)restarted;
             // CGS2 of the correction against the search space, then normalise
+            spk::dav_cgs(s, V, ld, m, m, sm + lay.pc1, nch, h->dt.p, n, sm + lay.pc2, 0);
+            spk::dav_cgs(s, V, ld, m, 0, sm + lay.pc2, nch, h->dt.p, n, sm + lay.pn, 1);
             double* vnew = V + size_t(m) * ld;
-            for (int pass = 0; pass < 2; ++pass) {
-                spk::multidot(s, V, ld, m, h->dt.p, n, sm + SM_C);
-                spk::sub_combo(s, V, ld, m, sm + SM_C, h->dt.p, n);
-            }
-            spk::normalize(s, h->dt.p, vnew, n, sm + SM_G + 4 * m + 6);
+            spk::dav_normalize(s, sm + lay.pn, nch, h->dt.p, vnew, n, sm + lay.tn);
             heff_apply(h, k, vnew, HV + size_t(m) * ld, NV + size_t(m) * ld);
             out.matvecs++;
-            spk::gram(s, V, HV, NV, ld, m, n, h->dpart.p, nparts, sm + SM_G);
-            HIPCK(hipMemcpyAsync(pin, sm + SM_G, (4 * m + 7) * sizeof(double), hipMemcpyDeviceToHost, s));
+            spk::dav_gram(s, V, HV, NV, ld, m, n, sm + lay.pg);
+            ncopy = size_t(lay.pg - lay.out) + size_t(nch) * (4 * m + 2);
         } else {
-            spk::gram(s, V, HV, NV, ld, 0, n, h->dpart.p, nparts, sm + SM_G);
-            HIPCK(hipMemcpyAsync(pin + 4 * m + 2 - 2, sm + SM_G + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+            ncopy = size_t(lay.px - lay.out) + 3 * size_t(nch);
         }
+        HIPCK(hipMemcpyAsync(dn, sm + lay.out, ncopy * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
-        const double xx = last ? pin[4 * m] : pin[4 * m + 2];
-        const double uu = last ? pin[4 * m + 1] : pin[4 * m + 3];
-        const double xn = last ? pin[4 * m + 2] : pin[4 * m + 4];
+        const double* px = dn + (lay.px - lay.out);
+        const double xx = chunk_total(px, 3, 0), uu = chunk_total(px, 3, 1), xn = chunk_total(px, 3, 2);
         if (!std::isfinite(xx) || !std::isfinite(uu) || !(xx > 0.0)) throw SpError(SP_ENAN, "non-finite Ritz vector");
         out.rnorm = std::sqrt(uu / xx);
         out.pnorm = xn / xx;
@@ -1626,14 +1929,16 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
             break;
         }
         if (last) break;
-        const double tn = pin[4 * m + 6];
+        const double tn = dn[lay.tn - lay.out];
         if (!(tn >= 1e-14)) break;
-        // extend the projected matrices with the new vector m (symmetrised)
+        // extend the projected matrices with the new vector m
+        const double* pg = dn + (lay.pg - lay.out);
+        const int nd = 4 * m + 2;
         for (int j = 0; j <= m; ++j) {
-            const double hv_new = pin[j];             // V_j . HV_m
-            const double nv_new = pin[m + 1 + j];     // V_j . NV_m
-            const double hv_old = (j < m) ? pin[2 * m + 2 + j] : hv_new;  // V_m . HV_j
-            const double nv_old = (j < m) ? pin[3 * m + 2 + j] : nv_new;
+            const double hv_new = chunk_total(pg, nd, j);          // V_j . HV_m
+            const double nv_new = chunk_total(pg, nd, m + 1 + j);  // V_j . NV_m
+            const double hv_old = (j < m) ? chunk_total(pg, nd, 2 * m + 2 + j) : hv_new;  // V_m . HV_j
+            const double nv_old = (j < m) ? chunk_total(pg, nd, 3 * m + 2 + j) : nv_new;
             Ht[j * S + m] = hv_new;
             Ht[m * S + j] = hv_old;
             Nt[j * S + m] = nv_new;
@@ -1709,6 +2014,7 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         long long Tmax = 0, Vmax = 0, qrs = 0, qrr = 0;
         for (int k = 1; k <= h->L; ++k) {
             build_plan(h.get(), k);
+            build_fused(h.get(), k);
             const SitePlan& P = h->plan[k - 1];
             Tmax = std::max({Tmax, P.Tsize, P.Zsize});
             Vmax = std::max({Vmax, P.Vsize, P.Ztsize});
@@ -1937,16 +2243,17 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
             if (plain) {
                 P.p1.launch(s, b, P.coef.p);
             } else {
-                spk::gather(s, P.xmap.p, x, h->Xd.p, P.Xd_size);
-                P.t_left.launch(s, b, P.coef.p, P.xmap.p);
+                spk::heff2(s, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_tdesc.p, P.dh_chans.p,
+                           P.dh_terms.p, P.dh_colinfo.p, P.dh_yout.p, P.h_rows, h->envL[site - 1].p,
+                           h->env[site - 1].size, h->envR[site].p, h->env[site].size, x, P.coef.p, P.nc, h->ypart.p,
+                           h->nypart.p, n);
             }
             HIPCK(hipEventRecord(ev[1], s));
-            P.mixl.launch(s, b, P.coef.p);
+            if (plain) P.mixl.launch(s, b, P.coef.p);
             HIPCK(hipEventRecord(ev[2], s));
             if (plain) {
                 P.yout.launch(s, b, P.coef.p);
             } else {
-                P.t_right.launch(s, b, P.coef.p, P.xmap.p);
                 spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
             }
             HIPCK(hipEventRecord(ev[3], s));
@@ -1961,12 +2268,22 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
         const double G = h->G, xs = double(h->sites[site - 1].size);
         const double Lb = G * h->env[site - 1].size, Rb = G * h->env[site].size;
         for (int i = 0; i < 3; ++i) out[i] = ms[i] / reps;
-        out[3] = P.p1.flops;
-        out[4] = P.mixl.flops;
-        out[5] = P.yout.flops;
-        out[6] = 8.0 * (Lb + xs + G * P.Tsize);
-        out[7] = 8.0 * (G * P.Tsize + G * P.Vsize);
-        out[8] = 8.0 * (G * P.Vsize + G * P.Tsize + Rb + 2.0 * xs);
+        if (plain) {
+            out[3] = P.p1.flops;
+            out[4] = P.mixl.flops;
+            out[5] = P.yout.flops;
+            out[6] = 8.0 * (Lb + xs + G * P.Tsize);
+            out[7] = 8.0 * (G * P.Tsize + G * P.Vsize);
+            out[8] = 8.0 * (G * P.Vsize + G * P.Tsize + Rb + 2.0 * xs);
+        } else {
+            // fused launch: environments and x read once, per-g partials written
+            out[3] = P.p1.flops + P.mixl.flops + P.yout.flops;
+            out[4] = 0.0;
+            out[5] = 2.0 * G * xs;
+            out[6] = 8.0 * (Lb + Rb + xs + 2.0 * G * xs);
+            out[7] = 0.0;
+            out[8] = 8.0 * (2.0 * G * xs + 2.0 * xs);
+        }
         HIPCK(hipGetLastError());
         return SP_OK;
     });

@@ -201,3 +201,27 @@ def test_zero_projected_norm_is_reported():
     with pytest.raises(sp.SpError) as e:
         gpu.energy()
     assert e.value.code == sp.SP_ENORM
+
+
+@pytest.mark.parametrize("path", ["tiled", "plain"])
+def test_sweep_with_restarts_reaches_ed(path):
+    # search space of 8 vectors (restart to 4) on a full-bond-dimension chain:
+    # every local solve still converges, so the energy must reach ED
+    L, twoS = 6, 0
+    G = oq.exact_point_count(L, L, twoS)
+    tab, gpu, orc = make_pair(L, L, 0, 64, twoS, G, oracle=False, path=path)
+    rc, steps = gpu.sweep(3, max_sub=8, keep=4, max_iter=2000, tol=1e-10)
+    assert abs(steps[-1]["theta"] - (-3.092565319505379)) < 1e-9
+
+
+@pytest.mark.parametrize("path", ["tiled", "plain"])
+def test_first_steps_with_restarts_match_oracle(path):
+    # capped solves with restarts from identical inputs: the first steps agree
+    # before the trajectories can separate.  The centre sites (1590 elements)
+    # span two Davidson chunks while the first ones fit in one.
+    tab, gpu, orc = make_pair(8, 8, 0, 64, 0, 5, U=4.0, seed=1, path=path)
+    assert max(gpu.site_size(k) for k in range(1, 9)) > 1024 > gpu.site_size(1)
+    rc, steps = gpu.sweep(1, max_sub=8, keep=4, max_iter=40)
+    ref = omps.sweep(orc, 1, max_sub=8, keep=4, max_iter=40)
+    for a, b in list(zip(steps, ref))[:5]:
+        assert abs(a["theta"] - b["theta"]) < 1e-8, (a, b)
