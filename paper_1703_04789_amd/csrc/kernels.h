@@ -141,31 +141,23 @@ void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* p
 
 // Davidson vector kernels (n = vector length, ld = stride between vectors)
 void normalize(hipStream_t s, const double* in, double* out, int n, double* norm_out);
-void ritz(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
-          const double* a, const double* theta, const double* dh, const double* dn, int n,
-          double floor_, double* x, double* t, double* partials, int* nblocks_out);
 void multidot(hipStream_t s, const double* A, long long ld, int m, const double* u, int n,
               double* out);
-void sub_combo(hipStream_t s, const double* A, long long ld, int m, const double* c, double* t,
-               int n);
 void basis_rotate(hipStream_t s, const double* A, long long ld, int m, const double* Q, int keep,
                   double* out, int n);
-void gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
-          int n, const double* partials, int npart, double* out);
-void scale(hipStream_t s, double* x, int n, const double* factor_inv_sqrt_of);
-
 // Grid-parallel Davidson passes.  Each work-group owns kDavChunk consecutive
 // elements and writes per-chunk partial sums; consumers add the partials of
 // all chunks in ascending chunk order (deterministic).  m <= kDavMaxVec.
 constexpr int kDavChunk = 256;
-constexpr int kGramGroup = 32;  // dots per work-group of the Gram pass
+constexpr int kGramGroup = 16;  // dots per work-group of the Gram pass
 constexpr int kDavMaxVec = 256;
 inline int dav_chunks(int n) { return (n + kDavChunk - 1) / kDavChunk; }
-// x = V a, u = HV a - theta NV a, t = -u / floor(dh - theta dn); part_x[3 per
-// chunk] = (x.x, u.u, x.(NV a)); part_c[m per chunk] = V_j . t
+// aq = (a_0 .. a_{m-1}, theta) (device or mapped host memory); x = V a,
+// u = HV a - theta NV a, t = -u / floor(dh - theta dn); part_x[3 per chunk] =
+// (x.x, u.u, x.(NV a)); part_c[m per chunk] = V_j . t
 void dav_ritz(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
-              const double* a, const double* theta, const double* dh, const double* dn, int n, double floor_,
-              double* x, double* t, double* part_x, double* part_c);
+              const double* aq, const double* dh, const double* dn, int n, double floor_, double* x, double* t,
+              double* part_x, double* part_c);
 // c = sum of part_in over chunks; t -= V c; then part_out = V_j . t (mode 0)
 // or part_out = t.t per chunk (mode 1)
 void dav_cgs(hipStream_t s, const double* V, long long ld, int m_sub, int m_dot, const double* part_in,
@@ -173,8 +165,10 @@ void dav_cgs(hipStream_t s, const double* V, long long ld, int m_sub, int m_dot,
 // vout = t / sqrt(sum part), tnorm = sqrt(sum part)
 void dav_normalize(hipStream_t s, const double* part, int nchunk, const double* t, double* vout, int n,
                    double* tnorm);
-// per chunk: V_j.HV_m (j<=m), V_j.NV_m (j<=m), V_m.HV_j (j<m), V_m.NV_j (j<m)
-void dav_gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m, int n,
-              double* part);
+// per chunk: V_j.HV_m (j<=m), V_j.NV_m (j<=m), HV_j.V_m (j<m), NV_j.V_m (j<m);
+// with ypart != nullptr, HV_m and NV_m are first formed as the sums over the
+// G quadrature partials (stride gstride) and stored
+void dav_gram(hipStream_t s, const double* V, double* HV, double* NV, long long ld, int m, int n,
+              const double* ypart, const double* nypart, long long gstride, int G, double* part);
 
 }  // namespace spk

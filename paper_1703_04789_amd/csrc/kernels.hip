@@ -241,47 +241,6 @@ __global__ __launch_bounds__(1024) void k_normalize(const double* __restrict__ i
     if (threadIdx.x == 0 && norm_out) *norm_out = nrm;
 }
 
-__global__ __launch_bounds__(kThreads) void k_ritz(const double* __restrict__ V,
-                                                     const double* __restrict__ HV,
-                                                     const double* __restrict__ NV, long long ld,
-                                                     int m, const double* __restrict__ a,
-                                                     const double* __restrict__ theta_p,
-                                                     const double* __restrict__ dh,
-                                                     const double* __restrict__ dn, int n,
-                                                     double floor_, double* __restrict__ x,
-                                                     double* __restrict__ t,
-                                                     double* __restrict__ partials) {
-    __shared__ double red[kThreads];
-    const int e = blockIdx.x * kThreads + threadIdx.x;
-    const double theta = *theta_p;
-    double xx = 0.0, uu = 0.0, xn = 0.0;
-    if (e < n) {
-        double xv = 0.0, hv = 0.0, nv = 0.0;
-        for (int j = 0; j < m; ++j) {
-            const double aj = a[j];
-            xv = fma(aj, V[j * ld + e], xv);
-            hv = fma(aj, HV[j * ld + e], hv);
-            nv = fma(aj, NV[j * ld + e], nv);
-        }
-        const double u = hv - theta * nv;
-        double den = dh[e] - theta * dn[e];
-        if (fabs(den) < floor_) den = (den < 0.0) ? -floor_ : floor_;
-        x[e] = xv;
-        t[e] = -u / den;
-        xx = xv * xv;
-        uu = u * u;
-        xn = xv * nv;
-    }
-    xx = block_sum(xx, red);
-    uu = block_sum(uu, red);
-    xn = block_sum(xn, red);
-    if (threadIdx.x == 0) {
-        partials[3 * blockIdx.x + 0] = xx;
-        partials[3 * blockIdx.x + 1] = uu;
-        partials[3 * blockIdx.x + 2] = xn;
-    }
-}
-
 __global__ __launch_bounds__(kThreads) void k_multidot(const double* __restrict__ A, long long ld,
                                                          const double* __restrict__ u, int n,
                                                          double* __restrict__ out) {
@@ -293,70 +252,34 @@ __global__ __launch_bounds__(kThreads) void k_multidot(const double* __restrict_
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kThreads) void k_sub_combo(const double* __restrict__ A, long long ld,
-                                                          int m, const double* __restrict__ c,
-                                                          double* __restrict__ t, int n) {
-    const int e = blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n) return;
-    double s = 0.0;
-    for (int j = 0; j < m; ++j) s = fma(c[j], A[j * ld + e], s);
-    t[e] -= s;
-}
-
+// out_i = sum_j Q[j][i] A_j for i < keep: eight outputs per pass, the A
+// loads of a pass batched eight vectors at a time
 __global__ __launch_bounds__(kThreads) void k_basis_rotate(const double* __restrict__ A,
                                                              long long ld, int m,
                                                              const double* __restrict__ Q, int keep,
                                                              double* __restrict__ out, int n) {
     const int e = blockIdx.x * kThreads + threadIdx.x;
     if (e >= n) return;
-    for (int i = 0; i < keep; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < m; ++j) s = fma(Q[j * keep + i], A[j * ld + e], s);
-        out[i * ld + e] = s;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_gram(const double* __restrict__ V,
-                                                     const double* __restrict__ HV,
-                                                     const double* __restrict__ NV, long long ld,
-                                                     int m, int n, const double* __restrict__ part,
-                                                     int npart, double* __restrict__ out) {
-    __shared__ double red[kThreads];
-    const int b = blockIdx.x;
-    const double *pa, *pb;
-    if (b <= m) {
-        pa = V + b * ld;
-        pb = HV + m * ld;
-    } else if (b <= 2 * m + 1) {
-        pa = V + (b - m - 1) * ld;
-        pb = NV + m * ld;
-    } else if (b <= 3 * m + 1) {
-        pa = V + m * ld;
-        pb = HV + (b - 2 * m - 2) * ld;
-    } else if (b <= 4 * m + 1) {
-        pa = V + m * ld;
-        pb = NV + (b - 3 * m - 2) * ld;
-    } else {
-        // fold the Ritz-kernel partial sums in a fixed order
-        if (threadIdx.x < 3) {
-            double s = 0.0;
-            for (int i = 0; i < npart; ++i) s += part[3 * i + threadIdx.x];
-            out[4 * m + 2 + threadIdx.x] = s;
+    for (int i0 = 0; i0 < keep; i0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+        for (int j0 = 0; j0 < m; j0 += 8) {
+            double av[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) av[v] = (j0 + v < m) ? A[(long long)(j0 + v) * ld + e] : 0.0;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                if (j0 + v >= m) break;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + u < keep) acc[u] = fma(Q[(j0 + v) * keep + i0 + u], av[v], acc[u]);
+            }
         }
-        return;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + u < keep) out[(long long)(i0 + u) * ld + e] = acc[u];
     }
-    double s = 0.0;
-    for (int e = threadIdx.x; e < n; e += kThreads) s = fma(pa[e], pb[e], s);
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) out[b] = s;
-}
-
-__global__ __launch_bounds__(kThreads) void k_scale(double* __restrict__ x, int n,
-                                                      const double* __restrict__ ss) {
-    const int e = blockIdx.x * kThreads + threadIdx.x;
-    if (e >= n) return;
-    const double s = *ss;
-    x[e] = s > 0.0 ? x[e] / sqrt(s) : x[e];
 }
 
 // 64x64 output tile per work-group of 256 threads (16 x 16 threads, 4 x 4
@@ -649,8 +572,12 @@ __global__ __launch_bounds__(kThreads) void k_gsum2(const double* __restrict__ p
 }
 
 // ---- grid-parallel Davidson passes ----------------------------------------
+// One element per thread, kDavChunk = kThreads elements per work-group.
+// Loads over the subspace index are batched eight vectors at a time so that
+// a wave keeps many independent loads in flight.
 
-constexpr int kDavPer = kDavChunk / kThreads;  // elements per thread
+static_assert(kDavChunk == kThreads, "one element per thread");
+constexpr int kBatch = 8;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -658,23 +585,70 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// per-chunk dots V_j . w (w held in registers) for j < m -> out[j]
-__device__ inline void chunk_dots(const double* __restrict__ V, long long ld, int m, const int* es, const double* wv,
-                                  int n, double (*wred)[kDavMaxVec], double* __restrict__ out) {
+// out[j] = sum over q < nchunk of part[q * stride + j], for j < m.  Wave w
+// adds the chunks q = w mod 4 (ascending), then the four wave sums are added
+// in wave order: a fixed order, so the result is deterministic.
+__device__ inline void reduce_partials(const double* __restrict__ part, int nchunk, int stride, int m,
+                                       double (*wred)[64], double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j = 0; j < m; ++j) {
-        double sacc = 0.0;
-#pragma unroll
-        for (int i = 0; i < kDavPer; ++i)
-            if (es[i] < n) sacc = fma(V[j * ld + es[i]], wv[i], sacc);
-        sacc = wave_sum(sacc);
-        if (lane == 0) wred[wave][j] = sacc;
+    for (int j0 = 0; j0 < m; j0 += 64) {
+        const int j = j0 + lane;
+        double acc = 0.0;
+        if (j < m) {
+            int q = wave;
+            for (; q + 12 < nchunk; q += 16) {
+                const double p0 = part[(long long)q * stride + j];
+                const double p1 = part[(long long)(q + 4) * stride + j];
+                const double p2 = part[(long long)(q + 8) * stride + j];
+                const double p3 = part[(long long)(q + 12) * stride + j];
+                acc += p0;
+                acc += p1;
+                acc += p2;
+                acc += p3;
+            }
+            for (; q < nchunk; q += 4) acc += part[(long long)q * stride + j];
+        }
+        wred[wave][lane] = acc;
+        __syncthreads();
+        if (threadIdx.x < 64 && j < m) out[j] = (wred[0][lane] + wred[1][lane]) + (wred[2][lane] + wred[3][lane]);
+        __syncthreads();
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < m; j += kThreads) out[j] = (wred[0][j] + wred[1][j]) + (wred[2][j] + wred[3][j]);
-    __syncthreads();
 }
 
+// out[j] = sum over the chunk of src_j[e] w[e] for j < m, src_j = base + j ld,
+// with w staged in LDS (ws, kDavChunk values).  Wave w takes j = w mod 4, four
+// vectors per pass (16 loads in flight per lane).
+__device__ inline void chunk_dots(const double* __restrict__ base, long long ld, int m, int e0, int n,
+                                  const double* ws, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nval = min(kDavChunk, n - e0);
+    double wv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wv[q] = ws[lane + 64 * q];
+    for (int j = wave; j < m; j += 16) {
+        double acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc[u] = 0.0;
+            const int jj = j + 4 * u;
+            if (jj < m) {
+                const double* __restrict__ src = base + (long long)jj * ld + e0;
+                double v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (lane + 64 * q < nval) ? src[lane + 64 * q] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[u] = fma(v[q], wv[q], acc[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double r = wave_sum(acc[u]);
+            if (lane == 0 && j + 4 * u < m) out[j + 4 * u] = r;
+        }
+    }
+}
+
+// sum of a block-wide value, broadcast to every thread (fixed order)
 __device__ inline double chunk_sum(double v, double* wsum) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     v = wave_sum(v);
@@ -687,51 +661,71 @@ __device__ inline double chunk_sum(double v, double* wsum) {
 
 __global__ __launch_bounds__(kThreads) void k_dav_ritz(const double* __restrict__ V, const double* __restrict__ HV,
                                                          const double* __restrict__ NV, long long ld, int m,
-                                                         const double* __restrict__ a,
-                                                         const double* __restrict__ theta_p,
+                                                         const double* __restrict__ aq,
                                                          const double* __restrict__ dh,
                                                          const double* __restrict__ dn, int n, double floor_,
                                                          double* __restrict__ x, double* __restrict__ t,
                                                          double* __restrict__ part_x, double* __restrict__ part_c) {
-    __shared__ double wred[4][kDavMaxVec];
-    __shared__ double wsum[4];
-    const double theta = *theta_p;
-    int es[kDavPer];
-    double tv[kDavPer];
-    double xx = 0.0, uu = 0.0, xn = 0.0;
+    __shared__ double sa[kDavMaxVec + 1];
+    __shared__ double ts[kDavChunk];
+    __shared__ double wsum[4][3];
+    for (int j = threadIdx.x; j <= m; j += kThreads) sa[j] = aq[j];
+    __syncthreads();
+    const double theta = sa[m];
+    const int e0 = blockIdx.x * kDavChunk;
+    const int e = e0 + threadIdx.x;
+    double tv = 0.0, xx = 0.0, uu = 0.0, xn = 0.0;
+    if (e < n) {
+        double xv = 0.0, hv = 0.0, nv = 0.0;
+        int j = 0;
+        for (; j + kBatch <= m; j += kBatch) {
+            double v[kBatch], h[kBatch], q[kBatch];
 #pragma unroll
-    for (int i = 0; i < kDavPer; ++i) {
-        const int e = blockIdx.x * kDavChunk + threadIdx.x + kThreads * i;
-        es[i] = e;
-        tv[i] = 0.0;
-        if (e < n) {
-            double xv = 0.0, hv = 0.0, nv = 0.0;
-            for (int j = 0; j < m; ++j) {
-                const double aj = a[j];
-                xv = fma(aj, V[j * ld + e], xv);
-                hv = fma(aj, HV[j * ld + e], hv);
-                nv = fma(aj, NV[j * ld + e], nv);
+            for (int u = 0; u < kBatch; ++u) {
+                const long long o = (long long)(j + u) * ld + e;
+                v[u] = V[o];
+                h[u] = HV[o];
+                q[u] = NV[o];
             }
-            const double u = hv - theta * nv;
-            double den = dh[e] - theta * dn[e];
-            if (fabs(den) < floor_) den = (den < 0.0) ? -floor_ : floor_;
-            tv[i] = -u / den;
-            x[e] = xv;
-            t[e] = tv[i];
-            xx = fma(xv, xv, xx);
-            uu = fma(u, u, uu);
-            xn = fma(xv, nv, xn);
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                xv = fma(sa[j + u], v[u], xv);
+                hv = fma(sa[j + u], h[u], hv);
+                nv = fma(sa[j + u], q[u], nv);
+            }
         }
+        for (; j < m; ++j) {
+            const long long o = (long long)j * ld + e;
+            xv = fma(sa[j], V[o], xv);
+            hv = fma(sa[j], HV[o], hv);
+            nv = fma(sa[j], NV[o], nv);
+        }
+        const double u = hv - theta * nv;
+        double den = dh[e] - theta * dn[e];
+        if (fabs(den) < floor_) den = (den < 0.0) ? -floor_ : floor_;
+        tv = -u / den;
+        x[e] = xv;
+        t[e] = tv;
+        xx = xv * xv;
+        uu = u * u;
+        xn = xv * nv;
     }
-    xx = chunk_sum(xx, wsum);
-    uu = chunk_sum(uu, wsum);
-    xn = chunk_sum(xn, wsum);
-    if (threadIdx.x == 0) {
-        part_x[3 * blockIdx.x + 0] = xx;
-        part_x[3 * blockIdx.x + 1] = uu;
-        part_x[3 * blockIdx.x + 2] = xn;
+    ts[threadIdx.x] = tv;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    xx = wave_sum(xx);
+    uu = wave_sum(uu);
+    xn = wave_sum(xn);
+    if (lane == 0) {
+        wsum[wave][0] = xx;
+        wsum[wave][1] = uu;
+        wsum[wave][2] = xn;
     }
-    chunk_dots(V, ld, m, es, tv, n, wred, part_c + (long long)blockIdx.x * m);
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        part_x[3 * blockIdx.x + c] = (wsum[0][c] + wsum[1][c]) + (wsum[2][c] + wsum[3][c]);
+    }
+    chunk_dots(V, ld, m, e0, n, ts, part_c + (long long)blockIdx.x * m);
 }
 
 __global__ __launch_bounds__(kThreads) void k_dav_cgs(const double* __restrict__ V, long long ld, int m,
@@ -739,34 +733,32 @@ __global__ __launch_bounds__(kThreads) void k_dav_cgs(const double* __restrict__
                                                         double* __restrict__ t, int n,
                                                         double* __restrict__ part_out, int mode) {
     __shared__ double c[kDavMaxVec];
-    __shared__ double wred[4][kDavMaxVec];
+    __shared__ double wred[4][64];
+    __shared__ double ts[kDavChunk];
     __shared__ double wsum[4];
-    for (int j = threadIdx.x; j < m; j += kThreads) {
-        double sacc = 0.0;
-        for (int q = 0; q < nchunk; ++q) sacc += part_in[(long long)q * m + j];
-        c[j] = sacc;
-    }
-    __syncthreads();
-    int es[kDavPer];
-    double tv[kDavPer];
-    double ss = 0.0;
+    reduce_partials(part_in, nchunk, m, m, wred, c);
+    const int e0 = blockIdx.x * kDavChunk;
+    const int e = e0 + threadIdx.x;
+    double v = 0.0;
+    if (e < n) {
+        v = t[e];
+        int j = 0;
+        for (; j + kBatch <= m; j += kBatch) {
+            double w[kBatch];
 #pragma unroll
-    for (int i = 0; i < kDavPer; ++i) {
-        const int e = blockIdx.x * kDavChunk + threadIdx.x + kThreads * i;
-        es[i] = e;
-        tv[i] = 0.0;
-        if (e < n) {
-            double v = t[e];
-            for (int j = 0; j < m; ++j) v = fma(-c[j], V[j * ld + e], v);
-            t[e] = v;
-            tv[i] = v;
-            ss = fma(v, v, ss);
+            for (int u = 0; u < kBatch; ++u) w[u] = V[(long long)(j + u) * ld + e];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) v = fma(-c[j + u], w[u], v);
         }
+        for (; j < m; ++j) v = fma(-c[j], V[(long long)j * ld + e], v);
+        t[e] = v;
     }
     if (mode == 0) {
-        chunk_dots(V, ld, m_dot, es, tv, n, wred, part_out + (long long)blockIdx.x * m_dot);
+        ts[threadIdx.x] = v;
+        __syncthreads();
+        chunk_dots(V, ld, m_dot, e0, n, ts, part_out + (long long)blockIdx.x * m_dot);
     } else {
-        ss = chunk_sum(ss, wsum);
+        const double ss = chunk_sum(v * v, wsum);
         if (threadIdx.x == 0) part_out[blockIdx.x] = ss;
     }
 }
@@ -775,64 +767,92 @@ __global__ __launch_bounds__(kThreads) void k_dav_normalize(const double* __rest
                                                               const double* __restrict__ t,
                                                               double* __restrict__ vout, int n,
                                                               double* __restrict__ tnorm) {
-    double ss = 0.0;
-    for (int q = 0; q < nchunk; ++q) ss += part[q];
-    const double nrm = sqrt(ss);
+    __shared__ double wred[4][64];
+    __shared__ double tot[1];
+    reduce_partials(part, nchunk, 1, 1, wred, tot);
+    const double nrm = sqrt(tot[0]);
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-#pragma unroll
-    for (int i = 0; i < kDavPer; ++i) {
-        const int e = blockIdx.x * kDavChunk + threadIdx.x + kThreads * i;
-        if (e < n) vout[e] = t[e] * inv;
-    }
+    const int e = blockIdx.x * kDavChunk + threadIdx.x;
+    if (e < n) vout[e] = t[e] * inv;
     if (blockIdx.x == 0 && threadIdx.x == 0) *tnorm = nrm;
 }
 
-__global__ __launch_bounds__(kThreads) void k_dav_gram(const double* __restrict__ V, const double* __restrict__ HV,
-                                                         const double* __restrict__ NV, long long ld, int m, int n,
+// Gram rows of the new vector m.  With ypart != nullptr the quadrature
+// partial sums of H_eff v_m and N_eff v_m are added here first (ascending g)
+// and written to HV_m and NV_m by the work-groups with blockIdx.y == 0.
+__global__ __launch_bounds__(kThreads) void k_dav_gram(const double* __restrict__ V, double* __restrict__ HV,
+                                                         double* __restrict__ NV, long long ld, int m, int n,
+                                                         const double* __restrict__ ypart,
+                                                         const double* __restrict__ nypart, long long gstride, int G,
                                                          double* __restrict__ part) {
-    __shared__ double wred[4][kGramGroup];
+    __shared__ double vs[kDavChunk], hs[kDavChunk], ns[kDavChunk];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nd = 4 * m + 2;
-    int es[kDavPer];
-    double vm[kDavPer], hm[kDavPer], nm[kDavPer];
-#pragma unroll
-    for (int i = 0; i < kDavPer; ++i) {
-        const int e = blockIdx.x * kDavChunk + threadIdx.x + kThreads * i;
-        es[i] = e;
-        const bool ok = e < n;
-        vm[i] = ok ? V[m * ld + e] : 0.0;
-        hm[i] = ok ? HV[m * ld + e] : 0.0;
-        nm[i] = ok ? NV[m * ld + e] : 0.0;
+    const int e0 = blockIdx.x * kDavChunk;
+    const int e = e0 + threadIdx.x;
+    const int nval = min(kDavChunk, n - e0);
+    double vm = 0.0, hm = 0.0, nm = 0.0;
+    if (e < n) {
+        const long long o = (long long)m * ld + e;
+        vm = V[o];
+        if (ypart) {
+            for (int g = 0; g < G; ++g) {
+                hm += ypart[g * gstride + e];
+                nm += nypart[g * gstride + e];
+            }
+            if (blockIdx.y == 0) {
+                HV[o] = hm;
+                NV[o] = nm;
+            }
+        } else {
+            hm = HV[o];
+            nm = NV[o];
+        }
     }
+    vs[threadIdx.x] = vm;
+    hs[threadIdx.x] = hm;
+    ns[threadIdx.x] = nm;
+    __syncthreads();
     double* out = part + (long long)blockIdx.x * nd;
     const int d0 = blockIdx.y * kGramGroup;
     const int d1 = min(nd, d0 + kGramGroup);
-    for (int d = d0; d < d1; ++d) {
-        const double* __restrict__ src;
-        int which;
-        if (d <= m) {
-            src = V + d * ld;
-            which = 0;
-        } else if (d <= 2 * m + 1) {
-            src = V + (d - m - 1) * ld;
-            which = 1;
-        } else if (d <= 3 * m + 1) {
-            src = HV + (d - 2 * m - 2) * ld;
-            which = 2;
-        } else {
-            src = NV + (d - 3 * m - 2) * ld;
-            which = 2;
-        }
-        double sacc = 0.0;
+    // d <= m: V_d.HV_m; then V_j.NV_m (j <= m); HV_j.V_m (j < m); NV_j.V_m (j < m)
+    for (int d = d0 + wave; d < d1; d += 16) {
+        double acc[4];
 #pragma unroll
-        for (int i = 0; i < kDavPer; ++i)
-            if (es[i] < n) sacc = fma(src[es[i]], which == 0 ? hm[i] : (which == 1 ? nm[i] : vm[i]), sacc);
-        sacc = wave_sum(sacc);
-        if (lane == 0) wred[wave][d - d0] = sacc;
+        for (int u = 0; u < 4; ++u) {
+            acc[u] = 0.0;
+            const int dd = d + 4 * u;
+            if (dd < d1) {
+                const double* __restrict__ src;
+                const double* w;
+                if (dd <= m) {
+                    src = V + (long long)dd * ld;
+                    w = hs;
+                } else if (dd <= 2 * m + 1) {
+                    src = V + (long long)(dd - m - 1) * ld;
+                    w = ns;
+                } else if (dd <= 3 * m + 1) {
+                    src = HV + (long long)(dd - 2 * m - 2) * ld;
+                    w = vs;
+                } else {
+                    src = NV + (long long)(dd - 3 * m - 2) * ld;
+                    w = vs;
+                }
+                src += e0;
+                double v[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = (lane + 64 * q < nval) ? src[lane + 64 * q] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[u] = fma(v[q], w[lane + 64 * q], acc[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double r = wave_sum(acc[u]);
+            if (lane == 0 && d + 4 * u < d1) out[d + 4 * u] = r;
+        }
     }
-    __syncthreads();
-    for (int d = d0 + threadIdx.x; d < d1; d += kThreads)
-        out[d] = (wred[0][d - d0] + wred[1][d - d0]) + (wred[2][d - d0] + wred[3][d - d0]);
 }
 
 inline int nblk(int n) { return (n + kThreads - 1) / kThreads; }
@@ -880,33 +900,18 @@ void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* p
 void normalize(hipStream_t s, const double* in, double* out, int n, double* norm_out) {
     hipLaunchKernelGGL(k_normalize, dim3(1), dim3(1024), 0, s, in, out, n, norm_out);
 }
-void ritz(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
-          const double* a, const double* theta, const double* dh, const double* dn, int n, double floor_,
-          double* x, double* t, double* partials, int* nblocks_out) {
-    const int nb = nblk(n);
-    hipLaunchKernelGGL(k_ritz, dim3(nb), dim3(kThreads), 0, s, V, HV, NV, ld, m, a, theta, dh, dn, n, floor_,
-                       x, t, partials);
-    if (nblocks_out) *nblocks_out = nb;
-}
 void multidot(hipStream_t s, const double* A, long long ld, int m, const double* u, int n, double* out) {
     if (m > 0) hipLaunchKernelGGL(k_multidot, dim3(m), dim3(kThreads), 0, s, A, ld, u, n, out);
-}
-void sub_combo(hipStream_t s, const double* A, long long ld, int m, const double* c, double* t, int n) {
-    if (m > 0) hipLaunchKernelGGL(k_sub_combo, dim3(nblk(n)), dim3(kThreads), 0, s, A, ld, m, c, t, n);
 }
 void basis_rotate(hipStream_t s, const double* A, long long ld, int m, const double* Q, int keep,
                   double* out, int n) {
     hipLaunchKernelGGL(k_basis_rotate, dim3(nblk(n)), dim3(kThreads), 0, s, A, ld, m, Q, keep, out, n);
 }
-void gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m, int n,
-          const double* partials, int npart, double* out) {
-    hipLaunchKernelGGL(k_gram, dim3(4 * m + 3), dim3(kThreads), 0, s, V, HV, NV, ld, m, n, partials, npart, out);
-}
 void dav_ritz(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
-              const double* a, const double* theta, const double* dh, const double* dn, int n, double floor_,
-              double* x, double* t, double* part_x, double* part_c) {
-    hipLaunchKernelGGL(k_dav_ritz, dim3(dav_chunks(n)), dim3(kThreads), 0, s, V, HV, NV, ld, m, a, theta, dh, dn, n,
-                       floor_, x, t, part_x, part_c);
+              const double* aq, const double* dh, const double* dn, int n, double floor_, double* x, double* t,
+              double* part_x, double* part_c) {
+    hipLaunchKernelGGL(k_dav_ritz, dim3(dav_chunks(n)), dim3(kThreads), 0, s, V, HV, NV, ld, m, aq, dh, dn, n, floor_,
+                       x, t, part_x, part_c);
 }
 void dav_cgs(hipStream_t s, const double* V, long long ld, int m_sub, int m_dot, const double* part_in,
              int nchunk, double* t, int n, double* part_out, int mode) {
@@ -917,14 +922,10 @@ void dav_normalize(hipStream_t s, const double* part, int nchunk, const double* 
                    double* tnorm) {
     hipLaunchKernelGGL(k_dav_normalize, dim3(dav_chunks(n)), dim3(kThreads), 0, s, part, nchunk, t, vout, n, tnorm);
 }
-void dav_gram(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m, int n,
-              double* part) {
+void dav_gram(hipStream_t s, const double* V, double* HV, double* NV, long long ld, int m, int n,
+              const double* ypart, const double* nypart, long long gstride, int G, double* part) {
     const int nd = 4 * m + 2;
     hipLaunchKernelGGL(k_dav_gram, dim3(dav_chunks(n), (nd + kGramGroup - 1) / kGramGroup), dim3(kThreads), 0, s, V, HV,
-                       NV, ld, m, n, part);
+                       NV, ld, m, n, ypart, nypart, gstride, G, part);
 }
-void scale(hipStream_t s, double* x, int n, const double* ss) {
-    hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(kThreads), 0, s, x, n, ss);
-}
-
 }  // namespace spk

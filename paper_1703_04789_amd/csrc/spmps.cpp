@@ -352,8 +352,10 @@ struct sp_handle {
     long long ld = 0;
     DArr<double> dV, dHV, dNV, dRot, dx, dt, ddh, ddn, dpart, dsmall, dy, dny;
     double* pin = nullptr;  // pinned host staging (device -> host)
+    double* pin_dev = nullptr;  // the same memory as kernels address it
     size_t pin_n = 0;
     double* pin_up = nullptr;  // pinned host staging (host -> device)
+    double* pin_up_dev = nullptr;
     size_t pin_up_n = 0;
     ~sp_handle() {
         if (pin) (void)hipHostFree(pin);
@@ -1566,7 +1568,10 @@ spk::BufSet bufset(sp_handle* h, int k, const double* x, double* y, double* ny, 
 
 void check_site(const sp_handle* h, int k) { SP_REQUIRE(k >= 1 && k <= h->L, "site out of range"); }
 
-void heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny) {
+// With defer_gsum on the tiled path only the per-quadrature-point partials
+// (h->ypart, h->nypart) are produced and the function returns true: the
+// caller adds them (the Davidson Gram pass does).
+bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, bool defer_gsum = false) {
     if (!h->Lvalid[k - 1] || !h->Rvalid[k])
         throw SpError(SP_ESTATE, "H_eff needs L[site-1] and R[site+1]; build them with sp_env_update");
     SitePlan& P = h->plan[k - 1];
@@ -1576,13 +1581,15 @@ void heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny) {
         P.p1.launch(s, b, P.coef.p);
         P.mixl.launch(s, b, P.coef.p);
         P.yout.launch(s, b, P.coef.p);
-        return;
+        return false;
     }
     const int n = int(h->sites[k - 1].size);
     spk::heff2(s, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_tdesc.p, P.dh_chans.p, P.dh_terms.p,
                P.dh_colinfo.p, P.dh_yout.p, P.h_rows, h->envL[k - 1].p, h->env[k - 1].size, h->envR[k].p,
                h->env[k].size, x, P.coef.p, P.nc, h->ypart.p, h->nypart.p, n);
+    if (defer_gsum) return true;
     spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
+    return false;
 }
 
 void env_left(sp_handle* h, int k) {
@@ -1676,17 +1683,25 @@ void invalidate_for_site(sp_handle* h, int k) {
 // ---------------------------------------------------------------------------
 // Davidson for the singular pencil H_eff x = theta N_eff x (Eq. [geproblem])
 
+// Pinned, mapped and coherent host memory: the Davidson kernels read the
+// subspace coefficients from it and write their per-chunk partial sums into
+// it directly, so an iteration needs no copy in either direction.
 void ensure_pinned(sp_handle* h, size_t n, size_t n_up) {
+    const unsigned flags = hipHostMallocMapped | hipHostMallocCoherent;
     if (h->pin_n < n) {
         if (h->pin) HIPCK(hipHostFree(h->pin));
         h->pin = nullptr;
-        HIPCK(hipHostMalloc(&h->pin, n * sizeof(double), hipHostMallocDefault));
+        h->pin_dev = nullptr;
+        HIPCK(hipHostMalloc(&h->pin, n * sizeof(double), flags));
+        HIPCK(hipHostGetDevicePointer((void**)&h->pin_dev, h->pin, 0));
         h->pin_n = n;
     }
     if (h->pin_up_n < n_up) {
         if (h->pin_up) HIPCK(hipHostFree(h->pin_up));
         h->pin_up = nullptr;
-        HIPCK(hipHostMalloc(&h->pin_up, n_up * sizeof(double), hipHostMallocDefault));
+        h->pin_up_dev = nullptr;
+        HIPCK(hipHostMalloc(&h->pin_up, n_up * sizeof(double), flags));
+        HIPCK(hipHostGetDevicePointer((void**)&h->pin_up_dev, h->pin_up, 0));
         h->pin_up_n = n_up;
     }
 }
@@ -1813,6 +1828,13 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     double* sm = h->dsmall.p;
     double* up = h->pin_up;
     double* dn = h->pin;
+    double* dn_dev = h->pin_dev;  // device view of dn: partial sums land here
+    auto gram = [&](int mm) {
+        double* vm = V + size_t(mm) * ld;
+        const bool deferred = heff_apply(h, k, vm, HV + size_t(mm) * ld, NV + size_t(mm) * ld, true);
+        spk::dav_gram(s, V, HV, NV, ld, mm, n, deferred ? h->ypart.p : nullptr, deferred ? h->nypart.p : nullptr,
+                      n, h->G, dn_dev + (lay.pg - lay.out));
+    };
     const double drop = 1e-10, floor_ = 1e-8;
     DavOut out;
     // fixed-order sums of per-chunk partials (host side)
@@ -1824,15 +1846,13 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
 
     diag(h, k, h->ddh.p, h->ddn.p);
     spk::normalize(s, site_ptr(h, k), V, n, nullptr);
-    heff_apply(h, k, V, HV, NV);
+    gram(0);
     out.matvecs = 1;
-    spk::dav_gram(s, V, HV, NV, ld, 0, n, sm + lay.pg);
-    HIPCK(hipMemcpyAsync(dn, sm + lay.pg, size_t(nch) * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     const int S = max_sub + 1;
     std::vector<double> Ht(size_t(S) * S, 0.0), Nt(size_t(S) * S, 0.0);
-    Ht[0] = chunk_total(dn, 2, 0);
-    Nt[0] = chunk_total(dn, 2, 1);
+    Ht[0] = chunk_total(dn + (lay.pg - lay.out), 2, 0);
+    Nt[0] = chunk_total(dn + (lay.pg - lay.out), 2, 1);
     int m = 1;
     std::vector<double> a, Xc;
     for (int it = 1; it <= max_iter; ++it) {
@@ -1865,18 +1885,16 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
                 for (int i = 0; i < m; ++i) Qk[i * nk + c] = v[i] / nr;
             }
         }
-        // upload a, theta (and the restart rotation) in one copy
+        // a and theta are read by the Ritz kernel straight from mapped host
+        // memory; the restart rotation is copied to the device
         for (int i = 0; i < m; ++i) up[lay.a + i] = a[i];
-        up[lay.theta] = theta;
-        size_t nup = size_t(lay.q);
+        up[lay.a + m] = theta;
         if (restart) {
             std::copy(Qk.begin(), Qk.end(), up + lay.q);
-            nup += Qk.size();
+            HIPCK(hipMemcpyAsync(sm + lay.q, up + lay.q, Qk.size() * sizeof(double), hipMemcpyHostToDevice, s));
         }
-        HIPCK(hipMemcpyAsync(sm, up, nup * sizeof(double), hipMemcpyHostToDevice, s));
-        spk::dav_ritz(s, V, HV, NV, ld, m, sm + lay.a, sm + lay.theta, h->ddh.p, h->ddn.p, n, floor_, h->dx.p,
-                      h->dt.p, sm + lay.px, sm + lay.pc1);
-        size_t ncopy;
+        spk::dav_ritz(s, V, HV, NV, ld, m, h->pin_up_dev + lay.a, h->ddh.p, h->ddn.p, n, floor_, h->dx.p, h->dt.p,
+                      dn_dev + (lay.px - lay.out), sm + lay.pc1);
         if (!last) {
             if (restart) {
                 for (double* B : {V, HV, NV}) {
@@ -1909,15 +1927,10 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
             spk::dav_cgs(s, V, ld, m, m, sm + lay.pc1, nch, h->dt.p, n, sm + lay.pc2, 0);
             spk::dav_cgs(s, V, ld, m, 0, sm + lay.pc2, nch, h->dt.p, n, sm + lay.pn, 1);
             double* vnew = V + size_t(m) * ld;
-            spk::dav_normalize(s, sm + lay.pn, nch, h->dt.p, vnew, n, sm + lay.tn);
-            heff_apply(h, k, vnew, HV + size_t(m) * ld, NV + size_t(m) * ld);
+            spk::dav_normalize(s, sm + lay.pn, nch, h->dt.p, vnew, n, dn_dev + (lay.tn - lay.out));
+            gram(m);
             out.matvecs++;
-            spk::dav_gram(s, V, HV, NV, ld, m, n, sm + lay.pg);
-            ncopy = size_t(lay.pg - lay.out) + size_t(nch) * (4 * m + 2);
-        } else {
-            ncopy = size_t(lay.px - lay.out) + 3 * size_t(nch);
         }
-        HIPCK(hipMemcpyAsync(dn, sm + lay.out, ncopy * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
         const double* px = dn + (lay.px - lay.out);
         const double xx = chunk_total(px, 3, 0), uu = chunk_total(px, 3, 1), xn = chunk_total(px, 3, 2);
