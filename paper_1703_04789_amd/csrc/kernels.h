@@ -85,47 +85,59 @@ void gather(hipStream_t s, const int* map, const double* src, double* dst, long 
 void gsum2(hipStream_t s, const double* pa, const double* pb, long long stride, int G, int n, double* outa,
            double* outb);
 
-// Fused H_eff x / N_eff x.  One work-group per (g, bra particle-number block
-// i of the left bond, rows [r0, r0 + rows)).
-//  phase A: every product T(c, s') = L_g(c, i, j_c)[rows] x(j_c, s', .) of a
-//           left channel c and ket index s' goes to LDS once, computed from
-//           the packed site vector through per-column sector descriptors
-//           (one thread per column, all rows at once);
-//  phase B: for each output sigma and each right channel c' (and the
-//           identity channel that gives N_eff): stage the right-environment
-//           rows the outputs need in LDS, form V = sum_terms coef * T (the
-//           W r mixing, coef includes coef_g), and accumulate the allowed
-//           (N, M) outputs y[r][colY] += sum_kk V[r][kk] R_g(c', N_b)[colY][kk].
-// Per-g partials go to ypart/nypart[g*n + packed index].
-struct H2Blk {
-    int t0, t1;        // T-block descriptors of this bra block
-    int ch0[4], ch1[4];  // channels per output sigma
-    int maxch, pad;
+// Fused H_eff x / N_eff x (all quadrature points in one launch).  One
+// work-group per (g, bra particle-number block i of the left bond, rows
+// [r0, r0 + rows)), rows <= RC (a compile-time row count, 1..8).
+//  phase A: the chunk's rows of every left-environment block L_g(c, i, .)
+//           are staged in LDS; then every product T(c, s') = L_g(c, i) x[s']
+//           (x block-sparse in M, so each T column runs over the ket rows of
+//           one (N, M) sector) is formed one column per thread, all rows at
+//           once, and kept in LDS column-major (RC rows per column);
+//  per output sigma: V(c') = sum_terms coef * T for every right channel c'
+//           of sigma (the W r mixing with coef_g; the identity channel gives
+//           N_eff), then every allowed (N, M) output
+//           y[sigma](r, b) = sum_c' sum_k V(c')(r, k) R_g(c')(b, k) is formed
+//           by a group of lanes that split k and add their partial sums
+//           with cross-lane shuffles (right environment read coalesced from
+//           global memory).
+// Per-g partials go to ypart/nypart[g*n + packed index].  All LDS offsets in
+// the descriptors are in doubles and already include the RC factors.
+struct H3Blk {
+    int c0, c1;        // T columns (H3Col list)
+    int l0, l1;        // left-environment blocks staged per chunk (H3LSrc list)
+    int s0[4], s1[4];  // right-channel segments per output sigma (H3Seg list)
 };
-struct H2T {
-    long long l_off;  // left environment block offset (within one g)
-    int l_ld, ci_off, ncol, colpos;  // colpos: LDS column offset (times rows)
+struct H3Col {
+    int x_off, x_ld, K;  // x entries x_off + kk * x_ld, kk < K
+    int l_lds, l_ld;     // staged L entry (rr, kk) at l_lds + rr * l_ld + kk
+    int t_pos;           // T entry (rr) at t_pos + rr
+    int pad0, pad1;
 };
-struct H2Chan {
-    long long r_off;  // right environment block offset (within one g)
-    int K, t0, t1, is_ny;
+struct H3LSrc {
+    int l_off, ld, lds, pad;  // rows of ld entries (within one g) -> LDS at lds + rr * ld
 };
-struct H2Term {
-    int tidx, cidx;  // T block (relative to the bra block's list), coefficient
+struct H3Seg {
+    int r_off, K;  // right-environment block (within one g): row b at r_off + b * K
+    int v_off;     // V entry (rr, k) at v_off + k * RC + rr
+    int t0, t1;    // mixing terms
+    int is_ny, pad0, pad1;
 };
-struct H2Task {
-    int g, blk, r0, r1;
-    int o0[4], o1[4];
-    int cy0[4], cy1[4];  // right-environment rows needed by the outputs of each sigma
+struct H3Term {
+    int t_base, cidx;  // T block in LDS (entry (rr, k) at t_base + k * RC + rr), coefficient index
 };
-constexpr int kH2TMax = 6144;  // doubles of LDS for the T rows
-constexpr int kH2VMax = 512;   // doubles of LDS for the V rows of one (sigma, channel)
-constexpr int kH2RMax = 2048;  // doubles of LDS for the staged right-environment rows
-constexpr int kH2TBlk = 64;    // T blocks per bra block (descriptors cached in LDS)
-constexpr int kH2Out = 2;      // outputs per thread and sigma (<= 512 per sigma and task)
-
-void heff2(hipStream_t s, const H2Task* tasks, int ntasks, const H2Blk* blks, const H2T* tdesc,
-           const H2Chan* chans, const H2Term* terms, const int4* colinfo, const int4* yout, int rows_max,
+struct H3Piece {
+    int rlo, rhi;         // chunk-relative rows of one left (N, M) sector
+    int b0, nb;           // right-block rows of the output columns
+    int out_off, out_ld;  // output (rr, b) at out_off + (rr - rlo) * out_ld + b
+    int pad0, pad1;
+};
+struct H3Task {
+    int g, blk, r0, rows;  // blk < 0: an empty task (padding)
+    int p0[4], p1[4];      // output pieces per sigma
+};
+constexpr int kH3MaxRC = 8;
+void heff3(hipStream_t s, int RC, int lds_doubles, const H3Task* tasks, int ntasks, const H3Blk* blks,
+           const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms, const H3Piece* pieces,
            const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
            const double* coef, int nc, double* ypart, double* nypart, long long n);
 

@@ -371,181 +371,149 @@ __global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ ta
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_heff2(
-    const H2Task* __restrict__ tasks, const H2Blk* __restrict__ blks, const H2T* __restrict__ tdesc,
-    const H2Chan* __restrict__ chans, const H2Term* __restrict__ terms, const int4* __restrict__ colinfo,
-    const int4* __restrict__ yout, int RC, const double* __restrict__ Lenv, long long Lsz,
+template <int RC>
+__global__ __launch_bounds__(kThreads) void k_heff3(
+    const H3Task* __restrict__ tasks, const H3Blk* __restrict__ blks, const H3Col* __restrict__ cols,
+    const H3LSrc* __restrict__ lsrc, const H3Seg* __restrict__ segs, const H3Term* __restrict__ terms,
+    const H3Piece* __restrict__ pieces, const double* __restrict__ Lenv, long long Lsz,
     const double* __restrict__ Renv, long long Rsz, const double* __restrict__ x, const double* __restrict__ coef,
     int nc, double* __restrict__ ypart, double* __restrict__ nypart, long long n) {
-    constexpr int kMaxRC = 8;
-    __shared__ double Ts[kH2TMax];
-    __shared__ double Vs[kH2VMax];
-    __shared__ double Rs[kH2RMax];
-    __shared__ H2T td[kH2TBlk];
-    __shared__ int tcols[kH2TBlk + 1];
-    __shared__ int s_pos[16];
-    __shared__ double s_cf[16];
-    // task and block descriptors live in LDS: their small arrays are indexed
-    // with a run-time sigma, which would otherwise put them in scratch
-    __shared__ H2Task tk;
-    __shared__ H2Blk B;
-    if (threadIdx.x == 0) {
-        tk = tasks[blockIdx.x];
-        B = blks[tk.blk];
+    extern __shared__ double lds[];
+    const H3Task* __restrict__ tkp = tasks + blockIdx.x;
+    const int blk = tkp->blk;
+    if (blk < 0) return;
+    const int g = tkp->g, r0 = tkp->r0, rows = tkp->rows;
+    const H3Blk* __restrict__ bp = blks + blk;
+    const double* __restrict__ L = Lenv + g * Lsz;
+    const double* __restrict__ R = Renv + g * Rsz;
+    const double* __restrict__ cf = coef + (long long)g * nc;
+    const int tid = threadIdx.x;
+
+    // stage the chunk's rows of the left-environment blocks (zero rows past
+    // the chunk so that every later loop runs over exactly RC rows)
+    const int l0 = bp->l0, l1 = bp->l1;
+    for (int q = l0; q < l1; ++q) {
+        const H3LSrc src = lsrc[q];
+        const int tot = RC * src.ld;
+        const double* __restrict__ lrow = L + src.l_off + (long long)r0 * src.ld;
+        for (int e = tid; e < tot; e += kThreads) lds[src.lds + e] = (e < rows * src.ld) ? lrow[e] : 0.0;
     }
     __syncthreads();
-    const double* __restrict__ L = Lenv + tk.g * Lsz;
-    const double* __restrict__ R = Renv + tk.g * Rsz;
-    const double* __restrict__ cf = coef + (long long)tk.g * nc;
-    const int rows = tk.r1 - tk.r0;
-    const int nt = B.t1 - B.t0;
-    for (int t = threadIdx.x; t < nt; t += kThreads) td[t] = tdesc[B.t0 + t];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int t = 0; t < nt; ++t) {
-            tcols[t] = acc;
-            acc += td[t].ncol;
-        }
-        tcols[nt] = acc;
-    }
-    __syncthreads();
-    // phase A: one thread per T column, all rows of the chunk; the column
-    // descriptors of all the thread's columns are loaded first
-    const int tsum = tcols[nt];
-    constexpr int kColReg = 8;
-    for (int base = 0; base < tsum; base += kThreads * kColReg) {
-        int4 cis[kColReg];
+
+    // phase A: T columns
+    const int c0 = bp->c0, c1 = bp->c1;
+    for (int ci = c0 + tid; ci < c1; ci += kThreads) {
+        const H3Col c = cols[ci];
+        double acc[RC];
 #pragma unroll
-        for (int j = 0; j < kColReg; ++j) {
-            const int idx = base + threadIdx.x + kThreads * j;
-            cis[j] = make_int4(0, 0, 0, 0);
-            if (idx < tsum) {
-                int t = 0;
-                while (tcols[t + 1] <= idx) ++t;
-                cis[j] = colinfo[td[t].ci_off + (idx - tcols[t])];
+        for (int rr = 0; rr < RC; ++rr) acc[rr] = 0.0;
+        const double* __restrict__ xp = x + c.x_off;
+        const double* lp = lds + c.l_lds;
+        int kk = 0;
+        for (; kk + 4 <= c.K; kk += 4) {
+            const double x0 = xp[kk * c.x_ld], x1 = xp[(kk + 1) * c.x_ld];
+            const double x2 = xp[(kk + 2) * c.x_ld], x3 = xp[(kk + 3) * c.x_ld];
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr) {
+                const double* l = lp + rr * c.l_ld + kk;
+                acc[rr] = fma(l[3], x3, fma(l[2], x2, fma(l[1], x1, fma(l[0], x0, acc[rr]))));
             }
         }
+        for (; kk < c.K; ++kk) {
+            const double xv = xp[kk * c.x_ld];
 #pragma unroll
-        for (int j = 0; j < kColReg; ++j) {
-            const int idx = base + threadIdx.x + kThreads * j;
-            if (idx >= tsum) continue;
-            int t = 0;
-            while (tcols[t + 1] <= idx) ++t;
-            const H2T T = td[t];
-            const int col = idx - tcols[t];
-            const int4 ci = cis[j];
-            double acc[kMaxRC];
-#pragma unroll
-            for (int rr = 0; rr < kMaxRC; ++rr) acc[rr] = 0.0;
-            const double* __restrict__ lbase = L + T.l_off + (long long)tk.r0 * T.l_ld + ci.w;
-            for (int kk = 0; kk < ci.z; ++kk) {
-                const double xv = x[ci.x + kk * ci.y];
-#pragma unroll
-                for (int rr = 0; rr < kMaxRC; ++rr)
-                    if (rr < rows) acc[rr] = fma(lbase[(long long)rr * T.l_ld + kk], xv, acc[rr]);
-            }
-#pragma unroll
-            for (int rr = 0; rr < kMaxRC; ++rr)
-                if (rr < rows) Ts[T.colpos * RC + rr * T.ncol + col] = acc[rr];
+            for (int rr = 0; rr < RC; ++rr) acc[rr] = fma(lp[rr * c.l_ld + kk], xv, acc[rr]);
         }
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr) lds[c.t_pos + rr] = acc[rr];
     }
     __syncthreads();
-    // phase B: (sigma, channel) steps with the whole work-group; the right-
-    // environment rows of the next step are fetched into registers while the
-    // current step computes (software pipelining of the global loads)
-    constexpr int kRReg = kH2RMax / kThreads;
-    double ay[kH2Out], an[kH2Out];
-#pragma unroll
-    for (int u = 0; u < kH2Out; ++u) ay[u] = an[u] = 0.0;
-    // flattened step list: step = (sigma, channel)
-    int nsteps = 0;
-    int s_first[5];
-#pragma unroll
+
     for (int sg = 0; sg < 4; ++sg) {
-        s_first[sg] = nsteps;
-        if (tk.o1[sg] > tk.o0[sg]) nsteps += B.ch1[sg] - B.ch0[sg];
-    }
-    s_first[4] = nsteps;
-    auto step_sigma = [&](int st) {
-        int sg = 0;
-        while (sg < 3 && st >= s_first[sg + 1]) ++sg;
-        return sg;
-    };
-    double pre[kRReg];
-    auto fetch = [&](int st) {
-        const int sg = step_sigma(st);
-        const H2Chan C = chans[B.ch0[sg] + (st - s_first[sg])];
-        const int tot = (tk.cy1[sg] - tk.cy0[sg]) * C.K;
-        const double* __restrict__ Rb = R + C.r_off + (long long)tk.cy0[sg] * C.K;
-#pragma unroll
-        for (int j = 0; j < kRReg; ++j) {
-            const int e = threadIdx.x + kThreads * j;
-            pre[j] = (tot <= kH2RMax && e < tot) ? Rb[e] : 0.0;
-        }
-    };
-    if (nsteps > 0) fetch(0);
-    for (int st = 0; st < nsteps; ++st) {
-        const int sg = step_sigma(st);
-        const H2Chan C = chans[B.ch0[sg] + (st - s_first[sg])];
-        const int K = C.K;
-        const int nterm = C.t1 - C.t0;
-        const int cy0 = tk.cy0[sg], ncy = tk.cy1[sg] - tk.cy0[sg];
-        const bool staged = ncy * K <= kH2RMax;  // else read the rows from global memory
-        const double* __restrict__ Rb = R + C.r_off + (long long)cy0 * K;
-        if (threadIdx.x < nterm) {
-            const H2Term term = terms[C.t0 + threadIdx.x];
-            s_pos[threadIdx.x] = td[term.tidx].colpos * RC;
-            s_cf[threadIdx.x] = cf[term.cidx];
-        }
-#pragma unroll
-        for (int j = 0; j < kRReg; ++j) Rs[threadIdx.x + kThreads * j] = pre[j];
-        __syncthreads();
-        if (st + 1 < nsteps) fetch(st + 1);
-        for (int e = threadIdx.x; e < rows * K; e += kThreads) {
-            double v = 0.0;
-            for (int tm = 0; tm < nterm; ++tm) v = fma(s_cf[tm], Ts[s_pos[tm] + e], v);
-            Vs[e] = v;
-        }
-        __syncthreads();
-        const int o0 = tk.o0[sg], o1 = tk.o1[sg];
-#pragma unroll
-        for (int u = 0; u < kH2Out; ++u) {
-            const int o = o0 + threadIdx.x + kThreads * u;
-            if (o < o1) {
-                const int4 yo = yout[o];
-                const double* vr = Vs + (yo.x - tk.r0) * K;
-                const double* rr = staged ? Rs + (yo.y - cy0) * K : Rb + (long long)(yo.y - cy0) * K;
-                double sacc = 0.0;
-                for (int kk = 0; kk < K; ++kk) sacc = fma(vr[kk], rr[kk], sacc);
-                if (C.is_ny) an[u] += sacc;
-                else ay[u] += sacc;
-            }
-        }
-        __syncthreads();
-        // last channel of this sigma: write its outputs and reset
-        if (st + 1 == s_first[sg + 1]) {
-#pragma unroll
-            for (int u = 0; u < kH2Out; ++u) {
-                const int o = o0 + threadIdx.x + kThreads * u;
-                if (o < o1) {
-                    const long long p = (long long)tk.g * n + yout[o].z;
-                    ypart[p] = ay[u];
-                    nypart[p] = an[u];
+        const int p0 = tkp->p0[sg], p1 = tkp->p1[sg];
+        if (p0 == p1) continue;
+        const int s0 = bp->s0[sg], s1 = bp->s1[sg];
+        // V of every right channel of sigma (the W r mixing)
+        for (int si = s0; si < s1; ++si) {
+            const H3Seg S = segs[si];
+            const int ne = S.K * RC;
+            for (int e = tid; e < ne; e += kThreads) {
+                double v = 0.0;
+                for (int t = S.t0; t < S.t1; ++t) {
+                    const H3Term tm = terms[t];
+                    v = fma(cf[tm.cidx], lds[tm.t_base + e], v);
                 }
-                ay[u] = an[u] = 0.0;
+                lds[S.v_off + e] = v;
             }
         }
-    }
-    // outputs of a sigma without channels are zero
+        __syncthreads();
+        // outputs: one group of SL lanes per output column of a piece
+        int items = 0;
+        for (int p = p0; p < p1; ++p) items += pieces[p].nb;
+        int SL = 16;
+        while (SL > 1 && items * SL > kThreads) SL >>= 1;
+        const int sl = tid & (SL - 1);
+        for (int it = tid / SL; it < items; it += kThreads / SL) {
+            int p = p0, b = it;
+            while (b >= pieces[p].nb) {
+                b -= pieces[p].nb;
+                ++p;
+            }
+            const H3Piece P = pieces[p];
+            double ay[RC], an[RC];
 #pragma unroll
-    for (int sg = 0; sg < 4; ++sg) {
-        if (s_first[sg + 1] > s_first[sg]) continue;
-        for (int o = tk.o0[sg] + threadIdx.x; o < tk.o1[sg]; o += kThreads) {
-            const long long p = (long long)tk.g * n + yout[o].z;
-            ypart[p] = 0.0;
-            nypart[p] = 0.0;
+            for (int rr = 0; rr < RC; ++rr) ay[rr] = an[rr] = 0.0;
+            for (int si = s0; si < s1; ++si) {
+                const H3Seg S = segs[si];
+                const double* __restrict__ rp = R + S.r_off + (long long)(P.b0 + b) * S.K;
+                const double* vp = lds + S.v_off;
+                const int K = S.K;
+                if (S.is_ny) {
+                    for (int k = sl; k < K; k += SL) {
+                        const double r = rp[k];
+#pragma unroll
+                        for (int rr = 0; rr < RC; ++rr) an[rr] = fma(vp[k * RC + rr], r, an[rr]);
+                    }
+                } else {
+                    int k = sl;
+                    for (; k + 3 * SL < K; k += 4 * SL) {
+                        const double ra = rp[k], rb = rp[k + SL], rc = rp[k + 2 * SL], rd = rp[k + 3 * SL];
+#pragma unroll
+                        for (int rr = 0; rr < RC; ++rr) {
+                            double v = ay[rr];
+                            v = fma(vp[k * RC + rr], ra, v);
+                            v = fma(vp[(k + SL) * RC + rr], rb, v);
+                            v = fma(vp[(k + 2 * SL) * RC + rr], rc, v);
+                            ay[rr] = fma(vp[(k + 3 * SL) * RC + rr], rd, v);
+                        }
+                    }
+                    for (; k < K; k += SL) {
+                        const double r = rp[k];
+#pragma unroll
+                        for (int rr = 0; rr < RC; ++rr) ay[rr] = fma(vp[k * RC + rr], r, ay[rr]);
+                    }
+                }
+            }
+            for (int o = SL >> 1; o > 0; o >>= 1) {
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr) {
+                    ay[rr] += __shfl_xor(ay[rr], o, 64);
+                    an[rr] += __shfl_xor(an[rr], o, 64);
+                }
+            }
+            if (sl == 0) {
+                const long long base = g * n + P.out_off + b;
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr) {
+                    if (rr >= P.rlo && rr < P.rhi) {
+                        const long long o = base + (long long)(rr - P.rlo) * P.out_ld;
+                        ypart[o] = ay[rr];
+                        nypart[o] = an[rr];
+                    }
+                }
+            }
         }
+        __syncthreads();
     }
 }
 
@@ -863,13 +831,30 @@ void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufS
            const int* map) {
     if (ntasks > 0) hipLaunchKernelGGL(k_tgemm, dim3(ntasks), dim3(kThreads), 0, s, tasks, segs, bufs, coef, map);
 }
-void heff2(hipStream_t s, const H2Task* tasks, int ntasks, const H2Blk* blks, const H2T* tdesc,
-           const H2Chan* chans, const H2Term* terms, const int4* colinfo, const int4* yout, int rows_max,
+void heff3(hipStream_t s, int RC, int lds_doubles, const H3Task* tasks, int ntasks, const H3Blk* blks,
+           const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms, const H3Piece* pieces,
            const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
            const double* coef, int nc, double* ypart, double* nypart, long long n) {
-    if (ntasks > 0)
-        hipLaunchKernelGGL(k_heff2, dim3(ntasks), dim3(kThreads), 0, s, tasks, blks, tdesc, chans, terms, colinfo, yout,
-                           rows_max, Lenv, Lsz, Renv, Rsz, x, coef, nc, ypart, nypart, n);
+    if (ntasks <= 0) return;
+    const size_t shm = size_t(lds_doubles) * sizeof(double);
+#define SPK_HEFF3(R)                                                                                              \
+    case R:                                                                                                       \
+        hipLaunchKernelGGL(k_heff3<R>, dim3(ntasks), dim3(kThreads), shm, s, tasks, blks, cols, lsrc, segs, terms, \
+                           pieces, Lenv, Lsz, Renv, Rsz, x, coef, nc, ypart, nypart, n);                                \
+        break;
+    switch (RC) {
+        SPK_HEFF3(1)
+        SPK_HEFF3(2)
+        SPK_HEFF3(3)
+        SPK_HEFF3(4)
+        SPK_HEFF3(5)
+        SPK_HEFF3(6)
+        SPK_HEFF3(7)
+        SPK_HEFF3(8)
+        default:
+            break;
+    }
+#undef SPK_HEFF3
 }
 void gather(hipStream_t s, const int* map, const double* src, double* dst, long long n) {
     if (n > 0) hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, map, src, dst, n);

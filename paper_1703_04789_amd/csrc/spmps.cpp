@@ -308,19 +308,22 @@ struct SitePlan {
     DArr<int> xmap;
     TList t_left, t_right, t_envl, t_zr, t_envr;
     // fused H_eff x
-    int h_rows = 1;
-    std::vector<spk::H2Task> h_tasks;
-    std::vector<spk::H2Blk> h_blks;
-    std::vector<spk::H2T> h_tdesc;
-    std::vector<spk::H2Chan> h_chans;
-    std::vector<spk::H2Term> h_terms;
-    std::vector<int4> h_colinfo, h_yout;
-    DArr<spk::H2Task> dh_tasks;
-    DArr<spk::H2Blk> dh_blks;
-    DArr<spk::H2T> dh_tdesc;
-    DArr<spk::H2Chan> dh_chans;
-    DArr<spk::H2Term> dh_terms;
-    DArr<int4> dh_colinfo, dh_yout;
+    int h_rows = 1;         // rows per task (RC)
+    int h_lds = 0;          // dynamic LDS per work-group (doubles)
+    std::vector<spk::H3Task> h_tasks;
+    std::vector<spk::H3Blk> h_blks;
+    std::vector<spk::H3Col> h_cols;
+    std::vector<spk::H3LSrc> h_lsrc;
+    std::vector<spk::H3Seg> h_segs;
+    std::vector<spk::H3Term> h_terms;
+    std::vector<spk::H3Piece> h_pieces;
+    DArr<spk::H3Task> dh_tasks;
+    DArr<spk::H3Blk> dh_blks;
+    DArr<spk::H3Col> dh_cols;
+    DArr<spk::H3LSrc> dh_lsrc;
+    DArr<spk::H3Seg> dh_segs;
+    DArr<spk::H3Term> dh_terms;
+    DArr<spk::H3Piece> dh_pieces;
 };
 
 }  // namespace
@@ -1120,6 +1123,9 @@ void build_plan(sp_handle* h, int k) {
 
 // fused H_eff x plan: column descriptors, products per bra block, channels
 // per output sigma, output lists and row-chunk tasks
+// LDS budget of the fused H_eff kernel per work-group (doubles)
+constexpr int kHeffLdsBudget = 9216;
+
 void build_fused(sp_handle* h, int k) {
     SitePlan& P = h->plan[k - 1];
     const int G = h->G;
@@ -1132,94 +1138,74 @@ void build_fused(sp_handle* h, int k) {
     const int lastR = wr - 1;
     std::map<std::array<int, 4>, int> wpos;
     for (int e = 0; e < P.nW; ++e) wpos[P.went[e]] = e;
-    std::vector<int> cioff(bl.nb.size() * 4, -1);
-    for (int j = 0; j < int(bl.nb.size()); ++j)
-        for (int q = 0; q < 4; ++q) {
-            const int jb = br.nblock(bl.nb[j].n + kSigmaN[q]);
-            if (jb < 0) continue;
-            cioff[size_t(j) * 4 + q] = int(P.h_colinfo.size());
-            const NBlock& NB = br.nb[jb];
-            for (int sb = NB.s0; sb < NB.s1; ++sb) {
-                const Sector& SB = br.sec[sb];
-                const int sa = bl.sector(SB.n - kSigmaN[q], SB.m2 - kSigma2M[q]);
-                const int xb = sa >= 0 ? si.find(sa, q) : -1;
-                for (int c = 0; c < SB.dim; ++c) {
-                    if (xb < 0) {
-                        P.h_colinfo.push_back(make_int4(0, 0, 0, 0));
-                    } else {
-                        const XBlk& X = si.blk[xb];
-                        P.h_colinfo.push_back(make_int4(int(X.off + c), X.cols, X.rows, bl.sec[sa].ro));
-                    }
-                }
-            }
-        }
     const int nb = int(bl.nb.size());
-    // per bra block: products, channels, outputs
-    std::vector<std::array<std::vector<int>, 4>> row_first(nb);
-    int tsum_max = 1, kmax = 1;
+
+    // RC-independent description of one bra block
+    struct TCol {
+        int x_off, x_ld, K, src, ro;  // src: local L source, ro: its first column
+    };
+    struct TBlk {
+        int ncol;
+        std::vector<TCol> cols;
+    };
+    struct SegD {
+        long long r_off;
+        int K, is_ny;
+        std::vector<std::pair<int, int>> terms;  // (local T block, coefficient)
+    };
+    struct BlkD {
+        std::vector<std::pair<long long, int>> lsrc;  // (L offset, ld)
+        std::vector<TBlk> T;
+        std::array<std::vector<SegD>, 4> seg;
+        int lsum = 0, tsum = 0, vmax = 0;
+    };
+    std::vector<BlkD> bd(nb);
     for (int i = 0; i < nb; ++i) {
         const NBlock& NA = bl.nb[i];
-        spk::H2Blk B{};
-        B.t0 = int(P.h_tdesc.size());
-        std::map<std::pair<int, int>, int> tloc;  // (c, s') -> local index
-        int colpos = 0;
+        BlkD& D = bd[i];
+        std::map<std::pair<int, int>, int> tloc;  // (c, s') -> local T block
         for (int c = 0; c < wl; ++c) {
             const int e = el.find(c, i);
             if (e < 0) continue;
-            const int j = el.blk[e].j;
+            const EnvBlk& EB = el.blk[e];
+            const int src = int(D.lsrc.size());
+            D.lsrc.push_back({EB.off, EB.cols});
+            D.lsum += EB.cols;
+            const int j = EB.j;
             for (int q = 0; q < 4; ++q) {
-                const int co = cioff[size_t(j) * 4 + q];
-                if (co < 0) continue;
                 const int jb = br.nblock(bl.nb[j].n + kSigmaN[q]);
-                spk::H2T T{};
-                T.l_off = el.blk[e].off;
-                T.l_ld = el.blk[e].cols;
-                T.ci_off = co;
-                T.ncol = br.nb[jb].dim;
-                T.colpos = colpos;
-                colpos += T.ncol;
-                tloc[{c, q}] = int(P.h_tdesc.size()) - B.t0;
-                P.h_tdesc.push_back(T);
+                if (jb < 0) continue;
+                const NBlock& NB = br.nb[jb];
+                TBlk T;
+                T.ncol = NB.dim;
+                for (int sb = NB.s0; sb < NB.s1; ++sb) {
+                    const Sector& SB = br.sec[sb];
+                    const int sa = bl.sector(SB.n - kSigmaN[q], SB.m2 - kSigma2M[q]);
+                    const int xb = sa >= 0 ? si.find(sa, q) : -1;
+                    for (int c2 = 0; c2 < SB.dim; ++c2) {
+                        if (xb < 0) {
+                            T.cols.push_back(TCol{0, 0, 0, src, 0});
+                        } else {
+                            const XBlk& X = si.blk[xb];
+                            SP_REQUIRE(bl.sec[sa].n == bl.nb[j].n, "internal: fused ket sector");
+                            T.cols.push_back(TCol{int(X.off + c2), X.cols, X.rows, src, bl.sec[sa].ro});
+                        }
+                    }
+                }
+                tloc[{c, q}] = int(D.T.size());
+                D.tsum += T.ncol;
+                D.T.push_back(std::move(T));
             }
         }
-        B.t1 = int(P.h_tdesc.size());
-        tsum_max = std::max(tsum_max, colpos);
-        B.maxch = 0;
         for (int sig = 0; sig < 4; ++sig) {
-            B.ch0[sig] = B.ch1[sig] = int(P.h_chans.size());
-            row_first[i][sig].assign(NA.dim + 1, int(P.h_yout.size()));
             const int nbb = br.nblock(NA.n + kSigmaN[sig]);
             if (nbb < 0) continue;
-            for (int r = 0; r < NA.dim; ++r) {
-                row_first[i][sig][r] = int(P.h_yout.size());
-                int sa = NA.s0;
-                while (bl.sec[sa].ro + bl.sec[sa].dim <= r) ++sa;
-                const Sector& SA = bl.sec[sa];
-                const int sb = br.sector(SA.n + kSigmaN[sig], SA.m2 + kSigma2M[sig]);
-                if (sb < 0) continue;
-                const int xb = si.find(sa, sig);
-                SP_REQUIRE(xb >= 0, "internal: missing site block");
-                const XBlk& X = si.blk[xb];
-                const Sector& SB = br.sec[sb];
-                for (int c = 0; c < SB.dim; ++c)
-                    P.h_yout.push_back(make_int4(r, SB.ro + c, int(X.off + (long long)(r - SA.ro) * X.cols + c), 0));
-            }
-            row_first[i][sig][NA.dim] = int(P.h_yout.size());
-            auto add_channel = [&](int re, int is_ny, const std::vector<std::pair<int, int>>& tl) {
+            auto add_seg = [&](int re, int is_ny, const std::vector<std::pair<int, int>>& tl) {
                 if (tl.empty()) return;
                 const EnvBlk& RB = er.blk[re];
-                spk::H2Chan C{};
-                C.r_off = RB.off;
-                C.K = RB.cols;
-                C.t0 = int(P.h_terms.size());
-                for (auto& pr : tl) {
-                    SP_REQUIRE(P.h_tdesc[B.t0 + pr.first].ncol == RB.cols, "internal: fused H_eff particle numbers");
-                    P.h_terms.push_back(spk::H2Term{pr.first, pr.second});
-                }
-                C.t1 = int(P.h_terms.size());
-                C.is_ny = is_ny;
-                P.h_chans.push_back(C);
-                kmax = std::max(kmax, RB.cols);
+                for (auto& pr : tl)
+                    SP_REQUIRE(D.T[pr.first].ncol == RB.cols, "internal: fused H_eff particle numbers");
+                D.seg[sig].push_back(SegD{RB.off, RB.cols, is_ny, tl});
             };
             for (int cp = 0; cp < wr; ++cp) {
                 const int re = er.find(cp, nbb);
@@ -1229,7 +1215,7 @@ void build_fused(sp_handle* h, int k) {
                     auto it = wpos.find({kv.first.first, cp, sig, kv.first.second});
                     if (it != wpos.end()) tl.push_back({kv.second, P.c_cwt(it->second)});
                 }
-                add_channel(re, 0, tl);
+                add_seg(re, 0, tl);
             }
             const int re = er.find(lastR, nbb);
             if (re >= 0) {
@@ -1241,59 +1227,129 @@ void build_fused(sp_handle* h, int k) {
                     SP_REQUIRE(el.blk[el.find(0, i)].j == i, "internal: identity channel must conserve N");
                     tl.push_back({it->second, P.c_gr(sig, q)});
                 }
-                add_channel(re, 1, tl);
+                add_seg(re, 1, tl);
             }
-            B.ch1[sig] = int(P.h_chans.size());
-            B.maxch = std::max(B.maxch, B.ch1[sig] - B.ch0[sig]);
+            int v = 0;
+            for (auto& sd : D.seg[sig]) v += sd.K;
+            D.vmax = std::max(D.vmax, v);
+        }
+    }
+    // rows per task: the largest RC <= 8 whose LDS fits the budget
+    int need1 = 1;
+    for (auto& D : bd) need1 = std::max(need1, D.lsum + D.tsum + D.vmax);
+    const int RC = std::min(spk::kH3MaxRC, kHeffLdsBudget / need1);
+    SP_REQUIRE(RC >= 1, "a particle-number block is too wide for the fused H_eff kernel");
+    P.h_rows = RC;
+    P.h_lds = RC * need1;
+    P.h_blks.clear();
+    P.h_cols.clear();
+    P.h_lsrc.clear();
+    P.h_segs.clear();
+    P.h_terms.clear();
+    P.h_pieces.clear();
+    P.h_tasks.clear();
+    for (int i = 0; i < nb; ++i) {
+        BlkD& D = bd[i];
+        spk::H3Blk B{};
+        B.l0 = int(P.h_lsrc.size());
+        std::vector<int> lds_src(D.lsrc.size());
+        int pos = 0;
+        for (size_t q = 0; q < D.lsrc.size(); ++q) {
+            SP_REQUIRE(D.lsrc[q].first < INT32_MAX, "environment too large for 32-bit offsets");
+            lds_src[q] = pos;
+            P.h_lsrc.push_back(spk::H3LSrc{int(D.lsrc[q].first), D.lsrc[q].second, pos, 0});
+            pos += RC * D.lsrc[q].second;
+        }
+        B.l1 = int(P.h_lsrc.size());
+        B.c0 = int(P.h_cols.size());
+        std::vector<int> tbase(D.T.size());
+        for (size_t t = 0; t < D.T.size(); ++t) {
+            tbase[t] = pos;
+            for (int c2 = 0; c2 < D.T[t].ncol; ++c2) {
+                const TCol& tc = D.T[t].cols[c2];
+                P.h_cols.push_back(spk::H3Col{tc.x_off, tc.x_ld, tc.K, lds_src[tc.src] + tc.ro,
+                                              D.lsrc[tc.src].second, pos + c2 * RC, 0, 0});
+            }
+            pos += RC * D.T[t].ncol;
+        }
+        B.c1 = int(P.h_cols.size());
+        const int vbase = pos;
+        for (int sig = 0; sig < 4; ++sig) {
+            B.s0[sig] = int(P.h_segs.size());
+            int v = vbase;
+            for (auto& sd : D.seg[sig]) {
+                SP_REQUIRE(sd.r_off < INT32_MAX, "environment too large for 32-bit offsets");
+                spk::H3Seg S{};
+                S.r_off = int(sd.r_off);
+                S.K = sd.K;
+                S.v_off = v;
+                S.t0 = int(P.h_terms.size());
+                for (auto& pr : sd.terms) P.h_terms.push_back(spk::H3Term{tbase[pr.first], pr.second});
+                S.t1 = int(P.h_terms.size());
+                S.is_ny = sd.is_ny;
+                P.h_segs.push_back(S);
+                v += RC * sd.K;
+            }
+            B.s1[sig] = int(P.h_segs.size());
         }
         P.h_blks.push_back(B);
     }
-    // rows per chunk from the LDS budgets
-    int RC = std::min({8, spk::kH2TMax / tsum_max, spk::kH2VMax / kmax});
-    SP_REQUIRE(RC >= 1, "a particle-number block is too wide for the fused H_eff kernel");
-    for (int i = 0; i < nb; ++i)
-        SP_REQUIRE(P.h_blks[i].t1 - P.h_blks[i].t0 <= spk::kH2TBlk, "too many products per block for the fused kernel");
-    auto cy_range = [&](int i, int sig, int r0, int r1, int& cy0, int& cy1) {
-        cy0 = INT32_MAX;
-        cy1 = 0;
-        for (int o = row_first[i][sig][r0]; o < row_first[i][sig][r1]; ++o) {
-            cy0 = std::min(cy0, P.h_yout[o].y);
-            cy1 = std::max(cy1, P.h_yout[o].y + 1);
-        }
-        if (cy1 <= cy0) cy0 = cy1 = 0;
-    };
-    for (;;) {  // outputs per sigma and chunk must fit the threads and the staged rows
-        bool ok = true;
-        for (int i = 0; i < nb && ok; ++i)
-            for (int sig = 0; sig < 4 && ok; ++sig)
-                for (int r0 = 0; r0 < bl.nb[i].dim; r0 += RC) {
-                    const int r1 = std::min(bl.nb[i].dim, r0 + RC);
-                    int cy0, cy1;
-                    cy_range(i, sig, r0, r1, cy0, cy1);
-                    if (row_first[i][sig][r1] - row_first[i][sig][r0] > 256 * spk::kH2Out) ok = false;
+    // tasks of one quadrature point: chunks of RC rows per bra block, with the
+    // output pieces (rows of one left sector x the columns its sigma allows)
+    std::vector<spk::H3Task> one;
+    for (int i = 0; i < nb; ++i) {
+        const NBlock& NA = bl.nb[i];
+        for (int r0 = 0; r0 < NA.dim; r0 += RC) {
+            spk::H3Task t{};
+            t.g = 0;
+            t.blk = i;
+            t.r0 = r0;
+            t.rows = std::min(RC, NA.dim - r0);
+            bool any = false;
+            for (int sig = 0; sig < 4; ++sig) {
+                t.p0[sig] = t.p1[sig] = int(P.h_pieces.size());
+                if (br.nblock(NA.n + kSigmaN[sig]) < 0) continue;
+                for (int sa = NA.s0; sa < NA.s1; ++sa) {
+                    const Sector& SA = bl.sec[sa];
+                    const int lo = std::max(r0, SA.ro), hi = std::min(r0 + t.rows, SA.ro + SA.dim);
+                    if (lo >= hi) continue;
+                    const int sb = br.sector(SA.n + kSigmaN[sig], SA.m2 + kSigma2M[sig]);
+                    if (sb < 0) continue;
+                    const int xb = si.find(sa, sig);
+                    SP_REQUIRE(xb >= 0, "internal: missing site block");
+                    const XBlk& X = si.blk[xb];
+                    spk::H3Piece pc{};
+                    pc.rlo = lo - r0;
+                    pc.rhi = hi - r0;
+                    pc.b0 = br.sec[sb].ro;
+                    pc.nb = br.sec[sb].dim;
+                    pc.out_off = int(X.off + (long long)(lo - SA.ro) * X.cols);
+                    pc.out_ld = X.cols;
+                    P.h_pieces.push_back(pc);
                 }
-        if (ok) break;
-        SP_REQUIRE(RC > 1, "too many outputs per row for the fused H_eff kernel");
-        --RC;
-    }
-    P.h_rows = RC;
-    for (int g = 0; g < G; ++g)
-        for (int i = 0; i < nb; ++i)
-            for (int r0 = 0; r0 < bl.nb[i].dim; r0 += RC) {
-                spk::H2Task t{};
-                t.g = g;
-                t.blk = i;
-                t.r0 = r0;
-                t.r1 = std::min(bl.nb[i].dim, r0 + RC);
-                bool any = false;
-                for (int sig = 0; sig < 4; ++sig) {
-                    t.o0[sig] = row_first[i][sig][r0];
-                    t.o1[sig] = row_first[i][sig][t.r1];
-                    cy_range(i, sig, r0, t.r1, t.cy0[sig], t.cy1[sig]);
-                    any = any || t.o1[sig] > t.o0[sig];
-                }
-                if (any) P.h_tasks.push_back(t);
+                t.p1[sig] = int(P.h_pieces.size());
+                any = any || t.p1[sig] > t.p0[sig];
             }
+            if (any) one.push_back(t);
+        }
+    }
+    // all quadrature points, dealt to the eight XCDs in contiguous runs of the
+    // g-ordered list (work-group w runs on XCD w mod 8), so that each XCD's L2
+    // holds the environments of about G/8 quadrature points
+    std::vector<spk::H3Task> all;
+    for (int g = 0; g < G; ++g)
+        for (spk::H3Task t : one) {
+            t.g = g;
+            all.push_back(t);
+        }
+    const int T = int(all.size()), nq = 8;
+    const int rounds = (T + nq - 1) / nq;
+    P.h_tasks.assign(size_t(rounds) * nq, spk::H3Task{0, -1, 0, 0, {0, 0, 0, 0}, {0, 0, 0, 0}});
+    for (int q = 0; q < nq; ++q) {
+        const int a0 = int((long long)T * q / nq), a1 = int((long long)T * (q + 1) / nq);
+        for (int r = 0; r < a1 - a0; ++r) P.h_tasks[size_t(r) * nq + q] = all[a0 + r];
+    }
+    while (!P.h_tasks.empty() && P.h_tasks.back().blk < 0) P.h_tasks.pop_back();
 }
 
 void upload_plan(sp_handle* h, int k) {
@@ -1325,11 +1381,11 @@ void upload_plan(sp_handle* h, int k) {
     P.t_envr.upload(s);
     P.dh_tasks.upload(P.h_tasks, s);
     P.dh_blks.upload(P.h_blks, s);
-    P.dh_tdesc.upload(P.h_tdesc, s);
-    P.dh_chans.upload(P.h_chans, s);
+    P.dh_cols.upload(P.h_cols, s);
+    P.dh_lsrc.upload(P.h_lsrc, s);
+    P.dh_segs.upload(P.h_segs, s);
     P.dh_terms.upload(P.h_terms, s);
-    P.dh_colinfo.upload(P.h_colinfo, s);
-    P.dh_yout.upload(P.h_yout, s);
+    P.dh_pieces.upload(P.h_pieces, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1444,59 +1500,64 @@ void validate_plans(sp_handle* h) {
         // fused H_eff lists
         {
             const long long Lg = h->env[k - 1].size, Rg = h->env[k].size;
-            const long long nci = (long long)P.h_colinfo.size(), nyo = (long long)P.h_yout.size();
-            const int RC = P.h_rows;
-            if (nyo != xs) throw SpError(SP_EINVAL, "internal: fused outputs do not cover the site");
-            std::vector<char> seen(xs, 0);
-            for (const int4& y : P.h_yout) {
-                check_span(y.z, y.z, xs, "fused output index");
-                if (seen[y.z]++) throw SpError(SP_EINVAL, "internal: fused output written twice");
-            }
-            for (const spk::H2Task& t : P.h_tasks) {
-                if (t.g < 0 || t.g >= h->G || t.blk < 0 || t.blk >= int(P.h_blks.size()) || t.r1 <= t.r0 ||
-                    t.r1 - t.r0 > RC)
+            const int RC = P.h_rows, lmax = P.h_lds;
+            const int nblk = int(P.h_blks.size());
+            auto in_lds = [&](long long a0, long long a1, const char* what) { check_span(a0, a1, lmax, what); };
+            if (RC < 1 || RC > spk::kH3MaxRC || lmax > kHeffLdsBudget) throw SpError(SP_EINVAL, "internal: fused shape");
+            std::vector<int> seen(size_t(xs) * h->G, 0);
+            for (const spk::H3Task& t : P.h_tasks) {
+                if (t.blk < 0) continue;
+                if (t.g < 0 || t.g >= h->G || t.blk >= nblk || t.rows < 1 || t.rows > RC)
                     throw SpError(SP_EINVAL, "internal: fused task");
-                const spk::H2Blk& B = P.h_blks[t.blk];
-                for (int tt = B.t0; tt < B.t1; ++tt) {
-                    const spk::H2T& T = P.h_tdesc[tt];
-                    if ((long long)(T.colpos + T.ncol) * RC > spk::kH2TMax) throw SpError(SP_EINVAL, "internal: fused T exceeds LDS");
-                    check_span(T.ci_off, T.ci_off + T.ncol - 1, nci, "fused column descriptors");
-                    for (int col = 0; col < T.ncol; ++col) {
-                        const int4 ci = P.h_colinfo[T.ci_off + col];
-                        if (ci.z <= 0) continue;
-                        check_span(ci.x, ci.x + (long long)(ci.z - 1) * ci.y, xs, "fused x column");
-                        if (ci.w + ci.z > T.l_ld) throw SpError(SP_EINVAL, "internal: fused L columns");
-                        check_span(T.l_off + (long long)t.r0 * T.l_ld + ci.w,
-                                   T.l_off + (long long)(t.r1 - 1) * T.l_ld + ci.w + ci.z - 1, Lg, "fused L rows");
-                    }
+                const spk::H3Blk& B = P.h_blks[t.blk];
+                check_span(B.l0, B.l1 - 1, (long long)P.h_lsrc.size(), "fused L sources");
+                for (int q = B.l0; q < B.l1; ++q) {
+                    const spk::H3LSrc& L = P.h_lsrc[q];
+                    check_span(L.l_off + (long long)t.r0 * L.ld, L.l_off + (long long)(t.r0 + t.rows) * L.ld - 1, Lg,
+                               "fused L rows");
+                    in_lds(L.lds, L.lds + (long long)RC * L.ld - 1, "fused staged L");
                 }
-                if (t.r1 - t.r0 > 8 || B.t1 - B.t0 > spk::kH2TBlk) throw SpError(SP_EINVAL, "internal: fused task shape");
+                if (B.c1 > B.c0) check_span(B.c0, B.c1 - 1, (long long)P.h_cols.size(), "fused columns");
+                for (int ci = B.c0; ci < B.c1; ++ci) {
+                    const spk::H3Col& c = P.h_cols[ci];
+                    if (c.K > 0) {
+                        check_span(c.x_off, c.x_off + (long long)(c.K - 1) * c.x_ld, xs, "fused x column");
+                        in_lds(c.l_lds, c.l_lds + (long long)(RC - 1) * c.l_ld + c.K - 1, "fused L entries");
+                    }
+                    in_lds(c.t_pos, c.t_pos + RC - 1, "fused T column");
+                }
                 for (int sig = 0; sig < 4; ++sig) {
-                    if (t.o1[sig] - t.o0[sig] > 256 * spk::kH2Out) throw SpError(SP_EINVAL, "internal: fused outputs per thread");
-                    if (t.o1[sig] > t.o0[sig]) check_span(t.o0[sig], t.o1[sig] - 1, nyo, "fused task outputs");
-                    for (int c = B.ch0[sig]; c < B.ch1[sig]; ++c) {
-                        const spk::H2Chan& C = P.h_chans[c];
-                        if ((long long)(t.r1 - t.r0) * C.K > spk::kH2VMax) throw SpError(SP_EINVAL, "internal: fused V exceeds LDS");
-                        if (C.t1 - C.t0 > 16) throw SpError(SP_EINVAL, "internal: fused channel has too many terms");
-                        if (t.o1[sig] > t.o0[sig])
-                            check_span(C.r_off + (long long)t.cy0[sig] * C.K, C.r_off + (long long)t.cy1[sig] * C.K - 1,
-                                       Rg, "fused staged R rows");
-                        for (int tm = C.t0; tm < C.t1; ++tm) {
-                            const spk::H2Term& term = P.h_terms[tm];
-                            if (term.tidx < 0 || B.t0 + term.tidx >= B.t1) throw SpError(SP_EINVAL, "internal: fused term");
-                            if (P.h_tdesc[B.t0 + term.tidx].ncol != C.K) throw SpError(SP_EINVAL, "internal: fused term width");
-                            check_span(term.cidx, term.cidx, P.nc, "fused coefficient");
+                    if (B.s1[sig] > B.s0[sig]) check_span(B.s0[sig], B.s1[sig] - 1, (long long)P.h_segs.size(), "fused segments");
+                    if (t.p1[sig] > t.p0[sig]) check_span(t.p0[sig], t.p1[sig] - 1, (long long)P.h_pieces.size(), "fused pieces");
+                    for (int p = t.p0[sig]; p < t.p1[sig]; ++p) {
+                        const spk::H3Piece& pc = P.h_pieces[p];
+                        if (pc.rlo < 0 || pc.rhi > t.rows || pc.rlo >= pc.rhi || pc.nb < 1)
+                            throw SpError(SP_EINVAL, "internal: fused piece");
+                        for (int rr = pc.rlo; rr < pc.rhi; ++rr)
+                            for (int b = 0; b < pc.nb; ++b) {
+                                const long long o = pc.out_off + (long long)(rr - pc.rlo) * pc.out_ld + b;
+                                check_span(o, o, xs, "fused output");
+                                if (seen[size_t(t.g) * xs + o]++) throw SpError(SP_EINVAL, "internal: fused output written twice");
+                            }
+                        for (int si = B.s0[sig]; si < B.s1[sig]; ++si) {
+                            const spk::H3Seg& S = P.h_segs[si];
+                            check_span(S.r_off + (long long)pc.b0 * S.K, S.r_off + (long long)(pc.b0 + pc.nb) * S.K - 1, Rg,
+                                       "fused R rows");
                         }
-                        for (int o = t.o0[sig]; o < t.o1[sig]; ++o) {
-                            const int4 y = P.h_yout[o];
-                            if (y.x < t.r0 || y.x >= t.r1 || y.y < t.cy0[sig] || y.y >= t.cy1[sig])
-                                throw SpError(SP_EINVAL, "internal: fused output row");
-                            check_span(C.r_off + (long long)y.y * C.K, C.r_off + (long long)y.y * C.K + C.K - 1, Rg,
-                                       "fused R row");
+                    }
+                    for (int si = B.s0[sig]; si < B.s1[sig]; ++si) {
+                        const spk::H3Seg& S = P.h_segs[si];
+                        in_lds(S.v_off, S.v_off + (long long)RC * S.K - 1, "fused V");
+                        if (S.t1 > S.t0) check_span(S.t0, S.t1 - 1, (long long)P.h_terms.size(), "fused terms");
+                        for (int tm = S.t0; tm < S.t1; ++tm) {
+                            in_lds(P.h_terms[tm].t_base, P.h_terms[tm].t_base + (long long)RC * S.K - 1, "fused T block");
+                            check_span(P.h_terms[tm].cidx, P.h_terms[tm].cidx, P.nc, "fused coefficient");
                         }
                     }
                 }
             }
+            for (long long o = 0; o < (long long)xs * h->G; ++o)
+                if (seen[o] != 1) throw SpError(SP_EINVAL, "internal: fused outputs do not cover the site");
         }
         if (k < h->L) {
             Sizes a{};
@@ -1584,8 +1645,8 @@ bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, boo
         return false;
     }
     const int n = int(h->sites[k - 1].size);
-    spk::heff2(s, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_tdesc.p, P.dh_chans.p, P.dh_terms.p,
-               P.dh_colinfo.p, P.dh_yout.p, P.h_rows, h->envL[k - 1].p, h->env[k - 1].size, h->envR[k].p,
+    spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_cols.p, P.dh_lsrc.p,
+               P.dh_segs.p, P.dh_terms.p, P.dh_pieces.p, h->envL[k - 1].p, h->env[k - 1].size, h->envR[k].p,
                h->env[k].size, x, P.coef.p, P.nc, h->ypart.p, h->nypart.p, n);
     if (defer_gsum) return true;
     spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
@@ -2256,8 +2317,8 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
             if (plain) {
                 P.p1.launch(s, b, P.coef.p);
             } else {
-                spk::heff2(s, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_tdesc.p, P.dh_chans.p,
-                           P.dh_terms.p, P.dh_colinfo.p, P.dh_yout.p, P.h_rows, h->envL[site - 1].p,
+                spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_cols.p,
+                           P.dh_lsrc.p, P.dh_segs.p, P.dh_terms.p, P.dh_pieces.p, h->envL[site - 1].p,
                            h->env[site - 1].size, h->envR[site].p, h->env[site].size, x, P.coef.p, P.nc, h->ypart.p,
                            h->nypart.p, n);
             }
