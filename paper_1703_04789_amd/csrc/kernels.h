@@ -177,10 +177,14 @@ void dav_cgs(hipStream_t s, const double* V, long long ld, int m_sub, int m_dot,
 // vout = t / sqrt(sum part), tnorm = sqrt(sum part)
 void dav_normalize(hipStream_t s, const double* part, int nchunk, const double* t, double* vout, int n,
                    double* tnorm);
-// per chunk: V_j.HV_m (j<=m), V_j.NV_m (j<=m), HV_j.V_m (j<m), NV_j.V_m (j<m);
-// with ypart != nullptr, HV_m and NV_m are first formed as the sums over the
-// G quadrature partials (stride gstride) and stored
-void dav_gram(hipStream_t s, const double* V, double* HV, double* NV, long long ld, int m, int n,
-              const double* ypart, const double* nypart, long long gstride, int G, double* part);
+// Gram rows of the new vector m, per chunk: V_j.HV_m (j<=m), V_j.NV_m (j<=m),
+// HV_j.V_m (j<m), NV_j.V_m (j<m).  With t != nullptr, V_m = t / |t| where
+// |t|^2 = the sum of the npn partials pn (|t| -> *tnorm) and H_eff t, N_eff t
+// are scaled by 1/|t| (t needs ypart); with ypart != nullptr they are the
+// sums over the G quadrature partials (stride gstride) and V_m (if t), HV_m
+// and NV_m are stored, else they are read from HV_m, NV_m.
+void dav_gram(hipStream_t s, double* V, double* HV, double* NV, long long ld, int m, int n, const double* t,
+              const double* pn, int npn, double* tnorm, const double* ypart, const double* nypart, long long gstride,
+              int G, double* part);
 
 }  // namespace spk

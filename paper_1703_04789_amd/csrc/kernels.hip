@@ -540,11 +540,15 @@ __global__ __launch_bounds__(kThreads) void k_gsum2(const double* __restrict__ p
 }
 
 // ---- grid-parallel Davidson passes ----------------------------------------
-// One element per thread, kDavChunk = kThreads elements per work-group.
-// Loads over the subspace index are batched eight vectors at a time so that
-// a wave keeps many independent loads in flight.
+// A work-group owns kDavChunk consecutive elements.  The Ritz and CGS passes
+// run 1024 threads per work-group: four groups of 256 threads split the
+// subspace index, each thread loading all of its vectors in one batch, and
+// their partial sums are added in LDS in a fixed order.
 
-static_assert(kDavChunk == kThreads, "one element per thread");
+constexpr int kDavWide = 1024;
+constexpr int kDavGroups = kDavWide / kDavChunk;  // 4
+constexpr int kDavWaves = kDavWide / 64;          // 16
+static_assert(kDavChunk == kThreads, "one element per thread of a group");
 constexpr int kBatch = 8;
 
 __device__ inline double wave_sum(double v) {
@@ -554,8 +558,9 @@ __device__ inline double wave_sum(double v) {
 }
 
 // out[j] = sum over q < nchunk of part[q * stride + j], for j < m.  Wave w
-// adds the chunks q = w mod 4 (ascending), then the four wave sums are added
-// in wave order: a fixed order, so the result is deterministic.
+// of NW adds the chunks q = w mod NW (ascending), then the NW wave sums are
+// added in wave order: a fixed order, so the result is deterministic.
+template <int NW>
 __device__ inline void reduce_partials(const double* __restrict__ part, int nchunk, int stride, int m,
                                        double (*wred)[64], double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -564,28 +569,34 @@ __device__ inline void reduce_partials(const double* __restrict__ part, int nchu
         double acc = 0.0;
         if (j < m) {
             int q = wave;
-            for (; q + 12 < nchunk; q += 16) {
+            for (; q + 3 * NW < nchunk; q += 4 * NW) {
                 const double p0 = part[(long long)q * stride + j];
-                const double p1 = part[(long long)(q + 4) * stride + j];
-                const double p2 = part[(long long)(q + 8) * stride + j];
-                const double p3 = part[(long long)(q + 12) * stride + j];
+                const double p1 = part[(long long)(q + NW) * stride + j];
+                const double p2 = part[(long long)(q + 2 * NW) * stride + j];
+                const double p3 = part[(long long)(q + 3 * NW) * stride + j];
                 acc += p0;
                 acc += p1;
                 acc += p2;
                 acc += p3;
             }
-            for (; q < nchunk; q += 4) acc += part[(long long)q * stride + j];
+            for (; q < nchunk; q += NW) acc += part[(long long)q * stride + j];
         }
         wred[wave][lane] = acc;
         __syncthreads();
-        if (threadIdx.x < 64 && j < m) out[j] = (wred[0][lane] + wred[1][lane]) + (wred[2][lane] + wred[3][lane]);
+        if (threadIdx.x < 64 && j < m) {
+            double r = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) r += wred[w][lane];
+            out[j] = r;
+        }
         __syncthreads();
     }
 }
 
 // out[j] = sum over the chunk of src_j[e] w[e] for j < m, src_j = base + j ld,
-// with w staged in LDS (ws, kDavChunk values).  Wave w takes j = w mod 4, four
-// vectors per pass (16 loads in flight per lane).
+// with w staged in LDS (ws, kDavChunk values).  Wave w of NW takes
+// j = w mod NW, four vectors per pass (16 loads in flight per lane).
+template <int NW>
 __device__ inline void chunk_dots(const double* __restrict__ base, long long ld, int m, int e0, int n,
                                   const double* ws, double* __restrict__ out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -593,12 +604,12 @@ __device__ inline void chunk_dots(const double* __restrict__ base, long long ld,
     double wv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) wv[q] = ws[lane + 64 * q];
-    for (int j = wave; j < m; j += 16) {
+    for (int j = wave; j < m; j += 4 * NW) {
         double acc[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             acc[u] = 0.0;
-            const int jj = j + 4 * u;
+            const int jj = j + NW * u;
             if (jj < m) {
                 const double* __restrict__ src = base + (long long)jj * ld + e0;
                 double v[4];
@@ -611,23 +622,20 @@ __device__ inline void chunk_dots(const double* __restrict__ base, long long ld,
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const double r = wave_sum(acc[u]);
-            if (lane == 0 && j + 4 * u < m) out[j + 4 * u] = r;
+            if (lane == 0 && j + NW * u < m) out[j + NW * u] = r;
         }
     }
 }
 
-// sum of a block-wide value, broadcast to every thread (fixed order)
-__device__ inline double chunk_sum(double v, double* wsum) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    v = wave_sum(v);
-    if (lane == 0) wsum[wave] = v;
-    __syncthreads();
-    const double r = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-    __syncthreads();
-    return r;
+// the subspace range [j0, j1) of thread group jg when m vectors are split
+// over kDavGroups groups
+__device__ inline void group_range(int m, int jg, int& j0, int& j1) {
+    const int per = (m + kDavGroups - 1) / kDavGroups;
+    j0 = min(m, jg * per);
+    j1 = min(m, j0 + per);
 }
 
-__global__ __launch_bounds__(kThreads) void k_dav_ritz(const double* __restrict__ V, const double* __restrict__ HV,
+__global__ __launch_bounds__(kDavWide) void k_dav_ritz(const double* __restrict__ V, const double* __restrict__ HV,
                                                          const double* __restrict__ NV, long long ld, int m,
                                                          const double* __restrict__ aq,
                                                          const double* __restrict__ dh,
@@ -635,99 +643,133 @@ __global__ __launch_bounds__(kThreads) void k_dav_ritz(const double* __restrict_
                                                          double* __restrict__ x, double* __restrict__ t,
                                                          double* __restrict__ part_x, double* __restrict__ part_c) {
     __shared__ double sa[kDavMaxVec + 1];
+    __shared__ double red[3][kDavGroups][kDavChunk];
     __shared__ double ts[kDavChunk];
     __shared__ double wsum[4][3];
-    for (int j = threadIdx.x; j <= m; j += kThreads) sa[j] = aq[j];
+    for (int j = threadIdx.x; j <= m; j += kDavWide) sa[j] = aq[j];
     __syncthreads();
     const double theta = sa[m];
+    const int el = threadIdx.x & (kDavChunk - 1), jg = threadIdx.x / kDavChunk;
     const int e0 = blockIdx.x * kDavChunk;
-    const int e = e0 + threadIdx.x;
-    double tv = 0.0, xx = 0.0, uu = 0.0, xn = 0.0;
-    if (e < n) {
+    const int e = e0 + el;
+    {
         double xv = 0.0, hv = 0.0, nv = 0.0;
-        int j = 0;
-        for (; j + kBatch <= m; j += kBatch) {
-            double v[kBatch], h[kBatch], q[kBatch];
+        if (e < n) {
+            int j0, j1;
+            group_range(m, jg, j0, j1);
+            int j = j0;
+            for (; j + kBatch <= j1; j += kBatch) {
+                double v[kBatch], h[kBatch], q[kBatch];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const long long o = (long long)(j + u) * ld + e;
-                v[u] = V[o];
-                h[u] = HV[o];
-                q[u] = NV[o];
+                for (int u = 0; u < kBatch; ++u) {
+                    const long long o = (long long)(j + u) * ld + e;
+                    v[u] = V[o];
+                    h[u] = HV[o];
+                    q[u] = NV[o];
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    xv = fma(sa[j + u], v[u], xv);
+                    hv = fma(sa[j + u], h[u], hv);
+                    nv = fma(sa[j + u], q[u], nv);
+                }
             }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                xv = fma(sa[j + u], v[u], xv);
-                hv = fma(sa[j + u], h[u], hv);
-                nv = fma(sa[j + u], q[u], nv);
+            for (; j < j1; ++j) {
+                const long long o = (long long)j * ld + e;
+                xv = fma(sa[j], V[o], xv);
+                hv = fma(sa[j], HV[o], hv);
+                nv = fma(sa[j], NV[o], nv);
             }
         }
-        for (; j < m; ++j) {
-            const long long o = (long long)j * ld + e;
-            xv = fma(sa[j], V[o], xv);
-            hv = fma(sa[j], HV[o], hv);
-            nv = fma(sa[j], NV[o], nv);
-        }
-        const double u = hv - theta * nv;
-        double den = dh[e] - theta * dn[e];
-        if (fabs(den) < floor_) den = (den < 0.0) ? -floor_ : floor_;
-        tv = -u / den;
-        x[e] = xv;
-        t[e] = tv;
-        xx = xv * xv;
-        uu = u * u;
-        xn = xv * nv;
+        red[0][jg][el] = xv;
+        red[1][jg][el] = hv;
+        red[2][jg][el] = nv;
     }
-    ts[threadIdx.x] = tv;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    xx = wave_sum(xx);
-    uu = wave_sum(uu);
-    xn = wave_sum(xn);
-    if (lane == 0) {
-        wsum[wave][0] = xx;
-        wsum[wave][1] = uu;
-        wsum[wave][2] = xn;
+    __syncthreads();
+    if (jg == 0) {
+        double tv = 0.0, xx = 0.0, uu = 0.0, xn = 0.0;
+        if (e < n) {
+            const double xv = (red[0][0][el] + red[0][1][el]) + (red[0][2][el] + red[0][3][el]);
+            const double hv = (red[1][0][el] + red[1][1][el]) + (red[1][2][el] + red[1][3][el]);
+            const double nv = (red[2][0][el] + red[2][1][el]) + (red[2][2][el] + red[2][3][el]);
+            const double u = hv - theta * nv;
+            double den = dh[e] - theta * dn[e];
+            if (fabs(den) < floor_) den = (den < 0.0) ? -floor_ : floor_;
+            tv = -u / den;
+            x[e] = xv;
+            t[e] = tv;
+            xx = xv * xv;
+            uu = u * u;
+            xn = xv * nv;
+        }
+        ts[el] = tv;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        xx = wave_sum(xx);
+        uu = wave_sum(uu);
+        xn = wave_sum(xn);
+        if (lane == 0) {
+            wsum[wave][0] = xx;
+            wsum[wave][1] = uu;
+            wsum[wave][2] = xn;
+        }
     }
     __syncthreads();
     if (threadIdx.x < 3) {
         const int c = threadIdx.x;
         part_x[3 * blockIdx.x + c] = (wsum[0][c] + wsum[1][c]) + (wsum[2][c] + wsum[3][c]);
     }
-    chunk_dots(V, ld, m, e0, n, ts, part_c + (long long)blockIdx.x * m);
+    chunk_dots<kDavWaves>(V, ld, m, e0, n, ts, part_c + (long long)blockIdx.x * m);
 }
 
-__global__ __launch_bounds__(kThreads) void k_dav_cgs(const double* __restrict__ V, long long ld, int m,
+__global__ __launch_bounds__(kDavWide) void k_dav_cgs(const double* __restrict__ V, long long ld, int m,
                                                         int m_dot, const double* __restrict__ part_in, int nchunk,
                                                         double* __restrict__ t, int n,
                                                         double* __restrict__ part_out, int mode) {
     __shared__ double c[kDavMaxVec];
-    __shared__ double wred[4][64];
+    __shared__ double wred[kDavWaves][64];
+    __shared__ double red[kDavGroups][kDavChunk];
     __shared__ double ts[kDavChunk];
     __shared__ double wsum[4];
-    reduce_partials(part_in, nchunk, m, m, wred, c);
+    reduce_partials<kDavWaves>(part_in, nchunk, m, m, wred, c);
+    const int el = threadIdx.x & (kDavChunk - 1), jg = threadIdx.x / kDavChunk;
     const int e0 = blockIdx.x * kDavChunk;
-    const int e = e0 + threadIdx.x;
-    double v = 0.0;
-    if (e < n) {
-        v = t[e];
-        int j = 0;
-        for (; j + kBatch <= m; j += kBatch) {
-            double w[kBatch];
+    const int e = e0 + el;
+    {
+        double s = 0.0;
+        if (e < n) {
+            int j0, j1;
+            group_range(m, jg, j0, j1);
+            int j = j0;
+            for (; j + kBatch <= j1; j += kBatch) {
+                double w[kBatch];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) w[u] = V[(long long)(j + u) * ld + e];
+                for (int u = 0; u < kBatch; ++u) w[u] = V[(long long)(j + u) * ld + e];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) v = fma(-c[j + u], w[u], v);
+                for (int u = 0; u < kBatch; ++u) s = fma(c[j + u], w[u], s);
+            }
+            for (; j < j1; ++j) s = fma(c[j], V[(long long)j * ld + e], s);
         }
-        for (; j < m; ++j) v = fma(-c[j], V[(long long)j * ld + e], v);
-        t[e] = v;
+        red[jg][el] = s;
+    }
+    __syncthreads();
+    double v = 0.0;
+    if (jg == 0) {
+        if (e < n) {
+            v = t[e] - ((red[0][el] + red[1][el]) + (red[2][el] + red[3][el]));
+            t[e] = v;
+        }
+        ts[el] = v;
     }
     if (mode == 0) {
-        ts[threadIdx.x] = v;
         __syncthreads();
-        chunk_dots(V, ld, m_dot, e0, n, ts, part_out + (long long)blockIdx.x * m_dot);
+        chunk_dots<kDavWaves>(V, ld, m_dot, e0, n, ts, part_out + (long long)blockIdx.x * m_dot);
     } else {
-        const double ss = chunk_sum(v * v, wsum);
-        if (threadIdx.x == 0) part_out[blockIdx.x] = ss;
+        // norm partial (the first four waves hold the chunk)
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        double ss = wave_sum(v * v);
+        if (jg == 0 && lane == 0) wsum[wave] = ss;
+        __syncthreads();
+        if (threadIdx.x == 0) part_out[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
     }
 }
 
@@ -737,7 +779,7 @@ __global__ __launch_bounds__(kThreads) void k_dav_normalize(const double* __rest
                                                               double* __restrict__ tnorm) {
     __shared__ double wred[4][64];
     __shared__ double tot[1];
-    reduce_partials(part, nchunk, 1, 1, wred, tot);
+    reduce_partials<4>(part, nchunk, 1, 1, wred, tot);
     const double nrm = sqrt(tot[0]);
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
     const int e = blockIdx.x * kDavChunk + threadIdx.x;
@@ -745,46 +787,84 @@ __global__ __launch_bounds__(kThreads) void k_dav_normalize(const double* __rest
     if (blockIdx.x == 0 && threadIdx.x == 0) *tnorm = nrm;
 }
 
-// Gram rows of the new vector m.  With ypart != nullptr the quadrature
-// partial sums of H_eff v_m and N_eff v_m are added here first (ascending g)
-// and written to HV_m and NV_m by the work-groups with blockIdx.y == 0.
-__global__ __launch_bounds__(kThreads) void k_dav_gram(const double* __restrict__ V, double* __restrict__ HV,
+// Gram rows of the new vector m.  With t != nullptr the new vector is
+// t / |t| (|t|^2 = the sum of the nchunk partials pn, written to *tnorm): the
+// work-groups with blockIdx.y == 0 store it as V_m, and H_eff t, N_eff t are
+// scaled by 1/|t| the same way (H_eff is linear).  With ypart != nullptr
+// H_eff t and N_eff t are the sums over the G quadrature partials (ascending
+// g) and stored, scaled, in HV_m, NV_m; else (t must then be nullptr) they
+// are read from HV_m, NV_m as they are.
+__global__ __launch_bounds__(kThreads) void k_dav_gram(double* __restrict__ V, double* __restrict__ HV,
                                                          double* __restrict__ NV, long long ld, int m, int n,
+                                                         const double* __restrict__ t,
+                                                         const double* __restrict__ pn, int npn,
+                                                         double* __restrict__ tnorm,
                                                          const double* __restrict__ ypart,
                                                          const double* __restrict__ nypart, long long gstride, int G,
                                                          double* __restrict__ part) {
     __shared__ double vs[kDavChunk], hs[kDavChunk], ns[kDavChunk];
+    __shared__ double wred[4][64];
+    __shared__ double tot[1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nd = 4 * m + 2;
     const int e0 = blockIdx.x * kDavChunk;
     const int e = e0 + threadIdx.x;
     const int nval = min(kDavChunk, n - e0);
+    double inv = 1.0;
+    if (t) {
+        reduce_partials<4>(pn, npn, 1, 1, wred, tot);
+        const double nrm = sqrt(tot[0]);
+        inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *tnorm = nrm;
+    }
     double vm = 0.0, hm = 0.0, nm = 0.0;
     if (e < n) {
         const long long o = (long long)m * ld + e;
-        vm = V[o];
+        vm = t ? t[e] * inv : V[o];
         if (ypart) {
-            for (int g = 0; g < G; ++g) {
+            int g = 0;
+            for (; g + 4 <= G; g += 4) {
+                const double a0 = ypart[g * gstride + e], a1 = ypart[(g + 1) * gstride + e];
+                const double a2 = ypart[(g + 2) * gstride + e], a3 = ypart[(g + 3) * gstride + e];
+                const double b0 = nypart[g * gstride + e], b1 = nypart[(g + 1) * gstride + e];
+                const double b2 = nypart[(g + 2) * gstride + e], b3 = nypart[(g + 3) * gstride + e];
+                hm += a0;
+                hm += a1;
+                hm += a2;
+                hm += a3;
+                nm += b0;
+                nm += b1;
+                nm += b2;
+                nm += b3;
+            }
+            for (; g < G; ++g) {
                 hm += ypart[g * gstride + e];
                 nm += nypart[g * gstride + e];
-            }
-            if (blockIdx.y == 0) {
-                HV[o] = hm;
-                NV[o] = nm;
             }
         } else {
             hm = HV[o];
             nm = NV[o];
         }
+        hm *= inv;
+        nm *= inv;
     }
     vs[threadIdx.x] = vm;
     hs[threadIdx.x] = hm;
     ns[threadIdx.x] = nm;
     __syncthreads();
+    // every work-group has read what it needs of HV_m, NV_m (only its own
+    // chunk, by its own threads) before the y == 0 groups overwrite them
+    if (blockIdx.y == 0 && e < n && ypart) {
+        const long long o = (long long)m * ld + e;
+        if (t) V[o] = vm;
+        HV[o] = hm;
+        NV[o] = nm;
+    }
     double* out = part + (long long)blockIdx.x * nd;
     const int d0 = blockIdx.y * kGramGroup;
     const int d1 = min(nd, d0 + kGramGroup);
-    // d <= m: V_d.HV_m; then V_j.NV_m (j <= m); HV_j.V_m (j < m); NV_j.V_m (j < m)
+    // d <= m: V_d.HV_m; then V_j.NV_m (j <= m); HV_j.V_m (j < m); NV_j.V_m (j < m).
+    // V_m itself is taken from LDS (it may be being stored right now).
     for (int d = d0 + wave; d < d1; d += 16) {
         double acc[4];
 #pragma unroll
@@ -792,27 +872,37 @@ __global__ __launch_bounds__(kThreads) void k_dav_gram(const double* __restrict_
             acc[u] = 0.0;
             const int dd = d + 4 * u;
             if (dd < d1) {
-                const double* __restrict__ src;
+                int row;
+                const double* __restrict__ base;
                 const double* w;
                 if (dd <= m) {
-                    src = V + (long long)dd * ld;
+                    row = dd;
+                    base = V;
                     w = hs;
                 } else if (dd <= 2 * m + 1) {
-                    src = V + (long long)(dd - m - 1) * ld;
+                    row = dd - m - 1;
+                    base = V;
                     w = ns;
                 } else if (dd <= 3 * m + 1) {
-                    src = HV + (long long)(dd - 2 * m - 2) * ld;
+                    row = dd - 2 * m - 2;
+                    base = HV;
                     w = vs;
                 } else {
-                    src = NV + (long long)(dd - 3 * m - 2) * ld;
+                    row = dd - 3 * m - 2;
+                    base = NV;
                     w = vs;
                 }
-                src += e0;
-                double v[4];
+                if (row == m) {  // V_m . (HV_m or NV_m), both in LDS
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (lane + 64 * q < nval) ? src[lane + 64 * q] : 0.0;
+                    for (int q = 0; q < 4; ++q) acc[u] = fma(vs[lane + 64 * q], w[lane + 64 * q], acc[u]);
+                } else {
+                    const double* __restrict__ src = base + (long long)row * ld + e0;
+                    double v[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[u] = fma(v[q], w[lane + 64 * q], acc[u]);
+                    for (int q = 0; q < 4; ++q) v[q] = (lane + 64 * q < nval) ? src[lane + 64 * q] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[u] = fma(v[q], w[lane + 64 * q], acc[u]);
+                }
             }
         }
 #pragma unroll
@@ -895,22 +985,24 @@ void basis_rotate(hipStream_t s, const double* A, long long ld, int m, const dou
 void dav_ritz(hipStream_t s, const double* V, const double* HV, const double* NV, long long ld, int m,
               const double* aq, const double* dh, const double* dn, int n, double floor_, double* x, double* t,
               double* part_x, double* part_c) {
-    hipLaunchKernelGGL(k_dav_ritz, dim3(dav_chunks(n)), dim3(kThreads), 0, s, V, HV, NV, ld, m, aq, dh, dn, n, floor_,
+    hipLaunchKernelGGL(k_dav_ritz, dim3(dav_chunks(n)), dim3(kDavWide), 0, s, V, HV, NV, ld, m, aq, dh, dn, n, floor_,
                        x, t, part_x, part_c);
 }
 void dav_cgs(hipStream_t s, const double* V, long long ld, int m_sub, int m_dot, const double* part_in,
              int nchunk, double* t, int n, double* part_out, int mode) {
-    hipLaunchKernelGGL(k_dav_cgs, dim3(dav_chunks(n)), dim3(kThreads), 0, s, V, ld, m_sub, m_dot, part_in, nchunk, t,
+    hipLaunchKernelGGL(k_dav_cgs, dim3(dav_chunks(n)), dim3(kDavWide), 0, s, V, ld, m_sub, m_dot, part_in, nchunk, t,
                        n, part_out, mode);
 }
 void dav_normalize(hipStream_t s, const double* part, int nchunk, const double* t, double* vout, int n,
                    double* tnorm) {
     hipLaunchKernelGGL(k_dav_normalize, dim3(dav_chunks(n)), dim3(kThreads), 0, s, part, nchunk, t, vout, n, tnorm);
 }
-void dav_gram(hipStream_t s, const double* V, double* HV, double* NV, long long ld, int m, int n,
-              const double* ypart, const double* nypart, long long gstride, int G, double* part) {
+void dav_gram(hipStream_t s, double* V, double* HV, double* NV, long long ld, int m, int n, const double* t,
+              const double* pn, int npn, double* tnorm, const double* ypart, const double* nypart, long long gstride,
+              int G, double* part) {
     const int nd = 4 * m + 2;
     hipLaunchKernelGGL(k_dav_gram, dim3(dav_chunks(n), (nd + kGramGroup - 1) / kGramGroup), dim3(kThreads), 0, s, V, HV,
-                       NV, ld, m, n, ypart, nypart, gstride, G, part);
+                       NV, ld, m, n, t, pn, npn, tnorm, ypart, nypart, gstride, G, part);
 }
+
 }  // namespace spk

@@ -1890,11 +1890,22 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     double* up = h->pin_up;
     double* dn = h->pin;
     double* dn_dev = h->pin_dev;  // device view of dn: partial sums land here
-    auto gram = [&](int mm) {
+    // new vector mm: on the tiled path H_eff is applied to the unnormalised
+    // correction t (or V_0 for mm = 0) and the Gram pass normalises V_mm,
+    // HV_mm and NV_mm; the plain path normalises first
+    auto extend = [&](int mm, bool from_t) {
         double* vm = V + size_t(mm) * ld;
-        const bool deferred = heff_apply(h, k, vm, HV + size_t(mm) * ld, NV + size_t(mm) * ld, true);
-        spk::dav_gram(s, V, HV, NV, ld, mm, n, deferred ? h->ypart.p : nullptr, deferred ? h->nypart.p : nullptr,
-                      n, h->G, dn_dev + (lay.pg - lay.out));
+        double* tn = dn_dev + (lay.tn - lay.out);
+        if (h->path == SP_PATH_PLAIN) {
+            if (from_t) spk::dav_normalize(s, sm + lay.pn, nch, h->dt.p, vm, n, tn);
+            heff_apply(h, k, vm, HV + size_t(mm) * ld, NV + size_t(mm) * ld);
+            spk::dav_gram(s, V, HV, NV, ld, mm, n, nullptr, nullptr, 0, nullptr, nullptr, nullptr, n, h->G,
+                          dn_dev + (lay.pg - lay.out));
+        } else {
+            heff_apply(h, k, from_t ? h->dt.p : vm, nullptr, nullptr, true);
+            spk::dav_gram(s, V, HV, NV, ld, mm, n, from_t ? h->dt.p : nullptr, sm + lay.pn, nch, tn, h->ypart.p,
+                          h->nypart.p, n, h->G, dn_dev + (lay.pg - lay.out));
+        }
     };
     const double drop = 1e-10, floor_ = 1e-8;
     DavOut out;
@@ -1907,7 +1918,7 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
 
     diag(h, k, h->ddh.p, h->ddn.p);
     spk::normalize(s, site_ptr(h, k), V, n, nullptr);
-    gram(0);
+    extend(0, false);
     out.matvecs = 1;
     HIPCK(hipStreamSynchronize(s));
     const int S = max_sub + 1;
@@ -1987,9 +1998,7 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
             // CGS2 of the correction against the search space, then normalise
             spk::dav_cgs(s, V, ld, m, m, sm + lay.pc1, nch, h->dt.p, n, sm + lay.pc2, 0);
             spk::dav_cgs(s, V, ld, m, 0, sm + lay.pc2, nch, h->dt.p, n, sm + lay.pn, 1);
-            double* vnew = V + size_t(m) * ld;
-            spk::dav_normalize(s, sm + lay.pn, nch, h->dt.p, vnew, n, dn_dev + (lay.tn - lay.out));
-            gram(m);
+            extend(m, true);
             out.matvecs++;
         }
         HIPCK(hipStreamSynchronize(s));
