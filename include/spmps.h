@@ -223,6 +223,15 @@ int sp_mpo_identity(int L, int* w, double* data, long long* n);
  * (n x n row-major). */
 int sp_small_eigh(int n, double* a, double* ev, double* vec);
 
+/* The Davidson subspace solve: lowest eigenpair of the symmetric pencil
+ * H c = theta N c (m x m, row-major, not modified) restricted to the span of
+ * the eigenvectors of N whose eigenvalues exceed drop * lambda_max(N)
+ * (canonical orthogonalisation; the local problem of Eq. [geproblem] in the
+ * search space).  On return theta, a (m coefficients, a^T N a = 1) and rank
+ * (the dimension kept).  SP_ENORM if N vanishes. */
+int sp_small_gen_lowest(int m, const double* H, const double* N, double drop, double* theta, double* a,
+                        int* rank);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_destroy", "sp_site_size", "sp_get_site", "sp_set_site", "sp_center", "sp_heff_flops",
            "sp_heff_profile",
            "sp_last_error", "sp_quadrature", "sp_exact_points", "sp_mpo_hubbard", "sp_mpo_s2",
-           "sp_mpo_identity", "sp_small_eigh"]
+           "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest"]
 
 
 class SpError(RuntimeError):
@@ -98,6 +98,7 @@ def lib():
         "sp_mpo_s2": [ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_identity": [ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_small_eigh": [ctypes.c_int, dp, dp, dp],
+        "sp_small_gen_lowest": [ctypes.c_int, dp, dp, ctypes.c_double, dp, dp, ctypes.POINTER(ctypes.c_int)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -169,6 +170,19 @@ def small_eigh(a):
     ev, vec = np.zeros(n), np.zeros((n, n))
     _check(lib().sp_small_eigh(n, _dptr(a), _dptr(ev), _dptr(vec)))
     return ev, vec
+
+
+def small_gen_lowest(H, N, drop=1e-10):
+    """Lowest (theta, a, rank) of the pencil (H, N) within the span of N's
+    eigenvectors above drop * max (the Davidson subspace solve)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    N = np.ascontiguousarray(N, dtype=np.float64)
+    m = H.shape[0]
+    theta = np.zeros(1)
+    a = np.zeros(m)
+    rank = ctypes.c_int(0)
+    _check(lib().sp_small_gen_lowest(m, _dptr(H), _dptr(N), float(drop), _dptr(theta), _dptr(a), ctypes.byref(rank)))
+    return float(theta[0]), a, rank.value
 
 
 # ---- the SP-MPS state ------------------------------------------------------

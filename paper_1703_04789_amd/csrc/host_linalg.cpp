@@ -250,12 +250,20 @@ static void tridiagonalize(int n, double* a, Tridiag& T) {
         const double beta = 2.0 / vv;
         T.beta[k] = beta;
         // trailing block S = A[k+1:, k+1:]:  S -= v w^T + w v^T
+        // (dot products with four independent partial sums)
         double vp = 0.0;
         for (int i = 0; i < len; ++i) {
             const double* row = &A(k + 1 + i, k + 1);
-            double sacc = 0.0;
-            for (int j = 0; j < len; ++j) sacc += row[j] * v[j];
-            p[i] = beta * sacc;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int j = 0;
+            for (; j + 4 <= len; j += 4) {
+                s0 += row[j] * v[j];
+                s1 += row[j + 1] * v[j + 1];
+                s2 += row[j + 2] * v[j + 2];
+                s3 += row[j + 3] * v[j + 3];
+            }
+            for (; j < len; ++j) s0 += row[j] * v[j];
+            p[i] = beta * ((s0 + s1) + (s2 + s3));
             vp += v[i] * p[i];
         }
         const double K = 0.5 * beta * vp;
@@ -373,71 +381,254 @@ int sym_eigh(int n, double* a, double* ev, double* vec) {
     return 0;
 }
 
+// number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence
+// of the LDL^T pivots of T - x I)
+static int sturm_count(int n, const double* d, const double* e, double x) {
+    int cnt = 0;
+    double q = d[0] - x;
+    if (q < 0.0) ++cnt;
+    for (int i = 1; i < n; ++i) {
+        const double qq = (q == 0.0) ? 1e-300 : q;
+        q = d[i] - x - e[i - 1] * e[i - 1] / qq;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// solve (T - shift) z = z in place (Gaussian elimination with partial
+// pivoting on the tridiagonal band) and normalise z
+static void tridiag_inverse_step(int n, const double* d, const double* e, double shift, double* z) {
+    std::vector<double> dd(n), du(n, 0.0), du2(n, 0.0), dl(n, 0.0);
+    std::vector<char> swp(n, 0);
+    for (int i = 0; i < n; ++i) dd[i] = d[i] - shift;
+    for (int i = 0; i + 1 < n; ++i) du[i] = dl[i] = e[i];
+    for (int i = 0; i + 1 < n; ++i) {
+        if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
+            const double f = (dd[i] != 0.0) ? dl[i] / dd[i] : 0.0;
+            dl[i] = f;
+            dd[i + 1] -= f * du[i];
+        } else {
+            swp[i] = 1;
+            const double f = dd[i] / dl[i];
+            dd[i] = dl[i];
+            dl[i] = f;
+            const double t = du[i];
+            du[i] = dd[i + 1];
+            dd[i + 1] = t - f * dd[i + 1];
+            if (i + 2 < n) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du[i + 1];
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (dd[i] == 0.0) dd[i] = 1e-300;
+    for (int i = 0; i + 1 < n; ++i) {
+        if (!swp[i]) {
+            z[i + 1] -= dl[i] * z[i];
+        } else {
+            const double t = z[i];
+            z[i] = z[i + 1];
+            z[i + 1] = t - dl[i] * z[i];
+        }
+    }
+    z[n - 1] /= dd[n - 1];
+    if (n > 1) z[n - 2] = (z[n - 2] - du[n - 2] * z[n - 1]) / dd[n - 2];
+    for (int i = n - 3; i >= 0; --i) z[i] = (z[i] - du[i] * z[i + 1] - du2[i] * z[i + 2]) / dd[i];
+    double nr = 0.0;
+    for (int i = 0; i < n; ++i) nr += z[i] * z[i];
+    nr = std::sqrt(nr);
+    for (int i = 0; i < n; ++i) z[i] /= nr;
+}
+
+// Lowest eigenpair of a symmetric tridiagonal: bisection with Sturm counts
+// narrows [lo, hi] around the lowest eigenvalue (lo stays strictly below
+// it), inverse iteration shifted to lo gives the vector, and the Rayleigh
+// quotient the value.
+static void tridiag_lowest(int n, const double* d, const double* e, double* lam, double* z) {
+    if (n == 1) {
+        *lam = d[0];
+        z[0] = 1.0;
+        return;
+    }
+    double lo = d[0], hi = d[0];
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    const double spread = std::max(hi - lo, 1e-300);
+    lo -= 1e-3 * spread;
+    hi += 1e-3 * spread;
+    // count(lo) == 0 <= count(hi) - 1
+    for (int it = 0; it < 200 && hi - lo > 1e-7 * spread; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_count(n, d, e, mid) >= 1) hi = mid;
+        else lo = mid;
+    }
+    for (int i = 0; i < n; ++i) z[i] = 1.0 / std::sqrt(double(n)) * (1.0 + 0.01 * i);
+    for (int it = 0; it < 3; ++it) tridiag_inverse_step(n, d, e, lo, z);
+    double rq = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double tz = d[i] * z[i];
+        if (i > 0) tz += e[i - 1] * z[i - 1];
+        if (i + 1 < n) tz += e[i] * z[i + 1];
+        rq += z[i] * tz;
+    }
+    *lam = rq;
+}
+
 int sym_eig_lowest(int n, double* a, double* ev0, double* v0) {
     if (n <= 0) return 0;
     Tridiag T;
     tridiagonalize(n, a, T);
-    std::vector<double> d = T.d, e = T.e;
-    if (!tridiag_qr(n, d.data(), e.data(), nullptr)) return -1;
-    double lam = d[0];
-    for (int i = 1; i < n; ++i) lam = std::min(lam, d[i]);
-    *ev0 = lam;
-    // inverse iteration on the tridiagonal (T - lam) z = z_prev with a tiny
-    // shift below lam; LU without pivoting is stable for this shift choice
-    // only up to a scale, so partial pivoting is used (Gaussian elimination on
-    // the tridiagonal band, 2 upper diagonals after pivoting)
-    const double scale = std::max(1.0, std::fabs(lam));
-    const double shift = lam - 1e-13 * scale;
-    std::vector<double> z(n, 1.0), dd(n), du(n), du2(n), dl(n);
-    std::vector<int> piv(n);
-    for (int it = 0; it < 3; ++it) {
-        for (int i = 0; i < n; ++i) dd[i] = T.d[i] - shift;
-        for (int i = 0; i + 1 < n; ++i) du[i] = dl[i] = T.e[i];
-        // factor (dgttrf-like elimination with row interchanges)
-        for (int i = 0; i < n; ++i) du2[i] = 0.0;
-        for (int i = 0; i + 1 < n; ++i) {
-            if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
-                piv[i] = i;
-                const double f = (dd[i] != 0.0) ? dl[i] / dd[i] : 0.0;
-                dl[i] = f;
-                dd[i + 1] -= f * du[i];
-            } else {
-                piv[i] = i + 1;
-                const double f = dd[i] / dl[i];
-                dd[i] = dl[i];
-                dl[i] = f;
-                const double t = du[i];
-                du[i] = dd[i + 1];
-                dd[i + 1] = t - f * dd[i + 1];
-                if (i + 2 < n) {
-                    du2[i] = du[i + 1];
-                    du[i + 1] = -f * du[i + 1];
-                }
-            }
-        }
-        for (int i = 0; i < n; ++i)
-            if (dd[i] == 0.0) dd[i] = 1e-300;
-        // solve L U x = z
-        for (int i = 0; i + 1 < n; ++i) {
-            if (piv[i] == i) {
-                z[i + 1] -= dl[i] * z[i];
-            } else {
-                const double t = z[i];
-                z[i] = z[i + 1];
-                z[i + 1] = t - dl[i] * z[i];
-            }
-        }
-        z[n - 1] /= dd[n - 1];
-        if (n > 1) z[n - 2] = (z[n - 2] - du[n - 2] * z[n - 1]) / dd[n - 2];
-        for (int i = n - 3; i >= 0; --i) z[i] = (z[i] - du[i] * z[i + 1] - du2[i] * z[i + 2]) / dd[i];
-        double nr = 0.0;
-        for (double q : z) nr += q * q;
-        nr = std::sqrt(nr);
-        for (double& q : z) q /= nr;
-    }
+    std::vector<double> z(n);
+    tridiag_lowest(n, T.d.data(), T.e.data(), ev0, z.data());
+    if (!std::isfinite(*ev0)) return -1;
     apply_q(T, z.data(), 1);
     std::copy(z.begin(), z.end(), v0);
     return 0;
+}
+
+// Cholesky N = L L^T (row-major, lower); false if a pivot is not positive
+static bool cholesky(int m, const double* N, double shift, std::vector<double>& L) {
+    L.assign(size_t(m) * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        double dsum = N[size_t(j) * m + j] - shift;
+        const double* lj = &L[size_t(j) * m];
+        for (int k = 0; k < j; ++k) dsum -= lj[k] * lj[k];
+        if (!(dsum > 0.0)) return false;
+        const double ljj = std::sqrt(dsum);
+        L[size_t(j) * m + j] = ljj;
+        for (int i = j + 1; i < m; ++i) {
+            const double* li = &L[size_t(i) * m];
+            double s0 = N[size_t(i) * m + j], s1 = 0.0;
+            int k = 0;
+            for (; k + 2 <= j; k += 2) {
+                s0 -= li[k] * lj[k];
+                s1 -= li[k + 1] * lj[k + 1];
+            }
+            for (; k < j; ++k) s0 -= li[k] * lj[k];
+            L[size_t(i) * m + j] = (s0 + s1) / ljj;
+        }
+    }
+    return true;
+}
+
+int gen_lowest(int m, const double* H, const double* N, double drop, double* theta, double* a, double* Xc,
+               int* rank) {
+    if (m <= 0) return -1;
+    // fast path (lowest pair only): if N - drop * U is positive definite,
+    // where U >= lambda_max(N) is the Gershgorin bound, no eigenvalue of N is
+    // dropped, and the restriction is the whole space: reduce with the
+    // Cholesky factor of N instead of its eigenvectors
+    if (!Xc) {
+        double U = 0.0;
+        for (int i = 0; i < m; ++i) {
+            double r = 0.0;
+            for (int j = 0; j < m; ++j) r += std::fabs(N[size_t(i) * m + j]);
+            U = std::max(U, r);
+        }
+        std::vector<double> L;
+        if (U > 1e-12 && cholesky(m, N, drop * U, L) && cholesky(m, N, 0.0, L)) {
+            // W = L^-1 H (columns by forward substitution), B = L^-1 W^T
+            std::vector<double> W(H, H + size_t(m) * m), B(size_t(m) * m);
+            for (int i = 0; i < m; ++i) {
+                double* wi = &W[size_t(i) * m];
+                for (int k = 0; k < i; ++k) {
+                    const double lik = L[size_t(i) * m + k];
+                    const double* wk = &W[size_t(k) * m];
+                    for (int c = 0; c < m; ++c) wi[c] -= lik * wk[c];
+                }
+                const double inv = 1.0 / L[size_t(i) * m + i];
+                for (int c = 0; c < m; ++c) wi[c] *= inv;
+            }
+            for (int i = 0; i < m; ++i)
+                for (int c = 0; c < m; ++c) B[size_t(i) * m + c] = W[size_t(c) * m + i];
+            for (int i = 0; i < m; ++i) {
+                double* bi = &B[size_t(i) * m];
+                for (int k = 0; k < i; ++k) {
+                    const double lik = L[size_t(i) * m + k];
+                    const double* bk = &B[size_t(k) * m];
+                    for (int c = 0; c < m; ++c) bi[c] -= lik * bk[c];
+                }
+                const double inv = 1.0 / L[size_t(i) * m + i];
+                for (int c = 0; c < m; ++c) bi[c] *= inv;
+            }
+            for (int r = 0; r < m; ++r)
+                for (int c = 0; c < r; ++c)
+                    B[size_t(r) * m + c] = B[size_t(c) * m + r] = 0.5 * (B[size_t(r) * m + c] + B[size_t(c) * m + r]);
+            std::vector<double> c0(m);
+            if (sym_eig_lowest(m, B.data(), theta, c0.data()) != 0) return -1;
+            // a = L^-T c0
+            for (int i = m - 1; i >= 0; --i) {
+                double v = c0[i];
+                for (int k = i + 1; k < m; ++k) v -= L[size_t(k) * m + i] * a[k];
+                a[i] = v / L[size_t(i) * m + i];
+            }
+            *rank = m;
+            return m;
+        }
+    }
+    // canonical orthogonalisation through the eigenvectors of N
+    std::vector<double> A(N, N + size_t(m) * m), ev(m), U(size_t(m) * m);
+    if (sym_eigh(m, A.data(), ev.data(), U.data()) != 0) return -1;
+    const double lmax = ev[m - 1];
+    if (!(lmax > 1e-12)) return 0;
+    std::vector<int> keep;
+    for (int i = 0; i < m; ++i)
+        if (ev[i] > drop * lmax) keep.push_back(i);
+    const int rk = int(keep.size());
+    std::vector<double> X(size_t(m) * rk);
+    for (int i = 0; i < m; ++i)
+        for (int c = 0; c < rk; ++c) X[size_t(i) * rk + c] = U[size_t(i) * m + keep[c]] / std::sqrt(ev[keep[c]]);
+    // B = X^T H X
+    std::vector<double> HX(size_t(m) * rk, 0.0), B(size_t(rk) * rk, 0.0);
+    for (int i = 0; i < m; ++i) {
+        double* hx = &HX[size_t(i) * rk];
+        for (int j = 0; j < m; ++j) {
+            const double hij = H[size_t(i) * m + j];
+            const double* xj = &X[size_t(j) * rk];
+            for (int c = 0; c < rk; ++c) hx[c] += hij * xj[c];
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        const double* xi = &X[size_t(i) * rk];
+        const double* hx = &HX[size_t(i) * rk];
+        for (int r = 0; r < rk; ++r) {
+            const double xir = xi[r];
+            double* br = &B[size_t(r) * rk];
+            for (int c = 0; c < rk; ++c) br[c] += xir * hx[c];
+        }
+    }
+    for (int r = 0; r < rk; ++r)
+        for (int c = 0; c < r; ++c)
+            B[size_t(r) * rk + c] = B[size_t(c) * rk + r] = 0.5 * (B[size_t(r) * rk + c] + B[size_t(c) * rk + r]);
+    *rank = rk;
+    if (!Xc) {
+        std::vector<double> c0(rk);
+        if (sym_eig_lowest(rk, B.data(), theta, c0.data()) != 0) return -1;
+        for (int i = 0; i < m; ++i) {
+            double v = 0.0;
+            for (int c = 0; c < rk; ++c) v += X[size_t(i) * rk + c] * c0[c];
+            a[i] = v;
+        }
+        return rk;
+    }
+    std::vector<double> mu(rk), C(size_t(rk) * rk);
+    if (sym_eigh(rk, B.data(), mu.data(), C.data()) != 0) return -1;
+    *theta = mu[0];
+    for (int i = 0; i < m * rk; ++i) Xc[i] = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double* xc = Xc + size_t(i) * rk;
+        for (int j = 0; j < rk; ++j) {
+            const double xij = X[size_t(i) * rk + j];
+            const double* cj = &C[size_t(j) * rk];
+            for (int c = 0; c < rk; ++c) xc[c] += xij * cj[c];
+        }
+    }
+    for (int i = 0; i < m; ++i) a[i] = Xc[size_t(i) * rk];
+    return rk;
 }
 
 }  // namespace sph

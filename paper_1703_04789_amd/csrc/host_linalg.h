@@ -18,5 +18,13 @@ int sym_eigh(int n, double* a, double* ev, double* vec);
 // lowest eigenvalue and its unit eigenvector (tridiagonal QR for the value,
 // inverse iteration for the vector); a is destroyed
 int sym_eig_lowest(int n, double* a, double* ev0, double* v0);
+// Lowest eigenpair of the symmetric pencil (H, N), m x m row-major, within
+// the span of the eigenvectors of N whose eigenvalues exceed drop * max
+// (canonical orthogonalisation).  a: m coefficients with a^T N a = 1.  If
+// Xc != nullptr it receives all Ritz coefficient vectors (m x rank,
+// ascending Ritz values).  Returns the rank (> 0), 0 if N vanishes, -1 on
+// failure.
+int gen_lowest(int m, const double* H, const double* N, double drop, double* theta, double* a, double* Xc,
+               int* rank);
 
 }  // namespace sph

@@ -148,8 +148,12 @@ void combine(hipStream_t s, const CTask* tasks, int ntasks, const CTerm* terms, 
 void heff_diag(hipStream_t s, const DiagBlk* blks, int nblk, const DiagTerm* terms,
                const double* lenv, long long lsize, const double* renv, long long rsize,
                const double* coef, int ncoef, int G, double* out);
-void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* pieces,
-                double* site, double* scratch, double* rout);
+// Per-sector positive-diagonal QR.  Tasks whose two rows x cols matrices
+// fit kQrLdsMax doubles run in LDS (lds_doubles = the largest 2 rows cols
+// of the list); otherwise they use the scratch buffer in global memory.
+constexpr int kQrLdsMax = 12288;
+void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* pieces, double* site,
+                double* scratch, double* rout, int lds_doubles);
 
 // Davidson vector kernels (n = vector length, ld = stride between vectors)
 void normalize(hipStream_t s, const double* in, double* out, int n, double* norm_out);

@@ -15,6 +15,12 @@ namespace {
 
 constexpr int kThreads = 256;
 
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ inline double block_sum(double v, double* red) {
     // fixed-order tree reduction over the work-group (blockDim.x power of 2)
     red[threadIdx.x] = v;
@@ -219,6 +225,100 @@ __global__ __launch_bounds__(kThreads) void k_qr(const QrTask* __restrict__ task
         for (int e = threadIdx.x; e < nel; e += kThreads) {
             const int rr = e / cols, cc = e - rr * cols;
             double v = Q[(long long)cc * rows + pc.row0 + rr];
+            if (diag_s[cc] < 0.0) v = -v;
+            if (pc.transposed) site[pc.off + (long long)cc * pc.pcol + rr] = v;
+            else site[pc.off + (long long)rr * pc.pcol + cc] = v;
+        }
+    }
+}
+
+// The same factorisation with both matrices in LDS: the norm of the pivot
+// column is a wave reduction, and each trailing (or Q) column is updated by
+// one wave (lanes over rows, dot product by cross-lane shuffles).
+__global__ __launch_bounds__(kThreads) void k_qr_lds(const QrTask* __restrict__ tasks,
+                                                       const QrPiece* __restrict__ pieces,
+                                                       double* __restrict__ site, double* __restrict__ rout) {
+    extern __shared__ double sh[];
+    __shared__ double tau_s[256];
+    __shared__ double diag_s[256];
+    const QrTask tk = tasks[blockIdx.x];
+    const int rows = tk.rows, cols = tk.cols;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* S = sh;                       // rows x cols, column-major
+    double* Q = sh + (long long)rows * cols;
+    for (int p = tk.p0; p < tk.p1; ++p) {
+        const QrPiece pc = pieces[p];
+        const int nr = pc.transposed ? pc.pcol : pc.prow;
+        const int nel = nr * cols;
+        for (int e = threadIdx.x; e < nel; e += kThreads) {
+            const int rr = e / cols, cc = e - rr * cols;
+            const double v = pc.transposed ? site[pc.off + (long long)cc * pc.pcol + rr]
+                                           : site[pc.off + (long long)rr * pc.pcol + cc];
+            S[cc * rows + pc.row0 + rr] = v;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < cols; ++j) {
+        const double* sj = S + j * rows;
+        if (wave == 0) {
+            double ss = 0.0;
+            for (int r = j + lane; r < rows; r += 64) ss = fma(sj[r], sj[r], ss);
+            ss = wave_sum64(ss);
+            if (lane == 0) {
+                const double x0 = sj[j];
+                const double nrm = sqrt(ss);
+                const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+                const double v0 = x0 - alpha;
+                const double vv = ss - x0 * x0 + v0 * v0;
+                tau_s[j] = (vv > 0.0) ? 2.0 / vv : 0.0;
+                diag_s[j] = alpha;
+                S[j * rows + j] = v0;
+            }
+        }
+        __syncthreads();
+        const double tau = tau_s[j];
+        for (int c = j + 1 + wave; c < cols; c += kThreads / 64) {
+            double* sc = S + c * rows;
+            double d = 0.0;
+            for (int r = j + lane; r < rows; r += 64) d = fma(sj[r], sc[r], d);
+            const double f = tau * wave_sum64(d);
+            for (int r = j + lane; r < rows; r += 64) sc[r] -= f * sj[r];
+        }
+        __syncthreads();
+    }
+    double* R = rout + tk.r_off;
+    for (int e = threadIdx.x; e < cols * cols; e += kThreads) {
+        const int i = e / cols, c = e - i * cols;
+        double v = 0.0;
+        if (c == i) v = diag_s[i];
+        else if (c > i) v = S[c * rows + i];
+        if (diag_s[i] < 0.0) v = -v;
+        R[e] = v;
+    }
+    for (int e = threadIdx.x; e < rows * cols; e += kThreads) {
+        const int c = e / rows, r = e - c * rows;
+        Q[e] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = cols - 1; j >= 0; --j) {
+        const double tau = tau_s[j];
+        const double* sj = S + j * rows;
+        for (int c = wave; c < cols; c += kThreads / 64) {
+            double* qc = Q + c * rows;
+            double d = 0.0;
+            for (int r = j + lane; r < rows; r += 64) d = fma(sj[r], qc[r], d);
+            const double f = tau * wave_sum64(d);
+            for (int r = j + lane; r < rows; r += 64) qc[r] -= f * sj[r];
+        }
+        __syncthreads();
+    }
+    for (int p = tk.p0; p < tk.p1; ++p) {
+        const QrPiece pc = pieces[p];
+        const int nr = pc.transposed ? pc.pcol : pc.prow;
+        const int nel = nr * cols;
+        for (int e = threadIdx.x; e < nel; e += kThreads) {
+            const int rr = e / cols, cc = e - rr * cols;
+            double v = Q[cc * rows + pc.row0 + rr];
             if (diag_s[cc] < 0.0) v = -v;
             if (pc.transposed) site[pc.off + (long long)cc * pc.pcol + rr] = v;
             else site[pc.off + (long long)rr * pc.pcol + cc] = v;
@@ -969,8 +1069,13 @@ void heff_diag(hipStream_t s, const DiagBlk* blks, int nb, const DiagTerm* terms
                            coef, ncoef, G, out);
 }
 void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* pieces, double* site,
-                double* scratch, double* rout) {
-    if (ntasks > 0) hipLaunchKernelGGL(k_qr, dim3(ntasks), dim3(kThreads), 0, s, tasks, pieces, site, scratch, rout);
+                double* scratch, double* rout, int lds_doubles) {
+    if (ntasks <= 0) return;
+    if (lds_doubles > 0 && lds_doubles <= kQrLdsMax)
+        hipLaunchKernelGGL(k_qr_lds, dim3(ntasks), dim3(kThreads), size_t(lds_doubles) * sizeof(double), s, tasks,
+                           pieces, site, rout);
+    else
+        hipLaunchKernelGGL(k_qr, dim3(ntasks), dim3(kThreads), 0, s, tasks, pieces, site, scratch, rout);
 }
 void normalize(hipStream_t s, const double* in, double* out, int n, double* norm_out) {
     hipLaunchKernelGGL(k_normalize, dim3(1), dim3(1024), 0, s, in, out, n, norm_out);

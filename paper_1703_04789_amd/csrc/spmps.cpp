@@ -298,6 +298,7 @@ struct SitePlan {
     DArr<spk::QrTask> dqr_tasks, dlq_tasks;
     DArr<spk::QrPiece> dqr_pieces, dlq_pieces;
     long long qr_scratch = 0, lq_scratch = 0, qr_rsize = 0, lq_rsize = 0;
+    int qr_lds = 0, lq_lds = 0;  // largest 2 * rows * cols of a task (doubles)
     std::vector<long long> qr_roff;  // per right sector of bond k
     std::vector<long long> lq_roff;  // per left sector of bond k-1
     BList absorb_right;  // R of site k into site k+1
@@ -904,6 +905,7 @@ void build_plan(sp_handle* h, int k) {
         P.qr_roff[sb] = ro;
         sc += 2LL * rows * t.cols;
         ro += (long long)t.cols * t.cols;
+        P.qr_lds = int(std::min<long long>(INT32_MAX, std::max<long long>(P.qr_lds, 2LL * rows * t.cols)));
         P.qr_tasks.push_back(t);
     }
     P.qr_scratch = sc;
@@ -931,6 +933,7 @@ void build_plan(sp_handle* h, int k) {
         P.lq_roff[sa] = ro;
         sc += 2LL * rows * t.cols;
         ro += (long long)t.cols * t.cols;
+        P.lq_lds = int(std::min<long long>(INT32_MAX, std::max<long long>(P.lq_lds, 2LL * rows * t.cols)));
         P.lq_tasks.push_back(t);
     }
     P.lq_scratch = sc;
@@ -1708,7 +1711,7 @@ void diag(sp_handle* h, int k, double* dh, double* dn) {
 void move_right(sp_handle* h, int k) {
     SitePlan& P = h->plan[k - 1];
     spk::qr_sectors(h->stream, P.dqr_tasks.p, int(P.qr_tasks.size()), P.dqr_pieces.p, site_ptr(h, k),
-                    h->qr_scratch.p, h->qr_r.p);
+                    h->qr_scratch.p, h->qr_r.p, P.qr_lds);
     if (k < h->L) {
         spk::BufSet b{};
         b.p[B_V] = h->qr_r.p;
@@ -1724,7 +1727,7 @@ void move_right(sp_handle* h, int k) {
 void move_left(sp_handle* h, int k) {
     SitePlan& P = h->plan[k - 1];
     spk::qr_sectors(h->stream, P.dlq_tasks.p, int(P.lq_tasks.size()), P.dlq_pieces.p, site_ptr(h, k),
-                    h->qr_scratch.p, h->qr_r.p);
+                    h->qr_scratch.p, h->qr_r.p, P.lq_lds);
     if (k > 1) {
         spk::BufSet b{};
         b.p[B_V] = h->qr_r.p;
@@ -1813,63 +1816,21 @@ struct DavOut {
 
 // lowest eigenpair of the pencil restricted to range(Nt) (canonical
 // orthogonalisation); returns false if the projected metric vanishes
-// (all Ritz coefficient vectors X C only when need_all, for restarts)
 bool small_solve(int m, const std::vector<double>& Ht, const std::vector<double>& Nt, int stride, double drop,
                  bool need_all, double& theta, std::vector<double>& a, std::vector<double>& Xc, int& rk) {
-    std::vector<double> A(size_t(m) * m), ev(m), U(size_t(m) * m);
+    std::vector<double> Hs(size_t(m) * m), Ns(size_t(m) * m);
     for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) A[i * m + j] = 0.5 * (Nt[i * stride + j] + Nt[j * stride + i]);
-    if (sph::sym_eigh(m, A.data(), ev.data(), U.data()) != 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
-    const double lmax = ev[m - 1];
-    if (!(lmax > 1e-12)) return false;
-    std::vector<int> keep;
-    for (int i = 0; i < m; ++i)
-        if (ev[i] > drop * lmax) keep.push_back(i);
-    rk = int(keep.size());
-    std::vector<double> X(size_t(m) * rk);
-    for (int i = 0; i < m; ++i)
-        for (int c = 0; c < rk; ++c) X[i * rk + c] = U[i * m + keep[c]] / std::sqrt(ev[keep[c]]);
-    // B = X^T Hs X
-    std::vector<double> HX(size_t(m) * rk, 0.0), B(size_t(rk) * rk, 0.0);
-    for (int i = 0; i < m; ++i)
-        for (int c = 0; c < rk; ++c) {
-            double s = 0.0;
-            for (int j = 0; j < m; ++j) s += 0.5 * (Ht[i * stride + j] + Ht[j * stride + i]) * X[j * rk + c];
-            HX[i * rk + c] = s;
+        for (int j = 0; j < m; ++j) {
+            Hs[size_t(i) * m + j] = 0.5 * (Ht[size_t(i) * stride + j] + Ht[size_t(j) * stride + i]);
+            Ns[size_t(i) * m + j] = 0.5 * (Nt[size_t(i) * stride + j] + Nt[size_t(j) * stride + i]);
         }
-    for (int r = 0; r < rk; ++r)
-        for (int c = 0; c < rk; ++c) {
-            double s = 0.0;
-            for (int i = 0; i < m; ++i) s += X[i * rk + r] * HX[i * rk + c];
-            B[r * rk + c] = s;
-        }
-    for (int r = 0; r < rk; ++r)
-        for (int c = 0; c < r; ++c) B[r * rk + c] = B[c * rk + r] = 0.5 * (B[r * rk + c] + B[c * rk + r]);
-    if (!need_all) {
-        std::vector<double> c0(rk);
-        if (sph::sym_eig_lowest(rk, B.data(), &theta, c0.data()) != 0)
-            throw SpError(SP_ENAN, "subspace eigensolver failed");
-        if (!std::isfinite(theta)) throw SpError(SP_ENAN, "non-finite Ritz value");
-        a.assign(m, 0.0);
-        for (int i = 0; i < m; ++i)
-            for (int c = 0; c < rk; ++c) a[i] += X[i * rk + c] * c0[c];
-        return true;
-    }
-    std::vector<double> mu(rk), C(size_t(rk) * rk);
-    if (sph::sym_eigh(rk, B.data(), mu.data(), C.data()) != 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
-    theta = mu[0];
-    if (!std::isfinite(theta)) throw SpError(SP_ENAN, "non-finite Ritz value");
     a.assign(m, 0.0);
-    for (int i = 0; i < m; ++i)
-        for (int c = 0; c < rk; ++c) a[i] += X[i * rk + c] * C[c * rk + 0];
-    // X C (all Ritz coefficient vectors, m x rk) for restarts
-    Xc.assign(size_t(m) * rk, 0.0);
-    for (int i = 0; i < m; ++i)
-        for (int c = 0; c < rk; ++c) {
-            double s = 0.0;
-            for (int j = 0; j < rk; ++j) s += X[i * rk + j] * C[j * rk + c];
-            Xc[i * rk + c] = s;
-        }
+    if (need_all) Xc.assign(size_t(m) * m, 0.0);
+    const int r = sph::gen_lowest(m, Hs.data(), Ns.data(), drop, &theta, a.data(), need_all ? Xc.data() : nullptr, &rk);
+    if (r < 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
+    if (r == 0) return false;
+    if (!std::isfinite(theta)) throw SpError(SP_ENAN, "non-finite Ritz value");
+    if (need_all) Xc.resize(size_t(m) * rk);
     return true;
 }
 
@@ -2400,6 +2361,17 @@ int sp_mpo_identity(int L, int* w, double* data, long long* n) {
     return guarded([&]() -> int {
         SP_REQUIRE(L >= 1 && w && n, "bad arguments");
         return sph::mpo_identity(L, w, data, n);
+    });
+}
+
+int sp_small_gen_lowest(int m, const double* H, const double* N, double drop, double* theta, double* a,
+                        int* rank) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(m >= 1 && H && N && theta && a && rank, "bad arguments");
+        const int r = sph::gen_lowest(m, H, N, drop, theta, a, nullptr, rank);
+        if (r < 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
+        if (r == 0) throw SpError(SP_ENORM, "the metric vanishes");
+        return SP_OK;
     });
 }
 

@@ -76,6 +76,54 @@ def test_small_eigh_degenerate_and_singular():
     np.testing.assert_allclose(ev, [1, 1, 2, 3])
 
 
+def _canonical_lowest(H, N, drop=1e-10):
+    """The subspace solve written out with numpy: eigendecompose N, keep the
+    eigenvalues above drop * max, reduce H and take its lowest eigenpair."""
+    lam, U = np.linalg.eigh(N)
+    sel = lam > drop * lam.max()
+    X = U[:, sel] / np.sqrt(lam[sel])[None, :]
+    mu, C = np.linalg.eigh(X.T @ H @ X)
+    return mu[0], X @ C[:, 0], int(sel.sum())
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 8, 17, 32])
+def test_small_gen_lowest_full_rank(m):
+    rng = np.random.default_rng(10 + m)
+    A = rng.standard_normal((m, m))
+    H = A + A.T
+    B = rng.standard_normal((m, m))
+    N = B @ B.T + 0.1 * np.eye(m)
+    theta, a, rank = sp.small_gen_lowest(H, N)
+    t_ref, a_ref, r_ref = _canonical_lowest(H, N)
+    assert rank == r_ref == m
+    assert abs(theta - t_ref) < 1e-11 * max(1.0, abs(t_ref))
+    assert abs(a @ N @ a - 1.0) < 1e-11
+    np.testing.assert_allclose(H @ a, theta * (N @ a), atol=1e-9 * max(1.0, np.abs(H).max()))
+    np.testing.assert_allclose(abs(a @ N @ a_ref), 1.0, atol=1e-9)
+
+
+@pytest.mark.parametrize("m,r", [(6, 3), (20, 12), (32, 31)])
+def test_small_gen_lowest_singular_metric(m, r):
+    # N of rank r: the solve must stay in range(N), like the reference
+    rng = np.random.default_rng(100 + m)
+    B = rng.standard_normal((m, r))
+    N = B @ B.T
+    A = rng.standard_normal((m, m))
+    H = A + A.T
+    theta, a, rank = sp.small_gen_lowest(H, N)
+    t_ref, a_ref, r_ref = _canonical_lowest(H, N)
+    assert rank == r_ref == r
+    assert abs(theta - t_ref) < 1e-9 * max(1.0, abs(t_ref))
+    P = B @ np.linalg.pinv(B)  # projector on range(N)
+    np.testing.assert_allclose(P @ a, a, atol=1e-8 * np.abs(a).max())
+
+
+def test_small_gen_lowest_rejects_zero_metric():
+    with pytest.raises(sp.SpError) as e:
+        sp.small_gen_lowest(np.eye(3), np.zeros((3, 3)))
+    assert e.value.code == -2
+
+
 class _Tab:
     def __init__(self, L, N, twoM, bonds):
         self.L, self.N, self.twoM, self.bonds = L, N, twoM, bonds
