@@ -71,7 +71,12 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", default="tiled", choices=["tiled", "plain"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the H_eff products inside the local solves (SP_FP64 / SP_FP32)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the reduced-precision (SP_FP32) run")
+    ap.add_argument("--fp32-tol", type=float, default=1e-6,
+                    help="local-solver residual tolerance of the SP_FP32 run (its products floor near 1e-6)")
     ap.add_argument("--heff-only", type=int, default=0,
                     help="only run this many H_eff x applications at the centre site, after a 64 MiB "
                          "device copy of known size (for hardware-counter runs), and exit")
@@ -99,7 +104,8 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=args.path)
+        gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=args.path,
+                       precision=args.precision)
         for j in range(1, kc):
             gpu.env_update(j, +1)
         x = torch.tensor(gpu.get_site(kc), dtype=torch.float64, device="cuda")
@@ -112,9 +118,11 @@ def main():
         gpu.close()
         return
 
-    def run(path):
-        log(f"[bench] {wl.name} path={path}: init")
-        gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=path)
+    def run(path, precision="fp64", tol=args.tol):
+        log(f"[bench] {wl.name} path={path} {precision}: init")
+        gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=path,
+                       precision=precision)
+        kw = dict(tol=tol, max_iter=args.max_iter, max_sub=args.max_sub, keep=args.keep)
         for i in range(args.warmup):
             rc, st = gpu.sweep(1, **kw)
             log(f"[bench] {path} warmup sweep {i}: E={st[-1]['theta']:.10f}")
@@ -156,6 +164,18 @@ def main():
                  "energy_after_timed_sweeps": pr["steps"][-1]["theta"],
                  "speedup_site_steps": value / pv, "speedup_heff": pr["heff_ms"] / heff_ms,
                  "max_step_dE_vs_this_path": max(abs(a["theta"] - b["theta"]) for a, b in zip(steps, pr["steps"]))}
+    fp32 = None
+    if args.path == "tiled" and not args.no_fp32:
+        fr = run("tiled", "fp32", args.fp32_tol)
+        fv = len(fr["steps"]) / fr["elapsed"]
+        e32 = fr["steps"][-1]["theta"]
+        fp32 = {"value": fv, "unit": "site steps/s", "solver_tol": args.fp32_tol,
+                "matvecs_per_site_step": float(np.mean([s["matvecs"] for s in fr["steps"]])),
+                "heff_ms": fr["heff_ms"], "heff_tflops": fr["heff_tflops"],
+                "energy_after_timed_sweeps": e32, "dE_vs_fp64_path": e32 - energy,
+                "speedup_site_steps_vs_plain_fp64": (fv / plain["value"]) if plain else None,
+                "note": "H_eff products in FP32 (FP32 environments, FP32 accumulation); Davidson, subspace "
+                        "solve and the per-step Rayleigh quotient in FP64"}
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
     intensity = dom["flops"] / dom["bytes"]
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
@@ -167,7 +187,7 @@ def main():
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel"] = f"{'k_bgemm' if args.path == 'plain' else 'k_heff_fused'} ({dom_name}) at site {kc}"
+    roof["kernel"] = f"{'k_bgemm' if args.path == 'plain' else 'k_heff3'} ({dom_name}) at site {kc}"
     roof["per_launch"] = {k: {"ms": v["ms"], "flops": v["flops"], "bytes": v["bytes"]} for k, v in prof.items()}
 
     out = {
@@ -195,6 +215,7 @@ def main():
         "heff_flops": heff_flops,
         "roofline": roof,
         "plain_fp64": plain,
+        "fp32": fp32,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, mv)

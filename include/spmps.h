@@ -49,6 +49,13 @@ extern "C" {
 #define SP_ENAN (-6)      /* NaN or Inf met in a local solve                    */
 
 #define SP_FP64 0         /* every contraction in FP64 */
+#define SP_FP32 1         /* the H_eff x / N_eff x products inside the local
+                             solves use FP32 copies of the environments,
+                             FP32 tiles and FP32 accumulation (tiled path
+                             only); environment updates, the Davidson
+                             orthogonalisation and subspace solve, and a
+                             final FP64 Rayleigh quotient per site step
+                             (the reported energy) stay FP64           */
 
 #define SP_PATH_TILED 0   /* LDS-tiled dense products over particle-number
                              blocks (zero-padded in M, empty K ranges
@@ -70,7 +77,7 @@ typedef struct sp_problem {
     int twoS;
     int twoM;
     int G;
-    int precision; /* SP_FP64 */
+    int precision; /* SP_FP64 or SP_FP32 */
     int path;      /* SP_PATH_TILED or SP_PATH_PLAIN: same results to rounding */
 } sp_problem;
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libspmps.so")
 SP_OK, SP_ENOCONV, SP_WINEXACT = 0, 1, 2
 SP_EINVAL, SP_ENORM, SP_EHIP, SP_ENOMEM, SP_ESTATE, SP_ENAN = -1, -2, -3, -4, -5, -6
 SP_FP64 = 0
+SP_FP32 = 1
 SP_PATH_TILED, SP_PATH_PLAIN = 0, 1
 
 EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_sweep", "sp_energy",
@@ -75,6 +76,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1703_04789_amd/build.py")
+    # PyTorch ships its own HIP runtime: load it first so that the library
+    # binds to the same runtime instance (one device context per process)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp, ip, dp = ctypes.c_void_p, P(ctypes.c_int), P(ctypes.c_double)
@@ -195,14 +202,15 @@ class SPMPS:
     tensors; ``mpo``: (w, data) as returned by :func:`mpo_hubbard`.
     """
 
-    def __init__(self, table, blocks, mpo, twoS, G, stream=None, path="tiled"):
+    def __init__(self, table, blocks, mpo, twoS, G, stream=None, path="tiled", precision="fp64"):
         import torch
         self._torch = torch
         nsec, sn, s2m, sdim = (np.ascontiguousarray(a, dtype=np.int32) for a in table.flat())
         self._keep = (nsec, sn, s2m, sdim)
         self.L, self.N, self.twoM, self.twoS, self.G = table.L, table.N, table.twoM, twoS, G
         self.path = path
-        prob = _Problem(self.L, 4, self.N, twoS, self.twoM, G, SP_FP64,
+        self.precision = precision
+        prob = _Problem(self.L, 4, self.N, twoS, self.twoM, G, {"fp64": SP_FP64, "fp32": SP_FP32}[precision],
                         {"tiled": SP_PATH_TILED, "plain": SP_PATH_PLAIN}[path])
         w, data = mpo
         w = np.ascontiguousarray(w, dtype=np.int32)

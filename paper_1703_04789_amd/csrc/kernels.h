@@ -136,10 +136,22 @@ struct H3Task {
     int p0[4], p1[4];      // output pieces per sigma
 };
 constexpr int kH3MaxRC = 8;
-void heff3(hipStream_t s, int RC, int lds_doubles, const H3Task* tasks, int ntasks, const H3Blk* blks,
+constexpr int kH3Threads = 256;  // threads per work-group of the fused kernel
+constexpr int kH3SlMax = 16;     // lanes per output column (at most)
+// lds_elems: LDS elements (of the environment type) per work-group
+void heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
            const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms, const H3Piece* pieces,
            const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
            const double* coef, int nc, double* ypart, double* nypart, long long n);
+// the same contraction with FP32 environments, FP32 LDS tiles and FP32
+// accumulation (x, the coefficients and the partial outputs stay FP64 in
+// memory and are converted on the fly)
+void heff3_f32(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
+               const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms,
+               const H3Piece* pieces, const float* Lenv, long long Lsz, const float* Renv, long long Rsz,
+               const double* x, const double* coef, int nc, double* ypart, double* nypart, long long n);
+// out = float(in), n elements
+void to_f32(hipStream_t s, const double* in, float* out, long long n);
 
 void bgemm(hipStream_t s, const BTask* tasks, int ntasks, const BTerm* terms, BufSet bufs,
            const double* coef);

@@ -471,21 +471,22 @@ __global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ ta
     }
 }
 
-template <int RC>
-__global__ __launch_bounds__(kThreads) void k_heff3(
+template <int RC, typename T>
+__global__ __launch_bounds__(kH3Threads) void k_heff3(
     const H3Task* __restrict__ tasks, const H3Blk* __restrict__ blks, const H3Col* __restrict__ cols,
     const H3LSrc* __restrict__ lsrc, const H3Seg* __restrict__ segs, const H3Term* __restrict__ terms,
-    const H3Piece* __restrict__ pieces, const double* __restrict__ Lenv, long long Lsz,
-    const double* __restrict__ Renv, long long Rsz, const double* __restrict__ x, const double* __restrict__ coef,
+    const H3Piece* __restrict__ pieces, const T* __restrict__ Lenv, long long Lsz,
+    const T* __restrict__ Renv, long long Rsz, const double* __restrict__ x, const double* __restrict__ coef,
     int nc, double* __restrict__ ypart, double* __restrict__ nypart, long long n) {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
     const H3Task* __restrict__ tkp = tasks + blockIdx.x;
     const int blk = tkp->blk;
     if (blk < 0) return;
     const int g = tkp->g, r0 = tkp->r0, rows = tkp->rows;
     const H3Blk* __restrict__ bp = blks + blk;
-    const double* __restrict__ L = Lenv + g * Lsz;
-    const double* __restrict__ R = Renv + g * Rsz;
+    const T* __restrict__ L = Lenv + g * Lsz;
+    const T* __restrict__ R = Renv + g * Rsz;
     const double* __restrict__ cf = coef + (long long)g * nc;
     const int tid = threadIdx.x;
 
@@ -495,32 +496,32 @@ __global__ __launch_bounds__(kThreads) void k_heff3(
     for (int q = l0; q < l1; ++q) {
         const H3LSrc src = lsrc[q];
         const int tot = RC * src.ld;
-        const double* __restrict__ lrow = L + src.l_off + (long long)r0 * src.ld;
-        for (int e = tid; e < tot; e += kThreads) lds[src.lds + e] = (e < rows * src.ld) ? lrow[e] : 0.0;
+        const T* __restrict__ lrow = L + src.l_off + (long long)r0 * src.ld;
+        for (int e = tid; e < tot; e += kH3Threads) lds[src.lds + e] = (e < rows * src.ld) ? lrow[e] : T(0);
     }
     __syncthreads();
 
     // phase A: T columns
     const int c0 = bp->c0, c1 = bp->c1;
-    for (int ci = c0 + tid; ci < c1; ci += kThreads) {
+    for (int ci = c0 + tid; ci < c1; ci += kH3Threads) {
         const H3Col c = cols[ci];
-        double acc[RC];
+        T acc[RC];
 #pragma unroll
-        for (int rr = 0; rr < RC; ++rr) acc[rr] = 0.0;
+        for (int rr = 0; rr < RC; ++rr) acc[rr] = T(0);
         const double* __restrict__ xp = x + c.x_off;
-        const double* lp = lds + c.l_lds;
+        const T* lp = lds + c.l_lds;
         int kk = 0;
         for (; kk + 4 <= c.K; kk += 4) {
-            const double x0 = xp[kk * c.x_ld], x1 = xp[(kk + 1) * c.x_ld];
-            const double x2 = xp[(kk + 2) * c.x_ld], x3 = xp[(kk + 3) * c.x_ld];
+            const T x0 = T(xp[kk * c.x_ld]), x1 = T(xp[(kk + 1) * c.x_ld]);
+            const T x2 = T(xp[(kk + 2) * c.x_ld]), x3 = T(xp[(kk + 3) * c.x_ld]);
 #pragma unroll
             for (int rr = 0; rr < RC; ++rr) {
-                const double* l = lp + rr * c.l_ld + kk;
+                const T* l = lp + rr * c.l_ld + kk;
                 acc[rr] = fma(l[3], x3, fma(l[2], x2, fma(l[1], x1, fma(l[0], x0, acc[rr]))));
             }
         }
         for (; kk < c.K; ++kk) {
-            const double xv = xp[kk * c.x_ld];
+            const T xv = T(xp[kk * c.x_ld]);
 #pragma unroll
             for (int rr = 0; rr < RC; ++rr) acc[rr] = fma(lp[rr * c.l_ld + kk], xv, acc[rr]);
         }
@@ -537,11 +538,11 @@ __global__ __launch_bounds__(kThreads) void k_heff3(
         for (int si = s0; si < s1; ++si) {
             const H3Seg S = segs[si];
             const int ne = S.K * RC;
-            for (int e = tid; e < ne; e += kThreads) {
-                double v = 0.0;
+            for (int e = tid; e < ne; e += kH3Threads) {
+                T v = T(0);
                 for (int t = S.t0; t < S.t1; ++t) {
                     const H3Term tm = terms[t];
-                    v = fma(cf[tm.cidx], lds[tm.t_base + e], v);
+                    v = fma(T(cf[tm.cidx]), lds[tm.t_base + e], v);
                 }
                 lds[S.v_off + e] = v;
             }
@@ -550,37 +551,44 @@ __global__ __launch_bounds__(kThreads) void k_heff3(
         // outputs: one group of SL lanes per output column of a piece
         int items = 0;
         for (int p = p0; p < p1; ++p) items += pieces[p].nb;
-        int SL = 16;
-        while (SL > 1 && items * SL > kThreads) SL >>= 1;
+        int SL = kH3SlMax;
+        while (SL > 1 && items * SL > kH3Threads) SL >>= 1;
         const int sl = tid & (SL - 1);
-        for (int it = tid / SL; it < items; it += kThreads / SL) {
+        for (int it = tid / SL; it < items; it += kH3Threads / SL) {
             int p = p0, b = it;
             while (b >= pieces[p].nb) {
                 b -= pieces[p].nb;
                 ++p;
             }
             const H3Piece P = pieces[p];
-            double ay[RC], an[RC];
+            T ay[RC], an[RC];
 #pragma unroll
-            for (int rr = 0; rr < RC; ++rr) ay[rr] = an[rr] = 0.0;
+            for (int rr = 0; rr < RC; ++rr) ay[rr] = an[rr] = T(0);
             for (int si = s0; si < s1; ++si) {
                 const H3Seg S = segs[si];
-                const double* __restrict__ rp = R + S.r_off + (long long)(P.b0 + b) * S.K;
-                const double* vp = lds + S.v_off;
+                const T* __restrict__ rp = R + S.r_off + (long long)(P.b0 + b) * S.K;
+                const T* vp = lds + S.v_off;
                 const int K = S.K;
                 if (S.is_ny) {
-                    for (int k = sl; k < K; k += SL) {
-                        const double r = rp[k];
+                    int k = sl;
+                    for (; k + SL < K; k += 2 * SL) {
+                        const T ra = rp[k], rb = rp[k + SL];
+#pragma unroll
+                        for (int rr = 0; rr < RC; ++rr)
+                            an[rr] = fma(vp[(k + SL) * RC + rr], rb, fma(vp[k * RC + rr], ra, an[rr]));
+                    }
+                    for (; k < K; k += SL) {
+                        const T r = rp[k];
 #pragma unroll
                         for (int rr = 0; rr < RC; ++rr) an[rr] = fma(vp[k * RC + rr], r, an[rr]);
                     }
                 } else {
                     int k = sl;
                     for (; k + 3 * SL < K; k += 4 * SL) {
-                        const double ra = rp[k], rb = rp[k + SL], rc = rp[k + 2 * SL], rd = rp[k + 3 * SL];
+                        const T ra = rp[k], rb = rp[k + SL], rc = rp[k + 2 * SL], rd = rp[k + 3 * SL];
 #pragma unroll
                         for (int rr = 0; rr < RC; ++rr) {
-                            double v = ay[rr];
+                            T v = ay[rr];
                             v = fma(vp[k * RC + rr], ra, v);
                             v = fma(vp[(k + SL) * RC + rr], rb, v);
                             v = fma(vp[(k + 2 * SL) * RC + rr], rc, v);
@@ -588,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_heff3(
                         }
                     }
                     for (; k < K; k += SL) {
-                        const double r = rp[k];
+                        const T r = rp[k];
 #pragma unroll
                         for (int rr = 0; rr < RC; ++rr) ay[rr] = fma(vp[k * RC + rr], r, ay[rr]);
                     }
@@ -607,14 +615,20 @@ __global__ __launch_bounds__(kThreads) void k_heff3(
                 for (int rr = 0; rr < RC; ++rr) {
                     if (rr >= P.rlo && rr < P.rhi) {
                         const long long o = base + (long long)(rr - P.rlo) * P.out_ld;
-                        ypart[o] = ay[rr];
-                        nypart[o] = an[rr];
+                        ypart[o] = double(ay[rr]);
+                        nypart[o] = double(an[rr]);
                     }
                 }
             }
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
+                                                       long long n) {
+    const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e < n) out[e] = float(in[e]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_gather(const int* __restrict__ map, const double* __restrict__ src,
@@ -1021,16 +1035,17 @@ void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufS
            const int* map) {
     if (ntasks > 0) hipLaunchKernelGGL(k_tgemm, dim3(ntasks), dim3(kThreads), 0, s, tasks, segs, bufs, coef, map);
 }
-void heff3(hipStream_t s, int RC, int lds_doubles, const H3Task* tasks, int ntasks, const H3Blk* blks,
-           const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms, const H3Piece* pieces,
-           const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
-           const double* coef, int nc, double* ypart, double* nypart, long long n) {
+template <typename T>
+static void launch_heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
+                         const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms,
+                         const H3Piece* pieces, const T* Lenv, long long Lsz, const T* Renv, long long Rsz,
+                         const double* x, const double* coef, int nc, double* ypart, double* nypart, long long n) {
     if (ntasks <= 0) return;
-    const size_t shm = size_t(lds_doubles) * sizeof(double);
+    const size_t shm = size_t(lds_elems) * sizeof(T);
 #define SPK_HEFF3(R)                                                                                              \
     case R:                                                                                                       \
-        hipLaunchKernelGGL(k_heff3<R>, dim3(ntasks), dim3(kThreads), shm, s, tasks, blks, cols, lsrc, segs, terms, \
-                           pieces, Lenv, Lsz, Renv, Rsz, x, coef, nc, ypart, nypart, n);                                \
+        hipLaunchKernelGGL((k_heff3<R, T>), dim3(ntasks), dim3(kH3Threads), shm, s, tasks, blks, cols, lsrc, segs,   \
+                           terms, pieces, Lenv, Lsz, Renv, Rsz, x, coef, nc, ypart, nypart, n);                     \
         break;
     switch (RC) {
         SPK_HEFF3(1)
@@ -1045,6 +1060,24 @@ void heff3(hipStream_t s, int RC, int lds_doubles, const H3Task* tasks, int ntas
             break;
     }
 #undef SPK_HEFF3
+}
+void heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
+           const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms, const H3Piece* pieces,
+           const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
+           const double* coef, int nc, double* ypart, double* nypart, long long n) {
+    launch_heff3<double>(s, RC, lds_elems, tasks, ntasks, blks, cols, lsrc, segs, terms, pieces, Lenv, Lsz, Renv, Rsz,
+                         x, coef, nc, ypart, nypart, n);
+}
+void heff3_f32(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
+               const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms,
+               const H3Piece* pieces, const float* Lenv, long long Lsz, const float* Renv, long long Rsz,
+               const double* x, const double* coef, int nc, double* ypart, double* nypart, long long n) {
+    launch_heff3<float>(s, RC, lds_elems, tasks, ntasks, blks, cols, lsrc, segs, terms, pieces, Lenv, Lsz, Renv, Rsz,
+                        x, coef, nc, ypart, nypart, n);
+}
+void to_f32(hipStream_t s, const double* in, float* out, long long n) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, in, out, n);
 }
 void gather(hipStream_t s, const int* map, const double* src, double* dst, long long n) {
     if (n > 0) hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, map, src, dst, n);

@@ -342,6 +342,8 @@ struct sp_handle {
     std::vector<SiteInfo> sites;           // index k-1
     std::vector<EnvLayout> env;            // per bond
     std::vector<DArr<double>> envL, envR;  // per bond, G * size
+    std::vector<DArr<float>> envL32, envR32;  // FP32 copies (precision SP_FP32)
+    int precision = SP_FP64;
     std::vector<char> Lvalid, Rvalid;
     DArr<double> mps;
     long long mps_size = 0, max_site = 0;
@@ -543,6 +545,16 @@ void alloc_envs(sp_handle* h) {
     std::vector<double> ones(h->G, 1.0);
     HIPCK(hipMemcpyAsync(h->envL[0].p, ones.data(), h->G * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCK(hipMemcpyAsync(h->envR[L].p, ones.data(), h->G * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    if (h->precision == SP_FP32) {
+        h->envL32.resize(L + 1);
+        h->envR32.resize(L + 1);
+        for (int k = 0; k <= L; ++k) {
+            h->envL32[k].alloc(size_t(h->G) * h->env[k].size);
+            h->envR32[k].alloc(size_t(h->G) * h->env[k].size);
+        }
+        spk::to_f32(h->stream, h->envL[0].p, h->envL32[0].p, h->G);
+        spk::to_f32(h->stream, h->envR[L].p, h->envR32[L].p, h->G);
+    }
     HIPCK(hipStreamSynchronize(h->stream));
     h->Lvalid[0] = 1;
     h->Rvalid[L] = 1;
@@ -1635,7 +1647,8 @@ void check_site(const sp_handle* h, int k) { SP_REQUIRE(k >= 1 && k <= h->L, "si
 // With defer_gsum on the tiled path only the per-quadrature-point partials
 // (h->ypart, h->nypart) are produced and the function returns true: the
 // caller adds them (the Davidson Gram pass does).
-bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, bool defer_gsum = false) {
+bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, bool defer_gsum = false,
+                bool force_fp64 = false) {
     if (!h->Lvalid[k - 1] || !h->Rvalid[k])
         throw SpError(SP_ESTATE, "H_eff needs L[site-1] and R[site+1]; build them with sp_env_update");
     SitePlan& P = h->plan[k - 1];
@@ -1648,9 +1661,14 @@ bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, boo
         return false;
     }
     const int n = int(h->sites[k - 1].size);
-    spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_cols.p, P.dh_lsrc.p,
-               P.dh_segs.p, P.dh_terms.p, P.dh_pieces.p, h->envL[k - 1].p, h->env[k - 1].size, h->envR[k].p,
-               h->env[k].size, x, P.coef.p, P.nc, h->ypart.p, h->nypart.p, n);
+    if (h->precision == SP_FP32 && !force_fp64)
+        spk::heff3_f32(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_cols.p,
+                       P.dh_lsrc.p, P.dh_segs.p, P.dh_terms.p, P.dh_pieces.p, h->envL32[k - 1].p, h->env[k - 1].size,
+                       h->envR32[k].p, h->env[k].size, x, P.coef.p, P.nc, h->ypart.p, h->nypart.p, n);
+    else
+        spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_cols.p, P.dh_lsrc.p,
+                   P.dh_segs.p, P.dh_terms.p, P.dh_pieces.p, h->envL[k - 1].p, h->env[k - 1].size, h->envR[k].p,
+                   h->env[k].size, x, P.coef.p, P.nc, h->ypart.p, h->nypart.p, n);
     if (defer_gsum) return true;
     spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
     return false;
@@ -1672,6 +1690,8 @@ void env_left(sp_handle* h, int k) {
         P.mixl.launch(s, b, P.coef.p);
         P.t_envl.launch(s, b, P.coef.p, P.xmap.p);
     }
+    if (h->precision == SP_FP32)
+        spk::to_f32(s, h->envL[k].p, h->envL32[k].p, (long long)h->G * h->env[k].size);
     h->Lvalid[k] = 1;
     for (int q = k + 1; q <= h->L; ++q) h->Lvalid[q] = 0;
 }
@@ -1692,6 +1712,8 @@ void env_right(sp_handle* h, int k) {
         P.mixr.launch(s, b, P.coef.p);
         P.t_envr.launch(s, b, P.coef.p, P.xmap.p);
     }
+    if (h->precision == SP_FP32)
+        spk::to_f32(s, h->envR[k - 1].p, h->envR32[k - 1].p, (long long)h->G * h->env[k - 1].size);
     h->Rvalid[k - 1] = 1;
     for (int q = 0; q < k - 1; ++q) h->Rvalid[q] = 0;
 }
@@ -1834,6 +1856,23 @@ bool small_solve(int m, const std::vector<double>& Ht, const std::vector<double>
     return true;
 }
 
+// FP64 Rayleigh quotient at site k for the device vector x (any norm):
+// theta = x.H_eff x / x.N_eff x, pnorm = x.N_eff x / x.x; uses dHV[0], dNV[0]
+void rayleigh64(sp_handle* h, int k, const double* x, double& theta, double& pnorm, double& xx_out) {
+    const int n = int(h->sites[k - 1].size);
+    heff_apply(h, k, x, h->dHV.p, h->dNV.p, false, true);
+    double* sm = h->dsmall.p;
+    spk::multidot(h->stream, h->dHV.p, 0, 1, x, n, sm);
+    spk::multidot(h->stream, h->dNV.p, 0, 1, x, n, sm + 1);
+    spk::multidot(h->stream, x, 0, 1, x, n, sm + 2);
+    HIPCK(hipMemcpyAsync(h->pin, sm, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCK(hipStreamSynchronize(h->stream));
+    const double xy = h->pin[0], xny = h->pin[1], xx = h->pin[2];
+    xx_out = xx;
+    theta = xy / xny;
+    pnorm = xx > 0.0 ? xny / xx : 0.0;
+}
+
 DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     const int n = int(h->sites[k - 1].size);
     const int max_sub = std::max(2, o.max_sub);
@@ -1868,7 +1907,10 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
                           h->nypart.p, n, h->G, dn_dev + (lay.pg - lay.out));
         }
     };
-    const double drop = 1e-10, floor_ = 1e-8;
+    // canonical orthogonalisation threshold: with FP32 products the null
+    // space of the projected metric is only resolved to about 1e-7 of its
+    // largest eigenvalue, so directions below 1e-5 are dropped there
+    const double drop = (h->precision == SP_FP32) ? 1e-5 : 1e-10, floor_ = 1e-8;
     DavOut out;
     // fixed-order sums of per-chunk partials (host side)
     auto chunk_total = [&](const double* part, int stride, int idx) {
@@ -1992,6 +2034,15 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     }
     // normalise x and write it into the site
     spk::normalize(s, h->dx.p, site_ptr(h, k), n, nullptr);
+    if (h->precision == SP_FP32) {
+        // the reported energy and norm: one FP64 product with the FP64
+        // environments (the vector itself comes from the FP32 solve)
+        double th, pn, xx;
+        rayleigh64(h, k, site_ptr(h, k), th, pn, xx);
+        if (!std::isfinite(th)) throw SpError(SP_ENAN, "non-finite Rayleigh quotient");
+        out.theta = th;
+        out.pnorm = pn;
+    }
     return out;
 }
 
@@ -2027,7 +2078,8 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         SP_REQUIRE(p && W && bonds && init_blocks && out, "null argument");
         *out = nullptr;
         SP_REQUIRE(p->L >= 1 && p->d == 4, "need L >= 1 and d == 4");
-        SP_REQUIRE(p->precision == SP_FP64, "only SP_FP64 is available");
+        SP_REQUIRE(p->precision == SP_FP64 || p->precision == SP_FP32, "precision must be SP_FP64 or SP_FP32");
+        SP_REQUIRE(p->precision == SP_FP64 || p->path == SP_PATH_TILED, "SP_FP32 needs the tiled path");
         SP_REQUIRE(p->path == SP_PATH_TILED || p->path == SP_PATH_PLAIN, "unknown kernel path");
         SP_REQUIRE(p->N >= 0 && p->N <= 2 * p->L, "N out of range");
         SP_REQUIRE((p->N + p->twoS) % 2 == 0, "N and 2S must have the same parity");
@@ -2038,6 +2090,7 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         std::unique_ptr<sp_handle> h(new sp_handle());
         h->stream = reinterpret_cast<hipStream_t>(hip_stream);
         h->path = p->path;
+        h->precision = p->precision;
         h->L = p->L;
         h->N = p->N;
         h->twoS = p->twoS;
@@ -2200,7 +2253,8 @@ int sp_energy(sp_handle* h, double* E, double* normP) {
         const int k = h->center;
         const int n = int(h->sites[k - 1].size);
         ensure_davidson(h, std::max(h->dav_sub, 2));
-        heff_apply(h, k, site_ptr(h, k), h->dHV.p, h->dNV.p);
+        // always FP64 (also with SP_FP32)
+        heff_apply(h, k, site_ptr(h, k), h->dHV.p, h->dNV.p, false, true);
         double* sm = h->dsmall.p;
         spk::multidot(h->stream, h->dHV.p, 0, 1, site_ptr(h, k), n, sm);
         spk::multidot(h->stream, h->dNV.p, 0, 1, site_ptr(h, k), n, sm + 1);
@@ -2287,10 +2341,7 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
             if (plain) {
                 P.p1.launch(s, b, P.coef.p);
             } else {
-                spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_cols.p,
-                           P.dh_lsrc.p, P.dh_segs.p, P.dh_terms.p, P.dh_pieces.p, h->envL[site - 1].p,
-                           h->env[site - 1].size, h->envR[site].p, h->env[site].size, x, P.coef.p, P.nc, h->ypart.p,
-                           h->nypart.p, n);
+                heff_apply(h, site, x, nullptr, nullptr, true);
             }
             HIPCK(hipEventRecord(ev[1], s));
             if (plain) P.mixl.launch(s, b, P.coef.p);

@@ -7,7 +7,8 @@ import workloads as W
 from oracle import mpo as ompo, mps as omps
 
 
-def make_pair(L, N, twoM, D, twoS, G, U=4.0, t=1.0, seed=1, op="hubbard", oracle=True, path="tiled"):
+def make_pair(L, N, twoM, D, twoS, G, U=4.0, t=1.0, seed=1, op="hubbard", oracle=True, path="tiled",
+              precision="fp64"):
     tab = W.make_block_table(L, N, twoM, D)
     blocks = W.random_blocks(tab, seed)
     if op == "hubbard":
@@ -16,8 +17,9 @@ def make_pair(L, N, twoM, D, twoS, G, U=4.0, t=1.0, seed=1, op="hubbard", oracle
         mine, ref = sp.mpo_s2(L), ompo.s2_mpo(L)
     else:
         mine, ref = sp.mpo_identity(L), ompo.identity_mpo(L)
-    print(f"[case] L={L} N={N} 2M={twoM} D={D} 2S={twoS} G={G} seed={seed} op={op} path={path}", flush=True)
-    gpu = sp.SPMPS(tab, blocks, mine, twoS, G, path=path)
+    print(f"[case] L={L} N={N} 2M={twoM} D={D} 2S={twoS} G={G} seed={seed} op={op} path={path} {precision}",
+          flush=True)
+    gpu = sp.SPMPS(tab, blocks, mine, twoS, G, path=path, precision=precision)
     orc = omps.SPMPSOracle(tab, blocks, ref, twoS, G) if oracle else None
     return tab, gpu, orc
 
