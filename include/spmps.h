@@ -167,6 +167,17 @@ int sp_heff_diag(sp_handle* h, int site, double* dh, double* dn);
  * solve stopped at max_iter.  `r` may be NULL. */
 int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r);
 
+/* Sweeps of n states together (each as sp_sweep would run them, same
+ * results to rounding): every round advances each unfinished state by one
+ * site step; the Davidson iterations of the states run in lockstep, with one
+ * fused H_eff launch (per row count) covering every state and quadrature
+ * point, batched Davidson passes, and the subspace solves on host threads.
+ * All handles: tiled path, one precision, one device and one stream, centre
+ * at site 1, each listed once.  r: n reports (or NULL).  The ability to
+ * run many states at once follows the paper's use of several
+ * broken-symmetry starting guesses (Sec. 3). */
+int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_report* r);
+
 /* Projected energy and norm at the canonical centre:
  * E = <x|H_eff x>/<x|N_eff x>, normP = <x|N_eff x> (the spin-S weight of
  * the underlying MPS when it is normalised).  Host scalars; synchronises. */

@@ -27,7 +27,7 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_destroy", "sp_site_size", "sp_get_site", "sp_set_site", "sp_center", "sp_heff_flops",
            "sp_heff_profile",
            "sp_last_error", "sp_quadrature", "sp_exact_points", "sp_mpo_hubbard", "sp_mpo_s2",
-           "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest"]
+           "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch"]
 
 
 class SpError(RuntimeError):
@@ -91,6 +91,7 @@ def lib():
         "sp_heff_apply": [vp, ctypes.c_int, vp, vp, vp],
         "sp_heff_diag": [vp, ctypes.c_int, vp, vp],
         "sp_sweep": [vp, P(_SweepOpts), P(_SweepReport)],
+        "sp_sweep_batch": [P(vp), ctypes.c_int, P(_SweepOpts), P(_SweepReport)],
         "sp_energy": [vp, dp, dp],
         "sp_destroy": [vp],
         "sp_site_size": [vp, ctypes.c_int, P(ctypes.c_longlong)],
@@ -286,15 +287,29 @@ class SPMPS:
 
     def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8):
         """Run sweeps; returns (status, list of per-step dicts)."""
-        L = self.L
-        cap = max(1, n_sweeps * max(1, 2 * (L - 1)))
-        steps = (_StepReport * cap)()
-        rep = _SweepReport(cap, 0, steps)
-        opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep)
-        rc = _check(lib().sp_sweep(self._h, ctypes.byref(opts), ctypes.byref(rep)))
-        out = []
-        for i in range(rep.n_steps):
-            s = steps[i]
-            out.append(dict(sweep=s.sweep, site=s.site, dir=s.dir, iters=s.iters, converged=bool(s.converged),
-                            matvecs=s.matvecs, theta=s.theta, pnorm=s.pnorm, rnorm=s.rnorm, usec=s.usec))
-        return rc, out
+        return sweep_batch([self], n_sweeps, tol, max_iter, max_sub, keep, _single=True)
+
+
+def _steps_out(steps, n):
+    out = []
+    for i in range(n):
+        s = steps[i]
+        out.append(dict(sweep=s.sweep, site=s.site, dir=s.dir, iters=s.iters, converged=bool(s.converged),
+                        matvecs=s.matvecs, theta=s.theta, pnorm=s.pnorm, rnorm=s.rnorm, usec=s.usec))
+    return out
+
+
+def sweep_batch(states, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, _single=False):
+    """Sweeps of several SPMPS states (``sp_sweep_batch``; one state:
+    ``sp_sweep``).  Returns (status, per-state lists of step dicts); for a
+    single state with _single=True, (status, step dicts)."""
+    opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep)
+    caps = [max(1, n_sweeps * max(1, 2 * (st.L - 1))) for st in states]
+    bufs = [(_StepReport * c)() for c in caps]
+    reps = (_SweepReport * len(states))(*[_SweepReport(c, 0, b) for c, b in zip(caps, bufs)])
+    if _single:
+        rc = _check(lib().sp_sweep(states[0]._h, ctypes.byref(opts), ctypes.byref(reps[0])))
+        return rc, _steps_out(bufs[0], reps[0].n_steps)
+    hs = (ctypes.c_void_p * len(states))(*[st._h.value for st in states])
+    rc = _check(lib().sp_sweep_batch(hs, len(states), ctypes.byref(opts), reps))
+    return rc, [_steps_out(bufs[i], reps[i].n_steps) for i in range(len(states))]

@@ -134,22 +134,42 @@ struct H3Piece {
 struct H3Task {
     int g, blk, r0, rows;  // blk < 0: an empty task (padding)
     int p0[4], p1[4];      // output pieces per sigma
+    int inst, pad0, pad1, pad2;  // instance of a batched launch (0 otherwise)
+};
+// Everything a task needs besides its own descriptor: the plan lists of its
+// site, the environments, x and the outputs of one SP-MPS instance.  Lenv and
+// Renv point to FP64 or FP32 data according to the launch.
+struct H3Inst {
+    const H3Blk* blks;
+    const H3Col* cols;
+    const H3LSrc* lsrc;
+    const H3Seg* segs;
+    const H3Term* terms;
+    const H3Piece* pieces;
+    const void* Lenv;
+    const void* Renv;
+    long long Lsz, Rsz;
+    const double* x;
+    const double* coef;
+    double* ypart;
+    double* nypart;
+    long long n;
+    int nc, pad;
 };
 constexpr int kH3MaxRC = 8;
 constexpr int kH3Threads = 256;  // threads per work-group of the fused kernel
 constexpr int kH3SlMax = 16;     // lanes per output column (at most)
-// lds_elems: LDS elements (of the environment type) per work-group
-void heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
-           const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms, const H3Piece* pieces,
-           const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
-           const double* coef, int nc, double* ypart, double* nypart, long long n);
+// lds_elems: LDS elements (of the environment type) per work-group.  One
+// instance (I, passed by value) or, with insts != nullptr, every task reads
+// its instance from insts[task.inst] (many SP-MPS states in one launch; all
+// tasks of a launch share RC).
+void heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Inst& I,
+           const H3Inst* insts = nullptr);
 // the same contraction with FP32 environments, FP32 LDS tiles and FP32
 // accumulation (x, the coefficients and the partial outputs stay FP64 in
 // memory and are converted on the fly)
-void heff3_f32(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
-               const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms,
-               const H3Piece* pieces, const float* Lenv, long long Lsz, const float* Renv, long long Rsz,
-               const double* x, const double* coef, int nc, double* ypart, double* nypart, long long n);
+void heff3_f32(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Inst& I,
+               const H3Inst* insts = nullptr);
 // out = float(in), n elements
 void to_f32(hipStream_t s, const double* in, float* out, long long n);
 
@@ -179,7 +199,7 @@ void basis_rotate(hipStream_t s, const double* A, long long ld, int m, const dou
 constexpr int kDavChunk = 256;
 constexpr int kGramGroup = 16;  // dots per work-group of the Gram pass
 constexpr int kDavMaxVec = 256;
-inline int dav_chunks(int n) { return (n + kDavChunk - 1) / kDavChunk; }
+__host__ __device__ inline int dav_chunks(int n) { return (n + kDavChunk - 1) / kDavChunk; }
 // aq = (a_0 .. a_{m-1}, theta) (device or mapped host memory); x = V a,
 // u = HV a - theta NV a, t = -u / floor(dh - theta dn); part_x[3 per chunk] =
 // (x.x, u.u, x.(NV a)); part_c[m per chunk] = V_j . t
@@ -202,5 +222,36 @@ void dav_normalize(hipStream_t s, const double* part, int nchunk, const double* 
 void dav_gram(hipStream_t s, double* V, double* HV, double* NV, long long ld, int m, int n, const double* t,
               const double* pn, int npn, double* tnorm, const double* ypart, const double* nypart, long long gstride,
               int G, double* part);
+
+// One instance of the batched Davidson passes (many SP-MPS states advanced
+// together): the arguments of the single-instance passes above, with the
+// partial-sum buffers pc1 (Ritz -> first CGS), pc2 (first -> second CGS)
+// and pn (second CGS -> Gram).  The Gram pass forms V_m from t when
+// from_t != 0 (then ypart must be set).
+struct DavInst {
+    double* V;
+    double* HV;
+    double* NV;
+    long long ld;
+    const double* aq;  // (a_0 .. a_{m-1}, theta), mapped host memory
+    const double* dh;
+    const double* dn;
+    double floor_;
+    double* x;
+    double* t;
+    double* part_x;  // 3 per chunk (mapped host memory)
+    double* pc1;
+    double* pc2;
+    double* pn;
+    double* pg;     // Gram rows, 4m+2 per chunk (mapped host memory)
+    double* tnorm;  // (mapped host memory)
+    const double* ypart;
+    const double* nypart;
+    long long gstride;
+    int G, m, n, active, from_t, mr;  // mr: subspace size of the Ritz pass
+};
+void bdav_ritz(hipStream_t s, const DavInst* insts, int ninst, int max_n);
+void bdav_cgs(hipStream_t s, const DavInst* insts, int ninst, int max_n, int mode);
+void bdav_gram(hipStream_t s, const DavInst* insts, int ninst, int max_n, int max_m);
 
 }  // namespace spk

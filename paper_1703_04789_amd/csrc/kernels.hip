@@ -471,23 +471,29 @@ __global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ ta
     }
 }
 
-template <int RC, typename T>
-__global__ __launch_bounds__(kH3Threads) void k_heff3(
-    const H3Task* __restrict__ tasks, const H3Blk* __restrict__ blks, const H3Col* __restrict__ cols,
-    const H3LSrc* __restrict__ lsrc, const H3Seg* __restrict__ segs, const H3Term* __restrict__ terms,
-    const H3Piece* __restrict__ pieces, const T* __restrict__ Lenv, long long Lsz,
-    const T* __restrict__ Renv, long long Rsz, const double* __restrict__ x, const double* __restrict__ coef,
-    int nc, double* __restrict__ ypart, double* __restrict__ nypart, long long n) {
+template <int RC, typename T, bool BATCH>
+__global__ __launch_bounds__(kH3Threads) void k_heff3(const H3Task* __restrict__ tasks,
+                                                        const H3Inst* __restrict__ insts, H3Inst one) {
     extern __shared__ double lds_raw[];
     T* lds = reinterpret_cast<T*>(lds_raw);
     const H3Task* __restrict__ tkp = tasks + blockIdx.x;
     const int blk = tkp->blk;
     if (blk < 0) return;
+    const H3Inst I = BATCH ? insts[tkp->inst] : one;
+    const H3Col* __restrict__ cols = I.cols;
+    const H3LSrc* __restrict__ lsrc = I.lsrc;
+    const H3Seg* __restrict__ segs = I.segs;
+    const H3Term* __restrict__ terms = I.terms;
+    const H3Piece* __restrict__ pieces = I.pieces;
+    const double* __restrict__ x = I.x;
+    double* __restrict__ ypart = I.ypart;
+    double* __restrict__ nypart = I.nypart;
+    const long long n = I.n;
     const int g = tkp->g, r0 = tkp->r0, rows = tkp->rows;
-    const H3Blk* __restrict__ bp = blks + blk;
-    const T* __restrict__ L = Lenv + g * Lsz;
-    const T* __restrict__ R = Renv + g * Rsz;
-    const double* __restrict__ cf = coef + (long long)g * nc;
+    const H3Blk* __restrict__ bp = I.blks + blk;
+    const T* __restrict__ L = static_cast<const T*>(I.Lenv) + g * I.Lsz;
+    const T* __restrict__ R = static_cast<const T*>(I.Renv) + g * I.Rsz;
+    const double* __restrict__ cf = I.coef + (long long)g * I.nc;
     const int tid = threadIdx.x;
 
     // stage the chunk's rows of the left-environment blocks (zero rows past
@@ -749,13 +755,13 @@ __device__ inline void group_range(int m, int jg, int& j0, int& j1) {
     j1 = min(m, j0 + per);
 }
 
-__global__ __launch_bounds__(kDavWide) void k_dav_ritz(const double* __restrict__ V, const double* __restrict__ HV,
+__device__ inline void dav_ritz_body(const double* __restrict__ V, const double* __restrict__ HV,
                                                          const double* __restrict__ NV, long long ld, int m,
                                                          const double* __restrict__ aq,
                                                          const double* __restrict__ dh,
                                                          const double* __restrict__ dn, int n, double floor_,
                                                          double* __restrict__ x, double* __restrict__ t,
-                                                         double* __restrict__ part_x, double* __restrict__ part_c) {
+                                                         double* __restrict__ part_x, double* __restrict__ part_c, int chunk) {
     __shared__ double sa[kDavMaxVec + 1];
     __shared__ double red[3][kDavGroups][kDavChunk];
     __shared__ double ts[kDavChunk];
@@ -764,7 +770,7 @@ __global__ __launch_bounds__(kDavWide) void k_dav_ritz(const double* __restrict_
     __syncthreads();
     const double theta = sa[m];
     const int el = threadIdx.x & (kDavChunk - 1), jg = threadIdx.x / kDavChunk;
-    const int e0 = blockIdx.x * kDavChunk;
+    const int e0 = chunk * kDavChunk;
     const int e = e0 + el;
     {
         double xv = 0.0, hv = 0.0, nv = 0.0;
@@ -830,15 +836,15 @@ __global__ __launch_bounds__(kDavWide) void k_dav_ritz(const double* __restrict_
     __syncthreads();
     if (threadIdx.x < 3) {
         const int c = threadIdx.x;
-        part_x[3 * blockIdx.x + c] = (wsum[0][c] + wsum[1][c]) + (wsum[2][c] + wsum[3][c]);
+        part_x[3 * chunk + c] = (wsum[0][c] + wsum[1][c]) + (wsum[2][c] + wsum[3][c]);
     }
-    chunk_dots<kDavWaves>(V, ld, m, e0, n, ts, part_c + (long long)blockIdx.x * m);
+    chunk_dots<kDavWaves>(V, ld, m, e0, n, ts, part_c + (long long)chunk * m);
 }
 
-__global__ __launch_bounds__(kDavWide) void k_dav_cgs(const double* __restrict__ V, long long ld, int m,
+__device__ inline void dav_cgs_body(const double* __restrict__ V, long long ld, int m,
                                                         int m_dot, const double* __restrict__ part_in, int nchunk,
                                                         double* __restrict__ t, int n,
-                                                        double* __restrict__ part_out, int mode) {
+                                                        double* __restrict__ part_out, int mode, int chunk) {
     __shared__ double c[kDavMaxVec];
     __shared__ double wred[kDavWaves][64];
     __shared__ double red[kDavGroups][kDavChunk];
@@ -846,7 +852,7 @@ __global__ __launch_bounds__(kDavWide) void k_dav_cgs(const double* __restrict__
     __shared__ double wsum[4];
     reduce_partials<kDavWaves>(part_in, nchunk, m, m, wred, c);
     const int el = threadIdx.x & (kDavChunk - 1), jg = threadIdx.x / kDavChunk;
-    const int e0 = blockIdx.x * kDavChunk;
+    const int e0 = chunk * kDavChunk;
     const int e = e0 + el;
     {
         double s = 0.0;
@@ -876,14 +882,14 @@ __global__ __launch_bounds__(kDavWide) void k_dav_cgs(const double* __restrict__
     }
     if (mode == 0) {
         __syncthreads();
-        chunk_dots<kDavWaves>(V, ld, m_dot, e0, n, ts, part_out + (long long)blockIdx.x * m_dot);
+        chunk_dots<kDavWaves>(V, ld, m_dot, e0, n, ts, part_out + (long long)chunk * m_dot);
     } else {
         // norm partial (the first four waves hold the chunk)
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         double ss = wave_sum(v * v);
         if (jg == 0 && lane == 0) wsum[wave] = ss;
         __syncthreads();
-        if (threadIdx.x == 0) part_out[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+        if (threadIdx.x == 0) part_out[chunk] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
     }
 }
 
@@ -908,20 +914,20 @@ __global__ __launch_bounds__(kThreads) void k_dav_normalize(const double* __rest
 // H_eff t and N_eff t are the sums over the G quadrature partials (ascending
 // g) and stored, scaled, in HV_m, NV_m; else (t must then be nullptr) they
 // are read from HV_m, NV_m as they are.
-__global__ __launch_bounds__(kThreads) void k_dav_gram(double* __restrict__ V, double* __restrict__ HV,
+__device__ inline void dav_gram_body(double* __restrict__ V, double* __restrict__ HV,
                                                          double* __restrict__ NV, long long ld, int m, int n,
                                                          const double* __restrict__ t,
                                                          const double* __restrict__ pn, int npn,
                                                          double* __restrict__ tnorm,
                                                          const double* __restrict__ ypart,
                                                          const double* __restrict__ nypart, long long gstride, int G,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part, int chunk, int grp) {
     __shared__ double vs[kDavChunk], hs[kDavChunk], ns[kDavChunk];
     __shared__ double wred[4][64];
     __shared__ double tot[1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nd = 4 * m + 2;
-    const int e0 = blockIdx.x * kDavChunk;
+    const int e0 = chunk * kDavChunk;
     const int e = e0 + threadIdx.x;
     const int nval = min(kDavChunk, n - e0);
     double inv = 1.0;
@@ -929,7 +935,7 @@ __global__ __launch_bounds__(kThreads) void k_dav_gram(double* __restrict__ V, d
         reduce_partials<4>(pn, npn, 1, 1, wred, tot);
         const double nrm = sqrt(tot[0]);
         inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *tnorm = nrm;
+        if (chunk == 0 && grp == 0 && threadIdx.x == 0) *tnorm = nrm;
     }
     double vm = 0.0, hm = 0.0, nm = 0.0;
     if (e < n) {
@@ -968,14 +974,14 @@ __global__ __launch_bounds__(kThreads) void k_dav_gram(double* __restrict__ V, d
     __syncthreads();
     // every work-group has read what it needs of HV_m, NV_m (only its own
     // chunk, by its own threads) before the y == 0 groups overwrite them
-    if (blockIdx.y == 0 && e < n && ypart) {
+    if (grp == 0 && e < n && ypart) {
         const long long o = (long long)m * ld + e;
         if (t) V[o] = vm;
         HV[o] = hm;
         NV[o] = nm;
     }
-    double* out = part + (long long)blockIdx.x * nd;
-    const int d0 = blockIdx.y * kGramGroup;
+    double* out = part + (long long)chunk * nd;
+    const int d0 = grp * kGramGroup;
     const int d1 = min(nd, d0 + kGramGroup);
     // d <= m: V_d.HV_m; then V_j.NV_m (j <= m); HV_j.V_m (j < m); NV_j.V_m (j < m).
     // V_m itself is taken from LDS (it may be being stored right now).
@@ -1027,6 +1033,59 @@ __global__ __launch_bounds__(kThreads) void k_dav_gram(double* __restrict__ V, d
     }
 }
 
+__global__ __launch_bounds__(kDavWide) void k_dav_ritz(const double* __restrict__ V, const double* __restrict__ HV,
+                                                         const double* __restrict__ NV, long long ld, int m,
+                                                         const double* __restrict__ aq,
+                                                         const double* __restrict__ dh,
+                                                         const double* __restrict__ dn, int n, double floor_,
+                                                         double* __restrict__ x, double* __restrict__ t,
+                                                         double* __restrict__ part_x, double* __restrict__ part_c) {
+    dav_ritz_body(V, HV, NV, ld, m, aq, dh, dn, n, floor_, x, t, part_x, part_c, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kDavWide) void k_dav_cgs(const double* __restrict__ V, long long ld, int m,
+                                                        int m_dot, const double* __restrict__ part_in, int nchunk,
+                                                        double* __restrict__ t, int n,
+                                                        double* __restrict__ part_out, int mode) {
+    dav_cgs_body(V, ld, m, m_dot, part_in, nchunk, t, n, part_out, mode, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_dav_gram(double* __restrict__ V, double* __restrict__ HV,
+                                                         double* __restrict__ NV, long long ld, int m, int n,
+                                                         const double* __restrict__ t,
+                                                         const double* __restrict__ pn, int npn,
+                                                         double* __restrict__ tnorm,
+                                                         const double* __restrict__ ypart,
+                                                         const double* __restrict__ nypart, long long gstride, int G,
+                                                         double* __restrict__ part) {
+    dav_gram_body(V, HV, NV, ld, m, n, t, pn, npn, tnorm, ypart, nypart, gstride, G, part, blockIdx.x, blockIdx.y);
+}
+
+// batched passes: blockIdx.y (blockIdx.z for the Gram pass) is the instance;
+// work-groups past an instance's chunk or dot count, or of an inactive
+// instance, exit at once
+__global__ __launch_bounds__(kDavWide) void k_bdav_ritz(const DavInst* __restrict__ insts) {
+    const DavInst I = insts[blockIdx.y];
+    if (!I.active || (int)blockIdx.x >= dav_chunks(I.n)) return;
+    dav_ritz_body(I.V, I.HV, I.NV, I.ld, I.mr, I.aq, I.dh, I.dn, I.n, I.floor_, I.x, I.t, I.part_x, I.pc1, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kDavWide) void k_bdav_cgs(const DavInst* __restrict__ insts, int mode) {
+    const DavInst I = insts[blockIdx.y];
+    if (!I.active || (int)blockIdx.x >= dav_chunks(I.n)) return;
+    const int nch = dav_chunks(I.n);
+    if (mode == 0) dav_cgs_body(I.V, I.ld, I.m, I.m, I.pc1, nch, I.t, I.n, I.pc2, 0, blockIdx.x);
+    else dav_cgs_body(I.V, I.ld, I.m, 0, I.pc2, nch, I.t, I.n, I.pn, 1, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_bdav_gram(const DavInst* __restrict__ insts) {
+    const DavInst I = insts[blockIdx.z];
+    const int nd = 4 * I.m + 2;
+    if (!I.active || (int)blockIdx.x >= dav_chunks(I.n) || (int)blockIdx.y * kGramGroup >= nd) return;
+    dav_gram_body(I.V, I.HV, I.NV, I.ld, I.m, I.n, I.from_t ? I.t : nullptr, I.pn, dav_chunks(I.n), I.tnorm,
+                  I.ypart, I.nypart, I.gstride, I.G, I.pg, blockIdx.x, blockIdx.y);
+}
+
 inline int nblk(int n) { return (n + kThreads - 1) / kThreads; }
 
 }  // namespace
@@ -1036,16 +1095,16 @@ void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufS
     if (ntasks > 0) hipLaunchKernelGGL(k_tgemm, dim3(ntasks), dim3(kThreads), 0, s, tasks, segs, bufs, coef, map);
 }
 template <typename T>
-static void launch_heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
-                         const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms,
-                         const H3Piece* pieces, const T* Lenv, long long Lsz, const T* Renv, long long Rsz,
-                         const double* x, const double* coef, int nc, double* ypart, double* nypart, long long n) {
+static void launch_heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Inst& I,
+                         const H3Inst* insts) {
     if (ntasks <= 0) return;
     const size_t shm = size_t(lds_elems) * sizeof(T);
-#define SPK_HEFF3(R)                                                                                              \
-    case R:                                                                                                       \
-        hipLaunchKernelGGL((k_heff3<R, T>), dim3(ntasks), dim3(kH3Threads), shm, s, tasks, blks, cols, lsrc, segs,   \
-                           terms, pieces, Lenv, Lsz, Renv, Rsz, x, coef, nc, ypart, nypart, n);                     \
+#define SPK_HEFF3(R)                                                                                               \
+    case R:                                                                                                        \
+        if (insts)                                                                                                 \
+            hipLaunchKernelGGL((k_heff3<R, T, true>), dim3(ntasks), dim3(kH3Threads), shm, s, tasks, insts, I);    \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_heff3<R, T, false>), dim3(ntasks), dim3(kH3Threads), shm, s, tasks, insts, I);   \
         break;
     switch (RC) {
         SPK_HEFF3(1)
@@ -1061,19 +1120,13 @@ static void launch_heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tas
     }
 #undef SPK_HEFF3
 }
-void heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
-           const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms, const H3Piece* pieces,
-           const double* Lenv, long long Lsz, const double* Renv, long long Rsz, const double* x,
-           const double* coef, int nc, double* ypart, double* nypart, long long n) {
-    launch_heff3<double>(s, RC, lds_elems, tasks, ntasks, blks, cols, lsrc, segs, terms, pieces, Lenv, Lsz, Renv, Rsz,
-                         x, coef, nc, ypart, nypart, n);
+void heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Inst& I,
+           const H3Inst* insts) {
+    launch_heff3<double>(s, RC, lds_elems, tasks, ntasks, I, insts);
 }
-void heff3_f32(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Blk* blks,
-               const H3Col* cols, const H3LSrc* lsrc, const H3Seg* segs, const H3Term* terms,
-               const H3Piece* pieces, const float* Lenv, long long Lsz, const float* Renv, long long Rsz,
-               const double* x, const double* coef, int nc, double* ypart, double* nypart, long long n) {
-    launch_heff3<float>(s, RC, lds_elems, tasks, ntasks, blks, cols, lsrc, segs, terms, pieces, Lenv, Lsz, Renv, Rsz,
-                        x, coef, nc, ypart, nypart, n);
+void heff3_f32(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Inst& I,
+               const H3Inst* insts) {
+    launch_heff3<float>(s, RC, lds_elems, tasks, ntasks, I, insts);
 }
 void to_f32(hipStream_t s, const double* in, float* out, long long n) {
     if (n > 0)
@@ -1141,6 +1194,19 @@ void dav_gram(hipStream_t s, double* V, double* HV, double* NV, long long ld, in
     const int nd = 4 * m + 2;
     hipLaunchKernelGGL(k_dav_gram, dim3(dav_chunks(n), (nd + kGramGroup - 1) / kGramGroup), dim3(kThreads), 0, s, V, HV,
                        NV, ld, m, n, t, pn, npn, tnorm, ypart, nypart, gstride, G, part);
+}
+
+void bdav_ritz(hipStream_t s, const DavInst* insts, int ninst, int max_n) {
+    if (ninst > 0) hipLaunchKernelGGL(k_bdav_ritz, dim3(dav_chunks(max_n), ninst), dim3(kDavWide), 0, s, insts);
+}
+void bdav_cgs(hipStream_t s, const DavInst* insts, int ninst, int max_n, int mode) {
+    if (ninst > 0) hipLaunchKernelGGL(k_bdav_cgs, dim3(dav_chunks(max_n), ninst), dim3(kDavWide), 0, s, insts, mode);
+}
+void bdav_gram(hipStream_t s, const DavInst* insts, int ninst, int max_n, int max_m) {
+    const int nd = 4 * max_m + 2;
+    if (ninst > 0)
+        hipLaunchKernelGGL(k_bdav_gram, dim3(dav_chunks(max_n), (nd + kGramGroup - 1) / kGramGroup, ninst),
+                           dim3(kThreads), 0, s, insts);
 }
 
 }  // namespace spk

@@ -24,6 +24,8 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <condition_variable>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -32,8 +34,10 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host_linalg.h"
@@ -1644,6 +1648,34 @@ spk::BufSet bufset(sp_handle* h, int k, const double* x, double* y, double* ny, 
 
 void check_site(const sp_handle* h, int k) { SP_REQUIRE(k >= 1 && k <= h->L, "site out of range"); }
 
+// the fused-kernel instance descriptor of site k applied to x
+spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32) {
+    SitePlan& P = h->plan[k - 1];
+    spk::H3Inst I{};
+    I.blks = P.dh_blks.p;
+    I.cols = P.dh_cols.p;
+    I.lsrc = P.dh_lsrc.p;
+    I.segs = P.dh_segs.p;
+    I.terms = P.dh_terms.p;
+    I.pieces = P.dh_pieces.p;
+    if (f32) {
+        I.Lenv = h->envL32[k - 1].p;
+        I.Renv = h->envR32[k].p;
+    } else {
+        I.Lenv = h->envL[k - 1].p;
+        I.Renv = h->envR[k].p;
+    }
+    I.Lsz = h->env[k - 1].size;
+    I.Rsz = h->env[k].size;
+    I.x = x;
+    I.coef = P.coef.p;
+    I.ypart = h->ypart.p;
+    I.nypart = h->nypart.p;
+    I.n = h->sites[k - 1].size;
+    I.nc = P.nc;
+    return I;
+}
+
 // With defer_gsum on the tiled path only the per-quadrature-point partials
 // (h->ypart, h->nypart) are produced and the function returns true: the
 // caller adds them (the Davidson Gram pass does).
@@ -1661,14 +1693,10 @@ bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, boo
         return false;
     }
     const int n = int(h->sites[k - 1].size);
-    if (h->precision == SP_FP32 && !force_fp64)
-        spk::heff3_f32(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_cols.p,
-                       P.dh_lsrc.p, P.dh_segs.p, P.dh_terms.p, P.dh_pieces.p, h->envL32[k - 1].p, h->env[k - 1].size,
-                       h->envR32[k].p, h->env[k].size, x, P.coef.p, P.nc, h->ypart.p, h->nypart.p, n);
-    else
-        spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), P.dh_blks.p, P.dh_cols.p, P.dh_lsrc.p,
-                   P.dh_segs.p, P.dh_terms.p, P.dh_pieces.p, h->envL[k - 1].p, h->env[k - 1].size, h->envR[k].p,
-                   h->env[k].size, x, P.coef.p, P.nc, h->ypart.p, h->nypart.p, n);
+    const bool f32 = h->precision == SP_FP32 && !force_fp64;
+    const spk::H3Inst I = heff_inst(h, k, x, f32);
+    if (f32) spk::heff3_f32(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
+    else spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
     if (defer_gsum) return true;
     spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
     return false;
@@ -2046,6 +2074,473 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     return out;
 }
 
+// ---------------------------------------------------------------------------
+// Batched sweeps: many SP-MPS states advanced together, one site step of
+// each per round.  Within a round the Davidson iterations of all states run
+// in lockstep: their subspace solves on a host thread pool, then one Ritz,
+// two CGS and one Gram launch for all of them and one fused H_eff launch
+// per row count (every state's quadrature points in the same launch).
+
+class Pool {
+  public:
+    explicit Pool(int n) {
+        for (int i = 0; i < n; ++i) th_.emplace_back([this] { loop(); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    // fn(i) for i < n on the pool and the calling thread
+    void run(int n, const std::function<void(int)>& fn) {
+        if (th_.empty() || n <= 1) {
+            for (int i = 0; i < n; ++i) fn(i);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            job_ = &fn;
+            njobs_ = n;
+            next_ = 0;
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (int i = next_.fetch_add(1); i < n; i = next_.fetch_add(1)) fn(i);
+        std::unique_lock<std::mutex> l(mu_);
+        done_.wait(l, [&] { return busy_ == 0; });
+        job_ = nullptr;
+    }
+
+  private:
+    void loop() {
+        long seen = 0;
+        for (;;) {
+            const std::function<void(int)>* fn;
+            int nj;
+            {
+                std::unique_lock<std::mutex> l(mu_);
+                cv_.wait(l, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                fn = job_;
+                nj = njobs_;
+                if (!fn) continue;
+                ++busy_;
+            }
+            for (int i = next_.fetch_add(1); i < nj; i = next_.fetch_add(1)) (*fn)(i);
+            {
+                std::lock_guard<std::mutex> l(mu_);
+                if (--busy_ == 0) done_.notify_all();
+            }
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)>* job_ = nullptr;
+    int njobs_ = 0, busy_ = 0;
+    std::atomic<int> next_{0};
+    long gen_ = 0;
+    bool stop_ = false;
+};
+
+struct BatchState {
+    sp_handle* h = nullptr;
+    std::vector<std::pair<int, int>> order;  // (site, dir) of every step
+    size_t step = 0;
+    int sweep_len = 1;
+    // Davidson state of the current step
+    int k = 0, n = 0, nch = 0, m = 0, it = 0, rk = 0, nk = 0;
+    bool in_solve = false, last = false, restart = false;
+    double theta = 0;
+    std::vector<double> Ht, Nt, a, Xc, Qk;
+    DavOut out;
+    std::chrono::steady_clock::time_point t0;
+    std::string err;
+    int err_code = 0;
+};
+
+struct BatchBufs {
+    DArr<spk::H3Task> tasks;
+    DArr<spk::H3Inst> insts;
+    DArr<spk::DavInst> dav;
+    double* pin = nullptr;  // staging of the per-round uploads
+    size_t pin_n = 0;
+    ~BatchBufs() {
+        if (pin) (void)hipHostFree(pin);
+    }
+    double* staging(size_t bytes) {
+        const size_t n = (bytes + 7) / 8;
+        if (pin_n < n) {
+            if (pin) HIPCK(hipHostFree(pin));
+            pin = nullptr;
+            HIPCK(hipHostMalloc(&pin, n * 8, hipHostMallocDefault));
+            pin_n = n;
+        }
+        return pin;
+    }
+};
+
+// one fused H_eff application for every state in `idx` (tiled path), x =
+// V_0 (from_v0) or t; outputs stay as per-g partials in each handle
+void batch_heff(std::vector<BatchState>& B, const std::vector<int>& idx, bool from_v0, BatchBufs& bb,
+                hipStream_t s) {
+    if (idx.empty()) return;
+    std::vector<spk::H3Inst> insts(idx.size());
+    std::map<int, std::vector<spk::H3Task>> by_rc;
+    std::map<int, int> lds_by_rc;
+    const bool f32 = B[idx[0]].h->precision == SP_FP32;
+    for (size_t q = 0; q < idx.size(); ++q) {
+        BatchState& st = B[idx[q]];
+        sp_handle* h = st.h;
+        insts[q] = heff_inst(h, st.k, from_v0 ? h->dV.p : h->dt.p, f32);
+        const SitePlan& P = h->plan[st.k - 1];
+        auto& v = by_rc[P.h_rows];
+        for (spk::H3Task t : P.h_tasks) {
+            if (t.blk < 0) continue;
+            t.inst = int(q);
+            v.push_back(t);
+        }
+        lds_by_rc[P.h_rows] = std::max(lds_by_rc[P.h_rows], P.h_lds);
+    }
+    size_t ntask = 0;
+    for (auto& kv : by_rc) ntask += kv.second.size();
+    const size_t bytes = insts.size() * sizeof(spk::H3Inst) + ntask * sizeof(spk::H3Task);
+    char* stage = reinterpret_cast<char*>(bb.staging(bytes));
+    // the previous round's launches read the staging buffer through their
+    // copies only, which the stream has completed before this host code runs
+    std::memcpy(stage, insts.data(), insts.size() * sizeof(spk::H3Inst));
+    size_t off = insts.size() * sizeof(spk::H3Inst);
+    for (auto& kv : by_rc) {
+        std::memcpy(stage + off, kv.second.data(), kv.second.size() * sizeof(spk::H3Task));
+        off += kv.second.size() * sizeof(spk::H3Task);
+    }
+    if (bb.insts.n < insts.size()) bb.insts.alloc(insts.size());
+    if (bb.tasks.n < ntask) bb.tasks.alloc(ntask);
+    HIPCK(hipMemcpyAsync(bb.insts.p, stage, insts.size() * sizeof(spk::H3Inst), hipMemcpyHostToDevice, s));
+    HIPCK(hipMemcpyAsync(bb.tasks.p, stage + insts.size() * sizeof(spk::H3Inst), ntask * sizeof(spk::H3Task),
+                         hipMemcpyHostToDevice, s));
+    size_t t0 = 0;
+    for (auto& kv : by_rc) {
+        const int nt = int(kv.second.size());
+        if (f32) spk::heff3_f32(s, kv.first, lds_by_rc[kv.first], bb.tasks.p + t0, nt, insts[0], bb.insts.p);
+        else spk::heff3(s, kv.first, lds_by_rc[kv.first], bb.tasks.p + t0, nt, insts[0], bb.insts.p);
+        t0 += nt;
+    }
+    // the staging buffer is rewritten by the next call only after the
+    // caller has synchronised the stream (once per round and iteration)
+}
+
+void batch_dav_upload(std::vector<spk::DavInst>& D, BatchBufs& bb, hipStream_t s) {
+    if (bb.dav.n < D.size()) bb.dav.alloc(D.size());
+    HIPCK(hipMemcpyAsync(bb.dav.p, D.data(), D.size() * sizeof(spk::DavInst), hipMemcpyHostToDevice, s));
+}
+
+spk::DavInst dav_inst(BatchState& st) {
+    sp_handle* h = st.h;
+    const long long ld = h->ld;
+    const DavLayout lay(h->dav_sub, spk::dav_chunks(int(ld)));
+    double* sm = h->dsmall.p;
+    double* dn_dev = h->pin_dev;
+    spk::DavInst I{};
+    I.V = h->dV.p;
+    I.HV = h->dHV.p;
+    I.NV = h->dNV.p;
+    I.ld = ld;
+    I.aq = h->pin_up_dev + lay.a;
+    I.dh = h->ddh.p;
+    I.dn = h->ddn.p;
+    I.floor_ = 1e-8;
+    I.x = h->dx.p;
+    I.t = h->dt.p;
+    I.part_x = dn_dev + (lay.px - lay.out);
+    I.pc1 = sm + lay.pc1;
+    I.pc2 = sm + lay.pc2;
+    I.pn = sm + lay.pn;
+    I.pg = dn_dev + (lay.pg - lay.out);
+    I.tnorm = dn_dev + (lay.tn - lay.out);
+    I.ypart = h->ypart.p;
+    I.nypart = h->nypart.p;
+    I.gstride = st.n;
+    I.G = h->G;
+    I.m = st.m;
+    I.mr = st.m;
+    I.n = st.n;
+    I.active = 1;
+    I.from_t = 1;
+    return I;
+}
+
+int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<sp_sweep_report*>& reps) {
+    hipStream_t s = B[0].h->stream;
+    const int max_sub = std::max(2, o.max_sub);
+    const int keep = std::max(1, std::min(o.keep, max_sub - 1));
+    const int max_iter = std::max(1, o.max_iter);
+    BatchBufs bb;
+    const int nthreads = std::max(0, std::min<int>(int(B.size()), std::min(16u, std::thread::hardware_concurrency())) - 1);
+    Pool pool(nthreads);
+    int status = SP_OK;
+    for (auto& st : B) ensure_davidson(st.h, max_sub);
+    for (;;) {
+        std::vector<int> act;
+        for (size_t i = 0; i < B.size(); ++i)
+            if (B[i].step < B[i].order.size()) act.push_back(int(i));
+        if (act.empty()) break;
+        // step start: diagonal, V_0, first product and Gram entries
+        for (int i : act) {
+            BatchState& st = B[i];
+            sp_handle* h = st.h;
+            st.k = st.order[st.step].first;
+            st.n = int(h->sites[st.k - 1].size);
+            st.nch = spk::dav_chunks(st.n);
+            st.m = 0;
+            st.it = 0;
+            st.in_solve = true;
+            st.out = DavOut{};
+            st.t0 = std::chrono::steady_clock::now();
+            const int S = max_sub + 1;
+            st.Ht.assign(size_t(S) * S, 0.0);
+            st.Nt.assign(size_t(S) * S, 0.0);
+            diag(h, st.k, h->ddh.p, h->ddn.p);
+            spk::normalize(s, site_ptr(h, st.k), h->dV.p, st.n, nullptr);
+        }
+        batch_heff(B, act, true, bb, s);
+        {
+            std::vector<spk::DavInst> D;
+            int max_n = 0;
+            for (int i : act) {
+                spk::DavInst I = dav_inst(B[i]);
+                I.from_t = 0;
+                D.push_back(I);
+                max_n = std::max(max_n, B[i].n);
+            }
+            batch_dav_upload(D, bb, s);
+            spk::bdav_gram(s, bb.dav.p, int(D.size()), max_n, 0);
+        }
+        HIPCK(hipStreamSynchronize(s));
+        auto chunk_total = [](const double* part, int nch, int stride, int idx) {
+            double acc = 0.0;
+            for (int q = 0; q < nch; ++q) acc += part[(size_t)q * stride + idx];
+            return acc;
+        };
+        for (int i : act) {
+            BatchState& st = B[i];
+            sp_handle* h = st.h;
+            const DavLayout lay(h->dav_sub, spk::dav_chunks(int(h->ld)));
+            const double* pg = h->pin + (lay.pg - lay.out);
+            st.Ht[0] = chunk_total(pg, st.nch, 2, 0);
+            st.Nt[0] = chunk_total(pg, st.nch, 2, 1);
+            st.m = 1;
+            st.out.matvecs = 1;
+        }
+        // lockstep Davidson iterations
+        const double drop64 = 1e-10, drop32 = 1e-5;
+        for (int it = 1; it <= max_iter; ++it) {
+            std::vector<int> sol;
+            for (int i : act)
+                if (B[i].in_solve) sol.push_back(i);
+            if (sol.empty()) break;
+            pool.run(int(sol.size()), [&](int q) {
+                BatchState& st = B[sol[q]];
+                try {
+                    const int S = max_sub + 1;
+                    st.it = it;
+                    st.out.iters = it;
+                    st.last = (it == max_iter);
+                    st.restart = !st.last && st.m >= max_sub;
+                    const double drop = st.h->precision == SP_FP32 ? drop32 : drop64;
+                    if (!small_solve(st.m, st.Ht, st.Nt, S, drop, st.restart, st.theta, st.a, st.Xc, st.rk))
+                        throw SpError(SP_ENORM, "projected norm vanishes in the search space");
+                    st.out.theta = st.theta;
+                    st.nk = 0;
+                    if (st.restart) {
+                        const int m = st.m;
+                        st.nk = std::min(keep, st.rk);
+                        st.Qk.assign(size_t(m) * st.nk, 0.0);
+                        for (int c = 0; c < st.nk; ++c) {
+                            std::vector<double> v(m);
+                            for (int r = 0; r < m; ++r) v[r] = st.Xc[r * st.rk + c];
+                            for (int p = 0; p < c; ++p) {
+                                double d = 0.0;
+                                for (int r = 0; r < m; ++r) d += st.Qk[r * st.nk + p] * v[r];
+                                for (int r = 0; r < m; ++r) v[r] -= d * st.Qk[r * st.nk + p];
+                            }
+                            double nr = 0.0;
+                            for (int r = 0; r < m; ++r) nr += v[r] * v[r];
+                            nr = std::sqrt(nr);
+                            for (int r = 0; r < m; ++r) st.Qk[r * st.nk + c] = v[r] / nr;
+                        }
+                    }
+                    sp_handle* h = st.h;
+                    const DavLayout lay(h->dav_sub, spk::dav_chunks(int(h->ld)));
+                    for (int r = 0; r < st.m; ++r) h->pin_up[lay.a + r] = st.a[r];
+                    h->pin_up[lay.a + st.m] = st.theta;
+                    if (st.restart) std::copy(st.Qk.begin(), st.Qk.end(), h->pin_up + lay.q);
+                } catch (const SpError& e) {
+                    st.err = e.what();
+                    st.err_code = e.code;
+                }
+            });
+            for (int i : sol)
+                if (B[i].err_code) throw SpError(B[i].err_code, B[i].err);
+            // Ritz pass (all), then the restarts (per state)
+            std::vector<spk::DavInst> D;
+            int max_n = 0;
+            for (int i : sol) {
+                D.push_back(dav_inst(B[i]));
+                max_n = std::max(max_n, B[i].n);
+            }
+            batch_dav_upload(D, bb, s);
+            spk::bdav_ritz(s, bb.dav.p, int(D.size()), max_n);
+            std::vector<int> ext;  // states that extend their search space
+            for (size_t q = 0; q < sol.size(); ++q) {
+                BatchState& st = B[sol[q]];
+                if (st.last) continue;
+                ext.push_back(sol[q]);
+                st.out.matvecs++;
+                if (!st.restart) continue;
+                sp_handle* h = st.h;
+                const long long ld = h->ld;
+                const DavLayout lay(h->dav_sub, spk::dav_chunks(int(ld)));
+                double* sm = h->dsmall.p;
+                HIPCK(hipMemcpyAsync(sm + lay.q, h->pin_up + lay.q, st.Qk.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, s));
+                for (double* Bv : {h->dV.p, h->dHV.p, h->dNV.p}) {
+                    spk::basis_rotate(s, Bv, ld, st.m, sm + lay.q, st.nk, h->dRot.p, st.n);
+                    HIPCK(hipMemcpyAsync(Bv, h->dRot.p, size_t(st.nk) * ld * sizeof(double), hipMemcpyDeviceToDevice, s));
+                }
+                const int S = max_sub + 1, m = st.m, nk = st.nk;
+                auto rot = [&](std::vector<double>& M) {
+                    std::vector<double> tmp(size_t(m) * nk, 0.0), res(size_t(S) * S, 0.0);
+                    for (int r = 0; r < m; ++r)
+                        for (int c = 0; c < nk; ++c) {
+                            double v = 0.0;
+                            for (int j = 0; j < m; ++j) v += M[r * S + j] * st.Qk[j * nk + c];
+                            tmp[r * nk + c] = v;
+                        }
+                    for (int r = 0; r < nk; ++r)
+                        for (int c = 0; c < nk; ++c) {
+                            double v = 0.0;
+                            for (int j = 0; j < m; ++j) v += st.Qk[j * nk + r] * tmp[j * nk + c];
+                            res[r * S + c] = v;
+                        }
+                    M.swap(res);
+                };
+                rot(st.Ht);
+                rot(st.Nt);
+                st.m = nk;
+                spk::dav_cgs(s, h->dV.p, ld, 0, st.m, sm + lay.pc2, st.nch, h->dt.p, st.n, sm + lay.pc1, 0);
+            }
+            if (!ext.empty()) {
+                D.clear();
+                max_n = 0;
+                int max_m = 0;
+                for (int i : ext) {
+                    D.push_back(dav_inst(B[i]));
+                    max_n = std::max(max_n, B[i].n);
+                    max_m = std::max(max_m, B[i].m);
+                }
+                batch_dav_upload(D, bb, s);
+                spk::bdav_cgs(s, bb.dav.p, int(D.size()), max_n, 0);
+                spk::bdav_cgs(s, bb.dav.p, int(D.size()), max_n, 1);
+                batch_heff(B, ext, false, bb, s);
+                batch_dav_upload(D, bb, s);
+                spk::bdav_gram(s, bb.dav.p, int(D.size()), max_n, max_m);
+            }
+            HIPCK(hipStreamSynchronize(s));
+            for (int i : sol) {
+                BatchState& st = B[i];
+                sp_handle* h = st.h;
+                const DavLayout lay(h->dav_sub, spk::dav_chunks(int(h->ld)));
+                const double* dn = h->pin;
+                const double* px = dn + (lay.px - lay.out);
+                const double xx = chunk_total(px, st.nch, 3, 0), uu = chunk_total(px, st.nch, 3, 1),
+                             xn = chunk_total(px, st.nch, 3, 2);
+                if (!std::isfinite(xx) || !std::isfinite(uu) || !(xx > 0.0)) throw SpError(SP_ENAN, "non-finite Ritz vector");
+                st.out.rnorm = std::sqrt(uu / xx);
+                st.out.pnorm = xn / xx;
+                if (st.out.rnorm <= o.tol) {
+                    st.out.converged = true;
+                    st.in_solve = false;
+                    continue;
+                }
+                if (st.last) {
+                    st.in_solve = false;
+                    continue;
+                }
+                const double tn = dn[lay.tn - lay.out];
+                if (!(tn >= 1e-14)) {
+                    st.in_solve = false;
+                    continue;
+                }
+                const double* pg = dn + (lay.pg - lay.out);
+                const int m = st.m, nd = 4 * m + 2, S = max_sub + 1;
+                for (int j = 0; j <= m; ++j) {
+                    const double hv_new = chunk_total(pg, st.nch, nd, j);
+                    const double nv_new = chunk_total(pg, st.nch, nd, m + 1 + j);
+                    const double hv_old = (j < m) ? chunk_total(pg, st.nch, nd, 2 * m + 2 + j) : hv_new;
+                    const double nv_old = (j < m) ? chunk_total(pg, st.nch, nd, 3 * m + 2 + j) : nv_new;
+                    st.Ht[j * S + m] = hv_new;
+                    st.Nt[j * S + m] = nv_new;
+                    st.Ht[m * S + j] = hv_old;
+                    st.Nt[m * S + j] = nv_old;
+                }
+                ++st.m;
+            }
+        }
+        // step end: x into the site, gauge move, environments (per state)
+        for (int i : act) {
+            BatchState& st = B[i];
+            sp_handle* h = st.h;
+            const int k = st.k, d = st.order[st.step].second, L = h->L;
+            spk::normalize(s, h->dx.p, site_ptr(h, k), st.n, nullptr);
+            if (h->precision == SP_FP32) {
+                double th, pn, xx;
+                rayleigh64(h, k, site_ptr(h, k), th, pn, xx);
+                st.out.theta = th;
+                st.out.pnorm = pn;
+            }
+            if (L > 1) {
+                if (d > 0) {
+                    move_right(h, k);
+                    env_left(h, k);
+                    h->center = k + 1;
+                } else {
+                    move_left(h, k);
+                    env_right(h, k);
+                    h->center = k - 1;
+                }
+            }
+        }
+        HIPCK(hipStreamSynchronize(s));
+        HIPCK(hipGetLastError());
+        const auto t1 = std::chrono::steady_clock::now();
+        for (int i : act) {
+            BatchState& st = B[i];
+            if (!st.out.converged) status = SP_ENOCONV;
+            sp_sweep_report* r = reps[i];
+            if (r && r->steps && r->n_steps < r->capacity) {
+                sp_step_report& rp = r->steps[r->n_steps++];
+                rp.sweep = int(st.step / st.sweep_len);
+                rp.site = st.k;
+                rp.dir = st.order[st.step].second;
+                rp.iters = st.out.iters;
+                rp.converged = st.out.converged ? 1 : 0;
+                rp.matvecs = st.out.matvecs;
+                rp.theta = st.out.theta;
+                rp.pnorm = st.out.pnorm;
+                rp.rnorm = st.out.rnorm;
+                rp.usec = std::chrono::duration<double, std::micro>(t1 - st.t0).count();
+            }
+            ++st.step;
+        }
+    }
+    return status;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2244,6 +2739,39 @@ int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r) {
             }
         }
         return status;
+    });
+}
+
+int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_report* r) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(hs && o && n >= 1, "bad arguments");
+        SP_REQUIRE(o->n_sweeps >= 0 && o->max_iter >= 1 && o->max_sub >= 2 && o->keep >= 1 && o->tol >= 0,
+                   "bad sweep options");
+        std::vector<BatchState> B(n);
+        std::vector<sp_sweep_report*> reps(n, nullptr);
+        for (int i = 0; i < n; ++i) {
+            sp_handle* h = hs[i];
+            SP_REQUIRE(h, "null handle");
+            SP_REQUIRE(h->path == SP_PATH_TILED, "batched sweeps need the tiled path");
+            SP_REQUIRE(h->stream == hs[0]->stream && h->device == hs[0]->device,
+                       "batched handles must share one device and one stream");
+            SP_REQUIRE(h->precision == hs[0]->precision, "batched handles must share the precision");
+            SP_REQUIRE(h->center == 1, "sweeps start with the canonical centre at site 1");
+            for (int j = 0; j < i; ++j) SP_REQUIRE(hs[j] != h, "a handle appears twice in the batch");
+            B[i].h = h;
+            const int L = h->L;
+            std::vector<std::pair<int, int>> one;
+            for (int k = 1; k < L; ++k) one.push_back({k, +1});
+            for (int k = L; k >= 2; --k) one.push_back({k, -1});
+            if (L == 1) one.push_back({1, +1});
+            B[i].sweep_len = int(one.size());
+            for (int sw = 0; sw < o->n_sweeps; ++sw) B[i].order.insert(B[i].order.end(), one.begin(), one.end());
+            if (r) {
+                reps[i] = &r[i];
+                r[i].n_steps = 0;
+            }
+        }
+        return sweep_batch(B, *o, reps);
     });
 }
 

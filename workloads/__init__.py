@@ -198,6 +198,30 @@ def random_blocks(table: BlockTable, seed: int) -> np.ndarray:
     return rng.standard_normal(table.total_size())
 
 
+def neel_blocks(table: BlockTable, seed: int, noise: float = 1e-2) -> np.ndarray:
+    """A broken-symmetry Neel-type product state embedded in the block table:
+    site k holds an alpha electron for odd k and a beta electron for even k
+    (N = L, N_alpha = N_beta for even L), i.e. entry (0, 0) of the block
+    (left sector of the product state's prefix, sigma_k) is 1, plus seeded
+    noise * N(0, 1) on every stored entry."""
+    rng = np.random.default_rng(seed)
+    out = noise * rng.standard_normal(table.total_size())
+    off = 0
+    n, m2 = 0, 0
+    for k in range(1, table.L + 1):
+        s_k = 2 if k % 2 == 1 else 1  # |a> on odd sites, |b> on even sites
+        left = table.bonds[k - 1]
+        pos = off
+        for (ia, s, ib, r, c) in table.site_blocks(k):
+            if s == s_k and left[ia][0] == n and left[ia][1] == m2:
+                out[pos] += 1.0
+            pos += r * c
+        off = pos
+        n += SIGMA_QN[s_k][0]
+        m2 += SIGMA_QN[s_k][1]
+    return out
+
+
 def site_offsets(table: BlockTable):
     """Start of each site (1..L) in the concatenated packed array."""
     offs = [0]
@@ -223,11 +247,15 @@ class HubbardWorkload:
     G: int
     sweeps: int
     seed: int
+    init: str = "random"  # "random": N(0,1) entries; "neel": product state + noise
+    noise: float = 1e-2
 
     def table(self) -> BlockTable:
         return make_block_table(self.L, self.N, self.twoM, self.D)
 
     def blocks(self) -> np.ndarray:
+        if self.init == "neel":
+            return neel_blocks(self.table(), self.seed, self.noise)
         return random_blocks(self.table(), self.seed)
 
 
@@ -243,3 +271,19 @@ def hubbard_bench(twoS: int = 0) -> HubbardWorkload:
     return HubbardWorkload(f"hubbard_L32_D256_G9_S{twoS // 2}", L=32, t=1.0, U=8.0, N=32,
                            twoS=twoS, twoM=0, D=256, G=9, sweeps=4,
                            seed=2 if twoS == 0 else 3)
+
+
+def hubbard_batch(n: int = 64, seed0: int = 100, D_choices=(64, 128, 256, 512)) -> list:
+    """Broken-symmetry guesses for many independent runs: instance i (seed
+    seed0 + i) draws an even L in [12, 32], U in {4, 8} and D from D_choices;
+    half filling N = L, M = 0, S = 0, G = 9, Neel-type initial state with
+    1e-2 noise."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(seed0 + i)
+        L = int(rng.choice(np.arange(12, 33, 2)))
+        U = float(rng.choice([4.0, 8.0]))
+        D = int(rng.choice(list(D_choices)))
+        out.append(HubbardWorkload(f"hubbard_batch{i}_L{L}_U{int(U)}_D{D}", L=L, t=1.0, U=U, N=L, twoS=0, twoM=0,
+                                   D=D, G=9, sweeps=4, seed=seed0 + i, init="neel", noise=1e-2))
+    return out
