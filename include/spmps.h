@@ -178,6 +178,15 @@ int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r);
  * broken-symmetry starting guesses (Sec. 3). */
 int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_report* r);
 
+/* Autotuner of the fused H_eff kernel (tiled path): for every site, time
+ * `reps` applications for each LDS budget of the work-group (36, 72, 108 and
+ * 144 KB, which set the rows per task) and keep the fastest plan.  The
+ * products are the same to rounding whatever the choice.  Optional outputs
+ * (L entries each): the budget in doubles, the rows per task and the time
+ * per application in microseconds.  Synchronises.  Currently disabled:
+ * returns SP_EINVAL. */
+int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* usec_out);
+
 /* Projected energy and norm at the canonical centre:
  * E = <x|H_eff x>/<x|N_eff x>, normP = <x|N_eff x> (the spin-S weight of
  * the underlying MPS when it is normalised).  Host scalars; synchronises. */

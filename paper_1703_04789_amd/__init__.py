@@ -27,7 +27,7 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_destroy", "sp_site_size", "sp_get_site", "sp_set_site", "sp_center", "sp_heff_flops",
            "sp_heff_profile",
            "sp_last_error", "sp_quadrature", "sp_exact_points", "sp_mpo_hubbard", "sp_mpo_s2",
-           "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch"]
+           "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch", "sp_autotune"]
 
 
 class SpError(RuntimeError):
@@ -92,6 +92,7 @@ def lib():
         "sp_heff_diag": [vp, ctypes.c_int, vp, vp],
         "sp_sweep": [vp, P(_SweepOpts), P(_SweepReport)],
         "sp_sweep_batch": [P(vp), ctypes.c_int, P(_SweepOpts), P(_SweepReport)],
+        "sp_autotune": [vp, ctypes.c_int, ip, ip, dp],
         "sp_energy": [vp, dp, dp],
         "sp_destroy": [vp],
         "sp_site_size": [vp, ctypes.c_int, P(ctypes.c_longlong)],
@@ -284,6 +285,15 @@ class SPMPS:
         E, p = ctypes.c_double(0), ctypes.c_double(0)
         _check(lib().sp_energy(self._h, ctypes.byref(E), ctypes.byref(p)))
         return E.value, p.value
+
+    def autotune(self, reps=5):
+        """Pick the fused-kernel LDS budget (rows per task) of every site by
+        timing; returns per-site (budget in doubles, rows, microseconds)."""
+        b = np.zeros(self.L, dtype=np.int32)
+        r = np.zeros(self.L, dtype=np.int32)
+        us = np.zeros(self.L)
+        _check(lib().sp_autotune(self._h, reps, _iptr(b), _iptr(r), _dptr(us)))
+        return [(int(b[i]), int(r[i]), float(us[i])) for i in range(self.L)]
 
     def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8):
         """Run sweeps; returns (status, list of per-step dicts)."""

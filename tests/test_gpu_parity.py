@@ -225,3 +225,40 @@ def test_first_steps_with_restarts_match_oracle(path):
     ref = omps.sweep(orc, 1, max_sub=8, keep=4, max_iter=40)
     for a, b in list(zip(steps, ref))[:5]:
         assert abs(a["theta"] - b["theta"]) < 1e-8, (a, b)
+
+
+AUTOTUNE_OFF = ("sp_autotune is switched off: its first GPU runs ended in a memory fault whose cause is not "
+                "shown yet (the candidate plans pass the host-side bounds checks and replay)")
+
+
+@pytest.mark.skip(reason=AUTOTUNE_OFF)
+def test_autotuned_plans_keep_parity():
+    # the autotuner only changes the rows per task of the fused kernel: the
+    # products stay equal to the oracle's at every site
+    tab, gpu, orc = make_pair(*CASES[3])
+    choice = gpu.autotune(reps=2)
+    assert len(choice) == tab.L and all(b > 0 and 1 <= r <= 8 for b, r, _ in choice)
+    rng = np.random.default_rng(9)
+    for k in range(1, tab.L + 1):
+        if k > 1:
+            gpu.env_update(k - 1, +1)
+            orc.update_left(k - 1)
+        n = gpu.site_size(k)
+        x = rng.standard_normal(n)
+        y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
+        xd = _dev(x)
+        y, ny = torch.empty_like(xd), torch.empty_like(xd)
+        gpu.heff_apply(k, xd, y, ny)
+        torch.cuda.synchronize()
+        assert rel_err(y.cpu().numpy(), orc.mps.site_packed(k, y_ref)) < 1e-11, k
+        assert rel_err(ny.cpu().numpy(), orc.mps.site_packed(k, ny_ref)) < 1e-11, k
+
+
+@pytest.mark.skip(reason=AUTOTUNE_OFF)
+def test_autotune_bench_shape_runs():
+    wl = W.hubbard_bench(0)
+    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed, oracle=False)
+    choice = gpu.autotune(reps=3)
+    print("[autotune] site: (budget, rows, us)", {k + 1: c for k, c in enumerate(choice)})
+    rc, steps = gpu.sweep(1)
+    assert np.isfinite(steps[-1]["theta"])
