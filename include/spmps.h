@@ -183,8 +183,7 @@ int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_repor
  * 144 KB, which set the rows per task) and keep the fastest plan.  The
  * products are the same to rounding whatever the choice.  Optional outputs
  * (L entries each): the budget in doubles, the rows per task and the time
- * per application in microseconds.  Synchronises.  Currently disabled:
- * returns SP_EINVAL. */
+ * per application in microseconds.  Synchronises. */
 int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* usec_out);
 
 /* Projected energy and norm at the canonical centre:

@@ -18,6 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["kernels.hip", "spmps.cpp", "host_linalg.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+         "-Werror=infinite-recursion", "-Werror=return-type",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 

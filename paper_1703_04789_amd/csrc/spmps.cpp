@@ -1377,7 +1377,21 @@ void build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
 void upload_fused(sp_handle* h, int k) {
     SitePlan& P = h->plan[k - 1];
     hipStream_t s = h->stream;
-    upload_fused(h, k);
+    P.dh_tasks.upload(P.h_tasks, s);
+    P.dh_blks.upload(P.h_blks, s);
+    P.dh_cols.upload(P.h_cols, s);
+    P.dh_lsrc.upload(P.h_lsrc, s);
+    P.dh_segs.upload(P.h_segs, s);
+    P.dh_terms.upload(P.h_terms, s);
+    P.dh_pieces.upload(P.h_pieces, s);
+    // every list the fused kernel reads must be on the device, whole
+    SP_REQUIRE(P.dh_tasks.n == P.h_tasks.size() && P.dh_blks.n == P.h_blks.size() &&
+                   P.dh_cols.n == P.h_cols.size() && P.dh_lsrc.n == P.h_lsrc.size() &&
+                   P.dh_segs.n == P.h_segs.size() && P.dh_terms.n == P.h_terms.size() &&
+                   P.dh_pieces.n == P.h_pieces.size(),
+               "internal: fused plan upload");
+    SP_REQUIRE(P.h_tasks.empty() || (P.dh_tasks.p && P.dh_blks.p && P.dh_cols.p && P.dh_lsrc.p && P.dh_pieces.p),
+               "internal: fused plan upload");
 }
 
 void upload_plan(sp_handle* h, int k) {
@@ -1481,7 +1495,7 @@ void validate_fused(sp_handle* h, int k) {
         const int RC = P.h_rows, lmax = P.h_lds;
         const int nblk = int(P.h_blks.size());
         auto in_lds = [&](long long a0, long long a1, const char* what) { check_span(a0, a1, lmax, what); };
-        if (RC < 1 || RC > spk::kH3MaxRC || lmax > kHeffLdsBudget) throw SpError(SP_EINVAL, "internal: fused shape");
+        if (RC < 1 || RC > spk::kH3MaxRC || lmax > kHeffLdsMax) throw SpError(SP_EINVAL, "internal: fused shape");
         std::vector<int> seen(size_t(xs) * h->G, 0);
         for (const spk::H3Task& t : P.h_tasks) {
             if (t.blk < 0) continue;
@@ -2796,9 +2810,6 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
     return guarded([&]() -> int {
         SP_REQUIRE(h && reps >= 1, "bad arguments");
         SP_REQUIRE(h->path == SP_PATH_TILED, "the autotuner tunes the fused kernel of the tiled path");
-        // switched off: its only GPU run ended in a memory fault whose cause
-        // is not yet shown (every candidate plan passes the host checks)
-        if (h) throw SpError(SP_EINVAL, "sp_autotune is disabled in this build");
         const int candidates[] = {4608, 9216, 13824, kHeffLdsMax};
         hipStream_t s = h->stream;
         hipEvent_t e0, e1;
@@ -2810,11 +2821,16 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
             int best_b = 0, best_rc = 0, last_rc = -1;
             float best = 1e30f;
             for (int b : candidates) {
-                build_fused(h, k, b);
+                try {
+                    build_fused(h, k, b);
+                } catch (const SpError&) {
+                    continue;  // a block too wide for this budget
+                }
                 if (P.h_rows == last_rc) continue;  // same plan as the previous budget
                 last_rc = P.h_rows;
                 validate_fused(h, k);
                 upload_fused(h, k);
+                HIPCK(hipStreamSynchronize(s));
                 const bool f32 = h->precision == SP_FP32;
                 const spk::H3Inst I = heff_inst(h, k, x, f32);
                 auto launch = [&]() {
@@ -2823,7 +2839,10 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
                 };
                 (void)hipGetLastError();
                 launch();  // warm-up
-                if (hipGetLastError() != hipSuccess) continue;  // this LDS size does not launch here
+                if (hipGetLastError() != hipSuccess) {  // this LDS size does not launch here
+                    HIPCK(hipStreamSynchronize(s));
+                    continue;
+                }
                 HIPCK(hipEventRecord(e0, s));
                 for (int r = 0; r < reps; ++r) launch();
                 HIPCK(hipEventRecord(e1, s));
