@@ -243,6 +243,23 @@ int sp_mpo_hubbard(int L, double t, double U, int* w, double* data, long long* n
 int sp_mpo_s2(int L, int* w, double* data, long long* n);
 int sp_mpo_identity(int L, int* w, double* data, long long* n);
 
+/* Spin-free property operators (Sec. 2.5), same layout: a single-site
+ * operator op (16 doubles, <s|op|t> at s*4+t) at site p; E_pq =
+ * sum_sigma a+_{p sigma} a_{q sigma} (the spin-free one-body density
+ * operator; E_pp = n_p), bond dimension 4; S_X . S_Y, bond dimension 5
+ * (X == Y: the local S^2).  Sites are 1-based. */
+int sp_mpo_site_op(int L, int p, const double* op, int* w, double* data, long long* n);
+int sp_mpo_epq(int L, int p, int q, int* w, double* data, long long* n);
+int sp_mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n);
+
+/* Projected expectation value of a spin-free operator given as an MPO,
+ * Eq. [PropSpinFree]: <O> = <Psi|O P|Psi> / <Psi|P|Psi> for the current
+ * state of h (any canonical centre), through the same environment and
+ * H_eff contractions with O in place of H, in FP64.  *normP (optional) =
+ * <P>.  The operator must commute with the total spin for this to be the
+ * expectation in the projected state.  Synchronises. */
+int sp_expect(sp_handle* h, const sp_mpo* O, double* value, double* normP);
+
 /* Symmetric eigensolver used for the Davidson subspace problem
  * (Householder tridiagonalisation + implicit QL): a is n x n row-major
  * (destroyed), eigenvalues ascending in ev, eigenvectors as columns of vec

@@ -251,3 +251,27 @@ def projected_energy(psi_sector, H, P) -> tuple:
     num = float(psi_sector @ (H @ ppsi))
     den = float(psi_sector @ ppsi)
     return num / den, den
+
+
+def epq_operator(L: int, p: int, q: int, states) -> sp.csr_matrix:
+    """E_pq = sum_s c+_{p s} c_{q s} on a sector basis (1-based sites)."""
+    terms = []
+    for spin in (0, 1):
+        a, b = _bit(L, p, spin), _bit(L, q, spin)
+        terms.append((1.0, lambda i, a=a, b=b: apply_cdag_c(i, a, b)))
+    return _build(states, L, terms)
+
+
+def spin_corr_operator(L: int, X: int, Y: int, states) -> sp.csr_matrix:
+    """S_X . S_Y on a sector basis: S^z_X S^z_Y + (S^+_X S^-_Y + S^-_X S^+_Y)/2
+    with S^+_k = c+_{k alpha} c_{k beta}."""
+    ax, bx, ay, by = _bit(L, X, 0), _bit(L, X, 1), _bit(L, Y, 0), _bit(L, Y, 1)
+
+    def szsz(i):
+        sx = 0.5 * (((i >> ax) & 1) - ((i >> bx) & 1))
+        sy = 0.5 * (((i >> ay) & 1) - ((i >> by) & 1))
+        return i, sx * sy
+    terms = [(1.0, szsz),
+             (0.5, lambda i: _chain(i, (ay, by), (bx, ax))),   # S^+_X S^-_Y: S^-_Y acts first
+             (0.5, lambda i: _chain(i, (by, ay), (ax, bx)))]   # S^-_X S^+_Y
+    return _build(states, L, terms)

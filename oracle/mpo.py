@@ -71,6 +71,73 @@ def s2_mpo(L: int):
     return _trim([w] * L)
 
 
+def _string_mpo(L, k0, k1, starts, ends, carry):
+    """MPO of a sum of two-site products sum_c starts[c]_k0 (x) carry^(k1-k0-1)
+    (x) ends[c]_k1 with k0 < k1, in the recursion layout: channel 0 of a
+    right vector holds the complete operator of sites [k, L], channels
+    1..nc an open product waiting for its left factor, the last channel the
+    identity.  Built by filling that right-vector recursion directly."""
+    nc = len(starts)
+    w = nc + 2
+    Ws = []
+    for k in range(1, L + 1):
+        W = np.zeros((w, w, 4, 4))
+        W[0, 0] = lo.I4
+        W[w - 1, w - 1] = lo.I4
+        if k == k0:
+            for c in range(nc):
+                W[0, 1 + c] = starts[c]
+        if k0 < k < k1:
+            for c in range(nc):
+                W[1 + c, 1 + c] = carry
+        if k == k1:
+            for c in range(nc):
+                W[1 + c, w - 1] = ends[c]
+        Ws.append(W)
+    return _trim(Ws)
+
+
+def site_op_mpo(L: int, p: int, op: np.ndarray):
+    """A single-site operator op at site p (1-based), bond dimension 2."""
+    Ws = []
+    for k in range(1, L + 1):
+        W = np.zeros((2, 2, 4, 4))
+        W[0, 0] = lo.I4
+        W[1, 1] = lo.I4
+        if k == p:
+            W[0, 1] = op
+        Ws.append(W)
+    return _trim(Ws)
+
+
+def epq_mpo(L: int, p: int, q: int):
+    """Spin-free one-body operator E_pq = sum_s a+_{p s} a_{q s} (Sec. 2.5).
+    p == q gives n_p.  For p < q the left factor is a+_s F (F the site
+    parity, the Jordan-Wigner string through the rest of site p), F is
+    carried over the sites in between and a_s closes the product at q; for
+    p > q the left factor is F a_s and a+_s closes it."""
+    if p == q:
+        return site_op_mpo(L, p, lo.N_A + lo.N_B)
+    F = lo.PARITY
+    if p < q:
+        starts = [lo.CDAG_A @ F, lo.CDAG_B @ F]
+        ends = [lo.C_A, lo.C_B]
+    else:
+        starts = [F @ lo.C_A, F @ lo.C_B]
+        ends = [lo.CDAG_A, lo.CDAG_B]
+    return _string_mpo(L, min(p, q), max(p, q), starts, ends, F)
+
+
+def spin_corr_mpo(L: int, X: int, Y: int):
+    """S_X . S_Y = S^z_X S^z_Y + (S^+_X S^-_Y + S^-_X S^+_Y)/2; X == Y gives
+    the local S^2.  Spin operators are even: no string."""
+    if X == Y:
+        return site_op_mpo(L, X, lo.S2_LOCAL)
+    starts = [lo.S_Z, 0.5 * lo.S_PLUS, 0.5 * lo.S_MINUS]
+    ends = [lo.S_Z, lo.S_MINUS, lo.S_PLUS]
+    return _string_mpo(L, min(X, Y), max(X, Y), starts, ends, lo.I4)
+
+
 def identity_mpo(L: int):
     """The identity operator as a bond-dimension-1 MPO."""
     return [lo.I4.reshape(1, 1, 4, 4).copy() for _ in range(L)]

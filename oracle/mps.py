@@ -425,3 +425,14 @@ def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
             if record is not None:
                 record(steps[-1])
     return steps
+
+
+def expect(table, packed, O, twoS, G):
+    """Projected expectation value of a spin-free operator O (an MPO),
+    Eq. [PropSpinFree]: <Psi|O P|Psi> / <Psi|P|Psi> for the MPS of the packed
+    site tensors, with the quadrature projector of (twoS, G).  Returns
+    (<O>, <P>/<Psi|Psi>)."""
+    st = SPMPSOracle(table, packed, O, twoS, G)
+    val, den = st.energy(1)
+    x = st.mps.A[0]
+    return val, den / float(np.sum(x * x))

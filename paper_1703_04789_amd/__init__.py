@@ -27,7 +27,8 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_destroy", "sp_site_size", "sp_get_site", "sp_set_site", "sp_center", "sp_heff_flops",
            "sp_heff_profile",
            "sp_last_error", "sp_quadrature", "sp_exact_points", "sp_mpo_hubbard", "sp_mpo_s2",
-           "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch", "sp_autotune"]
+           "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch", "sp_autotune",
+           "sp_mpo_site_op", "sp_mpo_epq", "sp_mpo_spin_corr", "sp_expect"]
 
 
 class SpError(RuntimeError):
@@ -93,6 +94,10 @@ def lib():
         "sp_sweep": [vp, P(_SweepOpts), P(_SweepReport)],
         "sp_sweep_batch": [P(vp), ctypes.c_int, P(_SweepOpts), P(_SweepReport)],
         "sp_autotune": [vp, ctypes.c_int, ip, ip, dp],
+        "sp_mpo_site_op": [ctypes.c_int, ctypes.c_int, dp, ip, dp, P(ctypes.c_longlong)],
+        "sp_mpo_epq": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
+        "sp_mpo_spin_corr": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
+        "sp_expect": [vp, P(_Mpo), dp, dp],
         "sp_energy": [vp, dp, dp],
         "sp_destroy": [vp],
         "sp_site_size": [vp, ctypes.c_int, P(ctypes.c_longlong)],
@@ -171,6 +176,21 @@ def mpo_s2(L):
 
 def mpo_identity(L):
     return _mpo(lib().sp_mpo_identity, L)
+
+
+def mpo_site_op(L, p, op):
+    op = np.ascontiguousarray(op, dtype=np.float64).reshape(16)
+    return _mpo(lib().sp_mpo_site_op, L, ctypes.c_int(p), _dptr(op))
+
+
+def mpo_epq(L, p, q):
+    """E_pq = sum_sigma a+_{p sigma} a_{q sigma} (1-based sites)."""
+    return _mpo(lib().sp_mpo_epq, L, ctypes.c_int(p), ctypes.c_int(q))
+
+
+def mpo_spin_corr(L, X, Y):
+    """S_X . S_Y (1-based sites)."""
+    return _mpo(lib().sp_mpo_spin_corr, L, ctypes.c_int(X), ctypes.c_int(Y))
 
 
 def small_eigh(a):
@@ -285,6 +305,41 @@ class SPMPS:
         E, p = ctypes.c_double(0), ctypes.c_double(0)
         _check(lib().sp_energy(self._h, ctypes.byref(E), ctypes.byref(p)))
         return E.value, p.value
+
+    def expect(self, mpo):
+        """<O P>/<P> of a spin-free operator (an MPO as returned by the
+        mpo_* builders) in the current projected state, and <P>."""
+        w, data = mpo
+        w = np.ascontiguousarray(w, dtype=np.int32)
+        data = np.ascontiguousarray(data, dtype=np.float64)
+        m = _Mpo(_iptr(w), _dptr(data))
+        val, normp = np.zeros(1), np.zeros(1)
+        _check(lib().sp_expect(self._h, ctypes.byref(m), _dptr(val), _dptr(normp)))
+        return float(val[0]), float(normp[0])
+
+    def one_rdm(self):
+        """Spin-free one-body density matrix gamma_pq = <E_pq> (L x L)."""
+        return np.array([[self.expect(mpo_epq(self.L, p, q))[0] for q in range(1, self.L + 1)]
+                         for p in range(1, self.L + 1)])
+
+    def spin_correlations(self):
+        """<S_X . S_Y> for all site pairs (L x L)."""
+        return np.array([[self.expect(mpo_spin_corr(self.L, x, y))[0] for y in range(1, self.L + 1)]
+                         for x in range(1, self.L + 1)])
+
+    def hubbard_energy_components(self, t, U):
+        """e_p of Sec. 2.5 for the open Hubbard chain: H_p = -t sum_sigma
+        (a+_p a_{p+1} + a+_p a_{p-1}) + U n_{p,a} n_{p,b}, so sum_p e_p = E."""
+        dbl = np.zeros(16)
+        dbl[15] = 1.0  # n_a n_b on |ab>
+        out = []
+        for p in range(1, self.L + 1):
+            e = U * self.expect(mpo_site_op(self.L, p, dbl))[0]
+            for q in (p - 1, p + 1):
+                if 1 <= q <= self.L:
+                    e += -t * self.expect(mpo_epq(self.L, p, q))[0]
+            out.append(e)
+        return np.array(out)
 
     def autotune(self, reps=5):
         """Pick the fused-kernel LDS budget (rows per task) of every site by

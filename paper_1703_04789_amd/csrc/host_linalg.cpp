@@ -204,6 +204,101 @@ int mpo_s2(int L, int* w, double* data, long long* n) {
     return emit(mb, w, data, n);
 }
 
+// site-dependent MPOs: full[k-1] holds the w x w operators of site k
+static int emit_sites(int L, int w, const std::vector<std::vector<M4>>& full, int* wout, double* data,
+                      long long* n) {
+    long long total = 0;
+    for (int k = 1; k <= L; ++k) total += (long long)((k == 1) ? 1 : w) * ((k == L) ? 1 : w) * 16;
+    if (wout)
+        for (int k = 0; k <= L; ++k) wout[k] = (k == 0 || k == L) ? 1 : w;
+    if (n) *n = total;
+    if (!data) return 0;
+    long long pos = 0;
+    for (int k = 1; k <= L; ++k) {
+        const int a1 = (k == 1) ? 1 : w;
+        const int b0 = (k == L) ? w - 1 : 0;
+        for (int a = 0; a < a1; ++a)
+            for (int b = b0; b < w; ++b)
+                for (int e = 0; e < 16; ++e) data[pos++] = full[k - 1][a * w + b][e];
+    }
+    return 0;
+}
+
+// channel 0 = nothing applied yet, channel w-1 = complete (identity carried
+// on both), in between: open two-site terms
+static std::vector<std::vector<M4>> blank_sites(int L, int w) {
+    std::vector<std::vector<M4>> full(L, std::vector<M4>(size_t(w) * w, zero4()));
+    for (int k = 0; k < L; ++k) {
+        full[k][0] = eye4();
+        full[k][size_t(w - 1) * w + (w - 1)] = eye4();
+    }
+    return full;
+}
+
+int mpo_site_op(int L, int p, const double* op, int* w, double* data, long long* n) {
+    if (p < 1 || p > L) return -1;
+    auto full = blank_sites(L, 2);
+    M4 m;
+    for (int e = 0; e < 16; ++e) m[e] = op[e];
+    full[p - 1][0 * 2 + 1] = m;
+    return emit_sites(L, 2, full, w, data, n);
+}
+
+int mpo_epq(int L, int p, int q, int* w, double* data, long long* n) {
+    if (p < 1 || p > L || q < 1 || q > L) return -1;
+    if (p == q) {
+        const M4 ca = c_alpha(), cb = c_beta();
+        const M4 nsum = [&] {
+            M4 a = mul4(tr4(ca), ca), b = mul4(tr4(cb), cb), r;
+            for (int e = 0; e < 16; ++e) r[e] = a[e] + b[e];
+            return r;
+        }();
+        return mpo_site_op(L, p, nsum.data(), w, data, n);
+    }
+    // sum over sigma of a+_{p sigma} a_{q sigma}: channels 1 (alpha) and 2
+    // (beta) carry the open term with the site parity as Jordan-Wigner
+    // string; the left end takes (a+ F) or (F a), the right end the bare
+    // operator, as in the hopping terms of the Hubbard MPO
+    const M4 ca = c_alpha(), cb = c_beta(), F = parity();
+    const M4 cda = tr4(ca), cdb = tr4(cb);
+    auto full = blank_sites(L, 4);
+    const int lo = std::min(p, q), hi = std::max(p, q);
+    const bool create_left = p < q;
+    full[lo - 1][0 * 4 + 1] = create_left ? mul4(cda, F) : mul4(F, ca);
+    full[lo - 1][0 * 4 + 2] = create_left ? mul4(cdb, F) : mul4(F, cb);
+    for (int k = lo + 1; k < hi; ++k) {
+        full[k - 1][1 * 4 + 1] = F;
+        full[k - 1][2 * 4 + 2] = F;
+    }
+    full[hi - 1][1 * 4 + 3] = create_left ? ca : cda;
+    full[hi - 1][2 * 4 + 3] = create_left ? cb : cdb;
+    return emit_sites(L, 4, full, w, data, n);
+}
+
+int mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n) {
+    if (X < 1 || X > L || Y < 1 || Y > L) return -1;
+    M4 sp = zero4(), sm = zero4(), sz = zero4(), s2 = zero4();
+    sp[2 * 4 + 1] = 1.0;
+    sm[1 * 4 + 2] = 1.0;
+    sz[1 * 4 + 1] = -0.5;
+    sz[2 * 4 + 2] = 0.5;
+    s2[1 * 4 + 1] = 0.75;
+    s2[2 * 4 + 2] = 0.75;
+    if (X == Y) return mpo_site_op(L, X, s2.data(), w, data, n);
+    // S_X.S_Y = Sz Sz + (S+ S- + S- S+)/2: spin operators are even, no string
+    const int lo = std::min(X, Y), hi = std::max(X, Y);
+    auto full = blank_sites(L, 5);
+    full[lo - 1][0 * 5 + 1] = sz;
+    full[lo - 1][0 * 5 + 2] = scal4(0.5, sp);
+    full[lo - 1][0 * 5 + 3] = scal4(0.5, sm);
+    for (int k = lo + 1; k < hi; ++k)
+        for (int c = 1; c <= 3; ++c) full[k - 1][size_t(c) * 5 + c] = eye4();
+    full[hi - 1][1 * 5 + 4] = sz;
+    full[hi - 1][2 * 5 + 4] = sm;
+    full[hi - 1][3 * 5 + 4] = sp;
+    return emit_sites(L, 5, full, w, data, n);
+}
+
 int mpo_identity(int L, int* w, double* data, long long* n) {
     MpoBuilder mb{L, 1, std::vector<M4>(1, eye4())};
     return emit(mb, w, data, n);

@@ -14,6 +14,12 @@ void projector_quadrature(int G, int twoS, int twoM, double* x, double* w, doubl
 int mpo_hubbard(int L, double t, double U, int* w, double* data, long long* n);
 int mpo_s2(int L, int* w, double* data, long long* n);
 int mpo_identity(int L, int* w, double* data, long long* n);
+// single-site operator op (4x4 row-major) at site p
+int mpo_site_op(int L, int p, const double* op, int* w, double* data, long long* n);
+// E_pq = sum_sigma a+_{p sigma} a_{q sigma} (p == q: the occupation n_p)
+int mpo_epq(int L, int p, int q, int* w, double* data, long long* n);
+// S_X . S_Y (X == Y: S_X^2)
+int mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n);
 int sym_eigh(int n, double* a, double* ev, double* vec);
 // lowest eigenvalue and its unit eigenvector (tridiagonal QR for the value,
 // inverse iteration for the vector); a is destroyed

@@ -347,6 +347,7 @@ struct sp_handle {
     std::vector<EnvLayout> env;            // per bond
     std::vector<DArr<double>> envL, envR;  // per bond, G * size
     std::vector<DArr<float>> envL32, envR32;  // FP32 copies (precision SP_FP32)
+    std::vector<int> tab_nsec, tab_n, tab_2m, tab_dim;  // the block table as given
     int precision = SP_FP64;
     std::vector<char> Lvalid, Rvalid;
     DArr<double> mps;
@@ -2632,6 +2633,14 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
                                   h->qcoef.data());
         build_mpo(h.get(), W);
         build_bonds(h.get(), bonds);
+        {
+            int tot = 0;
+            for (int k = 0; k <= h->L; ++k) tot += bonds->nsec[k];
+            h->tab_nsec.assign(bonds->nsec, bonds->nsec + h->L + 1);
+            h->tab_n.assign(bonds->sec_n, bonds->sec_n + tot);
+            h->tab_2m.assign(bonds->sec_2m, bonds->sec_2m + tot);
+            h->tab_dim.assign(bonds->sec_dim, bonds->sec_dim + tot);
+        }
         build_env_layouts(h.get());
         h->plan.resize(h->L);
         long long Tmax = 0, Vmax = 0, qrs = 0, qrr = 0;
@@ -2871,6 +2880,29 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
     });
 }
 
+int sp_expect(sp_handle* h, const sp_mpo* O, double* value, double* normP) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && O && value, "null argument");
+        // a second state with the operator's environments: the same site
+        // tensors (its set-up moves the canonical centre to site 1 without
+        // changing the state), then <O P>/<P> at its centre
+        std::vector<double> blocks(h->mps_size);
+        HIPCK(hipMemcpyAsync(blocks.data(), h->mps.p, h->mps_size * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCK(hipStreamSynchronize(h->stream));
+        sp_problem p{h->L, 4, h->N, h->twoS, h->twoM, h->G, SP_FP64, h->path};
+        sp_block_table bt{h->tab_nsec.data(), h->tab_n.data(), h->tab_2m.data(), h->tab_dim.data()};
+        sp_handle* t = nullptr;
+        const int rc = sp_init_mps(&p, O, &bt, blocks.data(), h->stream, &t);
+        if (rc < 0) throw SpError(rc, std::string("operator state: ") + g_last_error);
+        std::unique_ptr<sp_handle, int (*)(sp_handle*)> guard(t, sp_destroy);
+        double np = 0.0;
+        const int rc2 = sp_energy(t, value, &np);
+        if (rc2 < 0) throw SpError(rc2, g_last_error);
+        if (normP) *normP = np;
+        return SP_OK;
+    });
+}
+
 int sp_energy(sp_handle* h, double* E, double* normP) {
     return guarded([&]() -> int {
         SP_REQUIRE(h && E && normP, "null argument");
@@ -3036,6 +3068,25 @@ int sp_mpo_identity(int L, int* w, double* data, long long* n) {
     return guarded([&]() -> int {
         SP_REQUIRE(L >= 1 && w && n, "bad arguments");
         return sph::mpo_identity(L, w, data, n);
+    });
+}
+
+int sp_mpo_site_op(int L, int p, const double* op, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(L >= 1 && p >= 1 && p <= L && op && w && n, "bad arguments");
+        return sph::mpo_site_op(L, p, op, w, data, n);
+    });
+}
+int sp_mpo_epq(int L, int p, int q, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(L >= 1 && p >= 1 && p <= L && q >= 1 && q <= L && w && n, "bad arguments");
+        return sph::mpo_epq(L, p, q, w, data, n);
+    });
+}
+int sp_mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(L >= 1 && X >= 1 && X <= L && Y >= 1 && Y <= L && w && n, "bad arguments");
+        return sph::mpo_spin_corr(L, X, Y, w, data, n);
     });
 }
 

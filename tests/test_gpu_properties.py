@@ -1,0 +1,49 @@
+"""Projected spin-free properties through the library's contractions
+(sp_expect) against the oracle, FP64 (1e-10 absolute), plus the sum rules
+after sweeps: sum_p <n_p> = N, sum_{XY} <S_X.S_Y> = S(S+1), sum_p e_p = E."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_util import make_pair  # noqa: E402
+
+import paper_1703_04789_amd as sp  # noqa: E402
+from oracle import mpo as om, mps as omps  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (L, N, 2M, D, 2S, G)
+    (8, 8, 0, 16, 0, 5),
+    (6, 5, 1, 12, 1, 3),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_expectations_match_the_oracle(case):
+    tab, gpu, orc = make_pair(*case)
+    L, twoS, G = case[0], case[4], case[5]
+    blocks = orc.mps.packed()
+    for mine, ref in ((sp.mpo_epq(L, 1, 3), om.epq_mpo(L, 1, 3)),
+                      (sp.mpo_epq(L, L, 2), om.epq_mpo(L, L, 2)),
+                      (sp.mpo_epq(L, 2, 2), om.epq_mpo(L, 2, 2)),
+                      (sp.mpo_spin_corr(L, 1, L), om.spin_corr_mpo(L, 1, L))):
+        v, p = gpu.expect(mine)
+        vr, pr = omps.expect(tab, blocks, ref, twoS, G)
+        assert abs(v - vr) < 1e-10 and abs(p - pr) < 1e-10
+
+
+def test_sum_rules_after_sweeps():
+    L, N, twoM, D, twoS, G = 8, 8, 0, 16, 2, 5
+    t, U = 1.0, 4.0
+    tab, gpu, _ = make_pair(L, N, twoM, D, twoS, G, U=U, oracle=False)
+    rc, steps = gpu.sweep(2, max_sub=64, max_iter=100)
+    E, _ = gpu.energy()
+    gamma = gpu.one_rdm()
+    assert abs(np.trace(gamma) - N) < 1e-9
+    assert np.abs(gamma - gamma.T).max() < 1e-9
+    ss = gpu.spin_correlations()
+    assert abs(ss.sum() - 2.0) < 1e-9
+    e = gpu.hubbard_energy_components(t, U)
+    print(f"[props] E {E:.10f} sum e_p {e.sum():.10f}")
+    assert abs(e.sum() - E) < 1e-9
