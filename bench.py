@@ -28,6 +28,26 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a 64 MiB copy), or None
+    when the kernel source has changed since those counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "heff_hubbard_L32_D256_G9_fused_fp64_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1703_04789_amd", "csrc", "kernels.hip")
+    try:
+        txt = open(path).read()
+        now = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_b = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    m_h = re.search(r"kernels.hip sha256: ([0-9a-f]+)", txt)
+    if not m_b or not m_h or m_h.group(1) != now:
+        return None
+    return float(m_b.group(1))
+
+
 def cpu_baseline(wl, mv_per_step):
     """The oracle on a bounded sample of the same workload: its set-up (right
     canonical form and right environments), left environments to the centre,
@@ -188,6 +208,9 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
     roof["kernel"] = f"{'k_bgemm' if args.path == 'plain' else 'k_heff3'} ({dom_name}) at site {kc}"
+    if args.path == "tiled" and dom_name == "fused_heff":
+        roof["traffic"] = measured_traffic()
+        roof["traffic_unit"] = "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
     roof["per_launch"] = {k: {"ms": v["ms"], "flops": v["flops"], "bytes": v["bytes"]} for k, v in prof.items()}
 
     out = {
