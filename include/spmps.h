@@ -57,9 +57,13 @@ extern "C" {
                              final FP64 Rayleigh quotient per site step
                              (the reported energy) stay FP64           */
 
-#define SP_PATH_TILED 0   /* LDS-tiled dense products over particle-number
-                             blocks (zero-padded in M, empty K ranges
-                             skipped), per-g partial outputs              */
+#define SP_PATH_TILED 0   /* environment updates as LDS-tiled products over
+                             particle-number blocks; H_eff x in one fused
+                             launch per site with per-g partial outputs.
+                             A site whose particle-number block is too wide
+                             for the fused kernel's LDS (large MPO bond
+                             dimensions) runs LDS-tiled FP64 block products
+                             for H_eff x instead, in either precision      */
 #define SP_PATH_PLAIN 1   /* one work-group per (N, M) block product, the
                              plain FP64 reference path                      */
 
@@ -172,8 +176,9 @@ int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r);
  * site step; the Davidson iterations of the states run in lockstep, with one
  * fused H_eff launch (per row count) covering every state and quadrature
  * point, batched Davidson passes, and the subspace solves on host threads.
- * All handles: tiled path, one precision, one device and one stream, centre
- * at site 1, each listed once.  r: n reports (or NULL).  The ability to
+ * All handles: tiled path, one precision, one device and one stream,
+ * centre at site 1, each listed once.  Sites without a fused plan run their
+ * tiled products per state in the same round.  r: n reports (or NULL).  The ability to
  * run many states at once follows the paper's use of several
  * broken-symmetry starting guesses (Sec. 3). */
 int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_report* r);
@@ -183,8 +188,17 @@ int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_repor
  * 144 KB, which set the rows per task) and keep the fastest plan.  The
  * products are the same to rounding whatever the choice.  Optional outputs
  * (L entries each): the budget in doubles, the rows per task and the time
- * per application in microseconds.  Synchronises. */
+ * per application in microseconds.  A site where no budget fits keeps the
+ * tiled block products (rows 0).  Synchronises. */
 int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* usec_out);
+
+/* Choose the H_eff plan of one site (tiled path): the fused kernel with an
+ * LDS budget of `lds_budget` doubles per work-group (1..18432; it sets the
+ * rows per task), or 0 for the LDS-tiled block products.  A budget that no
+ * particle-number block of the site fits also selects the tiled products.
+ * *rows (optional) receives the rows per task, 0 for the tiled products.
+ * The products are the same to rounding either way.  Synchronises. */
+int sp_set_heff_plan(sp_handle* h, int site, int lds_budget, int* rows);
 
 /* Projected energy and norm at the canonical centre:
  * E = <x|H_eff x>/<x|N_eff x>, normP = <x|N_eff x> (the spin-S weight of
@@ -212,7 +226,8 @@ int sp_heff_flops(const sp_handle* h, int site, double* flops);
 
 /* Timing of the phases of sp_heff_apply at `site`, each averaged over
  * `reps` launches.  Plain path: left product, W r mixing, right product.
- * Tiled path: the fused launch (left product, mixing and right product in
+ * Tiled path: the fused launch (at a site without a fused plan the tiled
+ * block-product lists) (left product, mixing and right product in
  * one kernel), nothing, the g sum.  Each phase is averaged over
  * `reps` launches with HIP events on the handle's stream.  out[0..2]: mean
  * milliseconds per launch; out[3..5]: algorithmic flops per launch;
@@ -251,6 +266,18 @@ int sp_mpo_identity(int L, int* w, double* data, long long* n);
 int sp_mpo_site_op(int L, int p, const double* op, int* w, double* data, long long* n);
 int sp_mpo_epq(int L, int p, int q, int* w, double* data, long long* n);
 int sp_mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n);
+
+/* The ab-initio Hamiltonian of Eq. [sqH] for K real orbitals (Sec. 2.1):
+ * H = sum_pq h_pq sum_s a+_ps a_qs + 1/2 sum_pqrs (pq|rs) sum_st a+_ps a+_rt
+ * a_st a_qs, chemists' notation, no core energy.  h: K*K row-major; eri:
+ * K^4 with (pq|rs) at ((p*K + q)*K + r)*K + s (host memory, read only; no
+ * symmetry is assumed or enforced).  Output as for the builders above
+ * (w: K+1 ints; data == NULL returns the sizes only; the terms are
+ * enumerated on every call).  The bond dimension is O(K^2): every channel
+ * holds a partial product with at most two fermion operators named on one
+ * side of the bond.  SP_EINVAL if K is outside 2..64 or a bond would need
+ * more than 4096 channels. */
+int sp_mpo_abinitio(int K, const double* h, const double* eri, int* w, double* data, long long* n);
 
 /* Projected expectation value of a spin-free operator given as an MPO,
  * Eq. [PropSpinFree]: <O> = <Psi|O P|Psi> / <Psi|P|Psi> for the current

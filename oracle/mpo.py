@@ -155,3 +155,107 @@ def mpo_to_dense(Ws) -> np.ndarray:
         b, S, s, T, tt = cur.shape
         cur = cur.reshape(b, S * s, T * tt)
     return cur[0]
+
+
+def _fermion_factors(K: int, ops):
+    """Site factors of a product of spin-orbital creators/annihilators.
+
+    ``ops`` lists (site p 1-based, spin 0=alpha 1=beta, dagger) in operator
+    order, leftmost first.  Under the Jordan-Wigner mapping of Sec. 2.1 one
+    operator at site p is F on every earlier site, its local matrix at p and
+    the identity after p (F the site parity), so the product is the site-wise
+    product of these factors in operator order.  Returns K 4x4 matrices, or
+    None if one of them vanishes."""
+    local = {(0, 1): lo.CDAG_A, (1, 1): lo.CDAG_B, (0, 0): lo.C_A, (1, 0): lo.C_B}
+    out = []
+    for j in range(1, K + 1):
+        m = lo.I4
+        for (p, spin, dag) in ops:
+            if j < p:
+                m = m @ lo.PARITY
+            elif j == p:
+                m = m @ local[(spin, dag)]
+        m = m + 0.0                       # no negative zeros in the keys below
+        if not m.any():
+            return None
+        out.append(m)
+    return out
+
+
+def abinitio_terms(h: np.ndarray, eri: np.ndarray):
+    """The second-quantised Hamiltonian of Eq. [sqH] for real orbitals as a
+    list of (coefficient, operator product):
+        sum_pq h_pq sum_s a+_ps a_qs
+      + 1/2 sum_pqrs (pq|rs) sum_st a+_ps a+_rt a_st a_qs
+    (chemists' notation; no core energy).  Sites are 1-based."""
+    K = h.shape[0]
+    terms = []
+    for p in range(K):
+        for q in range(K):
+            if h[p, q] != 0.0:
+                for s in (0, 1):
+                    terms.append((h[p, q], ((p + 1, s, 1), (q + 1, s, 0))))
+    for p in range(K):
+        for q in range(K):
+            for r in range(K):
+                for s_ in range(K):
+                    v = eri[p, q, r, s_]
+                    if v == 0.0:
+                        continue
+                    for a in (0, 1):
+                        for b in (0, 1):
+                            terms.append((0.5 * v, ((p + 1, a, 1), (r + 1, b, 1), (s_ + 1, b, 0),
+                                                    (q + 1, a, 0))))
+    return terms
+
+
+def terms_mpo(K: int, terms):
+    """MPO of a sum of even fermionic operator products, built as the
+    automaton of the right-vector recursion of Sec. 2.1: at bond k a product
+    whose support [p_min, p_max] straddles the bond sits in the channel named
+    by its remaining site factors on k+1..p_max (products with the same
+    remainder share it), its coefficient enters at p_min, channel 0 carries
+    the complete operator of the sites to the right and the last channel the
+    identity.  Even products carry no string outside their support."""
+    prods = []
+    for coef, ops in terms:
+        f = _fermion_factors(K, ops)
+        if f is None:
+            continue
+        sup = [j for j in range(K) if not np.array_equal(f[j], lo.I4)]
+        if not sup:
+            raise ValueError("a constant term is not supported")
+        prods.append((coef, f, sup[0], sup[-1]))
+
+    def key(f, k, last):
+        return tuple(f[j].tobytes() for j in range(k, last + 1))
+
+    # channel index of every remainder at every inner bond k (after site k+1,
+    # 0-based sites): 1..n, 0 = complete operator, n+1 = identity
+    chans = [dict() for _ in range(K + 1)]
+    for coef, f, lo_, hi in prods:
+        for k in range(lo_, hi):            # bond after 0-based site k
+            kk = key(f, k + 1, hi)
+            if kk not in chans[k + 1]:
+                chans[k + 1][kk] = len(chans[k + 1]) + 1
+    # untrimmed widths: 2 at the outer bonds (trimmed to 1 at the end)
+    wf = [2] + [len(chans[k]) + 2 for k in range(1, K)] + [2]
+    Ws = [np.zeros((wf[k], wf[k + 1], 4, 4)) for k in range(K)]
+    for k in range(K):
+        Ws[k][0, 0] = lo.I4
+        Ws[k][-1, -1] = lo.I4
+    for coef, f, lo_, hi in prods:
+        for k in range(lo_, hi + 1):
+            a = 0 if k == lo_ else chans[k][key(f, k, hi)]
+            b = wf[k + 1] - 1 if k == hi else chans[k + 1][key(f, k + 1, hi)]
+            if k == lo_:
+                Ws[k][a, b] += coef * f[k]
+            else:
+                Ws[k][a, b] = f[k]
+    return _trim(Ws)
+
+
+def abinitio_mpo(h: np.ndarray, eri: np.ndarray):
+    """The ab-initio Hamiltonian (Eq. [sqH], chemists' integrals) as an MPO;
+    see :func:`terms_mpo` for the construction."""
+    return terms_mpo(h.shape[0], abinitio_terms(h, eri))

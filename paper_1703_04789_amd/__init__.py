@@ -28,7 +28,8 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_heff_profile",
            "sp_last_error", "sp_quadrature", "sp_exact_points", "sp_mpo_hubbard", "sp_mpo_s2",
            "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch", "sp_autotune",
-           "sp_mpo_site_op", "sp_mpo_epq", "sp_mpo_spin_corr", "sp_expect"]
+           "sp_mpo_site_op", "sp_mpo_epq", "sp_mpo_spin_corr", "sp_expect",
+           "sp_mpo_abinitio", "sp_set_heff_plan"]
 
 
 class SpError(RuntimeError):
@@ -94,9 +95,11 @@ def lib():
         "sp_sweep": [vp, P(_SweepOpts), P(_SweepReport)],
         "sp_sweep_batch": [P(vp), ctypes.c_int, P(_SweepOpts), P(_SweepReport)],
         "sp_autotune": [vp, ctypes.c_int, ip, ip, dp],
+        "sp_set_heff_plan": [vp, ctypes.c_int, ctypes.c_int, ip],
         "sp_mpo_site_op": [ctypes.c_int, ctypes.c_int, dp, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_epq": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_spin_corr": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
+        "sp_mpo_abinitio": [ctypes.c_int, dp, dp, ip, dp, P(ctypes.c_longlong)],
         "sp_expect": [vp, P(_Mpo), dp, dp],
         "sp_energy": [vp, dp, dp],
         "sp_destroy": [vp],
@@ -191,6 +194,17 @@ def mpo_epq(L, p, q):
 def mpo_spin_corr(L, X, Y):
     """S_X . S_Y (1-based sites)."""
     return _mpo(lib().sp_mpo_spin_corr, L, ctypes.c_int(X), ctypes.c_int(Y))
+
+
+def mpo_abinitio(h, eri):
+    """The ab-initio Hamiltonian of K real orbitals from h[p, q] and
+    eri[p, q, r, s] = (pq|rs)."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    K = h.shape[0]
+    if h.shape != (K, K) or eri.shape != (K, K, K, K):
+        raise ValueError("h must be K x K and eri K x K x K x K")
+    return _mpo(lib().sp_mpo_abinitio, K, _dptr(h), _dptr(eri))
 
 
 def small_eigh(a):
@@ -349,6 +363,13 @@ class SPMPS:
         us = np.zeros(self.L)
         _check(lib().sp_autotune(self._h, reps, _iptr(b), _iptr(r), _dptr(us)))
         return [(int(b[i]), int(r[i]), float(us[i])) for i in range(self.L)]
+
+    def set_heff_plan(self, site, lds_budget):
+        """Fused kernel with this LDS budget (doubles) at ``site``, or 0 for
+        the tiled block products; returns the rows per task (0: tiled)."""
+        rows = ctypes.c_int(0)
+        _check(lib().sp_set_heff_plan(self._h, site, lds_budget, ctypes.byref(rows)))
+        return rows.value
 
     def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8):
         """Run sweeps; returns (status, list of per-step dicts)."""

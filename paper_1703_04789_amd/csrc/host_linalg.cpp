@@ -3,6 +3,9 @@
 #include "host_linalg.h"
 
 #include <algorithm>
+#include <functional>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <numeric>
 #include <vector>
@@ -302,6 +305,185 @@ int mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n) {
 int mpo_identity(int L, int* w, double* data, long long* n) {
     MpoBuilder mb{L, 1, std::vector<M4>(1, eye4())};
     return emit(mb, w, data, n);
+}
+
+// ---------------------------------------------------------------------------
+// Ab-initio Hamiltonian (Eq. [sqH], real orbitals, chemists' integrals)
+//   H = sum_pq h_pq sum_s a+_ps a_qs + 1/2 sum_pqrs (pq|rs) sum_st a+_ps a+_rt a_st a_qs
+// as an MPO whose channels at a bond hold partial operator products.
+//
+// Every term is first brought to site order: a stable sort of its fermion
+// operators by site (operators on different sites anticommute, so the sign is
+// the parity of the sort; operators on one site keep their order).  Under the
+// Jordan-Wigner mapping of Sec. 2.1 the site factor of a site-ordered even
+// product at site j is (product of its operators at j) x F^(number of its
+// operators on later sites), F the site parity.  Across a bond the product
+// therefore splits into a left part fixed by the left operators and the
+// parity of the right count, and a right part fixed by the right operators.
+//
+// A term waits at a bond either in a "left" channel, named by its left part
+// (terms with the same left part share it; the coefficient is not applied
+// yet), or in a "right" channel, named by its right part (coefficient already
+// applied).  It uses the left form while fewer of its operators lie left of
+// the bond than right of it, and on a tie when the left side of the chain is
+// not longer than the right; once it switches it stays in right channels.
+// The coefficient enters on the one edge where a term switches.  With at most
+// two operators on the named side, a bond carries O(K^2) channels.
+
+namespace {
+struct FOp {
+    int site, spin, dag;  // site 1-based, spin 0 = alpha, dag 1 = creator
+    bool operator<(const FOp& o) const {
+        return std::tie(site, spin, dag) < std::tie(o.site, o.spin, o.dag);
+    }
+};
+// channel label: kind (0 left, 1 right), right-count parity (left kind), ops
+using Label = std::vector<int>;
+}  // namespace
+
+int mpo_abinitio(int K, const double* h, const double* eri, int* wout, double* data, long long* n) {
+    if (K < 2 || K > 64 || !h || !eri) return -1;
+    const M4 ca = c_alpha(), cb = c_beta(), F = parity(), I = eye4();
+    const M4 cda = tr4(ca), cdb = tr4(cb);
+    auto local = [&](const FOp& o) -> const M4& {
+        return o.spin == 0 ? (o.dag ? cda : ca) : (o.dag ? cdb : cb);
+    };
+    // enumerate the terms: f(coef, ops in operator order)
+    auto for_terms = [&](const std::function<void(double, std::vector<FOp>)>& f) {
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q) {
+                const double v = h[p * K + q];
+                if (v == 0.0) continue;
+                for (int s = 0; s < 2; ++s) f(v, {{p + 1, s, 1}, {q + 1, s, 0}});
+            }
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q)
+                for (int r = 0; r < K; ++r)
+                    for (int t = 0; t < K; ++t) {
+                        const double v = eri[((size_t(p) * K + q) * K + r) * K + t];
+                        if (v == 0.0) continue;
+                        for (int a = 0; a < 2; ++a)
+                            for (int b = 0; b < 2; ++b)
+                                f(0.5 * v, {{p + 1, a, 1}, {r + 1, b, 1}, {t + 1, b, 0}, {q + 1, a, 0}});
+                    }
+    };
+    // site order, sign and site factors; false if the product vanishes
+    struct Term {
+        double coef;
+        std::vector<FOp> ops;  // site-ordered
+        std::vector<M4> f;     // factors of sites pmin..pmax
+        int pmin, pmax;
+    };
+    auto prepare = [&](double coef, std::vector<FOp> ops, Term& T) -> bool {
+        int inv = 0;
+        for (size_t i = 0; i < ops.size(); ++i)
+            for (size_t j = i + 1; j < ops.size(); ++j)
+                if (ops[i].site > ops[j].site) ++inv;
+        std::stable_sort(ops.begin(), ops.end(), [](const FOp& a, const FOp& b) { return a.site < b.site; });
+        T.coef = (inv & 1) ? -coef : coef;
+        T.pmin = ops.front().site;
+        T.pmax = ops.back().site;
+        T.f.clear();
+        for (int j = T.pmin; j <= T.pmax; ++j) {
+            M4 m = I;
+            int later = 0;
+            for (const FOp& o : ops) {
+                if (o.site == j) m = mul4(m, local(o));
+                if (o.site > j) ++later;
+            }
+            if (later & 1) m = mul4(m, F);
+            bool nz = false;
+            for (double x : m) nz = nz || x != 0.0;
+            if (!nz) return false;
+            T.f.push_back(m);
+        }
+        T.ops = std::move(ops);
+        return true;
+    };
+    // channel of term T at inner bond b (pmin <= b < pmax)
+    auto label_at = [&](const Term& T, int b) -> Label {
+        int nl = 0;
+        for (const FOp& o : T.ops) nl += o.site <= b;
+        const int nr = int(T.ops.size()) - nl;
+        const bool left = nl < nr || (nl == nr && b <= K - b);
+        Label lab{left ? 0 : 1, left ? (nr & 1) : 0};
+        for (const FOp& o : T.ops)
+            if ((o.site <= b) == left) {
+                lab.push_back(o.site);
+                lab.push_back(o.spin);
+                lab.push_back(o.dag);
+            }
+        return lab;
+    };
+    // pass 1: the channels of every bond
+    std::vector<std::map<Label, int>> chan(K + 1);
+    Term T;
+    for_terms([&](double c, std::vector<FOp> ops) {
+        if (!prepare(c, std::move(ops), T)) return;
+        for (int b = T.pmin; b < T.pmax; ++b) chan[b].emplace(label_at(T, b), 0);
+    });
+    // numbering: 0 = nothing applied yet, then left channels, then right
+    // channels (map order puts kind 0 first), last = complete
+    std::vector<int> w(K + 1, 1);
+    for (int b = 1; b < K; ++b) {
+        int i = 1;
+        for (auto& kv : chan[b]) kv.second = i++;
+        w[b] = i + 1;
+        if (w[b] > 4096) return -2;
+    }
+    long long total = 0;
+    for (int k = 1; k <= K; ++k) total += (long long)w[k - 1] * w[k] * 16;
+    if (wout)
+        for (int k = 0; k <= K; ++k) wout[k] = w[k];
+    if (n) *n = total;
+    if (!data) return 0;
+    // pass 2: the edges
+    std::vector<std::map<std::pair<int, int>, M4>> edge(K + 1);
+    for (int k = 1; k <= K; ++k) {
+        if (k < K) edge[k][{0, 0}] = I;
+        if (k > 1) edge[k][{w[k - 1] - 1, w[k] - 1}] = I;
+    }
+    for_terms([&](double c, std::vector<FOp> ops) {
+        if (!prepare(c, std::move(ops), T)) return;
+        int a = 0;
+        bool a_left = true;  // "nothing applied yet" counts as a left channel
+        for (int k = T.pmin; k <= T.pmax; ++k) {
+            int b;
+            bool b_left;
+            if (k == T.pmax) {
+                b = w[k] - 1;
+                b_left = false;
+            } else {
+                const Label lab = label_at(T, k);
+                b = chan[k].at(lab);
+                b_left = lab[0] == 0;
+            }
+            const M4& fk = T.f[size_t(k - T.pmin)];
+            auto it = edge[k].find({a, b});
+            if (a_left && !b_left) {  // the switch: the coefficient enters here
+                const M4 add = scal4(T.coef, fk);
+                if (it == edge[k].end()) edge[k][{a, b}] = add;
+                else
+                    for (int e = 0; e < 16; ++e) it->second[e] += add[e];
+            } else {
+                edge[k][{a, b}] = fk;
+            }
+            a = b;
+            a_left = b_left;
+        }
+    });
+    std::fill(data, data + total, 0.0);
+    long long pos = 0;
+    for (int k = 1; k <= K; ++k) {
+        const int wl = w[k - 1], wr = w[k];
+        for (auto& kv : edge[k]) {
+            const int a = kv.first.first, b = kv.first.second;
+            if (a >= wl || b >= wr) return -3;
+            std::copy(kv.second.begin(), kv.second.end(), data + pos + (size_t(a) * wr + b) * 16);
+        }
+        pos += (long long)wl * wr * 16;
+    }
+    return 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -313,7 +313,7 @@ struct SitePlan {
     DArr<int> xmap;
     TList t_left, t_right, t_envl, t_zr, t_envr;
     // fused H_eff x
-    int h_rows = 1;         // rows per task (RC)
+    int h_rows = 0;         // rows per task (RC); 0: no fused plan
     int h_lds = 0;          // dynamic LDS per work-group (doubles)
     std::vector<spk::H3Task> h_tasks;
     std::vector<spk::H3Blk> h_blks;
@@ -1149,7 +1149,10 @@ void build_plan(sp_handle* h, int k) {
 constexpr int kHeffLdsBudget = 9216;
 constexpr int kHeffLdsMax = 18432;
 
-void build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
+// Returns false (and leaves the site without a fused plan, h_rows = 0) when
+// a particle-number block is too wide for the budget: the site then runs
+// the LDS-tiled block-product lists.
+bool build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
     SitePlan& P = h->plan[k - 1];
     const int G = h->G;
     const Bond& bl = h->bonds[k - 1];
@@ -1261,9 +1264,6 @@ void build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
     int need1 = 1;
     for (auto& D : bd) need1 = std::max(need1, D.lsum + D.tsum + D.vmax);
     const int RC = std::min(spk::kH3MaxRC, lds_budget / need1);
-    SP_REQUIRE(RC >= 1, "a particle-number block is too wide for the fused H_eff kernel");
-    P.h_rows = RC;
-    P.h_lds = RC * need1;
     P.h_blks.clear();
     P.h_cols.clear();
     P.h_lsrc.clear();
@@ -1271,6 +1271,13 @@ void build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
     P.h_terms.clear();
     P.h_pieces.clear();
     P.h_tasks.clear();
+    if (RC < 1) {
+        P.h_rows = 0;
+        P.h_lds = 0;
+        return false;
+    }
+    P.h_rows = RC;
+    P.h_lds = RC * need1;
     for (int i = 0; i < nb; ++i) {
         BlkD& D = bd[i];
         spk::H3Blk B{};
@@ -1373,6 +1380,7 @@ void build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
         for (int r = 0; r < a1 - a0; ++r) P.h_tasks[size_t(r) * nq + q] = all[a0 + r];
     }
     while (!P.h_tasks.empty() && P.h_tasks.back().blk < 0) P.h_tasks.pop_back();
+    return true;
 }
 
 void upload_fused(sp_handle* h, int k) {
@@ -1492,66 +1500,70 @@ void validate(const TList& b, const Sizes& sz, long long ncoef, long long map_si
 void validate_fused(sp_handle* h, int k) {
     const SitePlan& P = h->plan[k - 1];
     const long long xs = h->sites[k - 1].size;
-        const long long Lg = h->env[k - 1].size, Rg = h->env[k].size;
-        const int RC = P.h_rows, lmax = P.h_lds;
-        const int nblk = int(P.h_blks.size());
-        auto in_lds = [&](long long a0, long long a1, const char* what) { check_span(a0, a1, lmax, what); };
-        if (RC < 1 || RC > spk::kH3MaxRC || lmax > kHeffLdsMax) throw SpError(SP_EINVAL, "internal: fused shape");
-        std::vector<int> seen(size_t(xs) * h->G, 0);
-        for (const spk::H3Task& t : P.h_tasks) {
-            if (t.blk < 0) continue;
-            if (t.g < 0 || t.g >= h->G || t.blk >= nblk || t.rows < 1 || t.rows > RC)
-                throw SpError(SP_EINVAL, "internal: fused task");
-            const spk::H3Blk& B = P.h_blks[t.blk];
-            check_span(B.l0, B.l1 - 1, (long long)P.h_lsrc.size(), "fused L sources");
-            for (int q = B.l0; q < B.l1; ++q) {
-                const spk::H3LSrc& L = P.h_lsrc[q];
-                check_span(L.l_off + (long long)t.r0 * L.ld, L.l_off + (long long)(t.r0 + t.rows) * L.ld - 1, Lg,
-                           "fused L rows");
-                in_lds(L.lds, L.lds + (long long)RC * L.ld - 1, "fused staged L");
+    if (P.h_rows == 0) {  // no fused plan: the site runs the plain lists
+        if (!P.h_tasks.empty() || P.h_lds != 0) throw SpError(SP_EINVAL, "internal: fused plan state");
+        return;
+    }
+    const long long Lg = h->env[k - 1].size, Rg = h->env[k].size;
+    const int RC = P.h_rows, lmax = P.h_lds;
+    const int nblk = int(P.h_blks.size());
+    auto in_lds = [&](long long a0, long long a1, const char* what) { check_span(a0, a1, lmax, what); };
+    if (RC < 1 || RC > spk::kH3MaxRC || lmax > kHeffLdsMax) throw SpError(SP_EINVAL, "internal: fused shape");
+    std::vector<int> seen(size_t(xs) * h->G, 0);
+    for (const spk::H3Task& t : P.h_tasks) {
+        if (t.blk < 0) continue;
+        if (t.g < 0 || t.g >= h->G || t.blk >= nblk || t.rows < 1 || t.rows > RC)
+            throw SpError(SP_EINVAL, "internal: fused task");
+        const spk::H3Blk& B = P.h_blks[t.blk];
+        check_span(B.l0, B.l1 - 1, (long long)P.h_lsrc.size(), "fused L sources");
+        for (int q = B.l0; q < B.l1; ++q) {
+            const spk::H3LSrc& L = P.h_lsrc[q];
+            check_span(L.l_off + (long long)t.r0 * L.ld, L.l_off + (long long)(t.r0 + t.rows) * L.ld - 1, Lg,
+                       "fused L rows");
+            in_lds(L.lds, L.lds + (long long)RC * L.ld - 1, "fused staged L");
+        }
+        if (B.c1 > B.c0) check_span(B.c0, B.c1 - 1, (long long)P.h_cols.size(), "fused columns");
+        for (int ci = B.c0; ci < B.c1; ++ci) {
+            const spk::H3Col& c = P.h_cols[ci];
+            if (c.K > 0) {
+                check_span(c.x_off, c.x_off + (long long)(c.K - 1) * c.x_ld, xs, "fused x column");
+                in_lds(c.l_lds, c.l_lds + (long long)(RC - 1) * c.l_ld + c.K - 1, "fused L entries");
             }
-            if (B.c1 > B.c0) check_span(B.c0, B.c1 - 1, (long long)P.h_cols.size(), "fused columns");
-            for (int ci = B.c0; ci < B.c1; ++ci) {
-                const spk::H3Col& c = P.h_cols[ci];
-                if (c.K > 0) {
-                    check_span(c.x_off, c.x_off + (long long)(c.K - 1) * c.x_ld, xs, "fused x column");
-                    in_lds(c.l_lds, c.l_lds + (long long)(RC - 1) * c.l_ld + c.K - 1, "fused L entries");
-                }
-                in_lds(c.t_pos, c.t_pos + RC - 1, "fused T column");
-            }
-            for (int sig = 0; sig < 4; ++sig) {
-                if (B.s1[sig] > B.s0[sig]) check_span(B.s0[sig], B.s1[sig] - 1, (long long)P.h_segs.size(), "fused segments");
-                if (t.p1[sig] > t.p0[sig]) check_span(t.p0[sig], t.p1[sig] - 1, (long long)P.h_pieces.size(), "fused pieces");
-                for (int p = t.p0[sig]; p < t.p1[sig]; ++p) {
-                    const spk::H3Piece& pc = P.h_pieces[p];
-                    if (pc.rlo < 0 || pc.rhi > t.rows || pc.rlo >= pc.rhi || pc.nb < 1)
-                        throw SpError(SP_EINVAL, "internal: fused piece");
-                    for (int rr = pc.rlo; rr < pc.rhi; ++rr)
-                        for (int b = 0; b < pc.nb; ++b) {
-                            const long long o = pc.out_off + (long long)(rr - pc.rlo) * pc.out_ld + b;
-                            check_span(o, o, xs, "fused output");
-                            if (seen[size_t(t.g) * xs + o]++) throw SpError(SP_EINVAL, "internal: fused output written twice");
-                        }
-                    for (int si = B.s0[sig]; si < B.s1[sig]; ++si) {
-                        const spk::H3Seg& S = P.h_segs[si];
-                        check_span(S.r_off + (long long)pc.b0 * S.K, S.r_off + (long long)(pc.b0 + pc.nb) * S.K - 1, Rg,
-                                   "fused R rows");
+            in_lds(c.t_pos, c.t_pos + RC - 1, "fused T column");
+        }
+        for (int sig = 0; sig < 4; ++sig) {
+            if (B.s1[sig] > B.s0[sig]) check_span(B.s0[sig], B.s1[sig] - 1, (long long)P.h_segs.size(), "fused segments");
+            if (t.p1[sig] > t.p0[sig]) check_span(t.p0[sig], t.p1[sig] - 1, (long long)P.h_pieces.size(), "fused pieces");
+            for (int p = t.p0[sig]; p < t.p1[sig]; ++p) {
+                const spk::H3Piece& pc = P.h_pieces[p];
+                if (pc.rlo < 0 || pc.rhi > t.rows || pc.rlo >= pc.rhi || pc.nb < 1)
+                    throw SpError(SP_EINVAL, "internal: fused piece");
+                for (int rr = pc.rlo; rr < pc.rhi; ++rr)
+                    for (int b = 0; b < pc.nb; ++b) {
+                        const long long o = pc.out_off + (long long)(rr - pc.rlo) * pc.out_ld + b;
+                        check_span(o, o, xs, "fused output");
+                        if (seen[size_t(t.g) * xs + o]++) throw SpError(SP_EINVAL, "internal: fused output written twice");
                     }
-                }
                 for (int si = B.s0[sig]; si < B.s1[sig]; ++si) {
                     const spk::H3Seg& S = P.h_segs[si];
-                    in_lds(S.v_off, S.v_off + (long long)RC * S.K - 1, "fused V");
-                    if (S.t1 > S.t0) check_span(S.t0, S.t1 - 1, (long long)P.h_terms.size(), "fused terms");
-                    for (int tm = S.t0; tm < S.t1; ++tm) {
-                        in_lds(P.h_terms[tm].t_base, P.h_terms[tm].t_base + (long long)RC * S.K - 1, "fused T block");
-                        check_span(P.h_terms[tm].cidx, P.h_terms[tm].cidx, P.nc, "fused coefficient");
-                    }
+                    check_span(S.r_off + (long long)pc.b0 * S.K, S.r_off + (long long)(pc.b0 + pc.nb) * S.K - 1, Rg,
+                               "fused R rows");
+                }
+            }
+            for (int si = B.s0[sig]; si < B.s1[sig]; ++si) {
+                const spk::H3Seg& S = P.h_segs[si];
+                in_lds(S.v_off, S.v_off + (long long)RC * S.K - 1, "fused V");
+                if (S.t1 > S.t0) check_span(S.t0, S.t1 - 1, (long long)P.h_terms.size(), "fused terms");
+                for (int tm = S.t0; tm < S.t1; ++tm) {
+                    in_lds(P.h_terms[tm].t_base, P.h_terms[tm].t_base + (long long)RC * S.K - 1, "fused T block");
+                    check_span(P.h_terms[tm].cidx, P.h_terms[tm].cidx, P.nc, "fused coefficient");
                 }
             }
         }
-        for (long long o = 0; o < (long long)xs * h->G; ++o)
-            if (seen[o] != 1) throw SpError(SP_EINVAL, "internal: fused outputs do not cover the site");
     }
+    for (long long o = 0; o < (long long)xs * h->G; ++o)
+        if (seen[o] != 1) throw SpError(SP_EINVAL, "internal: fused outputs do not cover the site");
+}
 
 void validate_plans(sp_handle* h) {
     const long long G = h->G;
@@ -1698,6 +1710,19 @@ spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32) {
     return I;
 }
 
+// H_eff x at a tiled-path site without a fused plan (a particle-number block
+// too wide for its LDS): the LDS-tiled block-product lists, FP64 in either
+// precision, leaving the same per-g partials as the fused kernel
+void heff_tiled(sp_handle* h, int k, const double* x) {
+    SitePlan& P = h->plan[k - 1];
+    hipStream_t s = h->stream;
+    const spk::BufSet b = bufset(h, k, h->Xd.p, h->ypart.p, h->nypart.p, nullptr);
+    spk::gather(s, P.xmap.p, x, h->Xd.p, P.Xd_size);
+    P.t_left.launch(s, b, P.coef.p, P.xmap.p);
+    P.mixl.launch(s, b, P.coef.p);
+    P.t_right.launch(s, b, P.coef.p, P.xmap.p);
+}
+
 // With defer_gsum on the tiled path only the per-quadrature-point partials
 // (h->ypart, h->nypart) are produced and the function returns true: the
 // caller adds them (the Davidson Gram pass does).
@@ -1715,10 +1740,14 @@ bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, boo
         return false;
     }
     const int n = int(h->sites[k - 1].size);
-    const bool f32 = h->precision == SP_FP32 && !force_fp64;
-    const spk::H3Inst I = heff_inst(h, k, x, f32);
-    if (f32) spk::heff3_f32(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
-    else spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
+    if (P.h_rows == 0) {
+        heff_tiled(h, k, x);
+    } else {
+        const bool f32 = h->precision == SP_FP32 && !force_fp64;
+        const spk::H3Inst I = heff_inst(h, k, x, f32);
+        if (f32) spk::heff3_f32(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
+        else spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
+    }
     if (defer_gsum) return true;
     spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
     return false;
@@ -2220,8 +2249,13 @@ void batch_heff_mixed(std::vector<BatchState>& B, const std::vector<int>& idx, c
     for (size_t q = 0; q < idx.size(); ++q) {
         BatchState& st = B[idx[q]];
         sp_handle* h = st.h;
-        insts[q] = heff_inst(h, st.k, from_v0[idx[q]] ? h->dV.p : h->dt.p, f32);
+        const double* x = from_v0[idx[q]] ? h->dV.p : h->dt.p;
+        insts[q] = heff_inst(h, st.k, x, f32);
         const SitePlan& P = h->plan[st.k - 1];
+        if (P.h_rows == 0) {  // no fused plan: this state's tiled lists, same partials
+            heff_tiled(h, st.k, x);
+            continue;
+        }
         auto& v = by_rc[P.h_rows];
         for (spk::H3Task t : P.h_tasks) {
             if (t.blk < 0) continue;
@@ -2646,7 +2680,7 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         long long Tmax = 0, Vmax = 0, qrs = 0, qrr = 0;
         for (int k = 1; k <= h->L; ++k) {
             build_plan(h.get(), k);
-            build_fused(h.get(), k);
+            if (h->path == SP_PATH_TILED && !build_fused(h.get(), k)) build_fused(h.get(), k, kHeffLdsMax);
             const SitePlan& P = h->plan[k - 1];
             Tmax = std::max({Tmax, P.Tsize, P.Zsize});
             Vmax = std::max({Vmax, P.Vsize, P.Ztsize});
@@ -2830,11 +2864,7 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
             int best_b = 0, best_rc = 0, last_rc = -1;
             float best = 1e30f;
             for (int b : candidates) {
-                try {
-                    build_fused(h, k, b);
-                } catch (const SpError&) {
-                    continue;  // a block too wide for this budget
-                }
+                if (!build_fused(h, k, b)) continue;  // a block too wide for this budget
                 if (P.h_rows == last_rc) continue;  // same plan as the previous budget
                 last_rc = P.h_rows;
                 validate_fused(h, k);
@@ -2865,8 +2895,13 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
                     best_rc = P.h_rows;
                 }
             }
-            SP_REQUIRE(best_b > 0, "no fused-kernel plan could be launched");
-            build_fused(h, k, best_b);
+            if (best_b > 0) {
+                build_fused(h, k, best_b);
+            } else {  // no budget fits or launches: the site keeps the plain lists
+                P.h_rows = 0;
+                P.h_lds = 0;
+                P.h_tasks.clear();
+            }
             validate_fused(h, k);
             upload_fused(h, k);
             HIPCK(hipStreamSynchronize(s));
@@ -2876,6 +2911,28 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        return SP_OK;
+    });
+}
+
+int sp_set_heff_plan(sp_handle* h, int site, int lds_budget, int* rows) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h, "bad arguments");
+        check_site(h, site);
+        SP_REQUIRE(h->path == SP_PATH_TILED, "H_eff plans belong to the tiled path");
+        SP_REQUIRE(lds_budget == 0 || (lds_budget >= 1 && lds_budget <= kHeffLdsMax),
+                   "LDS budget outside 0..18432 doubles");
+        SitePlan& P = h->plan[site - 1];
+        HIPCK(hipStreamSynchronize(h->stream));  // the old plan may still be in use
+        if (lds_budget == 0 || !build_fused(h, site, lds_budget)) {
+            P.h_rows = 0;
+            P.h_lds = 0;
+            P.h_tasks.clear();
+        }
+        validate_fused(h, site);
+        upload_fused(h, site);
+        HIPCK(hipStreamSynchronize(h->stream));
+        if (rows) *rows = P.h_rows;
         return SP_OK;
     });
 }
@@ -3027,7 +3084,9 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
             out[7] = 8.0 * (G * P.Tsize + G * P.Vsize);
             out[8] = 8.0 * (G * P.Vsize + G * P.Tsize + Rb + 2.0 * xs);
         } else {
-            // fused launch: environments and x read once, per-g partials written
+            // the product into per-g partials (the fused launch, or the tiled
+            // lists at a site without a fused plan): environments and x read
+            // once, per-g partials written
             out[3] = P.p1.flops + P.mixl.flops + P.yout.flops;
             out[4] = 0.0;
             out[5] = 2.0 * G * xs;
@@ -3087,6 +3146,16 @@ int sp_mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n) {
     return guarded([&]() -> int {
         SP_REQUIRE(L >= 1 && X >= 1 && X <= L && Y >= 1 && Y <= L && w && n, "bad arguments");
         return sph::mpo_spin_corr(L, X, Y, w, data, n);
+    });
+}
+
+int sp_mpo_abinitio(int K, const double* h, const double* eri, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(K >= 2 && K <= 64 && h && eri && w && n, "bad arguments");
+        const int r = sph::mpo_abinitio(K, h, eri, w, data, n);
+        SP_REQUIRE(r != -2, "ab-initio MPO: a bond needs more than 4096 channels");
+        SP_REQUIRE(r == 0, "ab-initio MPO: internal error");
+        return 0;
     });
 }
 

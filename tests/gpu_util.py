@@ -8,10 +8,12 @@ from oracle import mpo as ompo, mps as omps
 
 
 def make_pair(L, N, twoM, D, twoS, G, U=4.0, t=1.0, seed=1, op="hubbard", oracle=True, path="tiled",
-              precision="fp64"):
+              precision="fp64", integrals=None):
     tab = W.make_block_table(L, N, twoM, D)
     blocks = W.random_blocks(tab, seed)
-    if op == "hubbard":
+    if op == "abinitio":  # integrals = (h, eri); each side builds its own MPO
+        mine, ref = sp.mpo_abinitio(*integrals), (ompo.abinitio_mpo(*integrals) if oracle else None)
+    elif op == "hubbard":
         mine, ref = sp.mpo_hubbard(L, t, U), ompo.hubbard_mpo(L, t, U)
     elif op == "s2":
         mine, ref = sp.mpo_s2(L), ompo.s2_mpo(L)

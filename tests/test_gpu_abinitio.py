@@ -1,0 +1,208 @@
+"""Parity of the HIP path with the FP64 oracle on ab-initio Hamiltonians
+(Eq. [sqH]) with seeded synthetic integrals.  The library builds its MPO with
+its own O(K^2) construction, the oracle with its own automaton; both are the
+same operator (pinned against exact diagonalisation on the CPU), so H_eff and
+N_eff as maps on the site tensor agree whatever the MPO layout.
+
+Cases cover the fused kernel, the LDS-tiled block products that sites too
+wide for the fused kernel run (forced here with sp_set_heff_plan), the plain
+path, FP32 products and batched sweeps.  Tolerances as in the Hubbard parity
+tests: 1e-11 relative for products, 1e-8 for sweep energies in FP64, 1e-6 in
+FP32."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_util import make_pair, rel_err  # noqa: E402
+
+import paper_1703_04789_amd as sp  # noqa: E402
+import workloads as W  # noqa: E402
+from oracle import ed, mps as omps, quadrature as oq  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = [  # (K, N, 2M, D, 2S)
+    (4, 4, 0, 16, 0),
+    (5, 4, 0, 24, 2),
+    (5, 5, 1, 20, 1),
+    (6, 6, 0, 32, 0),
+]
+
+
+def _pair(K, N, twoM, D, twoS, path="tiled", precision="fp64", oracle=True, seed=1):
+    G = oq.exact_point_count(N, K, twoS, twoM)
+    ints = W.abinitio_integrals(K, seed=4)
+    return make_pair(K, N, twoM, D, twoS, G, seed=seed, op="abinitio", integrals=ints, path=path,
+                     precision=precision, oracle=oracle)
+
+
+def _dev(a):
+    return torch.tensor(a, dtype=torch.float64, device="cuda")
+
+
+def _force_tiled(gpu):
+    for k in range(1, gpu.L + 1):
+        assert gpu.set_heff_plan(k, 0) == 0
+
+
+@pytest.mark.parametrize("plan", ["fused", "tiled-lists", "plain"])
+@pytest.mark.parametrize("case", CASES)
+def test_abinitio_heff_all_sites(case, plan):
+    tab, gpu, orc = _pair(*case, path="plain" if plan == "plain" else "tiled")
+    if plan == "tiled-lists":
+        _force_tiled(gpu)
+    rng = np.random.default_rng(3)
+    for k in range(1, tab.L + 1):
+        if k > 1:
+            gpu.env_update(k - 1, +1)
+            orc.update_left(k - 1)
+        n = gpu.site_size(k)
+        x = rng.standard_normal(n)
+        y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
+        xd = _dev(x)
+        y, ny = torch.empty_like(xd), torch.empty_like(xd)
+        gpu.heff_apply(k, xd, y, ny)
+        dh, dn = torch.empty_like(xd), torch.empty_like(xd)
+        gpu.heff_diag(k, dh, dn)
+        torch.cuda.synchronize()
+        assert rel_err(y.cpu().numpy(), orc.mps.site_packed(k, y_ref)) < 1e-11, k
+        assert rel_err(ny.cpu().numpy(), orc.mps.site_packed(k, ny_ref)) < 1e-11, k
+        dh_ref, dn_ref = orc.heff_diag(k)
+        assert rel_err(dh.cpu().numpy(), orc.mps.site_packed(k, dh_ref)) < 1e-11, k
+        assert rel_err(dn.cpu().numpy(), orc.mps.site_packed(k, dn_ref)) < 1e-11, k
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_abinitio_energy_at_centre(case):
+    tab, gpu, orc = _pair(*case)
+    E, p = gpu.energy()
+    Ef, pf = orc.full_contraction()
+    assert abs(E - Ef) < 1e-10
+
+
+@pytest.mark.parametrize("plan", ["fused", "tiled-lists", "plain"])
+def test_abinitio_sweep_matches_oracle(plan):
+    # exact local solves, so both trajectories are the same smooth function
+    # of the input
+    case = (5, 4, 0, 24, 2)
+    tab, gpu, orc = _pair(*case, path="plain" if plan == "plain" else "tiled")
+    if plan == "tiled-lists":
+        _force_tiled(gpu)
+    rc, steps = gpu.sweep(2, max_sub=128, max_iter=200)
+    ref = omps.sweep(orc, 2, max_sub=128, max_iter=200)
+    dE = max(abs(a["theta"] - b["theta"]) for a, b in zip(steps, ref))
+    assert dE < 1e-8, dE
+
+
+@pytest.mark.parametrize("twoS", [0, 2])
+def test_abinitio_full_bond_dimension_reaches_ed(twoS):
+    K, N = 4, 4
+    h, eri = W.abinitio_integrals(K, seed=4)
+    st = ed.sector_states(K, N, 0)
+    e_ed = ed.projected_ground_energy(ed.abinitio_hamiltonian(h, eri, st),
+                                      ed.lowdin_projector(ed.s2_operator(K, st), twoS, 0, N))
+    tab, gpu, _ = _pair(K, N, 0, 16, twoS, oracle=False, seed=5)
+    rc, steps = gpu.sweep(3, max_sub=128, max_iter=200)
+    assert abs(steps[-1]["theta"] - e_ed) < 1e-9
+    E, p = gpu.energy()
+    assert abs(E - e_ed) < 1e-9
+
+
+def test_abinitio_fp32_products():
+    # FP32 environments and accumulation: every site's products within 1e-5
+    # of the FP64 oracle relative to the largest entry (the FP32 bar of the
+    # Hubbard tests)
+    case = (6, 6, 0, 32, 0)
+    tab, gpu, orc = _pair(*case, precision="fp32")
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for k in range(1, tab.L + 1):
+        if k > 1:
+            orc.mps.left_orthonormalize(k - 1)
+            orc.update_left(k - 1)
+            gpu.set_site(k - 1, orc.mps.site_packed(k - 1))
+            gpu.set_site(k, orc.mps.site_packed(k))
+            gpu.env_update(k - 1, +1)
+        n = gpu.site_size(k)
+        x = rng.standard_normal(n)
+        y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
+        xd = _dev(x)
+        y, ny = torch.empty_like(xd), torch.empty_like(xd)
+        gpu.heff_apply(k, xd, y, ny)
+        torch.cuda.synchronize()
+        e1 = rel_err(y.cpu().numpy(), orc.mps.site_packed(k, y_ref))
+        e2 = rel_err(ny.cpu().numpy(), orc.mps.site_packed(k, ny_ref))
+        worst = max(worst, e1, e2)
+        assert e1 < 1e-5 and e2 < 1e-5, (k, e1, e2)
+    print(f"[abinitio fp32] worst product error {worst:.2e}", flush=True)
+
+
+def test_abinitio_fp32_sweeps_reach_the_fp64_energy():
+    # K=6, N=6, D=32: ten sweeps in FP32 (solver tolerance 1e-5) and in FP64
+    # (1e-9, pinned to the oracle step by step above); the energies reached
+    # agree to the reduced-precision target
+    case = (6, 6, 0, 32, 0)
+    res = {}
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-5)):
+        _, gpu, _ = _pair(*case, precision=prec, oracle=False)
+        rc, steps = gpu.sweep(10, max_sub=128, max_iter=200, tol=tol)
+        res[prec] = steps[-1]["theta"]
+        gpu.close()
+    dE = abs(res["fp32"] - res["fp64"])
+    print(f"[abinitio fp32] K=6 D=32 after 10 sweeps: fp64 {res['fp64']:.10f} fp32 {res['fp32']:.10f} "
+          f"|dE| {dE:.2e}", flush=True)
+    assert dE < 1e-6
+
+
+def test_abinitio_wide_mpo_tiled_and_plain_paths_agree():
+    # K = 12, D = 128: the centre sites are too wide for the fused kernel and
+    # run the tiled block products automatically; the plain path is the
+    # reference here (the oracle's automaton MPO is too large at K = 12)
+    wl = W.abinitio_reduced(12, 128, 11)
+    h, eri = wl.integrals()
+    mine = sp.mpo_abinitio(h, eri)
+    tab, blocks = wl.table(), wl.blocks()
+    print(f"[case] {wl.name}", flush=True)
+    a = sp.SPMPS(tab, blocks, mine, wl.twoS, wl.G, path="tiled")
+    b = sp.SPMPS(tab, blocks, mine, wl.twoS, wl.G, path="plain")
+    Ea, _ = a.energy()
+    Eb, _ = b.energy()
+    assert abs(Ea - Eb) < 1e-10 * max(1.0, abs(Eb))
+    rng = np.random.default_rng(2)
+    for k in range(1, wl.K // 2 + 1):
+        if k > 1:
+            a.env_update(k - 1, +1)
+            b.env_update(k - 1, +1)
+        n = a.site_size(k)
+        xd = _dev(rng.standard_normal(n))
+        ya, nya, yb, nyb = (torch.empty_like(xd) for _ in range(4))
+        a.heff_apply(k, xd, ya, nya)
+        b.heff_apply(k, xd, yb, nyb)
+        torch.cuda.synchronize()
+        assert rel_err(ya.cpu().numpy(), yb.cpu().numpy()) < 1e-11, k
+        assert rel_err(nya.cpu().numpy(), nyb.cpu().numpy()) < 1e-11, k
+
+
+def test_abinitio_batched_sweeps_match_single():
+    # two ab-initio states (one with every site on the tiled block products)
+    # and a Hubbard state advanced together
+    cases = [(5, 4, 0, 24, 2), (6, 6, 0, 32, 0)]
+    singles, batch = [], []
+    for i, c in enumerate(cases):
+        _, s1, _ = _pair(*c, oracle=False, seed=7 + i)
+        _, s2, _ = _pair(*c, oracle=False, seed=7 + i)
+        if i == 0:
+            _force_tiled(s1)
+            _force_tiled(s2)
+        singles.append(s1)
+        batch.append(s2)
+    _, hs1, _ = make_pair(8, 8, 0, 32, 0, 5, seed=3, oracle=False)
+    _, hs2, _ = make_pair(8, 8, 0, 32, 0, 5, seed=3, oracle=False)
+    singles.append(hs1)
+    batch.append(hs2)
+    ref = [s.sweep(2)[1] for s in singles]
+    rc, got = sp.sweep_batch(batch, 2)
+    for r, g in zip(ref, got):
+        assert len(r) == len(g)
+        assert max(abs(a["theta"] - b["theta"]) for a, b in zip(r, g)) < 1e-10

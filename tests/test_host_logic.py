@@ -203,3 +203,56 @@ def test_init_plans_pass_host_validation_odd_cases():
     tab = W.make_block_table(6, 6, 0, 20)
     rc, msg = _init_rc(tab, 2, 4, mpo_=sp.mpo_s2(6))
     assert rc == sp.SP_EHIP, msg
+
+
+def _mpo_sites(w, data):
+    out, pos = [], 0
+    for k in range(1, len(w)):
+        n = int(w[k - 1]) * int(w[k]) * 16
+        out.append(data[pos:pos + n].reshape(int(w[k - 1]), int(w[k]), 4, 4))
+        pos += n
+    return out
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_abinitio_mpo_matches_exact_hamiltonian(K):
+    from oracle import ed
+    h, eri = W.abinitio_integrals(K, seed=11)
+    w, data = sp.mpo_abinitio(h, eri)
+    Hd = mpo.mpo_to_dense(_mpo_sites(w, data))
+    for N in range(1, 2 * K):
+        for twoM in range(-N, N + 1, 2):
+            st = ed.sector_states(K, N, twoM)
+            if len(st):
+                np.testing.assert_allclose(Hd[np.ix_(st, st)], ed.abinitio_hamiltonian(h, eri, st).toarray(),
+                                           atol=1e-12)
+
+
+def test_abinitio_mpo_matches_oracle_mpo_and_is_compact():
+    K = 5
+    h, eri = W.abinitio_integrals(K, seed=4)
+    w, data = sp.mpo_abinitio(h, eri)
+    ref = mpo.abinitio_mpo(h, eri)
+    np.testing.assert_allclose(mpo.mpo_to_dense(_mpo_sites(w, data)), mpo.mpo_to_dense(ref), atol=1e-12)
+    # partial products named by at most two operators: O(K^2) channels, far
+    # fewer than the oracle's automaton that names whole remainders
+    assert max(w) < max(r.shape[1] for r in ref[:-1]) / 10
+    w16, _ = sp.mpo_abinitio(*W.abinitio_integrals(16, seed=4))
+    assert w16[0] == w16[16] == 1 and max(w16) <= 3 * 16 * 16
+
+
+def test_abinitio_mpo_rejects_bad_sizes():
+    with pytest.raises(sp.SpError):
+        sp.mpo_abinitio(np.zeros((1, 1)), np.zeros((1, 1, 1, 1)))
+
+
+@pytest.mark.parametrize("K,D,G", [(6, 32, 7), (8, 64, 9), (12, 128, 11)])
+def test_init_abinitio_plans_pass_host_validation(K, D, G):
+    """Wide MPOs: sites whose particle-number blocks do not fit the fused
+    kernel get the block-product lists; every list is bounds-checked."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present: covered by the GPU tests")
+    tab = W.make_block_table(K, K, 0, D)
+    rc, msg = _init_rc(tab, 0, G, mpo_=sp.mpo_abinitio(*W.abinitio_integrals(K, seed=4)))
+    assert rc == sp.SP_EHIP, msg

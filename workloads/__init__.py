@@ -287,3 +287,63 @@ def hubbard_batch(n: int = 64, seed0: int = 100, D_choices=(64, 128, 256, 512)) 
         out.append(HubbardWorkload(f"hubbard_batch{i}_L{L}_U{int(U)}_D{D}", L=L, t=1.0, U=U, N=L, twoS=0, twoM=0,
                                    D=D, G=9, sweeps=4, seed=seed0 + i, init="neel", noise=1e-2))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Synthetic ab-initio-shaped Hamiltonians (real orbitals, chemists' notation).
+
+
+def abinitio_integrals(K: int, seed: int, rank: int | None = None, decay: float = 4.0):
+    """Seeded one- and two-electron integrals of K spatial orbitals.
+
+    h_pq = h_qp = g_pq exp(-|p-q|/decay) with g_pq ~ N(0, 1) (upper triangle
+    drawn, mirrored).  (pq|rs) = sum_l B^l_pq B^l_rs over ``rank`` (default
+    2K) symmetric factors B^l_pq = g^l_pq exp(-|p-q|/decay) / sqrt(rank), so
+    the tensor has the 8-fold permutational symmetry of real orbitals and is
+    positive semidefinite as a (pq),(rs) matrix.  Returns (h, eri) with eri
+    indexed [p, q, r, s] = (pq|rs)."""
+    rank = 2 * K if rank is None else rank
+    rng = np.random.default_rng(seed)
+    idx = np.arange(K)
+    env = np.exp(-np.abs(idx[:, None] - idx[None, :]) / decay)
+
+    def sym(a):
+        return np.triu(a) + np.triu(a, 1).T
+
+    h = sym(rng.standard_normal((K, K))) * env
+    B = np.stack([sym(rng.standard_normal((K, K))) * env for _ in range(rank)]) / math.sqrt(rank)
+    eri = np.einsum("lpq,lrs->pqrs", B, B)
+    return np.ascontiguousarray(h), np.ascontiguousarray(eri)
+
+
+@dataclass
+class AbInitioWorkload:
+    name: str
+    K: int
+    N: int
+    twoS: int
+    twoM: int
+    D: int
+    G: int
+    sweeps: int
+    seed: int
+
+    def integrals(self):
+        return abinitio_integrals(self.K, self.seed)
+
+    def table(self) -> BlockTable:
+        return make_block_table(self.K, self.N, self.twoM, self.D)
+
+    def blocks(self) -> np.ndarray:
+        return random_blocks(self.table(), self.seed + 1000)
+
+
+def abinitio_full() -> AbInitioWorkload:
+    """K=30 orbitals, N=30, M=0, S=0, D=500, G=11, seed 4."""
+    return AbInitioWorkload("abinitio_K30_D500_G11", K=30, N=30, twoS=0, twoM=0, D=500, G=11, sweeps=4, seed=4)
+
+
+def abinitio_reduced(K: int = 12, D: int = 128, G: int = 11) -> AbInitioWorkload:
+    """The same integral recipe at fewer orbitals and a smaller bond
+    dimension: half filling, M=0, S=0, seed 4."""
+    return AbInitioWorkload(f"abinitio_K{K}_D{D}_G{G}", K=K, N=K, twoS=0, twoM=0, D=D, G=G, sweeps=4, seed=4)
