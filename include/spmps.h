@@ -192,6 +192,11 @@ int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_repor
  * tiled block products (rows 0).  Synchronises. */
 int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* usec_out);
 
+/* Current H_eff plan of a site: rows per task of the fused kernel and its
+ * LDS in doubles, or 0 and 0 (plain path, or a tiled-path site that runs the
+ * tiled block products).  Host only. */
+int sp_heff_plan(const sp_handle* h, int site, int* rows, int* lds_doubles);
+
 /* Choose the H_eff plan of one site (tiled path): the fused kernel with an
  * LDS budget of `lds_budget` doubles per work-group (1..18432; it sets the
  * rows per task), or 0 for the LDS-tiled block products.  A budget that no

@@ -29,7 +29,7 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_last_error", "sp_quadrature", "sp_exact_points", "sp_mpo_hubbard", "sp_mpo_s2",
            "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch", "sp_autotune",
            "sp_mpo_site_op", "sp_mpo_epq", "sp_mpo_spin_corr", "sp_expect",
-           "sp_mpo_abinitio", "sp_set_heff_plan"]
+           "sp_mpo_abinitio", "sp_set_heff_plan", "sp_heff_plan"]
 
 
 class SpError(RuntimeError):
@@ -96,6 +96,7 @@ def lib():
         "sp_sweep_batch": [P(vp), ctypes.c_int, P(_SweepOpts), P(_SweepReport)],
         "sp_autotune": [vp, ctypes.c_int, ip, ip, dp],
         "sp_set_heff_plan": [vp, ctypes.c_int, ctypes.c_int, ip],
+        "sp_heff_plan": [vp, ctypes.c_int, ip, ip],
         "sp_mpo_site_op": [ctypes.c_int, ctypes.c_int, dp, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_epq": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_spin_corr": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
@@ -363,6 +364,13 @@ class SPMPS:
         us = np.zeros(self.L)
         _check(lib().sp_autotune(self._h, reps, _iptr(b), _iptr(r), _dptr(us)))
         return [(int(b[i]), int(r[i]), float(us[i])) for i in range(self.L)]
+
+    def heff_plan(self, site):
+        """(rows per task, LDS doubles) of the site's fused plan; (0, 0) when
+        the site runs the tiled block products or the plain path."""
+        rows, lds = ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib().sp_heff_plan(self._h, site, ctypes.byref(rows), ctypes.byref(lds)))
+        return rows.value, lds.value
 
     def set_heff_plan(self, site, lds_budget):
         """Fused kernel with this LDS budget (doubles) at ``site``, or 0 for

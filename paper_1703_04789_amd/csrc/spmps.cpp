@@ -2915,6 +2915,16 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
     });
 }
 
+int sp_heff_plan(const sp_handle* h, int site, int* rows, int* lds_doubles) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && rows, "bad arguments");
+        check_site(h, site);
+        *rows = h->plan[site - 1].h_rows;
+        if (lds_doubles) *lds_doubles = h->plan[site - 1].h_lds;
+        return SP_OK;
+    });
+}
+
 int sp_set_heff_plan(sp_handle* h, int site, int lds_budget, int* rows) {
     return guarded([&]() -> int {
         SP_REQUIRE(h, "bad arguments");
