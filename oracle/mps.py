@@ -176,16 +176,20 @@ def rotated_mpo(W, r):
     return [np.einsum("abst,tu->absu", w, r) for w in W]
 
 
-def env_left(Lprev, A, Wt):
-    """L[b, v, d] = sum A[s,a,b] Lprev[a,w,c] Wt[w,v,s,t] A[t,c,d]."""
-    X1 = np.einsum("awc,tcd->awtd", Lprev, A, optimize=True)
+def env_left(Lprev, A, Wt, K=None):
+    """L[b, v, d] = sum A[s,a,b] Lprev[a,w,c] Wt[w,v,s,t] K[t,c,d]: bra
+    tensor A, ket tensor K (default A)."""
+    K = A if K is None else K
+    X1 = np.einsum("awc,tcd->awtd", Lprev, K, optimize=True)
     X2 = np.einsum("awtd,wvst->avsd", X1, Wt, optimize=True)
     return np.einsum("sab,avsd->bvd", A, X2, optimize=True)
 
 
-def env_right(Rnext, A, Wt):
-    """R[a, w, c] = sum A[s,a,b] Wt[w,v,s,t] A[t,c,d] Rnext[b,v,d]."""
-    Y1 = np.einsum("tcd,bvd->tcbv", A, Rnext, optimize=True)
+def env_right(Rnext, A, Wt, K=None):
+    """R[a, w, c] = sum A[s,a,b] Wt[w,v,s,t] K[t,c,d] Rnext[b,v,d]: bra A,
+    ket K (default A)."""
+    K = A if K is None else K
+    Y1 = np.einsum("tcd,bvd->tcbv", K, Rnext, optimize=True)
     Y2 = np.einsum("wvst,tcbv->swcb", Wt, Y1, optimize=True)
     return np.einsum("sab,swcb->awc", A, Y2, optimize=True)
 
@@ -316,16 +320,32 @@ class DavidsonResult:
 
 
 def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
-             drop=1e-10, floor=1e-8):
+             drop=1e-10, floor=1e-8, C=None):
     """Lowest theta of H x = theta N x within range(N).
 
     matvec(v) -> (H v, N v) on flat vectors.  Returns a DavidsonResult with
     x normalised to unit Euclidean norm and pnorm = x^T N x.
+
+    C (n x c, orthonormal columns) restricts the search to the complement of
+    span(C) (the constraints of Eq. [orthoB]): with Q = 1 - C C^T the
+    pencil becomes (Q H Q, Q N Q), i.e. the start vector, every H v, N v and
+    every correction are multiplied by Q (twice, for rounding), so the
+    residual is the projected one.
     """
-    v = x0 / np.linalg.norm(x0)
+    if C is not None and C.shape[1] > 0:
+        def proj(u):
+            for _ in range(2):
+                u = u - C @ (C.T @ u)
+            return u
+    else:
+        def proj(u):
+            return u
+    v = proj(x0)
+    v = v / np.linalg.norm(v)
     V = [v]
     HV, NV = [], []
     hv, nv = matvec(v)
+    hv, nv = proj(hv), proj(nv)
     HV.append(hv)
     NV.append(nv)
     theta = 0.0
@@ -360,7 +380,7 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
             break
         den = dH - theta * dN
         den = np.where(np.abs(den) < floor, np.where(den < 0, -floor, floor), den)
-        t = -r / den
+        t = proj(-r / den)
         if len(V) >= max_sub:
             nk = min(keep, Cm.shape[1])
             Ak = X @ Cm[:, :nk]
@@ -377,18 +397,88 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
         t = t / tn
         V.append(t)
         hv, nv = matvec(t)
+        hv, nv = proj(hv), proj(nv)
         HV.append(hv)
         NV.append(nv)
     pn = float(x @ nx)
     return DavidsonResult(theta, x, rn, it, rn <= tol, pn)
 
 
+def orthonormal_constraints(vectors, rel_drop=1e-10):
+    """Orthonormal basis of the constraint vectors B_j (Eq. [orthoB]) by
+    Gram-Schmidt in the given order, each projection done twice; a vector
+    whose remainder falls below rel_drop times its own norm is dependent on
+    the earlier ones and dropped.  Returns an n x c array."""
+    cols = []
+    for b in vectors:
+        nb = float(np.linalg.norm(b))
+        u = np.array(b, dtype=float)
+        for _ in range(2):
+            for c in cols:
+                u = u - c * float(c @ u)
+        nu = float(np.linalg.norm(u))
+        if nb > 0.0 and nu > rel_drop * nb:
+            cols.append(u / nu)
+    n = len(vectors[0]) if len(vectors) else 0
+    return np.array(cols).T if cols else np.zeros((n, 0))
+
+
+class OrthogonalityConstraint:
+    """Orthogonality of the optimised state Psi to a fixed state Psi_0 in the
+    projected metric, <Psi_0|P|Psi> = 0 (Sec. 2.3, Eq. [orthoB]).
+
+    Keeps, for every quadrature point, the environments of
+    <Psi|R(beta_g)|Psi_0> (bra: the optimised state, ket: Psi_0, the rotated
+    identity MPO between them), updated as the sweep changes Psi, and builds
+    B[k] = sum_g coef_g L_g[k-1] (r_g Psi_0[k]) R_g[k+1], the derivative of
+    <Psi|P|Psi_0> = <Psi_0|P|Psi> with respect to Psi's site tensor k.  Psi_0
+    keeps the gauge it is given in."""
+
+    def __init__(self, state: SPMPSOracle, table, packed0):
+        self.state = state
+        self.psi0 = OracleMPS(table, packed0)
+        L, G = state.L, state.G
+        one = np.ones((1, 1, 1))
+        self.Le = [[None] * (L + 2) for _ in range(G)]
+        self.Re = [[None] * (L + 2) for _ in range(G)]
+        for g in range(G):
+            self.Le[g][0] = one.copy()
+            self.Re[g][L + 1] = one.copy()
+        for k in range(L, 1, -1):
+            self.update_right(k)
+
+    def update_left(self, k):
+        A, K = self.state.mps.A[k - 1], self.psi0.A[k - 1]
+        for g in range(self.state.G):
+            self.Le[g][k] = env_left(self.Le[g][k - 1], A, self.state.It[g][k - 1], K)
+
+    def update_right(self, k):
+        A, K = self.state.mps.A[k - 1], self.psi0.A[k - 1]
+        for g in range(self.state.G):
+            self.Re[g][k] = env_right(self.Re[g][k + 1], A, self.state.It[g][k - 1], K)
+
+    def vector(self, k):
+        """B[k] in Psi's dense-padded site layout."""
+        out = np.zeros(self.state.mps.A[k - 1].shape)
+        for g in range(self.state.G):
+            out += self.state.quad["coef"][g] * apply_local(self.Le[g][k - 1], self.state.It[g][k - 1],
+                                                             self.Re[g][k + 1], self.psi0.A[k - 1])
+        return np.where(self.state.mps.mask[k - 1], out, 0.0)
+
+    def overlap(self, k):
+        """<Psi_0|P|Psi> from the environments around site k."""
+        return float(np.sum(self.vector(k) * self.state.mps.A[k - 1]))
+
+
 def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
-          keep=8, record=None):
+          keep=8, record=None, constraints=()):
     """One-site sweeps (Sec. 2.3): right-moving k = 1..L-1 then left-moving
     k = L..2.  Each step solves the local problem, restores the canonical
     form with a positive-diagonal QR (right-moving) or LQ (left-moving) and
-    updates the environments of the bond it leaves behind.
+    updates the environments of the bond it leaves behind.  With
+    ``constraints`` (OrthogonalityConstraint objects built on this state)
+    every local solve is restricted to the complement of the B[k] vectors
+    of Eq. [orthoB] (excited states).
 
     Returns a list of per-step dicts (sweep, site, dir, theta, pnorm, rnorm,
     iters)."""
@@ -409,17 +499,22 @@ def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
                 return y.ravel()[idx], ny.ravel()[idx]
             dh, dn = state.heff_diag(k)
             x0 = mps.A[k - 1].ravel()[idx]
+            C = orthonormal_constraints([c.vector(k).ravel()[idx] for c in constraints]) if constraints else None
             res = davidson(mv, dh.ravel()[idx], dn.ravel()[idx], x0, tol=tol,
-                           max_iter=max_iter, max_sub=max_sub, keep=keep)
+                           max_iter=max_iter, max_sub=max_sub, keep=keep, C=C)
             xd = np.zeros(int(np.prod(shape)))
             xd[idx] = res.x
             mps.A[k - 1] = xd.reshape(shape)
             if d > 0:
                 mps.left_orthonormalize(k)
                 state.update_left(k)
+                for c in constraints:
+                    c.update_left(k)
             else:
                 mps.right_orthonormalize(k)
                 state.update_right(k)
+                for c in constraints:
+                    c.update_right(k)
             steps.append(dict(sweep=sw, site=k, dir=d, theta=res.theta, pnorm=res.pnorm,
                               rnorm=res.rnorm, iters=res.iters, converged=res.converged))
             if record is not None:
