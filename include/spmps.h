@@ -205,6 +205,28 @@ int sp_heff_plan(const sp_handle* h, int site, int* rows, int* lds_doubles);
  * The products are the same to rounding either way.  Synchronises. */
 int sp_set_heff_plan(sp_handle* h, int site, int lds_budget, int* rows);
 
+/* Excited states (Sec. 2.3, Eq. [orthoB]): later sp_sweep calls on h keep
+ * h's state orthogonal to `lower` in the projected metric,
+ * <lower|P|h> = 0.  At every site step the vectors B[k] = d<lower|P|h>/dA[k]
+ * of all constraints are built from environments of <h|R(beta_g)|lower>
+ * (this state on the bra side), orthonormalised in the order the
+ * constraints were added (a vector dependent on the earlier ones to 1e-10
+ * is skipped), and the local solve runs on (Q H_eff Q, Q N_eff Q) with
+ * Q = 1 - C C^T: start vector, products and corrections are projected.
+ * `lower`'s tensors are copied at this call (later changes to `lower` are
+ * not seen); it must have the same L, N, S, M, G, block table and device.
+ * h's centre must be at site 1 (as after sp_init_mps or a full sweep); at
+ * most 8 constraints.  sp_set_site on h invalidates the constraint
+ * environments until the next sp_add_orthogonality.  States with
+ * constraints cannot go through sp_sweep_batch. */
+int sp_add_orthogonality(sp_handle* h, sp_handle* lower);
+/* Remove every orthogonality constraint of h. */
+int sp_clear_orthogonality(sp_handle* h);
+/* out[j] = <lower_j|P|h> / (|lower_j| |h|) for the current site tensors
+ * (host, one double per constraint, in the order added), from the
+ * environments at the canonical centre.  Synchronises. */
+int sp_orthogonality_overlaps(sp_handle* h, double* out);
+
 /* Projected energy and norm at the canonical centre:
  * E = <x|H_eff x>/<x|N_eff x>, normP = <x|N_eff x> (the spin-S weight of
  * the underlying MPS when it is normalised).  Host scalars; synchronises. */

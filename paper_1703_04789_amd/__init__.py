@@ -29,7 +29,8 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_last_error", "sp_quadrature", "sp_exact_points", "sp_mpo_hubbard", "sp_mpo_s2",
            "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch", "sp_autotune",
            "sp_mpo_site_op", "sp_mpo_epq", "sp_mpo_spin_corr", "sp_expect",
-           "sp_mpo_abinitio", "sp_set_heff_plan", "sp_heff_plan"]
+           "sp_mpo_abinitio", "sp_set_heff_plan", "sp_heff_plan", "sp_add_orthogonality",
+           "sp_clear_orthogonality", "sp_orthogonality_overlaps"]
 
 
 class SpError(RuntimeError):
@@ -97,6 +98,9 @@ def lib():
         "sp_autotune": [vp, ctypes.c_int, ip, ip, dp],
         "sp_set_heff_plan": [vp, ctypes.c_int, ctypes.c_int, ip],
         "sp_heff_plan": [vp, ctypes.c_int, ip, ip],
+        "sp_add_orthogonality": [vp, vp],
+        "sp_clear_orthogonality": [vp],
+        "sp_orthogonality_overlaps": [vp, dp],
         "sp_mpo_site_op": [ctypes.c_int, ctypes.c_int, dp, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_epq": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_spin_corr": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
@@ -364,6 +368,22 @@ class SPMPS:
         us = np.zeros(self.L)
         _check(lib().sp_autotune(self._h, reps, _iptr(b), _iptr(r), _dptr(us)))
         return [(int(b[i]), int(r[i]), float(us[i])) for i in range(self.L)]
+
+    def add_orthogonality(self, lower):
+        """Keep this state orthogonal to ``lower`` (an SPMPS) in the projected
+        metric in later sweeps (excited states)."""
+        _check(lib().sp_add_orthogonality(self._h, lower._h))
+        self._n_cons = getattr(self, "_n_cons", 0) + 1
+
+    def clear_orthogonality(self):
+        _check(lib().sp_clear_orthogonality(self._h))
+        self._n_cons = 0
+
+    def orthogonality_overlaps(self):
+        """<lower_j|P|this> for every constraint, in the order added."""
+        out = np.zeros(max(1, getattr(self, "_n_cons", 0)))
+        _check(lib().sp_orthogonality_overlaps(self._h, _dptr(out)))
+        return out[: getattr(self, "_n_cons", 0)]
 
     def heff_plan(self, site):
         """(rows per task, LDS doubles) of the site's fused plan; (0, 0) when

@@ -272,8 +272,10 @@ struct TList {
     }
 };
 
-// buffer slots of a launch
-enum Buf { B_ENVL = 0, B_ENVR = 1, B_X = 2, B_T = 3, B_V = 4, B_Y = 5, B_NY = 6, B_OUT = 7 };
+// buffer slots of a launch; B_BRA is the site tensor on the bra side of the
+// plain-path environment updates (the same as B_X except for the mixed
+// environments of an orthogonality constraint)
+enum Buf { B_ENVL = 0, B_ENVR = 1, B_X = 2, B_T = 3, B_V = 4, B_Y = 5, B_NY = 6, B_OUT = 7, B_BRA = 8 };
 
 struct SitePlan {
     // coefficient table [G][nc]
@@ -368,9 +370,20 @@ struct sp_handle {
     double* pin_up = nullptr;  // pinned host staging (host -> device)
     double* pin_up_dev = nullptr;
     size_t pin_up_n = 0;
+    // orthogonality constraints (excited states): one identity-MPO handle per
+    // lower state whose environments are mixed (bra: this state, ket: the
+    // lower state), the orthonormalised constraint vectors of the current
+    // site (cld apart) and their projection partials
+    std::vector<std::unique_ptr<sp_handle>> cons;
+    DArr<double> conB, conPart;
+    long long cld = 0;
+    int con_active = 0;
+    double* con_pin = nullptr;  // mapped: norm partials read by the host
+    double* con_pin_dev = nullptr;
     ~sp_handle() {
         if (pin) (void)hipHostFree(pin);
         if (pin_up) (void)hipHostFree(pin_up);
+        if (con_pin) (void)hipHostFree(con_pin);
     }
 };
 
@@ -754,7 +767,7 @@ void build_plan(sp_handle* h, int k) {
                     auto it = Voff.find({q, OB.c, bl.sec[sa].nb});
                     if (it == Voff.end()) continue;
                     SP_REQUIRE((Vcols[{q, OB.c, bl.sec[sa].nb}] == OB.cols), "internal: V and L blocks disagree");
-                    P.envl_out.add_term(B_X, X.off, 1, X.cols, B_V,
+                    P.envl_out.add_term(B_BRA, X.off, 1, X.cols, B_V,
                                         g * P.Vsize + it->second + (long long)bl.sec[sa].ro * OB.cols, OB.cols, 1,
                                         X.rows, g * P.nc + P.c_one());
                 }
@@ -850,7 +863,7 @@ void build_plan(sp_handle* h, int k) {
                     auto it = Ztoff.find({q, OB.c, OB.j});
                     if (it == Ztoff.end()) continue;
                     const int nbcols = Ztcols[{q, OB.c, OB.j}];
-                    P.envr_out.add_term(B_X, X.off, X.cols, 1, B_V, g * P.Ztsize + it->second + SB.ro, 1, nbcols,
+                    P.envr_out.add_term(B_BRA, X.off, X.cols, 1, B_V, g * P.Ztsize + it->second + SB.ro, 1, nbcols,
                                         X.cols, g * P.nc + P.c_one());
                 }
             }
@@ -1582,6 +1595,7 @@ void validate_plans(sp_handle* h) {
         z[B_V] = Vb;
         z[B_Y] = xs;
         z[B_NY] = xs;
+        z[B_BRA] = xs;
         if (G * P.Tsize > Tb || G * P.Vsize > Vb || G * P.Zsize > Tb || G * P.Ztsize > Vb)
             throw SpError(SP_EINVAL, "internal: scratch too small");
         validate(P.p1, z, nco, "left product");
@@ -1677,6 +1691,7 @@ spk::BufSet bufset(sp_handle* h, int k, const double* x, double* y, double* ny, 
     b.p[B_Y] = y;
     b.p[B_NY] = ny;
     b.p[B_OUT] = out;
+    b.p[B_BRA] = const_cast<double*>(x);
     return b;
 }
 
@@ -1851,6 +1866,87 @@ void invalidate_for_site(sp_handle* h, int k) {
 // Pinned, mapped and coherent host memory: the Davidson kernels read the
 // subspace coefficients from it and write their per-chunk partial sums into
 // it directly, so an iteration needs no copy in either direction.
+// ---------------------------------------------------------------------------
+// Orthogonality constraints (Sec. 2.3, Eq. [orthoB]).  A constraint handle
+// holds a lower state Psi_0 with the identity MPO on the plain path; its
+// environments are rebuilt with this state on the bra side, so that its
+// N_eff applied to Psi_0's site tensor k gives B[k] = d<Psi|P|Psi_0>/dA[k]
+// in this state's packed layout.
+
+constexpr int kMaxConstraints = 8;
+
+void env_left_mixed(sp_handle* a, int k, const double* bra) {
+    SitePlan& P = a->plan[k - 1];
+    spk::BufSet b = bufset(a, k, site_ptr(a, k), nullptr, nullptr, a->envL[k].p);
+    b.p[B_BRA] = const_cast<double*>(bra);
+    P.p1.launch(a->stream, b, P.coef.p);
+    P.mixl.launch(a->stream, b, P.coef.p);
+    P.envl_out.launch(a->stream, b, P.coef.p);
+    a->Lvalid[k] = 1;
+}
+
+void env_right_mixed(sp_handle* a, int k, const double* bra) {
+    SitePlan& P = a->plan[k - 1];
+    spk::BufSet b = bufset(a, k, site_ptr(a, k), nullptr, nullptr, a->envR[k - 1].p);
+    b.p[B_BRA] = const_cast<double*>(bra);
+    P.p1r.launch(a->stream, b, P.coef.p);
+    P.mixr.launch(a->stream, b, P.coef.p);
+    P.envr_out.launch(a->stream, b, P.coef.p);
+    a->Rvalid[k - 1] = 1;
+}
+
+// B[k] of constraint handle a into out (ny: scratch of the site's size)
+void constraint_vector(sp_handle* a, int k, double* out, double* ny) {
+    SitePlan& P = a->plan[k - 1];
+    const spk::BufSet b = bufset(a, k, site_ptr(a, k), out, ny, nullptr);
+    P.p1.launch(a->stream, b, P.coef.p);
+    P.mixl.launch(a->stream, b, P.coef.p);
+    P.yout.launch(a->stream, b, P.coef.p);
+}
+
+// u -= C (C^T u) for the con_active orthonormal constraint vectors, twice
+// (classical Gram-Schmidt with one reorthogonalisation)
+void project_out(sp_handle* h, double* u, int n) {
+    const int m = h->con_active;
+    if (m == 0) return;
+    hipStream_t s = h->stream;
+    const int nch = spk::dav_chunks(n);
+    double* P1 = h->conPart.p;
+    double* P2 = P1 + (size_t)nch * m;
+    spk::dav_cgs(s, h->conB.p, h->cld, 0, m, P1, nch, u, n, P1, 0);  // dots only
+    spk::dav_cgs(s, h->conB.p, h->cld, m, m, P1, nch, u, n, P2, 0);  // subtract, dots again
+    spk::dav_cgs(s, h->conB.p, h->cld, m, 0, P2, nch, u, n, P1, 0);  // subtract
+}
+
+// the orthonormal constraint vectors at site k: B[k] of every constraint in
+// order, each orthogonalised against the ones kept before it and dropped
+// when its remainder is below 1e-10 of its own norm
+void prepare_constraints(sp_handle* h, int k) {
+    h->con_active = 0;
+    if (h->cons.empty()) return;
+    hipStream_t s = h->stream;
+    const int n = int(h->sites[k - 1].size);
+    const int nch = spk::dav_chunks(n);
+    double* p0 = h->con_pin_dev;  // raw norm partials
+    double* p1 = p0 + nch;        // norm partials after the projection
+    for (auto& a : h->cons) {
+        double* row = h->conB.p + (size_t)h->con_active * h->cld;
+        constraint_vector(a.get(), k, row, h->tmp_site.p);
+        spk::dav_cgs(s, h->conB.p, h->cld, 0, 0, p0, nch, row, n, p0, 1);  // |B|^2 partials
+        project_out(h, row, n);
+        spk::dav_cgs(s, h->conB.p, h->cld, 0, 0, p1, nch, row, n, p1, 1);
+        HIPCK(hipStreamSynchronize(s));
+        double n0 = 0.0, n1 = 0.0;
+        for (int q = 0; q < nch; ++q) {
+            n0 += h->con_pin[q];
+            n1 += h->con_pin[nch + q];
+        }
+        if (!(n0 > 0.0) || !(n1 > 1e-20 * n0)) continue;  // dependent on the kept vectors
+        spk::dav_normalize(s, p1, nch, row, row, n, p0 + 2 * nch);
+        h->con_active++;
+    }
+}
+
 void ensure_pinned(sp_handle* h, size_t n, size_t n_up) {
     const unsigned flags = hipHostMallocMapped | hipHostMallocCoherent;
     if (h->pin_n < n) {
@@ -1985,6 +2081,10 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
             spk::dav_gram(s, V, HV, NV, ld, mm, n, from_t ? h->dt.p : nullptr, sm + lay.pn, nch, tn, h->ypart.p,
                           h->nypart.p, n, h->G, dn_dev + (lay.pg - lay.out));
         }
+        // constrained pencil (Q H Q, Q N Q): the Gram rows above are the same
+        // for the projected products, since every V_j is orthogonal to C
+        project_out(h, HV + size_t(mm) * ld, n);
+        project_out(h, NV + size_t(mm) * ld, n);
     };
     // canonical orthogonalisation threshold: with FP32 products the null
     // space of the projected metric is only resolved to about 1e-7 of its
@@ -2000,6 +2100,10 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
 
     diag(h, k, h->ddh.p, h->ddn.p);
     spk::normalize(s, site_ptr(h, k), V, n, nullptr);
+    if (h->con_active) {  // start in the complement of the constraints
+        project_out(h, V, n);
+        spk::normalize(s, V, V, n, nullptr);
+    }
     extend(0, false);
     out.matvecs = 1;
     HIPCK(hipStreamSynchronize(s));
@@ -2050,6 +2154,9 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
         spk::dav_ritz(s, V, HV, NV, ld, m, h->pin_up_dev + lay.a, h->ddh.p, h->ddn.p, n, floor_, h->dx.p, h->dt.p,
                       dn_dev + (lay.px - lay.out), sm + lay.pc1);
         if (!last) {
+            // the correction stays in the complement of the constraints (its
+            // dots with V are unchanged, V being orthogonal to them)
+            project_out(h, h->dt.p, n);
             if (restart) {
                 for (double* B : {V, HV, NV}) {
                     spk::basis_rotate(s, B, ld, m, sm + lay.q, nk, h->dRot.p, n);
@@ -2781,15 +2888,18 @@ int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r) {
             if (L == 1) order.push_back({1, +1});
             for (auto [k, d] : order) {
                 const auto t0 = std::chrono::steady_clock::now();
+                prepare_constraints(h, k);
                 DavOut dv = davidson(h, k, *o);
                 if (L > 1) {
                     if (d > 0) {
                         move_right(h, k);
                         env_left(h, k);
+                        for (auto& a : h->cons) env_left_mixed(a.get(), k, site_ptr(h, k));
                         h->center = k + 1;
                     } else {
                         move_left(h, k);
                         env_right(h, k);
+                        for (auto& a : h->cons) env_right_mixed(a.get(), k, site_ptr(h, k));
                         h->center = k - 1;
                     }
                 }
@@ -2827,6 +2937,7 @@ int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_repor
             sp_handle* h = hs[i];
             SP_REQUIRE(h, "null handle");
             SP_REQUIRE(h->path == SP_PATH_TILED, "batched sweeps need the tiled path");
+            SP_REQUIRE(h->cons.empty(), "states with orthogonality constraints sweep with sp_sweep");
             SP_REQUIRE(h->stream == hs[0]->stream && h->device == hs[0]->device,
                        "batched handles must share one device and one stream");
             SP_REQUIRE(h->precision == hs[0]->precision, "batched handles must share the precision");
@@ -2966,6 +3077,100 @@ int sp_expect(sp_handle* h, const sp_mpo* O, double* value, double* normP) {
         const int rc2 = sp_energy(t, value, &np);
         if (rc2 < 0) throw SpError(rc2, g_last_error);
         if (normP) *normP = np;
+        return SP_OK;
+    });
+}
+
+int sp_add_orthogonality(sp_handle* h, sp_handle* lower) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && lower && h != lower, "bad arguments");
+        SP_REQUIRE(int(h->cons.size()) < kMaxConstraints, "at most 8 orthogonality constraints");
+        SP_REQUIRE(h->center == 1, "constraints are added with the canonical centre at site 1");
+        SP_REQUIRE(lower->L == h->L && lower->N == h->N && lower->twoS == h->twoS && lower->twoM == h->twoM &&
+                       lower->G == h->G,
+                   "the lower state must have the same L, N, S, M and quadrature");
+        SP_REQUIRE(lower->tab_nsec == h->tab_nsec && lower->tab_n == h->tab_n && lower->tab_2m == h->tab_2m &&
+                       lower->tab_dim == h->tab_dim,
+                   "the lower state must have the same block table");
+        SP_REQUIRE(lower->device == h->device, "the lower state must live on the same device");
+        const int L = h->L;
+        // the lower state's tensors as they are now
+        std::vector<double> blocks(lower->mps_size);
+        HIPCK(hipStreamSynchronize(h->stream));
+        HIPCK(hipMemcpyAsync(blocks.data(), lower->mps.p, lower->mps_size * sizeof(double), hipMemcpyDeviceToHost,
+                             lower->stream));
+        HIPCK(hipStreamSynchronize(lower->stream));
+        std::vector<int> w(L + 1);
+        long long nw = 0;
+        sph::mpo_identity(L, w.data(), nullptr, &nw);
+        std::vector<double> wd(nw);
+        sph::mpo_identity(L, w.data(), wd.data(), &nw);
+        sp_problem p{L, 4, h->N, h->twoS, h->twoM, h->G, SP_FP64, SP_PATH_PLAIN};
+        sp_mpo W{w.data(), wd.data()};
+        sp_block_table bt{h->tab_nsec.data(), h->tab_n.data(), h->tab_2m.data(), h->tab_dim.data()};
+        sp_handle* a = nullptr;
+        const int rc = sp_init_mps(&p, &W, &bt, blocks.data(), h->stream, &a);
+        if (rc < 0) throw SpError(rc, std::string("constraint state: ") + g_last_error);
+        std::unique_ptr<sp_handle> ap(a);
+        // mixed right environments against this state's right-canonical sites
+        for (int k = L; k >= 2; --k) env_right_mixed(a, k, site_ptr(h, k));
+        if (h->conB.n == 0) {
+            h->cld = (h->max_site + 63) / 64 * 64;
+            h->conB.alloc(size_t(kMaxConstraints) * h->cld);
+            const int nch = spk::dav_chunks(int(h->max_site));
+            h->conPart.alloc(size_t(2) * nch * kMaxConstraints);
+            void* hp = nullptr;
+            HIPCK(hipHostMalloc(&hp, (size_t(2) * nch + 8) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+            h->con_pin = static_cast<double*>(hp);
+            void* dp = nullptr;
+            HIPCK(hipHostGetDevicePointer(&dp, hp, 0));
+            h->con_pin_dev = static_cast<double*>(dp);
+        }
+        HIPCK(hipStreamSynchronize(h->stream));
+        HIPCK(hipGetLastError());
+        h->cons.push_back(std::move(ap));
+        return SP_OK;
+    });
+}
+
+int sp_clear_orthogonality(sp_handle* h) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h, "null argument");
+        HIPCK(hipStreamSynchronize(h->stream));
+        h->cons.clear();
+        h->con_active = 0;
+        return SP_OK;
+    });
+}
+
+int sp_orthogonality_overlaps(sp_handle* h, double* out) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && (out || h->cons.empty()), "null argument");
+        const int c = h->center;
+        const int n = int(h->sites[c - 1].size);
+        const size_t nc = h->cons.size();
+        if (nc == 0) return SP_OK;
+        // per constraint: B.x, then |lower| (its site 1 carries the norm: the
+        // constraint state stays right-canonical) and |x| (x = the centre)
+        DArr<double> d;
+        d.alloc(2 * h->max_site + 2 * nc + 1);
+        double* res = d.p + 2 * h->max_site;
+        for (size_t j = 0; j < nc; ++j) {
+            sp_handle* a = h->cons[j].get();
+            SP_REQUIRE(a->Lvalid[c - 1] && a->Rvalid[c], "constraint environments do not reach the centre");
+            constraint_vector(a, c, d.p, d.p + h->max_site);
+            spk::multidot(h->stream, d.p, 0, 1, site_ptr(h, c), n, res + j);
+            spk::normalize(h->stream, site_ptr(a, 1), d.p, int(a->sites[0].size), res + nc + j);
+        }
+        spk::normalize(h->stream, site_ptr(h, c), d.p, n, res + 2 * nc);
+        std::vector<double> hres(2 * nc + 1);
+        HIPCK(hipMemcpyAsync(hres.data(), res, hres.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCK(hipStreamSynchronize(h->stream));
+        HIPCK(hipGetLastError());
+        for (size_t j = 0; j < nc; ++j) {
+            const double den = hres[nc + j] * hres[2 * nc];
+            out[j] = den > 0.0 ? hres[j] / den : 0.0;
+        }
         return SP_OK;
     });
 }
