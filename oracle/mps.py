@@ -320,7 +320,7 @@ class DavidsonResult:
 
 
 def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
-             drop=1e-10, floor=1e-8, C=None):
+             drop=1e-10, floor=1e-8, C=None, precond=None, record=None):
     """Lowest theta of H x = theta N x within range(N).
 
     matvec(v) -> (H v, N v) on flat vectors.  Returns a DavidsonResult with
@@ -331,6 +331,12 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
     pencil becomes (Q H Q, Q N Q), i.e. the start vector, every H v, N v and
     every correction are multiplied by Q (twice, for rounding), so the
     residual is the projected one.
+
+    precond(r, theta) -> t replaces the diagonal correction (a learned
+    preconditioner); it is abandoned for the rest of the solve once the
+    residual norm has failed three times in a row to reach a new minimum.
+    record (a list) receives, after a converged solve, one (r_j, theta_j,
+    x_j, x*, dH, dN) tuple per iteration but the last (training pairs).
     """
     if C is not None and C.shape[1] > 0:
         def proj(u):
@@ -352,6 +358,8 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
     x = v
     rn = np.inf
     it = 0
+    use_model, best, stall = precond is not None, np.inf, 0
+    trail = []
     for it in range(1, max_iter + 1):
         Vm = np.array(V).T
         Hm = np.array(HV).T
@@ -378,9 +386,20 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
         rn = float(np.linalg.norm(r))
         if rn <= tol or it == max_iter:
             break
-        den = dH - theta * dN
-        den = np.where(np.abs(den) < floor, np.where(den < 0, -floor, floor), den)
-        t = proj(-r / den)
+        if record is not None:
+            trail.append((r.copy(), theta, x.copy()))
+        if use_model:
+            if rn < best:
+                best, stall = rn, 0
+            else:
+                stall += 1
+                use_model = stall < 3
+        if use_model:
+            t = proj(np.asarray(precond(r, theta), dtype=float))
+        else:
+            den = dH - theta * dN
+            den = np.where(np.abs(den) < floor, np.where(den < 0, -floor, floor), den)
+            t = proj(-r / den)
         if len(V) >= max_sub:
             nk = min(keep, Cm.shape[1])
             Ak = X @ Cm[:, :nk]
@@ -401,6 +420,8 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
         HV.append(hv)
         NV.append(nv)
     pn = float(x @ nx)
+    if record is not None and rn <= tol:
+        record.extend((r_, th_, x_, x.copy(), dH, dN) for (r_, th_, x_) in trail)
     return DavidsonResult(theta, x, rn, it, rn <= tol, pn)
 
 
@@ -471,14 +492,16 @@ class OrthogonalityConstraint:
 
 
 def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
-          keep=8, record=None, constraints=()):
+          keep=8, record=None, constraints=(), model=None, pairs=None):
     """One-site sweeps (Sec. 2.3): right-moving k = 1..L-1 then left-moving
     k = L..2.  Each step solves the local problem, restores the canonical
     form with a positive-diagonal QR (right-moving) or LQ (left-moving) and
     updates the environments of the bond it leaves behind.  With
     ``constraints`` (OrthogonalityConstraint objects built on this state)
     every local solve is restricted to the complement of the B[k] vectors
-    of Eq. [orthoB] (excited states).
+    of Eq. [orthoB] (excited states).  ``model`` (weights of the learned
+    preconditioner, see oracle.precond) replaces the diagonal correction;
+    ``pairs`` (a list) collects the solver's training pairs.
 
     Returns a list of per-step dicts (sweep, site, dir, theta, pnorm, rnorm,
     iters)."""
@@ -500,8 +523,15 @@ def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
             dh, dn = state.heff_diag(k)
             x0 = mps.A[k - 1].ravel()[idx]
             C = orthonormal_constraints([c.vector(k).ravel()[idx] for c in constraints]) if constraints else None
-            res = davidson(mv, dh.ravel()[idx], dn.ravel()[idx], x0, tol=tol,
-                           max_iter=max_iter, max_sub=max_sub, keep=keep, C=C)
+            dhv, dnv = dh.ravel()[idx], dn.ravel()[idx]
+            pc = None
+            if model is not None:
+                from . import precond as pre
+
+                def pc(r, th, dhv=dhv, dnv=dnv):
+                    return pre.forward(model, pre.features(r, dhv, dnv, th))
+            res = davidson(mv, dhv, dnv, x0, tol=tol, max_iter=max_iter, max_sub=max_sub, keep=keep, C=C,
+                           precond=pc, record=pairs)
             xd = np.zeros(int(np.prod(shape)))
             xd[idx] = res.x
             mps.A[k - 1] = xd.reshape(shape)

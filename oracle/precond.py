@@ -1,0 +1,94 @@
+"""Learned Davidson preconditioner: plain reference of what the library's
+kernels compute.  Test infrastructure only.
+
+The paper leaves the local solver open (Sec. 2.3); the method's solver here
+is a Davidson iteration whose correction step is normally the diagonal
+preconditioner t = -r / (diag H_eff - theta diag N_eff).  The learned
+variant replaces it by a two-layer perceptron applied to every element of
+the site tensor separately:
+
+  features  f0 = r_i / rms(r)
+            f1 = asinh(d_i),            d_i = dh_i - theta dn_i
+            f2 = asinh(dn_i)
+            f3 = asinh(-f0 / d_i'),     d_i' = d_i floored to |d_i| >= floor
+  model     t_i = w2 . relu(W1 f + b1) + b2
+
+(the Davidson step normalises t, so only its direction matters).  Training
+pairs come from the solver itself: at iteration j of a converged local
+solve with Ritz vector x_j (unit norm) and final vector x*, the exact
+correction is e_j = x*/(x_j . x*) - x_j, the step after which the search
+space holds x*; its elements, divided by rms(e_j), are the targets of
+f(r_j).  Loss: mean squared error; optimiser: Adam (Kingma and Ba, 2015).
+Everything here is FP64 and element-by-element plain numpy.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def features(r, dh, dn, theta, floor=1e-8):
+    """Four features per element (n x 4)."""
+    r = np.asarray(r, dtype=float)
+    n = r.size
+    rms = np.sqrt(np.sum(r * r) / n)
+    f0 = r / rms if rms > 0 else np.zeros(n)
+    d = dh - theta * dn
+    dfl = np.where(np.abs(d) < floor, np.where(d < 0, -floor, floor), d)
+    return np.stack([f0, np.arcsinh(d), np.arcsinh(dn), np.arcsinh(-f0 / dfl)], axis=1)
+
+
+def forward(p, F):
+    """Model output for feature rows F (n x 4)."""
+    z = F @ np.asarray(p["W1"], float).T + np.asarray(p["b1"], float)[None, :]
+    h = np.maximum(z, 0.0)
+    return h @ np.asarray(p["w2"], float) + float(p["b2"])
+
+
+def loss_and_grads(p, F, Y):
+    """Mean squared error 0.5 * mean((y - Y)^2) and its gradients with
+    respect to W1, b1, w2, b2 by the chain rule."""
+    W1 = np.asarray(p["W1"], float)
+    b1 = np.asarray(p["b1"], float)
+    w2 = np.asarray(p["w2"], float)
+    n = F.shape[0]
+    z = F @ W1.T + b1[None, :]
+    h = np.maximum(z, 0.0)
+    y = h @ w2 + float(p["b2"])
+    dy = (y - Y) / n
+    loss = 0.5 * float(np.mean((y - Y) ** 2))
+    g_w2 = h.T @ dy
+    g_b2 = float(np.sum(dy))
+    dz = np.outer(dy, w2) * (z > 0.0)
+    g_W1 = dz.T @ F
+    g_b1 = dz.sum(axis=0)
+    return loss, {"W1": g_W1, "b1": g_b1, "w2": g_w2, "b2": g_b2}
+
+
+def adam_step(p, g, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update with bias correction; ``state`` holds m, v per
+    parameter and the step count t (created on the first call)."""
+    if not state:
+        state.update({k: (np.zeros_like(np.asarray(v, float)), np.zeros_like(np.asarray(v, float)))
+                      for k, v in p.items()})
+        state["t"] = 0
+    state["t"] += 1
+    t = state["t"]
+    out = {}
+    for k in ("W1", "b1", "w2", "b2"):
+        m, v = state[k]
+        gk = np.asarray(g[k], float)
+        m = beta1 * m + (1 - beta1) * gk
+        v = beta2 * v + (1 - beta2) * gk * gk
+        state[k] = (m, v)
+        mh = m / (1 - beta1 ** t)
+        vh = v / (1 - beta2 ** t)
+        out[k] = np.asarray(p[k], float) - lr * mh / (np.sqrt(vh) + eps)
+    out["b2"] = float(out["b2"])
+    return out
+
+
+def exact_correction(x, xstar):
+    """e = x*/(x . x*) - x for unit x, divided by its rms (zero if e = 0)."""
+    e = xstar / float(x @ xstar) - x
+    rms = np.sqrt(np.sum(e * e) / e.size)
+    return e / rms if rms > 0 else e

@@ -1,0 +1,127 @@
+"""Pins of the learned-preconditioner reference (oracle.precond): the
+back-propagated gradients against finite differences, closed forms of the
+model, of Adam's first step and of the exact correction, and the solver hook
+(the diagonal rule given as a preconditioner reproduces the default run)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mpo, mps, precond as pre, quadrature as q
+
+
+def _params(hidden=16, seed=0):
+    p = W.mlp_init(hidden, seed)
+    rng = np.random.default_rng(seed + 1)
+    p = {k: np.asarray(v, float) for k, v in p.items()}
+    p["b1"] = rng.standard_normal(hidden) * 0.1
+    p["b2"] = 0.3
+    return p
+
+
+def test_gradients_match_finite_differences():
+    rng = np.random.default_rng(4)
+    p = _params()
+    F = rng.standard_normal((50, 4))
+    Y = rng.standard_normal(50)
+    loss, g = pre.loss_and_grads(p, F, Y)
+    assert abs(loss - 0.5 * np.mean((pre.forward(p, F) - Y) ** 2)) < 1e-14
+    h = 1e-6
+    for k in ("W1", "b1", "w2", "b2"):
+        base = np.asarray(p[k], float)
+        flat = base.ravel()
+        for i in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            pp = dict(p)
+            pm = dict(p)
+            a = flat.copy()
+            a[i] += h
+            b_ = flat.copy()
+            b_[i] -= h
+            pp[k] = a.reshape(base.shape) if base.shape else float(a[0])
+            pm[k] = b_.reshape(base.shape) if base.shape else float(b_[0])
+            fd = (pre.loss_and_grads(pp, F, Y)[0] - pre.loss_and_grads(pm, F, Y)[0]) / (2 * h)
+            an = np.asarray(g[k], float).ravel()[i]
+            assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (k, i, fd, an)
+
+
+def test_forward_closed_form():
+    p = _params()
+    p["W1"] = np.zeros_like(p["W1"])
+    F = np.random.default_rng(0).standard_normal((7, 4))
+    y = pre.forward(p, F)
+    assert np.allclose(y, p["b2"] + np.maximum(p["b1"], 0) @ p["w2"], atol=1e-15)
+
+
+def test_adam_first_step_is_a_signed_step():
+    p = _params()
+    F = np.random.default_rng(1).standard_normal((30, 4))
+    Y = np.ones(30)
+    _, g = pre.loss_and_grads(p, F, Y)
+    st = {}
+    out = pre.adam_step(p, g, st, lr=1e-3)
+    for k in ("W1", "b1", "w2"):
+        gk = np.asarray(g[k], float)
+        exp = np.asarray(p[k], float) - 1e-3 * gk / (np.abs(gk) + 1e-8)
+        assert np.allclose(out[k], exp, atol=1e-15)
+    assert st["t"] == 1
+
+
+def test_exact_correction_reaches_the_target():
+    rng = np.random.default_rng(2)
+    xs = rng.standard_normal(40)
+    xs /= np.linalg.norm(xs)
+    x = xs + 0.1 * rng.standard_normal(40)
+    x /= np.linalg.norm(x)
+    e = pre.exact_correction(x, xs)
+    assert abs(x @ e) < 1e-12
+    assert abs(np.sqrt(np.mean(e * e)) - 1.0) < 1e-12
+    # x + c e is parallel to x* for the right c
+    e_raw = xs / (x @ xs) - x
+    y = x + e_raw
+    assert np.linalg.norm(y / np.linalg.norm(y) - xs) < 1e-12
+
+
+def test_features_definition():
+    r = np.array([1.0, -2.0, 0.0, 3.0])
+    dh = np.array([2.0, 1.0, 0.5, 1e-12])
+    dn = np.array([1.0, 0.5, 0.0, 0.0])
+    F = pre.features(r, dh, dn, theta=1.0)
+    rms = np.sqrt(np.mean(r * r))
+    assert np.allclose(F[:, 0], r / rms)
+    assert np.allclose(F[:, 1], np.arcsinh(dh - dn))
+    assert np.allclose(F[:, 2], np.arcsinh(dn))
+    d = dh - dn
+    d[3] = 1e-8  # floored
+    assert np.allclose(F[:, 3], np.arcsinh(-(r / rms) / d))
+
+
+def test_solver_hook_with_the_diagonal_rule_reproduces_the_default():
+    L = 6
+    tab = W.make_block_table(L, L, 0, 16)
+    G = q.exact_point_count(L, L, 0)
+    runs = []
+    for use_hook in (False, True):
+        o = mps.SPMPSOracle(tab, W.random_blocks(tab, 3), mpo.hubbard_mpo(L, 1.0, 4.0), 0, G)
+        k = 1
+        m = o.mps.mask[k - 1]
+        idx = np.flatnonzero(m.ravel())
+
+        def mv(v):
+            xd = np.zeros(m.size)
+            xd[idx] = v
+            y, ny = o.heff(k, xd.reshape(m.shape))
+            return y.ravel()[idx], ny.ravel()[idx]
+        dh, dn = (a.ravel()[idx] for a in o.heff_diag(k))
+
+        def diag_rule(r, th):
+            den = dh - th * dn
+            den = np.where(np.abs(den) < 1e-8, np.where(den < 0, -1e-8, 1e-8), den)
+            return -r / den
+        rec = []
+        res = mps.davidson(mv, dh, dn, o.mps.A[0].ravel()[idx], precond=diag_rule if use_hook else None,
+                           record=rec)
+        runs.append((res, rec))
+    (a, ra), (b, rb) = runs
+    assert a.iters == b.iters and abs(a.theta - b.theta) < 1e-14
+    assert len(ra) == len(rb) == a.iters - 1
+    r0, th0, x0, xs, _, _ = ra[0]
+    assert abs(np.linalg.norm(x0) - 1) < 1e-12 and abs(np.linalg.norm(xs) - 1) < 1e-12

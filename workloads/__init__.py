@@ -347,3 +347,19 @@ def abinitio_reduced(K: int = 12, D: int = 128, G: int = 11) -> AbInitioWorkload
     """The same integral recipe at fewer orbitals and a smaller bond
     dimension: half filling, M=0, S=0, seed 4."""
     return AbInitioWorkload(f"abinitio_K{K}_D{D}_G{G}", K=K, N=K, twoS=0, twoM=0, D=D, G=G, sweeps=4, seed=4)
+
+
+# ---------------------------------------------------------------------------
+# Initial weights of the learned Davidson preconditioner (a two-layer MLP on
+# four features per site-tensor element).
+
+
+def mlp_init(hidden: int = 256, seed: int = 0, n_in: int = 4):
+    """Seeded initial weights (FP32): W1 (hidden x n_in) and w2 (hidden)
+    uniform in +-sqrt(6/fan_in) (He initialisation for the ReLU layer,
+    +-sqrt(3/hidden) for the output), biases zero."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.uniform(-1.0, 1.0, (hidden, n_in)) * math.sqrt(6.0 / n_in)
+    w2 = rng.uniform(-1.0, 1.0, hidden) * math.sqrt(3.0 / hidden)
+    return {"W1": W1.astype(np.float32), "b1": np.zeros(hidden, np.float32),
+            "w2": w2.astype(np.float32), "b2": np.float32(0.0)}
