@@ -68,6 +68,7 @@ extern "C" {
                              plain FP64 reference path                      */
 
 typedef struct sp_handle sp_handle;
+typedef struct sp_mlp sp_mlp;
 
 /* Problem: L sites, d must be 4, N electrons, spin S = twoS/2 with projection
  * M = twoM/2, G quadrature points.  Requires N + twoS even, N + twoM even,
@@ -226,6 +227,53 @@ int sp_clear_orthogonality(sp_handle* h);
  * (host, one double per constraint, in the order added), from the
  * environments at the canonical centre.  Synchronises. */
 int sp_orthogonality_overlaps(sp_handle* h, double* out);
+
+/* Learned Davidson preconditioner.  The paper leaves the local solver of
+ * Sec. 2.3 open; the library's Davidson corrects with the diagonal rule
+ * t = -r / (diag H_eff - theta diag N_eff) (floored at 1e-8).  A model
+ * replaces it by a two-layer perceptron (hidden width H <= 256, ReLU)
+ * applied to each element of the site tensor separately, on the features
+ * f0 = |r_i| / rms(r), f1 = asinh(d_i), f2 = asinh(dN_i),
+ * f3 = asinh(-f0/d_i') (d = dH - theta dN, d' = d floored), with
+ * t_i = sign(r_i) g(f) (odd in r; Davidson normalises t).  While a model
+ * is in use, a local solve falls back to the diagonal rule for good once
+ * its residual norm has missed a new minimum three iterations in a row or
+ * has fallen by less than a factor of two over the last four iterations.
+ * Training pairs come from the solver: for iteration
+ * j of a converged solve with Ritz vector x_j and final vector x_f, the
+ * target of g at element i is sign(r_i) e_i / rms(e),
+ * e = x_f / (xh_j . x_f) - xh_j (xh_j =
+ * x_j / |x_j|): the step that puts x_f in the search space.  Weights and
+ * pairs are FP32 in device memory, arithmetic FP64; Adam (beta 0.9, 0.999,
+ * eps 1e-8) on the mean squared error.  A model belongs to the device that
+ * was current at sp_mlp_create; it must outlive every state that uses it. */
+
+/* w_init: mlp_size(H) = 6H + 1 floats, packed W1 (H x 4 row-major) | b1 (H)
+ * | w2 (H) | b2 (host, copied); capacity: rows (elements) of training
+ * pairs the model can record (0: none). */
+int sp_mlp_create(int hidden, const float* w_init, long long capacity, sp_mlp** out);
+int sp_mlp_destroy(sp_mlp* m);
+/* Current weights (host, 6H + 1 floats; may be NULL) and recorded rows. */
+int sp_mlp_get(sp_mlp* m, float* w_out, long long* rows);
+/* Recorded pairs [first, first + count): features (count x 4) and targets
+ * (host). */
+int sp_mlp_dataset(sp_mlp* m, long long first, long long count, float* F_out, float* Y_out);
+/* y = model(F) for n feature rows (device pointers, FP32) on `stream`
+ * (a hipStream_t, NULL = default). */
+int sp_mlp_forward(sp_mlp* m, const float* F, long long n, float* y, void* stream);
+/* One Adam step on the n pairs (F, Y) (device pointers); *loss (optional)
+ * = 0.5 mean (y - Y)^2 before the step.  Synchronises. */
+int sp_mlp_train_step(sp_mlp* m, const float* F, const float* Y, long long n, double lr, double* loss, void* stream);
+/* `epochs` passes over the recorded pairs in ceil(rows / batch) batches
+ * (at most 4096; batch b holds rows b, b + nb, b + 2 nb, ...), one Adam
+ * step per batch; loss_out[e] (optional) = the mean batch loss of epoch e.
+ * Synchronises. */
+int sp_mlp_train(sp_mlp* m, int epochs, long long batch, double lr, double* loss_out, void* stream);
+/* Local solves of later sp_sweep calls on h correct with `use` (NULL: the
+ * diagonal rule) and record their training pairs into `record` (NULL:
+ * none) until its capacity is reached.  States with a model cannot go
+ * through sp_sweep_batch. */
+int sp_set_precond(sp_handle* h, sp_mlp* use, sp_mlp* record);
 
 /* Projected energy and norm at the canonical centre:
  * E = <x|H_eff x>/<x|N_eff x>, normP = <x|N_eff x> (the spin-S weight of

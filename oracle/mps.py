@@ -334,7 +334,8 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
 
     precond(r, theta) -> t replaces the diagonal correction (a learned
     preconditioner); it is abandoned for the rest of the solve once the
-    residual norm has failed three times in a row to reach a new minimum.
+    residual norm has failed three times in a row to reach a new minimum, or
+    has fallen by less than a factor of two over the last four iterations.
     record (a list) receives, after a converged solve, one (r_j, theta_j,
     x_j, x*, dH, dN) tuple per iteration but the last (training pairs).
     """
@@ -358,7 +359,7 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
     x = v
     rn = np.inf
     it = 0
-    use_model, best, stall = precond is not None, np.inf, 0
+    use_model, best, stall, hist = precond is not None, np.inf, 0, []
     trail = []
     for it in range(1, max_iter + 1):
         Vm = np.array(V).T
@@ -389,13 +390,15 @@ def davidson(matvec, dH, dN, x0, tol=1e-9, max_iter=64, max_sub=32, keep=8,
         if record is not None:
             trail.append((r.copy(), theta, x.copy()))
         if use_model:
+            t = proj(np.asarray(precond(r, theta), dtype=float))
+            # the residual norms seen so far decide the next iterations
             if rn < best:
                 best, stall = rn, 0
             else:
                 stall += 1
-                use_model = stall < 3
-        if use_model:
-            t = proj(np.asarray(precond(r, theta), dtype=float))
+            hist.append(rn)
+            slow = len(hist) >= 5 and rn > 0.5 * hist[-5]
+            use_model = stall < 3 and not slow
         else:
             den = dH - theta * dN
             den = np.where(np.abs(den) < floor, np.where(den < 0, -floor, floor), den)
@@ -501,7 +504,9 @@ def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
     every local solve is restricted to the complement of the B[k] vectors
     of Eq. [orthoB] (excited states).  ``model`` (weights of the learned
     preconditioner, see oracle.precond) replaces the diagonal correction;
-    ``pairs`` (a list) collects the solver's training pairs.
+    ``pairs`` (a list) collects the solver's training pairs as (site,) +
+    the tuples of :func:`davidson` (vectors in the order of the site's
+    non-zero dense entries).
 
     Returns a list of per-step dicts (sweep, site, dir, theta, pnorm, rnorm,
     iters)."""
@@ -529,9 +534,12 @@ def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
                 from . import precond as pre
 
                 def pc(r, th, dhv=dhv, dnv=dnv):
-                    return pre.forward(model, pre.features(r, dhv, dnv, th))
+                    return pre.correction(model, r, dhv, dnv, th)
+            rec_k = [] if pairs is not None else None
             res = davidson(mv, dhv, dnv, x0, tol=tol, max_iter=max_iter, max_sub=max_sub, keep=keep, C=C,
-                           precond=pc, record=pairs)
+                           precond=pc, record=rec_k)
+            if pairs is not None:
+                pairs.extend((k,) + e for e in rec_k)
             xd = np.zeros(int(np.prod(shape)))
             xd[idx] = res.x
             mps.A[k - 1] = xd.reshape(shape)

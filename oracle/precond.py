@@ -7,18 +7,22 @@ preconditioner t = -r / (diag H_eff - theta diag N_eff).  The learned
 variant replaces it by a two-layer perceptron applied to every element of
 the site tensor separately:
 
-  features  f0 = r_i / rms(r)
+  features  f0 = |r_i| / rms(r)
             f1 = asinh(d_i),            d_i = dh_i - theta dn_i
             f2 = asinh(dn_i)
             f3 = asinh(-f0 / d_i'),     d_i' = d_i floored to |d_i| >= floor
-  model     t_i = w2 . relu(W1 f + b1) + b2
+  model     g(f) = w2 . relu(W1 f + b1) + b2
+  correction t_i = sign(r_i) g(f)
 
-(the Davidson step normalises t, so only its direction matters).  Training
-pairs come from the solver itself: at iteration j of a converged local
-solve with Ritz vector x_j (unit norm) and final vector x*, the exact
-correction is e_j = x*/(x_j . x*) - x_j, the step after which the search
-space holds x*; its elements, divided by rms(e_j), are the targets of
-f(r_j).  Loss: mean squared error; optimiser: Adam (Kingma and Ba, 2015).
+The correction is odd in r, as a linear preconditioner is, so the sign of
+the Ritz vector (free in an eigensolver) does not matter; the diagonal rule
+is the special case g = -f0 rms(r) / d_i'.  The Davidson step normalises t,
+so only its direction matters.  Training pairs come from the solver itself:
+at iteration j of a converged local solve with Ritz vector x_j (unit norm)
+and final vector x*, the exact correction is e_j = x*/(x_j . x*) - x_j, the
+step after which the search space holds x*; sign(r_i) e_ij / rms(e_j) is
+the target of g at element i.  Loss: mean squared error; optimiser: Adam
+(Kingma and Ba, 2015).
 Everything here is FP64 and element-by-element plain numpy.
 """
 from __future__ import annotations
@@ -31,10 +35,20 @@ def features(r, dh, dn, theta, floor=1e-8):
     r = np.asarray(r, dtype=float)
     n = r.size
     rms = np.sqrt(np.sum(r * r) / n)
-    f0 = r / rms if rms > 0 else np.zeros(n)
+    f0 = np.abs(r) / rms if rms > 0 else np.zeros(n)
     d = dh - theta * dn
     dfl = np.where(np.abs(d) < floor, np.where(d < 0, -floor, floor), d)
     return np.stack([f0, np.arcsinh(d), np.arcsinh(dn), np.arcsinh(-f0 / dfl)], axis=1)
+
+
+def correction(p, r, dh, dn, theta, floor=1e-8):
+    """The learned correction t = sign(r) g(f(r))."""
+    return np.sign(r) * forward(p, features(r, dh, dn, theta, floor))
+
+
+def target(r, x, xstar):
+    """Training target of g at every element: sign(r_i) e_i / rms(e)."""
+    return np.sign(r) * exact_correction(x, xstar)
 
 
 def forward(p, F):

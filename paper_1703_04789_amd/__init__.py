@@ -30,7 +30,9 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch", "sp_autotune",
            "sp_mpo_site_op", "sp_mpo_epq", "sp_mpo_spin_corr", "sp_expect",
            "sp_mpo_abinitio", "sp_set_heff_plan", "sp_heff_plan", "sp_add_orthogonality",
-           "sp_clear_orthogonality", "sp_orthogonality_overlaps"]
+           "sp_clear_orthogonality", "sp_orthogonality_overlaps", "sp_mlp_create", "sp_mlp_destroy",
+           "sp_mlp_get", "sp_mlp_dataset", "sp_mlp_forward", "sp_mlp_train_step", "sp_mlp_train",
+           "sp_set_precond"]
 
 
 class SpError(RuntimeError):
@@ -88,6 +90,7 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp, ip, dp = ctypes.c_void_p, P(ctypes.c_int), P(ctypes.c_double)
+    fp = P(ctypes.c_float)
     sig = {
         "sp_init_mps": [P(_Problem), P(_Mpo), P(_BlockTable), dp, vp, P(vp)],
         "sp_env_update": [vp, ctypes.c_int, ctypes.c_int],
@@ -101,6 +104,14 @@ def lib():
         "sp_add_orthogonality": [vp, vp],
         "sp_clear_orthogonality": [vp],
         "sp_orthogonality_overlaps": [vp, dp],
+        "sp_mlp_create": [ctypes.c_int, fp, ctypes.c_longlong, P(vp)],
+        "sp_mlp_destroy": [vp],
+        "sp_mlp_get": [vp, fp, P(ctypes.c_longlong)],
+        "sp_mlp_dataset": [vp, ctypes.c_longlong, ctypes.c_longlong, fp, fp],
+        "sp_mlp_forward": [vp, vp, ctypes.c_longlong, vp, vp],
+        "sp_mlp_train_step": [vp, vp, vp, ctypes.c_longlong, ctypes.c_double, dp, vp],
+        "sp_mlp_train": [vp, ctypes.c_int, ctypes.c_longlong, ctypes.c_double, dp, vp],
+        "sp_set_precond": [vp, vp, vp],
         "sp_mpo_site_op": [ctypes.c_int, ctypes.c_int, dp, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_epq": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_spin_corr": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
@@ -140,6 +151,17 @@ def _check(rc):
 
 def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _dev32(t):
+    """Device pointer of a contiguous float32 torch tensor."""
+    if t.dtype.__str__() != "torch.float32" or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("model buffers must be contiguous float32 tensors on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _iptr(a):
@@ -234,6 +256,77 @@ def small_gen_lowest(H, N, drop=1e-10):
 
 
 # ---- the SP-MPS state ------------------------------------------------------
+
+def pack_mlp(p):
+    """Packed FP32 weights W1 (H x 4) | b1 | w2 | b2 from a dict."""
+    return np.concatenate([np.asarray(p["W1"], np.float32).ravel(), np.asarray(p["b1"], np.float32),
+                           np.asarray(p["w2"], np.float32), np.asarray([p["b2"]], np.float32)])
+
+
+def unpack_mlp(w, H):
+    w = np.asarray(w, np.float32)
+    return {"W1": w[: 4 * H].reshape(H, 4), "b1": w[4 * H: 5 * H], "w2": w[5 * H: 6 * H], "b2": float(w[6 * H])}
+
+
+class MLP:
+    """A learned Davidson preconditioner (sp_mlp) on the current device."""
+
+    def __init__(self, params, capacity=0):
+        import torch
+        self._torch = torch
+        self.hidden = int(np.asarray(params["W1"]).shape[0])
+        w = pack_mlp(params)
+        h = ctypes.c_void_p()
+        _check(lib().sp_mlp_create(self.hidden, _fptr(w), int(capacity), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().sp_mlp_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        w = np.zeros(6 * self.hidden + 1, np.float32)
+        _check(lib().sp_mlp_get(self._h, _fptr(w), None))
+        return unpack_mlp(w, self.hidden)
+
+    def rows(self):
+        n = ctypes.c_longlong(0)
+        _check(lib().sp_mlp_get(self._h, None, ctypes.byref(n)))
+        return n.value
+
+    def dataset(self, first=0, count=None):
+        count = self.rows() - first if count is None else count
+        F = np.zeros((count, 4), np.float32)
+        Y = np.zeros(count, np.float32)
+        _check(lib().sp_mlp_dataset(self._h, first, count, _fptr(F), _fptr(Y)))
+        return F, Y
+
+    def forward(self, F):
+        """F: float32 (n x 4) CUDA tensor -> float32 CUDA tensor of n."""
+        y = self._torch.empty(F.shape[0], dtype=self._torch.float32, device=F.device)
+        _check(lib().sp_mlp_forward(self._h, _dev32(F), F.shape[0], _dev32(y),
+                                    ctypes.c_void_p(self._torch.cuda.current_stream().cuda_stream)))
+        return y
+
+    def train_step(self, F, Y, lr):
+        loss = ctypes.c_double(0.0)
+        _check(lib().sp_mlp_train_step(self._h, _dev32(F), _dev32(Y), F.shape[0], lr, ctypes.byref(loss),
+                                       ctypes.c_void_p(self._torch.cuda.current_stream().cuda_stream)))
+        return loss.value
+
+    def train(self, epochs, batch, lr):
+        out = np.zeros(max(1, epochs))
+        _check(lib().sp_mlp_train(self._h, epochs, batch, lr, _dptr(out),
+                                  ctypes.c_void_p(self._torch.cuda.current_stream().cuda_stream)))
+        return out[:epochs]
+
 
 class SPMPS:
     """Handle of one SP-MPS state on the current HIP device.
@@ -384,6 +477,13 @@ class SPMPS:
         out = np.zeros(max(1, getattr(self, "_n_cons", 0)))
         _check(lib().sp_orthogonality_overlaps(self._h, _dptr(out)))
         return out[: getattr(self, "_n_cons", 0)]
+
+    def set_precond(self, use=None, record=None):
+        """Correct local solves with the MLP ``use`` (None: diagonal rule) and
+        record training pairs into the MLP ``record`` (None: no recording)."""
+        _check(lib().sp_set_precond(self._h, use._h if use is not None else None,
+                                    record._h if record is not None else None))
+        self._models = (use, record)  # keep them alive while attached
 
     def heff_plan(self, site):
         """(rows per task, LDS doubles) of the site's fused plan; (0, 0) when

@@ -254,4 +254,27 @@ void bdav_ritz(hipStream_t s, const DavInst* insts, int ninst, int max_n);
 void bdav_cgs(hipStream_t s, const DavInst* insts, int ninst, int max_n, int mode);
 void bdav_gram(hipStream_t s, const DavInst* insts, int ninst, int max_n, int max_m);
 
+// Learned Davidson preconditioner (mlp.hip): two-layer perceptron on four
+// features per element; packed weights W1 (H x 4) | b1 (H) | w2 (H) | b2
+constexpr int kMlpIn = 4;
+constexpr int kMlpMaxHidden = 256;
+__host__ __device__ inline long long mlp_size(int H) { return (long long)H * (kMlpIn + 2) + 1; }
+// *out = sum over chunks of part[q * stride + idx] (fixed order)
+void sum_partials(hipStream_t s, const double* part, int nchunk, int stride, int idx, double* out);
+// features of every element from t = -r / d' (rr = |r|^2, theta device
+// scalars); feat (n x 4 FP32) and sgn (n, sign(r_i)) if feat is not null;
+// t replaced by the model's correction if w is not null
+void mlp_apply(hipStream_t s, const float* w, int H, double* t, const double* dh, const double* dn,
+               const double* theta, const double* rr, int n, double floor_, float* feat, float* sgn);
+void mlp_forward(hipStream_t s, const float* w, int H, const float* F, long long n, float* y);
+// targets of nrec recorded iterations (Ritz vectors ldx apart) against the
+// unit vector xstar, n per iteration; Y holds sign(r) on entry
+void mlp_targets(hipStream_t s, const double* X, long long ldx, int nrec, const double* xstar, int n, float* Y);
+// per-work-group gradient partials (mlp_size(H) + 1 doubles each, the last
+// the summed squared error) over rows row0 + q * stride, q < count
+void mlp_grad(hipStream_t s, const float* w, int H, const float* F, const float* Y, long long row0, long long stride,
+              long long count, double* gpart, int nparts);
+void mlp_adam(hipStream_t s, float* w, double* m, double* v, int H, const double* gpart, int nparts, double scale,
+              double lr, int step, double* loss_out);
+
 }  // namespace spk

@@ -380,11 +380,29 @@ struct sp_handle {
     int con_active = 0;
     double* con_pin = nullptr;  // mapped: norm partials read by the host
     double* con_pin_dev = nullptr;
+    // learned preconditioner: the model used for corrections and the one
+    // collecting training pairs (either may be null), Ritz vectors of the
+    // current solve for the targets, device scalars
+    sp_mlp* mlp_use = nullptr;
+    sp_mlp* mlp_rec = nullptr;
+    DArr<double> xrec, mlp_scal;
     ~sp_handle() {
         if (pin) (void)hipHostFree(pin);
         if (pin_up) (void)hipHostFree(pin_up);
         if (con_pin) (void)hipHostFree(con_pin);
     }
+};
+
+// a learned Davidson preconditioner and its training pairs (one device)
+struct sp_mlp {
+    int hidden = 0, device = 0;
+    DArr<float> w;       // packed weights
+    DArr<double> m, v;   // Adam moments
+    int step = 0;
+    long long cap = 0, rows = 0;
+    DArr<float> F, Y;    // recorded pairs: cap x 4 features, cap targets
+    DArr<double> gpart, scal;
+    int nparts = 0;
 };
 
 namespace {
@@ -2098,6 +2116,19 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
         return acc;
     };
 
+    // learned preconditioner: corrections from the model while the residual
+    // keeps reaching new minima and halves at least every four iterations
+    // (abandoned for the rest of the solve otherwise); training pairs
+    // recorded for every iteration of a converged solve
+    sp_mlp* use = h->mlp_use;
+    sp_mlp* rec = h->mlp_rec;
+    bool use_model = use != nullptr;
+    double best_r = INFINITY;
+    std::vector<double> rhist;
+    int stall = 0, nrec = 0, rec_last_it = 0;
+    const long long rec_base = rec ? rec->rows : 0;
+    if (rec && h->xrec.n < size_t(max_iter) * ld) h->xrec.alloc(size_t(max_iter) * ld);
+    if ((use || rec) && h->mlp_scal.n < 4) h->mlp_scal.alloc(4);
     diag(h, k, h->ddh.p, h->ddn.p);
     spk::normalize(s, site_ptr(h, k), V, n, nullptr);
     if (h->con_active) {  // start in the complement of the constraints
@@ -2154,6 +2185,22 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
         spk::dav_ritz(s, V, HV, NV, ld, m, h->pin_up_dev + lay.a, h->ddh.p, h->ddn.p, n, floor_, h->dx.p, h->dt.p,
                       dn_dev + (lay.px - lay.out), sm + lay.pc1);
         if (!last) {
+            const bool record_now = rec && rec_base + (long long)(nrec + 1) * n <= rec->cap;
+            if (use_model || record_now) {
+                spk::sum_partials(s, dn_dev + (lay.px - lay.out), nch, 3, 1, h->mlp_scal.p);
+                spk::mlp_apply(s, use_model ? use->w.p : nullptr, use ? use->hidden : 0, h->dt.p, h->ddh.p, h->ddn.p,
+                               h->pin_up_dev + lay.a + m, h->mlp_scal.p, n, floor_,
+                               record_now ? rec->F.p + (rec_base + (long long)nrec * n) * spk::kMlpIn : nullptr,
+                               record_now ? rec->Y.p + rec_base + (long long)nrec * n : nullptr);
+                if (record_now) {
+                    HIPCK(hipMemcpyAsync(h->xrec.p + size_t(nrec) * ld, h->dx.p, size_t(n) * sizeof(double),
+                                         hipMemcpyDeviceToDevice, s));
+                    ++nrec;
+                    rec_last_it = it;
+                }
+                // the dots of the new correction with the search space
+                if (use_model) spk::dav_cgs(s, V, ld, 0, m, sm + lay.pc1, nch, h->dt.p, n, sm + lay.pc1, 0);
+            }
             // the correction stays in the complement of the constraints (its
             // dots with V are unchanged, V being orthogonal to them)
             project_out(h, h->dt.p, n);
@@ -2200,6 +2247,18 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
             out.converged = true;
             break;
         }
+        if (use_model) {
+            if (out.rnorm < best_r) {
+                best_r = out.rnorm;
+                stall = 0;
+            } else {
+                ++stall;
+            }
+            rhist.push_back(out.rnorm);
+            const size_t nh = rhist.size();
+            const bool slow = nh >= 5 && out.rnorm > 0.5 * rhist[nh - 5];
+            if (stall >= 3 || slow) use_model = false;
+        }
         if (last) break;
         const double tn = dn[lay.tn - lay.out];
         if (!(tn >= 1e-14)) break;
@@ -2220,6 +2279,12 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     }
     // normalise x and write it into the site
     spk::normalize(s, h->dx.p, site_ptr(h, k), n, nullptr);
+    if (rec && out.converged && nrec > 0) {
+        // iterations before the converged one: targets against the final x
+        const int keep = nrec - (rec_last_it == out.iters ? 1 : 0);
+        spk::mlp_targets(s, h->xrec.p, ld, keep, site_ptr(h, k), n, rec->Y.p + rec_base);
+        rec->rows = rec_base + (long long)keep * n;
+    }
     if (h->precision == SP_FP32) {
         // the reported energy and norm: one FP64 product with the FP64
         // environments (the vector itself comes from the FP32 solve)
@@ -2938,6 +3003,7 @@ int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_repor
             SP_REQUIRE(h, "null handle");
             SP_REQUIRE(h->path == SP_PATH_TILED, "batched sweeps need the tiled path");
             SP_REQUIRE(h->cons.empty(), "states with orthogonality constraints sweep with sp_sweep");
+            SP_REQUIRE(!h->mlp_use && !h->mlp_rec, "states with a learned preconditioner sweep with sp_sweep");
             SP_REQUIRE(h->stream == hs[0]->stream && h->device == hs[0]->device,
                        "batched handles must share one device and one stream");
             SP_REQUIRE(h->precision == hs[0]->precision, "batched handles must share the precision");
@@ -3171,6 +3237,133 @@ int sp_orthogonality_overlaps(sp_handle* h, double* out) {
             const double den = hres[nc + j] * hres[2 * nc];
             out[j] = den > 0.0 ? hres[j] / den : 0.0;
         }
+        return SP_OK;
+    });
+}
+
+int sp_mlp_create(int hidden, const float* w_init, long long capacity, sp_mlp** out) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(out && w_init && hidden >= 1 && hidden <= spk::kMlpMaxHidden && capacity >= 0, "bad arguments");
+        auto m = std::make_unique<sp_mlp>();
+        m->hidden = hidden;
+        HIPCK(hipGetDevice(&m->device));
+        const long long P = spk::mlp_size(hidden);
+        m->w.alloc(P);
+        HIPCK(hipMemcpy(m->w.p, w_init, P * sizeof(float), hipMemcpyHostToDevice));
+        m->m.alloc(P);
+        m->v.alloc(P);
+        HIPCK(hipMemset(m->m.p, 0, P * sizeof(double)));
+        HIPCK(hipMemset(m->v.p, 0, P * sizeof(double)));
+        m->cap = capacity;
+        if (capacity > 0) {
+            m->F.alloc(size_t(capacity) * spk::kMlpIn);
+            m->Y.alloc(capacity);
+        }
+        m->nparts = 256;
+        m->gpart.alloc(size_t(m->nparts) * (P + 1));
+        m->scal.alloc(4096);
+        *out = m.release();
+        return SP_OK;
+    });
+}
+
+int sp_mlp_destroy(sp_mlp* m) {
+    return guarded([&]() -> int {
+        if (m) {
+            (void)hipDeviceSynchronize();
+            delete m;
+        }
+        return SP_OK;
+    });
+}
+
+int sp_mlp_get(sp_mlp* m, float* w_out, long long* rows) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(m, "null argument");
+        HIPCK(hipDeviceSynchronize());
+        if (w_out) HIPCK(hipMemcpy(w_out, m->w.p, spk::mlp_size(m->hidden) * sizeof(float), hipMemcpyDeviceToHost));
+        if (rows) *rows = m->rows;
+        return SP_OK;
+    });
+}
+
+int sp_mlp_dataset(sp_mlp* m, long long first, long long count, float* F_out, float* Y_out) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(m && F_out && Y_out && first >= 0 && count >= 0 && first + count <= m->rows, "bad arguments");
+        HIPCK(hipDeviceSynchronize());
+        if (count == 0) return SP_OK;
+        HIPCK(hipMemcpy(F_out, m->F.p + first * spk::kMlpIn, count * spk::kMlpIn * sizeof(float),
+                        hipMemcpyDeviceToHost));
+        HIPCK(hipMemcpy(Y_out, m->Y.p + first, count * sizeof(float), hipMemcpyDeviceToHost));
+        return SP_OK;
+    });
+}
+
+int sp_mlp_forward(sp_mlp* m, const float* F, long long n, float* y, void* stream) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(m && (n == 0 || (F && y)) && n >= 0, "bad arguments");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        spk::mlp_forward(s, m->w.p, m->hidden, F, n, y);
+        HIPCK(hipGetLastError());
+        return SP_OK;
+    });
+}
+
+int sp_mlp_train_step(sp_mlp* m, const float* F, const float* Y, long long n, double lr, double* loss, void* stream) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(m && F && Y && n >= 1 && lr > 0.0, "bad arguments");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int parts = int(std::min<long long>(m->nparts, std::max<long long>(1, n / 1024)));
+        spk::mlp_grad(s, m->w.p, m->hidden, F, Y, 0, 1, n, m->gpart.p, parts);
+        m->step++;
+        spk::mlp_adam(s, m->w.p, m->m.p, m->v.p, m->hidden, m->gpart.p, parts, 1.0 / double(n), lr, m->step,
+                      m->scal.p);
+        double l = 0.0;
+        HIPCK(hipMemcpyAsync(&l, m->scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        if (loss) *loss = l;
+        return SP_OK;
+    });
+}
+
+int sp_mlp_train(sp_mlp* m, int epochs, long long batch, double lr, double* loss_out, void* stream) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(m && epochs >= 0 && batch >= 1 && lr > 0.0, "bad arguments");
+        SP_REQUIRE(m->rows > 0, "no recorded training pairs");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const long long rows = m->rows;
+        const long long nb = std::min<long long>((rows + batch - 1) / batch, 4096);
+        for (int e = 0; e < epochs; ++e) {
+            // batch b: rows b, b + nb, b + 2 nb, ... (interleaves the solves)
+            for (long long b = 0; b < nb; ++b) {
+                const long long count = (rows - b + nb - 1) / nb;
+                const int parts = int(std::min<long long>(m->nparts, std::max<long long>(1, count / 1024)));
+                spk::mlp_grad(s, m->w.p, m->hidden, m->F.p, m->Y.p, b, nb, count, m->gpart.p, parts);
+                m->step++;
+                spk::mlp_adam(s, m->w.p, m->m.p, m->v.p, m->hidden, m->gpart.p, parts, 1.0 / double(count), lr,
+                              m->step, m->scal.p + b);
+            }
+            std::vector<double> l(nb);
+            HIPCK(hipMemcpyAsync(l.data(), m->scal.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCK(hipStreamSynchronize(s));
+            double tot = 0.0;
+            for (double x : l) tot += x;
+            if (loss_out) loss_out[e] = tot / double(nb);
+        }
+        HIPCK(hipGetLastError());
+        return SP_OK;
+    });
+}
+
+int sp_set_precond(sp_handle* h, sp_mlp* use, sp_mlp* record) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h, "null argument");
+        for (sp_mlp* m : {use, record})
+            if (m) SP_REQUIRE(m->device == h->device, "the model must live on the state's device");
+        if (record) SP_REQUIRE(record->cap > 0, "the recording model has no room for training pairs");
+        HIPCK(hipStreamSynchronize(h->stream));
+        h->mlp_use = use;
+        h->mlp_rec = record;
         return SP_OK;
     });
 }

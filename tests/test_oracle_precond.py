@@ -86,12 +86,26 @@ def test_features_definition():
     dn = np.array([1.0, 0.5, 0.0, 0.0])
     F = pre.features(r, dh, dn, theta=1.0)
     rms = np.sqrt(np.mean(r * r))
-    assert np.allclose(F[:, 0], r / rms)
+    assert np.allclose(F[:, 0], np.abs(r) / rms)
     assert np.allclose(F[:, 1], np.arcsinh(dh - dn))
     assert np.allclose(F[:, 2], np.arcsinh(dn))
     d = dh - dn
     d[3] = 1e-8  # floored
-    assert np.allclose(F[:, 3], np.arcsinh(-(r / rms) / d))
+    assert np.allclose(F[:, 3], np.arcsinh(-(np.abs(r) / rms) / d))
+
+
+def test_correction_is_odd_in_the_residual():
+    p = _params()
+    rng = np.random.default_rng(5)
+    r, dh, dn = rng.standard_normal(20), rng.standard_normal(20) + 3, rng.random(20)
+    a = pre.correction(p, r, dh, dn, 0.7)
+    b = pre.correction(p, -r, dh, dn, 0.7)
+    assert np.allclose(a, -b, atol=1e-15)
+    x, xs = rng.standard_normal(20), rng.standard_normal(20)
+    x /= np.linalg.norm(x)
+    xs /= np.linalg.norm(xs)
+    # flipping the Ritz vector flips r and e: the targets do not change
+    assert np.allclose(pre.target(r, x, xs), pre.target(-r, -x, xs), atol=1e-12)
 
 
 def test_solver_hook_with_the_diagonal_rule_reproduces_the_default():
