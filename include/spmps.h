@@ -234,7 +234,8 @@ int sp_orthogonality_overlaps(sp_handle* h, double* out);
  * replaces it by a two-layer perceptron (hidden width H <= 256, ReLU)
  * applied to each element of the site tensor separately, on the features
  * f0 = |r_i| / rms(r), f1 = asinh(d_i), f2 = asinh(dN_i),
- * f3 = asinh(-f0/d_i') (d = dH - theta dN, d' = d floored), with
+ * f3 = asinh(-f0/d_i'), f4 = sign(r_i) t_i / rms(t) (d = dH - theta dN,
+ * d' = d floored, t = -r / d' the diagonal correction), with
  * t_i = sign(r_i) g(f) (odd in r; Davidson normalises t).  While a model
  * is in use, a local solve falls back to the diagonal rule for good once
  * its residual norm has missed a new minimum three iterations in a row or
@@ -248,14 +249,14 @@ int sp_orthogonality_overlaps(sp_handle* h, double* out);
  * eps 1e-8) on the mean squared error.  A model belongs to the device that
  * was current at sp_mlp_create; it must outlive every state that uses it. */
 
-/* w_init: mlp_size(H) = 6H + 1 floats, packed W1 (H x 4 row-major) | b1 (H)
+/* w_init: mlp_size(H) = 7H + 1 floats, packed W1 (H x 5 row-major) | b1 (H)
  * | w2 (H) | b2 (host, copied); capacity: rows (elements) of training
  * pairs the model can record (0: none). */
 int sp_mlp_create(int hidden, const float* w_init, long long capacity, sp_mlp** out);
 int sp_mlp_destroy(sp_mlp* m);
-/* Current weights (host, 6H + 1 floats; may be NULL) and recorded rows. */
+/* Current weights (host, 7H + 1 floats; may be NULL) and recorded rows. */
 int sp_mlp_get(sp_mlp* m, float* w_out, long long* rows);
-/* Recorded pairs [first, first + count): features (count x 4) and targets
+/* Recorded pairs [first, first + count): features (count x 5) and targets
  * (host). */
 int sp_mlp_dataset(sp_mlp* m, long long first, long long count, float* F_out, float* Y_out);
 /* y = model(F) for n feature rows (device pointers, FP32) on `stream`

@@ -11,12 +11,13 @@ the site tensor separately:
             f1 = asinh(d_i),            d_i = dh_i - theta dn_i
             f2 = asinh(dn_i)
             f3 = asinh(-f0 / d_i'),     d_i' = d_i floored to |d_i| >= floor
+            f4 = sign(r_i) t_i / rms(t), t = -r / d' (the diagonal correction)
   model     g(f) = w2 . relu(W1 f + b1) + b2
   correction t_i = sign(r_i) g(f)
 
 The correction is odd in r, as a linear preconditioner is, so the sign of
 the Ritz vector (free in an eigensolver) does not matter; the diagonal rule
-is the special case g = -f0 rms(r) / d_i'.  The Davidson step normalises t,
+is the special case g = f4 (up to scale).  The Davidson step normalises t,
 so only its direction matters.  Training pairs come from the solver itself:
 at iteration j of a converged local solve with Ritz vector x_j (unit norm)
 and final vector x*, the exact correction is e_j = x*/(x_j . x*) - x_j, the
@@ -31,14 +32,17 @@ import numpy as np
 
 
 def features(r, dh, dn, theta, floor=1e-8):
-    """Four features per element (n x 4)."""
+    """Five features per element (n x 5)."""
     r = np.asarray(r, dtype=float)
     n = r.size
     rms = np.sqrt(np.sum(r * r) / n)
     f0 = np.abs(r) / rms if rms > 0 else np.zeros(n)
     d = dh - theta * dn
     dfl = np.where(np.abs(d) < floor, np.where(d < 0, -floor, floor), d)
-    return np.stack([f0, np.arcsinh(d), np.arcsinh(dn), np.arcsinh(-f0 / dfl)], axis=1)
+    t = -r / dfl
+    rmst = np.sqrt(np.sum(t * t) / n)
+    f4 = np.sign(r) * t / rmst if rmst > 0 else np.zeros(n)
+    return np.stack([f0, np.arcsinh(d), np.arcsinh(dn), np.arcsinh(-f0 / dfl), f4], axis=1)
 
 
 def correction(p, r, dh, dn, theta, floor=1e-8):
@@ -52,7 +56,7 @@ def target(r, x, xstar):
 
 
 def forward(p, F):
-    """Model output for feature rows F (n x 4)."""
+    """Model output for feature rows F (n x 5)."""
     z = F @ np.asarray(p["W1"], float).T + np.asarray(p["b1"], float)[None, :]
     h = np.maximum(z, 0.0)
     return h @ np.asarray(p["w2"], float) + float(p["b2"])

@@ -257,15 +257,20 @@ def small_gen_lowest(H, N, drop=1e-10):
 
 # ---- the SP-MPS state ------------------------------------------------------
 
+MLP_IN = 5  # features per element of the learned preconditioner
+
+
 def pack_mlp(p):
-    """Packed FP32 weights W1 (H x 4) | b1 | w2 | b2 from a dict."""
+    """Packed FP32 weights W1 (H x 5) | b1 | w2 | b2 from a dict."""
     return np.concatenate([np.asarray(p["W1"], np.float32).ravel(), np.asarray(p["b1"], np.float32),
                            np.asarray(p["w2"], np.float32), np.asarray([p["b2"]], np.float32)])
 
 
 def unpack_mlp(w, H):
     w = np.asarray(w, np.float32)
-    return {"W1": w[: 4 * H].reshape(H, 4), "b1": w[4 * H: 5 * H], "w2": w[5 * H: 6 * H], "b2": float(w[6 * H])}
+    k = MLP_IN
+    return {"W1": w[: k * H].reshape(H, k), "b1": w[k * H: (k + 1) * H], "w2": w[(k + 1) * H: (k + 2) * H],
+            "b2": float(w[(k + 2) * H])}
 
 
 class MLP:
@@ -292,7 +297,7 @@ class MLP:
             pass
 
     def params(self):
-        w = np.zeros(6 * self.hidden + 1, np.float32)
+        w = np.zeros((MLP_IN + 2) * self.hidden + 1, np.float32)
         _check(lib().sp_mlp_get(self._h, _fptr(w), None))
         return unpack_mlp(w, self.hidden)
 
@@ -303,13 +308,13 @@ class MLP:
 
     def dataset(self, first=0, count=None):
         count = self.rows() - first if count is None else count
-        F = np.zeros((count, 4), np.float32)
+        F = np.zeros((count, MLP_IN), np.float32)
         Y = np.zeros(count, np.float32)
         _check(lib().sp_mlp_dataset(self._h, first, count, _fptr(F), _fptr(Y)))
         return F, Y
 
     def forward(self, F):
-        """F: float32 (n x 4) CUDA tensor -> float32 CUDA tensor of n."""
+        """F: float32 (n x 5) CUDA tensor -> float32 CUDA tensor of n."""
         y = self._torch.empty(F.shape[0], dtype=self._torch.float32, device=F.device)
         _check(lib().sp_mlp_forward(self._h, _dev32(F), F.shape[0], _dev32(y),
                                     ctypes.c_void_p(self._torch.cuda.current_stream().cuda_stream)))

@@ -254,18 +254,21 @@ void bdav_ritz(hipStream_t s, const DavInst* insts, int ninst, int max_n);
 void bdav_cgs(hipStream_t s, const DavInst* insts, int ninst, int max_n, int mode);
 void bdav_gram(hipStream_t s, const DavInst* insts, int ninst, int max_n, int max_m);
 
-// Learned Davidson preconditioner (mlp.hip): two-layer perceptron on four
-// features per element; packed weights W1 (H x 4) | b1 (H) | w2 (H) | b2
-constexpr int kMlpIn = 4;
+// Learned Davidson preconditioner (mlp.hip): two-layer perceptron on five
+// features per element; packed weights W1 (H x 5) | b1 (H) | w2 (H) | b2
+constexpr int kMlpIn = 5;
 constexpr int kMlpMaxHidden = 256;
 __host__ __device__ inline long long mlp_size(int H) { return (long long)H * (kMlpIn + 2) + 1; }
 // *out = sum over chunks of part[q * stride + idx] (fixed order)
 void sum_partials(hipStream_t s, const double* part, int nchunk, int stride, int idx, double* out);
-// features of every element from t = -r / d' (rr = |r|^2, theta device
-// scalars); feat (n x 4 FP32) and sgn (n, sign(r_i)) if feat is not null;
+// features of every element from t = -r / d' (rr = |r|^2, tt = |t|^2,
+// theta device scalars); feat (n x 5 FP32) and sgn (n, sign(r_i)) if feat is not null;
 // t replaced by the model's correction if w is not null
 void mlp_apply(hipStream_t s, const float* w, int H, double* t, const double* dh, const double* dn,
-               const double* theta, const double* rr, int n, double floor_, float* feat, float* sgn);
+               const double* theta, const double* rr, const double* tt, int n, double floor_, float* feat,
+               float* sgn);
+// *out = v . v (one work-group, fixed order)
+void sumsq(hipStream_t s, const double* v, int n, double* out);
 void mlp_forward(hipStream_t s, const float* w, int H, const float* F, long long n, float* y);
 // targets of nrec recorded iterations (Ritz vectors ldx apart) against the
 // unit vector xstar, n per iteration; Y holds sign(r) on entry

@@ -3,8 +3,9 @@
 //
 // The paper leaves the local solver of Sec. 2.3 open; the library's solver
 // is Davidson with the diagonal correction t = -r / (dh - theta dn).  The
-// learned variant maps four features of each element,
-//   f0 = |r_i| / rms(r), f1 = asinh(d_i), f2 = asinh(dn_i), f3 = asinh(-f0 / d_i')
+// learned variant maps five features of each element,
+//   f0 = |r_i| / rms(r), f1 = asinh(d_i), f2 = asinh(dn_i), f3 = asinh(-f0 / d_i'),
+//   f4 = sign(r_i) t_i / rms(t)   (t = -r / d', the diagonal correction)
 // (d = dh - theta dn, d' = d floored to |d'| >= floor) to
 // t_i = sign(r_i) (w2 . relu(W1 f + b1) + b2): odd in r like a linear
 // preconditioner, so the free sign of the Ritz vector does not matter.
@@ -13,7 +14,7 @@
 // vector of iteration j, x* the converged one) divided by rms(e_j), times
 // sign(r_i).
 // Weights and recorded pairs are FP32 in memory; all arithmetic is FP64.
-// Packed weights: W1 (H x 4, row-major) | b1 (H) | w2 (H) | b2.
+// Packed weights: W1 (H x 5, row-major) | b1 (H) | w2 (H) | b2.
 
 #include <hip/hip_runtime.h>
 
@@ -79,26 +80,35 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_apply(const float* __restri
                                                            const double* __restrict__ dh,
                                                            const double* __restrict__ dn,
                                                            const double* __restrict__ theta,
-                                                           const double* __restrict__ rr, int n, double floor_,
+                                                           const double* __restrict__ rr,
+                                                           const double* __restrict__ tt, int n, double floor_,
                                                            float* __restrict__ feat, float* __restrict__ sgn) {
     extern __shared__ double sw[];
     if (w) load_weights(w, H, sw);
     const int i = blockIdx.x * kMlpThreads + threadIdx.x;
     if (i >= n) return;
     const double th = *theta;
-    const double rms = sqrt(*rr / n);
+    const double rms = sqrt(*rr / n), rmst = sqrt(*tt / n);
     const double d = dh[i] - th * dn[i];
     const double dfl = fabs(d) < floor_ ? (d < 0.0 ? -floor_ : floor_) : d;
     const double r = -t[i] * dfl;
     const double sr = r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0);
     const double f0 = rms > 0.0 ? fabs(r) / rms : 0.0;
-    double f[kMlpIn] = {f0, asinh(d), asinh(dn[i]), asinh(-f0 / dfl)};
+    double f[kMlpIn] = {f0, asinh(d), asinh(dn[i]), asinh(-f0 / dfl), rmst > 0.0 ? sr * t[i] / rmst : 0.0};
     if (feat) {
 #pragma unroll
         for (int c = 0; c < kMlpIn; ++c) feat[(long long)i * kMlpIn + c] = float(f[c]);
         sgn[i] = float(sr);
     }
     if (w) t[i] = sr * mlp_eval(sw, H, f);
+}
+
+__global__ __launch_bounds__(1024) void k_sumsq(const double* __restrict__ v, int n, double* __restrict__ out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s = fma(v[i], v[i], s);
+    s = group_sum(s, red);
+    if (threadIdx.x == 0) *out = s;
 }
 
 __global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(const float* __restrict__ w, int H,
@@ -153,7 +163,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad(const float* __restric
     __shared__ double sy[4];
     const int j = threadIdx.x;
     const bool own = j < H;
-    double W1[kMlpIn] = {0, 0, 0, 0}, b1 = 0.0, w2 = 0.0;
+    double W1[kMlpIn] = {}, b1 = 0.0, w2 = 0.0;
     if (own) {
 #pragma unroll
         for (int c = 0; c < kMlpIn; ++c) W1[c] = w[j * kMlpIn + c];
@@ -161,7 +171,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_grad(const float* __restric
         w2 = w[H * kMlpIn + H + j];
     }
     const double b2 = w[H * (kMlpIn + 2)];
-    double gW1[kMlpIn] = {0, 0, 0, 0}, gb1 = 0.0, gw2 = 0.0, gb2 = 0.0, loss = 0.0;
+    double gW1[kMlpIn] = {}, gb1 = 0.0, gw2 = 0.0, gb2 = 0.0, loss = 0.0;
     const long long per = (count + gridDim.x - 1) / gridDim.x;
     const long long q0 = (long long)blockIdx.x * per, q1 = min(count, q0 + per);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -262,11 +272,16 @@ void sum_partials(hipStream_t s, const double* part, int nchunk, int stride, int
 }
 
 void mlp_apply(hipStream_t s, const float* w, int H, double* t, const double* dh, const double* dn,
-               const double* theta, const double* rr, int n, double floor_, float* feat, float* sgn) {
+               const double* theta, const double* rr, const double* tt, int n, double floor_, float* feat,
+               float* sgn) {
     if (n <= 0) return;
     const size_t lds = w ? size_t(mlp_size(H)) * sizeof(double) : 0;
-    hipLaunchKernelGGL(k_mlp_apply, dim3(blocks_for(n)), dim3(kMlpThreads), lds, s, w, H, t, dh, dn, theta, rr, n,
-                       floor_, feat, sgn);
+    hipLaunchKernelGGL(k_mlp_apply, dim3(blocks_for(n)), dim3(kMlpThreads), lds, s, w, H, t, dh, dn, theta, rr, tt,
+                       n, floor_, feat, sgn);
+}
+
+void sumsq(hipStream_t s, const double* v, int n, double* out) {
+    hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(1024), 0, s, v, n, out);
 }
 
 void mlp_forward(hipStream_t s, const float* w, int H, const float* F, long long n, float* y) {

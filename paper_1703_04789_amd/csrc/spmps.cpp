@@ -2188,8 +2188,9 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
             const bool record_now = rec && rec_base + (long long)(nrec + 1) * n <= rec->cap;
             if (use_model || record_now) {
                 spk::sum_partials(s, dn_dev + (lay.px - lay.out), nch, 3, 1, h->mlp_scal.p);
+                spk::sumsq(s, h->dt.p, n, h->mlp_scal.p + 1);
                 spk::mlp_apply(s, use_model ? use->w.p : nullptr, use ? use->hidden : 0, h->dt.p, h->ddh.p, h->ddn.p,
-                               h->pin_up_dev + lay.a + m, h->mlp_scal.p, n, floor_,
+                               h->pin_up_dev + lay.a + m, h->mlp_scal.p, h->mlp_scal.p + 1, n, floor_,
                                record_now ? rec->F.p + (rec_base + (long long)nrec * n) * spk::kMlpIn : nullptr,
                                record_now ? rec->Y.p + rec_base + (long long)nrec * n : nullptr);
                 if (record_now) {

@@ -37,7 +37,7 @@ def _as64(p):
 def test_forward_matches_reference():
     p = _params(256)
     m = sp.MLP(p)
-    F = np.random.default_rng(1).standard_normal((5000, 4)).astype(np.float32)
+    F = np.random.default_rng(1).standard_normal((5000, 5)).astype(np.float32)
     y = m.forward(torch.tensor(F, device="cuda")).cpu().numpy()
     ref = pre.forward(_as64(p), F.astype(np.float64))
     assert np.abs(y - ref).max() < 1e-6 * np.abs(ref).max()
@@ -47,7 +47,7 @@ def test_train_steps_match_adam_reference():
     p = _params(128, 3)
     m = sp.MLP(p)
     rng = np.random.default_rng(2)
-    F = rng.standard_normal((6000, 4)).astype(np.float32)
+    F = rng.standard_normal((6000, 5)).astype(np.float32)
     Y = rng.standard_normal(6000).astype(np.float32)
     Fd, Yd = torch.tensor(F, device="cuda"), torch.tensor(Y, device="cuda")
     ref, state = _as64(p), {}

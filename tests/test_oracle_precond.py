@@ -21,7 +21,7 @@ def _params(hidden=16, seed=0):
 def test_gradients_match_finite_differences():
     rng = np.random.default_rng(4)
     p = _params()
-    F = rng.standard_normal((50, 4))
+    F = rng.standard_normal((50, 5))
     Y = rng.standard_normal(50)
     loss, g = pre.loss_and_grads(p, F, Y)
     assert abs(loss - 0.5 * np.mean((pre.forward(p, F) - Y) ** 2)) < 1e-14
@@ -46,14 +46,14 @@ def test_gradients_match_finite_differences():
 def test_forward_closed_form():
     p = _params()
     p["W1"] = np.zeros_like(p["W1"])
-    F = np.random.default_rng(0).standard_normal((7, 4))
+    F = np.random.default_rng(0).standard_normal((7, 5))
     y = pre.forward(p, F)
     assert np.allclose(y, p["b2"] + np.maximum(p["b1"], 0) @ p["w2"], atol=1e-15)
 
 
 def test_adam_first_step_is_a_signed_step():
     p = _params()
-    F = np.random.default_rng(1).standard_normal((30, 4))
+    F = np.random.default_rng(1).standard_normal((30, 5))
     Y = np.ones(30)
     _, g = pre.loss_and_grads(p, F, Y)
     st = {}
@@ -92,6 +92,8 @@ def test_features_definition():
     d = dh - dn
     d[3] = 1e-8  # floored
     assert np.allclose(F[:, 3], np.arcsinh(-(np.abs(r) / rms) / d))
+    t = -r / d
+    assert np.allclose(F[:, 4], np.sign(r) * t / np.sqrt(np.mean(t * t)))
 
 
 def test_correction_is_odd_in_the_residual():

@@ -351,10 +351,10 @@ def abinitio_reduced(K: int = 12, D: int = 128, G: int = 11) -> AbInitioWorkload
 
 # ---------------------------------------------------------------------------
 # Initial weights of the learned Davidson preconditioner (a two-layer MLP on
-# four features per site-tensor element).
+# five features per site-tensor element).
 
 
-def mlp_init(hidden: int = 256, seed: int = 0, n_in: int = 4):
+def mlp_init(hidden: int = 256, seed: int = 0, n_in: int = 5):
     """Seeded initial weights (FP32): W1 (hidden x n_in) and w2 (hidden)
     uniform in +-sqrt(6/fan_in) (He initialisation for the ReLU layer,
     +-sqrt(3/hidden) for the output), biases zero."""
