@@ -189,6 +189,8 @@ void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* p
 
 // Davidson vector kernels (n = vector length, ld = stride between vectors)
 void normalize(hipStream_t s, const double* in, double* out, int n, double* norm_out);
+// p[0..n) = value
+void fill(hipStream_t s, double* p, long long n, double value);
 void multidot(hipStream_t s, const double* A, long long ld, int m, const double* u, int n,
               double* out);
 void basis_rotate(hipStream_t s, const double* A, long long ld, int m, const double* Q, int keep,

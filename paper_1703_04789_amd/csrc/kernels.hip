@@ -328,6 +328,11 @@ __global__ __launch_bounds__(kThreads) void k_qr_lds(const QrTask* __restrict__ 
 
 // ---- Davidson vector kernels --------------------------------------------
 
+__global__ __launch_bounds__(kThreads) void k_fill(double* __restrict__ p, long long n, double value) {
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads)
+        p[i] = value;
+}
+
 __global__ __launch_bounds__(1024) void k_normalize(const double* __restrict__ in,
                                                      double* __restrict__ out, int n,
                                                      double* __restrict__ norm_out) {
@@ -1162,6 +1167,11 @@ void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* p
                            pieces, site, rout);
     else
         hipLaunchKernelGGL(k_qr, dim3(ntasks), dim3(kThreads), 0, s, tasks, pieces, site, scratch, rout);
+}
+void fill(hipStream_t s, double* p, long long n, double value) {
+    if (n <= 0) return;
+    const long long nb = std::min<long long>((n + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_fill, dim3(unsigned(nb)), dim3(kThreads), 0, s, p, n, value);
 }
 void normalize(hipStream_t s, const double* in, double* out, int n, double* norm_out) {
     hipLaunchKernelGGL(k_normalize, dim3(1), dim3(1024), 0, s, in, out, n, norm_out);

@@ -314,6 +314,7 @@ struct SitePlan {
     std::vector<int> xmap_h;  // dense element -> packed index or -1
     DArr<int> xmap;
     TList t_left, t_right, t_envl, t_zr, t_envr;
+    int tr_split = 1;  // channel chunks of the tiled right product (partials: tr_split * G)
     // fused H_eff x
     int h_rows = 0;         // rows per task (RC); 0: no fused plan
     int h_lds = 0;          // dynamic LDS per work-group (doubles)
@@ -358,6 +359,7 @@ struct sp_handle {
     int path = SP_PATH_TILED;
     DArr<double> T, V, qr_scratch, qr_r, tmp_site, Xd, ypart, nypart;
     long long Xd_cap = 0;
+    int tr_split_max = 1;  // partial slots per quadrature point (tiled lists)
     long long T_cap = 0, V_cap = 0, qr_scratch_cap = 0, qr_r_cap = 0;
     int center = 1;
     // Davidson workspace
@@ -1083,8 +1085,28 @@ void build_plan(sp_handle* h, int k) {
                                              g * P.nc + P.c_one());
                     }
             }
-    // right product: per g partial y and ny, scattered into the packed layout
+    // right product: per g partial y and ny, scattered into the packed layout.
+    // An output tile sums over every right channel; wide MPOs have hundreds,
+    // so the channel list of a tile is cut into up to tr_split chunks, each
+    // its own work-group writing partial slot (chunk * G + g): the consumers
+    // add all tr_split * G slots in a fixed order (slots a tile has no chunk
+    // for are zero-filled before the launch).  tr_split aims at about 8192
+    // work-groups, each with at least 4 channels, so that the extra partial
+    // slots stay few.
     const long long xs = si.size;
+    struct TSegD {
+        int a_buf;
+        long long a_off;
+        int lda, ta, b_buf;
+        long long b_off;
+        int ldb, tb, k0, k1, cidx;
+    };
+    struct TOut {
+        int c_buf, g, Nn, M, r0, c0;
+        long long pack;
+        std::vector<TSegD> segs;
+    };
+    std::vector<TOut> outs;
     for (int g = 0; g < G; ++g)
         for (int i = 0; i < int(bl.nb.size()); ++i)
             for (int sig = 0; sig < 4; ++sig) {
@@ -1096,30 +1118,51 @@ void build_plan(sp_handle* h, int k) {
                         int k0, k1;
                         if (!k_from_rows(i, sig, r0, std::min(M, r0 + TT), k0, k1)) continue;
                         if (k1 <= c0 || k0 >= std::min(Nn, c0 + TT)) continue;  // no (N, M) block in the tile
-                        P.t_right.add_task(B_Y, g * xs, Nn, M, Nn, r0, c0, 1, xdoff(i, sig));
+                        TOut oy{B_Y, g, Nn, M, r0, c0, xdoff(i, sig), {}};
                         for (int cp = 0; cp < wr; ++cp) {
                             auto it = Voff.find({sig, cp, i});
                             if (it == Voff.end()) continue;
                             const int re = er.find(cp, nbb);
                             if (re < 0) continue;
                             const EnvBlk& RB = er.blk[re];
-                            P.t_right.add_seg(B_V, g * P.Vsize + it->second, RB.cols, 0, B_ENVR, g * Rsz + RB.off,
-                                              RB.cols, 1, 0, RB.cols, g * P.nc + P.c_g());
+                            oy.segs.push_back(TSegD{B_V, g * P.Vsize + it->second, RB.cols, 0, B_ENVR,
+                                                    g * Rsz + RB.off, RB.cols, 1, 0, RB.cols, g * P.nc + P.c_g()});
                         }
-                        P.t_right.add_task(B_NY, g * xs, Nn, M, Nn, r0, c0, 1, xdoff(i, sig));
+                        outs.push_back(std::move(oy));
+                        TOut on{B_NY, g, Nn, M, r0, c0, xdoff(i, sig), {}};
                         const int e0 = el.find(0, i);
                         const int re = er.find(lastR, nbb);
-                        if (e0 < 0 || re < 0) continue;
-                        for (int q = 0; q < 4; ++q) {
-                            if (!rot_nonzero(sig, q)) continue;
-                            const long long to = Toff[size_t(e0) * 4 + q];
-                            if (to < 0) continue;
-                            const EnvBlk& RB = er.blk[re];
-                            P.t_right.add_seg(B_T, g * P.Tsize + to, Tcols[size_t(e0) * 4 + q], 0, B_ENVR,
-                                              g * Rsz + RB.off, RB.cols, 1, 0, RB.cols, g * P.nc + P.c_gr(sig, q));
-                        }
+                        if (e0 >= 0 && re >= 0)
+                            for (int q = 0; q < 4; ++q) {
+                                if (!rot_nonzero(sig, q)) continue;
+                                const long long to = Toff[size_t(e0) * 4 + q];
+                                if (to < 0) continue;
+                                const EnvBlk& RB = er.blk[re];
+                                on.segs.push_back(TSegD{B_T, g * P.Tsize + to, Tcols[size_t(e0) * 4 + q], 0, B_ENVR,
+                                                        g * Rsz + RB.off, RB.cols, 1, 0, RB.cols,
+                                                        g * P.nc + P.c_gr(sig, q)});
+                            }
+                        outs.push_back(std::move(on));
                     }
             }
+    size_t max_segs = 1;
+    for (const TOut& o : outs) max_segs = std::max(max_segs, o.segs.size());
+    const int want = int(std::max<size_t>(1, (8192 + outs.size() - 1) / std::max<size_t>(1, outs.size())));
+    const int kSegChunk = int(std::max<size_t>(4, (max_segs + want - 1) / want));
+    P.tr_split = 1;
+    for (const TOut& o : outs)
+        P.tr_split = std::max(P.tr_split, int((o.segs.size() + kSegChunk - 1) / kSegChunk));
+    for (const TOut& o : outs) {
+        const int nchunk = std::max(1, int((o.segs.size() + kSegChunk - 1) / kSegChunk));
+        for (int c = 0; c < nchunk; ++c) {
+            P.t_right.add_task(o.c_buf, ((long long)c * G + o.g) * xs, o.Nn, o.M, o.Nn, o.r0, o.c0, 1, o.pack);
+            const size_t s0 = size_t(c) * kSegChunk, s1 = std::min(o.segs.size(), s0 + kSegChunk);
+            for (size_t q = s0; q < s1; ++q) {
+                const TSegD& d = o.segs[q];
+                P.t_right.add_seg(d.a_buf, d.a_off, d.lda, d.ta, d.b_buf, d.b_off, d.ldb, d.tb, d.k0, d.k1, d.cidx);
+            }
+        }
+    }
     // left environment: L[k](c', b, b') = sum_sigma Xd(a, sigma, b)^T V(sigma, c', a)
     for (int g = 0; g < G; ++g)
         for (const EnvBlk& OB : er.blk)
@@ -1629,8 +1672,8 @@ void validate_plans(sp_handle* h) {
         {
             Sizes t = z;
             t[B_X] = h->Xd_cap;
-            t[B_Y] = G * h->max_site;
-            t[B_NY] = G * h->max_site;
+            t[B_Y] = G * h->tr_split_max * h->max_site;
+            t[B_NY] = G * h->tr_split_max * h->max_site;
             for (int e : P.xmap_h)
                 if (e >= xs) throw SpError(SP_EINVAL, "internal: packed map out of range");
             const long long ms = (long long)P.xmap_h.size();
@@ -1753,7 +1796,17 @@ void heff_tiled(sp_handle* h, int k, const double* x) {
     spk::gather(s, P.xmap.p, x, h->Xd.p, P.Xd_size);
     P.t_left.launch(s, b, P.coef.p, P.xmap.p);
     P.mixl.launch(s, b, P.coef.p);
+    if (P.tr_split > 1) {  // slots without a chunk of some tile stay zero
+        const long long nslot = (long long)P.tr_split * h->G * h->sites[k - 1].size;
+        spk::fill(s, h->ypart.p, nslot, 0.0);
+        spk::fill(s, h->nypart.p, nslot, 0.0);
+    }
     P.t_right.launch(s, b, P.coef.p, P.xmap.p);
+}
+
+// number of per-site partial outputs H_eff x leaves (in G * n blocks of n)
+int heff_parts(const sp_handle* h, int k) {
+    return (h->path == SP_PATH_TILED && h->plan[k - 1].h_rows == 0) ? h->G * h->plan[k - 1].tr_split : h->G;
 }
 
 // With defer_gsum on the tiled path only the per-quadrature-point partials
@@ -1782,7 +1835,7 @@ bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, boo
         else spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
     }
     if (defer_gsum) return true;
-    spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
+    spk::gsum2(s, h->ypart.p, h->nypart.p, n, heff_parts(h, k), n, y, ny);
     return false;
 }
 
@@ -2097,7 +2150,7 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
         } else {
             heff_apply(h, k, from_t ? h->dt.p : vm, nullptr, nullptr, true);
             spk::dav_gram(s, V, HV, NV, ld, mm, n, from_t ? h->dt.p : nullptr, sm + lay.pn, nch, tn, h->ypart.p,
-                          h->nypart.p, n, h->G, dn_dev + (lay.pg - lay.out));
+                          h->nypart.p, n, heff_parts(h, k), dn_dev + (lay.pg - lay.out));
         }
         // constrained pencil (Q H Q, Q N Q): the Gram rows above are the same
         // for the projected products, since every V_j is orthogonal to C
@@ -2492,7 +2545,7 @@ spk::DavInst dav_inst(BatchState& st) {
     I.ypart = h->ypart.p;
     I.nypart = h->nypart.p;
     I.gstride = st.n;
-    I.G = h->G;
+    I.G = heff_parts(h, st.k);
     I.m = st.m;
     I.mr = st.m;
     I.n = st.n;
@@ -2864,7 +2917,10 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         h->V_cap = h->G * std::max(1LL, Vmax);
         h->qr_scratch_cap = std::max(1LL, qrs);
         h->qr_r_cap = std::max(1LL, qrr);
-        for (int k = 1; k <= h->L; ++k) h->Xd_cap = std::max(h->Xd_cap, h->plan[k - 1].Xd_size);
+        for (int k = 1; k <= h->L; ++k) {
+            h->Xd_cap = std::max(h->Xd_cap, h->plan[k - 1].Xd_size);
+            h->tr_split_max = std::max(h->tr_split_max, h->plan[k - 1].tr_split);
+        }
         h->Xd_cap = std::max(1LL, h->Xd_cap);
         validate_plans(h.get());
         // every host-side check is done; device work starts here
@@ -2879,8 +2935,8 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         h->mps.alloc(h->mps_size);
         if (h->path == SP_PATH_TILED) {
             h->Xd.alloc(h->Xd_cap);
-            h->ypart.alloc(size_t(h->G) * h->max_site);
-            h->nypart.alloc(size_t(h->G) * h->max_site);
+            h->ypart.alloc(size_t(h->G) * h->tr_split_max * h->max_site);
+            h->nypart.alloc(size_t(h->G) * h->tr_split_max * h->max_site);
         }
         HIPCK(hipMemcpyAsync(h->mps.p, init_blocks, h->mps_size * sizeof(double), hipMemcpyHostToDevice, h->stream));
         // right-canonical form of sites L..2 and the right environments
@@ -3471,7 +3527,7 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
             if (plain) {
                 P.yout.launch(s, b, P.coef.p);
             } else {
-                spk::gsum2(s, h->ypart.p, h->nypart.p, n, h->G, n, y, ny);
+                spk::gsum2(s, h->ypart.p, h->nypart.p, n, heff_parts(h, site), n, y, ny);
             }
             HIPCK(hipEventRecord(ev[3], s));
             HIPCK(hipEventSynchronize(ev[3]));
