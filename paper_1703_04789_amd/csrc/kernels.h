@@ -75,10 +75,11 @@ struct TSeg {
     long long a_off, b_off;
     int a_buf, b_buf, lda, ldb, ta, tb, k0, k1, cidx, pad;
 };
-constexpr int kTile = 64;
+constexpr int kTile = 64;  // the wide tile; 32 is the narrow one
 
+// tile: 64 or 32 (the task grid of the list was built for that tile)
 void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
-           const int* map);
+           const int* map, int tile);
 // dst[e] = map[e] >= 0 ? src[map[e]] : 0, e < n
 void gather(hipStream_t s, const int* map, const double* src, double* dst, long long n);
 // out[e] = sum_{g < G} part[g*stride + e] in ascending g, for two arrays at once

@@ -387,19 +387,24 @@ __global__ __launch_bounds__(kThreads) void k_basis_rotate(const double* __restr
     }
 }
 
-// 64x64 output tile per work-group of 256 threads (16 x 16 threads, 4 x 4
-// outputs each, rows ty + 16 i and columns tx + 16 j); K staged through LDS
-// in chunks of 16 with coalesced global loads for either operand layout.
+// TILE x TILE output tile per work-group of (TILE/4)^2 threads, 4 x 4
+// outputs each (rows ty + TILE/4 i, columns tx + TILE/4 j); K staged
+// through LDS in chunks of 16 with coalesced global loads for either operand
+// layout.  TILE = 64 (256 threads) for wide particle-number blocks, 32 (64
+// threads) for narrow ones; every output sums its terms in the same order
+// for either tile.
 constexpr int kKC = 16;
 
-__global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ tasks,
-                                                      const TSeg* __restrict__ segs, BufSet bufs,
-                                                      const double* __restrict__ coef,
-                                                      const int* __restrict__ map) {
-    __shared__ double As[kKC][kTile + 1];
-    __shared__ double Bs[kKC][kTile + 1];
+template <int TILE>
+__global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* __restrict__ tasks,
+                                                                  const TSeg* __restrict__ segs, BufSet bufs,
+                                                                  const double* __restrict__ coef,
+                                                                  const int* __restrict__ map) {
+    constexpr int TPR = TILE / 4, NT = TPR * TPR;
+    __shared__ double As[kKC][TILE + 1];
+    __shared__ double Bs[kKC][TILE + 1];
     const TTask tk = tasks[blockIdx.x];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int tx = threadIdx.x % TPR, ty = threadIdx.x / TPR;
     double acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -411,14 +416,14 @@ __global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ ta
         const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
         const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
         for (int kb = sg.k0; kb < sg.k1; kb += kKC) {
-            for (int idx = threadIdx.x; idx < kTile * kKC; idx += kThreads) {
+            for (int idx = threadIdx.x; idx < TILE * kKC; idx += NT) {
                 int r, k;
                 if (sg.ta == 0) {
                     r = idx / kKC;
                     k = idx % kKC;
                 } else {
-                    k = idx / kTile;
-                    r = idx % kTile;
+                    k = idx / TILE;
+                    r = idx % TILE;
                 }
                 const int gr = tk.r0 + r, gk = kb + k;
                 double v = 0.0;
@@ -426,11 +431,11 @@ __global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ ta
                     v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
                 As[k][r] = cf * v;
             }
-            for (int idx = threadIdx.x; idx < kTile * kKC; idx += kThreads) {
+            for (int idx = threadIdx.x; idx < TILE * kKC; idx += NT) {
                 int c, k;
                 if (sg.tb == 0) {
-                    k = idx / kTile;
-                    c = idx % kTile;
+                    k = idx / TILE;
+                    c = idx % TILE;
                 } else {
                     c = idx / kKC;
                     k = idx % kKC;
@@ -446,9 +451,9 @@ __global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ ta
             for (int k = 0; k < kKC; ++k) {
                 double a[4], b[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
+                for (int i = 0; i < 4; ++i) a[i] = As[k][ty + TPR * i];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
+                for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + TPR * j];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -460,11 +465,11 @@ __global__ __launch_bounds__(kThreads) void k_tgemm(const TTask* __restrict__ ta
     double* C = bufs.p[tk.c_buf] + tk.c_off;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int r = tk.r0 + ty + 16 * i;
+        const int r = tk.r0 + ty + TPR * i;
         if (r >= tk.M) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int c = tk.c0 + tx + 16 * j;
+            const int c = tk.c0 + tx + TPR * j;
             if (c >= tk.N) continue;
             if (tk.mode == 0) {
                 C[(long long)r * tk.ldc + c] = acc[i][j];
@@ -1096,8 +1101,12 @@ inline int nblk(int n) { return (n + kThreads - 1) / kThreads; }
 }  // namespace
 
 void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
-           const int* map) {
-    if (ntasks > 0) hipLaunchKernelGGL(k_tgemm, dim3(ntasks), dim3(kThreads), 0, s, tasks, segs, bufs, coef, map);
+           const int* map, int tile) {
+    if (ntasks <= 0) return;
+    if (tile == 32)
+        hipLaunchKernelGGL(k_tgemm<32>, dim3(ntasks), dim3(64), 0, s, tasks, segs, bufs, coef, map);
+    else
+        hipLaunchKernelGGL(k_tgemm<64>, dim3(ntasks), dim3(256), 0, s, tasks, segs, bufs, coef, map);
 }
 template <typename T>
 static void launch_heff3(hipStream_t s, int RC, int lds_elems, const H3Task* tasks, int ntasks, const H3Inst& I,

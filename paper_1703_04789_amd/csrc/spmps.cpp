@@ -230,6 +230,7 @@ struct CList {
 struct TList {
     std::vector<spk::TTask> tasks;
     std::vector<spk::TSeg> segs;
+    int tile = spk::kTile;  // output tile of every task (64 or 32)
     DArr<spk::TTask> dtasks;
     DArr<spk::TSeg> dsegs;
     void add_task(int c_buf, long long c_off, int ldc, int M, int N, int r0, int c0, int mode, long long pack_off) {
@@ -268,7 +269,7 @@ struct TList {
         dsegs.upload(segs, s);
     }
     void launch(hipStream_t s, const spk::BufSet& b, const double* coef, const int* map) const {
-        spk::tgemm(s, dtasks.p, int(tasks.size()), dsegs.p, b, coef, map);
+        spk::tgemm(s, dtasks.p, int(tasks.size()), dsegs.p, b, coef, map, tile);
     }
 };
 
@@ -1067,7 +1068,19 @@ void build_plan(sp_handle* h, int k) {
         }
         return k1 > k0;
     };
-    const int TT = spk::kTile;
+    // output tile of the site's lists: 32 when the particle-number blocks of
+    // both bonds are narrow (dimension-weighted mean <= 32), else 64
+    int TT = spk::kTile;
+    {
+        double wsum = 0.0, dsum = 0.0;
+        for (const Bond* bd : {&bl, &br})
+            for (const NBlock& nb : bd->nb) {
+                wsum += double(nb.dim) * nb.dim;
+                dsum += nb.dim;
+            }
+        if (dsum > 0 && wsum / dsum <= 32.0) TT = 32;
+    }
+    for (TList* tl : {&P.t_left, &P.t_right, &P.t_envl, &P.t_zr, &P.t_envr}) tl->tile = TT;
     // left product: T(eb, sigma') = L_g(eb) Xd(j, sigma', jb)
     for (int g = 0; g < G; ++g)
         for (size_t e = 0; e < el.blk.size(); ++e)
@@ -1546,7 +1559,8 @@ void validate(const CList& b, const Sizes& sz, long long ncoef, const char* what
 
 void validate(const TList& b, const Sizes& sz, long long ncoef, long long map_size, long long packed_max,
               const char* what) {
-    const int TT = spk::kTile;
+    const int TT = b.tile;
+    if (TT != 32 && TT != 64) throw SpError(SP_EINVAL, std::string("internal tile size: ") + what);
     for (const spk::TTask& t : b.tasks) {
         if (t.r0 < 0 || t.c0 < 0 || t.r0 >= t.M || t.c0 >= t.N) throw SpError(SP_EINVAL, std::string("internal tile: ") + what);
         const int rl = std::min(t.M, t.r0 + TT) - 1, cl = std::min(t.N, t.c0 + TT) - 1;
