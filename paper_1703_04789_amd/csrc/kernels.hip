@@ -94,15 +94,42 @@ __global__ __launch_bounds__(kThreads) void k_bgemm(const BTask* __restrict__ ta
 __global__ __launch_bounds__(kThreads) void k_combine(const CTask* __restrict__ tasks,
                                                         const CTerm* __restrict__ terms,
                                                         BufSet bufs, const double* __restrict__ coef) {
+    // the task's terms (source pointer, coefficient) are staged in LDS by one
+    // thread each, 64 at a time, so that the element loop issues independent
+    // loads; every element still sums its terms in list order
+    constexpr int kTermsAtOnce = 64, kPer = 4;
+    __shared__ const double* sp[kTermsAtOnce];
+    __shared__ double sc[kTermsAtOnce];
     const CTask tk = tasks[blockIdx.x];
     double* C = bufs.p[tk.c_buf] + tk.c_off;
-    for (int e = threadIdx.x; e < tk.n; e += kThreads) {
-        double acc = 0.0;
-        for (int t = tk.t0; t < tk.t1; ++t) {
-            const CTerm tm = terms[t];
-            acc = fma(coef[tm.cidx], bufs.p[tm.a_buf][tm.a_off + e], acc);
+    for (int eb = 0; eb < tk.n; eb += kPer * kThreads) {
+        double acc[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) acc[u] = 0.0;
+        for (int tb = tk.t0; tb < tk.t1; tb += kTermsAtOnce) {
+            const int nt = min(kTermsAtOnce, tk.t1 - tb);
+            __syncthreads();
+            if ((int)threadIdx.x < nt) {
+                const CTerm tm = terms[tb + threadIdx.x];
+                sp[threadIdx.x] = bufs.p[tm.a_buf] + tm.a_off;
+                sc[threadIdx.x] = coef[tm.cidx];
+            }
+            __syncthreads();
+            for (int t = 0; t < nt; ++t) {
+                const double* __restrict__ a = sp[t];
+                const double c = sc[t];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    const int e = eb + threadIdx.x + u * kThreads;
+                    if (e < tk.n) acc[u] = fma(c, a[e], acc[u]);
+                }
+            }
         }
-        C[e] = acc;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = eb + threadIdx.x + u * kThreads;
+            if (e < tk.n) C[e] = acc[u];
+        }
     }
 }
 
