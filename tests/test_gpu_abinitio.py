@@ -206,3 +206,30 @@ def test_abinitio_batched_sweeps_match_single():
     for r, g in zip(ref, got):
         assert len(r) == len(g)
         assert max(abs(a["theta"] - b["theta"]) for a, b in zip(r, g)) < 1e-10
+
+
+def test_abinitio_fp32_products_on_fused_and_tiled_sites():
+    # K = 12, D = 128: with SP_FP32 the fused sites use FP32 environments and
+    # the sites on the tiled block products stay FP64
+    wl = W.abinitio_reduced(12, 128, 11)
+    mine = sp.mpo_abinitio(*wl.integrals())
+    tab, blocks = wl.table(), wl.blocks()
+    print(f"[case] {wl.name} fp32 vs fp64", flush=True)
+    a = sp.SPMPS(tab, blocks, mine, wl.twoS, wl.G, precision="fp32")
+    b = sp.SPMPS(tab, blocks, mine, wl.twoS, wl.G)
+    rng = np.random.default_rng(8)
+    seen = set()
+    for k in range(1, wl.K // 2 + 1):
+        if k > 1:
+            a.env_update(k - 1, +1)
+            b.env_update(k - 1, +1)
+        fused = a.heff_plan(k)[0] > 0
+        xd = _dev(rng.standard_normal(a.site_size(k)))
+        ya, nya, yb, nyb = (torch.empty_like(xd) for _ in range(4))
+        a.heff_apply(k, xd, ya, nya)
+        b.heff_apply(k, xd, yb, nyb)
+        torch.cuda.synchronize()
+        e = max(rel_err(ya.cpu().numpy(), yb.cpu().numpy()), rel_err(nya.cpu().numpy(), nyb.cpu().numpy()))
+        assert e < (1e-5 if fused else 1e-12), (k, fused, e)
+        seen.add(fused)
+    assert seen == {True, False}

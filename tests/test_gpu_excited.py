@@ -93,3 +93,24 @@ def test_constraints_reject_mismatched_states_and_batches():
     s2.clear_orthogonality()
     rc, st = sp.sweep_batch([s2, s0], 1)
     assert len(st) == 2
+
+
+def test_abinitio_first_excited_state_at_full_bond_dimension():
+    K, N, twoS = 4, 4, 0
+    h, eri = W.abinitio_integrals(K, seed=4)
+    st = ed.sector_states(K, N, 0)
+    H = ed.abinitio_hamiltonian(h, eri, st).toarray()
+    ev, vec = np.linalg.eigh(ed.s2_operator(K, st).toarray())
+    Z = vec[:, np.abs(ev) < 1e-8]
+    ref = np.linalg.eigvalsh(Z.T @ H @ Z)[:2]
+    G = oq.exact_point_count(N, K, twoS)
+    tab = W.make_block_table(K, N, 0, 16)
+    mpo = sp.mpo_abinitio(h, eri)
+    print("[case] ab-initio excited K=4", flush=True)
+    s0 = sp.SPMPS(tab, W.random_blocks(tab, 1), mpo, twoS, G)
+    s0.sweep(3, max_sub=128, max_iter=200)
+    s1 = sp.SPMPS(tab, W.random_blocks(tab, 2), mpo, twoS, G)
+    s1.add_orthogonality(s0)
+    rc, steps = s1.sweep(4, max_sub=128, max_iter=200)
+    assert abs(steps[-1]["theta"] - ref[1]) < 1e-9, (steps[-1]["theta"], ref)
+    assert abs(s1.orthogonality_overlaps()[0]) < 1e-10
