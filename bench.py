@@ -244,6 +244,8 @@ def main():
                     help="skip the batched-states run (8 broken-symmetry Hubbard guesses)")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the learned-preconditioner training and evaluation")
+    ap.add_argument("--heff-workload", default="hubbard", choices=["hubbard", "abinitio"],
+                    help="state of the --heff-only run: the benchmark Hubbard chain or the ab-initio workload")
     ap.add_argument("--heff-only", type=int, default=0,
                     help="only run this many H_eff x applications at the centre site, after a 64 MiB "
                          "device copy of known size (for hardware-counter runs), and exit")
@@ -271,8 +273,14 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=args.path,
-                       precision=args.precision)
+        if args.heff_workload == "abinitio":
+            aw = W.abinitio_reduced(12, 128, 11)
+            gpu = sp.SPMPS(aw.table(), aw.blocks(), sp.mpo_abinitio(*aw.integrals()), aw.twoS, aw.G, path=args.path,
+                           precision=args.precision)
+            kc = aw.K // 2
+        else:
+            gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=args.path,
+                           precision=args.precision)
         for j in range(1, kc):
             gpu.env_update(j, +1)
         x = torch.tensor(gpu.get_site(kc), dtype=torch.float64, device="cuda")
