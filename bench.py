@@ -148,6 +148,19 @@ def batch_runs(sp, W, torch, n=8):
     tb = time.perf_counter() - t0
     nsteps = sum(len(x) for x in st)
     eb = [x[-1]["theta"] for x in st]
+    # one batched fused H_eff launch over every state at its centre site,
+    # against the same products launched state by state
+    sites = [w.L // 2 for w in ws]
+    single_us = 0.0
+    for h, k in zip(hs, sites):
+        for j in range(1, k):
+            h.env_update(j, +1)
+        x = torch.tensor(h.get_site(k), dtype=torch.float64, device="cuda")
+        y, ny = torch.empty_like(x), torch.empty_like(x)
+        single_us += 1e3 * h.heff_profile(k, x, y, ny, reps=20)["fused_heff"]["ms"]
+    bp = sp.heff_batch_profile(hs, sites, reps=20)
+    log(f"[bench] batched H_eff launch: {bp['usec']:.1f} us for {len(hs)} states ({bp['flops'] / bp['usec'] / 1e6:.2f} "
+        f"TFLOP/s), {single_us:.1f} us one state at a time")
     for h in hs:
         h.close()
     log(f"[bench] batch of {n}: one after another")
@@ -164,7 +177,14 @@ def batch_runs(sp, W, torch, n=8):
     log(f"[bench] batch of {n}: {nsteps / tb:.1f} vs {nsteps / ts:.1f} site steps/s")
     return {"workload": f"hubbard_batch n={n} D<=256", "states": [w.name for w in ws], "site_steps": nsteps,
             "unit": "site steps/s", "batched": nsteps / tb, "one_after_another": nsteps / ts,
-            "speedup": ts / tb, "max_energy_diff": max(abs(a - b) for a, b in zip(eb, es))}
+            "speedup": ts / tb, "max_energy_diff": max(abs(a - b) for a, b in zip(eb, es)),
+            "batched_heff": {"sites": sites, "usec": bp["usec"], "flops": bp["flops"], "bytes": bp["bytes"],
+                             "workgroups": bp["workgroups"],
+                             "tflops": bp["flops"] / (bp["usec"] * 1e-6) / 1e12,
+                             "frac_fp64_peak": bp["flops"] / (bp["usec"] * 1e-6) / 1e12 / PEAK_FP64_TFLOPS,
+                             "gbs": bp["bytes"] / (bp["usec"] * 1e-6) / 1e9,
+                             "frac_hbm_peak": bp["bytes"] / (bp["usec"] * 1e-6) / 1e9 / PEAK_HBM_GBS,
+                             "usec_one_state_at_a_time": single_us}}
 
 
 def precond_runs(sp, W, torch):

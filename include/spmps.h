@@ -312,6 +312,16 @@ int sp_heff_flops(const sp_handle* h, int site, double* flops);
  * sp_heff_apply.  Synchronises. */
 int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y, double* ny, double* out);
 
+/* Timing of one batched fused H_eff launch (as sp_sweep_batch issues it):
+ * every state i at site sites[i] (tiled path, fused plan, environments
+ * built), all quadrature points, x = the site tensors themselves; per-g
+ * partial outputs land in each state's scratch.  out[0]: mean microseconds
+ * over `reps` launches (HIP events on the states' stream), out[1]: summed
+ * algorithmic flops, out[2]: summed algorithmic bytes (environments and x
+ * read once, partials written), out[3]: work-groups per launch.  All states
+ * on one device, stream and precision, each listed once.  Synchronises. */
+int sp_heff_batch_profile(sp_handle** hs, int n, const int* sites, int reps, double* out);
+
 /* Message of the last error on this thread. */
 const char* sp_last_error(void);
 

@@ -32,7 +32,7 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_mpo_abinitio", "sp_set_heff_plan", "sp_heff_plan", "sp_add_orthogonality",
            "sp_clear_orthogonality", "sp_orthogonality_overlaps", "sp_mlp_create", "sp_mlp_destroy",
            "sp_mlp_get", "sp_mlp_dataset", "sp_mlp_forward", "sp_mlp_train_step", "sp_mlp_train",
-           "sp_set_precond"]
+           "sp_set_precond", "sp_heff_batch_profile"]
 
 
 class SpError(RuntimeError):
@@ -112,6 +112,7 @@ def lib():
         "sp_mlp_train_step": [vp, vp, vp, ctypes.c_longlong, ctypes.c_double, dp, vp],
         "sp_mlp_train": [vp, ctypes.c_int, ctypes.c_longlong, ctypes.c_double, dp, vp],
         "sp_set_precond": [vp, vp, vp],
+        "sp_heff_batch_profile": [P(vp), ctypes.c_int, ip, ctypes.c_int, dp],
         "sp_mpo_site_op": [ctypes.c_int, ctypes.c_int, dp, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_epq": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_spin_corr": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
@@ -232,6 +233,16 @@ def mpo_abinitio(h, eri):
     if h.shape != (K, K) or eri.shape != (K, K, K, K):
         raise ValueError("h must be K x K and eri K x K x K x K")
     return _mpo(lib().sp_mpo_abinitio, K, _dptr(h), _dptr(eri))
+
+
+def heff_batch_profile(states, sites, reps=20):
+    """One batched fused H_eff launch over the states at the given sites:
+    dict(usec, flops, bytes, workgroups)."""
+    hs = (ctypes.c_void_p * len(states))(*[st._h.value for st in states])
+    ks = np.ascontiguousarray(sites, dtype=np.int32)
+    out = np.zeros(4)
+    _check(lib().sp_heff_batch_profile(hs, len(states), _iptr(ks), reps, _dptr(out)))
+    return {"usec": out[0], "flops": out[1], "bytes": out[2], "workgroups": int(out[3])}
 
 
 def small_eigh(a):

@@ -3514,6 +3514,77 @@ int sp_heff_flops(const sp_handle* h, int site, double* flops) {
     });
 }
 
+int sp_heff_batch_profile(sp_handle** hs, int n, const int* sites, int reps, double* out) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(hs && sites && out && n >= 1 && reps >= 1, "bad arguments");
+        hipStream_t s = hs[0]->stream;
+        std::vector<spk::H3Inst> insts(n);
+        std::map<int, std::vector<spk::H3Task>> by_rc;
+        std::map<int, int> lds_by_rc;
+        double flops = 0.0, bytes = 0.0;
+        for (int i = 0; i < n; ++i) {
+            sp_handle* h = hs[i];
+            SP_REQUIRE(h, "null handle");
+            check_site(h, sites[i]);
+            const int k = sites[i];
+            SP_REQUIRE(h->path == SP_PATH_TILED && h->plan[k - 1].h_rows > 0, "every site must have a fused plan");
+            SP_REQUIRE(h->stream == s && h->device == hs[0]->device && h->precision == hs[0]->precision,
+                       "one device, stream and precision");
+            SP_REQUIRE(h->Lvalid[k - 1] && h->Rvalid[k], "environments are not built");
+            for (int j = 0; j < i; ++j) SP_REQUIRE(hs[j] != h, "a handle appears twice");
+            insts[i] = heff_inst(h, k, site_ptr(h, k), h->precision == SP_FP32);
+            const SitePlan& P = h->plan[k - 1];
+            for (spk::H3Task t : P.h_tasks) {
+                if (t.blk < 0) continue;
+                t.inst = i;
+                by_rc[P.h_rows].push_back(t);
+            }
+            lds_by_rc[P.h_rows] = std::max(lds_by_rc[P.h_rows], P.h_lds);
+            flops += P.heff_flops;
+            const double G = h->G, xs = double(h->sites[k - 1].size);
+            bytes += 8.0 * (G * h->env[k - 1].size + G * h->env[k].size + xs + 2.0 * G * xs);
+        }
+        std::vector<spk::H3Task> all;
+        std::vector<std::pair<int, std::pair<size_t, int>>> groups;  // rc -> (first, count)
+        for (auto& kv : by_rc) {
+            groups.push_back({kv.first, {all.size(), int(kv.second.size())}});
+            all.insert(all.end(), kv.second.begin(), kv.second.end());
+        }
+        DArr<spk::H3Inst> dinst;
+        DArr<spk::H3Task> dtask;
+        dinst.upload(insts, s);
+        dtask.upload(all, s);
+        HIPCK(hipStreamSynchronize(s));
+        const bool f32 = hs[0]->precision == SP_FP32;
+        auto launch = [&]() {
+            for (auto& gr : groups) {
+                const int rc = gr.first;
+                const spk::H3Task* tp = dtask.p + gr.second.first;
+                if (f32) spk::heff3_f32(s, rc, lds_by_rc[rc], tp, gr.second.second, insts[0], dinst.p);
+                else spk::heff3(s, rc, lds_by_rc[rc], tp, gr.second.second, insts[0], dinst.p);
+            }
+        };
+        launch();  // warm-up
+        hipEvent_t e0, e1;
+        HIPCK(hipEventCreate(&e0));
+        HIPCK(hipEventCreate(&e1));
+        HIPCK(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch();
+        HIPCK(hipEventRecord(e1, s));
+        HIPCK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCK(hipGetLastError());
+        out[0] = 1e3 * double(ms) / reps;
+        out[1] = flops;
+        out[2] = bytes;
+        out[3] = double(all.size());
+        return SP_OK;
+    });
+}
+
 int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y, double* ny, double* out) {
     return guarded([&]() -> int {
         SP_REQUIRE(h && x && y && ny && out && reps >= 1, "bad arguments");

@@ -83,3 +83,17 @@ def test_batch_rejects_bad_input():
     d = _handles(CASES[:1], path="plain")[0]
     with pytest.raises(sp.SpError):
         sp.sweep_batch([b, d], 1)
+
+
+def test_batched_heff_profile_reports_the_summed_work():
+    ws = W.hubbard_batch(6, D_choices=(64, 128))[:3]
+    hs = [sp.SPMPS(w.table(), w.blocks(), sp.mpo_hubbard(w.L, w.t, w.U), w.twoS, w.G) for w in ws]
+    sites = [w.L // 2 for w in ws]
+    for h, k in zip(hs, sites):
+        for j in range(1, k):
+            h.env_update(j, +1)
+    out = sp.heff_batch_profile(hs, sites, reps=3)
+    assert out["usec"] > 0 and out["workgroups"] > 0
+    assert abs(out["flops"] - sum(h.heff_flops(k) for h, k in zip(hs, sites))) < 1.0
+    with pytest.raises(sp.SpError):
+        sp.heff_batch_profile([hs[0], hs[0]], [sites[0], sites[0]])
