@@ -28,10 +28,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def measured_traffic(rows):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     summary (FETCH_SIZE and WRITE_SIZE, calibrated on a 64 MiB copy), or None
-    when the kernel source has changed since those counters were taken."""
+    when the kernel source has changed since those counters were taken or
+    the counters were taken on another plan (rows per task) of the site."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "heff_hubbard_L32_D256_G9_fused_fp64_hbm_traffic.md")
@@ -43,7 +44,8 @@ def measured_traffic():
         return None
     m_b = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
     m_h = re.search(r"kernels.hip sha256: ([0-9a-f]+)", txt)
-    if not m_b or not m_h or m_h.group(1) != now:
+    m_r = re.search(r"rows_per_task: (\d+)", txt)
+    if not m_b or not m_h or m_h.group(1) != now or not m_r or int(m_r.group(1)) != rows:
         return None
     return float(m_b.group(1))
 
@@ -251,6 +253,8 @@ def main():
     ap.add_argument("--keep", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default fused-kernel plans instead of timing them per site (sp_autotune)")
     ap.add_argument("--path", default="tiled", choices=["tiled", "plain"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the H_eff products inside the local solves (SP_FP64 / SP_FP32)")
@@ -301,6 +305,8 @@ def main():
         else:
             gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=args.path,
                            precision=args.precision)
+        if args.path == "tiled" and not args.no_autotune:
+            gpu.autotune(reps=5)
         for j in range(1, kc):
             gpu.env_update(j, +1)
         x = torch.tensor(gpu.get_site(kc), dtype=torch.float64, device="cuda")
@@ -309,7 +315,7 @@ def main():
             gpu.heff_apply(kc, x, y, ny)
         torch.cuda.synchronize()
         log(f"[bench] {args.heff_only} H_eff x applications at site {kc} ({args.path}); "
-            f"site size {x.numel()}, algorithmic flops {gpu.heff_flops(kc):.4e}")
+            f"site size {x.numel()}, algorithmic flops {gpu.heff_flops(kc):.4e}, plan {gpu.heff_plan(kc)}")
         gpu.close()
         return
 
@@ -317,6 +323,10 @@ def main():
         log(f"[bench] {wl.name} path={path} {precision}: init")
         gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=path,
                        precision=precision)
+        tuned = None
+        if path == "tiled" and not args.no_autotune:
+            # the fused kernel's LDS budget (rows per task) of every site, by timing
+            tuned = gpu.autotune(reps=5)
         kw = dict(tol=tol, max_iter=args.max_iter, max_sub=args.max_sub, keep=args.keep)
         for i in range(args.warmup):
             rc, st = gpu.sweep(1, **kw)
@@ -338,11 +348,12 @@ def main():
         prof = gpu.heff_profile(kc, x, y, ny, reps=50)
         heff_ms = sum(p["ms"] for p in prof.values())
         heff_flops = gpu.heff_flops(kc)
+        plan = gpu.heff_plan(kc) if path == "tiled" else (0, 0)
         gpu.close()
         log(f"[bench] {path}: {len(steps) / (t1 - t0):.2f} site steps/s; H_eff x at site {kc}: {heff_ms:.3f} ms; "
             + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in prof.items()))
         return dict(steps=steps, elapsed=t1 - t0, prof=prof, heff_ms=heff_ms, heff_flops=heff_flops,
-                    heff_tflops=heff_flops / (heff_ms * 1e-3) / 1e12)
+                    heff_tflops=heff_flops / (heff_ms * 1e-3) / 1e12, plan=plan, tuned=tuned)
 
     main_run = run(args.path)
     steps, elapsed, prof = main_run["steps"], main_run["elapsed"], main_run["prof"]
@@ -389,8 +400,9 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
     roof["kernel"] = f"{'k_bgemm' if args.path == 'plain' else 'k_heff3'} ({dom_name}) at site {kc}"
+    roof["plan"] = {"rows_per_task": main_run["plan"][0], "lds_doubles": main_run["plan"][1]}
     if args.path == "tiled" and dom_name == "fused_heff":
-        roof["traffic"] = measured_traffic()
+        roof["traffic"] = measured_traffic(main_run["plan"][0])
         roof["traffic_unit"] = "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
     roof["per_launch"] = {k: {"ms": v["ms"], "flops": v["flops"], "bytes": v["bytes"]} for k, v in prof.items()}
 
@@ -410,7 +422,9 @@ def main():
         "config": {"workload": wl.name, "L": wl.L, "t": wl.t, "U": wl.U, "N": wl.N, "twoS": wl.twoS,
                    "twoM": wl.twoM, "D": wl.D, "G": wl.G, "seed": wl.seed, "path": f"{args.path} FP64",
                    "davidson": {"tol": args.tol, "max_iter": args.max_iter, "max_sub": args.max_sub,
-                                "keep": args.keep}},
+                                "keep": args.keep},
+                   "fused_plans": "autotuned per site (sp_autotune, 5 repetitions per LDS budget)"
+                   if main_run["tuned"] is not None else "default LDS budget"},
         "site_steps": n_site_steps,
         "matvecs_per_site_step": mv,
         "energy_after_timed_sweeps": energy,
