@@ -544,26 +544,70 @@ __global__ __launch_bounds__(kH3Threads) void k_heff3(const H3Task* __restrict__
     }
     __syncthreads();
 
-    // phase A: T columns
+    // phase A: T columns, two neighbours per thread; neighbours reading the
+    // same x column (the plan sorts them together) load it once
     const int c0 = bp->c0, c1 = bp->c1;
-    for (int ci = c0 + tid; ci < c1; ci += kH3Threads) {
-        const H3Col c = cols[ci];
+    for (int ci = c0 + 2 * tid; ci + 1 < c1; ci += 2 * kH3Threads) {
+        const H3Col ca = cols[ci], cb = cols[ci + 1];
+        if (ca.K == 0 || ca.x_off != cb.x_off || ca.x_ld != cb.x_ld || ca.K != cb.K) {
+            for (int h = 0; h < 2; ++h) {
+                const H3Col c = h ? cb : ca;
+                T acc[RC];
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr) acc[rr] = T(0);
+                const double* __restrict__ xp = x + c.x_off;
+                const T* lp = lds + c.l_lds;
+                for (int kk = 0; kk < c.K; ++kk) {
+                    const T xv = T(xp[kk * c.x_ld]);
+#pragma unroll
+                    for (int rr = 0; rr < RC; ++rr) acc[rr] = fma(lp[rr * c.l_ld + kk], xv, acc[rr]);
+                }
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr) lds[c.t_pos + rr] = acc[rr];
+            }
+            continue;
+        }
+        T aa[RC], ab[RC];
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr) aa[rr] = ab[rr] = T(0);
+        const double* __restrict__ xp = x + ca.x_off;
+        const T* la = lds + ca.l_lds;
+        const T* lb = lds + cb.l_lds;
+        int kk = 0;
+        for (; kk + 4 <= ca.K; kk += 4) {
+            const T x0 = T(xp[kk * ca.x_ld]), x1 = T(xp[(kk + 1) * ca.x_ld]);
+            const T x2 = T(xp[(kk + 2) * ca.x_ld]), x3 = T(xp[(kk + 3) * ca.x_ld]);
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr) {
+                const T* l = la + rr * ca.l_ld + kk;
+                aa[rr] = fma(l[3], x3, fma(l[2], x2, fma(l[1], x1, fma(l[0], x0, aa[rr]))));
+                const T* m = lb + rr * cb.l_ld + kk;
+                ab[rr] = fma(m[3], x3, fma(m[2], x2, fma(m[1], x1, fma(m[0], x0, ab[rr]))));
+            }
+        }
+        for (; kk < ca.K; ++kk) {
+            const T xv = T(xp[kk * ca.x_ld]);
+#pragma unroll
+            for (int rr = 0; rr < RC; ++rr) {
+                aa[rr] = fma(la[rr * ca.l_ld + kk], xv, aa[rr]);
+                ab[rr] = fma(lb[rr * cb.l_ld + kk], xv, ab[rr]);
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr) {
+            lds[ca.t_pos + rr] = aa[rr];
+            lds[cb.t_pos + rr] = ab[rr];
+        }
+    }
+    // an odd count leaves the last column to one thread
+    if (((c1 - c0) & 1) && tid == kH3Threads - 1) {
+        const H3Col c = cols[c1 - 1];
         T acc[RC];
 #pragma unroll
         for (int rr = 0; rr < RC; ++rr) acc[rr] = T(0);
         const double* __restrict__ xp = x + c.x_off;
         const T* lp = lds + c.l_lds;
-        int kk = 0;
-        for (; kk + 4 <= c.K; kk += 4) {
-            const T x0 = T(xp[kk * c.x_ld]), x1 = T(xp[(kk + 1) * c.x_ld]);
-            const T x2 = T(xp[(kk + 2) * c.x_ld]), x3 = T(xp[(kk + 3) * c.x_ld]);
-#pragma unroll
-            for (int rr = 0; rr < RC; ++rr) {
-                const T* l = lp + rr * c.l_ld + kk;
-                acc[rr] = fma(l[3], x3, fma(l[2], x2, fma(l[1], x1, fma(l[0], x0, acc[rr]))));
-            }
-        }
-        for (; kk < c.K; ++kk) {
+        for (int kk = 0; kk < c.K; ++kk) {
             const T xv = T(xp[kk * c.x_ld]);
 #pragma unroll
             for (int rr = 0; rr < RC; ++rr) acc[rr] = fma(lp[rr * c.l_ld + kk], xv, acc[rr]);

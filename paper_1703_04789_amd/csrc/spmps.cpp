@@ -1390,6 +1390,14 @@ bool build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
             pos += RC * D.T[t].ncol;
         }
         B.c1 = int(P.h_cols.size());
+        // columns that read the same x column (channels with the same ket
+        // block) next to each other: the kernel pairs neighbours and loads a
+        // shared x column once; empty columns last
+        std::stable_sort(P.h_cols.begin() + B.c0, P.h_cols.begin() + B.c1,
+                         [](const spk::H3Col& a, const spk::H3Col& b) {
+                             if ((a.K == 0) != (b.K == 0)) return b.K == 0;
+                             return std::tie(a.x_off, a.x_ld, a.K) < std::tie(b.x_off, b.x_ld, b.K);
+                         });
         const int vbase = pos;
         for (int sig = 0; sig < 4; ++sig) {
             B.s0[sig] = int(P.h_segs.size());
