@@ -276,7 +276,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the SP-MPS path here is single-GPU "
-              "(sharding over quadrature points is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding over quadrature points is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
