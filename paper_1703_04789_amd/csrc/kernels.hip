@@ -414,29 +414,37 @@ __global__ __launch_bounds__(kThreads) void k_basis_rotate(const double* __restr
     }
 }
 
-// TILE x TILE output tile per work-group of (TILE/4)^2 threads, 4 x 4
-// outputs each (rows ty + TILE/4 i, columns tx + TILE/4 j); K staged
-// through LDS in chunks of 16 with coalesced global loads for either operand
-// layout.  TILE = 64 (256 threads) for wide particle-number blocks, 32 (64
-// threads) for narrow ones; every output sums its terms in the same order
-// for either tile.
+// TILE x TILE output tile per work-group of (TILE/4)^2 threads, i.e.
+// (TILE/32)^2 wavefronts; each wavefront owns a 32 x 32 quarter (TILE = 64)
+// or the whole tile (TILE = 32) as 2 x 2 FP64 matrix-core blocks of 16 x 16
+// (v_mfma_f64_16x16x4: lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16)
+// of a 16 x 4 by 4 x 16 step and holds D(4 v + l / 16, l % 16), v < 4).  K is
+// staged through LDS in chunks of 16 with coalesced global loads for either
+// operand layout, zero-padded past the segment and the tile edge.  TILE = 64
+// (256 threads) for wide particle-number blocks, 32 (64 threads) for narrow
+// ones; every output accumulates the same sequence of 4-deep matrix-core
+// steps for either tile, so both tiles give the same bits.
 constexpr int kKC = 16;
+typedef double d4_t __attribute__((ext_vector_type(4)));
 
 template <int TILE>
 __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* __restrict__ tasks,
                                                                   const TSeg* __restrict__ segs, BufSet bufs,
                                                                   const double* __restrict__ coef,
                                                                   const int* __restrict__ map) {
-    constexpr int TPR = TILE / 4, NT = TPR * TPR;
+    constexpr int NT = (TILE / 4) * (TILE / 4), WPR = TILE / 32;
+    static_assert(NT == 64 * WPR * WPR, "one wavefront per 32 x 32 quarter");
     __shared__ double As[kKC][TILE + 1];
     __shared__ double Bs[kKC][TILE + 1];
     const TTask tk = tasks[blockIdx.x];
-    const int tx = threadIdx.x % TPR, ty = threadIdx.x / TPR;
-    double acc[4][4];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wr = (wave / WPR) * 32, wc = (wave % WPR) * 32;
+    const int li = lane % 16, lk = lane / 16;
+    d4_t acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
     for (int s = tk.s0; s < tk.s1; ++s) {
         const TSeg sg = segs[s];
         const double cf = coef[sg.cidx];
@@ -475,34 +483,34 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
             }
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < kKC; ++k) {
-                double a[4], b[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) a[i] = As[k][ty + TPR * i];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + TPR * j];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+            for (int ks = 0; ks < kKC; ks += 4) {
+                const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
+                const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
             }
             __syncthreads();
         }
     }
     double* C = bufs.p[tk.c_buf] + tk.c_off;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = tk.r0 + ty + TPR * i;
-        if (r >= tk.M) continue;
+    for (int i = 0; i < 2; ++i) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = tk.c0 + tx + TPR * j;
-            if (c >= tk.N) continue;
-            if (tk.mode == 0) {
-                C[(long long)r * tk.ldc + c] = acc[i][j];
-            } else {
-                const int p = map[tk.pack_off + (long long)r * tk.N + c];
-                if (p >= 0) C[p] = acc[i][j];
+        for (int v = 0; v < 4; ++v) {
+            const int r = tk.r0 + wr + 16 * i + 4 * v + lk;
+            if (r >= tk.M) continue;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int c = tk.c0 + wc + 16 * j + li;
+                if (c >= tk.N) continue;
+                if (tk.mode == 0) {
+                    C[(long long)r * tk.ldc + c] = acc[i][j][v];
+                } else {
+                    const int p = map[tk.pack_off + (long long)r * tk.N + c];
+                    if (p >= 0) C[p] = acc[i][j][v];
+                }
             }
         }
     }
