@@ -5,7 +5,7 @@
 
 namespace spk {
 
-constexpr int kMaxBufs = 9;
+constexpr int kMaxBufs = 10;
 
 // One output block C (M x N, row stride ldc) = sum over terms of
 // coef[cidx] * A(M x K) B(K x N); accumulate != 0 adds to C.  A term with

@@ -276,7 +276,7 @@ struct TList {
 // buffer slots of a launch; B_BRA is the site tensor on the bra side of the
 // plain-path environment updates (the same as B_X except for the mixed
 // environments of an orthogonality constraint)
-enum Buf { B_ENVL = 0, B_ENVR = 1, B_X = 2, B_T = 3, B_V = 4, B_Y = 5, B_NY = 6, B_OUT = 7, B_BRA = 8 };
+enum Buf { B_ENVL = 0, B_ENVR = 1, B_X = 2, B_T = 3, B_V = 4, B_Y = 5, B_NY = 6, B_OUT = 7, B_BRA = 8, B_LT = 9 };
 
 struct SitePlan {
     // coefficient table [G][nc]
@@ -315,6 +315,13 @@ struct SitePlan {
     std::vector<int> xmap_h;  // dense element -> packed index or -1
     DArr<int> xmap;
     TList t_left, t_right, t_envl, t_zr, t_envr;
+    // H_eff x of the tiled block products from the pre-mixed left
+    // environment Lt(sigma, c', sigma', i) = sum_c W~_g[c, c', sigma, sigma'] L_g(c, i)
+    // (premix, once per local problem), V = sum_sigma' Lt Xd(sigma') (t_leftv)
+    // and the identity-channel products T(0, i, sigma') for N_eff (t_left0)
+    CList premix;
+    TList t_leftv, t_left0;
+    long long LTsize = 0;
     int tr_split = 1;  // channel chunks of the tiled right product (partials: tr_split * G)
     // fused H_eff x
     int h_rows = 0;         // rows per task (RC); 0: no fused plan
@@ -359,6 +366,13 @@ struct sp_handle {
     std::vector<SitePlan> plan;            // index k-1
     int path = SP_PATH_TILED;
     DArr<double> T, V, qr_scratch, qr_r, tmp_site, Xd, ypart, nypart;
+    // pre-mixed left environment of one site (tiled block products); valid
+    // for site lt_site while the generation of L[lt_site - 1] is lt_gen
+    DArr<double> LT;
+    long long LT_cap = 0;
+    std::vector<long long> Lgen;
+    int lt_site = -1;
+    long long lt_gen = -1;
     long long Xd_cap = 0;
     int tr_split_max = 1;  // partial slots per quadrature point (tiled lists)
     long long T_cap = 0, V_cap = 0, qr_scratch_cap = 0, qr_r_cap = 0;
@@ -570,6 +584,7 @@ void build_env_layouts(sp_handle* h) {
     SP_REQUIRE(h->env[0].size == 1 && h->env[L].size == 1, "boundary environments must be 1x1");
     h->Lvalid.assign(L + 1, 0);
     h->Rvalid.assign(L + 1, 0);
+    h->Lgen.assign(L + 1, 0);
 }
 
 void alloc_envs(sp_handle* h) {
@@ -597,6 +612,7 @@ void alloc_envs(sp_handle* h) {
     HIPCK(hipStreamSynchronize(h->stream));
     h->Lvalid[0] = 1;
     h->Rvalid[L] = 1;
+    ++h->Lgen[0];
 }
 
 // rotated MPO W[k] r(beta_g): pattern and values
@@ -691,7 +707,7 @@ void build_plan(sp_handle* h, int k) {
     std::map<std::array<int, 3>, long long> Voff;  // (sigma, c', i) -> offset
     std::map<std::array<int, 3>, int> Vcols;
     long long voff = 0;
-    struct VTerm { int sig, cp, i; long long toffv; int widx; };
+    struct VTerm { int sig, cp, i; long long toffv; int widx, e, q; };
     std::vector<VTerm> vterms;
     for (int sig = 0; sig < 4; ++sig)
         for (int cp = 0; cp < wr; ++cp)
@@ -709,7 +725,7 @@ void build_plan(sp_handle* h, int k) {
                         if (it == wpos.end() || Toff[size_t(e) * 4 + q] < 0) continue;
                         const int jb = br.nblock(bl.nb[el.blk[e].j].n + kSigmaN[q]);
                         SP_REQUIRE(jb == nbp, "internal: inconsistent particle numbers in the MPO mixing");
-                        vterms.push_back({sig, cp, i, Toff[size_t(e) * 4 + q], it->second});
+                        vterms.push_back({sig, cp, i, Toff[size_t(e) * 4 + q], it->second, e, q});
                         any = true;
                     }
                 }
@@ -1098,6 +1114,87 @@ void build_plan(sp_handle* h, int k) {
                                              g * P.nc + P.c_one());
                     }
             }
+    // pre-mixed left environment: one Lt block per (sigma, c', i, sigma') of
+    // the mixing, shaped like the environment blocks it sums (rows of bra
+    // N-block i x ket N-block j, the same j for every channel c of the group)
+    for (TList* tl : {&P.t_leftv, &P.t_left0}) tl->tile = TT;
+    {
+        struct LtBlk {
+            int sig, cp, i, q, j;
+            long long off;
+            std::vector<std::pair<int, int>> terms;  // (env block e, rotated-MPO entry)
+        };
+        std::vector<LtBlk> lts;
+        std::map<std::array<int, 4>, int> ltidx;
+        long long lto = 0;
+        for (const VTerm& v : vterms) {
+            const EnvBlk& eb = el.blk[v.e];
+            auto it = ltidx.find({v.sig, v.cp, v.i, v.q});
+            if (it == ltidx.end()) {
+                ltidx[{v.sig, v.cp, v.i, v.q}] = int(lts.size());
+                lts.push_back(LtBlk{v.sig, v.cp, v.i, v.q, eb.j, lto, {}});
+                lto += (long long)eb.rows * eb.cols;
+                it = ltidx.find({v.sig, v.cp, v.i, v.q});
+            }
+            LtBlk& lb = lts[it->second];
+            SP_REQUIRE(lb.j == eb.j && eb.i == v.i, "internal: inconsistent particle numbers in the pre-mixed environment");
+            lb.terms.push_back({v.e, v.widx});
+        }
+        P.LTsize = lto;
+        for (int g = 0; g < G; ++g)
+            for (const LtBlk& lb : lts) {
+                const EnvBlk& e0 = el.blk[lb.terms[0].first];
+                P.premix.add_task(B_LT, g * P.LTsize + lb.off, e0.rows * e0.cols);
+                for (const auto& tm : lb.terms)
+                    P.premix.add_term(B_ENVL, g * Lsz + el.blk[tm.first].off, g * P.nc + P.c_wt(tm.second));
+            }
+        // V(sigma, c', i) = sum over sigma' (ascending) of Lt(sigma, c', i, sigma') Xd(j, sigma', .)
+        for (int g = 0; g < G; ++g)
+            for (int sig = 0; sig < 4; ++sig)
+                for (int cp = 0; cp < wr; ++cp)
+                    for (int i = 0; i < int(bl.nb.size()); ++i) {
+                        auto vo = Voff.find({sig, cp, i});
+                        if (vo == Voff.end()) continue;
+                        const int ncol = Vcols[{sig, cp, i}];
+                        const int nbk = br.nblock(bl.nb[i].n + kSigmaN[sig]);
+                        const int nbp = br.nblock(br.nb[nbk].n - h->dn[k][cp]);
+                        const int M = bl.nb[i].dim;
+                        for (int r0 = 0; r0 < M; r0 += TT)
+                            for (int c0 = 0; c0 < ncol; c0 += TT) {
+                                P.t_leftv.add_task(B_V, g * P.Vsize + vo->second, ncol, M, ncol, r0, c0, 0, 0);
+                                for (int q = 0; q < 4; ++q) {
+                                    auto li = ltidx.find({sig, cp, i, q});
+                                    if (li == ltidx.end()) continue;
+                                    const LtBlk& lb = lts[li->second];
+                                    SP_REQUIRE(br.nblock(bl.nb[lb.j].n + kSigmaN[q]) == nbp,
+                                               "internal: pre-mixed product columns");
+                                    int k0, k1;
+                                    if (k_from_cols(nbp, q, c0, std::min(ncol, c0 + TT), k0, k1))
+                                        P.t_leftv.add_seg(B_LT, g * P.LTsize + lb.off, bl.nb[lb.j].dim, 0, B_X,
+                                                          xdoff(lb.j, q), ncol, 0, k0, k1, g * P.nc + P.c_one());
+                                }
+                            }
+                    }
+        // T of the identity channel (c = 0) only, for N_eff
+        for (int g = 0; g < G; ++g)
+            for (size_t e = 0; e < el.blk.size(); ++e) {
+                if (el.blk[e].c != 0) continue;
+                for (int q = 0; q < 4; ++q) {
+                    if (Toff[e * 4 + q] < 0) continue;
+                    const EnvBlk& eb = el.blk[e];
+                    const int jb = br.nblock(bl.nb[eb.j].n + kSigmaN[q]);
+                    const int ncol = br.nb[jb].dim;
+                    for (int r0 = 0; r0 < eb.rows; r0 += TT)
+                        for (int c0 = 0; c0 < ncol; c0 += TT) {
+                            P.t_left0.add_task(B_T, g * P.Tsize + Toff[e * 4 + q], ncol, eb.rows, ncol, r0, c0, 0, 0);
+                            int k0, k1;
+                            if (k_from_cols(jb, q, c0, std::min(ncol, c0 + TT), k0, k1))
+                                P.t_left0.add_seg(B_ENVL, g * Lsz + eb.off, eb.cols, 0, B_X, xdoff(eb.j, q), ncol, 0, k0,
+                                                  k1, g * P.nc + P.c_one());
+                        }
+                }
+            }
+    }
     // right product: per g partial y and ny, scattered into the packed layout.
     // An output tile sums over every right channel; wide MPOs have hundreds,
     // so the channel list of a tile is cut into up to tr_split chunks, each
@@ -1521,6 +1618,9 @@ void upload_plan(sp_handle* h, int k) {
     P.absorb_left.upload(s);
     P.xmap.upload(P.xmap_h, s);
     P.t_left.upload(s);
+    P.t_leftv.upload(s);
+    P.t_left0.upload(s);
+    P.premix.upload(s);
     P.t_right.upload(s);
     P.t_envl.upload(s);
     P.t_zr.upload(s);
@@ -1700,6 +1800,14 @@ void validate_plans(sp_handle* h) {
                 if (e >= xs) throw SpError(SP_EINVAL, "internal: packed map out of range");
             const long long ms = (long long)P.xmap_h.size();
             validate(P.t_left, t, nco, ms, xs, "tiled left product");
+            if (h->path == SP_PATH_TILED) {  // the plain path has no pre-mixed environment buffer
+                t[B_LT] = h->LT_cap;
+                if (G * P.LTsize > h->LT_cap)
+                    throw SpError(SP_EINVAL, "internal: pre-mixed environment scratch too small");
+                validate(P.t_leftv, t, nco, ms, xs, "tiled product of the pre-mixed environment");
+                validate(P.t_left0, t, nco, ms, xs, "tiled identity-channel product");
+                validate(P.premix, t, nco, "pre-mixed left environment");
+            }
             validate(P.t_right, t, nco, ms, xs, "tiled right product");
             validate(P.t_zr, t, nco, ms, xs, "tiled right-pass product");
             t[B_OUT] = Rb;
@@ -1775,6 +1883,7 @@ spk::BufSet bufset(sp_handle* h, int k, const double* x, double* y, double* ny, 
     b.p[B_NY] = ny;
     b.p[B_OUT] = out;
     b.p[B_BRA] = const_cast<double*>(x);
+    b.p[B_LT] = h->LT.p;
     return b;
 }
 
@@ -1810,14 +1919,23 @@ spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32) {
 
 // H_eff x at a tiled-path site without a fused plan (a particle-number block
 // too wide for its LDS): the LDS-tiled block-product lists, FP64 in either
-// precision, leaving the same per-g partials as the fused kernel
+// precision, leaving the same per-g partials as the fused kernel.  The W r
+// mixing is applied to the left environment instead of to the products
+// L_g x: the pre-mixed environment depends only on L[k-1] and is built once
+// per local problem (the first product after L[k-1] changes), so each
+// product is two block-product launches and no mixing pass.
 void heff_tiled(sp_handle* h, int k, const double* x) {
     SitePlan& P = h->plan[k - 1];
     hipStream_t s = h->stream;
     const spk::BufSet b = bufset(h, k, h->Xd.p, h->ypart.p, h->nypart.p, nullptr);
     spk::gather(s, P.xmap.p, x, h->Xd.p, P.Xd_size);
-    P.t_left.launch(s, b, P.coef.p, P.xmap.p);
-    P.mixl.launch(s, b, P.coef.p);
+    if (h->lt_site != k || h->lt_gen != h->Lgen[k - 1]) {  // once per left environment and site
+        P.premix.launch(s, b, P.coef.p);
+        h->lt_site = k;
+        h->lt_gen = h->Lgen[k - 1];
+    }
+    P.t_left0.launch(s, b, P.coef.p, P.xmap.p);
+    P.t_leftv.launch(s, b, P.coef.p, P.xmap.p);
     if (P.tr_split > 1) {  // slots without a chunk of some tile stay zero
         const long long nslot = (long long)P.tr_split * h->G * h->sites[k - 1].size;
         spk::fill(s, h->ypart.p, nslot, 0.0);
@@ -1880,6 +1998,7 @@ void env_left(sp_handle* h, int k) {
     if (h->precision == SP_FP32)
         spk::to_f32(s, h->envL[k].p, h->envL32[k].p, (long long)h->G * h->env[k].size);
     h->Lvalid[k] = 1;
+    ++h->Lgen[k];
     for (int q = k + 1; q <= h->L; ++q) h->Lvalid[q] = 0;
 }
 
@@ -1976,6 +2095,7 @@ void env_left_mixed(sp_handle* a, int k, const double* bra) {
     P.mixl.launch(a->stream, b, P.coef.p);
     P.envl_out.launch(a->stream, b, P.coef.p);
     a->Lvalid[k] = 1;
+    ++a->Lgen[k];
 }
 
 void env_right_mixed(sp_handle* a, int k, const double* bra) {
@@ -2925,18 +3045,20 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         }
         build_env_layouts(h.get());
         h->plan.resize(h->L);
-        long long Tmax = 0, Vmax = 0, qrs = 0, qrr = 0;
+        long long Tmax = 0, Vmax = 0, qrs = 0, qrr = 0, LTmax = 0;
         for (int k = 1; k <= h->L; ++k) {
             build_plan(h.get(), k);
             if (h->path == SP_PATH_TILED && !build_fused(h.get(), k)) build_fused(h.get(), k, kHeffLdsMax);
             const SitePlan& P = h->plan[k - 1];
             Tmax = std::max({Tmax, P.Tsize, P.Zsize});
             Vmax = std::max({Vmax, P.Vsize, P.Ztsize});
+            LTmax = std::max(LTmax, P.LTsize);
             qrs = std::max({qrs, P.qr_scratch, P.lq_scratch});
             qrr = std::max({qrr, P.qr_rsize, P.lq_rsize});
         }
         h->T_cap = h->G * std::max(1LL, Tmax);
         h->V_cap = h->G * std::max(1LL, Vmax);
+        h->LT_cap = h->path == SP_PATH_TILED ? h->G * std::max(1LL, LTmax) : 1;
         h->qr_scratch_cap = std::max(1LL, qrs);
         h->qr_r_cap = std::max(1LL, qrr);
         for (int k = 1; k <= h->L; ++k) {
@@ -2951,6 +3073,7 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         for (int k = 1; k <= h->L; ++k) upload_plan(h.get(), k);
         h->T.alloc(h->T_cap);
         h->V.alloc(h->V_cap);
+        h->LT.alloc(h->LT_cap);
         h->qr_scratch.alloc(h->qr_scratch_cap);
         h->qr_r.alloc(h->qr_r_cap);
         h->tmp_site.alloc(h->max_site);

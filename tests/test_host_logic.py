@@ -132,12 +132,12 @@ class _Tab:
         return W.BlockTable(self.L, self.N, self.twoM, self.bonds).flat()
 
 
-def _init_rc(table, twoS, G, mpo_=None, N=None):
+def _init_rc(table, twoS, G, mpo_=None, N=None, path=sp.SP_PATH_TILED):
     """sp_init_mps return code for host-rejected inputs (never reaches HIP)."""
     nsec, sn, s2m, sdim = (np.ascontiguousarray(a, dtype=np.int32) for a in table.flat())
     w, data = mpo_ or sp.mpo_hubbard(table.L, 1.0, 4.0)
     w = np.ascontiguousarray(w, dtype=np.int32)
-    prob = sp._Problem(table.L, 4, table.N if N is None else N, twoS, table.twoM, G, 0, 0)
+    prob = sp._Problem(table.L, 4, table.N if N is None else N, twoS, table.twoM, G, 0, path)
     m = sp._Mpo(sp._iptr(w), sp._dptr(data))
     bt = sp._BlockTable(sp._iptr(nsec), sp._iptr(sn), sp._iptr(s2m), sp._iptr(sdim))
     blocks = np.zeros(max(1, W.BlockTable(table.L, table.N, table.twoM, table.bonds).total_size()))
@@ -187,8 +187,9 @@ def test_init_plans_pass_host_validation(wl):
     import torch
     if torch.cuda.is_available():
         pytest.skip("GPU present: covered by the GPU tests")
-    rc, msg = _init_rc(wl.table(), wl.twoS, wl.G, mpo_=sp.mpo_hubbard(wl.L, wl.t, wl.U))
-    assert rc == sp.SP_EHIP, msg
+    for path in (sp.SP_PATH_TILED, sp.SP_PATH_PLAIN):
+        rc, msg = _init_rc(wl.table(), wl.twoS, wl.G, mpo_=sp.mpo_hubbard(wl.L, wl.t, wl.U), path=path)
+        assert rc == sp.SP_EHIP, (path, msg)
 
 
 def test_init_plans_pass_host_validation_odd_cases():
