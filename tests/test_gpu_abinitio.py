@@ -73,6 +73,37 @@ def test_abinitio_heff_all_sites(case, plan):
         assert rel_err(dn.cpu().numpy(), orc.mps.site_packed(k, dn_ref)) < 1e-11, k
 
 
+@pytest.mark.parametrize("case", [CASES[1], CASES[3]])
+def test_abinitio_tiled_product_follows_the_left_environment(case):
+    """The tiled products keep the W r mixing of L[k-1] from one product to
+    the next: after a new left tensor and a rebuilt L[k-1], the next product
+    at the same site must use the new environment."""
+    tab, gpu, orc = _pair(*case)
+    _force_tiled(gpu)
+    k = 3
+    rng = np.random.default_rng(11)
+    for j in range(1, k):
+        gpu.env_update(j, +1)
+        orc.update_left(j)
+    for rep in range(3):
+        if rep:
+            a = rng.standard_normal(gpu.site_size(k - 1))
+            gpu.set_site(k - 1, a)
+            orc.mps.A[k - 2] = orc.mps.dense_site(k - 1, a)
+            gpu.env_update(k - 1, +1)
+            orc.update_left(k - 1)
+        print(f"[case] K={tab.L} site={k} rebuild={rep}", flush=True)
+        for _ in range(2):  # twice with the same environment, new x each time
+            x = rng.standard_normal(gpu.site_size(k))
+            y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
+            xd = _dev(x)
+            y, ny = torch.empty_like(xd), torch.empty_like(xd)
+            gpu.heff_apply(k, xd, y, ny)
+            torch.cuda.synchronize()
+            assert rel_err(y.cpu().numpy(), orc.mps.site_packed(k, y_ref)) < 1e-11, rep
+            assert rel_err(ny.cpu().numpy(), orc.mps.site_packed(k, ny_ref)) < 1e-11, rep
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_abinitio_energy_at_centre(case):
     tab, gpu, orc = _pair(*case)
