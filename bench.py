@@ -93,16 +93,18 @@ def abinitio_runs(sp, W, torch, sweeps=1):
     mpo = sp.mpo_abinitio(h, eri)
     tab, blocks = wl.table(), wl.blocks()
     res = {}
-    for path in ("tiled", "plain"):
-        log(f"[bench] {wl.name} path={path}: init")
-        st = sp.SPMPS(tab, blocks, mpo, wl.twoS, wl.G, path=path)
+    runs = (("tiled", "tiled", "fp64", 1e-9), ("plain", "plain", "fp64", 1e-9),
+            ("fp32", "tiled", "fp32", 1e-6), ("bf16x3", "tiled", "bf16x3", 1e-5))
+    for name, path, prec, tol in runs:
+        log(f"[bench] {wl.name} path={path} {prec}: init")
+        st = sp.SPMPS(tab, blocks, mpo, wl.twoS, wl.G, path=path, precision=prec)
         plans = [st.heff_plan(k)[0] for k in range(1, wl.K + 1)]
-        rc, _ = st.sweep(1)
+        rc, _ = st.sweep(1, tol=tol)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         steps = []
         for _ in range(sweeps):
-            rc, s1 = st.sweep(1)
+            rc, s1 = st.sweep(1, tol=tol)
             steps += s1
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -115,19 +117,26 @@ def abinitio_runs(sp, W, torch, sweeps=1):
         ms = sum(p["ms"] for p in prof.values())
         fl = st.heff_flops(kc)
         st.close()
-        res[path] = {"value": len(steps) / dt, "energy_after_timed_sweeps": steps[-1]["theta"],
+        res[name] = {"value": len(steps) / dt, "energy_after_timed_sweeps": steps[-1]["theta"],
                      "matvecs_per_site_step": float(sum(s["matvecs"] for s in steps) / len(steps)),
                      "heff_ms_centre": ms, "heff_flops_centre": fl, "heff_tflops_centre": fl / (ms * 1e-3) / 1e12,
                      "fused_sites": sum(1 for r in plans if r > 0), "steps": steps}
-        log(f"[bench] {wl.name} {path}: {res[path]['value']:.2f} site steps/s, H_eff x at site {kc} {ms:.3f} ms "
-            f"({res[path]['heff_tflops_centre']:.3f} TFLOP/s), fused sites {res[path]['fused_sites']}/{wl.K}")
+        if prec != "fp64":
+            res[name].update(solver_tol=tol, dE_vs_fp64_tiled=steps[-1]["theta"] - res["tiled"]["energy_after_timed_sweeps"],
+                             speedup_site_steps_vs_fp64_tiled=res[name]["value"] / res["tiled"]["value"])
+        log(f"[bench] {wl.name} {name}: {res[name]['value']:.2f} site steps/s, H_eff x at site {kc} {ms:.3f} ms "
+            f"({res[name]['heff_tflops_centre']:.3f} TFLOP/s), fused sites {res[name]['fused_sites']}/{wl.K}")
     t, p = res["tiled"], res["plain"]
     dE = max(abs(a["theta"] - b["theta"]) for a, b in zip(t["steps"], p["steps"]))
     for r in res.values():
         del r["steps"]
+    res["fp32"]["note"] = "fused products in FP32; tiled block products FP64; FP64 Rayleigh quotient per step"
+    res["bf16x3"]["note"] = ("fused products in FP32; tiled block products in split BF16 (hi+lo, three matrix-core "
+                             "products, FP32 accumulation); FP64 Rayleigh quotient per step")
     return {"workload": wl.name, "K": wl.K, "N": wl.N, "twoS": wl.twoS, "D": wl.D, "G": wl.G, "seed": wl.seed,
             "mpo_max_bond": int(max(mpo[0])), "unit": "site steps/s", "dtype": "f64",
-            "tiled": t, "plain_fp64": p, "speedup_site_steps": t["value"] / p["value"],
+            "tiled": t, "plain_fp64": p, "fp32": res["fp32"], "bf16x3": res["bf16x3"],
+            "speedup_site_steps": t["value"] / p["value"],
             "max_step_dE_tiled_vs_plain": dE,
             "note": "integrals from the seeded recipe of the 30-orbital workload at 12 orbitals; sites whose "
                     "particle-number blocks exceed the fused kernel's LDS run the tiled block products"}

@@ -56,6 +56,13 @@ extern "C" {
                              orthogonalisation and subspace solve, and a
                              final FP64 Rayleigh quotient per site step
                              (the reported energy) stay FP64           */
+#define SP_BF16X3 2       /* as SP_FP32, and the LDS-tiled block products of
+                             sites too wide for the fused kernel run in
+                             split BF16 on the matrix cores: each operand
+                             value v ~ hi + lo (two bf16, round to nearest
+                             even), three products hi hi + hi lo + lo hi
+                             with FP32 accumulation (relative error of
+                             order 1e-5); values must lie in FP32 range  */
 
 #define SP_PATH_TILED 0   /* environment updates as LDS-tiled products over
                              particle-number blocks; H_eff x in one fused
@@ -82,7 +89,7 @@ typedef struct sp_problem {
     int twoS;
     int twoM;
     int G;
-    int precision; /* SP_FP64 or SP_FP32 */
+    int precision; /* SP_FP64, SP_FP32 or SP_BF16X3 */
     int path;      /* SP_PATH_TILED or SP_PATH_PLAIN: same results to rounding */
 } sp_problem;
 

@@ -21,6 +21,7 @@ SP_OK, SP_ENOCONV, SP_WINEXACT = 0, 1, 2
 SP_EINVAL, SP_ENORM, SP_EHIP, SP_ENOMEM, SP_ESTATE, SP_ENAN = -1, -2, -3, -4, -5, -6
 SP_FP64 = 0
 SP_FP32 = 1
+SP_BF16X3 = 2
 SP_PATH_TILED, SP_PATH_PLAIN = 0, 1
 
 EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_sweep", "sp_energy",
@@ -360,7 +361,7 @@ class SPMPS:
         self.L, self.N, self.twoM, self.twoS, self.G = table.L, table.N, table.twoM, twoS, G
         self.path = path
         self.precision = precision
-        prob = _Problem(self.L, 4, self.N, twoS, self.twoM, G, {"fp64": SP_FP64, "fp32": SP_FP32}[precision],
+        prob = _Problem(self.L, 4, self.N, twoS, self.twoM, G, {"fp64": SP_FP64, "fp32": SP_FP32, "bf16x3": SP_BF16X3}[precision],
                         {"tiled": SP_PATH_TILED, "plain": SP_PATH_PLAIN}[path])
         w, data = mpo
         w = np.ascontiguousarray(w, dtype=np.int32)

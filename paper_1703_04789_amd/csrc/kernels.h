@@ -80,6 +80,10 @@ constexpr int kTile = 64;  // the wide tile; 32 is the narrow one
 // tile: 64 or 32 (the task grid of the list was built for that tile)
 void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
            const int* map, int tile);
+// the same products in split BF16 (hi + lo per operand, three matrix-core
+// products, FP32 accumulation); relative error of order 1e-5
+void tgemm_bf3(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
+               const int* map, int tile);
 // dst[e] = map[e] >= 0 ? src[map[e]] : 0, e < n
 void gather(hipStream_t s, const int* map, const double* src, double* dst, long long n);
 // out[e] = sum_{g < G} part[g*stride + e] in ascending g, for two arrays at once

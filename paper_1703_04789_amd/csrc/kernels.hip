@@ -516,6 +516,131 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
     }
 }
 
+// The same block products in split BF16 (three matrix-core products per
+// step, FP32 accumulation).  Every operand value v (FP64, the A operand
+// already times its segment coefficient) is split as v ~ hi + lo with
+// hi = bf16(v) and lo = bf16(v - hi), round to nearest even, and
+// A B ~ hi_A hi_B + hi_A lo_B + lo_A hi_B (the lo lo term is dropped): about
+// 16 significant bits per operand, so products carry a relative error of
+// order 1e-5.  K is staged in chunks of 32 as bf16 pairs, k contiguous per
+// row of A and per column of B, so that a lane fetches its eight k values of
+// a v_mfma_f32_16x16x32_bf16 step with one 16-byte LDS read (lane l supplies
+// A(l % 16, 8 (l / 16) + t) and B(8 (l / 16) + t, l % 16), t < 8, and holds
+// D(4 (l / 16) + v, l % 16), v < 4).  Tiles, wavefront layout and output
+// addressing as in k_tgemm; values must lie in the FP32 range.
+constexpr int kKC3 = 32;
+constexpr int kKC3Pad = kKC3 + 8;  // bf16 per LDS row (16-byte aligned rows)
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_rne(float f) {
+    unsigned int u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline void split_bf16(double v, unsigned short& hi, unsigned short& lo) {
+    hi = bf16_rne(float(v));
+    const double h = double(__uint_as_float((unsigned int)hi << 16));
+    lo = bf16_rne(float(v - h));
+}
+
+template <int TILE>
+__global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm_bf3(const TTask* __restrict__ tasks,
+                                                                      const TSeg* __restrict__ segs, BufSet bufs,
+                                                                      const double* __restrict__ coef,
+                                                                      const int* __restrict__ map) {
+    constexpr int NT = (TILE / 4) * (TILE / 4), WPR = TILE / 32;
+    static_assert(NT == 64 * WPR * WPR, "one wavefront per 32 x 32 quarter");
+    __shared__ __align__(16) unsigned short Ah[TILE][kKC3Pad], Al[TILE][kKC3Pad];
+    __shared__ __align__(16) unsigned short Bh[TILE][kKC3Pad], Bl[TILE][kKC3Pad];
+    const TTask tk = tasks[blockIdx.x];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wr = (wave / WPR) * 32, wc = (wave % WPR) * 32;
+    const int li = lane % 16, lk = lane / 16;
+    f4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int s = tk.s0; s < tk.s1; ++s) {
+        const TSeg sg = segs[s];
+        const double cf = coef[sg.cidx];
+        const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
+        const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
+        for (int kb = sg.k0; kb < sg.k1; kb += kKC3) {
+            for (int idx = threadIdx.x; idx < TILE * kKC3; idx += NT) {
+                int r, k;
+                if (sg.ta == 0) {
+                    r = idx / kKC3;
+                    k = idx % kKC3;
+                } else {
+                    k = idx / TILE;
+                    r = idx % TILE;
+                }
+                const int gr = tk.r0 + r, gk = kb + k;
+                double v = 0.0;
+                if (gr < tk.M && gk < sg.k1)
+                    v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
+                split_bf16(cf * v, Ah[r][k], Al[r][k]);
+            }
+            for (int idx = threadIdx.x; idx < TILE * kKC3; idx += NT) {
+                int c, k;
+                if (sg.tb == 0) {
+                    k = idx / TILE;
+                    c = idx % TILE;
+                } else {
+                    c = idx / kKC3;
+                    k = idx % kKC3;
+                }
+                const int gc = tk.c0 + c, gk = kb + k;
+                double v = 0.0;
+                if (gc < tk.N && gk < sg.k1)
+                    v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
+                split_bf16(v, Bh[c][k], Bl[c][k]);
+            }
+            __syncthreads();
+            bf8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ah[i] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const u4_t*>(&Ah[wr + 16 * i + li][8 * lk]));
+                al[i] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const u4_t*>(&Al[wr + 16 * i + li][8 * lk]));
+                bh[i] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const u4_t*>(&Bh[wc + 16 * i + li][8 * lk]));
+                bl[i] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const u4_t*>(&Bl[wc + 16 * i + li][8 * lk]));
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+            __syncthreads();
+        }
+    }
+    double* C = bufs.p[tk.c_buf] + tk.c_off;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = tk.r0 + wr + 16 * i + 4 * lk + v;
+            if (r >= tk.M) continue;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int c = tk.c0 + wc + 16 * j + li;
+                if (c >= tk.N) continue;
+                if (tk.mode == 0) {
+                    C[(long long)r * tk.ldc + c] = double(acc[i][j][v]);
+                } else {
+                    const int p = map[tk.pack_off + (long long)r * tk.N + c];
+                    if (p >= 0) C[p] = double(acc[i][j][v]);
+                }
+            }
+        }
+    }
+}
+
 template <int RC, typename T, bool BATCH>
 __global__ __launch_bounds__(kH3Threads) void k_heff3(const H3Task* __restrict__ tasks,
                                                         const H3Inst* __restrict__ insts, H3Inst one) {
@@ -1178,6 +1303,15 @@ __global__ __launch_bounds__(kThreads) void k_bdav_gram(const DavInst* __restric
 inline int nblk(int n) { return (n + kThreads - 1) / kThreads; }
 
 }  // namespace
+
+void tgemm_bf3(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
+               const int* map, int tile) {
+    if (ntasks <= 0) return;
+    if (tile == 32)
+        hipLaunchKernelGGL(k_tgemm_bf3<32>, dim3(ntasks), dim3(64), 0, s, tasks, segs, bufs, coef, map);
+    else
+        hipLaunchKernelGGL(k_tgemm_bf3<64>, dim3(ntasks), dim3(256), 0, s, tasks, segs, bufs, coef, map);
+}
 
 void tgemm(hipStream_t s, const TTask* tasks, int ntasks, const TSeg* segs, BufSet bufs, const double* coef,
            const int* map, int tile) {

@@ -268,8 +268,9 @@ struct TList {
         dtasks.upload(tasks, s);
         dsegs.upload(segs, s);
     }
-    void launch(hipStream_t s, const spk::BufSet& b, const double* coef, const int* map) const {
-        spk::tgemm(s, dtasks.p, int(tasks.size()), dsegs.p, b, coef, map, tile);
+    void launch(hipStream_t s, const spk::BufSet& b, const double* coef, const int* map, bool bf3 = false) const {
+        if (bf3) spk::tgemm_bf3(s, dtasks.p, int(tasks.size()), dsegs.p, b, coef, map, tile);
+        else spk::tgemm(s, dtasks.p, int(tasks.size()), dsegs.p, b, coef, map, tile);
     }
 };
 
@@ -409,6 +410,17 @@ struct sp_handle {
         if (con_pin) (void)hipHostFree(con_pin);
     }
 };
+
+// reduced-precision local solves (SP_FP32 or SP_BF16X3): FP32 fused products,
+// FP64 Rayleigh quotient per site step, looser canonical orthogonalisation
+inline bool reduced(const sp_handle* h) { return h->precision != SP_FP64; }
+// canonical orthogonalisation of the projected metric: eigenvalues below
+// drop x the largest are discarded; the threshold sits about two orders
+// above the relative noise of the products (FP64 ~1e-15, FP32 ~1e-7,
+// split BF16 ~1e-5)
+inline double metric_drop(const sp_handle* h) {
+    return h->precision == SP_FP64 ? 1e-10 : (h->precision == SP_FP32 ? 1e-5 : 1e-3);
+}
 
 // a learned Davidson preconditioner and its training pairs (one device)
 struct sp_mlp {
@@ -599,7 +611,7 @@ void alloc_envs(sp_handle* h) {
     std::vector<double> ones(h->G, 1.0);
     HIPCK(hipMemcpyAsync(h->envL[0].p, ones.data(), h->G * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCK(hipMemcpyAsync(h->envR[L].p, ones.data(), h->G * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    if (h->precision == SP_FP32) {
+    if (reduced(h)) {
         h->envL32.resize(L + 1);
         h->envR32.resize(L + 1);
         for (int k = 0; k <= L; ++k) {
@@ -1924,7 +1936,7 @@ spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32) {
 // L_g x: the pre-mixed environment depends only on L[k-1] and is built once
 // per local problem (the first product after L[k-1] changes), so each
 // product is two block-product launches and no mixing pass.
-void heff_tiled(sp_handle* h, int k, const double* x) {
+void heff_tiled(sp_handle* h, int k, const double* x, bool bf3 = false) {
     SitePlan& P = h->plan[k - 1];
     hipStream_t s = h->stream;
     const spk::BufSet b = bufset(h, k, h->Xd.p, h->ypart.p, h->nypart.p, nullptr);
@@ -1934,14 +1946,14 @@ void heff_tiled(sp_handle* h, int k, const double* x) {
         h->lt_site = k;
         h->lt_gen = h->Lgen[k - 1];
     }
-    P.t_left0.launch(s, b, P.coef.p, P.xmap.p);
-    P.t_leftv.launch(s, b, P.coef.p, P.xmap.p);
+    P.t_left0.launch(s, b, P.coef.p, P.xmap.p, bf3);
+    P.t_leftv.launch(s, b, P.coef.p, P.xmap.p, bf3);
     if (P.tr_split > 1) {  // slots without a chunk of some tile stay zero
         const long long nslot = (long long)P.tr_split * h->G * h->sites[k - 1].size;
         spk::fill(s, h->ypart.p, nslot, 0.0);
         spk::fill(s, h->nypart.p, nslot, 0.0);
     }
-    P.t_right.launch(s, b, P.coef.p, P.xmap.p);
+    P.t_right.launch(s, b, P.coef.p, P.xmap.p, bf3);
 }
 
 // number of per-site partial outputs H_eff x leaves (in G * n blocks of n)
@@ -1967,9 +1979,9 @@ bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, boo
     }
     const int n = int(h->sites[k - 1].size);
     if (P.h_rows == 0) {
-        heff_tiled(h, k, x);
+        heff_tiled(h, k, x, h->precision == SP_BF16X3 && !force_fp64);
     } else {
-        const bool f32 = h->precision == SP_FP32 && !force_fp64;
+        const bool f32 = reduced(h) && !force_fp64;
         const spk::H3Inst I = heff_inst(h, k, x, f32);
         if (f32) spk::heff3_f32(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
         else spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
@@ -1995,7 +2007,7 @@ void env_left(sp_handle* h, int k) {
         P.mixl.launch(s, b, P.coef.p);
         P.t_envl.launch(s, b, P.coef.p, P.xmap.p);
     }
-    if (h->precision == SP_FP32)
+    if (reduced(h))
         spk::to_f32(s, h->envL[k].p, h->envL32[k].p, (long long)h->G * h->env[k].size);
     h->Lvalid[k] = 1;
     ++h->Lgen[k];
@@ -2018,7 +2030,7 @@ void env_right(sp_handle* h, int k) {
         P.mixr.launch(s, b, P.coef.p);
         P.t_envr.launch(s, b, P.coef.p, P.xmap.p);
     }
-    if (h->precision == SP_FP32)
+    if (reduced(h))
         spk::to_f32(s, h->envR[k - 1].p, h->envR32[k - 1].p, (long long)h->G * h->env[k - 1].size);
     h->Rvalid[k - 1] = 1;
     for (int q = 0; q < k - 1; ++q) h->Rvalid[q] = 0;
@@ -2302,7 +2314,7 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     // canonical orthogonalisation threshold: with FP32 products the null
     // space of the projected metric is only resolved to about 1e-7 of its
     // largest eigenvalue, so directions below 1e-5 are dropped there
-    const double drop = (h->precision == SP_FP32) ? 1e-5 : 1e-10, floor_ = 1e-8;
+    const double drop = metric_drop(h), floor_ = 1e-8;
     DavOut out;
     // fixed-order sums of per-chunk partials (host side)
     auto chunk_total = [&](const double* part, int stride, int idx) {
@@ -2481,7 +2493,7 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
         spk::mlp_targets(s, h->xrec.p, ld, keep, site_ptr(h, k), n, rec->Y.p + rec_base);
         rec->rows = rec_base + (long long)keep * n;
     }
-    if (h->precision == SP_FP32) {
+    if (reduced(h)) {
         // the reported energy and norm: one FP64 product with the FP64
         // environments (the vector itself comes from the FP32 solve)
         double th, pn, xx;
@@ -2613,7 +2625,7 @@ void batch_heff_mixed(std::vector<BatchState>& B, const std::vector<int>& idx, c
     std::vector<spk::H3Inst> insts(idx.size());
     std::map<int, std::vector<spk::H3Task>> by_rc;
     std::map<int, int> lds_by_rc;
-    const bool f32 = B[idx[0]].h->precision == SP_FP32;
+    const bool f32 = reduced(B[idx[0]].h);
     for (size_t q = 0; q < idx.size(); ++q) {
         BatchState& st = B[idx[q]];
         sp_handle* h = st.h;
@@ -2621,7 +2633,7 @@ void batch_heff_mixed(std::vector<BatchState>& B, const std::vector<int>& idx, c
         insts[q] = heff_inst(h, st.k, x, f32);
         const SitePlan& P = h->plan[st.k - 1];
         if (P.h_rows == 0) {  // no fused plan: this state's tiled lists, same partials
-            heff_tiled(h, st.k, x);
+            heff_tiled(h, st.k, x, h->precision == SP_BF16X3);
             continue;
         }
         auto& v = by_rc[P.h_rows];
@@ -2705,7 +2717,6 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
     const int keep = std::max(1, std::min(o.keep, max_sub - 1));
     const int max_iter = std::max(1, o.max_iter);
     const int S = max_sub + 1;
-    const double drop64 = 1e-10, drop32 = 1e-5;
     BatchBufs bb;
     const int nthreads =
         std::max(0, std::min<int>(int(B.size()), std::min(16u, std::thread::hardware_concurrency())) - 1);
@@ -2752,7 +2763,7 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
                 st.out.iters = st.it;
                 st.last = (st.it == max_iter);
                 st.restart = !st.last && st.m >= max_sub;
-                const double drop = st.h->precision == SP_FP32 ? drop32 : drop64;
+                const double drop = metric_drop(st.h);
                 if (!small_solve(st.m, st.Ht, st.Nt, S, drop, st.restart, st.theta, st.a, st.Xc, st.rk))
                     throw SpError(SP_ENORM, "projected norm vanishes in the search space");
                 st.out.theta = st.theta;
@@ -2928,7 +2939,7 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
             sp_handle* h = st.h;
             const int k = st.k, d = st.order[st.step].second, L = h->L;
             spk::normalize(s, h->dx.p, site_ptr(h, k), st.n, nullptr);
-            if (h->precision == SP_FP32) {
+            if (reduced(h)) {
                 double th, pn, xx;
                 rayleigh64(h, k, site_ptr(h, k), th, pn, xx);
                 st.out.theta = th;
@@ -3007,8 +3018,9 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         SP_REQUIRE(p && W && bonds && init_blocks && out, "null argument");
         *out = nullptr;
         SP_REQUIRE(p->L >= 1 && p->d == 4, "need L >= 1 and d == 4");
-        SP_REQUIRE(p->precision == SP_FP64 || p->precision == SP_FP32, "precision must be SP_FP64 or SP_FP32");
-        SP_REQUIRE(p->precision == SP_FP64 || p->path == SP_PATH_TILED, "SP_FP32 needs the tiled path");
+        SP_REQUIRE(p->precision == SP_FP64 || p->precision == SP_FP32 || p->precision == SP_BF16X3,
+                   "precision must be SP_FP64, SP_FP32 or SP_BF16X3");
+        SP_REQUIRE(p->precision == SP_FP64 || p->path == SP_PATH_TILED, "reduced precision needs the tiled path");
         SP_REQUIRE(p->path == SP_PATH_TILED || p->path == SP_PATH_PLAIN, "unknown kernel path");
         SP_REQUIRE(p->N >= 0 && p->N <= 2 * p->L, "N out of range");
         SP_REQUIRE((p->N + p->twoS) % 2 == 0, "N and 2S must have the same parity");
@@ -3249,7 +3261,7 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
                 validate_fused(h, k);
                 upload_fused(h, k);
                 HIPCK(hipStreamSynchronize(s));
-                const bool f32 = h->precision == SP_FP32;
+                const bool f32 = reduced(h);
                 const spk::H3Inst I = heff_inst(h, k, x, f32);
                 auto launch = [&]() {
                     if (f32) spk::heff3_f32(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
@@ -3663,7 +3675,7 @@ int sp_heff_batch_profile(sp_handle** hs, int n, const int* sites, int reps, dou
                        "one device, stream and precision");
             SP_REQUIRE(h->Lvalid[k - 1] && h->Rvalid[k], "environments are not built");
             for (int j = 0; j < i; ++j) SP_REQUIRE(hs[j] != h, "a handle appears twice");
-            insts[i] = heff_inst(h, k, site_ptr(h, k), h->precision == SP_FP32);
+            insts[i] = heff_inst(h, k, site_ptr(h, k), reduced(h));
             const SitePlan& P = h->plan[k - 1];
             for (spk::H3Task t : P.h_tasks) {
                 if (t.blk < 0) continue;
@@ -3686,7 +3698,7 @@ int sp_heff_batch_profile(sp_handle** hs, int n, const int* sites, int reps, dou
         dinst.upload(insts, s);
         dtask.upload(all, s);
         HIPCK(hipStreamSynchronize(s));
-        const bool f32 = hs[0]->precision == SP_FP32;
+        const bool f32 = reduced(hs[0]);
         auto launch = [&]() {
             for (auto& gr : groups) {
                 const int rc = gr.first;
