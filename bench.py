@@ -266,8 +266,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default fused-kernel plans instead of timing them per site (sp_autotune)")
     ap.add_argument("--path", default="tiled", choices=["tiled", "plain"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
-                    help="precision of the H_eff products inside the local solves (SP_FP64 / SP_FP32)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="precision of the H_eff products inside the local solves (SP_FP64 / SP_FP32 / SP_BF16X3)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-fp32", action="store_true", help="skip the reduced-precision (SP_FP32) run")
     ap.add_argument("--fp32-tol", type=float, default=1e-6,

@@ -415,11 +415,12 @@ struct sp_handle {
 // FP64 Rayleigh quotient per site step, looser canonical orthogonalisation
 inline bool reduced(const sp_handle* h) { return h->precision != SP_FP64; }
 // canonical orthogonalisation of the projected metric: eigenvalues below
-// drop x the largest are discarded; the threshold sits about two orders
-// above the relative noise of the products (FP64 ~1e-15, FP32 ~1e-7,
-// split BF16 ~1e-5)
+// drop x the largest are discarded; the threshold sits above the relative
+// noise of the products (FP64 ~1e-15, FP32 ~1e-7, split BF16 ~5e-6) by two
+// orders, one order for split BF16 (1e-3 there slowed the descent of the
+// sweeps by discarding directions of small spin-S weight)
 inline double metric_drop(const sp_handle* h) {
-    return h->precision == SP_FP64 ? 1e-10 : (h->precision == SP_FP32 ? 1e-5 : 1e-3);
+    return h->precision == SP_FP64 ? 1e-10 : (h->precision == SP_FP32 ? 1e-5 : 1e-4);
 }
 
 // a learned Davidson preconditioner and its training pairs (one device)
