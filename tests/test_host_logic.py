@@ -132,12 +132,12 @@ class _Tab:
         return W.BlockTable(self.L, self.N, self.twoM, self.bonds).flat()
 
 
-def _init_rc(table, twoS, G, mpo_=None, N=None, path=sp.SP_PATH_TILED):
+def _init_rc(table, twoS, G, mpo_=None, N=None, path=sp.SP_PATH_TILED, precision=sp.SP_FP64):
     """sp_init_mps return code for host-rejected inputs (never reaches HIP)."""
     nsec, sn, s2m, sdim = (np.ascontiguousarray(a, dtype=np.int32) for a in table.flat())
     w, data = mpo_ or sp.mpo_hubbard(table.L, 1.0, 4.0)
     w = np.ascontiguousarray(w, dtype=np.int32)
-    prob = sp._Problem(table.L, 4, table.N if N is None else N, twoS, table.twoM, G, 0, path)
+    prob = sp._Problem(table.L, 4, table.N if N is None else N, twoS, table.twoM, G, precision, path)
     m = sp._Mpo(sp._iptr(w), sp._dptr(data))
     bt = sp._BlockTable(sp._iptr(nsec), sp._iptr(sn), sp._iptr(s2m), sp._iptr(sdim))
     blocks = np.zeros(max(1, W.BlockTable(table.L, table.N, table.twoM, table.bonds).total_size()))
@@ -154,6 +154,19 @@ def test_init_rejects_bad_spin_parity_and_range():
     assert _init_rc(tab, 0, 0)[0] == sp.SP_EINVAL            # G < 1
     tab2 = W.make_block_table(4, 4, 2, 8)
     assert _init_rc(tab2, 0, 3)[0] == sp.SP_EINVAL           # |M| > S
+
+
+def test_init_precision_modes():
+    """SP_FP32 and SP_BF16X3 need the tiled path; unknown modes are rejected
+    on the host."""
+    import torch
+    tab = W.make_block_table(4, 4, 0, 8)
+    assert _init_rc(tab, 0, 3, precision=7)[0] == sp.SP_EINVAL
+    for prec in (sp.SP_FP32, sp.SP_BF16X3):
+        rc, msg = _init_rc(tab, 0, 3, precision=prec, path=sp.SP_PATH_PLAIN)
+        assert rc == sp.SP_EINVAL and "tiled" in msg
+        if not torch.cuda.is_available():  # accepted: the call then stops at the first HIP call
+            assert _init_rc(tab, 0, 3, precision=prec)[0] == sp.SP_EHIP
 
 
 def test_init_rejects_inconsistent_block_table():
