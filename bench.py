@@ -85,7 +85,7 @@ def cpu_baseline(wl, mv_per_step):
 def abinitio_runs(sp, W, torch, sweeps=1):
     """Synthetic ab-initio-shaped Hamiltonian (seeded integrals, K=12, N=12,
     S=0, D=128, G=11): FP64 site steps per second of the tiled path (fused
-    kernel where a site fits it, tiled block products elsewhere) against
+    kernel or tiled block products per site, autotuned) against
     the plain path, one warm-up and `sweeps` timed sweeps each, and one
     H_eff x at the centre."""
     wl = W.abinitio_reduced(12, 128, 11)
@@ -98,6 +98,8 @@ def abinitio_runs(sp, W, torch, sweeps=1):
     for name, path, prec, tol in runs:
         log(f"[bench] {wl.name} path={path} {prec}: init")
         st = sp.SPMPS(tab, blocks, mpo, wl.twoS, wl.G, path=path, precision=prec)
+        if path == "tiled":
+            st.autotune(reps=3)  # fused plan or tiled block products, per site, by timing
         plans = [st.heff_plan(k)[0] for k in range(1, wl.K + 1)]
         rc, _ = st.sweep(1, tol=tol)
         torch.cuda.synchronize()

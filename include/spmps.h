@@ -191,13 +191,13 @@ int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r);
  * broken-symmetry starting guesses (Sec. 3). */
 int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_report* r);
 
-/* Autotuner of the fused H_eff kernel (tiled path): for every site, time
- * `reps` applications for each LDS budget of the work-group (36, 72, 108 and
- * 144 KB, which set the rows per task) and keep the fastest plan.  The
- * products are the same to rounding whatever the choice.  Optional outputs
- * (L entries each): the budget in doubles, the rows per task and the time
- * per application in microseconds.  A site where no budget fits keeps the
- * tiled block products (rows 0).  Synchronises. */
+/* Autotuner of the H_eff plans (tiled path): for every site, time `reps`
+ * applications of the fused kernel for each LDS budget of the work-group
+ * (36, 72, 108 and 144 KB, which set the rows per task) and of the LDS-tiled
+ * block products, and keep the fastest.  The products are the same to
+ * rounding whatever the choice.  Optional outputs (L entries each): the
+ * budget in doubles (0: block products), the rows per task (0: block
+ * products) and the time per application in microseconds.  Synchronises. */
 int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* usec_out);
 
 /* Current H_eff plan of a site: rows per task of the fused kernel and its

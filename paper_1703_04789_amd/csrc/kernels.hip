@@ -419,12 +419,17 @@ __global__ __launch_bounds__(kThreads) void k_basis_rotate(const double* __restr
 // or the whole tile (TILE = 32) as 2 x 2 FP64 matrix-core blocks of 16 x 16
 // (v_mfma_f64_16x16x4: lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16)
 // of a 16 x 4 by 4 x 16 step and holds D(4 v + l / 16, l % 16), v < 4).  K is
-// staged through LDS in chunks of 16 with coalesced global loads for either
-// operand layout, zero-padded past the segment and the tile edge.  TILE = 64
+// staged through LDS in chunks of kKC with coalesced global loads for either
+// operand layout, zero-padded past the segment and the tile edge.  The chunk
+// is short (8) so that a 64-thread work-group needs 4 KB of LDS and a CU can
+// hold as many of these latency-bound work-groups as it has wave slots (a
+// chunk of 16 halves that and is 1.3x slower at the ab-initio centre, 32 is
+// 1.8x slower); the chunk size does not change the sequence of 4-deep steps,
+// so results are the same bits for any chunk.  TILE = 64
 // (256 threads) for wide particle-number blocks, 32 (64 threads) for narrow
 // ones; every output accumulates the same sequence of 4-deep matrix-core
 // steps for either tile, so both tiles give the same bits.
-constexpr int kKC = 16;
+constexpr int kKC = 8;
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 template <int TILE>

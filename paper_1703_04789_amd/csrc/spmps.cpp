@@ -3062,6 +3062,15 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         for (int k = 1; k <= h->L; ++k) {
             build_plan(h.get(), k);
             if (h->path == SP_PATH_TILED && !build_fused(h.get(), k)) build_fused(h.get(), k, kHeffLdsMax);
+            if (h->path == SP_PATH_TILED && h->plan[k - 1].h_rows == 1) {
+                // one row per task re-reads the right environment once per
+                // row (wide MPOs): the tiled block products are faster there
+                // (3.6 ms against about 1 ms at the K = 12 ab-initio sites)
+                SitePlan& P1 = h->plan[k - 1];
+                P1.h_rows = 0;
+                P1.h_lds = 0;
+                P1.h_tasks.clear();
+            }
             const SitePlan& P = h->plan[k - 1];
             Tmax = std::max({Tmax, P.Tsize, P.Zsize});
             Vmax = std::max({Vmax, P.Vsize, P.Ztsize});
@@ -3287,9 +3296,34 @@ int sp_autotune(sp_handle* h, int reps, int* budget_out, int* rows_out, double* 
                     best_rc = P.h_rows;
                 }
             }
+            {
+                // the LDS-tiled block products are a candidate too: for wide
+                // MPOs a fused plan of one or two rows per task re-reads the
+                // right environment once per row and can lose to them
+                P.h_rows = 0;
+                P.h_lds = 0;
+                P.h_tasks.clear();
+                validate_fused(h, k);
+                upload_fused(h, k);
+                HIPCK(hipStreamSynchronize(s));
+                const bool bf3 = h->precision == SP_BF16X3;
+                heff_tiled(h, k, x, bf3);  // warm-up (also forms the pre-mixed environment)
+                HIPCK(hipEventRecord(e0, s));
+                for (int r = 0; r < reps; ++r) heff_tiled(h, k, x, bf3);
+                HIPCK(hipEventRecord(e1, s));
+                HIPCK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCK(hipEventElapsedTime(&ms, e0, e1));
+                HIPCK(hipGetLastError());
+                if (ms < best) {
+                    best = ms;
+                    best_b = 0;
+                    best_rc = 0;
+                }
+            }
             if (best_b > 0) {
                 build_fused(h, k, best_b);
-            } else {  // no budget fits or launches: the site keeps the plain lists
+            } else {  // the tiled block products were fastest, or no budget fits
                 P.h_rows = 0;
                 P.h_lds = 0;
                 P.h_tasks.clear();

@@ -228,11 +228,12 @@ def test_first_steps_with_restarts_match_oracle(path):
 
 
 def test_autotuned_plans_keep_parity():
-    # the autotuner only changes the rows per task of the fused kernel: the
-    # products stay equal to the oracle's at every site
+    # the autotuner only picks the rows per task of the fused kernel or the
+    # tiled block products: the products stay equal to the oracle's at every
+    # site
     tab, gpu, orc = make_pair(*CASES[3])
     choice = gpu.autotune(reps=2)
-    assert len(choice) == tab.L and all(b > 0 and 1 <= r <= 8 for b, r, _ in choice)
+    assert len(choice) == tab.L and all((b > 0 and 1 <= r <= 8) or (b == 0 and r == 0) for b, r, _ in choice)
     rng = np.random.default_rng(9)
     for k in range(1, tab.L + 1):
         if k > 1:
