@@ -182,9 +182,14 @@ void bgemm(hipStream_t s, const BTask* tasks, int ntasks, const BTerm* terms, Bu
            const double* coef);
 void combine(hipStream_t s, const CTask* tasks, int ntasks, const CTerm* terms, BufSet bufs,
              const double* coef);
+// nsplit > 1: the (g, term) range of every block is cut into nsplit parts
+// summed in a fixed order through part (nsplit x ntot doubles, ntot = the
+// site size); nsplit = 1 sums straight into out
+constexpr int kDiagSplitMax = 8;
 void heff_diag(hipStream_t s, const DiagBlk* blks, int nblk, const DiagTerm* terms,
                const double* lenv, long long lsize, const double* renv, long long rsize,
-               const double* coef, int ncoef, int G, double* out);
+               const double* coef, int ncoef, int G, double* out, int nsplit = 1, double* part = nullptr,
+               long long ntot = 0);
 // Per-sector positive-diagonal QR.  Tasks whose two rows x cols matrices
 // fit kQrLdsMax doubles run in LDS (lds_doubles = the largest 2 rows cols
 // of the list); otherwise they use the scratch buffer in global memory.

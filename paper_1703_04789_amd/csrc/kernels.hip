@@ -133,27 +133,53 @@ __global__ __launch_bounds__(kThreads) void k_combine(const CTask* __restrict__ 
     }
 }
 
+// Diagonal of H_eff (or N_eff) for one packed (N, M) block: for element
+// (r, c), sum over g and the block's terms t of coef * L_g,t(r, r) * R_g,t(c, c).
+// The (g, t) range, g outer, is cut into gridDim.y equal parts: part j sums
+// its range in order and writes part[j * ntot + index] (one part: straight
+// to out), and k_diag_sum adds the parts in ascending j.  Wide MPOs have
+// thousands of terms per block, so one work-group per block would run them
+// all in sequence.
 __global__ __launch_bounds__(kThreads) void k_diag(const DiagBlk* __restrict__ blks,
                                                      const DiagTerm* __restrict__ terms,
                                                      const double* __restrict__ lenv, long long lsize,
                                                      const double* __restrict__ renv, long long rsize,
                                                      const double* __restrict__ coef, int ncoef, int G,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, double* __restrict__ part,
+                                                     long long ntot) {
     const DiagBlk b = blks[blockIdx.x];
     const int n = b.rows * b.cols;
+    const int T = b.t1 - b.t0, nsplit = gridDim.y, j = blockIdx.y;
+    const long long U = (long long)G * T;
+    const long long u0 = U * j / nsplit, u1 = U * (j + 1) / nsplit;
     for (int e = threadIdx.x; e < n; e += kThreads) {
         const int r = e / b.cols, c = e - r * b.cols;
         double acc = 0.0;
-        for (int g = 0; g < G; ++g) {
-            for (int t = b.t0; t < b.t1; ++t) {
+        if (T > 0) {
+            int g = int(u0 / T), t = b.t0 + int(u0 % T);
+            for (long long u = u0; u < u1; ++u) {
                 const DiagTerm tm = terms[t];
                 const double lv = lenv[g * lsize + tm.l_off + (long long)r * (tm.l_ld + 1)];
                 const double rv = renv[g * rsize + tm.r_off + (long long)c * (tm.r_ld + 1)];
                 acc = fma(coef[g * ncoef + tm.cidx], lv * rv, acc);
+                if (++t == b.t1) {
+                    t = b.t0;
+                    ++g;
+                }
             }
         }
-        out[b.x_off + e] = acc;
+        if (nsplit == 1) out[b.x_off + e] = acc;
+        else part[(long long)j * ntot + b.x_off + e] = acc;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_diag_sum(const double* __restrict__ part, int nsplit, long long ntot,
+                                                         double* __restrict__ out) {
+    const long long e = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= ntot) return;
+    double acc = 0.0;
+    for (int j = 0; j < nsplit; ++j) acc += part[(long long)j * ntot + e];
+    out[e] = acc;
 }
 
 // Householder QR of one gathered sector matrix (rows >= cols), column-major
@@ -1381,10 +1407,14 @@ void combine(hipStream_t s, const CTask* tasks, int ntasks, const CTerm* terms, 
 }
 void heff_diag(hipStream_t s, const DiagBlk* blks, int nb, const DiagTerm* terms, const double* lenv,
                long long lsize, const double* renv, long long rsize, const double* coef, int ncoef,
-               int G, double* out) {
-    if (nb > 0)
-        hipLaunchKernelGGL(k_diag, dim3(nb), dim3(kThreads), 0, s, blks, terms, lenv, lsize, renv, rsize,
-                           coef, ncoef, G, out);
+               int G, double* out, int nsplit, double* part, long long ntot) {
+    if (nb <= 0) return;
+    if (nsplit < 1 || (nsplit > 1 && !part)) nsplit = 1;
+    hipLaunchKernelGGL(k_diag, dim3(nb, nsplit), dim3(kThreads), 0, s, blks, terms, lenv, lsize, renv, rsize,
+                       coef, ncoef, G, out, part, ntot);
+    if (nsplit > 1)
+        hipLaunchKernelGGL(k_diag_sum, dim3((unsigned)((ntot + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                           part, nsplit, ntot, out);
 }
 void qr_sectors(hipStream_t s, const QrTask* tasks, int ntasks, const QrPiece* pieces, double* site,
                 double* scratch, double* rout, int lds_doubles) {

@@ -371,6 +371,7 @@ struct sp_handle {
     // for site lt_site while the generation of L[lt_site - 1] is lt_gen
     DArr<double> LT;
     long long LT_cap = 0;
+    DArr<double> diag_part;  // partial sums of the split diagonal (kDiagSplitMax x max_site)
     std::vector<long long> Lgen;
     int lt_site = -1;
     long long lt_gen = -1;
@@ -2042,10 +2043,19 @@ void diag(sp_handle* h, int k, double* dh, double* dn) {
     SitePlan& P = h->plan[k - 1];
     const EnvLayout& el = h->env[k - 1];
     const EnvLayout& er = h->env[k];
+    // wide MPOs: cut each block's (g, term) range into parts summed in a
+    // fixed order, so that a block's thousands of terms run in parallel
+    auto split = [&](const std::vector<spk::DiagBlk>& bl) {
+        int tmax = 0;
+        for (const spk::DiagBlk& d : bl) tmax = std::max(tmax, d.t1 - d.t0);
+        const long long u = (long long)h->G * tmax / 1024;
+        return int(std::min<long long>(std::max<long long>(u, 1), spk::kDiagSplitMax));
+    };
+    const long long ntot = h->sites[k - 1].size;
     spk::heff_diag(h->stream, P.ddblk_h.p, int(P.dblk_h.size()), P.ddterm_h.p, h->envL[k - 1].p, el.size,
-                   h->envR[k].p, er.size, P.coef.p, P.nc, h->G, dh);
+                   h->envR[k].p, er.size, P.coef.p, P.nc, h->G, dh, split(P.dblk_h), h->diag_part.p, ntot);
     spk::heff_diag(h->stream, P.ddblk_n.p, int(P.dblk_n.size()), P.ddterm_n.p, h->envL[k - 1].p, el.size,
-                   h->envR[k].p, er.size, P.coef.p, P.nc, h->G, dn);
+                   h->envR[k].p, er.size, P.coef.p, P.nc, h->G, dn, split(P.dblk_n), h->diag_part.p, ntot);
 }
 
 // positive-diagonal QR per right sector of site k, R pushed into site k+1
@@ -3096,6 +3106,7 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         h->T.alloc(h->T_cap);
         h->V.alloc(h->V_cap);
         h->LT.alloc(h->LT_cap);
+        h->diag_part.alloc(size_t(spk::kDiagSplitMax) * std::max(1LL, h->max_site));
         h->qr_scratch.alloc(h->qr_scratch_cap);
         h->qr_r.alloc(h->qr_r_cap);
         h->tmp_site.alloc(h->max_site);
