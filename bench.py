@@ -280,8 +280,9 @@ def main():
                     help="skip the batched-states run (8 broken-symmetry Hubbard guesses)")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the learned-preconditioner training and evaluation")
-    ap.add_argument("--heff-workload", default="hubbard", choices=["hubbard", "abinitio"],
-                    help="state of the --heff-only run: the benchmark Hubbard chain or the ab-initio workload")
+    ap.add_argument("--heff-workload", default="hubbard", choices=["hubbard", "abinitio", "abinitio16"],
+                    help="state of the --heff-only run: the benchmark Hubbard chain, the ab-initio workload "
+                         "(K=12, D=128) or a larger ab-initio state (K=16, D=256)")
     ap.add_argument("--heff-only", type=int, default=0,
                     help="only run this many H_eff x applications at the centre site, after a 64 MiB "
                          "device copy of known size (for hardware-counter runs), and exit")
@@ -309,8 +310,8 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        if args.heff_workload == "abinitio":
-            aw = W.abinitio_reduced(12, 128, 11)
+        if args.heff_workload in ("abinitio", "abinitio16"):
+            aw = W.abinitio_reduced(12, 128, 11) if args.heff_workload == "abinitio" else W.abinitio_reduced(16, 256, 11)
             gpu = sp.SPMPS(aw.table(), aw.blocks(), sp.mpo_abinitio(*aw.integrals()), aw.twoS, aw.G, path=args.path,
                            precision=args.precision)
             kc = aw.K // 2
@@ -341,6 +342,11 @@ def main():
             torch.cuda.synchronize()
             log(f"[bench] {args.heff_only} H_eff x applications at site {kc} ({args.path}); "
                 f"site size {x.numel()}, algorithmic flops {gpu.heff_flops(kc):.4e}, plan {gpu.heff_plan(kc)}")
+        if args.heff_workload != "hubbard":
+            prof = gpu.heff_profile(kc, x, y, ny, reps=5)
+            ms = sum(p["ms"] for p in prof.values())
+            log(f"[bench] {args.heff_workload} H_eff x at site {kc}: {ms:.3f} ms, "
+                f"{gpu.heff_flops(kc) / (ms * 1e-3) / 1e12:.3f} TFLOP/s algorithmic")
         gpu.close()
         return
 
@@ -448,7 +454,7 @@ def main():
                    "twoM": wl.twoM, "D": wl.D, "G": wl.G, "seed": wl.seed, "path": f"{args.path} FP64",
                    "davidson": {"tol": args.tol, "max_iter": args.max_iter, "max_sub": args.max_sub,
                                 "keep": args.keep},
-                   "fused_plans": "autotuned per site (sp_autotune, 5 repetitions per LDS budget)"
+                   "fused_plans": "autotuned per site (sp_autotune: the fused kernel at each LDS budget or the tiled block products, 5 repetitions each)"
                    if main_run["tuned"] is not None else "default LDS budget"},
         "site_steps": n_site_steps,
         "matvecs_per_site_step": mv,

@@ -73,6 +73,29 @@ def test_abinitio_heff_all_sites(case, plan):
         assert rel_err(dn.cpu().numpy(), orc.mps.site_packed(k, dn_ref)) < 1e-11, k
 
 
+def test_abinitio_autotuned_plans_keep_parity():
+    # the autotuner chooses per site between fused plans and the tiled block
+    # products; every choice must keep the products equal to the oracle's
+    case = CASES[3]
+    tab, gpu, orc = _pair(*case)
+    choice = gpu.autotune(reps=2)
+    print(f"[autotune] (budget, rows, us) {choice}", flush=True)
+    assert all((b > 0 and 1 <= r <= 8) or (b == 0 and r == 0) for b, r, _ in choice)
+    rng = np.random.default_rng(12)
+    for k in range(1, tab.L + 1):
+        if k > 1:
+            gpu.env_update(k - 1, +1)
+            orc.update_left(k - 1)
+        x = rng.standard_normal(gpu.site_size(k))
+        y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
+        xd = _dev(x)
+        y, ny = torch.empty_like(xd), torch.empty_like(xd)
+        gpu.heff_apply(k, xd, y, ny)
+        torch.cuda.synchronize()
+        assert rel_err(y.cpu().numpy(), orc.mps.site_packed(k, y_ref)) < 1e-11, k
+        assert rel_err(ny.cpu().numpy(), orc.mps.site_packed(k, ny_ref)) < 1e-11, k
+
+
 @pytest.mark.parametrize("case", [CASES[1], CASES[3]])
 def test_abinitio_tiled_product_follows_the_left_environment(case):
     """The tiled products keep the W r mixing of L[k-1] from one product to
