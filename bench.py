@@ -140,8 +140,10 @@ def abinitio_runs(sp, W, torch, sweeps=1):
             "tiled": t, "plain_fp64": p, "fp32": res["fp32"], "bf16x3": res["bf16x3"],
             "speedup_site_steps": t["value"] / p["value"],
             "max_step_dE_tiled_vs_plain": dE,
-            "note": "integrals from the seeded recipe of the 30-orbital workload at 12 orbitals; sites whose "
-                    "particle-number blocks exceed the fused kernel's LDS run the tiled block products"}
+            "note": "integrals from the seeded recipe of the 30-orbital workload at 12 orbitals; the tiled path "
+                    "runs, per site, the fused kernel or the block products from the pre-mixed left environment "
+                    "(autotuned; sites whose particle-number blocks exceed the fused kernel's LDS always run "
+                    "the block products)"}
 
 
 def batch_runs(sp, W, torch, n=8):
