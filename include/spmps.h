@@ -64,13 +64,18 @@ extern "C" {
                              with FP32 accumulation (relative error of
                              order 1e-5); values must lie in FP32 range  */
 
-#define SP_PATH_TILED 0   /* environment updates as LDS-tiled products over
-                             particle-number blocks; H_eff x in one fused
-                             launch per site with per-g partial outputs.
-                             A site whose particle-number block is too wide
-                             for the fused kernel's LDS (large MPO bond
-                             dimensions) runs LDS-tiled FP64 block products
-                             for H_eff x instead, in either precision      */
+#define SP_PATH_TILED 0   /* environment updates as LDS-tiled block products
+                             over particle-number blocks (FP64 matrix
+                             cores); H_eff x per site either in one fused
+                             launch with per-g partial outputs, or as block
+                             products from the left environment with the
+                             rotated MPO mixed in (formed once per L[site-1])
+                             - the latter where a particle-number block is
+                             too wide for the fused kernel's LDS, where the
+                             fused plan has one row per task, or where
+                             sp_autotune / sp_set_heff_plan choose it.  The
+                             block products are FP64 in SP_FP64 and SP_FP32
+                             and split BF16 in SP_BF16X3                  */
 #define SP_PATH_PLAIN 1   /* one work-group per (N, M) block product, the
                              plain FP64 reference path                      */
 
