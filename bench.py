@@ -176,7 +176,8 @@ def batch_runs(sp, W, torch, n=8):
         single_us += 1e3 * h.heff_profile(k, x, y, ny, reps=20)["fused_heff"]["ms"]
     bp = sp.heff_batch_profile(hs, sites, reps=20)
     log(f"[bench] batched H_eff launch: {bp['usec']:.1f} us for {len(hs)} states ({bp['flops'] / bp['usec'] / 1e6:.2f} "
-        f"TFLOP/s), {single_us:.1f} us one state at a time")
+        f"TFLOP/s), {single_us:.1f} us one state at a time; as a HIP graph {bp['graph_usec']:.1f} us "
+        f"(replays exact to {bp['graph_max_diff']:.1e})")
     for h in hs:
         h.close()
     log(f"[bench] batch of {n}: one after another")
@@ -200,7 +201,8 @@ def batch_runs(sp, W, torch, n=8):
                              "frac_fp64_peak": bp["flops"] / (bp["usec"] * 1e-6) / 1e12 / PEAK_FP64_TFLOPS,
                              "gbs": bp["bytes"] / (bp["usec"] * 1e-6) / 1e9,
                              "frac_hbm_peak": bp["bytes"] / (bp["usec"] * 1e-6) / 1e9 / PEAK_HBM_GBS,
-                             "usec_one_state_at_a_time": single_us}}
+                             "usec_one_state_at_a_time": single_us,
+                             "graph_usec": bp["graph_usec"], "graph_replay_max_diff": bp["graph_max_diff"]}}
 
 
 def precond_runs(sp, W, torch):

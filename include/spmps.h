@@ -330,8 +330,13 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
  * partial outputs land in each state's scratch.  out[0]: mean microseconds
  * over `reps` launches (HIP events on the states' stream), out[1]: summed
  * algorithmic flops, out[2]: summed algorithmic bytes (environments and x
- * read once, partials written), out[3]: work-groups per launch.  All states
- * on one device, stream and precision, each listed once.  Synchronises. */
+ * read once, partials written), out[3]: work-groups per launch, out[4]:
+ * mean microseconds per replay of the same launches captured once in a HIP
+ * graph (replayed on a private stream), out[5]: largest difference between
+ * the partials of three checked replays (each after eager work that clears
+ * them) and those of an eager launch (0 when the replays are exact).  All
+ * states on one device, stream and precision, each listed once; out holds
+ * 6 doubles.  Synchronises. */
 int sp_heff_batch_profile(sp_handle** hs, int n, const int* sites, int reps, double* out);
 
 /* Message of the last error on this thread. */

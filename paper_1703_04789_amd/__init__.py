@@ -237,13 +237,15 @@ def mpo_abinitio(h, eri):
 
 
 def heff_batch_profile(states, sites, reps=20):
-    """One batched fused H_eff launch over the states at the given sites:
-    dict(usec, flops, bytes, workgroups)."""
+    """One batched fused H_eff launch over the states at the given sites,
+    eager and as a captured HIP graph: dict(usec, flops, bytes, workgroups,
+    graph_usec, graph_max_diff)."""
     hs = (ctypes.c_void_p * len(states))(*[st._h.value for st in states])
     ks = np.ascontiguousarray(sites, dtype=np.int32)
-    out = np.zeros(4)
+    out = np.zeros(6)
     _check(lib().sp_heff_batch_profile(hs, len(states), _iptr(ks), reps, _dptr(out)))
-    return {"usec": out[0], "flops": out[1], "bytes": out[2], "workgroups": int(out[3])}
+    return {"usec": out[0], "flops": out[1], "bytes": out[2], "workgroups": int(out[3]),
+            "graph_usec": out[4], "graph_max_diff": out[5]}
 
 
 def small_eigh(a):

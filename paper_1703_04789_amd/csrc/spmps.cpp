@@ -3745,14 +3745,15 @@ int sp_heff_batch_profile(sp_handle** hs, int n, const int* sites, int reps, dou
         dtask.upload(all, s);
         HIPCK(hipStreamSynchronize(s));
         const bool f32 = reduced(hs[0]);
-        auto launch = [&]() {
+        auto launch_on = [&](hipStream_t st) {
             for (auto& gr : groups) {
                 const int rc = gr.first;
                 const spk::H3Task* tp = dtask.p + gr.second.first;
-                if (f32) spk::heff3_f32(s, rc, lds_by_rc[rc], tp, gr.second.second, insts[0], dinst.p);
-                else spk::heff3(s, rc, lds_by_rc[rc], tp, gr.second.second, insts[0], dinst.p);
+                if (f32) spk::heff3_f32(st, rc, lds_by_rc[rc], tp, gr.second.second, insts[0], dinst.p);
+                else spk::heff3(st, rc, lds_by_rc[rc], tp, gr.second.second, insts[0], dinst.p);
             }
         };
+        auto launch = [&]() { launch_on(s); };
         launch();  // warm-up
         hipEvent_t e0, e1;
         HIPCK(hipEventCreate(&e0));
@@ -3763,13 +3764,65 @@ int sp_heff_batch_profile(sp_handle** hs, int n, const int* sites, int reps, dou
         HIPCK(hipEventSynchronize(e1));
         float ms = 0.f;
         HIPCK(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         HIPCK(hipGetLastError());
         out[0] = 1e3 * double(ms) / reps;
         out[1] = flops;
         out[2] = bytes;
         out[3] = double(all.size());
+
+        // The same launches captured once in a HIP graph (on a private
+        // stream: the handles' stream may be the null stream) and replayed.
+        // Every checked replay follows eager work that clears the partials,
+        // and its partials must equal the eager launch's bit for bit.
+        std::vector<std::vector<double>> ref(n), got(n);
+        auto partials = [&](std::vector<std::vector<double>>& dst) {
+            for (int i = 0; i < n; ++i) {
+                const size_t m = size_t(hs[i]->G) * hs[i]->sites[sites[i] - 1].size;
+                dst[i].resize(2 * m);
+                HIPCK(hipMemcpy(dst[i].data(), hs[i]->ypart.p, m * sizeof(double), hipMemcpyDeviceToHost));
+                HIPCK(hipMemcpy(dst[i].data() + m, hs[i]->nypart.p, m * sizeof(double), hipMemcpyDeviceToHost));
+            }
+        };
+        launch();
+        HIPCK(hipStreamSynchronize(s));
+        partials(ref);
+        hipStream_t gs = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIPCK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+        HIPCK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        launch_on(gs);
+        HIPCK(hipStreamEndCapture(gs, &graph));
+        HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        double maxdiff = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            for (int i = 0; i < n; ++i) {
+                const long long m = (long long)hs[i]->G * hs[i]->sites[sites[i] - 1].size;
+                spk::fill(s, hs[i]->ypart.p, m, 0.0);
+                spk::fill(s, hs[i]->nypart.p, m, 0.0);
+            }
+            HIPCK(hipStreamSynchronize(s));
+            HIPCK(hipGraphLaunch(exec, gs));
+            HIPCK(hipStreamSynchronize(gs));
+            partials(got);
+            for (int i = 0; i < n; ++i)
+                for (size_t e = 0; e < ref[i].size(); ++e)
+                    maxdiff = std::max(maxdiff, std::fabs(got[i][e] - ref[i][e]));
+        }
+        HIPCK(hipEventRecord(e0, gs));
+        for (int r = 0; r < reps; ++r) HIPCK(hipGraphLaunch(exec, gs));
+        HIPCK(hipEventRecord(e1, gs));
+        HIPCK(hipEventSynchronize(e1));
+        float gms = 0.f;
+        HIPCK(hipEventElapsedTime(&gms, e0, e1));
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(gs);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCK(hipGetLastError());
+        out[4] = 1e3 * double(gms) / reps;
+        out[5] = maxdiff;
         return SP_OK;
     });
 }

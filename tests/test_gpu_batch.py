@@ -94,6 +94,9 @@ def test_batched_heff_profile_reports_the_summed_work():
             h.env_update(j, +1)
     out = sp.heff_batch_profile(hs, sites, reps=3)
     assert out["usec"] > 0 and out["workgroups"] > 0
+    # the launches captured in a HIP graph: three replays, each after eager
+    # work that clears the outputs, reproduce the eager partials exactly
+    assert out["graph_usec"] > 0 and out["graph_max_diff"] == 0.0
     assert abs(out["flops"] - sum(h.heff_flops(k) for h, k in zip(hs, sites))) < 1.0
     with pytest.raises(sp.SpError):
         sp.heff_batch_profile([hs[0], hs[0]], [sites[0], sites[0]])
