@@ -553,17 +553,20 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
 // hi = bf16(v) and lo = bf16(v - hi), round to nearest even, and
 // A B ~ hi_A hi_B + hi_A lo_B + lo_A hi_B (the lo lo term is dropped): about
 // 16 significant bits per operand, so products carry a relative error of
-// order 1e-5.  K is staged in chunks of 32 as bf16 pairs, k contiguous per
-// row of A and per column of B, so that a lane fetches its eight k values of
-// a v_mfma_f32_16x16x32_bf16 step with one 16-byte LDS read (lane l supplies
-// A(l % 16, 8 (l / 16) + t) and B(8 (l / 16) + t, l % 16), t < 8, and holds
-// D(4 (l / 16) + v, l % 16), v < 4).  Tiles, wavefront layout and output
-// addressing as in k_tgemm; values must lie in the FP32 range.
-constexpr int kKC3 = 32;
-constexpr int kKC3Pad = kKC3 + 8;  // bf16 per LDS row (16-byte aligned rows)
-typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+// order 1e-5.  K is staged in chunks of 16 as bf16 pairs, k contiguous per
+// row of A and per column of B, so that a lane fetches its four k values of
+// a v_mfma_f32_16x16x16_bf16 step with one 8-byte LDS read (lane l supplies
+// A(l % 16, 4 (l / 16) + t) and B(4 (l / 16) + t, l % 16), t < 4, and holds
+// D(4 (l / 16) + v, l % 16), v < 4).  The 16-deep steps keep a 64-thread
+// work-group at 5 KB of LDS and 48 VGPRs, so a CU holds as many as it has
+// wave slots (the 32-deep v_mfma_f32_16x16x32_bf16 with chunks of 32 needed
+// 10 KB and 97 VGPRs and was 1.5x slower at the K = 12 ab-initio centre).
+// Tiles, wavefront layout and output addressing as in k_tgemm; values must
+// lie in the FP32 range.
+constexpr int kKC3 = 16;
+constexpr int kKC3Pad = kKC3 + 4;  // bf16 per LDS row (8-byte aligned rows)
 typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline unsigned short bf16_rne(float f) {
     unsigned int u = __float_as_uint(f);
@@ -631,21 +634,21 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm_bf3(const TTa
                 split_bf16(v, Bh[c][k], Bl[c][k]);
             }
             __syncthreads();
-            bf8_t ah[2], al[2], bh[2], bl[2];
+            s4_t ah[2], al[2], bh[2], bl[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                ah[i] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const u4_t*>(&Ah[wr + 16 * i + li][8 * lk]));
-                al[i] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const u4_t*>(&Al[wr + 16 * i + li][8 * lk]));
-                bh[i] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const u4_t*>(&Bh[wc + 16 * i + li][8 * lk]));
-                bl[i] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const u4_t*>(&Bl[wc + 16 * i + li][8 * lk]));
+                ah[i] = *reinterpret_cast<const s4_t*>(&Ah[wr + 16 * i + li][4 * lk]);
+                al[i] = *reinterpret_cast<const s4_t*>(&Al[wr + 16 * i + li][4 * lk]);
+                bh[i] = *reinterpret_cast<const s4_t*>(&Bh[wc + 16 * i + li][4 * lk]);
+                bl[i] = *reinterpret_cast<const s4_t*>(&Bl[wc + 16 * i + li][4 * lk]);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
                 }
             __syncthreads();
         }
