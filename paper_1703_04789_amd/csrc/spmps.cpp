@@ -1214,9 +1214,12 @@ void build_plan(sp_handle* h, int k) {
     // so the channel list of a tile is cut into up to tr_split chunks, each
     // its own work-group writing partial slot (chunk * G + g): the consumers
     // add all tr_split * G slots in a fixed order (slots a tile has no chunk
-    // for are zero-filled before the launch).  tr_split aims at about 8192
-    // work-groups, each with at least 4 channels, so that the extra partial
-    // slots stay few.
+    // for are zero-filled before the launch).  tr_split aims at about 16384
+    // work-groups (two per wave slot of the GPU for the 64-thread tiles: a
+    // work-group's channels run as a chain of dependent chunk loads, so the
+    // chains are cut short; 8192 was 9% and 32768 1% slower at the K = 12
+    // ab-initio centre), each with at least 4 channels, so that the extra
+    // partial slots stay few.
     const long long xs = si.size;
     struct TSegD {
         int a_buf;
@@ -1271,7 +1274,7 @@ void build_plan(sp_handle* h, int k) {
             }
     size_t max_segs = 1;
     for (const TOut& o : outs) max_segs = std::max(max_segs, o.segs.size());
-    const int want = int(std::max<size_t>(1, (8192 + outs.size() - 1) / std::max<size_t>(1, outs.size())));
+    const int want = int(std::max<size_t>(1, (16384 + outs.size() - 1) / std::max<size_t>(1, outs.size())));
     const int kSegChunk = int(std::max<size_t>(4, (max_segs + want - 1) / want));
     P.tr_split = 1;
     for (const TOut& o : outs)
