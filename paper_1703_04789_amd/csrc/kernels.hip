@@ -893,16 +893,39 @@ __global__ __launch_bounds__(kThreads) void k_gather(const int* __restrict__ map
     dst[e] = p >= 0 ? src[p] : 0.0;
 }
 
+// sa += pa[g stride + e], sb += pb[g stride + e] for g = 0..G-1 in order,
+// the loads of U slots issued together (wide sums: the tiled products leave
+// G x tr_split slots, over a hundred)
+template <int U>
+__device__ inline void sum_slots(const double* __restrict__ pa, const double* __restrict__ pb, long long stride,
+                                 int G, long long e, double& sa, double& sb) {
+    int g = 0;
+    for (; g + U <= G; g += U) {
+        double a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = pa[(g + u) * stride + e];
+            b[u] = pb[(g + u) * stride + e];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            sa += a[u];
+            sb += b[u];
+        }
+    }
+    for (; g < G; ++g) {
+        sa += pa[g * stride + e];
+        sb += pb[g * stride + e];
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_gsum2(const double* __restrict__ pa, const double* __restrict__ pb,
                                                       long long stride, int G, int n, double* __restrict__ outa,
                                                       double* __restrict__ outb) {
     const int e = blockIdx.x * kThreads + threadIdx.x;
     if (e >= n) return;
     double sa = 0.0, sb = 0.0;
-    for (int g = 0; g < G; ++g) {
-        sa += pa[g * stride + e];
-        sb += pb[g * stride + e];
-    }
+    sum_slots<16>(pa, pb, stride, G, e, sa, sb);
     outa[e] = sa;
     outb[e] = sb;
 }
@@ -1190,25 +1213,7 @@ __device__ inline void dav_gram_body(double* __restrict__ V, double* __restrict_
         const long long o = (long long)m * ld + e;
         vm = t ? t[e] * inv : V[o];
         if (ypart) {
-            int g = 0;
-            for (; g + 4 <= G; g += 4) {
-                const double a0 = ypart[g * gstride + e], a1 = ypart[(g + 1) * gstride + e];
-                const double a2 = ypart[(g + 2) * gstride + e], a3 = ypart[(g + 3) * gstride + e];
-                const double b0 = nypart[g * gstride + e], b1 = nypart[(g + 1) * gstride + e];
-                const double b2 = nypart[(g + 2) * gstride + e], b3 = nypart[(g + 3) * gstride + e];
-                hm += a0;
-                hm += a1;
-                hm += a2;
-                hm += a3;
-                nm += b0;
-                nm += b1;
-                nm += b2;
-                nm += b3;
-            }
-            for (; g < G; ++g) {
-                hm += ypart[g * gstride + e];
-                nm += nypart[g * gstride + e];
-            }
+            sum_slots<8>(ypart, nypart, gstride, G, e, hm, nm);
         } else {
             hm = HV[o];
             nm = NV[o];
