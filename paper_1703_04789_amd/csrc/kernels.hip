@@ -451,10 +451,12 @@ __global__ __launch_bounds__(kThreads) void k_basis_rotate(const double* __restr
 // hold as many of these latency-bound work-groups as it has wave slots (a
 // chunk of 16 halves that and is 1.3x slower at the ab-initio centre, 32 is
 // 1.8x slower); the chunk size does not change the sequence of 4-deep steps,
-// so results are the same bits for any chunk.  The chunks of all segments
-// run as one sequence in which each chunk's global loads are issued before
-// the products of the previous one (1.14x faster at the ab-initio centre
-// despite 124 VGPRs against 52).  TILE = 64
+// so results are the same bits for any chunk.  In the 64-thread tile the
+// chunks of all segments run as one sequence in which each chunk's global
+// loads are issued before the products of the previous one (1.14x faster at
+// the K = 12 ab-initio centre despite 124 VGPRs against 52); the 256-thread
+// tile keeps the plain loop, since there the extra registers halved the
+// occupancy and the K = 16 centre product went from 4.9 to 5.7 ms.  TILE = 64
 // (256 threads) for wide particle-number blocks, 32 (64 threads) for narrow
 // ones; every output accumulates the same sequence of 4-deep matrix-core
 // steps for either tile, so both tiles give the same bits.
@@ -479,97 +481,149 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-    // the chunks of all segments in order; the global loads of the next
-    // chunk are issued before the products of the current one
-    constexpr int PER = TILE * kKC / NT;
-    static_assert(PER * NT == TILE * kKC, "a chunk is PER values per thread and operand");
-    int s = tk.s0, kb = 0;
-    TSeg sg{};
-    while (s < tk.s1) {
-        sg = segs[s];
-        if (sg.k0 < sg.k1) {
-            kb = sg.k0;
-            break;
-        }
-        ++s;
-    }
-    double ra[PER], rb[PER];
-    int cta = 0, ctb = 0;
-    auto fetch = [&]() {
-        const double cf = coef[sg.cidx];
-        const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
-        const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            const int idx = threadIdx.x + p * NT;
-            int r, k;
-            if (sg.ta == 0) {
-                r = idx / kKC;
-                k = idx % kKC;
-            } else {
-                k = idx / TILE;
-                r = idx % TILE;
+    if constexpr (TILE == 32) {
+        // the chunks of all segments in order; the global loads of the next
+        // chunk are issued before the products of the current one
+        constexpr int PER = TILE * kKC / NT;
+        static_assert(PER * NT == TILE * kKC, "a chunk is PER values per thread and operand");
+        int s = tk.s0, kb = 0;
+        TSeg sg{};
+        while (s < tk.s1) {
+            sg = segs[s];
+            if (sg.k0 < sg.k1) {
+                kb = sg.k0;
+                break;
             }
-            const int gr = tk.r0 + r, gk = kb + k;
-            double v = 0.0;
-            if (gr < tk.M && gk < sg.k1)
-                v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
-            ra[p] = cf * v;
-        }
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            const int idx = threadIdx.x + p * NT;
-            int c, k;
-            if (sg.tb == 0) {
-                k = idx / TILE;
-                c = idx % TILE;
-            } else {
-                c = idx / kKC;
-                k = idx % kKC;
-            }
-            const int gc = tk.c0 + c, gk = kb + k;
-            double v = 0.0;
-            if (gc < tk.N && gk < sg.k1)
-                v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
-            rb[p] = v;
-        }
-        cta = sg.ta;
-        ctb = sg.tb;
-    };
-    if (s < tk.s1) fetch();
-    while (s < tk.s1) {
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            const int idx = threadIdx.x + p * NT;
-            if (cta == 0) As[idx % kKC][idx / kKC] = ra[p];
-            else As[idx / TILE][idx % TILE] = ra[p];
-            if (ctb == 0) Bs[idx / TILE][idx % TILE] = rb[p];
-            else Bs[idx % kKC][idx / kKC] = rb[p];
-        }
-        __syncthreads();
-        kb += kKC;
-        if (kb >= sg.k1) {
             ++s;
-            while (s < tk.s1) {
-                sg = segs[s];
-                if (sg.k0 < sg.k1) {
-                    kb = sg.k0;
-                    break;
+        }
+        double ra[PER], rb[PER];
+        int cta = 0, ctb = 0;
+        auto fetch = [&]() {
+            const double cf = coef[sg.cidx];
+            const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
+            const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
+    #pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int idx = threadIdx.x + p * NT;
+                int r, k;
+                if (sg.ta == 0) {
+                    r = idx / kKC;
+                    k = idx % kKC;
+                } else {
+                    k = idx / TILE;
+                    r = idx % TILE;
                 }
+                const int gr = tk.r0 + r, gk = kb + k;
+                double v = 0.0;
+                if (gr < tk.M && gk < sg.k1)
+                    v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
+                ra[p] = cf * v;
+            }
+    #pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int idx = threadIdx.x + p * NT;
+                int c, k;
+                if (sg.tb == 0) {
+                    k = idx / TILE;
+                    c = idx % TILE;
+                } else {
+                    c = idx / kKC;
+                    k = idx % kKC;
+                }
+                const int gc = tk.c0 + c, gk = kb + k;
+                double v = 0.0;
+                if (gc < tk.N && gk < sg.k1)
+                    v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
+                rb[p] = v;
+            }
+            cta = sg.ta;
+            ctb = sg.tb;
+        };
+        if (s < tk.s1) fetch();
+        while (s < tk.s1) {
+    #pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int idx = threadIdx.x + p * NT;
+                if (cta == 0) As[idx % kKC][idx / kKC] = ra[p];
+                else As[idx / TILE][idx % TILE] = ra[p];
+                if (ctb == 0) Bs[idx / TILE][idx % TILE] = rb[p];
+                else Bs[idx % kKC][idx / kKC] = rb[p];
+            }
+            __syncthreads();
+            kb += kKC;
+            if (kb >= sg.k1) {
                 ++s;
+                while (s < tk.s1) {
+                    sg = segs[s];
+                    if (sg.k0 < sg.k1) {
+                        kb = sg.k0;
+                        break;
+                    }
+                    ++s;
+                }
+            }
+            if (s < tk.s1) fetch();
+    #pragma unroll
+            for (int ks = 0; ks < kKC; ks += 4) {
+                const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
+                const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+    } else {  // 256 threads: the prefetch registers would halve the occupancy
+        for (int s = tk.s0; s < tk.s1; ++s) {
+            const TSeg sg = segs[s];
+            const double cf = coef[sg.cidx];
+            const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
+            const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
+            for (int kb = sg.k0; kb < sg.k1; kb += kKC) {
+                for (int idx = threadIdx.x; idx < TILE * kKC; idx += NT) {
+                    int r, k;
+                    if (sg.ta == 0) {
+                        r = idx / kKC;
+                        k = idx % kKC;
+                    } else {
+                        k = idx / TILE;
+                        r = idx % TILE;
+                    }
+                    const int gr = tk.r0 + r, gk = kb + k;
+                    double v = 0.0;
+                    if (gr < tk.M && gk < sg.k1)
+                        v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
+                    As[k][r] = cf * v;
+                }
+                for (int idx = threadIdx.x; idx < TILE * kKC; idx += NT) {
+                    int c, k;
+                    if (sg.tb == 0) {
+                        k = idx / TILE;
+                        c = idx % TILE;
+                    } else {
+                        c = idx / kKC;
+                        k = idx % kKC;
+                    }
+                    const int gc = tk.c0 + c, gk = kb + k;
+                    double v = 0.0;
+                    if (gc < tk.N && gk < sg.k1)
+                        v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
+                    Bs[k][c] = v;
+                }
+                __syncthreads();
+    #pragma unroll
+                for (int ks = 0; ks < kKC; ks += 4) {
+                    const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
+                    const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
+                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                }
+                __syncthreads();
             }
         }
-        if (s < tk.s1) fetch();
-#pragma unroll
-        for (int ks = 0; ks < kKC; ks += 4) {
-            const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
-            const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-        __syncthreads();
     }
     double* C = bufs.p[tk.c_buf] + tk.c_off;
 #pragma unroll
