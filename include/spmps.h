@@ -361,7 +361,7 @@ int sp_mpo_hubbard(int L, double t, double U, int* w, double* data, long long* n
 int sp_mpo_s2(int L, int* w, double* data, long long* n);
 int sp_mpo_identity(int L, int* w, double* data, long long* n);
 
-/* Spin-free property operators (Sec. 2.5), same layout: a single-site
+/* Spin-free property operators (Sec. 2.4), same layout: a single-site
  * operator op (16 doubles, <s|op|t> at s*4+t) at site p; E_pq =
  * sum_sigma a+_{p sigma} a_{q sigma} (the spin-free one-body density
  * operator; E_pp = n_p), bond dimension 4; S_X . S_Y, bond dimension 5

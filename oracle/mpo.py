@@ -111,7 +111,7 @@ def site_op_mpo(L: int, p: int, op: np.ndarray):
 
 
 def epq_mpo(L: int, p: int, q: int):
-    """Spin-free one-body operator E_pq = sum_s a+_{p s} a_{q s} (Sec. 2.5).
+    """Spin-free one-body operator E_pq = sum_s a+_{p s} a_{q s} (Sec. 2.4).
     p == q gives n_p.  For p < q the left factor is a+_s F (F the site
     parity, the Jordan-Wigner string through the rest of site p), F is
     carried over the sites in between and a_s closes the product at q; for

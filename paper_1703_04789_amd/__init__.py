@@ -459,7 +459,7 @@ class SPMPS:
                          for x in range(1, self.L + 1)])
 
     def hubbard_energy_components(self, t, U):
-        """e_p of Sec. 2.5 for the open Hubbard chain: H_p = -t sum_sigma
+        """e_p of Sec. 2.4 for the open Hubbard chain: H_p = -t sum_sigma
         (a+_p a_{p+1} + a+_p a_{p-1}) + U n_{p,a} n_{p,b}, so sum_p e_p = E."""
         dbl = np.zeros(16)
         dbl[15] = 1.0  # n_a n_b on |ab>

@@ -100,3 +100,23 @@ def test_batched_heff_profile_reports_the_summed_work():
     assert abs(out["flops"] - sum(h.heff_flops(k) for h, k in zip(hs, sites))) < 1.0
     with pytest.raises(sp.SpError):
         sp.heff_batch_profile([hs[0], hs[0]], [sites[0], sites[0]])
+
+
+def test_batch_matches_oracle():
+    # three states of different L, N, S and D advanced together, with exact
+    # local solves (the search space covers every local problem): each
+    # state's step energies follow the oracle's own sweep of that state
+    from oracle import mps as omps
+    cases = [(8, 8, 0, 16, 0, 5), (6, 5, 1, 12, 1, 3), (7, 6, 2, 20, 4, 4)]
+    pairs = [make_pair(*c) for c in cases]
+    opts = dict(max_sub=224, max_iter=400)
+    rc, batch = sp.sweep_batch([g for _, g, _ in pairs], 2, **opts)
+    assert rc == sp.SP_OK
+    for (tab, gpu, orc), steps in zip(pairs, batch):
+        ref = omps.sweep(orc, 2, **opts)
+        assert len(steps) == len(ref) == 2 * 2 * (tab.L - 1)
+        for a, b in zip(steps, ref):
+            assert (a["site"], a["dir"]) == (b["site"], b["dir"])
+            assert abs(a["theta"] - b["theta"]) < 1e-8, (a, b)
+        E, _ = gpu.energy()
+        assert abs(E - ref[-1]["theta"]) < 1e-8

@@ -257,3 +257,89 @@ def test_autotune_bench_shape_runs():
     print("[autotune] site: (budget, rows, us)", {k + 1: c for k, c in enumerate(choice)})
     rc, steps = gpu.sweep(1)
     assert np.isfinite(steps[-1]["theta"])
+
+
+def _largest_qr_work(tab):
+    """Largest 2 rows cols over the sector factorisations of every site: QR
+    of the rows gathered per right sector (right-moving) and LQ per left
+    sector (left-moving).  Above 12288 doubles the factorisation runs from
+    global scratch instead of LDS."""
+    best = 0
+    for k in range(1, tab.L + 1):
+        rows_r, rows_l = {}, {}
+        for ia, s, ib, r, c in tab.site_blocks(k):
+            rows_r[ib] = rows_r.get(ib, 0) + r
+            rows_l[ia] = rows_l.get(ia, 0) + c
+        best = max([best] + [2 * r * tab.bonds[k][ib][2] for ib, r in rows_r.items()]
+                   + [2 * r * tab.bonds[k - 1][ia][2] for ia, r in rows_l.items()])
+    return best
+
+
+@pytest.mark.parametrize("path", ["tiled", "plain"])
+def test_gauge_moves_large_sectors(path):
+    # L=12, D=256: some sectors are too large for the LDS-resident
+    # factorisation, so those sites run the global-scratch QR/LQ kernel;
+    # max_iter = 1 keeps every local solve at its start vector, and every
+    # site tensor after the sweep must equal the oracle's (SVD-based) gauge
+    tab, gpu, orc = make_pair(12, 12, 0, 256, 0, 4, U=4.0, seed=1, path=path)
+    assert _largest_qr_work(tab) > 12288
+    rc, steps = gpu.sweep(1, max_iter=1)
+    assert rc == sp.SP_ENOCONV
+    ref = omps.sweep(orc, 1, max_iter=1)
+    assert len(steps) == len(ref) == 2 * (tab.L - 1)
+    for a, b in zip(steps, ref):
+        assert abs(a["theta"] - b["theta"]) < 1e-10 * max(1.0, abs(b["theta"])), (a, b)
+    for k in range(1, tab.L + 1):
+        assert rel_err(gpu.get_site(k), orc.mps.site_packed(k)) < 1e-10, k
+
+
+@pytest.mark.parametrize("twoS", [0, 2])
+def test_bench_shape_spin_targets(twoS):
+    # L=32, U=8, D=256, G=9 with S=0 (seed 2) and S=1 (seed 3): energy, and
+    # H_eff x, N_eff x and their diagonals at the centre site (fused plan)
+    wl = W.hubbard_bench(twoS)
+    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed)
+    assert gpu.status == sp.SP_OK
+    E, p = gpu.energy()
+    Eo, po = orc.energy(1)
+    assert abs(E - Eo) < 1e-9 * max(1, abs(Eo))
+    kc = wl.L // 2
+    _left_envs_to(gpu, orc, kc)
+    n = gpu.site_size(kc)
+    x = np.random.default_rng(11 + twoS).standard_normal(n)
+    y_ref, ny_ref = orc.heff(kc, orc.mps.dense_site(kc, x))
+    xd = _dev(x)
+    y, ny = torch.empty_like(xd), torch.empty_like(xd)
+    gpu.heff_apply(kc, xd, y, ny)
+    dh, dn = torch.empty_like(xd), torch.empty_like(xd)
+    gpu.heff_diag(kc, dh, dn)
+    torch.cuda.synchronize()
+    assert rel_err(y.cpu().numpy(), orc.mps.site_packed(kc, y_ref)) < 1e-11
+    assert rel_err(ny.cpu().numpy(), orc.mps.site_packed(kc, ny_ref)) < 1e-11
+    dh_ref, dn_ref = orc.heff_diag(kc)
+    assert rel_err(dh.cpu().numpy(), orc.mps.site_packed(kc, dh_ref)) < 1e-11
+    assert rel_err(dn.cpu().numpy(), orc.mps.site_packed(kc, dn_ref)) < 1e-11
+
+
+def test_status_inexact_quadrature():
+    # one point below the exact count of Eq. [exactQuadrature]: the state is
+    # built (the projector is approximate) and the warning is returned
+    L, N, twoS = 6, 6, 2
+    G = sp.exact_points(N, L, twoS)
+    assert G == oq.exact_point_count(N, L, twoS)
+    _, exact, _ = make_pair(L, N, 0, 16, twoS, G, oracle=False)
+    assert exact.status == sp.SP_OK
+    _, short, _ = make_pair(L, N, 0, 16, twoS, G - 1, oracle=False)
+    assert short.status == sp.SP_WINEXACT
+    E, p = short.energy()
+    assert np.isfinite(E) and p > 0
+
+
+def test_status_unconverged_sweep():
+    # a single Ritz evaluation per local solve cannot meet the tolerance
+    # (SP_ENOCONV); exact local solves on the same state do
+    tab, gpu, _ = make_pair(6, 6, 0, 16, 0, 4, oracle=False)
+    rc, steps = gpu.sweep(1, max_iter=1)
+    assert rc == sp.SP_ENOCONV and not any(s["converged"] for s in steps)
+    rc, steps = gpu.sweep(1, max_sub=128, max_iter=200)
+    assert rc == sp.SP_OK and all(s["converged"] for s in steps)

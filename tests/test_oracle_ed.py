@@ -25,7 +25,7 @@ def test_two_site_closed_form(U):
     assert abs(_ground(2, 2, 0, U, 2)) < 1e-12
 
 
-@pytest.mark.parametrize("L", [4, 6])
+@pytest.mark.parametrize("L", [4, 6, 8])
 def test_free_chain_closed_form(L):
     # U = 0, N = L: eps_j = -2 cos(pi j/(L+1)); singlet fills the lowest L/2
     # levels twice, the triplet promotes one electron across the Fermi level
@@ -66,6 +66,6 @@ def test_abinitio_reduces_to_hubbard():
         np.testing.assert_allclose(A, B, atol=1e-13)
 
 
-@pytest.mark.parametrize("case", [c for c in ED["cases"] if c["L"] <= 6])
+@pytest.mark.parametrize("case", ED["cases"])
 def test_stored_ed_energies(case):
     assert abs(_ground(case["L"], case["N"], case["twoM"], case["U"], case["twoS"]) - case["E"]) < 1e-10

@@ -1,4 +1,4 @@
-"""Spin-free properties (Sec. 2.5, Eq. [PropSpinFree]) in the oracle and the
+"""Spin-free properties (Sec. 2.4, Eq. [PropSpinFree]) in the oracle and the
 library's operator builders.
 
 Pins: the operator MPOs contract to the Jordan-Wigner operators built
