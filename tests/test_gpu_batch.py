@@ -103,13 +103,16 @@ def test_batched_heff_profile_reports_the_summed_work():
 
 
 def test_batch_matches_oracle():
-    # three states of different L, N, S and D advanced together, with exact
-    # local solves (the search space covers every local problem): each
-    # state's step energies follow the oracle's own sweep of that state
+    # three states of different L, N, S, M and D advanced together, with
+    # exact local solves (the search space covers every local problem): each
+    # state's step energies follow the oracle's own sweep of that state.
+    # The cases are ones whose two-sweep trajectory is stable: a 1e-13
+    # relative change of the initial blocks moves the oracle's step energies
+    # by at most 3e-11 (some states of tiny spin-S weight amplify it to 1e-3)
     from oracle import mps as omps
-    cases = [(8, 8, 0, 16, 0, 5), (6, 5, 1, 12, 1, 3), (7, 6, 2, 20, 4, 4)]
+    cases = [(8, 8, 0, 16, 0, 5), (6, 5, 1, 12, 1, 3), (6, 6, 2, 16, 4, 4)]
     pairs = [make_pair(*c) for c in cases]
-    opts = dict(max_sub=224, max_iter=400)
+    opts = dict(max_sub=128, max_iter=200)
     rc, batch = sp.sweep_batch([g for _, g, _ in pairs], 2, **opts)
     assert rc == sp.SP_OK
     for (tab, gpu, orc), steps in zip(pairs, batch):
