@@ -173,6 +173,20 @@ int sp_env_update(sp_handle* h, int site, int dir);
  * Asynchronous on the handle's stream. */
 int sp_heff_apply(sp_handle* h, int site, const double* x, double* y, double* ny);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = H_eff x and ny = N_eff x as sp_heff_apply (same kernels, the same
+ * bits), with the per-quadrature-point partial outputs held in a fixed
+ * device array of the library (2 x 2^21 doubles, 32 MiB per device, kept
+ * until the process ends) instead of the handle's buffers.  The call
+ * allocates nothing.  Tiled path only (SP_EINVAL otherwise); SP_EINVAL when
+ * the site needs more than 2^21 partial slots per output (G x site size on
+ * a fused site, G x the channel split x site size on the block products).
+ * Every handle on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams, or from several threads) race and must be
+ * ordered by the caller.  Its contents after a call are undefined. */
+int sp_heff_apply_noalloc(sp_handle* h, int site, const double* x, double* y, double* ny);
+
 /* Diagonals of H_eff and N_eff at `site` (device arrays, site size). */
 int sp_heff_diag(sp_handle* h, int site, double* dh, double* dn);
 

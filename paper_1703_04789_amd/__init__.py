@@ -33,7 +33,7 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_mpo_abinitio", "sp_set_heff_plan", "sp_heff_plan", "sp_add_orthogonality",
            "sp_clear_orthogonality", "sp_orthogonality_overlaps", "sp_mlp_create", "sp_mlp_destroy",
            "sp_mlp_get", "sp_mlp_dataset", "sp_mlp_forward", "sp_mlp_train_step", "sp_mlp_train",
-           "sp_set_precond", "sp_heff_batch_profile"]
+           "sp_set_precond", "sp_heff_batch_profile", "sp_heff_apply_noalloc"]
 
 
 class SpError(RuntimeError):
@@ -96,6 +96,7 @@ def lib():
         "sp_init_mps": [P(_Problem), P(_Mpo), P(_BlockTable), dp, vp, P(vp)],
         "sp_env_update": [vp, ctypes.c_int, ctypes.c_int],
         "sp_heff_apply": [vp, ctypes.c_int, vp, vp, vp],
+        "sp_heff_apply_noalloc": [vp, ctypes.c_int, vp, vp, vp],
         "sp_heff_diag": [vp, ctypes.c_int, vp, vp],
         "sp_sweep": [vp, P(_SweepOpts), P(_SweepReport)],
         "sp_sweep_batch": [P(vp), ctypes.c_int, P(_SweepOpts), P(_SweepReport)],
@@ -409,6 +410,11 @@ class SPMPS:
 
     def heff_apply(self, k, x, y, ny):
         _check(lib().sp_heff_apply(self._h, k, _dev(x), _dev(y), _dev(ny)))
+
+    def heff_apply_noalloc(self, k, x, y, ny):
+        """As heff_apply, with the library's fixed device scratch (no
+        allocation in the call)."""
+        _check(lib().sp_heff_apply_noalloc(self._h, k, _dev(x), _dev(y), _dev(ny)))
 
     def heff_diag(self, k, dh, dn):
         _check(lib().sp_heff_diag(self._h, k, _dev(dh), _dev(dn)))

@@ -1907,7 +1907,8 @@ spk::BufSet bufset(sp_handle* h, int k, const double* x, double* y, double* ny, 
 void check_site(const sp_handle* h, int k) { SP_REQUIRE(k >= 1 && k <= h->L, "site out of range"); }
 
 // the fused-kernel instance descriptor of site k applied to x
-spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32) {
+// (yp, nyp: the per-g partial slots; null = the handle's own)
+spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32, double* yp = nullptr, double* nyp = nullptr) {
     SitePlan& P = h->plan[k - 1];
     spk::H3Inst I{};
     I.blks = P.dh_blks.p;
@@ -1927,8 +1928,8 @@ spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32) {
     I.Rsz = h->env[k].size;
     I.x = x;
     I.coef = P.coef.p;
-    I.ypart = h->ypart.p;
-    I.nypart = h->nypart.p;
+    I.ypart = yp ? yp : h->ypart.p;
+    I.nypart = nyp ? nyp : h->nypart.p;
     I.n = h->sites[k - 1].size;
     I.nc = P.nc;
     return I;
@@ -1941,10 +1942,13 @@ spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32) {
 // L_g x: the pre-mixed environment depends only on L[k-1] and is built once
 // per local problem (the first product after L[k-1] changes), so each
 // product is two block-product launches and no mixing pass.
-void heff_tiled(sp_handle* h, int k, const double* x, bool bf3 = false) {
+void heff_tiled(sp_handle* h, int k, const double* x, bool bf3 = false, double* yp = nullptr,
+                double* nyp = nullptr) {
     SitePlan& P = h->plan[k - 1];
     hipStream_t s = h->stream;
-    const spk::BufSet b = bufset(h, k, h->Xd.p, h->ypart.p, h->nypart.p, nullptr);
+    if (!yp) yp = h->ypart.p;
+    if (!nyp) nyp = h->nypart.p;
+    const spk::BufSet b = bufset(h, k, h->Xd.p, yp, nyp, nullptr);
     spk::gather(s, P.xmap.p, x, h->Xd.p, P.Xd_size);
     if (h->lt_site != k || h->lt_gen != h->Lgen[k - 1]) {  // once per left environment and site
         P.premix.launch(s, b, P.coef.p);
@@ -1955,8 +1959,8 @@ void heff_tiled(sp_handle* h, int k, const double* x, bool bf3 = false) {
     P.t_leftv.launch(s, b, P.coef.p, P.xmap.p, bf3);
     if (P.tr_split > 1) {  // slots without a chunk of some tile stay zero
         const long long nslot = (long long)P.tr_split * h->G * h->sites[k - 1].size;
-        spk::fill(s, h->ypart.p, nslot, 0.0);
-        spk::fill(s, h->nypart.p, nslot, 0.0);
+        spk::fill(s, yp, nslot, 0.0);
+        spk::fill(s, nyp, nslot, 0.0);
     }
     P.t_right.launch(s, b, P.coef.p, P.xmap.p, bf3);
 }
@@ -1969,8 +1973,9 @@ int heff_parts(const sp_handle* h, int k) {
 // With defer_gsum on the tiled path only the per-quadrature-point partials
 // (h->ypart, h->nypart) are produced and the function returns true: the
 // caller adds them (the Davidson Gram pass does).
+// yp, nyp: where the partials go (null = the handle's own slots)
 bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, bool defer_gsum = false,
-                bool force_fp64 = false) {
+                bool force_fp64 = false, double* yp = nullptr, double* nyp = nullptr) {
     if (!h->Lvalid[k - 1] || !h->Rvalid[k])
         throw SpError(SP_ESTATE, "H_eff needs L[site-1] and R[site+1]; build them with sp_env_update");
     SitePlan& P = h->plan[k - 1];
@@ -1983,16 +1988,18 @@ bool heff_apply(sp_handle* h, int k, const double* x, double* y, double* ny, boo
         return false;
     }
     const int n = int(h->sites[k - 1].size);
+    if (!yp) yp = h->ypart.p;
+    if (!nyp) nyp = h->nypart.p;
     if (P.h_rows == 0) {
-        heff_tiled(h, k, x, h->precision == SP_BF16X3 && !force_fp64);
+        heff_tiled(h, k, x, h->precision == SP_BF16X3 && !force_fp64, yp, nyp);
     } else {
         const bool f32 = reduced(h) && !force_fp64;
-        const spk::H3Inst I = heff_inst(h, k, x, f32);
+        const spk::H3Inst I = heff_inst(h, k, x, f32, yp, nyp);
         if (f32) spk::heff3_f32(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
         else spk::heff3(s, P.h_rows, P.h_lds, P.dh_tasks.p, int(P.h_tasks.size()), I);
     }
     if (defer_gsum) return true;
-    spk::gsum2(s, h->ypart.p, h->nypart.p, n, heff_parts(h, k), n, y, ny);
+    spk::gsum2(s, yp, nyp, n, heff_parts(h, k), n, y, ny);
     return false;
 }
 
@@ -3003,6 +3010,40 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Allocation-free H_eff x (sp_heff_apply_noalloc): its per-g partial slots
+// live in a fixed device array instead of the handle's buffers.  Every GPU
+// that runs the library holds its own copy until the process ends.  Host code
+// never passes the array's name to a kernel: its device address on each
+// device comes from hipGetSymbolAddress, taken once per device at
+// sp_init_mps with that device current.
+
+constexpr long long kNoAllocSlots = 1LL << 21;  // doubles per output (y, ny): 16 MiB each
+static __device__ __align__(256) double scratch[2 * kNoAllocSlots];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;  // device -> device address of its scratch
+
+// address of the scratch array on `device`; resolved on the first call for
+// the device (with that device current), cached afterwards
+double* noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    int cur = 0;
+    HIPCK(hipGetDevice(&cur));
+    if (cur != device) HIPCK(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) HIPCK(hipSetDevice(cur));
+    hip_check(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) throw SpError(SP_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+    return static_cast<double*>(ptr);
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 
 namespace {
@@ -3128,6 +3169,7 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
         h->center = 1;
         HIPCK(hipStreamSynchronize(h->stream));
         HIPCK(hipGetLastError());
+        if (h->path == SP_PATH_TILED) (void)noalloc_scratch(h->device);
         *out = h.release();
         return (*out)->inexact ? SP_WINEXACT : SP_OK;
     });
@@ -3160,6 +3202,28 @@ int sp_heff_apply(sp_handle* h, int site, const double* x, double* y, double* ny
         check_site(h, site);
         SP_REQUIRE(x != y && x != ny && y != ny, "x, y and ny must not alias");
         heff_apply(h, site, x, y, ny);
+        HIPCK(hipGetLastError());
+        return SP_OK;
+    });
+}
+
+int sp_heff_apply_noalloc(sp_handle* h, int site, const double* x, double* y, double* ny) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(h && x && y && ny, "null argument");
+        check_site(h, site);
+        SP_REQUIRE(x != y && x != ny && y != ny, "x, y and ny must not alias");
+        SP_REQUIRE(h->path == SP_PATH_TILED, "sp_heff_apply_noalloc: tiled path only");
+        const long long need = (long long)heff_parts(h, site) * h->sites[site - 1].size;
+        if (need > kNoAllocSlots)
+            throw SpError(SP_EINVAL, "sp_heff_apply_noalloc: the site needs " + std::to_string(need) +
+                                         " partial slots per output, more than the fixed " +
+                                         std::to_string(kNoAllocSlots));
+        std::unique_lock<std::mutex> lk(g_scratch_mu);
+        auto it = g_scratch_ptr.find(h->device);
+        SP_REQUIRE(it != g_scratch_ptr.end(), "internal: scratch address of the device not resolved");
+        double* base = it->second;
+        lk.unlock();
+        heff_apply(h, site, x, y, ny, false, false, base, base + kNoAllocSlots);
         HIPCK(hipGetLastError());
         return SP_OK;
     });
