@@ -396,6 +396,19 @@ int sp_mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n);
  * more than 4096 channels. */
 int sp_mpo_abinitio(int K, const double* h, const double* eri, int* w, double* data, long long* n);
 
+/* Energy component H_p of orbital p (1-based) for the fragment energies of
+ * Sec. 2.4 (e_p = <H_p P>/<P>, sum_p e_p = E): the terms of the Hamiltonian
+ * above whose first creator acts on orbital p,
+ *   H_p = sum_q h_pq sum_s a+_ps a_qs + 1/2 sum_qrs (pq|rs) sum_st a+_ps a+_rt a_st a_qs,
+ * so sum_p H_p = H and both spin orbitals of p lie in H_p (spin-free in the
+ * expectation of Eq. [PropSpinFree] for real states).  Arguments and output
+ * as for sp_mpo_abinitio; SP_EINVAL if p is outside 1..K.  The Hubbard form
+ * takes the open chain's integrals (h = -t on nearest neighbours,
+ * (pp|pp) = U), i.e. H_p = -t sum_s (a+_ps a_{p+1,s} + a+_ps a_{p-1,s})
+ * + U n_pa n_pb; L in 2..64. */
+int sp_mpo_abinitio_component(int K, int p, const double* h, const double* eri, int* w, double* data, long long* n);
+int sp_mpo_hubbard_component(int L, int p, double t, double U, int* w, double* data, long long* n);
+
 /* Projected expectation value of a spin-free operator given as an MPO,
  * Eq. [PropSpinFree]: <O> = <Psi|O P|Psi> / <Psi|P|Psi> for the current
  * state of h (any canonical centre), through the same environment and

@@ -259,3 +259,26 @@ def abinitio_mpo(h: np.ndarray, eri: np.ndarray):
     """The ab-initio Hamiltonian (Eq. [sqH], chemists' integrals) as an MPO;
     see :func:`terms_mpo` for the construction."""
     return terms_mpo(h.shape[0], abinitio_terms(h, eri))
+
+
+def abinitio_component_mpo(h: np.ndarray, eri: np.ndarray, p: int):
+    """Energy component H_p (orbital p, 1-based) for the fragment energies
+    e_p of Sec. 2.4: the terms of :func:`abinitio_terms` whose leftmost
+    creator acts on orbital p,
+        H_p = sum_q h_pq E_pq + 1/2 sum_qrs (pq|rs) sum_st a+_ps a+_rt a_st a_qs,
+    so that sum_p H_p = H and both spin orbitals of p lie in H_p."""
+    terms = [(c, ops) for (c, ops) in abinitio_terms(h, eri) if ops[0][0] == p]
+    return terms_mpo(h.shape[0], terms)
+
+
+def hubbard_integrals(L: int, t: float, U: float):
+    """The open Hubbard chain as integrals of Eq. [sqH]: h = -t between
+    nearest neighbours, (pp|pp) = U, every other integral zero."""
+    h = np.zeros((L, L))
+    for q in range(L - 1):
+        h[q, q + 1] = h[q + 1, q] = -t
+    eri = np.zeros((L, L, L, L))
+    for q in range(L):
+        eri[q, q, q, q] = U
+    return h, eri
+

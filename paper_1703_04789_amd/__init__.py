@@ -33,7 +33,8 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_mpo_abinitio", "sp_set_heff_plan", "sp_heff_plan", "sp_add_orthogonality",
            "sp_clear_orthogonality", "sp_orthogonality_overlaps", "sp_mlp_create", "sp_mlp_destroy",
            "sp_mlp_get", "sp_mlp_dataset", "sp_mlp_forward", "sp_mlp_train_step", "sp_mlp_train",
-           "sp_set_precond", "sp_heff_batch_profile", "sp_heff_apply_noalloc"]
+           "sp_set_precond", "sp_heff_batch_profile", "sp_heff_apply_noalloc",
+           "sp_mpo_abinitio_component", "sp_mpo_hubbard_component"]
 
 
 class SpError(RuntimeError):
@@ -119,6 +120,9 @@ def lib():
         "sp_mpo_epq": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_spin_corr": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_mpo_abinitio": [ctypes.c_int, dp, dp, ip, dp, P(ctypes.c_longlong)],
+        "sp_mpo_abinitio_component": [ctypes.c_int, ctypes.c_int, dp, dp, ip, dp, P(ctypes.c_longlong)],
+        "sp_mpo_hubbard_component": [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ip, dp,
+                                     P(ctypes.c_longlong)],
         "sp_expect": [vp, P(_Mpo), dp, dp],
         "sp_energy": [vp, dp, dp],
         "sp_destroy": [vp],
@@ -235,6 +239,23 @@ def mpo_abinitio(h, eri):
     if h.shape != (K, K) or eri.shape != (K, K, K, K):
         raise ValueError("h must be K x K and eri K x K x K x K")
     return _mpo(lib().sp_mpo_abinitio, K, _dptr(h), _dptr(eri))
+
+
+def mpo_abinitio_component(h, eri, p):
+    """Energy component H_p (orbital p, 1-based) of the ab-initio
+    Hamiltonian: the terms whose first creator acts on p (sum_p H_p = H)."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    K = h.shape[0]
+    if h.shape != (K, K) or eri.shape != (K, K, K, K):
+        raise ValueError("h must be K x K and eri K x K x K x K")
+    return _mpo(lib().sp_mpo_abinitio_component, K, ctypes.c_int(p), _dptr(h), _dptr(eri))
+
+
+def mpo_hubbard_component(L, p, t, U):
+    """Energy component H_p of the open Hubbard chain (site p, 1-based):
+    -t sum_s (a+_ps a_{p+1,s} + a+_ps a_{p-1,s}) + U n_pa n_pb."""
+    return _mpo(lib().sp_mpo_hubbard_component, L, ctypes.c_int(p), ctypes.c_double(t), ctypes.c_double(U))
 
 
 def heff_batch_profile(states, sites, reps=20):
@@ -465,18 +486,13 @@ class SPMPS:
                          for x in range(1, self.L + 1)])
 
     def hubbard_energy_components(self, t, U):
-        """e_p of Sec. 2.4 for the open Hubbard chain: H_p = -t sum_sigma
-        (a+_p a_{p+1} + a+_p a_{p-1}) + U n_{p,a} n_{p,b}, so sum_p e_p = E."""
-        dbl = np.zeros(16)
-        dbl[15] = 1.0  # n_a n_b on |ab>
-        out = []
-        for p in range(1, self.L + 1):
-            e = U * self.expect(mpo_site_op(self.L, p, dbl))[0]
-            for q in (p - 1, p + 1):
-                if 1 <= q <= self.L:
-                    e += -t * self.expect(mpo_epq(self.L, p, q))[0]
-            out.append(e)
-        return np.array(out)
+        """e_p = <H_p P>/<P> of Sec. 2.4 for the open Hubbard chain, one
+        sp_expect per site with the library's H_p MPO (sum_p e_p = E)."""
+        return np.array([self.expect(mpo_hubbard_component(self.L, p, t, U))[0] for p in range(1, self.L + 1)])
+
+    def abinitio_energy_components(self, h, eri):
+        """e_p = <H_p P>/<P> of Sec. 2.4 for an ab-initio Hamiltonian."""
+        return np.array([self.expect(mpo_abinitio_component(h, eri, p))[0] for p in range(1, self.L + 1)])
 
     def autotune(self, reps=5):
         """Pick the fused-kernel LDS budget (rows per task) of every site by

@@ -329,6 +329,11 @@ int mpo_identity(int L, int* w, double* data, long long* n) {
 // not longer than the right; once it switches it stays in right channels.
 // The coefficient enters on the one edge where a term switches.  With at most
 // two operators on the named side, a bond carries O(K^2) channels.
+//
+// With only_p >= 0 (0-based) only the terms whose first creator acts on
+// orbital only_p are built: the energy component H_p of Sec. 2.4,
+//   H_p = sum_q h_pq sum_s a+_ps a_qs + 1/2 sum_qrs (pq|rs) sum_st a+_ps a+_rt a_st a_qs,
+// so that sum_p H_p = H and every H_p contains both spin orbitals of p.
 
 namespace {
 struct FOp {
@@ -341,8 +346,8 @@ struct FOp {
 using Label = std::vector<int>;
 }  // namespace
 
-int mpo_abinitio(int K, const double* h, const double* eri, int* wout, double* data, long long* n) {
-    if (K < 2 || K > 64 || !h || !eri) return -1;
+int mpo_abinitio(int K, const double* h, const double* eri, int* wout, double* data, long long* n, int only_p) {
+    if (K < 2 || K > 64 || !h || !eri || only_p >= K) return -1;
     const M4 ca = c_alpha(), cb = c_beta(), F = parity(), I = eye4();
     const M4 cda = tr4(ca), cdb = tr4(cb);
     auto local = [&](const FOp& o) -> const M4& {
@@ -350,13 +355,14 @@ int mpo_abinitio(int K, const double* h, const double* eri, int* wout, double* d
     };
     // enumerate the terms: f(coef, ops in operator order)
     auto for_terms = [&](const std::function<void(double, std::vector<FOp>)>& f) {
-        for (int p = 0; p < K; ++p)
+        const int p0 = only_p < 0 ? 0 : only_p, p1 = only_p < 0 ? K : only_p + 1;
+        for (int p = p0; p < p1; ++p)
             for (int q = 0; q < K; ++q) {
                 const double v = h[p * K + q];
                 if (v == 0.0) continue;
                 for (int s = 0; s < 2; ++s) f(v, {{p + 1, s, 1}, {q + 1, s, 0}});
             }
-        for (int p = 0; p < K; ++p)
+        for (int p = p0; p < p1; ++p)
             for (int q = 0; q < K; ++q)
                 for (int r = 0; r < K; ++r)
                     for (int t = 0; t < K; ++t) {

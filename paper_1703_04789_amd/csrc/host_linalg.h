@@ -21,8 +21,10 @@ int mpo_epq(int L, int p, int q, int* w, double* data, long long* n);
 // S_X . S_Y (X == Y: S_X^2)
 int mpo_spin_corr(int L, int X, int Y, int* w, double* data, long long* n);
 // ab-initio Hamiltonian of K orbitals from h (K x K) and (pq|rs) (K^4,
-// index ((p*K + q)*K + r)*K + s); data == nullptr: sizes only
-int mpo_abinitio(int K, const double* h, const double* eri, int* w, double* data, long long* n);
+// index ((p*K + q)*K + r)*K + s); data == nullptr: sizes only.  only_p >= 0
+// (0-based orbital): only the energy component H_p (the terms whose first
+// creator acts on orbital p)
+int mpo_abinitio(int K, const double* h, const double* eri, int* w, double* data, long long* n, int only_p = -1);
 int sym_eigh(int n, double* a, double* ev, double* vec);
 // lowest eigenvalue and its unit eigenvector (tridiagonal QR for the value,
 // inverse iteration for the vector); a is destroyed

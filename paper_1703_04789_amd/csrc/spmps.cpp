@@ -4018,6 +4018,31 @@ int sp_mpo_abinitio(int K, const double* h, const double* eri, int* w, double* d
     });
 }
 
+int sp_mpo_abinitio_component(int K, int p, const double* h, const double* eri, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(K >= 2 && K <= 64 && h && eri && w && n, "bad arguments");
+        SP_REQUIRE(p >= 1 && p <= K, "orbital p out of range");
+        const int r = sph::mpo_abinitio(K, h, eri, w, data, n, p - 1);
+        SP_REQUIRE(r != -2, "ab-initio MPO: a bond needs more than 4096 channels");
+        SP_REQUIRE(r == 0, "ab-initio MPO: internal error");
+        return 0;
+    });
+}
+
+int sp_mpo_hubbard_component(int L, int p, double t, double U, int* w, double* data, long long* n) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(L >= 2 && L <= 64 && w && n, "bad arguments");
+        SP_REQUIRE(p >= 1 && p <= L, "site p out of range");
+        // the open chain as integrals: h = -t on nearest neighbours, (pp|pp) = U
+        std::vector<double> hh(size_t(L) * L, 0.0), eri(size_t(L) * L * L * L, 0.0);
+        for (int q = 0; q + 1 < L; ++q) hh[size_t(q) * L + q + 1] = hh[size_t(q + 1) * L + q] = -t;
+        for (int q = 0; q < L; ++q) eri[((size_t(q) * L + q) * L + q) * L + q] = U;
+        const int r = sph::mpo_abinitio(L, hh.data(), eri.data(), w, data, n, p - 1);
+        SP_REQUIRE(r == 0, "Hubbard component MPO: internal error");
+        return 0;
+    });
+}
+
 int sp_small_gen_lowest(int m, const double* H, const double* N, double drop, double* theta, double* a,
                         int* rank) {
     return guarded([&]() -> int {

@@ -47,3 +47,28 @@ def test_sum_rules_after_sweeps():
     e = gpu.hubbard_energy_components(t, U)
     print(f"[props] E {E:.10f} sum e_p {e.sum():.10f}")
     assert abs(e.sum() - E) < 1e-9
+
+
+def test_energy_components_match_the_oracle():
+    # e_p of Sec. 2.4 (one sp_expect per orbital with the library's H_p MPO)
+    # against the oracle's expectation of its own H_p MPO, and sum_p e_p = E
+    import workloads as W
+    tab, gpu, orc = make_pair(8, 8, 0, 16, 0, 5)
+    blocks = orc.mps.packed()
+    h, eri = om.hubbard_integrals(8, 1.0, 4.0)
+    e = gpu.hubbard_energy_components(1.0, 4.0)
+    for p in range(1, 9):
+        ref, _ = omps.expect(tab, blocks, om.abinitio_component_mpo(h, eri, p), 0, 5)
+        assert abs(e[p - 1] - ref) < 1e-10, p
+    E, _ = gpu.energy()
+    assert abs(e.sum() - E) < 1e-10
+    K = 5
+    h, eri = W.abinitio_integrals(K, 4)
+    tab, gpu, orc = make_pair(K, K, 1, 24, 1, 3, op="abinitio", integrals=(h, eri))
+    blocks = orc.mps.packed()
+    e = gpu.abinitio_energy_components(h, eri)
+    for p in range(1, K + 1):
+        ref, _ = omps.expect(tab, blocks, om.abinitio_component_mpo(h, eri, p), 1, 3)
+        assert abs(e[p - 1] - ref) < 1e-10, p
+    E, _ = gpu.energy()
+    assert abs(e.sum() - E) < 1e-10

@@ -101,3 +101,67 @@ def test_library_operator_builders_match_the_oracle(L):
                     assert a.shape == b.shape and np.abs(a - b).max() < 1e-15
         for a, b in zip(_unpack(L, sp.mpo_site_op(L, p, op)), om.site_op_mpo(L, p, op)):
             assert a.shape == b.shape and np.abs(a - b).max() < 1e-15
+
+
+def _nn(L, p, st):
+    """n_{p alpha} n_{p beta} on the sector basis (diagonal)."""
+    a, b = ed._bit(L, p, 0), ed._bit(L, p, 1)
+    return np.diag([float(((i >> a) & 1) and ((i >> b) & 1)) for i in st])
+
+
+@pytest.mark.parametrize("L,N,twoM", [(4, 4, 0), (5, 4, 2)])
+def test_hubbard_components_are_the_site_terms(L, N, twoM):
+    # H_p of the Hubbard chain = -t sum_s (a+_ps a_{p+1,s} + a+_ps a_{p-1,s})
+    # + U n_pa n_pb, built independently from the occupation-number operators
+    t, U = 1.3, 3.7
+    st = ed.sector_states(L, N, twoM)
+    h, eri = om.hubbard_integrals(L, t, U)
+    tot = np.zeros((len(st), len(st)))
+    for p in range(1, L + 1):
+        ref = U * _nn(L, p, st)
+        for q in (p - 1, p + 1):
+            if 1 <= q <= L:
+                ref = ref - t * ed.epq_operator(L, p, q, st).toarray()
+        got = _sector_dense(om.abinitio_component_mpo(h, eri, p), st)
+        assert np.abs(got - ref).max() < 1e-13, p
+        tot += got
+    assert np.abs(tot - ed.hubbard_hamiltonian(L, t, U, st).toarray()).max() < 1e-13
+
+
+def test_abinitio_components_add_up_to_the_hamiltonian():
+    K = 4
+    h, eri = W.abinitio_integrals(K, 7)
+    for (N, twoM) in [(4, 0), (3, 1)]:
+        st = ed.sector_states(K, N, twoM)
+        tot = sum(_sector_dense(om.abinitio_component_mpo(h, eri, p), st) for p in range(1, K + 1))
+        ref = ed.abinitio_hamiltonian(h, eri, st).toarray()
+        assert np.abs(tot - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_library_component_mpos_match_the_oracle(K):
+    # different automata on each side: compared as operators on every
+    # (N, M) sector
+    h, eri = W.abinitio_integrals(K, 3)
+    for p in range(1, K + 1):
+        a = om.mpo_to_dense(_unpack(K, sp.mpo_abinitio_component(h, eri, p)))
+        b = om.mpo_to_dense(om.abinitio_component_mpo(h, eri, p))
+        assert np.abs(a - b).max() < 1e-12, p
+        hh, ee = om.hubbard_integrals(K, 1.0, 4.0)
+        a = om.mpo_to_dense(_unpack(K, sp.mpo_hubbard_component(K, p, 1.0, 4.0)))
+        b = om.mpo_to_dense(om.abinitio_component_mpo(hh, ee, p))
+        assert np.abs(a - b).max() < 1e-13, p
+    with pytest.raises(sp.SpError):
+        sp.mpo_abinitio_component(h, eri, K + 1)
+
+
+def test_energy_components_sum_to_the_energy_at_a_random_state():
+    L, N, twoS = 6, 6, 2
+    tab = W.make_block_table(L, N, 0, 24)
+    blocks = W.random_blocks(tab, 4)
+    G = oq.exact_point_count(N, L, twoS)
+    h, eri = om.hubbard_integrals(L, 1.0, 4.0)
+    E, _ = omps.expect(tab, blocks, om.hubbard_mpo(L, 1.0, 4.0), twoS, G)
+    e = [omps.expect(tab, blocks, om.abinitio_component_mpo(h, eri, p), twoS, G)[0] for p in range(1, L + 1)]
+    assert abs(sum(e) - E) < 1e-10
+
