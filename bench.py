@@ -51,35 +51,107 @@ def measured_traffic(rows):
     return float(m_b.group(1))
 
 
+def host_cpu():
+    """Cores this process may use and the CPU model (Linux)."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return cores, model
+
+
 def cpu_baseline(wl, mv_per_step):
-    """The oracle on a bounded sample of the same workload: its set-up (right
-    canonical form and right environments), left environments to the centre,
-    then one H_eff x + N_eff x and one environment update at the centre.
-    Rate = 1 / (mean matvecs per site step * t_matvec + t_env)."""
+    """The oracle on a bounded sample of the same workload, timed on the host
+    cores: its set-up (right canonical form and right environments) and left
+    environments to the centre, one untimed H_eff x + N_eff x, then the
+    median of 5 H_eff x + N_eff x with NumPy's BLAS on every core and of 3 on
+    one thread, and one environment update at the centre.  Site steps per
+    second are extrapolated from these: 1 / (mean matvecs per site step of
+    the GPU run x t_matvec + t_env)."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import mpo as ompo, mps as omps
+    nproc, model = host_cpu()
+    # BLAS threads as configured for this process (OMP_NUM_THREADS and the
+    # like); the many-thread leg runs with them
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     tab = wl.table()
     t0 = time.perf_counter()
     orc = omps.SPMPSOracle(tab, wl.blocks(), ompo.hubbard_mpo(wl.L, wl.t, wl.U), wl.twoS, wl.G)
     kc = wl.L // 2
     for j in range(1, kc):
         orc.update_left(j)
-    t1 = time.perf_counter()
+    t_setup = time.perf_counter() - t0
     x = orc.mps.A[kc - 1]
-    orc.heff(kc, x)
-    t2 = time.perf_counter()
-    orc.update_left(kc)
-    t3 = time.perf_counter()
-    t_mv, t_env = t2 - t1, t3 - t2
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    legs = {}
+    with threadpool_limits(limits=cores):
+        orc.heff(kc, x)  # warm-up
+        for leg, reps, lim in (("blas_threads", 5, cores), ("one_thread", 3, 1)):
+            with threadpool_limits(limits=lim):
+                ts = []
+                for _ in range(reps):
+                    a = time.perf_counter()
+                    orc.heff(kc, x)
+                    ts.append(time.perf_counter() - a)
+            legs[leg] = {"threads": lim, "heff_s_median": float(np.median(ts)), "heff_s_all": ts}
+        a = time.perf_counter()
+        orc.update_left(kc)
+        t_env = time.perf_counter() - a
+    t_mv = legs["blas_threads"]["heff_s_median"]
     rate = 1.0 / (mv_per_step * t_mv + t_env)
-    log(f"[cpu] oracle set-up {t1 - t0:.1f}s, matvec {t_mv:.2f}s, env update {t_env:.2f}s")
-    return {"value": rate, "unit": "site steps/s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle set-up + left environments to site {kc} ({t1 - t0:.1f}s), then one "
-                       f"H_eff x/N_eff x ({t_mv:.2f}s) and one environment update ({t_env:.2f}s) at site {kc}; "
-                       f"rate = 1/({mv_per_step:.1f} matvecs per site step x t_matvec + t_env)")}
+    log(f"[cpu] {cores} BLAS threads of {nproc} usable cores ({model}): oracle set-up {t_setup:.1f}s, H_eff x median {t_mv:.3f}s "
+        f"(one thread {legs['one_thread']['heff_s_median']:.3f}s), env update {t_env:.2f}s")
+    return {"value": rate, "unit": "site steps/s", "cores": cores, "kind": "oracle", "cpu_model": model,
+            "nproc": nproc,
+            "extrapolated": True, "heff_s_median": t_mv, "env_update_s": t_env, "setup_s": t_setup,
+            "legs": legs,
+            "sample": (f"{wl.name}: oracle set-up + left environments to site {kc} ({t_setup:.1f}s); after one "
+                       f"warm-up, median of 5 H_eff x/N_eff x at site {kc} with {cores} BLAS threads ({t_mv:.3f}s; median "
+                       f"of 3 on one thread {legs['one_thread']['heff_s_median']:.3f}s) and one environment "
+                       f"update ({t_env:.2f}s); rate extrapolated as 1/({mv_per_step:.1f} matvecs per site step "
+                       f"x t_matvec + t_env)")}
+
+
+def small_sweep_runs(sp, W, torch):
+    """The L=8, D=16, G=5 workload (4 sweeps, default solver settings) timed
+    whole on the GPU and in the oracle on the host: the one size where full
+    sweeps compare directly.  Local solves stop at max_iter on both sides,
+    so the trajectories separate at the 1e-7 level."""
+    from oracle import mpo as ompo, mps as omps
+    wl = W.hubbard_small()
+    tab, blocks = wl.table(), wl.blocks()
+    from threadpoolctl import threadpool_info
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    g = sp.SPMPS(tab, blocks, sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G)
+    g.sweep(1)  # warm-up on a throw-away copy of the state
+    g.close()
+    g = sp.SPMPS(tab, blocks, sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, gs = g.sweep(wl.sweeps)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    g.close()
+    t0 = time.perf_counter()
+    orc = omps.SPMPSOracle(tab, blocks, ompo.hubbard_mpo(wl.L, wl.t, wl.U), wl.twoS, wl.G)
+    os_ = omps.sweep(orc, wl.sweeps)
+    to = time.perf_counter() - t0
+    log(f"[bench] {wl.name}: GPU {len(gs) / tg:.1f} site steps/s, oracle {len(os_) / to:.1f} site steps/s "
+        f"({cores} BLAS threads); E {gs[-1]['theta']:.10f} vs {os_[-1]['theta']:.10f}")
+    return {"workload": wl.name, "sweeps": wl.sweeps, "site_steps": len(gs), "unit": "site steps/s",
+            "gpu": len(gs) / tg, "oracle": len(os_) / to, "oracle_blas_threads": cores,
+            "gpu_energy": gs[-1]["theta"], "oracle_energy": os_[-1]["theta"],
+            "dE_final": gs[-1]["theta"] - os_[-1]["theta"], "ed_energy": -4.235806999129714,
+            "note": "whole sweeps timed on both sides (oracle: set-up included); capped local solves"}
 
 
 def abinitio_runs(sp, W, torch, sweeps=1):
@@ -475,6 +547,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, mv)
+        out["small_sweeps"] = small_sweep_runs(sp, W, torch)
     print(json.dumps(out), flush=True)
 
 
