@@ -218,17 +218,20 @@ def abinitio_runs(sp, W, torch, sweeps=1):
                     "the block products)"}
 
 
-def batch_runs(sp, W, torch, n=8):
-    """Eight broken-symmetry Hubbard guesses (L in 12..32, D <= 256, G=9):
-    one sweep of all of them through sp_sweep_batch against the same sweep
-    of each state one after another (after one warm-up sweep each way)."""
-    ws = W.hubbard_batch(4 * n, D_choices=(64, 128, 256))[:n]
+def batch_runs(sp, W, torch, n=64):
+    """The broken-symmetry guesses of the batched workload (n = 64 Hubbard
+    states, L in 12..32, U in {4, 8}, D in {64, 128, 256, 512}, G=9): one
+    sweep of all of them through sp_sweep_batch against the same sweep of
+    each state one after another (fresh states each way, no warm-up: a sweep
+    of every state is the unit of work), and one batched fused H_eff launch
+    over every state at its centre site against the same products launched
+    state by state."""
+    ws = W.hubbard_batch(n)
 
     def make():
         return [sp.SPMPS(w.table(), w.blocks(), sp.mpo_hubbard(w.L, w.t, w.U), w.twoS, w.G) for w in ws]
     log(f"[bench] batch of {n}: batched")
     hs = make()
-    sp.sweep_batch(hs, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc, st = sp.sweep_batch(hs, 1)
@@ -245,8 +248,8 @@ def batch_runs(sp, W, torch, n=8):
             h.env_update(j, +1)
         x = torch.tensor(h.get_site(k), dtype=torch.float64, device="cuda")
         y, ny = torch.empty_like(x), torch.empty_like(x)
-        single_us += 1e3 * h.heff_profile(k, x, y, ny, reps=20)["fused_heff"]["ms"]
-    bp = sp.heff_batch_profile(hs, sites, reps=20)
+        single_us += 1e3 * h.heff_profile(k, x, y, ny, reps=10)["fused_heff"]["ms"]
+    bp = sp.heff_batch_profile(hs, sites, reps=10)
     log(f"[bench] batched H_eff launch: {bp['usec']:.1f} us for {len(hs)} states ({bp['flops'] / bp['usec'] / 1e6:.2f} "
         f"TFLOP/s), {single_us:.1f} us one state at a time; as a HIP graph {bp['graph_usec']:.1f} us "
         f"(replays exact to {bp['graph_max_diff']:.1e})")
@@ -254,8 +257,6 @@ def batch_runs(sp, W, torch, n=8):
         h.close()
     log(f"[bench] batch of {n}: one after another")
     hs = make()
-    for h in hs:
-        h.sweep(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     es = [h.sweep(1)[1][-1]["theta"] for h in hs]
@@ -264,8 +265,8 @@ def batch_runs(sp, W, torch, n=8):
     for h in hs:
         h.close()
     log(f"[bench] batch of {n}: {nsteps / tb:.1f} vs {nsteps / ts:.1f} site steps/s")
-    return {"workload": f"hubbard_batch n={n} D<=256", "states": [w.name for w in ws], "site_steps": nsteps,
-            "unit": "site steps/s", "batched": nsteps / tb, "one_after_another": nsteps / ts,
+    return {"workload": f"hubbard_batch n={n} L 12..32 D 64..512 G=9", "states": [w.name for w in ws],
+            "site_steps": nsteps, "unit": "site steps/s", "batched": nsteps / tb, "one_after_another": nsteps / ts,
             "speedup": ts / tb, "max_energy_diff": max(abs(a - b) for a, b in zip(eb, es)),
             "batched_heff": {"sites": sites, "usec": bp["usec"], "flops": bp["flops"], "bytes": bp["bytes"],
                              "workgroups": bp["workgroups"],
@@ -279,14 +280,16 @@ def batch_runs(sp, W, torch, n=8):
 
 def precond_runs(sp, W, torch):
     """Learned Davidson preconditioner: record the solver's training pairs on
-    the L=8, D=16 workload and six broken-symmetry guesses (D <= 128; one
-    sweep each, search space 64, 128 iterations), train the 256-wide model
-    for 20 epochs (batches of 16384 rows, Adam, lr 1e-3), then two sweeps of
-    Hubbard L=24, U=6, D=128, G=9 at S=0 and S=2 with the diagonal rule and
-    with the model (search space 32, 64 iterations, tolerance 1e-9)."""
+    the L=8, D=16 workload, the L=32, D=256 workload and six broken-symmetry
+    guesses (D <= 128; one sweep each, search space 64, 128 iterations),
+    train the 256-wide model for 20 epochs (batches of 16384 rows, Adam,
+    lr 1e-3), then two sweeps of Hubbard L=48, U=6, D=512, G=9 at S=0 and
+    S=2 with the diagonal rule and with the model (search space 32, 64
+    iterations, tolerance 1e-9).  G=9 is below the exact point count of
+    L=48, so the projector there is approximate."""
     log("[bench] learned preconditioner: recording")
     model = sp.MLP(W.mlp_init(256, 0), capacity=20_000_000)
-    srcs = [W.hubbard_small()] + W.hubbard_batch(16, D_choices=(64, 128))[:6]
+    srcs = [W.hubbard_small(), W.hubbard_bench(0)] + W.hubbard_batch(16, D_choices=(64, 128))[:6]
     t0 = time.perf_counter()
     for w in srcs:
         st = sp.SPMPS(w.table(), w.blocks(), sp.mpo_hubbard(w.L, w.t, w.U), w.twoS, w.G)
@@ -303,8 +306,8 @@ def precond_runs(sp, W, torch):
     log(f"[bench] learned preconditioner: {rows} pairs, loss {loss[0]:.4f} -> {loss[-1]:.4f}")
     evals = []
     for twoS, seed in ((0, 5), (4, 6)):
-        wl = W.HubbardWorkload(f"hubbard_L24_U6_D128_G9_S{twoS // 2}", L=24, t=1.0, U=6.0, N=24, twoS=twoS,
-                               twoM=0, D=128, G=9, sweeps=2, seed=seed)
+        wl = W.HubbardWorkload(f"hubbard_L48_U6_D512_G9_S{twoS // 2}", L=48, t=1.0, U=6.0, N=48, twoS=twoS,
+                               twoM=0, D=512, G=9, sweeps=2, seed=seed)
         row = {"workload": wl.name}
         for name, use in (("diagonal", None), ("learned", model)):
             st = sp.SPMPS(wl.table(), wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G)
@@ -353,7 +356,7 @@ def main():
     ap.add_argument("--no-abinitio", action="store_true",
                     help="skip the ab-initio-shaped Hamiltonian runs (K=12 orbitals, D=128, G=11)")
     ap.add_argument("--no-batch", action="store_true",
-                    help="skip the batched-states run (8 broken-symmetry Hubbard guesses)")
+                    help="skip the batched-states run (64 broken-symmetry Hubbard guesses, D up to 512)")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the learned-preconditioner training and evaluation")
     ap.add_argument("--heff-workload", default="hubbard", choices=["hubbard", "abinitio", "abinitio16"],
