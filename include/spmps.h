@@ -131,6 +131,14 @@ typedef struct sp_sweep_opts {
     int max_iter;     /* Ritz evaluations per local solve                   */
     int max_sub;      /* search-space size that triggers a restart          */
     int keep;         /* Ritz vectors kept at a restart                     */
+    int host_solve;   /* 0: the Davidson iteration runs on the device (the
+                         FP64 subspace solve in one work-group per state,
+                         every iteration of all states replayed from one
+                         HIP graph) whenever the tiled path, max_sub <= 47,
+                         keep <= 16 and no constraint or learned model
+                         apply; 1: the subspace solve on a host core
+                         between device passes.  Both run the same
+                         algorithm; results agree to rounding            */
 } sp_sweep_opts;
 
 typedef struct sp_step_report {
@@ -422,6 +430,18 @@ int sp_expect(sp_handle* h, const sp_mpo* O, double* value, double* normP);
  * (destroyed), eigenvalues ascending in ev, eigenvectors as columns of vec
  * (n x n row-major). */
 int sp_small_eigh(int n, double* a, double* ev, double* vec);
+
+/* The same subspace solve on the GPU (the device-resident iteration's
+ * kernel, one work-group), for tests: H, N (m x m row-major, host, copied)
+ * with m <= 47.  need_all = 0: theta and a as sp_small_gen_lowest, *rank
+ * the dimension kept.  need_all = 1 (a restart): also the Ritz vectors of
+ * the `keep` lowest values (keep <= 16), orthonormalised (modified
+ * Gram-Schmidt), in Qk (m x nk row-major, nk = min(keep, rank) in *rank),
+ * and H, N overwritten by Qk^T H Qk, Qk^T N Qk in their leading nk x nk
+ * (row stride m).  Synchronises the current device.  SP_ENORM if N
+ * vanishes. */
+int sp_small_gen_lowest_gpu(int m, double* H, double* N, double drop, int need_all, int keep, double* theta,
+                            double* a, double* Qk, int* rank);
 
 /* The Davidson subspace solve: lowest eigenpair of the symmetric pencil
  * H c = theta N c (m x m, row-major, not modified) restricted to the span of

@@ -34,7 +34,7 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_clear_orthogonality", "sp_orthogonality_overlaps", "sp_mlp_create", "sp_mlp_destroy",
            "sp_mlp_get", "sp_mlp_dataset", "sp_mlp_forward", "sp_mlp_train_step", "sp_mlp_train",
            "sp_set_precond", "sp_heff_batch_profile", "sp_heff_apply_noalloc",
-           "sp_mpo_abinitio_component", "sp_mpo_hubbard_component"]
+           "sp_mpo_abinitio_component", "sp_mpo_hubbard_component", "sp_small_gen_lowest_gpu"]
 
 
 class SpError(RuntimeError):
@@ -60,7 +60,7 @@ class _BlockTable(ctypes.Structure):
 
 class _SweepOpts(ctypes.Structure):
     _fields_ = [("n_sweeps", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("max_sub", ctypes.c_int), ("keep", ctypes.c_int)]
+                ("max_sub", ctypes.c_int), ("keep", ctypes.c_int), ("host_solve", ctypes.c_int)]
 
 
 class _StepReport(ctypes.Structure):
@@ -139,6 +139,8 @@ def lib():
         "sp_mpo_identity": [ctypes.c_int, ip, dp, P(ctypes.c_longlong)],
         "sp_small_eigh": [ctypes.c_int, dp, dp, dp],
         "sp_small_gen_lowest": [ctypes.c_int, dp, dp, ctypes.c_double, dp, dp, ctypes.POINTER(ctypes.c_int)],
+        "sp_small_gen_lowest_gpu": [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp,
+                                    ctypes.POINTER(ctypes.c_int)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -276,6 +278,23 @@ def small_eigh(a):
     ev, vec = np.zeros(n), np.zeros((n, n))
     _check(lib().sp_small_eigh(n, _dptr(a), _dptr(ev), _dptr(vec)))
     return ev, vec
+
+
+def small_gen_lowest_gpu(H, N, drop=1e-10, keep=0):
+    """The device-resident iteration's subspace solve on the current GPU:
+    (theta, a, rank) and, with keep > 0 (a restart), also (Qk, H', N') with
+    the orthonormalised lowest Ritz vectors and the rotated pencil."""
+    H = np.array(H, dtype=np.float64, order="C")
+    N = np.array(N, dtype=np.float64, order="C")
+    m = H.shape[0]
+    theta, a, rank = ctypes.c_double(0), np.zeros(m), ctypes.c_int(0)
+    Qk = np.zeros(m * max(1, keep))
+    _check(lib().sp_small_gen_lowest_gpu(m, _dptr(H), _dptr(N), drop, 1 if keep else 0, max(1, keep),
+                                         ctypes.byref(theta), _dptr(a), _dptr(Qk), ctypes.byref(rank)))
+    if not keep:
+        return theta.value, a, rank.value
+    nk = rank.value
+    return theta.value, a, nk, Qk[: m * nk].reshape(m, nk), H[:nk, :nk].copy(), N[:nk, :nk].copy()
 
 
 def small_gen_lowest(H, N, drop=1e-10):
@@ -540,9 +559,11 @@ class SPMPS:
         _check(lib().sp_set_heff_plan(self._h, site, lds_budget, ctypes.byref(rows)))
         return rows.value
 
-    def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8):
-        """Run sweeps; returns (status, list of per-step dicts)."""
-        return sweep_batch([self], n_sweeps, tol, max_iter, max_sub, keep, _single=True)
+    def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, host_solve=False):
+        """Run sweeps; returns (status, list of per-step dicts).  host_solve:
+        the Davidson subspace solve on a host core instead of the
+        device-resident iteration."""
+        return sweep_batch([self], n_sweeps, tol, max_iter, max_sub, keep, _single=True, host_solve=host_solve)
 
 
 def _steps_out(steps, n):
@@ -554,11 +575,11 @@ def _steps_out(steps, n):
     return out
 
 
-def sweep_batch(states, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, _single=False):
+def sweep_batch(states, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, _single=False, host_solve=False):
     """Sweeps of several SPMPS states (``sp_sweep_batch``; one state:
     ``sp_sweep``).  Returns (status, per-state lists of step dicts); for a
     single state with _single=True, (status, step dicts)."""
-    opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep)
+    opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep, 1 if host_solve else 0)
     caps = [max(1, n_sweeps * max(1, 2 * (st.L - 1))) for st in states]
     bufs = [(_StepReport * c)() for c in caps]
     reps = (_SweepReport * len(states))(*[_SweepReport(c, 0, b) for c, b in zip(caps, bufs)])

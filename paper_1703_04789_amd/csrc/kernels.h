@@ -160,6 +160,7 @@ struct H3Inst {
     double* nypart;
     long long n;
     int nc, pad;
+    const int* gate;  // when set, tasks of this instance return at once while *gate == 0
 };
 constexpr int kH3MaxRC = 8;
 constexpr int kH3Threads = 256;  // threads per work-group of the fused kernel
@@ -261,10 +262,46 @@ struct DavInst {
     const double* nypart;
     long long gstride;
     int G, m, n, active, from_t, mr;  // mr: subspace size of the Ritz pass
+    int ext;  // the search space grows this iteration (CGS, H_eff and Gram passes run)
+    // device-resident iteration (davdev.hip): the state the host-driven
+    // solver keeps on the host, here in this record on the device
+    int it, max_iter, max_sub, keep, nk, restart, last, converged, matvecs, err, S, nch;
+    double tol, drop, theta, rnorm, pnorm;
+    double* Ht;      // S x S projected H_eff (device)
+    double* Nt;      // S x S projected N_eff (device)
+    double* Qk;      // restart rotation, m x nk (device)
+    double* aqd;     // where the subspace solve writes (a, theta); aq reads it
+    double* status;  // 8 doubles per instance for the host (mapped memory)
 };
 void bdav_ritz(hipStream_t s, const DavInst* insts, int ninst, int max_n);
+// mode 0, 1: the two CGS passes; mode 2: after a restart, the dots of the
+// correction with the rotated basis (instances without a restart skip it)
 void bdav_cgs(hipStream_t s, const DavInst* insts, int ninst, int max_n, int mode);
 void bdav_gram(hipStream_t s, const DavInst* insts, int ninst, int max_n, int max_m);
+
+// Device-resident Davidson iteration (davdev.hip).  Subspace sizes up to
+// kDevSubMax - 1 vectors and restarts keeping up to kDevKeepMax.
+constexpr int kDevSubMax = 48;
+constexpr int kDevKeepMax = 16;
+// LDS bytes of the subspace solve for m vectors
+__host__ __device__ inline int dev_solve_lds(int m) { return (7 * m * m + 8 * m + 512) * 8; }
+// after the first product and Gram pass of a local solve: Ht[0], Nt[0] from
+// the Gram partials, m = 1, iteration counters reset
+void bdav_start(hipStream_t s, DavInst* insts, int ninst);
+// one subspace solve per active instance (one work-group each): lowest pair
+// of the projected pencil by canonical orthogonalisation, the restart
+// rotation when the space is full, the fields the passes of the iteration read
+void bdav_solve(hipStream_t s, DavInst* insts, int ninst, int max_m);
+// restart: V, HV, NV rotated in place by Qk (instances without a restart skip)
+void bdav_rotate(hipStream_t s, const DavInst* insts, int ninst, int max_n);
+// end of an iteration: residual norm, convergence, the new Gram row, status
+void bdav_update(hipStream_t s, DavInst* insts, int ninst);
+// one instance's subspace solve on host data (tests): H, N m x m row-major;
+// need_all != 0 also forms the restart rotation of `keep` vectors into Qk
+// (m x keep) and the rotated H, N (keep x keep, into H and N); returns the
+// rank kept (0: the metric vanishes)
+int dev_small_solve(int m, double* H, double* N, double drop, int need_all, int keep, double* theta, double* a,
+                    double* Qk);
 
 // Learned Davidson preconditioner (mlp.hip): two-layer perceptron on five
 // features per element; packed weights W1 (H x 5) | b1 (H) | w2 (H) | b2

@@ -887,6 +887,7 @@ __global__ __launch_bounds__(kH3Threads) void k_heff3(const H3Task* __restrict__
     const int blk = tkp->blk;
     if (blk < 0) return;
     const H3Inst I = BATCH ? insts[tkp->inst] : one;
+    if (I.gate && *I.gate == 0) return;
     const H3Col* __restrict__ cols = I.cols;
     const H3LSrc* __restrict__ lsrc = I.lsrc;
     const H3Seg* __restrict__ segs = I.segs;
@@ -1528,16 +1529,17 @@ __global__ __launch_bounds__(kDavWide) void k_bdav_ritz(const DavInst* __restric
 
 __global__ __launch_bounds__(kDavWide) void k_bdav_cgs(const DavInst* __restrict__ insts, int mode) {
     const DavInst I = insts[blockIdx.y];
-    if (!I.active || (int)blockIdx.x >= dav_chunks(I.n)) return;
+    if (!I.active || !I.ext || (int)blockIdx.x >= dav_chunks(I.n)) return;
     const int nch = dav_chunks(I.n);
     if (mode == 0) dav_cgs_body(I.V, I.ld, I.m, I.m, I.pc1, nch, I.t, I.n, I.pc2, 0, blockIdx.x);
-    else dav_cgs_body(I.V, I.ld, I.m, 0, I.pc2, nch, I.t, I.n, I.pn, 1, blockIdx.x);
+    else if (mode == 1) dav_cgs_body(I.V, I.ld, I.m, 0, I.pc2, nch, I.t, I.n, I.pn, 1, blockIdx.x);
+    else if (I.restart) dav_cgs_body(I.V, I.ld, 0, I.m, I.pc2, nch, I.t, I.n, I.pc1, 0, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kThreads) void k_bdav_gram(const DavInst* __restrict__ insts) {
     const DavInst I = insts[blockIdx.z];
     const int nd = 4 * I.m + 2;
-    if (!I.active || (int)blockIdx.x >= dav_chunks(I.n) || (int)blockIdx.y * kGramGroup >= nd) return;
+    if (!I.active || !I.ext || (int)blockIdx.x >= dav_chunks(I.n) || (int)blockIdx.y * kGramGroup >= nd) return;
     dav_gram_body(I.V, I.HV, I.NV, I.ld, I.m, I.n, I.from_t ? I.t : nullptr, I.pn, dav_chunks(I.n), I.tnorm,
                   I.ypart, I.nypart, I.gstride, I.G, I.pg, blockIdx.x, blockIdx.y);
 }

@@ -383,6 +383,7 @@ struct sp_handle {
     int dav_sub = 0;
     long long ld = 0;
     DArr<double> dV, dHV, dNV, dRot, dx, dt, ddh, ddn, dpart, dsmall, dy, dny;
+    DArr<double> dHt, dNt;  // projected H_eff, N_eff of the device-resident solve ((dav_sub+1)^2)
     double* pin = nullptr;  // pinned host staging (device -> host)
     double* pin_dev = nullptr;  // the same memory as kernels address it
     size_t pin_n = 0;
@@ -2247,6 +2248,8 @@ void ensure_davidson(sp_handle* h, int max_sub) {
     const int nch = spk::dav_chunks(int(h->ld));
     const DavLayout lay(max_sub, nch);
     h->dsmall.alloc(lay.total);
+    h->dHt.alloc(size_t(max_sub + 1) * (max_sub + 1));
+    h->dNt.alloc(size_t(max_sub + 1) * (max_sub + 1));
     h->dav_sub = max_sub;
     ensure_pinned(h, lay.total - lay.out + 8, lay.pc1 + 8);
 }
@@ -2725,6 +2728,7 @@ spk::DavInst dav_inst(BatchState& st) {
     I.mr = st.m;
     I.n = st.n;
     I.active = 1;
+    I.ext = 1;
     I.from_t = 1;
     return I;
 }
@@ -3009,6 +3013,281 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Sweeps with the device-resident Davidson iteration.  Every state (one or
+// many) advances in rounds: in a round each unfinished state solves the
+// local problem at its next site.  The first product (V_0) runs eagerly; then
+// one iteration of every state - subspace solve, Ritz pass, restart
+// rotation, CGS2, H_eff of the correction (one fused launch for all states
+// and quadrature points), Gram pass, residual and convergence bookkeeping -
+// is captured once in a HIP graph and replayed until no state iterates (the
+// host polls a mapped status record every few replays).  A state whose solve
+// has ended is idle in the remaining replays of its round: its passes and
+// its fused H_eff tasks return at once.  Then the gauge moves and
+// environment updates of all states run eagerly, and the next round starts.
+
+// whether these settings can use the device-resident iteration
+bool device_solver_ok(const sp_handle* h, const sp_sweep_opts& o) {
+    const int max_sub = std::max(2, o.max_sub);
+    const int keep = std::max(1, std::min(o.keep, max_sub - 1));
+    return h->path == SP_PATH_TILED && h->cons.empty() && !h->mlp_use && !h->mlp_rec && !o.host_solve &&
+           max_sub + 1 <= spk::kDevSubMax && keep <= spk::kDevKeepMax;
+}
+
+spk::DavInst dev_inst(BatchState& st, const sp_sweep_opts& o, int max_sub, int keep, int max_iter, double* status) {
+    sp_handle* h = st.h;
+    const long long ld = h->ld;
+    const DavLayout lay(h->dav_sub, spk::dav_chunks(int(ld)));
+    double* sm = h->dsmall.p;
+    spk::DavInst I{};
+    I.V = h->dV.p;
+    I.HV = h->dHV.p;
+    I.NV = h->dNV.p;
+    I.ld = ld;
+    I.aqd = sm + lay.a;
+    I.aq = I.aqd;
+    I.dh = h->ddh.p;
+    I.dn = h->ddn.p;
+    I.floor_ = 1e-8;
+    I.x = h->dx.p;
+    I.t = h->dt.p;
+    I.part_x = sm + lay.px;
+    I.pc1 = sm + lay.pc1;
+    I.pc2 = sm + lay.pc2;
+    I.pn = sm + lay.pn;
+    I.pg = sm + lay.pg;
+    I.tnorm = sm + lay.tn;
+    I.ypart = h->ypart.p;
+    I.nypart = h->nypart.p;
+    I.gstride = st.n;
+    I.G = heff_parts(h, st.k);
+    I.m = 0;  // the first Gram pass (V_0, products read from the partials)
+    I.mr = 0;
+    I.n = st.n;
+    I.active = 1;
+    I.from_t = 0;
+    I.ext = 1;
+    I.max_iter = max_iter;
+    I.max_sub = max_sub;
+    I.keep = keep;
+    I.S = max_sub + 1;
+    I.nch = st.nch;
+    I.tol = o.tol;
+    I.drop = metric_drop(h);
+    I.Ht = h->dHt.p;
+    I.Nt = h->dNt.p;
+    I.Qk = sm + lay.q;
+    I.status = status;
+    return I;
+}
+
+int sweep_rounds(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<sp_sweep_report*>& reps) {
+    hipStream_t s = B[0].h->stream;
+    const int max_sub = std::max(2, o.max_sub);
+    const int keep = std::max(1, std::min(o.keep, max_sub - 1));
+    const int max_iter = std::max(1, o.max_iter);
+    const int nb = int(B.size());
+    for (auto& st : B) ensure_davidson(st.h, max_sub);
+    BatchBufs bb;
+    // mapped status (8 doubles per state) and pinned staging of the records
+    double *stat = nullptr, *stat_dev = nullptr, *stage = nullptr;
+    HIPCK(hipHostMalloc(&stat, size_t(8) * nb * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCK(hipHostGetDevicePointer((void**)&stat_dev, stat, 0));
+    HIPCK(hipHostMalloc(&stage, size_t(nb) * sizeof(spk::DavInst), hipHostMallocDefault));
+    hipStream_t gs = nullptr;
+    HIPCK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+    struct Cleanup {
+        double *a, *b;
+        hipStream_t g;
+        ~Cleanup() {
+            if (a) (void)hipHostFree(a);
+            if (b) (void)hipHostFree(b);
+            if (g) (void)hipStreamDestroy(g);
+        }
+    } cleanup{stat, stage, gs};
+    DArr<spk::DavInst> dinst;
+    dinst.alloc(nb);
+    DArr<spk::H3Inst> ginst;
+    DArr<spk::H3Task> gtask;
+    int status = SP_OK;
+    const int poll = 4;  // replays between two looks at the status
+    for (;;) {
+        std::vector<int> idx;
+        for (int i = 0; i < nb; ++i)
+            if (B[i].step < B[i].order.size()) idx.push_back(i);
+        if (idx.empty()) break;
+        const int na = int(idx.size());
+        int max_n = 0;
+        // step start: diagonal, V_0 and its products (eager)
+        for (int i : idx) {
+            BatchState& st = B[i];
+            sp_handle* h = st.h;
+            st.k = st.order[st.step].first;
+            st.n = int(h->sites[st.k - 1].size);
+            st.nch = spk::dav_chunks(st.n);
+            st.t0 = std::chrono::steady_clock::now();
+            max_n = std::max(max_n, st.n);
+            diag(h, st.k, h->ddh.p, h->ddn.p);
+            spk::normalize(s, site_ptr(h, st.k), h->dV.p, st.n, nullptr);
+        }
+        {
+            std::vector<int> from_v0(B.size(), 1);
+            batch_heff_mixed(B, idx, from_v0, bb, s);
+        }
+        spk::DavInst* D = reinterpret_cast<spk::DavInst*>(stage);
+        for (int q = 0; q < na; ++q) {
+            for (int c = 0; c < 8; ++c) stat[8 * q + c] = 0.0;
+            D[q] = dev_inst(B[idx[q]], o, max_sub, keep, max_iter, stat_dev + 8 * q);
+        }
+        HIPCK(hipMemcpyAsync(dinst.p, D, size_t(na) * sizeof(spk::DavInst), hipMemcpyHostToDevice, s));
+        spk::bdav_gram(s, dinst.p, na, max_n, 0);
+        spk::bdav_start(s, dinst.p, na);
+        // the fused H_eff of the corrections: instance records and tasks on
+        // the device for the whole round, each instance gated by its record
+        std::vector<spk::H3Inst> hi(na);
+        std::map<int, std::vector<spk::H3Task>> by_rc;
+        std::map<int, int> lds_by_rc;
+        std::vector<int> tiled;
+        const bool f32 = reduced(B[idx[0]].h);
+        for (int q = 0; q < na; ++q) {
+            BatchState& st = B[idx[q]];
+            sp_handle* h = st.h;
+            hi[q] = heff_inst(h, st.k, h->dt.p, f32);
+            hi[q].gate = reinterpret_cast<const int*>(reinterpret_cast<const char*>(dinst.p + q) +
+                                                     offsetof(spk::DavInst, ext));
+            const SitePlan& P = h->plan[st.k - 1];
+            if (P.h_rows == 0) {
+                tiled.push_back(q);
+                continue;
+            }
+            for (spk::H3Task t : P.h_tasks) {
+                if (t.blk < 0) continue;
+                t.inst = q;
+                by_rc[P.h_rows].push_back(t);
+            }
+            lds_by_rc[P.h_rows] = std::max(lds_by_rc[P.h_rows], P.h_lds);
+        }
+        std::vector<spk::H3Task> all;
+        std::vector<std::pair<int, std::pair<size_t, int>>> groups;
+        for (auto& kv : by_rc) {
+            groups.push_back({kv.first, {all.size(), int(kv.second.size())}});
+            all.insert(all.end(), kv.second.begin(), kv.second.end());
+        }
+        if (ginst.n < size_t(na)) ginst.alloc(na);
+        if (gtask.n < all.size()) gtask.alloc(all.size());
+        HIPCK(hipMemcpy(ginst.p, hi.data(), size_t(na) * sizeof(spk::H3Inst), hipMemcpyHostToDevice));
+        if (!all.empty())
+            HIPCK(hipMemcpy(gtask.p, all.data(), all.size() * sizeof(spk::H3Task), hipMemcpyHostToDevice));
+        HIPCK(hipStreamSynchronize(s));
+        // one iteration of every state, captured on the private stream
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        std::vector<hipStream_t> saved;
+        for (int q : tiled) saved.push_back(B[idx[q]].h->stream);
+        for (int q : tiled) B[idx[q]].h->stream = gs;  // their block products launch on the capture stream
+        hipError_t ce = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
+        if (ce == hipSuccess) {
+            spk::bdav_solve(gs, dinst.p, na, max_sub);
+            spk::bdav_ritz(gs, dinst.p, na, max_n);
+            spk::bdav_rotate(gs, dinst.p, na, max_n);
+            spk::bdav_cgs(gs, dinst.p, na, max_n, 2);
+            spk::bdav_cgs(gs, dinst.p, na, max_n, 0);
+            spk::bdav_cgs(gs, dinst.p, na, max_n, 1);
+            for (auto& gr : groups) {
+                const spk::H3Task* tp = gtask.p + gr.second.first;
+                if (f32) spk::heff3_f32(gs, gr.first, lds_by_rc[gr.first], tp, gr.second.second, hi[0], ginst.p);
+                else spk::heff3(gs, gr.first, lds_by_rc[gr.first], tp, gr.second.second, hi[0], ginst.p);
+            }
+            for (int q : tiled) {
+                BatchState& st = B[idx[q]];
+                heff_tiled(st.h, st.k, st.h->dt.p, st.h->precision == SP_BF16X3);
+            }
+            spk::bdav_gram(gs, dinst.p, na, max_n, max_sub);
+            spk::bdav_update(gs, dinst.p, na);
+            ce = hipStreamEndCapture(gs, &graph);
+        }
+        for (size_t j = 0; j < tiled.size(); ++j) B[idx[tiled[j]]].h->stream = saved[j];
+        hip_check(ce, "capture of the Davidson iteration");
+        HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        int replays = 0;
+        bool running = true;
+        while (running && replays < max_iter + 1) {
+            for (int r = 0; r < poll && replays < max_iter + 1; ++r, ++replays) HIPCK(hipGraphLaunch(exec, gs));
+            HIPCK(hipStreamSynchronize(gs));
+            running = false;
+            for (int q = 0; q < na; ++q) running = running || stat[8 * q] != 0.0;
+        }
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        HIPCK(hipGetLastError());
+        if (running) throw SpError(SP_EHIP, "internal: a device-resident local solve did not end");
+        // step end
+        for (int q = 0; q < na; ++q) {
+            const double* sq = stat + 8 * q;
+            const int err = int(sq[7]);
+            if (err == SP_ENORM) throw SpError(SP_ENORM, "projected norm vanishes in the search space");
+            if (err != 0) throw SpError(SP_ENAN, "non-finite value in a local solve");
+            BatchState& st = B[idx[q]];
+            st.out = DavOut{};
+            st.out.converged = sq[1] != 0.0;
+            st.out.iters = int(sq[2]);
+            st.out.matvecs = int(sq[3]);
+            st.out.theta = sq[4];
+            st.out.rnorm = sq[5];
+            st.out.pnorm = sq[6];
+            sp_handle* h = st.h;
+            const int k = st.k, d = st.order[st.step].second, L = h->L;
+            spk::normalize(s, h->dx.p, site_ptr(h, k), st.n, nullptr);
+            if (reduced(h)) {
+                double th, pn, xx;
+                rayleigh64(h, k, site_ptr(h, k), th, pn, xx);
+                if (!std::isfinite(th)) throw SpError(SP_ENAN, "non-finite Rayleigh quotient");
+                st.out.theta = th;
+                st.out.pnorm = pn;
+            }
+            if (L > 1) {
+                if (d > 0) {
+                    move_right(h, k);
+                    env_left(h, k);
+                    h->center = k + 1;
+                } else {
+                    move_left(h, k);
+                    env_right(h, k);
+                    h->center = k - 1;
+                }
+            }
+        }
+        HIPCK(hipStreamSynchronize(s));
+        HIPCK(hipGetLastError());
+        const auto t1 = std::chrono::steady_clock::now();
+        for (int q = 0; q < na; ++q) {
+            const int i = idx[q];
+            BatchState& st = B[i];
+            if (!st.out.converged) status = SP_ENOCONV;
+            sp_sweep_report* r = reps[i];
+            if (r && r->steps && r->n_steps < r->capacity) {
+                sp_step_report& rp = r->steps[r->n_steps++];
+                rp.sweep = int(st.step / st.sweep_len);
+                rp.site = st.k;
+                rp.dir = st.order[st.step].second;
+                rp.iters = st.out.iters;
+                rp.converged = st.out.converged ? 1 : 0;
+                rp.matvecs = st.out.matvecs;
+                rp.theta = st.out.theta;
+                rp.pnorm = st.out.pnorm;
+                rp.rnorm = st.out.rnorm;
+                rp.usec = std::chrono::duration<double, std::micro>(t1 - st.t0).count();
+            }
+            ++st.step;
+        }
+    }
+    return status;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // Allocation-free H_eff x (sp_heff_apply_noalloc): its per-g partial slots
 // live in a fixed device array instead of the handle's buffers.  Every GPU
@@ -3246,6 +3525,19 @@ int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r) {
                    "bad sweep options");
         SP_REQUIRE(h->center == 1, "sweeps start with the canonical centre at site 1");
         if (r) r->n_steps = 0;
+        if (device_solver_ok(h, *o)) {
+            std::vector<BatchState> B(1);
+            std::vector<sp_sweep_report*> reps(1, r);
+            B[0].h = h;
+            const int L = h->L;
+            std::vector<std::pair<int, int>> one;
+            for (int k = 1; k < L; ++k) one.push_back({k, +1});
+            for (int k = L; k >= 2; --k) one.push_back({k, -1});
+            if (L == 1) one.push_back({1, +1});
+            B[0].sweep_len = int(one.size());
+            for (int sw = 0; sw < o->n_sweeps; ++sw) B[0].order.insert(B[0].order.end(), one.begin(), one.end());
+            return sweep_rounds(B, *o, reps);
+        }
         int status = SP_OK;
         const int L = h->L;
         for (int sw = 0; sw < o->n_sweeps; ++sw) {
@@ -3324,7 +3616,9 @@ int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_repor
                 r[i].n_steps = 0;
             }
         }
-        return sweep_batch(B, *o, reps);
+        bool dev = true;
+        for (int i = 0; i < n; ++i) dev = dev && device_solver_ok(hs[i], *o);
+        return dev ? sweep_rounds(B, *o, reps) : sweep_batch(B, *o, reps);
     });
 }
 
@@ -4050,6 +4344,19 @@ int sp_small_gen_lowest(int m, const double* H, const double* N, double drop, do
         const int r = sph::gen_lowest(m, H, N, drop, theta, a, nullptr, rank);
         if (r < 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
         if (r == 0) throw SpError(SP_ENORM, "the metric vanishes");
+        return SP_OK;
+    });
+}
+
+int sp_small_gen_lowest_gpu(int m, double* H, double* N, double drop, int need_all, int keep, double* theta,
+                            double* a, double* Qk, int* rank) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(m >= 1 && m < spk::kDevSubMax && H && N && theta && a && rank, "bad arguments");
+        SP_REQUIRE(!need_all || (Qk && keep >= 1 && keep <= spk::kDevKeepMax), "bad restart arguments");
+        const int r = spk::dev_small_solve(m, H, N, drop, need_all, keep, theta, a, Qk);
+        SP_REQUIRE(r >= 0, "device subspace solve failed");
+        *rank = r;
+        if (r == 0) throw SpError(SP_ENORM, "the projected metric vanishes");
         return SP_OK;
     });
 }
