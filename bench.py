@@ -154,35 +154,28 @@ def small_sweep_runs(sp, W, torch):
             "note": "whole sweeps timed on both sides (oracle: set-up included); capped local solves"}
 
 
-def abinitio_runs(sp, W, torch, sweeps=1):
+def abinitio_runs(sp, W, torch, sweeps=6):
     """Synthetic ab-initio-shaped Hamiltonian (seeded integrals, K=12, N=12,
-    S=0, D=128, G=11): FP64 site steps per second of the tiled path (fused
-    kernel or tiled block products per site, autotuned) against
-    the plain path, one warm-up and `sweeps` timed sweeps each, and one
-    H_eff x at the centre."""
+    S=0, D=128, G=11) with the default per-site plans (no timing-based plan
+    choice, so every precision runs the same kernels at every site):
+      - FP64 tiled path: `sweeps` sweeps, energy after each;
+      - FP32 products: the same number of sweeps, energy difference to the
+        FP64 run after each sweep; its speed-up counts only when the final
+        difference is at most 1e-6;
+      - split-BF16 products: sweeps until the energy reaches the FP64 run's
+        final energy + 1e-6 (at most 2 x `sweeps`): time to that energy
+        against the FP64 time (energies are FP64 Rayleigh quotients, i.e.
+        variational), plus its difference at equal sweep counts;
+      - plain FP64 path: one sweep, against the first FP64 sweep step by
+        step;
+    and one H_eff x at the centre for each."""
     wl = W.abinitio_reduced(12, 128, 11)
     h, eri = wl.integrals()
     mpo = sp.mpo_abinitio(h, eri)
     tab, blocks = wl.table(), wl.blocks()
-    res = {}
-    runs = (("tiled", "tiled", "fp64", 1e-9), ("plain", "plain", "fp64", 1e-9),
-            ("fp32", "tiled", "fp32", 1e-6), ("bf16x3", "tiled", "bf16x3", 1e-5))
-    for name, path, prec, tol in runs:
-        log(f"[bench] {wl.name} path={path} {prec}: init")
-        st = sp.SPMPS(tab, blocks, mpo, wl.twoS, wl.G, path=path, precision=prec)
-        if path == "tiled":
-            st.autotune(reps=3)  # fused plan or tiled block products, per site, by timing
-        plans = [st.heff_plan(k)[0] for k in range(1, wl.K + 1)]
-        rc, _ = st.sweep(1, tol=tol)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        steps = []
-        for _ in range(sweeps):
-            rc, s1 = st.sweep(1, tol=tol)
-            steps += s1
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        kc = wl.K // 2
+    kc = wl.K // 2
+
+    def centre_heff(st):
         for j in range(1, kc):
             st.env_update(j, +1)
         x = torch.tensor(st.get_site(kc), dtype=torch.float64, device="cuda")
@@ -190,32 +183,62 @@ def abinitio_runs(sp, W, torch, sweeps=1):
         prof = st.heff_profile(kc, x, y, ny, reps=10)
         ms = sum(p["ms"] for p in prof.values())
         fl = st.heff_flops(kc)
+        return ms, fl
+
+    def run(path, prec, tol, n_max, target=None):
+        log(f"[bench] {wl.name} path={path} {prec}: init")
+        st = sp.SPMPS(tab, blocks, mpo, wl.twoS, wl.G, path=path, precision=prec)
+        plans = [st.heff_plan(k)[0] for k in range(1, wl.K + 1)]
+        energies, times, steps, t = [], [], [], 0.0
+        for _ in range(n_max):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, s1 = st.sweep(1, tol=tol)
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            energies.append(s1[-1]["theta"])
+            times.append(t)
+            steps += s1
+            if target is not None and energies[-1] <= target:
+                break
+        ms, fl = centre_heff(st)
         st.close()
-        res[name] = {"value": len(steps) / dt, "energy_after_timed_sweeps": steps[-1]["theta"],
-                     "matvecs_per_site_step": float(sum(s["matvecs"] for s in steps) / len(steps)),
-                     "heff_ms_centre": ms, "heff_flops_centre": fl, "heff_tflops_centre": fl / (ms * 1e-3) / 1e12,
-                     "fused_sites": sum(1 for r in plans if r > 0), "steps": steps}
-        if prec != "fp64":
-            res[name].update(solver_tol=tol, dE_vs_fp64_tiled=steps[-1]["theta"] - res["tiled"]["energy_after_timed_sweeps"],
-                             speedup_site_steps_vs_fp64_tiled=res[name]["value"] / res["tiled"]["value"])
-        log(f"[bench] {wl.name} {name}: {res[name]['value']:.2f} site steps/s, H_eff x at site {kc} {ms:.3f} ms "
-            f"({res[name]['heff_tflops_centre']:.3f} TFLOP/s), fused sites {res[name]['fused_sites']}/{wl.K}")
-    t, p = res["tiled"], res["plain"]
-    dE = max(abs(a["theta"] - b["theta"]) for a, b in zip(t["steps"], p["steps"]))
-    for r in res.values():
-        del r["steps"]
-    res["fp32"]["note"] = "fused products in FP32; tiled block products FP64; FP64 Rayleigh quotient per step"
-    res["bf16x3"]["note"] = ("fused products in FP32; tiled block products in split BF16 (hi+lo, three matrix-core "
-                             "products, FP32 accumulation); FP64 Rayleigh quotient per step")
+        r = {"sweeps": len(energies), "seconds": t, "value": len(steps) / t, "energies": energies,
+             "seconds_after_sweep": times, "solver_tol": tol,
+             "matvecs_per_site_step": float(sum(x["matvecs"] for x in steps) / len(steps)),
+             "heff_ms_centre": ms, "heff_flops_centre": fl, "heff_tflops_centre": fl / (ms * 1e-3) / 1e12,
+             "fused_sites": sum(1 for p in plans if p > 0)}
+        log(f"[bench] {wl.name} {path} {prec}: {r['value']:.2f} site steps/s over {len(energies)} sweeps, "
+            f"E {energies[-1]:.10f}, H_eff x at site {kc} {ms:.3f} ms")
+        return r, steps
+
+    t64, s64 = run("tiled", "fp64", 1e-9, sweeps)
+    plain, sp1 = run("plain", "fp64", 1e-9, 1)
+    dE_plain = max(abs(a["theta"] - b["theta"]) for a, b in zip(sp1, s64[:len(sp1)]))
+    f32, _ = run("tiled", "fp32", 1e-6, sweeps)
+    f32["dE_vs_fp64_per_sweep"] = [a - b for a, b in zip(f32["energies"], t64["energies"])]
+    f32["matched"] = abs(f32["dE_vs_fp64_per_sweep"][-1]) <= 1e-6
+    f32["speedup_site_steps_vs_fp64_tiled"] = f32["value"] / t64["value"] if f32["matched"] else None
+    f32["note"] = "fused and tiled products: FP32 fused kernel, FP64 block products; FP64 Rayleigh quotient per step"
+    target = t64["energies"][-1] + 1e-6
+    b16, _ = run("tiled", "bf16x3", 1e-5, 2 * sweeps, target=target)
+    n_eq = min(len(b16["energies"]), len(t64["energies"]))
+    b16["dE_vs_fp64_per_sweep"] = [a - b for a, b in zip(b16["energies"][:n_eq], t64["energies"][:n_eq])]
+    b16["reached_fp64_energy"] = b16["energies"][-1] <= target
+    b16["time_to_fp64_energy_speedup"] = (t64["seconds"] / b16["seconds"]) if b16["reached_fp64_energy"] else None
+    b16["note"] = ("block products in split BF16 (hi+lo, three matrix-core products, FP32 accumulation), fused "
+                   "products FP32, FP64 Rayleigh quotient per step; its looser local solves and metric threshold "
+                   "follow another trajectory, so it is compared by the time to reach the FP64 run's energy "
+                   f"after {sweeps} sweeps (within 1e-6), not at equal sweep counts")
+    log(f"[bench] {wl.name}: FP32 dE {f32['dE_vs_fp64_per_sweep'][-1]:.2e} (matched {f32['matched']}); split BF16 "
+        f"reached the FP64 energy in {b16['sweeps']} sweeps, {b16['seconds']:.2f} s against {t64['seconds']:.2f} s")
     return {"workload": wl.name, "K": wl.K, "N": wl.N, "twoS": wl.twoS, "D": wl.D, "G": wl.G, "seed": wl.seed,
-            "mpo_max_bond": int(max(mpo[0])), "unit": "site steps/s", "dtype": "f64",
-            "tiled": t, "plain_fp64": p, "fp32": res["fp32"], "bf16x3": res["bf16x3"],
-            "speedup_site_steps": t["value"] / p["value"],
-            "max_step_dE_tiled_vs_plain": dE,
-            "note": "integrals from the seeded recipe of the 30-orbital workload at 12 orbitals; the tiled path "
-                    "runs, per site, the fused kernel or the block products from the pre-mixed left environment "
-                    "(autotuned; sites whose particle-number blocks exceed the fused kernel's LDS always run "
-                    "the block products)"}
+            "mpo_max_bond": int(max(mpo[0])), "unit": "site steps/s", "dtype": "f64", "plans": "default per site",
+            "tiled": t64, "plain_fp64": plain, "fp32": f32, "bf16x3": b16,
+            "speedup_site_steps": t64["value"] / plain["value"],
+            "max_step_dE_tiled_vs_plain_first_sweep": dE_plain,
+            "note": "integrals from the seeded recipe of the 30-orbital workload at 12 orbitals; one-site sweeps "
+                    "with a fixed block table descend slowly here (about 1e-3 per sweep after ten sweeps)"}
 
 
 def batch_runs(sp, W, torch, n=64):
@@ -255,6 +278,15 @@ def batch_runs(sp, W, torch, n=64):
         f"(replays exact to {bp['graph_max_diff']:.1e})")
     for h in hs:
         h.close()
+    log(f"[bench] batch of {n}: batched, host-driven subspace solves")
+    hs = make()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, sth = sp.sweep_batch(hs, 1, solver="host")
+    torch.cuda.synchronize()
+    th = time.perf_counter() - t0
+    for h in hs:
+        h.close()
     log(f"[bench] batch of {n}: one after another")
     hs = make()
     torch.cuda.synchronize()
@@ -266,7 +298,9 @@ def batch_runs(sp, W, torch, n=64):
         h.close()
     log(f"[bench] batch of {n}: {nsteps / tb:.1f} vs {nsteps / ts:.1f} site steps/s")
     return {"workload": f"hubbard_batch n={n} L 12..32 D 64..512 G=9", "states": [w.name for w in ws],
-            "site_steps": nsteps, "unit": "site steps/s", "batched": nsteps / tb, "one_after_another": nsteps / ts,
+            "site_steps": nsteps, "unit": "site steps/s", "batched": nsteps / tb,
+            "batched_host_driven": sum(len(x) for x in sth) / th, "one_after_another": nsteps / ts,
+            "batched_driver": "device-resident Davidson iteration (one HIP graph per round for all states)",
             "speedup": ts / tb, "max_energy_diff": max(abs(a - b) for a, b in zip(eb, es)),
             "batched_heff": {"sites": sites, "usec": bp["usec"], "flops": bp["flops"], "bytes": bp["bytes"],
                              "workgroups": bp["workgroups"],
@@ -351,6 +385,8 @@ def main():
                     help="precision of the H_eff products inside the local solves (SP_FP64 / SP_FP32 / SP_BF16X3)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-fp32", action="store_true", help="skip the reduced-precision (SP_FP32) run")
+    ap.add_argument("--no-device", action="store_true",
+                    help="skip the run with the device-resident Davidson iteration")
     ap.add_argument("--fp32-tol", type=float, default=1e-6,
                     help="local-solver residual tolerance of the SP_FP32 run (its products floor near 1e-6)")
     ap.add_argument("--no-abinitio", action="store_true",
@@ -429,8 +465,8 @@ def main():
         gpu.close()
         return
 
-    def run(path, precision="fp64", tol=args.tol):
-        log(f"[bench] {wl.name} path={path} {precision}: init")
+    def run(path, precision="fp64", tol=args.tol, solver="auto", n_steps=args.steps, warmup=args.warmup):
+        log(f"[bench] {wl.name} path={path} {precision} solver={solver}: init")
         gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=path,
                        precision=precision)
         tuned = None
@@ -438,13 +474,15 @@ def main():
             # the fused kernel's LDS budget (rows per task) of every site, by timing
             tuned = gpu.autotune(reps=5)
         kw = dict(tol=tol, max_iter=args.max_iter, max_sub=args.max_sub, keep=args.keep)
-        for i in range(args.warmup):
+        if path == "tiled":
+            kw["solver"] = solver
+        for i in range(warmup):
             rc, st = gpu.sweep(1, **kw)
             log(f"[bench] {path} warmup sweep {i}: E={st[-1]['theta']:.10f}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         steps = []
-        for i in range(args.steps):
+        for i in range(n_steps):
             rc, st = gpu.sweep(1, **kw)
             steps += st
             log(f"[bench] {path} timed sweep {i}: E={st[-1]['theta']:.10f}")
@@ -483,6 +521,18 @@ def main():
                  "max_step_dE_vs_this_path": max(abs(a["theta"] - b["theta"]) for a, b in zip(steps, pr["steps"])),
                  "note": "step energies of the two paths differ while local solves stop at max_iter (rounding "
                          "steers the truncated Davidson runs apart); the energies reached agree"}
+    device_resident = None
+    if args.path == "tiled" and not args.no_device:
+        dr = run("tiled", solver="device", n_steps=min(args.steps, 3), warmup=1)
+        iters = sum(s["iters"] for s in dr["steps"])
+        device_resident = {"value": len(dr["steps"]) / dr["elapsed"], "unit": "site steps/s",
+                           "sweeps": min(args.steps, 3),
+                           "usec_per_iteration": 1e6 * dr["elapsed"] / iters,
+                           "usec_per_iteration_host_driven": 1e6 * elapsed / sum(s["iters"] for s in steps),
+                           "energy_after_timed_sweeps": dr["steps"][-1]["theta"],
+                           "note": "the same sweeps with the device-resident Davidson iteration (FP64 subspace "
+                                   "solve in one GPU work-group, each iteration replayed from a HIP graph, no "
+                                   "host decision within a local solve) instead of the host-core subspace solve"}
     fp32 = None
     if args.path == "tiled" and not args.no_fp32:
         fr = run("tiled", "fp32", args.fp32_tol)
@@ -543,6 +593,7 @@ def main():
         "heff_flops": heff_flops,
         "roofline": roof,
         "plain_fp64": plain,
+        "device_resident": device_resident,
         "fp32": fp32,
         "abinitio": abinitio,
         "batch": batch,

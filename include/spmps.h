@@ -64,6 +64,10 @@ extern "C" {
                              with FP32 accumulation (relative error of
                              order 1e-5); values must lie in FP32 range  */
 
+#define SP_SOLVER_AUTO 0    /* sp_sweep_opts.solver */
+#define SP_SOLVER_HOST 1
+#define SP_SOLVER_DEVICE 2
+
 #define SP_PATH_TILED 0   /* environment updates as LDS-tiled block products
                              over particle-number blocks (FP64 matrix
                              cores); H_eff x per site either in one fused
@@ -131,14 +135,21 @@ typedef struct sp_sweep_opts {
     int max_iter;     /* Ritz evaluations per local solve                   */
     int max_sub;      /* search-space size that triggers a restart          */
     int keep;         /* Ritz vectors kept at a restart                     */
-    int host_solve;   /* 0: the Davidson iteration runs on the device (the
-                         FP64 subspace solve in one work-group per state,
-                         every iteration of all states replayed from one
-                         HIP graph) whenever the tiled path, max_sub <= 47,
-                         keep <= 16 and no constraint or learned model
-                         apply; 1: the subspace solve on a host core
-                         between device passes.  Both run the same
-                         algorithm; results agree to rounding            */
+    int solver;       /* where the Davidson iteration is driven:
+                         SP_SOLVER_HOST: the FP64 subspace solve on a host
+                         core between the device passes (one round trip
+                         per iteration); SP_SOLVER_DEVICE: device resident
+                         - the FP64 subspace solve in one work-group per
+                         state, every iteration of all states replayed from
+                         one HIP graph, no host decision inside a local
+                         solve (tiled path, max_sub <= 47, keep <= 16, no
+                         constraint or learned model; otherwise the host
+                         driver runs); SP_SOLVER_AUTO (0): device resident
+                         for two or more states, host for one state (a
+                         single work-group solve is slower than a host core,
+                         in a batch the states' solves run side by side).
+                         The same algorithm either way; results agree to
+                         rounding                                          */
 } sp_sweep_opts;
 
 typedef struct sp_step_report {

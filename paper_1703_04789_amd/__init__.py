@@ -23,6 +23,7 @@ SP_FP64 = 0
 SP_FP32 = 1
 SP_BF16X3 = 2
 SP_PATH_TILED, SP_PATH_PLAIN = 0, 1
+SOLVERS = {"auto": 0, "host": 1, "device": 2}
 
 EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_sweep", "sp_energy",
            "sp_destroy", "sp_site_size", "sp_get_site", "sp_set_site", "sp_center", "sp_heff_flops",
@@ -60,7 +61,7 @@ class _BlockTable(ctypes.Structure):
 
 class _SweepOpts(ctypes.Structure):
     _fields_ = [("n_sweeps", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("max_sub", ctypes.c_int), ("keep", ctypes.c_int), ("host_solve", ctypes.c_int)]
+                ("max_sub", ctypes.c_int), ("keep", ctypes.c_int), ("solver", ctypes.c_int)]
 
 
 class _StepReport(ctypes.Structure):
@@ -559,11 +560,11 @@ class SPMPS:
         _check(lib().sp_set_heff_plan(self._h, site, lds_budget, ctypes.byref(rows)))
         return rows.value
 
-    def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, host_solve=False):
-        """Run sweeps; returns (status, list of per-step dicts).  host_solve:
-        the Davidson subspace solve on a host core instead of the
-        device-resident iteration."""
-        return sweep_batch([self], n_sweeps, tol, max_iter, max_sub, keep, _single=True, host_solve=host_solve)
+    def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, solver="auto"):
+        """Run sweeps; returns (status, list of per-step dicts).  solver:
+        "host" (subspace solve on a host core), "device" (device-resident
+        iteration replayed from a HIP graph) or "auto" (host for one state)."""
+        return sweep_batch([self], n_sweeps, tol, max_iter, max_sub, keep, _single=True, solver=solver)
 
 
 def _steps_out(steps, n):
@@ -575,11 +576,13 @@ def _steps_out(steps, n):
     return out
 
 
-def sweep_batch(states, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, _single=False, host_solve=False):
+def sweep_batch(states, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, _single=False, solver="auto"):
     """Sweeps of several SPMPS states (``sp_sweep_batch``; one state:
-    ``sp_sweep``).  Returns (status, per-state lists of step dicts); for a
-    single state with _single=True, (status, step dicts)."""
-    opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep, 1 if host_solve else 0)
+    ``sp_sweep``).  solver: "auto" (device-resident iteration for two or more
+    states, host-driven for one), "host" or "device".  Returns (status,
+    per-state lists of step dicts); for a single state with _single=True,
+    (status, step dicts)."""
+    opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep, SOLVERS[solver])
     caps = [max(1, n_sweeps * max(1, 2 * (st.L - 1))) for st in states]
     bufs = [(_StepReport * c)() for c in caps]
     reps = (_SweepReport * len(states))(*[_SweepReport(c, 0, b) for c, b in zip(caps, bufs)])

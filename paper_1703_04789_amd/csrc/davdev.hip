@@ -50,11 +50,27 @@ __device__ inline double wg_max(double v, double* red) {
     return r;
 }
 
-// sum over q < nch of part[q * stride + idx], ascending q (the host's order)
+// sum over q < nch of part[q * stride + idx], ascending q (the host's
+// order); eight loads in flight at a time
 __device__ inline double chunk_total(const double* part, int nch, int stride, int idx) {
     double acc = 0.0;
-    for (int q = 0; q < nch; ++q) acc += part[(long long)q * stride + idx];
+    int q = 0;
+    for (; q + 8 <= nch; q += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(long long)(q + u) * stride + idx];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; q < nch; ++q) acc += part[(long long)q * stride + idx];
     return acc;
+}
+
+// sum over the lanes of wave 0 (callers: threads of wave 0 only)
+__device__ inline double wave0_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 // LDS of one solve, m <= kDevSubMax: seven m x m matrices, eight m-vectors
@@ -88,61 +104,73 @@ __device__ inline Work carve(double* base, int m) {
     return w;
 }
 
-// Cholesky factors of N - shift I (L2) and of N (L), lower, row-major, in
-// one pass over the columns; false if a pivot of either is not positive
+// Cholesky factors of N - shift I (L2) and of N (L), lower, stored
+// column-major (entry (i, k) at k m + i, so that the dot products of the rows
+// read consecutive LDS words), in one pass over the columns; false if a
+// pivot of either is not positive
 __device__ bool chol2(int m, const double* N, double shift, double* L, double* L2, double* flag) {
     const int tid = threadIdx.x;
     for (int e = tid; e < m * m; e += kST) L[e] = L2[e] = 0.0;
     if (tid == 0) flag[0] = 1.0;
     __syncthreads();
     for (int j = 0; j < m; ++j) {
-        if (tid == 0) {
-            double d1 = N[j * m + j] - shift, d0 = N[j * m + j];
-            for (int k = 0; k < j; ++k) d1 -= L2[j * m + k] * L2[j * m + k];
-            for (int k = 0; k < j; ++k) d0 -= L[j * m + k] * L[j * m + k];
-            if (!(d1 > 0.0) || !(d0 > 0.0)) {
-                flag[0] = 0.0;
-            } else {
-                L2[j * m + j] = sqrt(d1);
-                L[j * m + j] = sqrt(d0);
+        if (tid < 64) {
+            const double a = (tid < j) ? L2[tid * m + j] : 0.0;
+            const double b = (tid < j) ? L[tid * m + j] : 0.0;
+            const double s1 = wave0_sum(a * a), s0 = wave0_sum(b * b);
+            if (tid == 0) {
+                const double d1 = N[j * m + j] - shift - s1, d0 = N[j * m + j] - s0;
+                if (!(d1 > 0.0) || !(d0 > 0.0)) {
+                    flag[0] = 0.0;
+                } else {
+                    L2[j * m + j] = sqrt(d1);
+                    L[j * m + j] = sqrt(d0);
+                }
             }
         }
         __syncthreads();
         if (flag[0] == 0.0) return false;
-        const double* lj = L + j * m;
-        const double* l2j = L2 + j * m;
+        const double ljj = L[j * m + j], l2jj = L2[j * m + j];
         for (int i = j + 1 + tid; i < m; i += kST) {
-            const double* li = L + i * m;
-            const double* l2i = L2 + i * m;
             double s0 = N[i * m + j], s1 = 0.0, t0 = N[i * m + j], t1 = 0.0;
             int k = 0;
             for (; k + 2 <= j; k += 2) {
-                s0 -= li[k] * lj[k];
-                s1 -= li[k + 1] * lj[k + 1];
-                t0 -= l2i[k] * l2j[k];
-                t1 -= l2i[k + 1] * l2j[k + 1];
+                s0 -= L[k * m + i] * L[k * m + j];
+                s1 -= L[(k + 1) * m + i] * L[(k + 1) * m + j];
+                t0 -= L2[k * m + i] * L2[k * m + j];
+                t1 -= L2[(k + 1) * m + i] * L2[(k + 1) * m + j];
             }
             for (; k < j; ++k) {
-                s0 -= li[k] * lj[k];
-                t0 -= l2i[k] * l2j[k];
+                s0 -= L[k * m + i] * L[k * m + j];
+                t0 -= L2[k * m + i] * L2[k * m + j];
             }
-            L[i * m + j] = (s0 + s1) / lj[j];
-            L2[i * m + j] = (t0 + t1) / l2j[j];
+            L[j * m + i] = (s0 + s1) / ljj;
+            L2[j * m + i] = (t0 + t1) / l2jj;
         }
         __syncthreads();
     }
     return true;
 }
 
-// out = L^-1 in (transpose_in: in^T), column by column, one thread per column
-__device__ void tri_solve(int m, const double* L, const double* in, bool transpose_in, double* out) {
+// out = L^-1 in (L column-major as from chol2), column by column, one
+// thread per column of `in` (reads of `in` and `out` are consecutive across
+// threads, L entries are the same for all)
+__device__ void tri_solve(int m, const double* L, const double* in, double* out) {
     const int c = threadIdx.x;
     if (c < m) {
         for (int i = 0; i < m; ++i) {
-            double acc = transpose_in ? in[c * m + i] : in[i * m + c];
-            for (int k = 0; k < i; ++k) acc -= L[i * m + k] * out[k * m + c];
+            double acc = in[i * m + c];
+            for (int k = 0; k < i; ++k) acc -= L[k * m + i] * out[k * m + c];
             out[i * m + c] = acc * (1.0 / L[i * m + i]);
         }
+    }
+    __syncthreads();
+}
+
+__device__ void transpose(int m, const double* in, double* out) {
+    for (int e = threadIdx.x; e < m * m; e += kST) {
+        const int r = e / m, c = e - r * m;
+        out[c * m + r] = in[e];
     }
     __syncthreads();
 }
@@ -166,11 +194,12 @@ __device__ void tridiagonalise(int m, double* A, double* hv, double* beta, doubl
     for (int k = 0; k + 2 < m; ++k) {
         const int len = m - k - 1;
         double* v = hv + k * m;
-        if (tid < len) v[tid] = A[(k + 1 + tid) * m + k];
+        const double vt = (tid < len) ? A[k * m + k + 1 + tid] : 0.0;  // row k = column k (symmetric)
+        if (tid < len) v[tid] = vt;
+        double ss = 0.0;
+        if (tid < 64) ss = wave0_sum(vt * vt);
         __syncthreads();
         if (tid == 0) {
-            double ss = 0.0;
-            for (int i = 0; i < len; ++i) ss += v[i] * v[i];
             const double nrm = sqrt(ss);
             misc[0] = 0.0;  // skip
             if (nrm == 0.0) {
@@ -191,24 +220,25 @@ __device__ void tridiagonalise(int m, double* A, double* hv, double* beta, doubl
         __syncthreads();
         if (misc[0] != 0.0) continue;
         const double bk = beta[k];
+        double pt = 0.0;
         if (tid < len) {
-            const double* row = A + (k + 1 + tid) * m + k + 1;
+            // row (k+1+tid) of the trailing block read as its column
+            const double* col = A + (k + 1) * m + k + 1 + tid;
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
             int j = 0;
             for (; j + 4 <= len; j += 4) {
-                s0 += row[j] * v[j];
-                s1 += row[j + 1] * v[j + 1];
-                s2 += row[j + 2] * v[j + 2];
-                s3 += row[j + 3] * v[j + 3];
+                s0 += col[j * m] * v[j];
+                s1 += col[(j + 1) * m] * v[j + 1];
+                s2 += col[(j + 2) * m] * v[j + 2];
+                s3 += col[(j + 3) * m] * v[j + 3];
             }
-            for (; j < len; ++j) s0 += row[j] * v[j];
-            p[tid] = bk * ((s0 + s1) + (s2 + s3));
+            for (; j < len; ++j) s0 += col[j * m] * v[j];
+            pt = bk * ((s0 + s1) + (s2 + s3));
+            p[tid] = pt;
         }
-        __syncthreads();
-        if (tid == 0) {
-            double vp = 0.0;
-            for (int i = 0; i < len; ++i) vp += v[i] * p[i];
-            misc[2] = 0.5 * bk * vp;
+        if (tid < 64) {
+            const double vp = wave0_sum((tid < len) ? v[tid] * pt : 0.0);
+            if (tid == 0) misc[2] = 0.5 * bk * vp;
         }
         __syncthreads();
         const double K = misc[2];
@@ -367,10 +397,9 @@ __device__ void apply_q(int m, const double* hv, const double* beta, double* z, 
         if (beta[k] == 0.0) continue;
         const int len = m - k - 1;
         const double* v = hv + k * m;
-        if (tid == 0) {
-            double t = 0.0;
-            for (int i = 0; i < len; ++i) t += v[i] * z[k + 1 + i];
-            misc[0] = t;
+        if (tid < 64) {
+            const double t = wave0_sum((tid < len) ? v[tid] * z[k + 1 + tid] : 0.0);
+            if (tid == 0) misc[0] = t;
         }
         __syncthreads();
         const double t = misc[0];
@@ -429,7 +458,7 @@ __device__ void jacobi(int m, double* A, double* V, double* rot, double* red) {
             }
             __syncthreads();
             for (int e = tid; e < half * m; e += kST) {  // columns p, q of A and V
-                const int sl = e / m, i = e - sl * m;
+                const int i = e / half, sl = e - i * half;
                 const int p = int(rot[4 * sl]), q = int(rot[4 * sl + 1]);
                 if (q >= m) continue;
                 const double c = rot[4 * sl + 2], s = rot[4 * sl + 3];
@@ -477,8 +506,9 @@ __device__ void solve_pencil(int m, Work& w, double drop, bool need_all, double*
         }
         U = wg_max(U, red);
         if (U > 1e-12 && chol2(m, w.N, drop * U, w.L, w.L2, misc + 8)) {
-            tri_solve(m, w.L, w.H, false, w.W);   // W = L^-1 H
-            tri_solve(m, w.L, w.W, true, w.B);    // B = L^-1 W^T
+            tri_solve(m, w.L, w.H, w.W);   // W = L^-1 H
+            transpose(m, w.W, w.L2);       // W^T (the shifted factor is no longer needed)
+            tri_solve(m, w.L, w.L2, w.B);  // B = L^-1 W^T
             symmetrise(m, w.B);
             // lowest pair of B: tridiagonal form (vectors in Z), bisection,
             // inverse iteration, back-transformation
@@ -489,7 +519,7 @@ __device__ void solve_pencil(int m, Work& w, double drop, bool need_all, double*
                 // a = L^-T c0
                 for (int i = m - 1; i >= 0; --i) {
                     double v = w.v5[i];
-                    for (int k = i + 1; k < m; ++k) v -= w.L[k * m + i] * w.v6[k];
+                    for (int k = i + 1; k < m; ++k) v -= w.L[i * m + k] * w.v6[k];  // L(k, i), column-major
                     w.v6[i] = v / w.L[i * m + i];
                 }
                 misc[0] = misc[24];
@@ -700,15 +730,20 @@ __global__ __launch_bounds__(256) void k_bdav_rotate(const DavInst* __restrict__
 }
 
 __global__ __launch_bounds__(kST) void k_bdav_update(DavInst* __restrict__ insts) {
+    __shared__ double tot[4 * kDevSubMax + 8];
     __shared__ double sh[4];
     DavInst* P = insts + blockIdx.x;
     if (!P->active) return;
     const int tid = threadIdx.x;
     const int m = P->m, S = P->S, nch = P->nch;
+    const int nd = 4 * m + 2;
+    // every chunk total at once, one thread per quantity (each in ascending
+    // chunk order): the three Ritz sums, then the nd Gram rows
+    if (tid < 3) tot[tid] = chunk_total(P->part_x, nch, 3, tid);
+    else if (tid < 3 + nd && P->ext) tot[tid] = chunk_total(P->pg, nch, nd, tid - 3);
+    __syncthreads();
     if (tid == 0) {
-        const double xx = chunk_total(P->part_x, nch, 3, 0);
-        const double uu = chunk_total(P->part_x, nch, 3, 1);
-        const double xn = chunk_total(P->part_x, nch, 3, 2);
+        const double xx = tot[0], uu = tot[1], xn = tot[2];
         int grow = 0;
         if (!isfinite(xx) || !isfinite(uu) || !(xx > 0.0)) {
             P->err = kSpErrNan;
@@ -731,12 +766,11 @@ __global__ __launch_bounds__(kST) void k_bdav_update(DavInst* __restrict__ insts
     }
     __syncthreads();
     if (sh[0] != 0.0) {
-        const int nd = 4 * m + 2;
+        const double* g = tot + 3;
         for (int j = tid; j <= m; j += kST) {
-            const double hv_new = chunk_total(P->pg, nch, nd, j);
-            const double nv_new = chunk_total(P->pg, nch, nd, m + 1 + j);
-            const double hv_old = (j < m) ? chunk_total(P->pg, nch, nd, 2 * m + 2 + j) : hv_new;
-            const double nv_old = (j < m) ? chunk_total(P->pg, nch, nd, 3 * m + 2 + j) : nv_new;
+            const double hv_new = g[j], nv_new = g[m + 1 + j];
+            const double hv_old = (j < m) ? g[2 * m + 2 + j] : hv_new;
+            const double nv_old = (j < m) ? g[3 * m + 2 + j] : nv_new;
             P->Ht[(long long)j * S + m] = hv_new;
             P->Nt[(long long)j * S + m] = nv_new;
             P->Ht[(long long)m * S + j] = hv_old;

@@ -3028,11 +3028,13 @@ namespace {
 // its fused H_eff tasks return at once.  Then the gauge moves and
 // environment updates of all states run eagerly, and the next round starts.
 
-// whether these settings can use the device-resident iteration
-bool device_solver_ok(const sp_handle* h, const sp_sweep_opts& o) {
+// whether these settings run the device-resident iteration for a sweep of
+// nstates states
+bool device_solver_ok(const sp_handle* h, const sp_sweep_opts& o, int nstates) {
     const int max_sub = std::max(2, o.max_sub);
     const int keep = std::max(1, std::min(o.keep, max_sub - 1));
-    return h->path == SP_PATH_TILED && h->cons.empty() && !h->mlp_use && !h->mlp_rec && !o.host_solve &&
+    const bool want = o.solver == SP_SOLVER_DEVICE || (o.solver == SP_SOLVER_AUTO && nstates >= 2);
+    return want && h->path == SP_PATH_TILED && h->cons.empty() && !h->mlp_use && !h->mlp_rec &&
            max_sub + 1 <= spk::kDevSubMax && keep <= spk::kDevKeepMax;
 }
 
@@ -3525,7 +3527,8 @@ int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r) {
                    "bad sweep options");
         SP_REQUIRE(h->center == 1, "sweeps start with the canonical centre at site 1");
         if (r) r->n_steps = 0;
-        if (device_solver_ok(h, *o)) {
+        SP_REQUIRE(o->solver >= SP_SOLVER_AUTO && o->solver <= SP_SOLVER_DEVICE, "unknown solver");
+        if (device_solver_ok(h, *o, 1)) {
             std::vector<BatchState> B(1);
             std::vector<sp_sweep_report*> reps(1, r);
             B[0].h = h;
@@ -3616,8 +3619,9 @@ int sp_sweep_batch(sp_handle** hs, int n, const sp_sweep_opts* o, sp_sweep_repor
                 r[i].n_steps = 0;
             }
         }
+        SP_REQUIRE(o->solver >= SP_SOLVER_AUTO && o->solver <= SP_SOLVER_DEVICE, "unknown solver");
         bool dev = true;
-        for (int i = 0; i < n; ++i) dev = dev && device_solver_ok(hs[i], *o);
+        for (int i = 0; i < n; ++i) dev = dev && device_solver_ok(hs[i], *o, n);
         return dev ? sweep_rounds(B, *o, reps) : sweep_batch(B, *o, reps);
     });
 }

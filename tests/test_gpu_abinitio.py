@@ -255,11 +255,12 @@ def test_abinitio_batched_sweeps_match_single():
     _, hs2, _ = make_pair(8, 8, 0, 32, 0, 5, seed=3, oracle=False)
     singles.append(hs1)
     batch.append(hs2)
-    ref = [s.sweep(2)[1] for s in singles]
-    rc, got = sp.sweep_batch(batch, 2)
-    for r, g in zip(ref, got):
-        assert len(r) == len(g)
-        assert max(abs(a["theta"] - b["theta"]) for a, b in zip(r, g)) < 1e-10
+    for solver in ("device", "host"):  # each driver against its own single-state sweeps
+        ref = [s.sweep(2, solver=solver)[1] for s in singles]
+        rc, got = sp.sweep_batch(batch, 2, solver=solver)
+        for r, g in zip(ref, got):
+            assert len(r) == len(g)
+            assert max(abs(a["theta"] - b["theta"]) for a, b in zip(r, g)) < 1e-10
 
 
 def test_abinitio_fp32_products_on_fused_and_tiled_sites():

@@ -1,7 +1,7 @@
 """Batched sweeps (sp_sweep_batch): several states advanced together must
-reproduce their single-state sweeps.  The batched passes run the same
-per-state arithmetic in the same order, so the step energies agree to
-rounding (1e-12 is asserted)."""
+reproduce their single-state sweeps run by the same driver.  The batched
+passes run the same per-state arithmetic in the same order, so the step
+energies agree to rounding (1e-12 is asserted)."""
 import numpy as np
 import pytest
 
@@ -25,15 +25,18 @@ def _handles(cases, **kw):
     return [make_pair(*c, oracle=False, **kw)[1] for c in cases]
 
 
+@pytest.mark.parametrize("solver", ["device", "host"])
 @pytest.mark.parametrize("opts", [dict(), dict(max_sub=8, keep=4, max_iter=30)])
-def test_batch_matches_single_runs(opts):
+def test_batch_matches_single_runs(opts, solver):
+    # both drivers: the device-resident iteration (one graph per round for
+    # all states) and the host-driven one (states advance independently)
     singles = []
     for h in _handles(CASES):
-        rc, steps = h.sweep(2, **opts)
+        rc, steps = h.sweep(2, solver=solver, **opts)
         singles.append(steps)
         h.close()
     hs = _handles(CASES)
-    rc, batch = sp.sweep_batch(hs, 2, **opts)
+    rc, batch = sp.sweep_batch(hs, 2, solver=solver, **opts)
     for one, many in zip(singles, batch):
         assert len(one) == len(many)
         for a, b in zip(one, many):
@@ -48,7 +51,7 @@ def test_batch_matches_single_runs(opts):
 def test_batch_fp32_matches_single_runs():
     singles = []
     for h in _handles(CASES, precision="fp32"):
-        singles.append(h.sweep(1, tol=1e-5)[1])
+        singles.append(h.sweep(1, tol=1e-5, solver="device")[1])
         h.close()
     rc, batch = sp.sweep_batch(_handles(CASES, precision="fp32"), 1, tol=1e-5)
     for one, many in zip(singles, batch):
@@ -66,7 +69,7 @@ def test_batch_of_neel_guesses():
             print(f"[case] {w.name}", flush=True)
             out.append(sp.SPMPS(w.table(), w.blocks(), sp.mpo_hubbard(w.L, w.t, w.U), w.twoS, w.G))
         return out
-    singles = [h.sweep(1)[1] for h in mk()]
+    singles = [h.sweep(1, solver="device")[1] for h in mk()]
     rc, batch = sp.sweep_batch(mk(), 1)
     for one, many in zip(singles, batch):
         assert np.isfinite([s["theta"] for s in many]).all()

@@ -106,7 +106,7 @@ def test_device_sweeps_match_oracle(case):
     # every local problem fits the search space, so each solve is exact and
     # the whole trajectory is fixed by the input
     tab, gpu, orc = make_pair(*case)
-    rc, steps = gpu.sweep(2, **EXACT)
+    rc, steps = gpu.sweep(2, solver="device", **EXACT)
     ref = omps.sweep(orc, 2, **EXACT)
     assert rc == sp.SP_OK and len(steps) == len(ref)
     for a, b in zip(steps, ref):
@@ -120,15 +120,32 @@ def test_device_and_host_solves_agree():
     for case in STABLE:
         _, dev, _ = make_pair(*case, oracle=False)
         _, host, _ = make_pair(*case, oracle=False)
-        _, sd = dev.sweep(2, **EXACT)
-        _, sh = host.sweep(2, host_solve=True, **EXACT)
+        _, sd = dev.sweep(2, solver="device", **EXACT)
+        _, sh = host.sweep(2, solver="host", **EXACT)
         assert max(abs(a["theta"] - b["theta"]) for a, b in zip(sd, sh)) < 1e-9
+
+
+def test_device_and_host_batches_agree():
+    # the same batch through both drivers (device resident is the default
+    # for batches): step energies equal to rounding
+    pairs = [make_pair(*c, oracle=False) for c in STABLE]
+    _, dev = sp.sweep_batch([g for _, g, _ in pairs], 2, **EXACT)
+    pairs = [make_pair(*c, oracle=False) for c in STABLE]
+    _, host = sp.sweep_batch([g for _, g, _ in pairs], 2, solver="host", **EXACT)
+    for a, b in zip(dev, host):
+        assert max(abs(x["theta"] - y["theta"]) for x, y in zip(a, b)) < 1e-9
+
+
+def test_solver_option_is_checked():
+    _, gpu, _ = make_pair(*STABLE[0], oracle=False)
+    with pytest.raises(KeyError):
+        gpu.sweep(1, solver="gpu")
 
 
 def test_device_batch_matches_oracle():
     # the four states in one batch: one graph per round covers all of them
     pairs = [make_pair(*c) for c in STABLE]
-    rc, batch = sp.sweep_batch([g for _, g, _ in pairs], 2, **EXACT)
+    rc, batch = sp.sweep_batch([g for _, g, _ in pairs], 2, solver="device", **EXACT)
     assert rc == sp.SP_OK
     for (tab, gpu, orc), steps in zip(pairs, batch):
         ref = omps.sweep(orc, 2, **EXACT)
@@ -142,6 +159,6 @@ def test_device_restarts_reach_ed():
     L, twoS = 6, 0
     G = oq.exact_point_count(L, L, twoS)
     _, gpu, _ = make_pair(L, L, 0, 64, twoS, G, oracle=False)
-    rc, steps = gpu.sweep(3, max_sub=8, keep=4, max_iter=2000, tol=1e-10)
+    rc, steps = gpu.sweep(3, max_sub=8, keep=4, max_iter=2000, tol=1e-10, solver="device")
     assert abs(steps[-1]["theta"] - (-3.092565319505379)) < 1e-9
     assert max(s["iters"] for s in steps) > 8  # restarts happened
