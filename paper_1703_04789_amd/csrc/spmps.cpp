@@ -650,20 +650,33 @@ void build_plan(sp_handle* h, int k) {
     const int wl = h->w[k - 1], wr = h->w[k];
     const auto& Wk = h->W[k - 1];
     // ---- rotated MPO pattern and coefficient table
-    std::map<std::array<int, 4>, int> wpos;
     for (int a = 0; a < wl; ++a)
-        for (int b = 0; b < wr; ++b)
+        for (int b = 0; b < wr; ++b) {
+            const double* op = &Wk[(size_t(a) * wr + b) * 16];
+            bool any = false;
+            for (int e = 0; e < 16; ++e) any = any || op[e] != 0.0;
+            if (!any) continue;
             for (int s = 0; s < 4; ++s)
                 for (int u = 0; u < 4; ++u) {
                     bool nz = false;
                     for (int t = 0; t < 4; ++t)
-                        if (Wk[((size_t(a) * wr + b) * 4 + s) * 4 + t] != 0.0 && rot_nonzero(t, u)) nz = true;
-                    if (nz) {
-                        wpos[{a, b, s, u}] = int(P.went.size());
-                        P.went.push_back({a, b, s, u});
-                    }
+                        if (op[s * 4 + t] != 0.0 && rot_nonzero(t, u)) nz = true;
+                    if (nz) P.went.push_back({a, b, s, u});
                 }
+        }
     P.nW = int(P.went.size());
+    // the rotated-MPO entries by (sigma, right channel) as (left channel,
+    // sigma', entry), by (sigma, left channel) as (right channel, sigma',
+    // entry), and the diagonal ones (sigma' = sigma) by sigma as (left
+    // channel, right channel, entry), each in ascending order (the order of
+    // the entry list)
+    std::vector<std::vector<std::array<int, 3>>> byL(size_t(4) * wr), byR(size_t(4) * wl), byD(4);
+    for (int e = 0; e < P.nW; ++e) {
+        const auto& q = P.went[e];
+        byL[size_t(q[2]) * wr + q[1]].push_back({q[0], q[3], e});
+        byR[size_t(q[2]) * wl + q[0]].push_back({q[1], q[3], e});
+        if (q[2] == q[3]) byD[q[2]].push_back({q[0], q[1], e});
+    }
     P.nc = 2 * P.nW + 18;
     P.coef_h.assign(size_t(G) * P.nc, 0.0);
     for (int g = 0; g < G; ++g) {
@@ -732,17 +745,14 @@ void build_plan(sp_handle* h, int k) {
                 const int nbp = br.nblock(br.nb[nbk].n - h->dn[k][cp]);
                 if (nbp < 0) continue;
                 bool any = false;
-                for (int c = 0; c < wl; ++c) {
+                for (const auto& ent : byL[size_t(sig) * wr + cp]) {
+                    const int c = ent[0], q = ent[1];
                     const int e = el.find(c, i);
-                    if (e < 0) continue;
-                    for (int q = 0; q < 4; ++q) {
-                        auto it = wpos.find({c, cp, sig, q});
-                        if (it == wpos.end() || Toff[size_t(e) * 4 + q] < 0) continue;
-                        const int jb = br.nblock(bl.nb[el.blk[e].j].n + kSigmaN[q]);
-                        SP_REQUIRE(jb == nbp, "internal: inconsistent particle numbers in the MPO mixing");
-                        vterms.push_back({sig, cp, i, Toff[size_t(e) * 4 + q], it->second, e, q});
-                        any = true;
-                    }
+                    if (e < 0 || Toff[size_t(e) * 4 + q] < 0) continue;
+                    const int jb = br.nblock(bl.nb[el.blk[e].j].n + kSigmaN[q]);
+                    SP_REQUIRE(jb == nbp, "internal: inconsistent particle numbers in the MPO mixing");
+                    vterms.push_back({sig, cp, i, Toff[size_t(e) * 4 + q], ent[2], e, q});
+                    any = true;
                 }
                 if (!any) continue;
                 Voff[{sig, cp, i}] = voff;
@@ -869,17 +879,14 @@ void build_plan(sp_handle* h, int k) {
                 const int nbb = br.nblock(bl.nb[ia].n + kSigmaN[sig]);
                 if (nbb < 0) continue;
                 bool any = false;
-                for (int cp = 0; cp < wr; ++cp) {
+                for (const auto& ent : byR[size_t(sig) * wl + c]) {
+                    const int cp = ent[0], q = ent[1];
                     const int e = er.find(cp, nbb);
-                    if (e < 0) continue;
-                    for (int q = 0; q < 4; ++q) {
-                        auto it = wpos.find({c, cp, sig, q});
-                        if (it == wpos.end() || Zoff[size_t(e) * 4 + q] < 0) continue;
-                        const int irow = bl.nblock(br.nb[er.blk[e].j].n - kSigmaN[q]);
-                        SP_REQUIRE(irow == ip, "internal: inconsistent particle numbers in the right mixing");
-                        zterms.push_back({sig, c, ip, Zoff[size_t(e) * 4 + q], it->second});
-                        any = true;
-                    }
+                    if (e < 0 || Zoff[size_t(e) * 4 + q] < 0) continue;
+                    const int irow = bl.nblock(br.nb[er.blk[e].j].n - kSigmaN[q]);
+                    SP_REQUIRE(irow == ip, "internal: inconsistent particle numbers in the right mixing");
+                    zterms.push_back({sig, c, ip, Zoff[size_t(e) * 4 + q], ent[2]});
+                    any = true;
                 }
                 if (!any) continue;
                 Ztoff[{sig, c, ip}] = ztoff;
@@ -930,20 +937,19 @@ void build_plan(sp_handle* h, int k) {
         db.cols = X.cols;
         db.sigma = X.s;
         db.t0 = int(P.dterm_h.size());
-        for (int c = 0; c < wl; ++c) {
+        for (const auto& ent : byD[X.s]) {
+            const int c = ent[0], cp = ent[1];
             const int e = el.find(c, SA.nb);
             if (e < 0 || el.blk[e].j != SA.nb) continue;
-            for (int cp = 0; cp < wr; ++cp) {
+            {
                 const int re = er.find(cp, SB.nb);
                 if (re < 0 || er.blk[re].j != SB.nb) continue;
-                auto it = wpos.find({c, cp, X.s, X.s});
-                if (it == wpos.end()) continue;
                 spk::DiagTerm dt{};
                 dt.l_off = el.blk[e].off + (long long)SA.ro * (el.blk[e].cols + 1);
                 dt.r_off = er.blk[re].off + (long long)SB.ro * (er.blk[re].cols + 1);
                 dt.l_ld = el.blk[e].cols;
                 dt.r_ld = er.blk[re].cols;
-                dt.cidx = P.c_cwt(it->second);
+                dt.cidx = P.c_cwt(ent[2]);
                 P.dterm_h.push_back(dt);
             }
         }
@@ -1364,8 +1370,12 @@ bool build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
     const EnvLayout& er = h->env[k];
     const int wl = h->w[k - 1], wr = h->w[k];
     const int lastR = wr - 1;
-    std::map<std::array<int, 4>, int> wpos;
-    for (int e = 0; e < P.nW; ++e) wpos[P.went[e]] = e;
+    // rotated-MPO entries by (sigma, right channel): (left channel, sigma', entry)
+    std::vector<std::vector<std::array<int, 3>>> byL(size_t(4) * wr);
+    for (int e = 0; e < P.nW; ++e) {
+        const auto& q = P.went[e];
+        byL[size_t(q[2]) * wr + q[1]].push_back({q[0], q[3], e});
+    }
     const int nb = int(bl.nb.size());
 
     // RC-independent description of one bra block
@@ -1439,9 +1449,9 @@ bool build_fused(sp_handle* h, int k, int lds_budget = kHeffLdsBudget) {
                 const int re = er.find(cp, nbb);
                 if (re < 0) continue;
                 std::vector<std::pair<int, int>> tl;
-                for (auto& kv : tloc) {
-                    auto it = wpos.find({kv.first.first, cp, sig, kv.first.second});
-                    if (it != wpos.end()) tl.push_back({kv.second, P.c_cwt(it->second)});
+                for (const auto& ent : byL[size_t(sig) * wr + cp]) {  // ascending (c, s'), as tloc
+                    auto it = tloc.find({ent[0], ent[1]});
+                    if (it != tloc.end()) tl.push_back({it->second, P.c_cwt(ent[2])});
                 }
                 add_seg(re, 0, tl);
             }
