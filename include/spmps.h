@@ -179,7 +179,11 @@ int sp_init_mps(const sp_problem* p, const sp_mpo* W, const sp_block_table* bond
 /* Environments (Fig. [spmpsOpt]): dir = +1 builds the left environments
  * L_g[site] (sites 1..site) from L_g[site-1] and the current site tensor,
  * for every g; dir = -1 builds R_g[site] (sites site..L) from R_g[site+1].
- * site in 1..L.  SP_ESTATE if the input environment was never built. */
+ * site in 1..L.  SP_ESTATE if the input environment was never built.
+ * An interior bond (1..L-1) stores its left and right environments in one
+ * device buffer, as a sweep never needs both at once: building L[k] marks
+ * R[k] as not built and building R[k] marks L[k] as not built, so a later
+ * call that needs the retired one returns SP_ESTATE until it is rebuilt. */
 int sp_env_update(sp_handle* h, int site, int dir);
 
 /* y = H_eff x and ny = N_eff x at `site` (Eq. [geproblem]) with the current

@@ -106,6 +106,11 @@ struct DArr {  // owned device array
     }
 };
 
+template <class T>
+struct DRef {  // view of device memory owned elsewhere
+    T* p = nullptr;
+};
+
 struct Sector {
     int n, m2, dim, off, nb, ro;
 };
@@ -357,8 +362,14 @@ struct sp_handle {
     std::vector<Bond> bonds;
     std::vector<SiteInfo> sites;           // index k-1
     std::vector<EnvLayout> env;            // per bond
-    std::vector<DArr<double>> envL, envR;  // per bond, G * size
-    std::vector<DArr<float>> envL32, envR32;  // FP32 copies (precision SP_FP32)
+    // Environments per bond, G * size each.  An interior bond keeps one
+    // buffer for both sides: a sweep builds L[k] only after its last use of
+    // R[k] and the other way round, so at most one of the two is valid at a
+    // time (Lvalid/Rvalid); the boundary bonds 0 and L keep both.
+    std::vector<DArr<double>> envmem;
+    std::vector<DArr<float>> envmem32;     // FP32 copies (reduced precisions)
+    std::vector<DRef<double>> envL, envR;
+    std::vector<DRef<float>> envL32, envR32;
     std::vector<int> tab_nsec, tab_n, tab_2m, tab_dim;  // the block table as given
     int precision = SP_FP64;
     std::vector<char> Lvalid, Rvalid;
@@ -602,25 +613,38 @@ void build_env_layouts(sp_handle* h) {
     h->Lgen.assign(L + 1, 0);
 }
 
+// Interior bonds 1..L-1 hold one buffer shared by L[k] and R[k]; bonds 0
+// and L hold two (the boundary ones and the full contractions).
+template <class T>
+void alloc_env_set(const sp_handle* h, std::vector<DArr<T>>& mem, std::vector<DRef<T>>& l,
+                   std::vector<DRef<T>>& r) {
+    const int L = h->L;
+    mem.clear();
+    mem.resize(L + 3);
+    l.assign(L + 1, {});
+    r.assign(L + 1, {});
+    for (int k = 0; k <= L; ++k) {
+        mem[k].alloc(size_t(h->G) * h->env[k].size);
+        l[k].p = r[k].p = mem[k].p;
+    }
+    mem[L + 1].alloc(size_t(h->G) * h->env[0].size);
+    mem[L + 2].alloc(size_t(h->G) * h->env[L].size);
+    r[0].p = mem[L + 1].p;
+    r[L].p = mem[L + 2].p;
+}
+
+// an interior bond's two environments share storage
+inline bool env_shared(const sp_handle* h, int k) { return k > 0 && k < h->L; }
+
 void alloc_envs(sp_handle* h) {
     const int L = h->L;
-    h->envL.resize(L + 1);
-    h->envR.resize(L + 1);
-    for (int k = 0; k <= L; ++k) {
-        h->envL[k].alloc(size_t(h->G) * h->env[k].size);
-        h->envR[k].alloc(size_t(h->G) * h->env[k].size);
-    }
+    alloc_env_set(h, h->envmem, h->envL, h->envR);
     // boundary environments: one 1x1 block equal to 1 for every g
     std::vector<double> ones(h->G, 1.0);
     HIPCK(hipMemcpyAsync(h->envL[0].p, ones.data(), h->G * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCK(hipMemcpyAsync(h->envR[L].p, ones.data(), h->G * sizeof(double), hipMemcpyHostToDevice, h->stream));
     if (reduced(h)) {
-        h->envL32.resize(L + 1);
-        h->envR32.resize(L + 1);
-        for (int k = 0; k <= L; ++k) {
-            h->envL32[k].alloc(size_t(h->G) * h->env[k].size);
-            h->envR32[k].alloc(size_t(h->G) * h->env[k].size);
-        }
+        alloc_env_set(h, h->envmem32, h->envL32, h->envR32);
         spk::to_f32(h->stream, h->envL[0].p, h->envL32[0].p, h->G);
         spk::to_f32(h->stream, h->envR[L].p, h->envR32[L].p, h->G);
     }
@@ -2034,6 +2058,7 @@ void env_left(sp_handle* h, int k) {
         spk::to_f32(s, h->envL[k].p, h->envL32[k].p, (long long)h->G * h->env[k].size);
     h->Lvalid[k] = 1;
     ++h->Lgen[k];
+    if (env_shared(h, k)) h->Rvalid[k] = 0;
     for (int q = k + 1; q <= h->L; ++q) h->Lvalid[q] = 0;
 }
 
@@ -2056,6 +2081,7 @@ void env_right(sp_handle* h, int k) {
     if (reduced(h))
         spk::to_f32(s, h->envR[k - 1].p, h->envR32[k - 1].p, (long long)h->G * h->env[k - 1].size);
     h->Rvalid[k - 1] = 1;
+    if (env_shared(h, k - 1)) h->Lvalid[k - 1] = 0;
     for (int q = 0; q < k - 1; ++q) h->Rvalid[q] = 0;
 }
 
@@ -2140,6 +2166,7 @@ void env_left_mixed(sp_handle* a, int k, const double* bra) {
     P.envl_out.launch(a->stream, b, P.coef.p);
     a->Lvalid[k] = 1;
     ++a->Lgen[k];
+    if (env_shared(a, k)) a->Rvalid[k] = 0;
 }
 
 void env_right_mixed(sp_handle* a, int k, const double* bra) {
@@ -2150,6 +2177,7 @@ void env_right_mixed(sp_handle* a, int k, const double* bra) {
     P.mixr.launch(a->stream, b, P.coef.p);
     P.envr_out.launch(a->stream, b, P.coef.p);
     a->Rvalid[k - 1] = 1;
+    if (env_shared(a, k - 1)) a->Lvalid[k - 1] = 0;
 }
 
 // B[k] of constraint handle a into out (ny: scratch of the site's size)

@@ -158,8 +158,8 @@ def test_bench_shape_heff_parity(path):
     assert abs(E - Eo) < 1e-9 * max(1, abs(Eo))
     rng = np.random.default_rng(7)
     kc = wl.L // 2
-    _left_envs_to(gpu, orc, kc)
     for k in (1, kc):
+        _left_envs_to(gpu, orc, k)  # nothing for k = 1
         n = gpu.site_size(k)
         x = rng.standard_normal(n)
         y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
@@ -169,6 +169,35 @@ def test_bench_shape_heff_parity(path):
         torch.cuda.synchronize()
         assert rel_err(y.cpu().numpy(), orc.mps.site_packed(k, y_ref)) < 1e-11
         assert rel_err(ny.cpu().numpy(), orc.mps.site_packed(k, ny_ref)) < 1e-11
+
+
+def test_bond_environments_share_storage():
+    # L[k] and R[k] of an interior bond live in one buffer: building L[k]
+    # retires R[k], so H_eff at site k is refused until R[k] is rebuilt
+    # from R[k+1], after which it again matches the oracle
+    case = (8, 8, 0, 16, 0, 5)
+    tab, gpu, orc = make_pair(*case)
+    k = 3
+    _left_envs_to(gpu, orc, k)
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal(gpu.site_size(k))
+    y_ref, ny_ref = orc.heff(k, orc.mps.dense_site(k, x))
+    xd = _dev(x)
+    y, ny = torch.empty_like(xd), torch.empty_like(xd)
+    gpu.env_update(k, +1)
+    with pytest.raises(sp.SpError) as e:
+        gpu.heff_apply(k, xd, y, ny)
+    assert e.value.code == sp.SP_ESTATE
+    gpu.env_update(k + 1, -1)
+    gpu.heff_apply(k, xd, y, ny)
+    torch.cuda.synchronize()
+    assert rel_err(y.cpu().numpy(), orc.mps.site_packed(k, y_ref)) < 1e-11
+    assert rel_err(ny.cpu().numpy(), orc.mps.site_packed(k, ny_ref)) < 1e-11
+    # the rebuilt R[k] retired L[k]: the next site's product needs it again
+    with pytest.raises(sp.SpError) as e:
+        gpu.heff_apply(k + 1, _dev(np.zeros(gpu.site_size(k + 1))), *(torch.empty(
+            gpu.site_size(k + 1), dtype=torch.float64, device="cuda") for _ in range(2)))
+    assert e.value.code == sp.SP_ESTATE
 
 
 def test_zero_projected_norm_is_reported():
