@@ -150,6 +150,9 @@ typedef struct sp_sweep_opts {
                          in a batch the states' solves run side by side).
                          The same algorithm either way; results agree to
                          rounding                                          */
+    int verbose;      /* nonzero: one line per finished site step on stderr
+                         (state, sweep, site, direction, energy, matvecs,
+                         wall time)                                        */
 } sp_sweep_opts;
 
 typedef struct sp_step_report {

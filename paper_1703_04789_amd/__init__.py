@@ -61,7 +61,8 @@ class _BlockTable(ctypes.Structure):
 
 class _SweepOpts(ctypes.Structure):
     _fields_ = [("n_sweeps", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("max_sub", ctypes.c_int), ("keep", ctypes.c_int), ("solver", ctypes.c_int)]
+                ("max_sub", ctypes.c_int), ("keep", ctypes.c_int), ("solver", ctypes.c_int),
+                ("verbose", ctypes.c_int)]
 
 
 class _StepReport(ctypes.Structure):
@@ -560,11 +561,13 @@ class SPMPS:
         _check(lib().sp_set_heff_plan(self._h, site, lds_budget, ctypes.byref(rows)))
         return rows.value
 
-    def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, solver="auto"):
+    def sweep(self, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, solver="auto", verbose=False):
         """Run sweeps; returns (status, list of per-step dicts).  solver:
         "host" (subspace solve on a host core), "device" (device-resident
-        iteration replayed from a HIP graph) or "auto" (host for one state)."""
-        return sweep_batch([self], n_sweeps, tol, max_iter, max_sub, keep, _single=True, solver=solver)
+        iteration replayed from a HIP graph) or "auto" (host for one state).
+        verbose: the library prints a line per site step on stderr."""
+        return sweep_batch([self], n_sweeps, tol, max_iter, max_sub, keep, _single=True, solver=solver,
+                           verbose=verbose)
 
 
 def _steps_out(steps, n):
@@ -576,13 +579,14 @@ def _steps_out(steps, n):
     return out
 
 
-def sweep_batch(states, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, _single=False, solver="auto"):
+def sweep_batch(states, n_sweeps, tol=1e-9, max_iter=64, max_sub=32, keep=8, _single=False, solver="auto",
+                verbose=False):
     """Sweeps of several SPMPS states (``sp_sweep_batch``; one state:
     ``sp_sweep``).  solver: "auto" (device-resident iteration for two or more
     states, host-driven for one), "host" or "device".  Returns (status,
     per-state lists of step dicts); for a single state with _single=True,
     (status, step dicts)."""
-    opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep, SOLVERS[solver])
+    opts = _SweepOpts(n_sweeps, tol, max_iter, max_sub, keep, SOLVERS[solver], int(bool(verbose)))
     caps = [max(1, n_sweeps * max(1, 2 * (st.L - 1))) for st in states]
     bufs = [(_StepReport * c)() for c in caps]
     reps = (_SweepReport * len(states))(*[_SweepReport(c, 0, b) for c, b in zip(caps, bufs)])

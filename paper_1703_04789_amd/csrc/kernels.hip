@@ -473,8 +473,15 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
     __shared__ double As[kKC][TILE + 1];
     __shared__ double Bs[kKC][TILE + 1];
     const TTask tk = tasks[blockIdx.x];
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int wr = (wave / WPR) * 32, wc = (wave % WPR) * 32;
+    // the 16 x 16 blocks of the wavefront's quarter that hold outputs of the
+    // task: a tile at the edge of a narrow block skips the rest's products
+    bool live[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) live[i][j] = tk.r0 + wr + 16 * i < tk.M && tk.c0 + wc + 16 * j < tk.N;
     const int li = lane % 16, lk = lane / 16;
     d4_t acc[2][2];
 #pragma unroll
@@ -567,10 +574,10 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
             for (int ks = 0; ks < kKC; ks += 4) {
                 const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
                 const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
-                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                if (live[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                if (live[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                if (live[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                if (live[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
             }
             __syncthreads();
         }
@@ -616,10 +623,10 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
                 for (int ks = 0; ks < kKC; ks += 4) {
                     const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
                     const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
-                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-                    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                    if (live[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                    if (live[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                    if (live[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                    if (live[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
                 }
                 __syncthreads();
             }
@@ -690,8 +697,15 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm_bf3(const TTa
     __shared__ __align__(16) unsigned short Ah[TILE][kKC3Pad], Al[TILE][kKC3Pad];
     __shared__ __align__(16) unsigned short Bh[TILE][kKC3Pad], Bl[TILE][kKC3Pad];
     const TTask tk = tasks[blockIdx.x];
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int wr = (wave / WPR) * 32, wc = (wave % WPR) * 32;
+    // the 16 x 16 blocks of the wavefront's quarter that hold outputs of the
+    // task: a tile at the edge of a narrow block skips the rest's products
+    bool live[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) live[i][j] = tk.r0 + wr + 16 * i < tk.M && tk.c0 + wc + 16 * j < tk.N;
     const int li = lane % 16, lk = lane / 16;
     f4_t acc[2][2];
 #pragma unroll
@@ -792,6 +806,7 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm_bf3(const TTa
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
+                    if (!live[i][j]) continue;
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
@@ -848,6 +863,7 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm_bf3(const TTa
                 for (int i = 0; i < 2; ++i)
     #pragma unroll
                     for (int j = 0; j < 2; ++j) {
+                        if (!live[i][j]) continue;
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);

@@ -2771,6 +2771,16 @@ spk::DavInst dav_inst(BatchState& st) {
     return I;
 }
 
+// A finished site step: into the caller's report (while it has room) and,
+// when asked, one line on stderr.
+void record_step(sp_sweep_report* r, int verbose, int state, const sp_step_report& st) {
+    if (r && r->steps && r->n_steps < r->capacity) r->steps[r->n_steps++] = st;
+    if (verbose)
+        std::fprintf(stderr, "[sp_sweep] state %d sweep %d site %d dir %+d: theta %.12f, %d matvecs%s, %.1f ms\n",
+                     state, st.sweep, st.site, st.dir, st.theta, st.matvecs, st.converged ? "" : " (not converged)",
+                     st.usec * 1e-3);
+}
+
 // One Davidson iteration of every running state per round (states are not
 // aligned on site steps: a state that finishes its local solve moves its
 // gauge, updates its environments and starts its next step at once).
@@ -3028,20 +3038,10 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
         for (int i : finished) {
             BatchState& st = B[i];
             if (!st.out.converged) status = SP_ENOCONV;
-            sp_sweep_report* r = reps[i];
-            if (r && r->steps && r->n_steps < r->capacity) {
-                sp_step_report& rp = r->steps[r->n_steps++];
-                rp.sweep = int(st.step / st.sweep_len);
-                rp.site = st.k;
-                rp.dir = st.order[st.step].second;
-                rp.iters = st.out.iters;
-                rp.converged = st.out.converged ? 1 : 0;
-                rp.matvecs = st.out.matvecs;
-                rp.theta = st.out.theta;
-                rp.pnorm = st.out.pnorm;
-                rp.rnorm = st.out.rnorm;
-                rp.usec = std::chrono::duration<double, std::micro>(t1 - st.t0).count();
-            }
+            record_step(reps[i], o.verbose, i,
+                        {int(st.step / st.sweep_len), st.k, st.order[st.step].second, st.out.iters,
+                         st.out.converged ? 1 : 0, st.out.matvecs, st.out.theta, st.out.pnorm, st.out.rnorm,
+                         std::chrono::duration<double, std::micro>(t1 - st.t0).count()});
             ++st.step;
             phase[i] = st.step < st.order.size() ? 0 : 2;
         }
@@ -3306,20 +3306,10 @@ int sweep_rounds(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector
             const int i = idx[q];
             BatchState& st = B[i];
             if (!st.out.converged) status = SP_ENOCONV;
-            sp_sweep_report* r = reps[i];
-            if (r && r->steps && r->n_steps < r->capacity) {
-                sp_step_report& rp = r->steps[r->n_steps++];
-                rp.sweep = int(st.step / st.sweep_len);
-                rp.site = st.k;
-                rp.dir = st.order[st.step].second;
-                rp.iters = st.out.iters;
-                rp.converged = st.out.converged ? 1 : 0;
-                rp.matvecs = st.out.matvecs;
-                rp.theta = st.out.theta;
-                rp.pnorm = st.out.pnorm;
-                rp.rnorm = st.out.rnorm;
-                rp.usec = std::chrono::duration<double, std::micro>(t1 - st.t0).count();
-            }
+            record_step(reps[i], o.verbose, i,
+                        {int(st.step / st.sweep_len), st.k, st.order[st.step].second, st.out.iters,
+                         st.out.converged ? 1 : 0, st.out.matvecs, st.out.theta, st.out.pnorm, st.out.rnorm,
+                         std::chrono::duration<double, std::micro>(t1 - st.t0).count()});
             ++st.step;
         }
     }
@@ -3607,19 +3597,9 @@ int sp_sweep(sp_handle* h, const sp_sweep_opts* o, sp_sweep_report* r) {
                 HIPCK(hipGetLastError());
                 const auto t1 = std::chrono::steady_clock::now();
                 if (!dv.converged) status = SP_ENOCONV;
-                if (r && r->steps && r->n_steps < r->capacity) {
-                    sp_step_report& st = r->steps[r->n_steps++];
-                    st.sweep = sw;
-                    st.site = k;
-                    st.dir = d;
-                    st.iters = dv.iters;
-                    st.converged = dv.converged ? 1 : 0;
-                    st.matvecs = dv.matvecs;
-                    st.theta = dv.theta;
-                    st.pnorm = dv.pnorm;
-                    st.rnorm = dv.rnorm;
-                    st.usec = std::chrono::duration<double, std::micro>(t1 - t0).count();
-                }
+                record_step(r, o->verbose, 0,
+                            {sw, k, d, dv.iters, dv.converged ? 1 : 0, dv.matvecs, dv.theta, dv.pnorm, dv.rnorm,
+                             std::chrono::duration<double, std::micro>(t1 - t0).count()});
             }
         }
         return status;
