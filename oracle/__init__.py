@@ -19,6 +19,9 @@ Modules, each following the paper (Li & Chan, SP-MPS):
 * ``mps``        -- the SP-MPS sweep: environments for every quadrature point,
   H_eff x and N_eff x, the diagonal, the Davidson local solve and the
   canonical gauge moves (Sec. 2.3).
+* ``slater``     -- closed-form energies of one or two occupation-number
+  determinants of the ab-initio Hamiltonian (Slater-Condon rules), with the
+  spin projector for an open-shell pair: exact values at any orbital count.
 
 Functions whose result is not pinned by a test against a closed form, a
 library routine, brute force or a printed value of the paper say
