@@ -30,6 +30,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def fused_kernel_sha256():
+    """sha256 of the fused kernel's source and the header of its task
+    layout, which key the committed hardware-counter summaries."""
+    import hashlib
+    hs = hashlib.sha256()
+    for f in ("heff3.hip", "kernels.h"):
+        hs.update(open(os.path.join(ROOT, "paper_1703_04789_amd", "csrc", f), "rb").read())
+    return hs.hexdigest()
+
+
 def measured_traffic(rows):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     summary (FETCH_SIZE and WRITE_SIZE, calibrated on a 64 MiB copy), or None
@@ -38,14 +48,13 @@ def measured_traffic(rows):
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "heff_hubbard_L32_D256_G9_fused_fp64_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_1703_04789_amd", "csrc", "kernels.hip")
     try:
         txt = open(path).read()
-        now = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        now = fused_kernel_sha256()
     except OSError:
         return None
     m_b = re.search(r"traffic_bytes_per_launch\[rows_per_task=%d\]: (\d+)" % rows, txt)
-    m_h = re.search(r"kernels.hip sha256: ([0-9a-f]+)", txt)
+    m_h = re.search(r"heff3.hip\+kernels.h sha256: ([0-9a-f]+)", txt)
     if not m_b or not m_h or m_h.group(1) != now:
         return None
     return float(m_b.group(1))
@@ -154,6 +163,12 @@ def small_sweep_runs(sp, W, torch):
             "note": "whole sweeps timed on both sides (oracle: set-up included); capped local solves"}
 
 
+def product_ms(prof):
+    """Milliseconds of one H_eff x from sp_heff_profile's phases, without the
+    once-per-local-problem pre-mixing of the left environment."""
+    return sum(p["ms"] for name, p in prof.items() if name != "premix_once")
+
+
 def abinitio_runs(sp, W, torch, sweeps=6):
     """Synthetic ab-initio-shaped Hamiltonian (seeded integrals, K=12, N=12,
     S=0, D=128, G=11) with the default per-site plans (no timing-based plan
@@ -181,9 +196,9 @@ def abinitio_runs(sp, W, torch, sweeps=6):
         x = torch.tensor(st.get_site(kc), dtype=torch.float64, device="cuda")
         y, ny = torch.empty_like(x), torch.empty_like(x)
         prof = st.heff_profile(kc, x, y, ny, reps=10)
-        ms = sum(p["ms"] for p in prof.values())
+        ms = product_ms(prof)
         fl = st.heff_flops(kc)
-        return ms, fl
+        return ms, fl, prof.get("premix_once", {}).get("ms", 0.0)
 
     def run(path, prec, tol, n_max, target=None):
         log(f"[bench] {wl.name} path={path} {prec}: init")
@@ -201,13 +216,13 @@ def abinitio_runs(sp, W, torch, sweeps=6):
             steps += s1
             if target is not None and energies[-1] <= target:
                 break
-        ms, fl = centre_heff(st)
+        ms, fl, pm = centre_heff(st)
         st.close()
         r = {"sweeps": len(energies), "seconds": t, "value": len(steps) / t, "energies": energies,
              "seconds_after_sweep": times, "solver_tol": tol,
              "matvecs_per_site_step": float(sum(x["matvecs"] for x in steps) / len(steps)),
              "heff_ms_centre": ms, "heff_flops_centre": fl, "heff_tflops_centre": fl / (ms * 1e-3) / 1e12,
-             "fused_sites": sum(1 for p in plans if p > 0)}
+             "premix_ms_centre_once_per_local_solve": pm, "fused_sites": sum(1 for p in plans if p > 0)}
         log(f"[bench] {wl.name} {path} {prec}: {r['value']:.2f} site steps/s over {len(energies)} sweeps, "
             f"E {energies[-1]:.10f}, H_eff x at site {kc} {ms:.3f} ms")
         return r, steps
@@ -239,6 +254,77 @@ def abinitio_runs(sp, W, torch, sweeps=6):
             "max_step_dE_tiled_vs_plain_first_sweep": dE_plain,
             "note": "integrals from the seeded recipe of the 30-orbital workload at 12 orbitals; one-site sweeps "
                     "with a fixed block table descend slowly here (about 1e-3 per sweep after ten sweeps)"}
+
+
+def abinitio_full_runs(sp, W, torch, sweeps=3):
+    """The 30-orbital workload at its stated size (K=30, N=30, S=0, D=500,
+    G=11, seed 4) from the seeded random start: `sweeps` FP64 sweeps, then
+    split-BF16 sweeps from the same start until the energy reaches the FP64
+    run's final energy + 1e-6 (at most 2 x `sweeps`), each with the site
+    steps per second, energy after every sweep and the centre H_eff x after
+    the sweeps.  The library prints one line per site step."""
+    wl = W.abinitio_full()
+    h, eri = wl.integrals()
+    t0 = time.perf_counter()
+    mpo = sp.mpo_abinitio(h, eri)
+    t_mpo = time.perf_counter() - t0
+    log(f"[bench] {wl.name}: MPO {t_mpo:.1f} s, max bond {int(max(mpo[0]))}")
+    tab, blocks = wl.table(), wl.blocks()
+    kc = wl.K // 2
+
+    def run(prec, tol, n_max, target=None):
+        log(f"[bench] {wl.name} {prec}: init")
+        t0 = time.perf_counter()
+        st = sp.SPMPS(tab, blocks, mpo, wl.twoS, wl.G, precision=prec)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+        free, total = torch.cuda.mem_get_info()
+        energies, times, steps, t = [], [], [], 0.0
+        for n in range(n_max):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, s1 = st.sweep(1, tol=tol, verbose=True)
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            energies.append(s1[-1]["theta"])
+            times.append(t)
+            steps += s1
+            log(f"[bench] {wl.name} {prec} sweep {n}: E {energies[-1]:.10f}, {len(steps) / t:.3f} site steps/s")
+            if target is not None and energies[-1] <= target:
+                break
+        for j in range(1, kc):
+            st.env_update(j, +1)
+        x = torch.tensor(st.get_site(kc), dtype=torch.float64, device="cuda")
+        y, ny = torch.empty_like(x), torch.empty_like(x)
+        prof = st.heff_profile(kc, x, y, ny, reps=3)
+        ms = product_ms(prof)
+        pm = prof.get("premix_once", {}).get("ms", 0.0)
+        fl = st.heff_flops(kc)
+        st.close()
+        del st
+        torch.cuda.empty_cache()
+        return {"setup_s": t_init, "device_gb_in_use_after_setup": (total - free) / 1e9, "solver_tol": tol,
+                "sweeps": len(energies), "seconds": t, "value": len(steps) / t, "energies": energies,
+                "seconds_after_sweep": times,
+                "matvecs_per_site_step": float(sum(x["matvecs"] for x in steps) / len(steps)),
+                "converged_steps": int(sum(1 for x in steps if x["converged"])), "site_steps": len(steps),
+                "heff_ms_centre": ms, "heff_flops_centre": fl, "heff_tflops_centre": fl / (ms * 1e-3) / 1e12,
+                "premix_ms_centre_once_per_local_solve": pm}
+
+    t64 = run("fp64", 1e-9, sweeps)
+    target = t64["energies"][-1] + 1e-6
+    b16 = run("bf16x3", 1e-5, 2 * sweeps, target=target)
+    n_eq = min(len(b16["energies"]), len(t64["energies"]))
+    b16["dE_vs_fp64_per_sweep"] = [a - b for a, b in zip(b16["energies"][:n_eq], t64["energies"][:n_eq])]
+    b16["reached_fp64_energy"] = b16["energies"][-1] <= target
+    b16["time_to_fp64_energy_speedup"] = (t64["seconds"] / b16["seconds"]) if b16["reached_fp64_energy"] else None
+    log(f"[bench] {wl.name}: FP64 {t64['value']:.3f} site steps/s, E {t64['energies'][-1]:.10f} after {sweeps} "
+        f"sweeps in {t64['seconds']:.1f} s; split BF16 {b16['value']:.3f} site steps/s, "
+        f"E {b16['energies'][-1]:.10f} after {b16['sweeps']} sweeps in {b16['seconds']:.1f} s "
+        f"(reached the FP64 energy: {b16['reached_fp64_energy']})")
+    return {"workload": wl.name, "K": wl.K, "N": wl.N, "twoS": wl.twoS, "D": wl.D, "G": wl.G, "seed": wl.seed,
+            "mpo_max_bond": int(max(mpo[0])), "mpo_build_s": t_mpo, "unit": "site steps/s", "fp64": t64,
+            "bf16x3": b16}
 
 
 def batch_runs(sp, W, torch, n=64):
@@ -395,9 +481,14 @@ def main():
                     help="skip the batched-states run (64 broken-symmetry Hubbard guesses, D up to 512)")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the learned-preconditioner training and evaluation")
-    ap.add_argument("--heff-workload", default="hubbard", choices=["hubbard", "abinitio", "abinitio16"],
+    ap.add_argument("--heff-workload", default="hubbard", choices=["hubbard", "abinitio", "abinitio16", "abinitio30"],
                     help="state of the --heff-only run: the benchmark Hubbard chain, the ab-initio workload "
-                         "(K=12, D=128) or a larger ab-initio state (K=16, D=256)")
+                         "(K=12, D=128), a larger ab-initio state (K=16, D=256) or the 30-orbital one at its "
+                         "stated size (K=30, D=500)")
+    ap.add_argument("--abinitio-full", action="store_true",
+                    help="only the 30-orbital ab-initio workload at K=30, D=500, G=11: FP64 sweeps, then split "
+                         "BF16 until it reaches the FP64 energy (about 15 minutes); one JSON line")
+    ap.add_argument("--abinitio-sweeps", type=int, default=3, help="FP64 sweeps of --abinitio-full")
     ap.add_argument("--heff-only", type=int, default=0,
                     help="only run this many H_eff x applications at the centre site, after a 64 MiB "
                          "device copy of known size (for hardware-counter runs), and exit")
@@ -419,24 +510,40 @@ def main():
     kw = dict(tol=args.tol, max_iter=args.max_iter, max_sub=args.max_sub, keep=args.keep)
     kc = wl.L // 2
 
+    if args.abinitio_full:
+        r = abinitio_full_runs(sp, W, torch, sweeps=args.abinitio_sweeps)
+        print(json.dumps({"metric": "projected-sweep site steps per second", "value": r["fp64"]["value"],
+                          "unit": "site steps/s", "n_gpus": 1, "steps": r["fp64"]["sweeps"], "warmup": 0,
+                          "ms_per_step": r["fp64"]["seconds"] / r["fp64"]["sweeps"] * 1e3,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": r["workload"], "K": r["K"], "D": r["D"],
+                                                          "G": r["G"], "twoS": r["twoS"]},
+                          "abinitio_full": r}), flush=True)
+        return
+
     if args.heff_only:
         # calibration: a plain copy of exactly 64 MiB (read 64 MiB, write 64 MiB)
         src = torch.ones(8 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        if args.heff_workload in ("abinitio", "abinitio16"):
-            aw = W.abinitio_reduced(12, 128, 11) if args.heff_workload == "abinitio" else W.abinitio_reduced(16, 256, 11)
+        if args.heff_workload in ("abinitio", "abinitio16", "abinitio30"):
+            aw = {"abinitio": lambda: W.abinitio_reduced(12, 128, 11),
+                  "abinitio16": lambda: W.abinitio_reduced(16, 256, 11),
+                  "abinitio30": W.abinitio_full}[args.heff_workload]()
             gpu = sp.SPMPS(aw.table(), aw.blocks(), sp.mpo_abinitio(*aw.integrals()), aw.twoS, aw.G, path=args.path,
                            precision=args.precision)
             kc = aw.K // 2
         else:
             gpu = sp.SPMPS(tab, wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G, path=args.path,
                            precision=args.precision)
+        log(f"[bench] --heff-only: state of {args.heff_workload} set up")
         if args.path == "tiled" and not args.no_autotune:
             gpu.autotune(reps=5)
         for j in range(1, kc):
             gpu.env_update(j, +1)
+        torch.cuda.synchronize()
+        log(f"[bench] --heff-only: left environments up to site {kc} built")
         x = torch.tensor(gpu.get_site(kc), dtype=torch.float64, device="cuda")
         y, ny = torch.empty_like(x), torch.empty_like(x)
         # the Hubbard centre runs every fused plan the autotuner can choose
@@ -459,7 +566,7 @@ def main():
                 f"site size {x.numel()}, algorithmic flops {gpu.heff_flops(kc):.4e}, plan {gpu.heff_plan(kc)}")
         if args.heff_workload != "hubbard":
             prof = gpu.heff_profile(kc, x, y, ny, reps=5)
-            ms = sum(p["ms"] for p in prof.values())
+            ms = product_ms(prof)
             log(f"[bench] {args.heff_workload} H_eff x at site {kc}: {ms:.3f} ms, "
                 f"{gpu.heff_flops(kc) / (ms * 1e-3) / 1e12:.3f} TFLOP/s algorithmic")
         gpu.close()
@@ -494,7 +601,7 @@ def main():
         x = torch.tensor(gpu.get_site(kc), dtype=torch.float64, device="cuda")
         y, ny = torch.empty_like(x), torch.empty_like(x)
         prof = gpu.heff_profile(kc, x, y, ny, reps=50)
-        heff_ms = sum(p["ms"] for p in prof.values())
+        heff_ms = product_ms(prof)
         heff_flops = gpu.heff_flops(kc)
         plan = gpu.heff_plan(kc) if path == "tiled" else (0, 0)
         gpu.close()

@@ -354,11 +354,14 @@ int sp_heff_flops(const sp_handle* h, int site, double* flops);
 
 /* Timing of the phases of sp_heff_apply at `site`, each averaged over
  * `reps` launches.  Plain path: left product, W r mixing, right product.
- * Tiled path: the fused launch (at a site without a fused plan the tiled
- * block-product lists) (left product, mixing and right product in
- * one kernel), nothing, the g sum.  Each phase is averaged over
- * `reps` launches with HIP events on the handle's stream.  out[0..2]: mean
- * milliseconds per launch; out[3..5]: algorithmic flops per launch;
+ * Tiled path: the fused launch (left product, mixing and right product in
+ * one kernel) or, at a site without a fused plan, the tiled block-product
+ * lists; then the pre-mixing of the left environment that the block
+ * products build once per local problem (timed once, before the products,
+ * and not part of their time; 0 at a fused site); then the g sum.  Phases
+ * are timed with HIP events on the handle's stream.  out[0..2]: mean
+ * milliseconds per launch; out[3..5]: algorithmic flops per launch (tiled
+ * path: the product, the pre-mixing's scaled adds, the g sum);
  * out[6..8]: algorithmic bytes per launch (every array read or written once:
  * environments, site vector, intermediates, outputs).  x, y, ny as in
  * sp_heff_apply.  Synchronises. */

@@ -468,11 +468,14 @@ class SPMPS:
 
     def heff_profile(self, k, x, y, ny, reps=20):
         """Per-launch timing of H_eff x at site k: dict of (ms, flops, bytes)
-        for the left product, the mixing and the right product."""
+        for the left product, the mixing and the right product (plain path),
+        or for the product, the once-per-local-problem pre-mixing of the left
+        environment (block-product sites; not part of the product's time)
+        and the g sum (tiled path)."""
         out = np.zeros(9)
         _check(lib().sp_heff_profile(self._h, k, reps, _dev(x), _dev(y), _dev(ny), _dptr(out)))
         names = (("left_product", "mixing", "right_product") if self.path == "plain"
-                 else ("fused_heff", None, "g_sum"))
+                 else ("fused_heff", "premix_once", "g_sum"))
         return {n: dict(ms=out[i], flops=out[3 + i], bytes=out[6 + i]) for i, n in enumerate(names) if n}
 
     def center(self):

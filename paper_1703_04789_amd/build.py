@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libspmps.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "mlp.hip", "davdev.hip", "spmps.cpp", "host_linalg.cpp"]
+SOURCES = ["kernels.hip", "heff3.hip", "mlp.hip", "davdev.hip", "spmps.cpp", "host_linalg.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Werror=infinite-recursion", "-Werror=return-type",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

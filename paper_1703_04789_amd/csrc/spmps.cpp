@@ -4224,6 +4224,21 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
         hipEvent_t ev[4];
         for (auto& e : ev) HIPCK(hipEventCreate(&e));
         double ms[3] = {0, 0, 0};
+        double premix_ms = 0.0;
+        if (!plain && P.h_rows == 0) {
+            // the pre-mixed left environment of the block products is built
+            // once per local problem and reused by every product of the
+            // solve: timed on its own, outside the products
+            HIPCK(hipEventRecord(ev[0], s));
+            P.premix.launch(s, b, P.coef.p);
+            HIPCK(hipEventRecord(ev[1], s));
+            HIPCK(hipEventSynchronize(ev[1]));
+            float t = 0.f;
+            HIPCK(hipEventElapsedTime(&t, ev[0], ev[1]));
+            premix_ms = t;
+            h->lt_site = site;
+            h->lt_gen = h->Lgen[site - 1];
+        }
         for (int r = 0; r < reps; ++r) {
             HIPCK(hipEventRecord(ev[0], s));
             if (plain) {
@@ -4262,8 +4277,9 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
             // the product into per-g partials (the fused launch, or the tiled
             // lists at a site without a fused plan): environments and x read
             // once, per-g partials written
+            out[1] = premix_ms;
             out[3] = P.p1.flops + P.mixl.flops + P.yout.flops;
-            out[4] = 0.0;
+            out[4] = P.premix.flops;
             out[5] = 2.0 * G * xs;
             out[6] = 8.0 * (Lb + Rb + xs + 2.0 * G * xs);
             out[7] = 0.0;
