@@ -4279,7 +4279,7 @@ int sp_heff_profile(sp_handle* h, int site, int reps, const double* x, double* y
             // once, per-g partials written
             out[1] = premix_ms;
             out[3] = P.p1.flops + P.mixl.flops + P.yout.flops;
-            out[4] = P.premix.flops;
+            out[4] = P.h_rows == 0 ? P.premix.flops : 0.0;
             out[5] = 2.0 * G * xs;
             out[6] = 8.0 * (Lb + Rb + xs + 2.0 * G * xs);
             out[7] = 0.0;
