@@ -35,6 +35,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -295,6 +296,11 @@ struct SitePlan {
     int c_g() const { return 2 * nW; }
     int c_gr(int s, int u) const { return 2 * nW + 1 + 4 * s + u; }
     int c_one() const { return 2 * nW + 17; }
+    // unrotated MPO entries W[a, b, s, s'] (block-product path) and the
+    // rotation r_g(s, u) itself
+    int nWr = 0;
+    int c_wr(int e) const { return 2 * nW + 18 + e; }
+    int c_r(int s, int u) const { return 2 * nW + 18 + nWr + 4 * s + u; }
     // scratch sizes per quadrature point
     long long Tsize = 0, Vsize = 0, Zsize = 0, Ztsize = 0;
     BList p1, yout, envl_out, p1r, envr_out;
@@ -325,7 +331,7 @@ struct SitePlan {
     // environment Lt(sigma, c', sigma', i) = sum_c W~_g[c, c', sigma, sigma'] L_g(c, i)
     // (premix, once per local problem), V = sum_sigma' Lt Xd(sigma') (t_leftv)
     // and the identity-channel products T(0, i, sigma') for N_eff (t_left0)
-    CList premix;
+    CList premix, xrmix;
     TList t_leftv, t_left0;
     long long LTsize = 0;
     int tr_split = 1;  // channel chunks of the tiled right product (partials: tr_split * G)
@@ -701,7 +707,27 @@ void build_plan(sp_handle* h, int k) {
         byR[size_t(q[2]) * wl + q[0]].push_back({q[1], q[3], e});
         if (q[2] == q[3]) byD[q[2]].push_back({q[0], q[1], e});
     }
-    P.nc = 2 * P.nW + 18;
+    // the unrotated entries W[a, b, s, s'] of the blocks in the pattern, by
+    // (s, b) as (a, s', entry) in ascending order: the block products
+    // pre-mix the left environment with them and apply the rotation to the
+    // site vector instead (Eq. [expSy] acts on s' only)
+    std::vector<std::vector<std::array<int, 3>>> byWr(size_t(4) * wr);
+    std::vector<double> wr_val;
+    {
+        std::set<std::pair<int, int>> blocks;
+        for (const auto& q : P.went) blocks.insert({q[0], q[1]});
+        for (const auto& ab : blocks) {
+            const double* op = &Wk[(size_t(ab.first) * wr + ab.second) * 16];
+            for (int s2 = 0; s2 < 4; ++s2)
+                for (int v = 0; v < 4; ++v)
+                    if (op[s2 * 4 + v] != 0.0) {
+                        byWr[size_t(s2) * wr + ab.second].push_back({ab.first, v, int(wr_val.size())});
+                        wr_val.push_back(op[s2 * 4 + v]);
+                    }
+        }
+    }
+    P.nWr = int(wr_val.size());
+    P.nc = 2 * P.nW + 18 + P.nWr + 16;
     P.coef_h.assign(size_t(G) * P.nc, 0.0);
     for (int g = 0; g < G; ++g) {
         double* cf = &P.coef_h[size_t(g) * P.nc];
@@ -717,6 +743,9 @@ void build_plan(sp_handle* h, int k) {
         for (int s = 0; s < 4; ++s)
             for (int u = 0; u < 4; ++u) cf[P.c_gr(s, u)] = h->qcoef[g] * rot_value(s, u, h->qc[g], h->qs[g]);
         cf[P.c_one()] = 1.0;
+        for (int e = 0; e < P.nWr; ++e) cf[P.c_wr(e)] = wr_val[e];
+        for (int s = 0; s < 4; ++s)
+            for (int u = 0; u < 4; ++u) cf[P.c_r(s, u)] = rot_value(s, u, h->qc[g], h->qs[g]);
     }
     const long long Lsz = el.size, Rsz = er.size;
 
@@ -1159,41 +1188,73 @@ void build_plan(sp_handle* h, int k) {
                                              g * P.nc + P.c_one());
                     }
             }
-    // pre-mixed left environment: one Lt block per (sigma, c', i, sigma') of
-    // the mixing, shaped like the environment blocks it sums (rows of bra
-    // N-block i x ket N-block j, the same j for every channel c of the group)
+    // Pre-mixed left environment with the unrotated MPO, Lt(sigma, c', i,
+    // sigma'') = sum_c W[c, c', sigma, sigma''] L(c, i) (rows of bra N-block i
+    // x ket N-block j, the same j for every channel c of the group), and the
+    // rotated site vector Xr(sigma'', j) = sum_sigma' r_g(sigma'', sigma')
+    // Xd(j, sigma') (Eq. [expSy]: it mixes the two singly occupied states
+    // only, so Xr = Xd for the empty and doubly occupied states), so that
+    // V(sigma, c', i) = sum_sigma'' Lt(sigma, c', i, sigma'') Xr(sigma'', j).
+    // The rotation acts on the site vector, which is small, instead of
+    // multiplying the environment blocks: fewer and smaller Lt blocks.  The
+    // Lt blocks are built once per local problem, the Xr blocks with every
+    // product; both live in the pre-mixed scratch (Lt first, then Xr).
     for (TList* tl : {&P.t_leftv, &P.t_left0}) tl->tile = TT;
     {
         struct LtBlk {
-            int sig, cp, i, q, j;
+            int j;
             long long off;
-            std::vector<std::pair<int, int>> terms;  // (env block e, rotated-MPO entry)
+            std::vector<std::pair<int, int>> terms;  // (env block e, unrotated entry)
         };
         std::vector<LtBlk> lts;
-        std::map<std::array<int, 4>, int> ltidx;
+        std::map<std::array<int, 4>, int> ltidx;  // (sigma, c', i, sigma'')
         long long lto = 0;
-        for (const VTerm& v : vterms) {
-            const EnvBlk& eb = el.blk[v.e];
-            auto it = ltidx.find({v.sig, v.cp, v.i, v.q});
-            if (it == ltidx.end()) {
-                ltidx[{v.sig, v.cp, v.i, v.q}] = int(lts.size());
-                lts.push_back(LtBlk{v.sig, v.cp, v.i, v.q, eb.j, lto, {}});
-                lto += (long long)eb.rows * eb.cols;
-                it = ltidx.find({v.sig, v.cp, v.i, v.q});
+        for (int sig = 0; sig < 4; ++sig)
+            for (int cp = 0; cp < wr; ++cp)
+                for (int i = 0; i < int(bl.nb.size()); ++i) {
+                    if (!Voff.count({sig, cp, i})) continue;
+                    for (const auto& ent : byWr[size_t(sig) * wr + cp]) {
+                        const int c = ent[0], s2 = ent[1];
+                        const int e = el.find(c, i);
+                        if (e < 0) continue;
+                        const EnvBlk& eb = el.blk[e];
+                        if (xdoff(eb.j, s2) < 0) continue;
+                        auto it = ltidx.find({sig, cp, i, s2});
+                        if (it == ltidx.end()) {
+                            it = ltidx.emplace(std::array<int, 4>{sig, cp, i, s2}, int(lts.size())).first;
+                            lts.push_back(LtBlk{eb.j, lto, {}});
+                            lto += (long long)eb.rows * eb.cols;
+                        }
+                        LtBlk& lb = lts[it->second];
+                        SP_REQUIRE(lb.j == eb.j, "internal: inconsistent particle numbers in the pre-mixed environment");
+                        lb.terms.push_back({e, ent[2]});
+                    }
+                }
+        // rotated site-vector blocks of the singly occupied states
+        std::map<std::array<int, 2>, long long> xroff;  // (sigma'' in {1, 2}, j)
+        long long xro = lto;
+        for (int j = 0; j < int(bl.nb.size()); ++j)
+            for (int s2 = 1; s2 <= 2; ++s2) {
+                if (xdoff(j, s2) < 0) continue;
+                xroff[{s2, j}] = xro;
+                xro += (long long)bl.nb[j].dim * br.nb[br.nblock(bl.nb[j].n + kSigmaN[s2])].dim;
             }
-            LtBlk& lb = lts[it->second];
-            SP_REQUIRE(lb.j == eb.j && eb.i == v.i, "internal: inconsistent particle numbers in the pre-mixed environment");
-            lb.terms.push_back({v.e, v.widx});
-        }
-        P.LTsize = lto;
+        P.LTsize = xro;
         for (int g = 0; g < G; ++g)
             for (const LtBlk& lb : lts) {
                 const EnvBlk& e0 = el.blk[lb.terms[0].first];
                 P.premix.add_task(B_LT, g * P.LTsize + lb.off, e0.rows * e0.cols);
                 for (const auto& tm : lb.terms)
-                    P.premix.add_term(B_ENVL, g * Lsz + el.blk[tm.first].off, g * P.nc + P.c_wt(tm.second));
+                    P.premix.add_term(B_ENVL, g * Lsz + el.blk[tm.first].off, g * P.nc + P.c_wr(tm.second));
             }
-        // V(sigma, c', i) = sum over sigma' (ascending) of Lt(sigma, c', i, sigma') Xd(j, sigma', .)
+        for (int g = 0; g < G; ++g)
+            for (const auto& kv : xroff) {
+                const int s2 = kv.first[0], j = kv.first[1];
+                const int ncol = br.nb[br.nblock(bl.nb[j].n + kSigmaN[s2])].dim;
+                P.xrmix.add_task(B_LT, g * P.LTsize + kv.second, bl.nb[j].dim * ncol);
+                for (int q = 1; q <= 2; ++q) P.xrmix.add_term(B_X, xdoff(j, q), g * P.nc + P.c_r(s2, q));
+            }
+        // V(sigma, c', i) = sum over sigma'' (ascending) of Lt(sigma, c', i, sigma'') Xr(sigma'', j)
         for (int g = 0; g < G; ++g)
             for (int sig = 0; sig < 4; ++sig)
                 for (int cp = 0; cp < wr; ++cp)
@@ -1207,16 +1268,30 @@ void build_plan(sp_handle* h, int k) {
                         for (int r0 = 0; r0 < M; r0 += TT)
                             for (int c0 = 0; c0 < ncol; c0 += TT) {
                                 P.t_leftv.add_task(B_V, g * P.Vsize + vo->second, ncol, M, ncol, r0, c0, 0, 0);
-                                for (int q = 0; q < 4; ++q) {
-                                    auto li = ltidx.find({sig, cp, i, q});
+                                for (int s2 = 0; s2 < 4; ++s2) {
+                                    auto li = ltidx.find({sig, cp, i, s2});
                                     if (li == ltidx.end()) continue;
                                     const LtBlk& lb = lts[li->second];
-                                    SP_REQUIRE(br.nblock(bl.nb[lb.j].n + kSigmaN[q]) == nbp,
+                                    SP_REQUIRE(br.nblock(bl.nb[lb.j].n + kSigmaN[s2]) == nbp,
                                                "internal: pre-mixed product columns");
-                                    int k0, k1;
-                                    if (k_from_cols(nbp, q, c0, std::min(ncol, c0 + TT), k0, k1))
+                                    // rows of Xr reached by the tile's columns: those of
+                                    // every state the rotation mixes into sigma''
+                                    int k0 = INT32_MAX, k1 = -1;
+                                    for (int q = 0; q < 4; ++q) {
+                                        int a0, a1;
+                                        if (rot_nonzero(s2, q) && k_from_cols(nbp, q, c0, std::min(ncol, c0 + TT), a0, a1)) {
+                                            k0 = std::min(k0, a0);
+                                            k1 = std::max(k1, a1);
+                                        }
+                                    }
+                                    if (k1 <= k0) continue;
+                                    if (s2 == 1 || s2 == 2)
+                                        P.t_leftv.add_seg(B_LT, g * P.LTsize + lb.off, bl.nb[lb.j].dim, 0, B_LT,
+                                                          g * P.LTsize + xroff.at({s2, lb.j}), ncol, 0, k0, k1,
+                                                          g * P.nc + P.c_one());
+                                    else
                                         P.t_leftv.add_seg(B_LT, g * P.LTsize + lb.off, bl.nb[lb.j].dim, 0, B_X,
-                                                          xdoff(lb.j, q), ncol, 0, k0, k1, g * P.nc + P.c_one());
+                                                          xdoff(lb.j, s2), ncol, 0, k0, k1, g * P.nc + P.c_one());
                                 }
                             }
                     }
@@ -1673,6 +1748,7 @@ void upload_plan(sp_handle* h, int k) {
     P.t_leftv.upload(s);
     P.t_left0.upload(s);
     P.premix.upload(s);
+    P.xrmix.upload(s);
     P.t_right.upload(s);
     P.t_envl.upload(s);
     P.t_zr.upload(s);
@@ -1859,6 +1935,7 @@ void validate_plans(sp_handle* h) {
                 validate(P.t_leftv, t, nco, ms, xs, "tiled product of the pre-mixed environment");
                 validate(P.t_left0, t, nco, ms, xs, "tiled identity-channel product");
                 validate(P.premix, t, nco, "pre-mixed left environment");
+                validate(P.xrmix, t, nco, "rotated site vector");
             }
             validate(P.t_right, t, nco, ms, xs, "tiled right product");
             validate(P.t_zr, t, nco, ms, xs, "tiled right-pass product");
@@ -1990,6 +2067,7 @@ void heff_tiled(sp_handle* h, int k, const double* x, bool bf3 = false, double* 
         h->lt_site = k;
         h->lt_gen = h->Lgen[k - 1];
     }
+    P.xrmix.launch(s, b, P.coef.p);
     P.t_left0.launch(s, b, P.coef.p, P.xmap.p, bf3);
     P.t_leftv.launch(s, b, P.coef.p, P.xmap.p, bf3);
     if (P.tr_split > 1) {  // slots without a chunk of some tile stay zero
