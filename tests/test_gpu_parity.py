@@ -372,3 +372,17 @@ def test_status_unconverged_sweep():
     assert rc == sp.SP_ENOCONV and not any(s["converged"] for s in steps)
     rc, steps = gpu.sweep(1, max_sub=128, max_iter=200)
     assert rc == sp.SP_OK and all(s["converged"] for s in steps)
+
+
+def test_verbose_sweep_prints_one_line_per_step(capfd):
+    # the library reports every finished site step on stderr when asked, in
+    # the order of the step reports, and stays silent otherwise
+    tab, gpu, _ = make_pair(6, 6, 0, 16, 0, 4, oracle=False)
+    rc, steps = gpu.sweep(1, verbose=True)
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("[sp_sweep]")]
+    assert len(lines) == len(steps) == 2 * (tab.L - 1)
+    for ln, st in zip(lines, steps):
+        assert f"site {st['site']} dir {st['dir']:+d}" in ln and f"theta {st['theta']:.12f}" in ln
+    gpu.sweep(1)
+    assert not [ln for ln in capfd.readouterr().err.splitlines() if ln.startswith("[sp_sweep]")]
