@@ -10,6 +10,11 @@ steps per second; the JSON line also carries H_eff x throughput, the
 roofline of the dominant kernel and the oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+
+Other modes, each printing its own JSON line: --abinitio-full (the
+30-orbital workload at K=30, D=500, G=11: FP64 sweeps, then split-BF16
+sweeps to the same energy) and --heff-only N (N products at a centre site,
+for hardware-counter runs; --heff-workload picks the state).
 """
 import argparse
 import json
