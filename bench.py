@@ -11,10 +11,10 @@ roofline of the dominant kernel and the oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 
-Other modes, each printing its own JSON line: --abinitio-full (the
-30-orbital workload at K=30, D=500, G=11: FP64 sweeps, then split-BF16
-sweeps to the same energy) and --heff-only N (N products at a centre site,
-for hardware-counter runs; --heff-workload picks the state).
+Other modes: --abinitio-full (the 30-orbital workload at K=30, D=500,
+G=11: FP64 sweeps, then split-BF16 sweeps to the same energy; its own JSON
+line) and --heff-only N (N products at a centre site for hardware-counter
+runs, --heff-workload picking the state; log lines only).
 """
 import argparse
 import json
