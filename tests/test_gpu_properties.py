@@ -72,3 +72,24 @@ def test_energy_components_match_the_oracle():
         assert abs(e[p - 1] - ref) < 1e-10, p
     E, _ = gpu.energy()
     assert abs(e.sum() - E) < 1e-10
+
+
+@pytest.mark.parametrize("twoS", [0, 2])
+def test_bench_shape_projected_invariants(twoS):
+    # L=32, U=8, D=256, G=9 (the benchmark workload, S=0 and S=1) after one
+    # sweep: with the exact quadrature the projected state is a pure spin-S
+    # state, so <S^2 P>/<P> = S(S+1) exactly at any bond dimension (checks
+    # the rotated environments and the projector on the benchmark's own
+    # state; no oracle fits this size), and the energy of the final state is
+    # the last step's eigenvalue
+    import workloads as W
+    wl = W.hubbard_bench(twoS)
+    gpu = sp.SPMPS(wl.table(), wl.blocks(), sp.mpo_hubbard(wl.L, wl.t, wl.U), wl.twoS, wl.G)
+    print(f"[case] bench shape 2S={twoS}", flush=True)
+    rc, steps = gpu.sweep(1)
+    s2, p = gpu.expect(sp.mpo_s2(wl.L))
+    S = twoS / 2
+    assert abs(s2 - S * (S + 1)) < 1e-8 and 0.0 < p <= 1.0 + 1e-12
+    E, _ = gpu.energy()
+    assert abs(E - steps[-1]["theta"]) < 1e-8
+    gpu.close()
