@@ -75,3 +75,19 @@ def test_open_shell_singlet(ham):
     E_ref, n_ref = slater.open_shell_singlet(h, eri, core, p, q)
     assert abs(normP - n_ref) < 1e-10
     assert abs(E - E_ref) < 1e-8
+
+
+def test_full_size_state_is_projected_to_the_singlet():
+    # the seeded K=30, D=500 starting state of the 30-orbital workload with
+    # the S^2 operator in place of H: <S^2 P>/<P> = 0 for the S=0 projector
+    # with G=11 points (above the exact count), through the full block table
+    # and all 11 rotated environments
+    wl = W.abinitio_full()
+    tab = wl.table()
+    print(f"[case] K={wl.K} D={wl.D} G={wl.G} S^2", flush=True)
+    st = sp.SPMPS(tab, wl.blocks(), sp.mpo_s2(wl.K), wl.twoS, wl.G)
+    try:
+        s2, normP = st.energy()
+    finally:
+        st.close()
+    assert abs(s2) < 1e-8 and 0.0 < normP < 1.0
