@@ -91,3 +91,35 @@ def test_full_size_state_is_projected_to_the_singlet():
     finally:
         st.close()
     assert abs(s2) < 1e-8 and 0.0 < normP < 1.0
+
+
+def test_full_size_centre_products_are_symmetric():
+    # H_eff and N_eff at the centre of the K=30, D=500, G=11 state (the
+    # benchmark's tiled plan: 64 x 64 tiles, split channel sums) are the
+    # symmetric matrices Phi^T H P Phi and Phi^T P Phi (P commutes with H and
+    # is symmetric, the quadrature being exact), and N_eff is positive
+    # semidefinite: <u, H v> = <v, H u>, <u, N v> = <v, N u>, <u, N u> >= 0
+    import torch
+    wl = W.abinitio_full()
+    h, eri = wl.integrals()
+    print(f"[case] K={wl.K} D={wl.D} G={wl.G} centre products", flush=True)
+    st = sp.SPMPS(wl.table(), wl.blocks(), sp.mpo_abinitio(h, eri), wl.twoS, wl.G)
+    try:
+        kc = wl.K // 2
+        for j in range(1, kc):
+            st.env_update(j, +1)
+        n = st.site_size(kc)
+        rng = np.random.default_rng(30)
+        u = torch.tensor(rng.standard_normal(n), dtype=torch.float64, device="cuda")
+        v = torch.tensor(rng.standard_normal(n), dtype=torch.float64, device="cuda")
+        hu, nu, hv, nv = (torch.empty_like(u) for _ in range(4))
+        st.heff_apply(kc, u, hu, nu)
+        st.heff_apply(kc, v, hv, nv)
+        torch.cuda.synchronize()
+        scale_h = float(torch.linalg.norm(u) * max(torch.linalg.norm(hu), torch.linalg.norm(hv)))
+        scale_n = float(torch.linalg.norm(u) * max(torch.linalg.norm(nu), torch.linalg.norm(nv)))
+        assert abs(float(u @ hv - v @ hu)) < 1e-11 * scale_h
+        assert abs(float(u @ nv - v @ nu)) < 1e-11 * scale_n
+        assert float(u @ nu) > -1e-11 * scale_n and float(v @ nv) > -1e-11 * scale_n
+    finally:
+        st.close()
