@@ -2048,12 +2048,14 @@ spk::H3Inst heff_inst(sp_handle* h, int k, const double* x, bool f32, double* yp
 }
 
 // H_eff x at a tiled-path site without a fused plan (a particle-number block
-// too wide for its LDS): the LDS-tiled block-product lists, FP64 in either
-// precision, leaving the same per-g partials as the fused kernel.  The W r
-// mixing is applied to the left environment instead of to the products
-// L_g x: the pre-mixed environment depends only on L[k-1] and is built once
-// per local problem (the first product after L[k-1] changes), so each
-// product is two block-product launches and no mixing pass.
+// too wide for its LDS): the LDS-tiled block-product lists (FP64, or split
+// BF16 in that mode), leaving the same per-g partials as the fused kernel.
+// The MPO is mixed into the left environment instead of into the products
+// L_g x, and the rotation r_g into the site vector: the pre-mixed
+// environment depends only on L[k-1] and is built once per local problem
+// (the first product after L[k-1] changes), the rotated site vector (two
+// small blocks per particle-number block) with every product, so each
+// product is one small mixing launch and two block-product launches.
 void heff_tiled(sp_handle* h, int k, const double* x, bool bf3 = false, double* yp = nullptr,
                 double* nyp = nullptr) {
     SitePlan& P = h->plan[k - 1];
