@@ -451,12 +451,13 @@ __global__ __launch_bounds__(kThreads) void k_basis_rotate(const double* __restr
 // hold as many of these latency-bound work-groups as it has wave slots (a
 // chunk of 16 halves that and is 1.3x slower at the ab-initio centre, 32 is
 // 1.8x slower); the chunk size does not change the sequence of 4-deep steps,
-// so results are the same bits for any chunk.  In the 64-thread tile the
-// chunks of all segments run as one sequence in which each chunk's global
-// loads are issued before the products of the previous one (1.14x faster at
-// the K = 12 ab-initio centre despite 124 VGPRs against 52); the 256-thread
-// tile keeps the plain loop, since there the extra registers halved the
-// occupancy and the K = 16 centre product went from 4.9 to 5.7 ms.  TILE = 64
+// so results are the same bits for any chunk.  The chunks of all segments
+// run as one sequence in which each chunk's global loads are issued before
+// the products of the previous one: 1.14x faster than a plain load-then-
+// multiply loop at the K = 12 ab-initio centre in the 64-thread tile, and
+// 1.16-1.23x at K = 16-24 in the 256-thread tile (36 VGPRs, 7 waves per
+// SIMD; an earlier form of that tile had needed enough registers to halve
+// its occupancy and was slower).  TILE = 64
 // (256 threads) for wide particle-number blocks, 32 (64 threads) for narrow
 // ones; every output accumulates the same sequence of 4-deep matrix-core
 // steps for either tile, so both tiles give the same bits.
@@ -488,149 +489,97 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
-    if constexpr (TILE == 32) {
-        // the chunks of all segments in order; the global loads of the next
-        // chunk are issued before the products of the current one
-        constexpr int PER = TILE * kKC / NT;
-        static_assert(PER * NT == TILE * kKC, "a chunk is PER values per thread and operand");
-        int s = tk.s0, kb = 0;
-        TSeg sg{};
-        while (s < tk.s1) {
-            sg = segs[s];
-            if (sg.k0 < sg.k1) {
-                kb = sg.k0;
-                break;
+    // the chunks of all segments in order; the global loads of the next
+    // chunk are issued before the products of the current one
+    constexpr int PER = TILE * kKC / NT;
+    static_assert(PER * NT == TILE * kKC, "a chunk is PER values per thread and operand");
+    int s = tk.s0, kb = 0;
+    TSeg sg{};
+    while (s < tk.s1) {
+        sg = segs[s];
+        if (sg.k0 < sg.k1) {
+            kb = sg.k0;
+            break;
+        }
+        ++s;
+    }
+    double ra[PER], rb[PER];
+    int cta = 0, ctb = 0;
+    auto fetch = [&]() {
+        const double cf = coef[sg.cidx];
+        const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
+        const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int idx = threadIdx.x + p * NT;
+            int r, k;
+            if (sg.ta == 0) {
+                r = idx / kKC;
+                k = idx % kKC;
+            } else {
+                k = idx / TILE;
+                r = idx % TILE;
             }
+            const int gr = tk.r0 + r, gk = kb + k;
+            double v = 0.0;
+            if (gr < tk.M && gk < sg.k1)
+                v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
+            ra[p] = cf * v;
+        }
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int idx = threadIdx.x + p * NT;
+            int c, k;
+            if (sg.tb == 0) {
+                k = idx / TILE;
+                c = idx % TILE;
+            } else {
+                c = idx / kKC;
+                k = idx % kKC;
+            }
+            const int gc = tk.c0 + c, gk = kb + k;
+            double v = 0.0;
+            if (gc < tk.N && gk < sg.k1)
+                v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
+            rb[p] = v;
+        }
+        cta = sg.ta;
+        ctb = sg.tb;
+    };
+    if (s < tk.s1) fetch();
+    while (s < tk.s1) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int idx = threadIdx.x + p * NT;
+            if (cta == 0) As[idx % kKC][idx / kKC] = ra[p];
+            else As[idx / TILE][idx % TILE] = ra[p];
+            if (ctb == 0) Bs[idx / TILE][idx % TILE] = rb[p];
+            else Bs[idx % kKC][idx / kKC] = rb[p];
+        }
+        __syncthreads();
+        kb += kKC;
+        if (kb >= sg.k1) {
             ++s;
-        }
-        double ra[PER], rb[PER];
-        int cta = 0, ctb = 0;
-        auto fetch = [&]() {
-            const double cf = coef[sg.cidx];
-            const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
-            const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
-    #pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                const int idx = threadIdx.x + p * NT;
-                int r, k;
-                if (sg.ta == 0) {
-                    r = idx / kKC;
-                    k = idx % kKC;
-                } else {
-                    k = idx / TILE;
-                    r = idx % TILE;
+            while (s < tk.s1) {
+                sg = segs[s];
+                if (sg.k0 < sg.k1) {
+                    kb = sg.k0;
+                    break;
                 }
-                const int gr = tk.r0 + r, gk = kb + k;
-                double v = 0.0;
-                if (gr < tk.M && gk < sg.k1)
-                    v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
-                ra[p] = cf * v;
-            }
-    #pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                const int idx = threadIdx.x + p * NT;
-                int c, k;
-                if (sg.tb == 0) {
-                    k = idx / TILE;
-                    c = idx % TILE;
-                } else {
-                    c = idx / kKC;
-                    k = idx % kKC;
-                }
-                const int gc = tk.c0 + c, gk = kb + k;
-                double v = 0.0;
-                if (gc < tk.N && gk < sg.k1)
-                    v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
-                rb[p] = v;
-            }
-            cta = sg.ta;
-            ctb = sg.tb;
-        };
-        if (s < tk.s1) fetch();
-        while (s < tk.s1) {
-    #pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                const int idx = threadIdx.x + p * NT;
-                if (cta == 0) As[idx % kKC][idx / kKC] = ra[p];
-                else As[idx / TILE][idx % TILE] = ra[p];
-                if (ctb == 0) Bs[idx / TILE][idx % TILE] = rb[p];
-                else Bs[idx % kKC][idx / kKC] = rb[p];
-            }
-            __syncthreads();
-            kb += kKC;
-            if (kb >= sg.k1) {
                 ++s;
-                while (s < tk.s1) {
-                    sg = segs[s];
-                    if (sg.k0 < sg.k1) {
-                        kb = sg.k0;
-                        break;
-                    }
-                    ++s;
-                }
-            }
-            if (s < tk.s1) fetch();
-    #pragma unroll
-            for (int ks = 0; ks < kKC; ks += 4) {
-                const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
-                const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
-                if (live[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-                if (live[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-                if (live[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-                if (live[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-            }
-            __syncthreads();
-        }
-    } else {  // 256 threads: the prefetch registers would halve the occupancy
-        for (int s = tk.s0; s < tk.s1; ++s) {
-            const TSeg sg = segs[s];
-            const double cf = coef[sg.cidx];
-            const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
-            const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
-            for (int kb = sg.k0; kb < sg.k1; kb += kKC) {
-                for (int idx = threadIdx.x; idx < TILE * kKC; idx += NT) {
-                    int r, k;
-                    if (sg.ta == 0) {
-                        r = idx / kKC;
-                        k = idx % kKC;
-                    } else {
-                        k = idx / TILE;
-                        r = idx % TILE;
-                    }
-                    const int gr = tk.r0 + r, gk = kb + k;
-                    double v = 0.0;
-                    if (gr < tk.M && gk < sg.k1)
-                        v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
-                    As[k][r] = cf * v;
-                }
-                for (int idx = threadIdx.x; idx < TILE * kKC; idx += NT) {
-                    int c, k;
-                    if (sg.tb == 0) {
-                        k = idx / TILE;
-                        c = idx % TILE;
-                    } else {
-                        c = idx / kKC;
-                        k = idx % kKC;
-                    }
-                    const int gc = tk.c0 + c, gk = kb + k;
-                    double v = 0.0;
-                    if (gc < tk.N && gk < sg.k1)
-                        v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
-                    Bs[k][c] = v;
-                }
-                __syncthreads();
-    #pragma unroll
-                for (int ks = 0; ks < kKC; ks += 4) {
-                    const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
-                    const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
-                    if (live[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-                    if (live[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-                    if (live[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-                    if (live[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-                }
-                __syncthreads();
             }
         }
+        if (s < tk.s1) fetch();
+#pragma unroll
+        for (int ks = 0; ks < kKC; ks += 4) {
+            const double a0 = As[ks + lk][wr + li], a1 = As[ks + lk][wr + 16 + li];
+            const double b0 = Bs[ks + lk][wc + li], b1 = Bs[ks + lk][wc + 16 + li];
+            if (live[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            if (live[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            if (live[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            if (live[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
     }
     double* C = bufs.p[tk.c_buf] + tk.c_off;
 #pragma unroll
@@ -668,8 +617,9 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm(const TTask* 
 // work-group at 5 KB of LDS and 48 VGPRs, so a CU holds as many as it has
 // wave slots (the 32-deep v_mfma_f32_16x16x32_bf16 with chunks of 32 needed
 // 10 KB and 97 VGPRs and was 1.5x slower at the K = 12 ab-initio centre).
-// The 64-thread tile pipelines its chunk loads as k_tgemm does (1.4x faster
-// there).  Tiles, wavefront layout and output addressing as in k_tgemm;
+// The chunk loads are pipelined as in k_tgemm (1.4x faster in the 64-thread
+// tile, 1.2-1.25x in the 256-thread tile at K = 16-24).  Tiles, wavefront
+// layout and output addressing as in k_tgemm;
 // values must lie in the FP32 range.
 constexpr int kKC3 = 16;
 constexpr int kKC3Pad = kKC3 + 4;  // bf16 per LDS row (8-byte aligned rows)
@@ -712,165 +662,105 @@ __global__ __launch_bounds__((TILE / 4) * (TILE / 4)) void k_tgemm_bf3(const TTa
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
-    if constexpr (TILE == 32) {
-        // as in k_tgemm: the chunks of all segments in order, each chunk's
-        // global loads issued before the products of the previous one
-        constexpr int PER = TILE * kKC3 / NT;
-        static_assert(PER * NT == TILE * kKC3, "a chunk is PER values per thread and operand");
-        int s = tk.s0, kb = 0;
-        TSeg sg{};
-        while (s < tk.s1) {
-            sg = segs[s];
-            if (sg.k0 < sg.k1) {
-                kb = sg.k0;
-                break;
+    // as in k_tgemm: the chunks of all segments in order, each chunk's
+    // global loads issued before the products of the previous one
+    constexpr int PER = TILE * kKC3 / NT;
+    static_assert(PER * NT == TILE * kKC3, "a chunk is PER values per thread and operand");
+    int s = tk.s0, kb = 0;
+    TSeg sg{};
+    while (s < tk.s1) {
+        sg = segs[s];
+        if (sg.k0 < sg.k1) {
+            kb = sg.k0;
+            break;
+        }
+        ++s;
+    }
+    double ra[PER], rb[PER];
+    int cta = 0, ctb = 0;
+    auto fetch = [&]() {
+        const double cf = coef[sg.cidx];
+        const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
+        const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int idx = threadIdx.x + p * NT;
+            int r, k;
+            if (sg.ta == 0) {
+                r = idx / kKC3;
+                k = idx % kKC3;
+            } else {
+                k = idx / TILE;
+                r = idx % TILE;
             }
+            const int gr = tk.r0 + r, gk = kb + k;
+            double v = 0.0;
+            if (gr < tk.M && gk < sg.k1)
+                v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
+            ra[p] = cf * v;
+        }
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int idx = threadIdx.x + p * NT;
+            int c, k;
+            if (sg.tb == 0) {
+                k = idx / TILE;
+                c = idx % TILE;
+            } else {
+                c = idx / kKC3;
+                k = idx % kKC3;
+            }
+            const int gc = tk.c0 + c, gk = kb + k;
+            double v = 0.0;
+            if (gc < tk.N && gk < sg.k1)
+                v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
+            rb[p] = v;
+        }
+        cta = sg.ta;
+        ctb = sg.tb;
+    };
+    if (s < tk.s1) fetch();
+    while (s < tk.s1) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int idx = threadIdx.x + p * NT;
+            const int ar = cta == 0 ? idx / kKC3 : idx % TILE, ak = cta == 0 ? idx % kKC3 : idx / TILE;
+            const int bc = ctb == 0 ? idx % TILE : idx / kKC3, bk = ctb == 0 ? idx / TILE : idx % kKC3;
+            split_bf16(ra[p], Ah[ar][ak], Al[ar][ak]);
+            split_bf16(rb[p], Bh[bc][bk], Bl[bc][bk]);
+        }
+        __syncthreads();
+        kb += kKC3;
+        if (kb >= sg.k1) {
             ++s;
-        }
-        double ra[PER], rb[PER];
-        int cta = 0, ctb = 0;
-        auto fetch = [&]() {
-            const double cf = coef[sg.cidx];
-            const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
-            const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
-#pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                const int idx = threadIdx.x + p * NT;
-                int r, k;
-                if (sg.ta == 0) {
-                    r = idx / kKC3;
-                    k = idx % kKC3;
-                } else {
-                    k = idx / TILE;
-                    r = idx % TILE;
+            while (s < tk.s1) {
+                sg = segs[s];
+                if (sg.k0 < sg.k1) {
+                    kb = sg.k0;
+                    break;
                 }
-                const int gr = tk.r0 + r, gk = kb + k;
-                double v = 0.0;
-                if (gr < tk.M && gk < sg.k1)
-                    v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
-                ra[p] = cf * v;
-            }
-#pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                const int idx = threadIdx.x + p * NT;
-                int c, k;
-                if (sg.tb == 0) {
-                    k = idx / TILE;
-                    c = idx % TILE;
-                } else {
-                    c = idx / kKC3;
-                    k = idx % kKC3;
-                }
-                const int gc = tk.c0 + c, gk = kb + k;
-                double v = 0.0;
-                if (gc < tk.N && gk < sg.k1)
-                    v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
-                rb[p] = v;
-            }
-            cta = sg.ta;
-            ctb = sg.tb;
-        };
-        if (s < tk.s1) fetch();
-        while (s < tk.s1) {
-#pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                const int idx = threadIdx.x + p * NT;
-                const int ar = cta == 0 ? idx / kKC3 : idx % TILE, ak = cta == 0 ? idx % kKC3 : idx / TILE;
-                const int bc = ctb == 0 ? idx % TILE : idx / kKC3, bk = ctb == 0 ? idx / TILE : idx % kKC3;
-                split_bf16(ra[p], Ah[ar][ak], Al[ar][ak]);
-                split_bf16(rb[p], Bh[bc][bk], Bl[bc][bk]);
-            }
-            __syncthreads();
-            kb += kKC3;
-            if (kb >= sg.k1) {
                 ++s;
-                while (s < tk.s1) {
-                    sg = segs[s];
-                    if (sg.k0 < sg.k1) {
-                        kb = sg.k0;
-                        break;
-                    }
-                    ++s;
-                }
-            }
-            if (s < tk.s1) fetch();
-            s4_t ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                ah[i] = *reinterpret_cast<const s4_t*>(&Ah[wr + 16 * i + li][4 * lk]);
-                al[i] = *reinterpret_cast<const s4_t*>(&Al[wr + 16 * i + li][4 * lk]);
-                bh[i] = *reinterpret_cast<const s4_t*>(&Bh[wc + 16 * i + li][4 * lk]);
-                bl[i] = *reinterpret_cast<const s4_t*>(&Bl[wc + 16 * i + li][4 * lk]);
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    if (!live[i][j]) continue;
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                }
-            __syncthreads();
-        }
-    } else {
-        for (int s = tk.s0; s < tk.s1; ++s) {
-            const TSeg sg = segs[s];
-            const double cf = coef[sg.cidx];
-            const double* __restrict__ A = bufs.p[sg.a_buf] + sg.a_off;
-            const double* __restrict__ B = bufs.p[sg.b_buf] + sg.b_off;
-            for (int kb = sg.k0; kb < sg.k1; kb += kKC3) {
-                for (int idx = threadIdx.x; idx < TILE * kKC3; idx += NT) {
-                    int r, k;
-                    if (sg.ta == 0) {
-                        r = idx / kKC3;
-                        k = idx % kKC3;
-                    } else {
-                        k = idx / TILE;
-                        r = idx % TILE;
-                    }
-                    const int gr = tk.r0 + r, gk = kb + k;
-                    double v = 0.0;
-                    if (gr < tk.M && gk < sg.k1)
-                        v = (sg.ta == 0) ? A[(long long)gr * sg.lda + gk] : A[(long long)gk * sg.lda + gr];
-                    split_bf16(cf * v, Ah[r][k], Al[r][k]);
-                }
-                for (int idx = threadIdx.x; idx < TILE * kKC3; idx += NT) {
-                    int c, k;
-                    if (sg.tb == 0) {
-                        k = idx / TILE;
-                        c = idx % TILE;
-                    } else {
-                        c = idx / kKC3;
-                        k = idx % kKC3;
-                    }
-                    const int gc = tk.c0 + c, gk = kb + k;
-                    double v = 0.0;
-                    if (gc < tk.N && gk < sg.k1)
-                        v = (sg.tb == 0) ? B[(long long)gk * sg.ldb + gc] : B[(long long)gc * sg.ldb + gk];
-                    split_bf16(v, Bh[c][k], Bl[c][k]);
-                }
-                __syncthreads();
-                s4_t ah[2], al[2], bh[2], bl[2];
-    #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    ah[i] = *reinterpret_cast<const s4_t*>(&Ah[wr + 16 * i + li][4 * lk]);
-                    al[i] = *reinterpret_cast<const s4_t*>(&Al[wr + 16 * i + li][4 * lk]);
-                    bh[i] = *reinterpret_cast<const s4_t*>(&Bh[wc + 16 * i + li][4 * lk]);
-                    bl[i] = *reinterpret_cast<const s4_t*>(&Bl[wc + 16 * i + li][4 * lk]);
-                }
-    #pragma unroll
-                for (int i = 0; i < 2; ++i)
-    #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        if (!live[i][j]) continue;
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                    }
-                __syncthreads();
             }
         }
+        if (s < tk.s1) fetch();
+        s4_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            ah[i] = *reinterpret_cast<const s4_t*>(&Ah[wr + 16 * i + li][4 * lk]);
+            al[i] = *reinterpret_cast<const s4_t*>(&Al[wr + 16 * i + li][4 * lk]);
+            bh[i] = *reinterpret_cast<const s4_t*>(&Bh[wc + 16 * i + li][4 * lk]);
+            bl[i] = *reinterpret_cast<const s4_t*>(&Bl[wc + 16 * i + li][4 * lk]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (!live[i][j]) continue;
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        __syncthreads();
     }
     double* C = bufs.p[tk.c_buf] + tk.c_off;
 #pragma unroll
