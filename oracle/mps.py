@@ -55,6 +55,15 @@ class OracleMPS:
             self.A.append(np.zeros(m.shape))
         self.set_packed(packed)
 
+    def nblock_labels(self, k):
+        """N-block of every allowed element of site k, in the order of the
+        site's non-zero dense entries: elements share a label when they
+        share the particle numbers of both bonds (left N and local n fix
+        the right N), whatever their M."""
+        m = self.mask[k - 1]
+        s, a, _ = np.unravel_index(np.flatnonzero(m.ravel()), m.shape)
+        return self.qn[k - 1][a, 0] * 3 + SIGMA_QN[s, 0]
+
     # --- packed <-> dense, canonical block order ---------------------------
     def _ranges(self, k):
         out, off = [], 0
@@ -495,7 +504,7 @@ class OrthogonalityConstraint:
 
 
 def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
-          keep=8, record=None, constraints=(), model=None, pairs=None):
+          keep=8, record=None, constraints=(), model=None, pairs=None, nblock=False):
     """One-site sweeps (Sec. 2.3): right-moving k = 1..L-1 then left-moving
     k = L..2.  Each step solves the local problem, restores the canonical
     form with a positive-diagonal QR (right-moving) or LQ (left-moving) and
@@ -503,7 +512,8 @@ def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
     ``constraints`` (OrthogonalityConstraint objects built on this state)
     every local solve is restricted to the complement of the B[k] vectors
     of Eq. [orthoB] (excited states).  ``model`` (weights of the learned
-    preconditioner, see oracle.precond) replaces the diagonal correction;
+    preconditioner, see oracle.precond; per N-block with ``nblock``)
+    replaces the diagonal correction;
     ``pairs`` (a list) collects the solver's training pairs as (site,) +
     the tuples of :func:`davidson` (vectors in the order of the site's
     non-zero dense entries).
@@ -533,8 +543,10 @@ def sweep(state: SPMPSOracle, n_sweeps: int, tol=1e-9, max_iter=64, max_sub=32,
             if model is not None:
                 from . import precond as pre
 
-                def pc(r, th, dhv=dhv, dnv=dnv):
-                    return pre.correction(model, r, dhv, dnv, th)
+                grp = mps.nblock_labels(k) if nblock else None
+
+                def pc(r, th, dhv=dhv, dnv=dnv, grp=grp):
+                    return pre.correction(model, r, dhv, dnv, th, groups=grp)
             rec_k = [] if pairs is not None else None
             res = davidson(mv, dhv, dnv, x0, tol=tol, max_iter=max_iter, max_sub=max_sub, keep=keep, C=C,
                            precond=pc, record=rec_k)

@@ -24,6 +24,14 @@ and final vector x*, the exact correction is e_j = x*/(x_j . x*) - x_j, the
 step after which the search space holds x*; sign(r_i) e_ij / rms(e_j) is
 the target of g at element i.  Loss: mean squared error; optimiser: Adam
 (Kingma and Ba, 2015).
+
+Per-N-block scope (``groups`` given: one label per element, elements of one
+label forming one N-block of the site tensor, i.e. sharing the particle
+numbers of both bonds): the model sees the residual restricted to one
+block.  The root mean squares in f0 and f4 are taken over the element's
+block, the correction is sign(r_i) g(f) rms_b(t) (the model shapes the
+correction inside a block, the diagonal rule keeps the weight of the
+block), and the target divides e by its rms over the element's block.
 Everything here is FP64 and element-by-element plain numpy.
 """
 from __future__ import annotations
@@ -31,28 +39,54 @@ from __future__ import annotations
 import numpy as np
 
 
-def features(r, dh, dn, theta, floor=1e-8):
-    """Five features per element (n x 5)."""
-    r = np.asarray(r, dtype=float)
-    n = r.size
-    rms = np.sqrt(np.sum(r * r) / n)
-    f0 = np.abs(r) / rms if rms > 0 else np.zeros(n)
+def rms_over(v, groups=None):
+    """Root mean square of v over the whole vector (groups None) or, element
+    by element, over the element's group."""
+    v = np.asarray(v, dtype=float)
+    if groups is None:
+        return np.full(v.size, np.sqrt(np.sum(v * v) / v.size))
+    groups = np.asarray(groups)
+    out = np.empty(v.size)
+    for g in np.unique(groups):
+        sel = groups == g
+        out[sel] = np.sqrt(np.sum(v[sel] ** 2) / np.count_nonzero(sel))
+    return out
+
+
+def _safe_div(a, b):
+    return np.where(b > 0, a / np.where(b > 0, b, 1.0), 0.0)
+
+
+def diagonal_correction(r, dh, dn, theta, floor=1e-8):
+    """t = -r / d' with d = dh - theta dn floored to |d'| >= floor."""
     d = dh - theta * dn
     dfl = np.where(np.abs(d) < floor, np.where(d < 0, -floor, floor), d)
-    t = -r / dfl
-    rmst = np.sqrt(np.sum(t * t) / n)
-    f4 = np.sign(r) * t / rmst if rmst > 0 else np.zeros(n)
+    return -np.asarray(r, dtype=float) / dfl, d, dfl
+
+
+def features(r, dh, dn, theta, floor=1e-8, groups=None):
+    """Five features per element (n x 5); rms over the vector, or over the
+    element's N-block when ``groups`` is given."""
+    r = np.asarray(r, dtype=float)
+    t, d, dfl = diagonal_correction(r, dh, dn, theta, floor)
+    f0 = _safe_div(np.abs(r), rms_over(r, groups))
+    f4 = _safe_div(np.sign(r) * t, rms_over(t, groups))
     return np.stack([f0, np.arcsinh(d), np.arcsinh(dn), np.arcsinh(-f0 / dfl), f4], axis=1)
 
 
-def correction(p, r, dh, dn, theta, floor=1e-8):
-    """The learned correction t = sign(r) g(f(r))."""
-    return np.sign(r) * forward(p, features(r, dh, dn, theta, floor))
+def correction(p, r, dh, dn, theta, floor=1e-8, groups=None):
+    """The learned correction t = sign(r) g(f(r)); per N-block it is scaled
+    by the block rms of the diagonal correction."""
+    y = np.sign(r) * forward(p, features(r, dh, dn, theta, floor, groups))
+    if groups is not None:
+        y = y * rms_over(diagonal_correction(r, dh, dn, theta, floor)[0], groups)
+    return y
 
 
-def target(r, x, xstar):
-    """Training target of g at every element: sign(r_i) e_i / rms(e)."""
-    return np.sign(r) * exact_correction(x, xstar)
+def target(r, x, xstar, groups=None):
+    """Training target of g at every element: sign(r_i) e_i / rms(e), the
+    rms over the vector or over the element's N-block."""
+    return np.sign(r) * exact_correction(x, xstar, groups)
 
 
 def forward(p, F):
@@ -105,8 +139,8 @@ def adam_step(p, g, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return out
 
 
-def exact_correction(x, xstar):
-    """e = x*/(x . x*) - x for unit x, divided by its rms (zero if e = 0)."""
+def exact_correction(x, xstar, groups=None):
+    """e = x*/(x . x*) - x for unit x, divided by its rms over the vector or
+    over each element's N-block (zero where that rms is zero)."""
     e = xstar / float(x @ xstar) - x
-    rms = np.sqrt(np.sum(e * e) / e.size)
-    return e / rms if rms > 0 else e
+    return _safe_div(e, rms_over(e, groups))
