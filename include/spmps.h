@@ -301,10 +301,25 @@ int sp_orthogonality_overlaps(sp_handle* h, double* out);
  * eps 1e-8) on the mean squared error.  A model belongs to the device that
  * was current at sp_mlp_create; it must outlive every state that uses it. */
 
+#define SP_MLP_VECTOR 0  /* root mean squares over the whole site vector   */
+#define SP_MLP_NBLOCK 1  /* per N-block: see sp_mlp_set_scope            */
+
 /* w_init: mlp_size(H) = 7H + 1 floats, packed W1 (H x 5 row-major) | b1 (H)
  * | w2 (H) | b2 (host, copied); capacity: rows (elements) of training
  * pairs the model can record (0: none). */
 int sp_mlp_create(int hidden, const float* w_init, long long capacity, sp_mlp** out);
+/* Scope of the model (default SP_MLP_VECTOR).  SP_MLP_NBLOCK: the model
+ * sees the residual restricted to one N-block of the site tensor (the
+ * elements that share the particle numbers of both bonds, whatever their
+ * M; Sec. 2.3 solves in these blocks after the subduction to N-only
+ * symmetry): rms(r) and rms(t) in f0 and f4 are taken over the element's
+ * block, the correction is sign(r_i) g(f) rms_block(t), so the model shapes
+ * the correction inside each block while the diagonal rule keeps the
+ * weight of the block, and the targets divide e by its rms over the
+ * element's block.  Set it before the model records or is used: a model
+ * holding training pairs of the other scope is refused (SP_EINVAL), as are
+ * a model in use and a recording one of different scopes (sp_set_precond). */
+int sp_mlp_set_scope(sp_mlp* m, int scope);
 int sp_mlp_destroy(sp_mlp* m);
 /* Current weights (host, 7H + 1 floats; may be NULL) and recorded rows. */
 int sp_mlp_get(sp_mlp* m, float* w_out, long long* rows);

@@ -32,8 +32,8 @@ EXPORTS = ["sp_init_mps", "sp_env_update", "sp_heff_apply", "sp_heff_diag", "sp_
            "sp_mpo_identity", "sp_small_eigh", "sp_small_gen_lowest", "sp_sweep_batch", "sp_autotune",
            "sp_mpo_site_op", "sp_mpo_epq", "sp_mpo_spin_corr", "sp_expect",
            "sp_mpo_abinitio", "sp_set_heff_plan", "sp_heff_plan", "sp_add_orthogonality",
-           "sp_clear_orthogonality", "sp_orthogonality_overlaps", "sp_mlp_create", "sp_mlp_destroy",
-           "sp_mlp_get", "sp_mlp_dataset", "sp_mlp_forward", "sp_mlp_train_step", "sp_mlp_train",
+           "sp_clear_orthogonality", "sp_orthogonality_overlaps", "sp_mlp_create", "sp_mlp_set_scope",
+           "sp_mlp_destroy", "sp_mlp_get", "sp_mlp_dataset", "sp_mlp_forward", "sp_mlp_train_step", "sp_mlp_train",
            "sp_set_precond", "sp_heff_batch_profile", "sp_heff_apply_noalloc",
            "sp_mpo_abinitio_component", "sp_mpo_hubbard_component", "sp_small_gen_lowest_gpu"]
 
@@ -110,6 +110,7 @@ def lib():
         "sp_clear_orthogonality": [vp],
         "sp_orthogonality_overlaps": [vp, dp],
         "sp_mlp_create": [ctypes.c_int, fp, ctypes.c_longlong, P(vp)],
+        "sp_mlp_set_scope": [vp, ctypes.c_int],
         "sp_mlp_destroy": [vp],
         "sp_mlp_get": [vp, fp, P(ctypes.c_longlong)],
         "sp_mlp_dataset": [vp, ctypes.c_longlong, ctypes.c_longlong, fp, fp],
@@ -333,7 +334,8 @@ def unpack_mlp(w, H):
 class MLP:
     """A learned Davidson preconditioner (sp_mlp) on the current device."""
 
-    def __init__(self, params, capacity=0):
+    def __init__(self, params, capacity=0, scope="vector"):
+        """scope: "vector" (SP_MLP_VECTOR) or "nblock" (SP_MLP_NBLOCK)."""
         import torch
         self._torch = torch
         self.hidden = int(np.asarray(params["W1"]).shape[0])
@@ -341,6 +343,13 @@ class MLP:
         h = ctypes.c_void_p()
         _check(lib().sp_mlp_create(self.hidden, _fptr(w), int(capacity), ctypes.byref(h)))
         self._h = h
+        self.scope = scope
+        if scope != "vector":
+            self.set_scope(scope)
+
+    def set_scope(self, scope):
+        _check(lib().sp_mlp_set_scope(self._h, {"vector": 0, "nblock": 1}[scope]))
+        self.scope = scope
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -13,6 +13,11 @@
 // solver's own exact corrections e_j = x*/(x_j . x*) - x_j (x_j the unit Ritz
 // vector of iteration j, x* the converged one) divided by rms(e_j), times
 // sign(r_i).
+// Per-N-block scope: the root mean squares in f0 and f4 and in the targets
+// are taken over the element's N-block of the site tensor (elements sharing
+// both bond particle numbers), and the correction is scaled by the block's
+// rms of the diagonal correction, so the model shapes the correction inside
+// a block and the diagonal rule keeps the block's weight.
 // Weights and recorded pairs are FP32 in memory; all arithmetic is FP64.
 // Packed weights: W1 (H x 5, row-major) | b1 (H) | w2 (H) | b2.
 
@@ -82,13 +87,23 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_apply(const float* __restri
                                                            const double* __restrict__ theta,
                                                            const double* __restrict__ rr,
                                                            const double* __restrict__ tt, int n, double floor_,
-                                                           float* __restrict__ feat, float* __restrict__ sgn) {
+                                                           float* __restrict__ feat, float* __restrict__ sgn,
+                                                           const int* __restrict__ gid,
+                                                           const double* __restrict__ grms) {
     extern __shared__ double sw[];
     if (w) load_weights(w, H, sw);
     const int i = blockIdx.x * kMlpThreads + threadIdx.x;
     if (i >= n) return;
     const double th = *theta;
-    const double rms = sqrt(*rr / n), rmst = sqrt(*tt / n);
+    double rms, rmst;
+    if (gid) {
+        const int q = gid[i];
+        rms = grms[2 * q];
+        rmst = grms[2 * q + 1];
+    } else {
+        rms = sqrt(*rr / n);
+        rmst = sqrt(*tt / n);
+    }
     const double d = dh[i] - th * dn[i];
     const double dfl = fabs(d) < floor_ ? (d < 0.0 ? -floor_ : floor_) : d;
     const double r = -t[i] * dfl;
@@ -100,7 +115,38 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_apply(const float* __restri
         for (int c = 0; c < kMlpIn; ++c) feat[(long long)i * kMlpIn + c] = float(f[c]);
         sgn[i] = float(sr);
     }
-    if (w) t[i] = sr * mlp_eval(sw, H, f);
+    if (w) t[i] = sr * mlp_eval(sw, H, f) * (gid ? rmst : 1.0);
+}
+
+// one work-group per group of element ranges: rms of r = -t d' and of t
+__global__ __launch_bounds__(kMlpThreads) void k_mlp_group_rms(const double* __restrict__ t,
+                                                               const double* __restrict__ dh,
+                                                               const double* __restrict__ dn,
+                                                               const double* __restrict__ theta, double floor_,
+                                                               ElemGroups g, double* __restrict__ grms) {
+    __shared__ double red[kMlpThreads / 64];
+    const int q = blockIdx.x;
+    const double th = *theta;
+    double rr = 0.0, tt = 0.0;
+    long long cnt = 0;
+    for (int j = g.gptr[q]; j < g.gptr[q + 1]; ++j) {
+        const long long o = g.roff[j];
+        cnt += g.rlen[j];
+        for (int e = threadIdx.x; e < g.rlen[j]; e += kMlpThreads) {
+            const long long i = o + e;
+            const double d = dh[i] - th * dn[i];
+            const double dfl = fabs(d) < floor_ ? (d < 0.0 ? -floor_ : floor_) : d;
+            const double r = -t[i] * dfl;
+            rr = fma(r, r, rr);
+            tt = fma(t[i], t[i], tt);
+        }
+    }
+    rr = group_sum(rr, red);
+    tt = group_sum(tt, red);
+    if (threadIdx.x == 0) {
+        grms[2 * q] = cnt > 0 ? sqrt(rr / double(cnt)) : 0.0;
+        grms[2 * q + 1] = cnt > 0 ? sqrt(tt / double(cnt)) : 0.0;
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_sumsq(const double* __restrict__ v, int n, double* __restrict__ out) {
@@ -149,6 +195,60 @@ __global__ __launch_bounds__(1024) void k_mlp_targets(const double* __restrict__
     const double rms = sqrt(ee / n);
     const double inv = rms > 0.0 ? 1.0 / rms : 0.0;
     for (int i = threadIdx.x; i < n; i += 1024) out[i] = float(double(out[i]) * (xs[i] / c - x[i] / nx) * inv);
+}
+
+// grouped targets, first pass: one work-group per recorded iteration j,
+// scal[2j] = |x_j|, scal[2j+1] = xh . x*
+__global__ __launch_bounds__(1024) void k_mlp_target_dots(const double* __restrict__ X, long long ldx,
+                                                          const double* __restrict__ xs, int n,
+                                                          double* __restrict__ scal) {
+    __shared__ double red[16];
+    const double* x = X + (long long)blockIdx.x * ldx;
+    double xx = 0.0, xy = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        xx = fma(x[i], x[i], xx);
+        xy = fma(x[i], xs[i], xy);
+    }
+    xx = group_sum(xx, red);
+    xy = group_sum(xy, red);
+    if (threadIdx.x == 0) {
+        const double nx = sqrt(xx);
+        scal[2 * blockIdx.x] = nx;
+        scal[2 * blockIdx.x + 1] = xy / nx;
+    }
+}
+
+// grouped targets, second pass: work-group (group q, iteration j) divides
+// e_j on the group's ranges by its rms there; Y holds sign(r) on entry
+__global__ __launch_bounds__(kMlpThreads) void k_mlp_targets_grouped(const double* __restrict__ X, long long ldx,
+                                                                     const double* __restrict__ xs, int n,
+                                                                     ElemGroups g, const double* __restrict__ scal,
+                                                                     float* __restrict__ Y) {
+    __shared__ double red[kMlpThreads / 64];
+    const int q = blockIdx.x, j = blockIdx.y;
+    const double* x = X + (long long)j * ldx;
+    float* out = Y + (long long)j * n;
+    const double nx = scal[2 * j], c = scal[2 * j + 1];
+    double ee = 0.0;
+    long long cnt = 0;
+    for (int k = g.gptr[q]; k < g.gptr[q + 1]; ++k) {
+        const long long o = g.roff[k];
+        cnt += g.rlen[k];
+        for (int e = threadIdx.x; e < g.rlen[k]; e += kMlpThreads) {
+            const double v = xs[o + e] / c - x[o + e] / nx;
+            ee = fma(v, v, ee);
+        }
+    }
+    ee = group_sum(ee, red);
+    const double rms = cnt > 0 ? sqrt(ee / double(cnt)) : 0.0;
+    const double inv = rms > 0.0 ? 1.0 / rms : 0.0;
+    for (int k = g.gptr[q]; k < g.gptr[q + 1]; ++k) {
+        const long long o = g.roff[k];
+        for (int e = threadIdx.x; e < g.rlen[k]; e += kMlpThreads) {
+            const long long i = o + e;
+            out[i] = float(double(out[i]) * (xs[i] / c - x[i] / nx) * inv);
+        }
+    }
 }
 
 // gradient partials of 0.5 * sum (y - Y)^2 over rows row0 + q*stride,
@@ -273,11 +373,17 @@ void sum_partials(hipStream_t s, const double* part, int nchunk, int stride, int
 
 void mlp_apply(hipStream_t s, const float* w, int H, double* t, const double* dh, const double* dn,
                const double* theta, const double* rr, const double* tt, int n, double floor_, float* feat,
-               float* sgn) {
+               float* sgn, const int* gid, const double* grms) {
     if (n <= 0) return;
     const size_t lds = w ? size_t(mlp_size(H)) * sizeof(double) : 0;
     hipLaunchKernelGGL(k_mlp_apply, dim3(blocks_for(n)), dim3(kMlpThreads), lds, s, w, H, t, dh, dn, theta, rr, tt,
-                       n, floor_, feat, sgn);
+                       n, floor_, feat, sgn, gid, grms);
+}
+
+void mlp_group_rms(hipStream_t s, const double* t, const double* dh, const double* dn, const double* theta,
+                   double floor_, ElemGroups g, double* grms) {
+    if (g.ng > 0)
+        hipLaunchKernelGGL(k_mlp_group_rms, dim3(g.ng), dim3(kMlpThreads), 0, s, t, dh, dn, theta, floor_, g, grms);
 }
 
 void sumsq(hipStream_t s, const double* v, int n, double* out) {
@@ -292,6 +398,14 @@ void mlp_forward(hipStream_t s, const float* w, int H, const float* F, long long
 
 void mlp_targets(hipStream_t s, const double* X, long long ldx, int nrec, const double* xstar, int n, float* Y) {
     if (nrec > 0 && n > 0) hipLaunchKernelGGL(k_mlp_targets, dim3(nrec), dim3(1024), 0, s, X, ldx, xstar, n, Y);
+}
+
+void mlp_targets_grouped(hipStream_t s, const double* X, long long ldx, int nrec, const double* xstar, int n,
+                         ElemGroups g, double* scal, float* Y) {
+    if (nrec <= 0 || n <= 0 || g.ng <= 0) return;
+    hipLaunchKernelGGL(k_mlp_target_dots, dim3(nrec), dim3(1024), 0, s, X, ldx, xstar, n, scal);
+    hipLaunchKernelGGL(k_mlp_targets_grouped, dim3(g.ng, nrec), dim3(kMlpThreads), 0, s, X, ldx, xstar, n, g, scal,
+                       Y);
 }
 
 void mlp_grad(hipStream_t s, const float* w, int H, const float* F, const float* Y, long long row0, long long stride,

@@ -146,6 +146,17 @@ struct SiteInfo {
         return it == by_sa_s.end() ? -1 : it->second;
     }
 };
+// N-blocks of one site tensor (elements sharing both bond particle numbers)
+// as groups of contiguous block ranges, and the group of every element; the
+// host vectors stay alive as the sources of the uploads
+struct NBlocks {
+    int ng = 0;
+    std::vector<int> gptr_h, rlen_h, gid_h;
+    std::vector<long long> roff_h;
+    DArr<int> gptr, rlen, gid;
+    DArr<long long> roff;
+    spk::ElemGroups groups() const { return spk::ElemGroups{ng, gptr.p, roff.p, rlen.p}; }
+};
 struct EnvBlk {
     int c, i, j, rows, cols;
     long long off;
@@ -422,7 +433,8 @@ struct sp_handle {
     // current solve for the targets, device scalars
     sp_mlp* mlp_use = nullptr;
     sp_mlp* mlp_rec = nullptr;
-    DArr<double> xrec, mlp_scal;
+    DArr<double> xrec, mlp_scal, mlp_grms, mlp_tscal;
+    std::vector<NBlocks> nblocks;  // per site (index k-1), built on first use
     ~sp_handle() {
         if (pin) (void)hipHostFree(pin);
         if (pin_up) (void)hipHostFree(pin_up);
@@ -449,9 +461,10 @@ struct sp_mlp {
     DArr<double> m, v;   // Adam moments
     int step = 0;
     long long cap = 0, rows = 0;
-    DArr<float> F, Y;    // recorded pairs: cap x 4 features, cap targets
+    DArr<float> F, Y;    // recorded pairs: cap x 5 features, cap targets
     DArr<double> gpart, scal;
     int nparts = 0;
+    int scope = SP_MLP_VECTOR;  // rms over the site vector or per N-block
 };
 
 namespace {
@@ -2001,6 +2014,45 @@ void validate_plans(sp_handle* h) {
 
 double* site_ptr(sp_handle* h, int k) { return h->mps.p + h->sites[k - 1].goff; }
 
+// the N-blocks of site k's tensor: its (left sector, sigma) blocks grouped by
+// the left bond's particle number and that of sigma (hence also the right
+// bond's), whatever their M
+const NBlocks& site_nblocks(sp_handle* h, int k) {
+    if (h->nblocks.size() != size_t(h->L)) h->nblocks.resize(h->L);
+    NBlocks& nb = h->nblocks[k - 1];
+    if (nb.ng > 0) return nb;
+    const SiteInfo& si = h->sites[k - 1];
+    const Bond& bl = h->bonds[k - 1];
+    std::map<std::pair<int, int>, int> key;
+    std::vector<int> grp(si.blk.size());
+    for (size_t b = 0; b < si.blk.size(); ++b) {
+        const XBlk& x = si.blk[b];
+        grp[b] = key.emplace(std::make_pair(bl.sec[x.sa].n, kSigmaN[x.s]), int(key.size())).first->second;
+    }
+    const int ng = int(key.size());
+    nb.gptr_h.assign(ng + 1, 0);
+    for (int g : grp) ++nb.gptr_h[g + 1];
+    for (int g = 0; g < ng; ++g) nb.gptr_h[g + 1] += nb.gptr_h[g];
+    nb.roff_h.assign(si.blk.size(), 0);
+    nb.rlen_h.assign(si.blk.size(), 0);
+    nb.gid_h.assign(size_t(si.size), 0);
+    std::vector<int> fill(nb.gptr_h.begin(), nb.gptr_h.end() - 1);
+    for (size_t b = 0; b < si.blk.size(); ++b) {  // site order inside a group
+        const XBlk& x = si.blk[b];
+        const long long len = (long long)x.rows * x.cols;
+        const int j = fill[grp[b]]++;
+        nb.roff_h[j] = x.off;
+        nb.rlen_h[j] = int(len);
+        std::fill(nb.gid_h.begin() + x.off, nb.gid_h.begin() + x.off + len, grp[b]);
+    }
+    nb.gptr.upload(nb.gptr_h, h->stream);
+    nb.roff.upload(nb.roff_h, h->stream);
+    nb.rlen.upload(nb.rlen_h, h->stream);
+    nb.gid.upload(nb.gid_h, h->stream);
+    nb.ng = ng;
+    return nb;
+}
+
 spk::BufSet bufset(sp_handle* h, int k, const double* x, double* y, double* ny, double* out) {
     spk::BufSet b{};
     b.p[B_ENVL] = h->envL[k - 1].p;
@@ -2478,6 +2530,12 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     const long long rec_base = rec ? rec->rows : 0;
     if (rec && h->xrec.n < size_t(max_iter) * ld) h->xrec.alloc(size_t(max_iter) * ld);
     if ((use || rec) && h->mlp_scal.n < 4) h->mlp_scal.alloc(4);
+    SP_REQUIRE(!use || !rec || use->scope == rec->scope, "the model in use and the recording one differ in scope");
+    const NBlocks* nbk = ((use && use->scope == SP_MLP_NBLOCK) || (rec && rec->scope == SP_MLP_NBLOCK))
+                             ? &site_nblocks(h, k)
+                             : nullptr;
+    if (nbk && h->mlp_grms.n < size_t(2 * nbk->ng)) h->mlp_grms.alloc(2 * nbk->ng);
+    if (nbk && rec && h->mlp_tscal.n < size_t(2 * max_iter)) h->mlp_tscal.alloc(2 * max_iter);
     diag(h, k, h->ddh.p, h->ddn.p);
     spk::normalize(s, site_ptr(h, k), V, n, nullptr);
     if (h->con_active) {  // start in the complement of the constraints
@@ -2536,12 +2594,18 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
         if (!last) {
             const bool record_now = rec && rec_base + (long long)(nrec + 1) * n <= rec->cap;
             if (use_model || record_now) {
-                spk::sum_partials(s, dn_dev + (lay.px - lay.out), nch, 3, 1, h->mlp_scal.p);
-                spk::sumsq(s, h->dt.p, n, h->mlp_scal.p + 1);
+                if (nbk) {
+                    spk::mlp_group_rms(s, h->dt.p, h->ddh.p, h->ddn.p, h->pin_up_dev + lay.a + m, floor_,
+                                       nbk->groups(), h->mlp_grms.p);
+                } else {
+                    spk::sum_partials(s, dn_dev + (lay.px - lay.out), nch, 3, 1, h->mlp_scal.p);
+                    spk::sumsq(s, h->dt.p, n, h->mlp_scal.p + 1);
+                }
                 spk::mlp_apply(s, use_model ? use->w.p : nullptr, use ? use->hidden : 0, h->dt.p, h->ddh.p, h->ddn.p,
                                h->pin_up_dev + lay.a + m, h->mlp_scal.p, h->mlp_scal.p + 1, n, floor_,
                                record_now ? rec->F.p + (rec_base + (long long)nrec * n) * spk::kMlpIn : nullptr,
-                               record_now ? rec->Y.p + rec_base + (long long)nrec * n : nullptr);
+                               record_now ? rec->Y.p + rec_base + (long long)nrec * n : nullptr,
+                               nbk ? nbk->gid.p : nullptr, nbk ? h->mlp_grms.p : nullptr);
                 if (record_now) {
                     HIPCK(hipMemcpyAsync(h->xrec.p + size_t(nrec) * ld, h->dx.p, size_t(n) * sizeof(double),
                                          hipMemcpyDeviceToDevice, s));
@@ -2632,7 +2696,11 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     if (rec && out.converged && nrec > 0) {
         // iterations before the converged one: targets against the final x
         const int keep = nrec - (rec_last_it == out.iters ? 1 : 0);
-        spk::mlp_targets(s, h->xrec.p, ld, keep, site_ptr(h, k), n, rec->Y.p + rec_base);
+        if (nbk)
+            spk::mlp_targets_grouped(s, h->xrec.p, ld, keep, site_ptr(h, k), n, nbk->groups(), h->mlp_tscal.p,
+                                     rec->Y.p + rec_base);
+        else
+            spk::mlp_targets(s, h->xrec.p, ld, keep, site_ptr(h, k), n, rec->Y.p + rec_base);
         rec->rows = rec_base + (long long)keep * n;
     }
     if (reduced(h)) {
@@ -3990,6 +4058,16 @@ int sp_mlp_create(int hidden, const float* w_init, long long capacity, sp_mlp** 
     });
 }
 
+int sp_mlp_set_scope(sp_mlp* m, int scope) {
+    return guarded([&]() -> int {
+        SP_REQUIRE(m, "null argument");
+        SP_REQUIRE(scope == SP_MLP_VECTOR || scope == SP_MLP_NBLOCK, "unknown model scope");
+        SP_REQUIRE(m->rows == 0 || scope == m->scope, "the model holds training pairs of the other scope");
+        m->scope = scope;
+        return SP_OK;
+    });
+}
+
 int sp_mlp_destroy(sp_mlp* m) {
     return guarded([&]() -> int {
         if (m) {
@@ -4084,6 +4162,8 @@ int sp_set_precond(sp_handle* h, sp_mlp* use, sp_mlp* record) {
         for (sp_mlp* m : {use, record})
             if (m) SP_REQUIRE(m->device == h->device, "the model must live on the state's device");
         if (record) SP_REQUIRE(record->cap > 0, "the recording model has no room for training pairs");
+        if (use && record)
+            SP_REQUIRE(use->scope == record->scope, "the model in use and the recording one differ in scope");
         HIPCK(hipStreamSynchronize(h->stream));
         h->mlp_use = use;
         h->mlp_rec = record;

@@ -6,8 +6,8 @@ arithmetic on FP32 weights and features, FP32 result); Adam steps 2e-7
 absolute on the weights (FP32 storage after each step); recorded features
 1e-5 and targets 1e-4 relative (FP32 storage; compared only where the
 residual and the exact correction are not yet at the rounding level of the
-trajectory);
-sweep energies 1e-8 (converged local solves)."""
+trajectory: over the vector for the vector scope, over the N-block for the
+per-N-block scope); sweep energies 1e-8 (converged local solves)."""
 import numpy as np
 import pytest
 
@@ -118,6 +118,76 @@ def test_learned_sweep_matches_the_oracle_with_the_same_weights():
     assert all(s["converged"] for s in steps)
     assert [s["iters"] for s in steps] == [s["iters"] for s in ref]
     assert max(abs(a["theta"] - b["theta"]) for a, b in zip(steps, ref)) < 1e-8
+
+
+def test_nblock_recorded_pairs_match_the_oracle():
+    # per-N-block scope: block root mean squares in the features and the
+    # targets; compared on the blocks whose residual and exact correction
+    # are above the rounding level of the two trajectories
+    wl = W.hubbard_small()
+    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed)
+    rec = sp.MLP(_params(), capacity=2_000_000, scope="nblock")
+    gpu.set_precond(record=rec)
+    gpu.sweep(1, max_sub=32, max_iter=64)
+    pairs = []
+    omps.sweep(orc, 1, max_sub=32, max_iter=64, pairs=pairs)
+    F, Y = rec.dataset()
+    sizes = [len(p[1]) for p in pairs]
+    assert F.shape[0] == sum(sizes), (F.shape, sum(sizes))
+
+    def packed(k, v):
+        m = orc.mps.mask[k - 1]
+        d = np.zeros(m.size)
+        d[np.flatnonzero(m.ravel())] = v
+        return orc.mps.site_packed(k, d.reshape(m.shape))
+    off, checked = 0, 0
+    for (k, r, th, x, xs, dh, dn), n in zip(pairs, sizes):
+        grp = np.rint(packed(k, orc.mps.nblock_labels(k).astype(float))).astype(int)
+        r, x, xs, dh, dn = (packed(k, v) for v in (r, x, xs, dh, dn))
+        e_raw = xs / float(x @ xs) - x
+        ok = (pre.rms_over(r, grp) > 1e-6) & (pre.rms_over(e_raw, grp) > 1e-6)
+        if ok.sum() > n // 2:
+            fr = pre.features(r, dh, dn, th, groups=grp)
+            blk = F[off: off + n].astype(np.float64)
+            assert np.abs(blk[ok] - fr[ok]).max() < 1e-5 * max(1.0, np.abs(fr[ok]).max())
+            yr = pre.target(r, x, xs, groups=grp)
+            assert np.abs(Y[off: off + n][ok] - yr[ok]).max() < 1e-4 * max(1.0, np.abs(yr[ok]).max())
+            checked += 1
+        off += n
+    assert checked >= 10
+
+
+def test_nblock_learned_sweep_matches_the_oracle_with_the_same_weights():
+    wl = W.hubbard_small()
+    tab, gpu, orc = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed)
+    rec = sp.MLP(_params(64, 5), capacity=2_000_000, scope="nblock")
+    gpu.set_precond(record=rec)
+    gpu.sweep(1)
+    rec.train(3, 4096, 3e-3)
+    model = rec.params()
+    _, g2, o2 = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed + 1)
+    g2.set_precond(use=rec)
+    rc, steps = g2.sweep(2, max_sub=128, max_iter=200)
+    ref = omps.sweep(o2, 2, max_sub=128, max_iter=200, model=_as64(model), nblock=True)
+    print("[precond] iterations per step (learned, per N-block):", [s["iters"] for s in steps], flush=True)
+    assert all(s["converged"] for s in steps)
+    assert [s["iters"] for s in steps] == [s["iters"] for s in ref]
+    assert max(abs(a["theta"] - b["theta"]) for a, b in zip(steps, ref)) < 1e-8
+
+
+def test_model_scope_rules():
+    wl = W.hubbard_small()
+    _, g, _ = make_pair(wl.L, wl.N, wl.twoM, wl.D, wl.twoS, wl.G, U=wl.U, seed=wl.seed, oracle=False)
+    vec = sp.MLP(_params(16), capacity=100_000)
+    blk = sp.MLP(_params(16), scope="nblock")
+    with pytest.raises(sp.SpError):
+        g.set_precond(use=blk, record=vec)
+    g.set_precond(record=vec)
+    g.sweep(1)
+    assert vec.rows() > 0
+    with pytest.raises(sp.SpError):
+        vec.set_scope("nblock")
+    vec.set_scope("vector")
 
 
 def test_bad_model_falls_back_and_converges():
