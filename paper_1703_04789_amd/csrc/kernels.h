@@ -312,35 +312,16 @@ __host__ __device__ inline long long mlp_size(int H) { return (long long)H * (kM
 void sum_partials(hipStream_t s, const double* part, int nchunk, int stride, int idx, double* out);
 // features of every element from t = -r / d' (rr = |r|^2, tt = |t|^2,
 // theta device scalars); feat (n x 5 FP32) and sgn (n, sign(r_i)) if feat is not null;
-// t replaced by the model's correction if w is not null.  Per-N-block scope
-// (gid not null): element i belongs to group gid[i], the root mean squares
-// are grms[2 gid[i]] (r) and grms[2 gid[i] + 1] (t) instead of those of rr,
-// tt, and the correction is scaled by the group's rms of t
+// t replaced by the model's correction if w is not null
 void mlp_apply(hipStream_t s, const float* w, int H, double* t, const double* dh, const double* dn,
                const double* theta, const double* rr, const double* tt, int n, double floor_, float* feat,
-               float* sgn, const int* gid, const double* grms);
-// groups of element ranges: group q holds ranges gptr[q] .. gptr[q+1] - 1,
-// range j the elements roff[j] .. roff[j] + rlen[j] - 1
-struct ElemGroups {
-    int ng;
-    const int* gptr;
-    const long long* roff;
-    const int* rlen;
-};
-// grms[2q] = rms of r = -t d' and grms[2q+1] = rms of t over group q (one
-// work-group per group, fixed order)
-void mlp_group_rms(hipStream_t s, const double* t, const double* dh, const double* dn, const double* theta,
-                   double floor_, ElemGroups g, double* grms);
+               float* sgn);
 // *out = v . v (one work-group, fixed order)
 void sumsq(hipStream_t s, const double* v, int n, double* out);
 void mlp_forward(hipStream_t s, const float* w, int H, const float* F, long long n, float* y);
 // targets of nrec recorded iterations (Ritz vectors ldx apart) against the
 // unit vector xstar, n per iteration; Y holds sign(r) on entry
 void mlp_targets(hipStream_t s, const double* X, long long ldx, int nrec, const double* xstar, int n, float* Y);
-// the same with e_j divided by its rms over each element's group; scal:
-// 2 nrec doubles of device scratch
-void mlp_targets_grouped(hipStream_t s, const double* X, long long ldx, int nrec, const double* xstar, int n,
-                         ElemGroups g, double* scal, float* Y);
 // per-work-group gradient partials (mlp_size(H) + 1 doubles each, the last
 // the summed squared error) over rows row0 + q * stride, q < count
 void mlp_grad(hipStream_t s, const float* w, int H, const float* F, const float* Y, long long row0, long long stride,

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "mlp.h"
 
 namespace spk {
 
@@ -373,7 +374,13 @@ void sum_partials(hipStream_t s, const double* part, int nchunk, int stride, int
 
 void mlp_apply(hipStream_t s, const float* w, int H, double* t, const double* dh, const double* dn,
                const double* theta, const double* rr, const double* tt, int n, double floor_, float* feat,
-               float* sgn, const int* gid, const double* grms) {
+               float* sgn) {
+    mlp_apply_grouped(s, w, H, t, dh, dn, theta, rr, tt, n, floor_, feat, sgn, nullptr, nullptr);
+}
+
+void mlp_apply_grouped(hipStream_t s, const float* w, int H, double* t, const double* dh, const double* dn,
+                       const double* theta, const double* rr, const double* tt, int n, double floor_, float* feat,
+                       float* sgn, const int* gid, const double* grms) {
     if (n <= 0) return;
     const size_t lds = w ? size_t(mlp_size(H)) * sizeof(double) : 0;
     hipLaunchKernelGGL(k_mlp_apply, dim3(blocks_for(n)), dim3(kMlpThreads), lds, s, w, H, t, dh, dn, theta, rr, tt,

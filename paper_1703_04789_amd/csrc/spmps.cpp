@@ -43,6 +43,7 @@
 
 #include "host_linalg.h"
 #include "kernels.h"
+#include "mlp.h"
 
 namespace {
 
@@ -2601,11 +2602,12 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
                     spk::sum_partials(s, dn_dev + (lay.px - lay.out), nch, 3, 1, h->mlp_scal.p);
                     spk::sumsq(s, h->dt.p, n, h->mlp_scal.p + 1);
                 }
-                spk::mlp_apply(s, use_model ? use->w.p : nullptr, use ? use->hidden : 0, h->dt.p, h->ddh.p, h->ddn.p,
-                               h->pin_up_dev + lay.a + m, h->mlp_scal.p, h->mlp_scal.p + 1, n, floor_,
-                               record_now ? rec->F.p + (rec_base + (long long)nrec * n) * spk::kMlpIn : nullptr,
-                               record_now ? rec->Y.p + rec_base + (long long)nrec * n : nullptr,
-                               nbk ? nbk->gid.p : nullptr, nbk ? h->mlp_grms.p : nullptr);
+                spk::mlp_apply_grouped(
+                    s, use_model ? use->w.p : nullptr, use ? use->hidden : 0, h->dt.p, h->ddh.p, h->ddn.p,
+                    h->pin_up_dev + lay.a + m, h->mlp_scal.p, h->mlp_scal.p + 1, n, floor_,
+                    record_now ? rec->F.p + (rec_base + (long long)nrec * n) * spk::kMlpIn : nullptr,
+                    record_now ? rec->Y.p + rec_base + (long long)nrec * n : nullptr, nbk ? nbk->gid.p : nullptr,
+                    nbk ? h->mlp_grms.p : nullptr);
                 if (record_now) {
                     HIPCK(hipMemcpyAsync(h->xrec.p + size_t(nrec) * ld, h->dx.p, size_t(n) * sizeof(double),
                                          hipMemcpyDeviceToDevice, s));
