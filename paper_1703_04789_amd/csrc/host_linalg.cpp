@@ -914,4 +914,175 @@ int gen_lowest(int m, const double* H, const double* N, double drop, double* the
     return rk;
 }
 
+// ---------------------------------------------------------------------------
+// GrowingPencil: every entry below is formed by the expression and in the
+// order that cholesky() and the reduction in gen_lowest use for it.
+
+void GrowingPencil::reserve(int m) {
+    if (m <= cap_) return;
+    const int nc = std::max(m, 2 * cap_);
+    for (std::vector<double>* v : {&H_, &N_, &L_, &Ls_, &W_, &B_}) {
+        std::vector<double> t(size_t(nc) * nc, 0.0);
+        for (int i = 0; i < m_; ++i)
+            for (int j = 0; j < m_; ++j) t[size_t(i) * nc + j] = (*v)[size_t(i) * cap_ + j];
+        v->swap(t);
+    }
+    cap_ = nc;
+}
+
+// row i of the Cholesky factor of N - shift I (rows < i present)
+static bool chol_row(std::vector<double>& L, int ld, const double* N, int nld, int i, double shift) {
+    double* li = &L[size_t(i) * ld];
+    for (int j = 0; j < i; ++j) {
+        const double* lj = &L[size_t(j) * ld];
+        double s0 = N[size_t(i) * nld + j], s1 = 0.0;
+        int k = 0;
+        for (; k + 2 <= j; k += 2) {
+            s0 -= li[k] * lj[k];
+            s1 -= li[k + 1] * lj[k + 1];
+        }
+        for (; k < j; ++k) s0 -= li[k] * lj[k];
+        li[j] = (s0 + s1) / lj[j];
+    }
+    double dsum = N[size_t(i) * nld + i] - shift;
+    for (int k = 0; k < i; ++k) dsum -= li[k] * li[k];
+    if (!(dsum > 0.0)) return false;
+    li[i] = std::sqrt(dsum);
+    return true;
+}
+
+int GrowingPencil::build(int m, const double* H, const double* N, double drop) {
+    m_ = 0;
+    double U = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < m; ++j) r += std::fabs(N[size_t(i) * m + j]);
+        U = std::max(U, r);
+    }
+    if (!(U > 1e-12)) return -2;
+    reserve(m);
+    shift_ = 2.0 * drop * U;
+    for (int i = 0; i < m; ++i)
+        if (!chol_row(Ls_, cap_, N, m, i, shift_) || !chol_row(L_, cap_, N, m, i, 0.0)) return -2;
+    const int ld = cap_;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            H_[size_t(i) * ld + j] = H[size_t(i) * m + j];
+            N_[size_t(i) * ld + j] = N[size_t(i) * m + j];
+        }
+    // W = L^-1 H, B = L^-1 W^T (rows by forward substitution)
+    for (int i = 0; i < m; ++i) {
+        double* wi = &W_[size_t(i) * ld];
+        for (int c = 0; c < m; ++c) wi[c] = H[size_t(i) * m + c];
+        for (int k = 0; k < i; ++k) {
+            const double lik = L_[size_t(i) * ld + k];
+            const double* wk = &W_[size_t(k) * ld];
+            for (int c = 0; c < m; ++c) wi[c] -= lik * wk[c];
+        }
+        const double inv = 1.0 / L_[size_t(i) * ld + i];
+        for (int c = 0; c < m; ++c) wi[c] *= inv;
+    }
+    for (int i = 0; i < m; ++i) {
+        double* bi = &B_[size_t(i) * ld];
+        for (int c = 0; c < m; ++c) bi[c] = W_[size_t(c) * ld + i];
+        for (int k = 0; k < i; ++k) {
+            const double lik = L_[size_t(i) * ld + k];
+            const double* bk = &B_[size_t(k) * ld];
+            for (int c = 0; c < m; ++c) bi[c] -= lik * bk[c];
+        }
+        const double inv = 1.0 / L_[size_t(i) * ld + i];
+        for (int c = 0; c < m; ++c) bi[c] *= inv;
+    }
+    m_ = m;
+    return m;
+}
+
+// extend the cached factors of the leading (m-1) x (m-1) pencil to m
+bool GrowingPencil::grow(int m, const double* H, const double* N, double drop) {
+    const int p = m - 1;  // the new row and column
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+            if (H_[size_t(i) * cap_ + j] != H[size_t(i) * m + j] || N_[size_t(i) * cap_ + j] != N[size_t(i) * m + j])
+                return false;
+    double U = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < m; ++j) r += std::fabs(N[size_t(i) * m + j]);
+        U = std::max(U, r);
+    }
+    if (!(drop * U <= shift_)) return false;
+    reserve(m);
+    const int ld = cap_;
+    if (!chol_row(Ls_, ld, N, m, p, shift_) || !chol_row(L_, ld, N, m, p, 0.0)) return false;
+    for (int j = 0; j < m; ++j) {
+        H_[size_t(p) * ld + j] = H[size_t(p) * m + j];
+        H_[size_t(j) * ld + p] = H[size_t(j) * m + p];
+        N_[size_t(p) * ld + j] = N[size_t(p) * m + j];
+        N_[size_t(j) * ld + p] = N[size_t(j) * m + p];
+    }
+    // W: the new column of rows 0..p-1, then the new row
+    for (int i = 0; i < p; ++i) {
+        double w = H[size_t(i) * m + p];
+        for (int k = 0; k < i; ++k) w -= L_[size_t(i) * ld + k] * W_[size_t(k) * ld + p];
+        W_[size_t(i) * ld + p] = w * (1.0 / L_[size_t(i) * ld + i]);
+    }
+    {
+        double* wp = &W_[size_t(p) * ld];
+        for (int c = 0; c < m; ++c) wp[c] = H[size_t(p) * m + c];
+        for (int k = 0; k < p; ++k) {
+            const double lpk = L_[size_t(p) * ld + k];
+            const double* wk = &W_[size_t(k) * ld];
+            for (int c = 0; c < m; ++c) wp[c] -= lpk * wk[c];
+        }
+        const double inv = 1.0 / L_[size_t(p) * ld + p];
+        for (int c = 0; c < m; ++c) wp[c] *= inv;
+    }
+    // B: the new column of rows 0..p-1 (B[i][p] from W[p][i]), then the new row
+    for (int i = 0; i < p; ++i) {
+        double b = W_[size_t(p) * ld + i];
+        for (int k = 0; k < i; ++k) b -= L_[size_t(i) * ld + k] * B_[size_t(k) * ld + p];
+        B_[size_t(i) * ld + p] = b * (1.0 / L_[size_t(i) * ld + i]);
+    }
+    {
+        double* bp = &B_[size_t(p) * ld];
+        for (int c = 0; c < m; ++c) bp[c] = W_[size_t(c) * ld + p];
+        for (int k = 0; k < p; ++k) {
+            const double lpk = L_[size_t(p) * ld + k];
+            const double* bk = &B_[size_t(k) * ld];
+            for (int c = 0; c < m; ++c) bp[c] -= lpk * bk[c];
+        }
+        const double inv = 1.0 / L_[size_t(p) * ld + p];
+        for (int c = 0; c < m; ++c) bp[c] *= inv;
+    }
+    m_ = m;
+    return true;
+}
+
+int GrowingPencil::lowest(int m, const double* H, const double* N, double drop, double* theta, double* a) {
+    if (m <= 0) return -2;
+    const bool grown = (m_ > 0 && m == m_ + 1 && grow(m, H, N, drop));
+    if (!grown && build(m, H, N, drop) != m) {
+        m_ = 0;
+        return -2;
+    }
+    const int ld = cap_;
+    std::vector<double> Bs(size_t(m) * m);
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) Bs[size_t(r) * m + c] = B_[size_t(r) * ld + c];
+    for (int r = 0; r < m; ++r)
+        for (int c = 0; c < r; ++c)
+            Bs[size_t(r) * m + c] = Bs[size_t(c) * m + r] = 0.5 * (Bs[size_t(r) * m + c] + Bs[size_t(c) * m + r]);
+    std::vector<double> c0(m);
+    if (sym_eig_lowest(m, Bs.data(), theta, c0.data()) != 0) {
+        m_ = 0;
+        return -1;
+    }
+    for (int i = m - 1; i >= 0; --i) {
+        double v = c0[i];
+        for (int k = i + 1; k < m; ++k) v -= L_[size_t(k) * ld + i] * a[k];
+        a[i] = v / L_[size_t(i) * ld + i];
+    }
+    return m;
+}
+
 }  // namespace sph

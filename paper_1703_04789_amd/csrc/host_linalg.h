@@ -1,6 +1,7 @@
 // Host-side numerics of the SP-MPS library.
 #pragma once
 #include <array>
+#include <vector>
 
 namespace sph {
 
@@ -37,5 +38,31 @@ int sym_eig_lowest(int n, double* a, double* ev0, double* v0);
 // failure.
 int gen_lowest(int m, const double* H, const double* N, double drop, double* theta, double* a, double* Xc,
                int* rank);
+
+// The fast path of gen_lowest (nothing dropped, Cholesky reduction) for a
+// pencil that grows by one row and column per call, as the projected
+// matrices of a Davidson solve do between restarts.  It keeps the Cholesky
+// factor L of N, W = L^-1 H and B = L^-1 W^T and extends them by one row and
+// column per call, each new entry formed by the same operations as in a
+// full factorisation, so the result is the one gen_lowest gives.  The
+// certificate that nothing would be dropped is a Cholesky factor of
+// N - s I, s = 2 drop U (U the Gershgorin bound when the factors were
+// built), extended alike and valid while drop U stays below s.  lowest()
+// returns m, or -2 if the fast path does not apply (no certificate, or a
+// pencil that is not the cached one grown by one): the caller then takes
+// gen_lowest.
+class GrowingPencil {
+public:
+    void reset() { m_ = 0; }
+    int lowest(int m, const double* H, const double* N, double drop, double* theta, double* a);
+
+private:
+    int m_ = 0, cap_ = 0;
+    double shift_ = 0.0;
+    std::vector<double> H_, N_, L_, Ls_, W_, B_;  // cap_ x cap_, row-major
+    void reserve(int m);
+    int build(int m, const double* H, const double* N, double drop);
+    bool grow(int m, const double* H, const double* N, double drop);
+};
 
 }  // namespace sph

@@ -2432,9 +2432,12 @@ struct DavOut {
 };
 
 // lowest eigenpair of the pencil restricted to range(Nt) (canonical
-// orthogonalisation); returns false if the projected metric vanishes
+// orthogonalisation); returns false if the projected metric vanishes.  gp
+// (may be null) keeps the reduction of the pencil between the calls of one
+// solve, which grows it by one row and column per call until a restart
 bool small_solve(int m, const std::vector<double>& Ht, const std::vector<double>& Nt, int stride, double drop,
-                 bool need_all, double& theta, std::vector<double>& a, std::vector<double>& Xc, int& rk) {
+                 bool need_all, double& theta, std::vector<double>& a, std::vector<double>& Xc, int& rk,
+                 sph::GrowingPencil* gp) {
     std::vector<double> Hs(size_t(m) * m), Ns(size_t(m) * m);
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < m; ++j) {
@@ -2442,6 +2445,17 @@ bool small_solve(int m, const std::vector<double>& Ht, const std::vector<double>
             Ns[size_t(i) * m + j] = 0.5 * (Nt[size_t(i) * stride + j] + Nt[size_t(j) * stride + i]);
         }
     a.assign(m, 0.0);
+    if (gp && need_all) gp->reset();
+    if (gp && !need_all) {
+        const int r = gp->lowest(m, Hs.data(), Ns.data(), drop, &theta, a.data());
+        if (r == -1) throw SpError(SP_ENAN, "subspace eigensolver failed");
+        if (r == m) {
+            if (!std::isfinite(theta)) throw SpError(SP_ENAN, "non-finite Ritz value");
+            rk = m;
+            return true;
+        }
+        a.assign(m, 0.0);
+    }
     if (need_all) Xc.assign(size_t(m) * m, 0.0);
     const int r = sph::gen_lowest(m, Hs.data(), Ns.data(), drop, &theta, a.data(), need_all ? Xc.data() : nullptr, &rk);
     if (r < 0) throw SpError(SP_ENAN, "subspace eigensolver failed");
@@ -2552,13 +2566,14 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     Nt[0] = chunk_total(dn + (lay.pg - lay.out), 2, 1);
     int m = 1;
     std::vector<double> a, Xc;
+    sph::GrowingPencil gp;
     for (int it = 1; it <= max_iter; ++it) {
         out.iters = it;
         double theta;
         int rk = 0;
         const bool last = (it == max_iter);
         const bool restart = !last && m >= max_sub;
-        if (!small_solve(m, Ht, Nt, S, drop, restart, theta, a, Xc, rk))
+        if (!small_solve(m, Ht, Nt, S, drop, restart, theta, a, Xc, rk, &gp))
             throw SpError(SP_ENORM, "projected norm vanishes in the search space");
         out.theta = theta;
         int nk = 0;
@@ -2791,6 +2806,7 @@ class Pool {
 };
 
 struct BatchState {
+    sph::GrowingPencil gp;  // reduction of the growing subspace pencil
     sp_handle* h = nullptr;
     std::vector<std::pair<int, int>> order;  // (site, dir) of every step
     size_t step = 0;
@@ -2987,7 +3003,7 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
                 st.last = (st.it == max_iter);
                 st.restart = !st.last && st.m >= max_sub;
                 const double drop = metric_drop(st.h);
-                if (!small_solve(st.m, st.Ht, st.Nt, S, drop, st.restart, st.theta, st.a, st.Xc, st.rk))
+                if (!small_solve(st.m, st.Ht, st.Nt, S, drop, st.restart, st.theta, st.a, st.Xc, st.rk, &st.gp))
                     throw SpError(SP_ENORM, "projected norm vanishes in the search space");
                 st.out.theta = st.theta;
                 st.nk = 0;
