@@ -2425,6 +2425,17 @@ void ensure_davidson(sp_handle* h, int max_sub) {
     ensure_pinned(h, lay.total - lay.out + 8, lay.pc1 + 8);
 }
 
+// tot[i] = the sum over chunks q < nch of part[q * stride + i], i < stride,
+// each in ascending q, read from the chunk-major partials in one contiguous
+// pass (the same sums as chunk by chunk per i, without the strided reads)
+void chunk_totals(const double* part, int nch, int stride, double* tot) {
+    for (int i = 0; i < stride; ++i) tot[i] = 0.0;
+    for (int q = 0; q < nch; ++q) {
+        const double* row = part + (size_t)q * stride;
+        for (int i = 0; i < stride; ++i) tot[i] += row[i];
+    }
+}
+
 struct DavOut {
     double theta = 0, rnorm = 0, pnorm = 0;
     int iters = 0, matvecs = 0;
@@ -2565,7 +2576,7 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
     Ht[0] = chunk_total(dn + (lay.pg - lay.out), 2, 0);
     Nt[0] = chunk_total(dn + (lay.pg - lay.out), 2, 1);
     int m = 1;
-    std::vector<double> a, Xc;
+    std::vector<double> a, Xc, gt;
     sph::GrowingPencil gp;
     for (int it = 1; it <= max_iter; ++it) {
         out.iters = it;
@@ -2669,8 +2680,9 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
             out.matvecs++;
         }
         HIPCK(hipStreamSynchronize(s));
-        const double* px = dn + (lay.px - lay.out);
-        const double xx = chunk_total(px, 3, 0), uu = chunk_total(px, 3, 1), xn = chunk_total(px, 3, 2);
+        double xt[3];
+        chunk_totals(dn + (lay.px - lay.out), nch, 3, xt);
+        const double xx = xt[0], uu = xt[1], xn = xt[2];
         if (!std::isfinite(xx) || !std::isfinite(uu) || !(xx > 0.0)) throw SpError(SP_ENAN, "non-finite Ritz vector");
         out.rnorm = std::sqrt(uu / xx);
         out.pnorm = xn / xx;
@@ -2694,13 +2706,14 @@ DavOut davidson(sp_handle* h, int k, const sp_sweep_opts& o) {
         const double tn = dn[lay.tn - lay.out];
         if (!(tn >= 1e-14)) break;
         // extend the projected matrices with the new vector m
-        const double* pg = dn + (lay.pg - lay.out);
         const int nd = 4 * m + 2;
+        gt.resize(nd);
+        chunk_totals(dn + (lay.pg - lay.out), nch, nd, gt.data());
         for (int j = 0; j <= m; ++j) {
-            const double hv_new = chunk_total(pg, nd, j);          // V_j . HV_m
-            const double nv_new = chunk_total(pg, nd, m + 1 + j);  // V_j . NV_m
-            const double hv_old = (j < m) ? chunk_total(pg, nd, 2 * m + 2 + j) : hv_new;  // V_m . HV_j
-            const double nv_old = (j < m) ? chunk_total(pg, nd, 3 * m + 2 + j) : nv_new;
+            const double hv_new = gt[j];          // V_j . HV_m
+            const double nv_new = gt[m + 1 + j];  // V_j . NV_m
+            const double hv_old = (j < m) ? gt[2 * m + 2 + j] : hv_new;  // V_m . HV_j
+            const double nv_old = (j < m) ? gt[3 * m + 2 + j] : nv_new;
             Ht[j * S + m] = hv_new;
             Ht[m * S + j] = hv_old;
             Nt[j * S + m] = nv_new;
@@ -3138,9 +3151,9 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
             sp_handle* h = st.h;
             const DavLayout lay(h->dav_sub, spk::dav_chunks(int(h->ld)));
             const double* dn = h->pin;
-            const double* px = dn + (lay.px - lay.out);
-            const double xx = chunk_total(px, st.nch, 3, 0), uu = chunk_total(px, st.nch, 3, 1),
-                         xn = chunk_total(px, st.nch, 3, 2);
+            double xt[3];
+            chunk_totals(dn + (lay.px - lay.out), st.nch, 3, xt);
+            const double xx = xt[0], uu = xt[1], xn = xt[2];
             if (!std::isfinite(xx) || !std::isfinite(uu) || !(xx > 0.0)) throw SpError(SP_ENAN, "non-finite Ritz vector");
             st.out.rnorm = std::sqrt(uu / xx);
             st.out.pnorm = xn / xx;
@@ -3158,13 +3171,14 @@ int sweep_batch(std::vector<BatchState>& B, const sp_sweep_opts& o, std::vector<
                 finished.push_back(i);
                 continue;
             }
-            const double* pg = dn + (lay.pg - lay.out);
             const int m = st.m, nd = 4 * m + 2;
+            std::vector<double> gt(nd);
+            chunk_totals(dn + (lay.pg - lay.out), st.nch, nd, gt.data());
             for (int j = 0; j <= m; ++j) {
-                const double hv_new = chunk_total(pg, st.nch, nd, j);
-                const double nv_new = chunk_total(pg, st.nch, nd, m + 1 + j);
-                const double hv_old = (j < m) ? chunk_total(pg, st.nch, nd, 2 * m + 2 + j) : hv_new;
-                const double nv_old = (j < m) ? chunk_total(pg, st.nch, nd, 3 * m + 2 + j) : nv_new;
+                const double hv_new = gt[j];
+                const double nv_new = gt[m + 1 + j];
+                const double hv_old = (j < m) ? gt[2 * m + 2 + j] : hv_new;
+                const double nv_old = (j < m) ? gt[3 * m + 2 + j] : nv_new;
                 st.Ht[j * S + m] = hv_new;
                 st.Nt[j * S + m] = nv_new;
                 st.Ht[m * S + j] = hv_old;
